@@ -1,0 +1,326 @@
+"""F-Hash FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, obviously correct CPU implementation of what the F-Hash hot path
+computes (oracle.c, FP64 C).  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package; the product path
+never does.  It shares no code with the HIP library: the two meet only through
+the seeded input generators and through plain numpy arrays.
+
+Parity status of each function is documented in oracle.h / the test-suite:
+every routine here is pinned by tests that do not reuse its own formula.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+MAX_LEVELS = 32
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C11, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+               "-ffp-contract=off", "-o", _LIB_PATH, os.path.join(_HERE, "oracle.c"), "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+P = C.c_void_p
+I64 = C.c_int64
+U64 = C.c_uint64
+
+
+class OrGrid(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_features", C.c_int32),
+                ("res", (C.c_int64 * 4) * MAX_LEVELS),
+                ("slot_offset", C.c_int64 * (MAX_LEVELS + 1)),
+                ("vtx_offset", C.c_int64 * (MAX_LEVELS + 1)),
+                ("slot_map", P)]
+
+
+def _declare(L):
+    L.or_fold_num_levels.restype = C.c_int
+    L.or_fold_num_levels.argtypes = [I64, I64]
+    L.or_fold_resolutions.restype = C.c_int
+    L.or_fold_resolutions.argtypes = [P, I64, C.c_int, P]
+    L.or_geometric_resolutions.restype = C.c_int
+    L.or_geometric_resolutions.argtypes = [C.c_int, I64, I64, I64, I64, P, P]
+    L.or_voxel_cells.restype = None
+    L.or_voxel_cells.argtypes = [I64, I64, I64, P, P]
+    L.or_cell_activity.restype = None
+    L.or_cell_activity.argtypes = [P, P, P, P]
+    L.or_build_level_slots.restype = I64
+    L.or_build_level_slots.argtypes = [P, P, P, P]
+    L.or_locate.restype = None
+    L.or_locate.argtypes = [C.c_float, I64, P, P]
+    L.or_corners.restype = None
+    L.or_corners.argtypes = [P, P, I64, P, P]
+    L.or_encode_fwd.restype = None
+    L.or_encode_fwd.argtypes = [P, P, I64, P, P, P]
+    L.or_encode_bwd.restype = None
+    L.or_encode_bwd.argtypes = [P, P, I64, P, P, P]
+    L.or_mlp_num_params.restype = I64
+    L.or_mlp_num_params.argtypes = [C.c_int, P]
+    L.or_mlp_fwd.restype = None
+    L.or_mlp_fwd.argtypes = [C.c_int, P, P, P, I64, P, P, P, P]
+    L.or_mlp_bwd.restype = None
+    L.or_mlp_bwd.argtypes = [C.c_int, P, P, P, P, P, P, I64, P, P, P, P]
+    L.or_mse.restype = C.c_double
+    L.or_mse.argtypes = [P, P, I64, P]
+    L.or_adam.restype = None
+    L.or_adam.argtypes = [P, P, P, P, I64, C.c_double, C.c_double, C.c_double, C.c_double, I64]
+    L.or_psnr.restype = C.c_double
+    L.or_psnr.argtypes = [C.c_double]
+    L.or_philox4x32_10.restype = None
+    L.or_philox4x32_10.argtypes = [P, P, P]
+    L.or_sample_ids.restype = None
+    L.or_sample_ids.argtypes = [U64, U64, I64, U64, P]
+    L.or_sample_batch.restype = None
+    L.or_sample_batch.argtypes = [U64, U64, I64, P, U64, P, P, P, P]
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(P)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# --------------------------------------------------------------------------- resolutions
+def fold_num_levels(S: int, f: int) -> int:
+    return lib().or_fold_num_levels(S, f)
+
+
+def fold_resolutions(S4, f: int) -> np.ndarray:
+    """Paper fold policy; rows are paper levels 1..L_s (row 0 = finest)."""
+    S = _c(S4, np.int64)
+    out = np.zeros((MAX_LEVELS, 4), np.int64)
+    L = lib().or_fold_resolutions(_p(S), f, MAX_LEVELS, _p(out))
+    if L < 0:
+        raise ValueError("too many levels")
+    return out[:L].copy()
+
+
+def geometric_resolutions(L, rmin_s, rmax_s, rmin_t, rmax_t, S4) -> np.ndarray:
+    """Geometric policy; row 0 = coarsest level."""
+    S = _c(S4, np.int64)
+    out = np.zeros((MAX_LEVELS, 4), np.int64)
+    if lib().or_geometric_resolutions(L, rmin_s, rmax_s, rmin_t, rmax_t, _p(S), _p(out)) < 0:
+        raise ValueError("bad level count")
+    return out[:L].copy()
+
+
+# --------------------------------------------------------------------------- index
+def voxel_cells(i, S, R):
+    lo, hi = C.c_int64(), C.c_int64()
+    lib().or_voxel_cells(i, S, R, C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def cell_activity(res4, mask: np.ndarray) -> np.ndarray:
+    """mask: uint8 [T][Sz][Sy][Sx]; returns uint8 [Rt-1][Rz-1][Ry-1][Rx-1]."""
+    r = _c(res4, np.int64)
+    m = _c(mask, np.uint8)
+    S = np.array([m.shape[3], m.shape[2], m.shape[1], m.shape[0]], np.int64)
+    out = np.zeros((r[3] - 1, r[2] - 1, r[1] - 1, r[0] - 1), np.uint8)
+    lib().or_cell_activity(_p(r), _p(m), _p(S), _p(out))
+    return out
+
+
+def level_slots(res4, mask):
+    """Slot map of one level (vertex -> slot within level, -1 inactive), count."""
+    r = _c(res4, np.int64)
+    nv = int(np.prod(r))
+    out = np.zeros(nv, np.int64)
+    if mask is None:
+        S = np.zeros(4, np.int64)
+        cnt = lib().or_build_level_slots(_p(r), None, _p(S), _p(out))
+    else:
+        m = _c(mask, np.uint8)
+        S = np.array([m.shape[3], m.shape[2], m.shape[1], m.shape[0]], np.int64)
+        cnt = lib().or_build_level_slots(_p(r), _p(m), _p(S), _p(out))
+    return out, int(cnt)
+
+
+class Grid:
+    """Oracle-side level structure + (optional) active-vertex slot maps."""
+
+    def __init__(self, res, n_features, mask=None):
+        res = np.asarray(res, np.int64).reshape(-1, 4)
+        self.res = res
+        self.L = res.shape[0]
+        self.F = n_features
+        self.maps = []
+        self.counts = []
+        for l in range(self.L):
+            m, c = level_slots(res[l], mask)
+            self.maps.append(m)
+            self.counts.append(c)
+        self.dense = mask is None
+        self.slot_offset = np.zeros(self.L + 1, np.int64)
+        self.slot_offset[1:] = np.cumsum(self.counts)
+        self.vtx_offset = np.zeros(self.L + 1, np.int64)
+        self.vtx_offset[1:] = np.cumsum([int(np.prod(r)) for r in res])
+        self._map = None if self.dense else np.concatenate(self.maps)
+        g = OrGrid()
+        g.n_levels = self.L
+        g.n_features = n_features
+        for l in range(self.L):
+            for d in range(4):
+                g.res[l][d] = int(res[l][d])
+        for l in range(self.L + 1):
+            g.slot_offset[l] = int(self.slot_offset[l])
+            g.vtx_offset[l] = int(self.vtx_offset[l])
+        g.slot_map = None if self.dense else self._map.ctypes.data_as(P)
+        self._g = g
+
+    @property
+    def total_slots(self) -> int:
+        return int(self.slot_offset[-1])
+
+    def ref(self):
+        return C.byref(self._g)
+
+
+def locate(p: float, R: int):
+    c, f = C.c_int64(), C.c_double()
+    lib().or_locate(C.c_float(p), R, C.byref(c), C.byref(f))
+    return c.value, f.value
+
+
+def corners(grid: Grid, pos):
+    pos = _c(pos, np.float32)
+    n = pos.shape[0]
+    slots = np.zeros((n, grid.L, 16), np.int64)
+    w = np.zeros((n, grid.L, 16), np.float64)
+    lib().or_corners(grid.ref(), _p(pos), n, _p(slots), _p(w))
+    return slots, w
+
+
+def encode_fwd(grid: Grid, pos, table):
+    pos = _c(pos, np.float32)
+    tab = _c(table, np.float64)
+    n = pos.shape[0]
+    enc = np.zeros((n, grid.L * grid.F), np.float64)
+    mag = np.zeros_like(enc)
+    lib().or_encode_fwd(grid.ref(), _p(pos), n, _p(tab), _p(enc), _p(mag))
+    return enc, mag
+
+
+def encode_bwd(grid: Grid, pos, d_enc):
+    pos = _c(pos, np.float32)
+    de = _c(d_enc, np.float64)
+    n = pos.shape[0]
+    dt = np.zeros((grid.total_slots, grid.F), np.float64)
+    mag = np.zeros_like(dt)
+    lib().or_encode_bwd(grid.ref(), _p(pos), n, _p(de), _p(dt), _p(mag))
+    return dt, mag
+
+
+# --------------------------------------------------------------------------- MLP
+def mlp_num_params(width) -> int:
+    w = _c(width, np.int32)
+    return int(lib().or_mlp_num_params(len(w) - 1, _p(w)))
+
+
+def mlp_fwd(width, params, x, x_mag=None):
+    w = _c(width, np.int32)
+    nl = len(w) - 1
+    prm = _c(params, np.float64)
+    x = _c(x, np.float64)
+    n = x.shape[0]
+    y = np.zeros((n, w[-1]), np.float64)
+    acts = np.zeros(int(n * w.sum()), np.float64)
+    ymag = np.zeros_like(y)
+    xm = None if x_mag is None else _c(x_mag, np.float64)
+    lib().or_mlp_fwd(nl, _p(w), _p(prm), _p(x), n, _p(y), _p(acts), _p(xm), _p(ymag))
+    return y, acts, ymag
+
+
+def mlp_bwd(width, params, acts, dy, n, dy_mag=None, x_mag=None):
+    w = _c(width, np.int32)
+    nl = len(w) - 1
+    prm = _c(params, np.float64)
+    acts = _c(acts, np.float64)
+    dy = _c(dy, np.float64)
+    dp = np.zeros(prm.shape[0], np.float64)
+    dpm = np.zeros_like(dp)
+    dx = np.zeros((n, w[0]), np.float64)
+    dxm = np.zeros_like(dx)
+    dym = None if dy_mag is None else _c(dy_mag, np.float64)
+    xm = None if x_mag is None else _c(x_mag, np.float64)
+    lib().or_mlp_bwd(nl, _p(w), _p(prm), _p(acts), _p(dy), _p(dym), _p(xm), n, _p(dp), _p(dx),
+                     _p(dpm), _p(dxm))
+    return dp, dx, dpm, dxm
+
+
+# --------------------------------------------------------------------------- loss / adam / psnr
+def mse(y, v):
+    y = _c(y, np.float64).ravel()
+    v = _c(v, np.float64).ravel()
+    dy = np.zeros_like(y)
+    L = lib().or_mse(_p(y), _p(v), y.shape[0], _p(dy))
+    return L, dy
+
+
+def adam(p, g, m, v, lr, beta1, beta2, eps, step):
+    """In-place on float64 arrays p, m, v."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _c(g, np.float64)
+    lib().or_adam(_p(p), _p(g), _p(m), _p(v), p.size, lr, beta1, beta2, eps, step)
+
+
+def psnr(mse_value: float) -> float:
+    return float(lib().or_psnr(mse_value))
+
+
+# --------------------------------------------------------------------------- RNG / sampler
+def philox4x32_10(ctr, key):
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def sample_ids(seed, step, n, M):
+    ids = np.zeros(n, np.uint64)
+    lib().or_sample_ids(seed, step, n, M, _p(ids))
+    return ids
+
+
+def sample_batch(seed, step, n, field, coreset=None):
+    """field: float32 [T][Sz][Sy][Sx].  Returns pos [n][4] f32, target [n] f32."""
+    f = _c(field, np.float32)
+    S = np.array([f.shape[3], f.shape[2], f.shape[1], f.shape[0]], np.int64)
+    pos = np.zeros((n, 4), np.float32)
+    tgt = np.zeros(n, np.float32)
+    if coreset is None:
+        M = int(f.size)
+        cs = None
+    else:
+        cs = _c(coreset, np.uint64)
+        M = int(cs.shape[0])
+    lib().or_sample_batch(seed, step, n, _p(cs), M, _p(S), _p(f), _p(pos), _p(tgt))
+    return pos, tgt
