@@ -1,0 +1,317 @@
+/*
+ * fhash.h -- C ABI of the MI355X (gfx950) F-Hash hot path.
+ *
+ * F-Hash (feature-based hash for time-varying volumes, arXiv 2507.03836)
+ * encodes a 4D sample (x, y, z, t) with a stack of multi-resolution
+ * "tesseract" embedding grids (Sec. 3.2), each addressed by a collision-free
+ * per-level hash (Sec. 3.2.3), interpolates the 16 corner embeddings of the
+ * containing 4D cell (Sec. 3.2.4), concatenates the levels and decodes them
+ * with a small MLP.  Training is Adam (Sec. 5.1.3); rendering is ray marching
+ * with an adaptive marching pace (Sec. 3.3, Algorithm 1).
+ *
+ * Conventions shared by every call
+ *  - Every call returns an int status (FHASH_OK = 0, negative on error) and
+ *    never throws.  A message for the last failure on the calling thread is
+ *    available from fhash_last_error().
+ *  - All arguments are validated on the host before any launch; invalid ones
+ *    return FHASH_EINVAL and launch nothing.
+ *  - "device" pointers are HIP device memory owned by the caller.  The library
+ *    allocates nothing; calls that need scratch memory take a workspace
+ *    (void* ws, size_t* ws_bytes): with ws == NULL the call only writes the
+ *    required size to *ws_bytes and returns FHASH_OK.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = default
+ *    stream) unless stated otherwise.  Launch failures surface as FHASH_EHIP.
+ *  - Positions are FP32 (x, y, z, t) in [0,1]^4, 16-byte aligned, one float4
+ *    per sample.  Values outside [0,1] are clamped (NaN -> 0).
+ *  - Level vertex i of a dimension with R vertices sits at i/(R-1); level 0 is
+ *    the coarsest level and the MLP input is levels 0..L-1 concatenated,
+ *    F features per level.
+ */
+#ifndef FHASH_H
+#define FHASH_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FHASH_VERSION 1
+#define FHASH_MAX_LEVELS 24
+#define FHASH_MAX_LAYERS 8
+
+enum {
+  FHASH_OK = 0,
+  FHASH_EINVAL = -1,  /* bad argument (NULL, size, shape, alignment)        */
+  FHASH_ENOMEM = -2,  /* workspace too small                                 */
+  FHASH_EHIP = -3,    /* HIP launch / runtime error                          */
+  FHASH_ERANGE = -4,  /* a count or index exceeds its representable range    */
+  FHASH_ENOTSUP = -5  /* valid but not built (dtype, feature count, width)   */
+};
+
+typedef enum { FHASH_F32 = 0, FHASH_F16 = 1, FHASH_BF16 = 2 } fhash_dtype;
+
+/* Level structure of the multi-resolution tesseract grid (Sec. 3.2.1-3.2.2).
+ * res[l] = vertex counts (x, y, z, t) of level l, each in [2, 2^24].
+ * n_features = F, the embedding size of a vertex (Sec. 4.1): 1, 2, 4 or 8. */
+typedef struct {
+  int32_t n_levels;
+  int32_t n_features;
+  int32_t res[FHASH_MAX_LEVELS][4];
+} fhash_grid_desc;
+
+/* Voxel feature mask (the dilated feature region d_k of Sec. 3.1, one bit per
+ * voxel and timestep).  dims = (Sx, Sy, Sz, T), each >= 2; voxel i of a
+ * dimension with S samples sits at i/(S-1).  Layout: rows of ceil(Sx/64)
+ * uint64 words, [T][Sz][Sy][ceil(Sx/64)]; bit b of word w of a row is voxel
+ * x = 64 w + b; padding bits must be zero.  bits == NULL: the dense box. */
+typedef struct {
+  const uint64_t* bits; /* device */
+  int64_t dims[4];
+} fhash_mask_desc;
+
+/* Built index (a plain view; valid while `dir` lives).  Filled by
+ * fhash_build_index; callers treat it as read-only and may share it. */
+typedef struct {
+  fhash_grid_desc grid;
+  int32_t active;   /* 0: dense box, every vertex has a slot; 1: active vertices only */
+  int32_t reserved;
+  const void* dir;  /* device rank directory (16-byte entries), NULL when dense */
+  int64_t dir_offset[FHASH_MAX_LEVELS + 1];  /* first directory entry of each level */
+  int64_t slot_offset[FHASH_MAX_LEVELS + 1]; /* first table row of each level; [L] = rows */
+} fhash_index;
+
+int fhash_version(void);
+const char* fhash_last_error(void);
+
+/* ---------------------------------------------------------------- index ----
+ * The per-level collision-free hash (Sec. 3.2.3, the F-Hash equation, and the
+ * "irregular feature region" variant of Sec. 3.1 that it makes fast).
+ *
+ * A 4D cell of level l is active iff its closed box contains a masked voxel;
+ * a vertex is active iff it is a corner of an active cell (embeddings live at
+ * cell corners, Sec. 3.2.4 step 3).  The slot of an active vertex is its rank
+ * among the level's active vertices in the F-Hash linearisation
+ *   lin = ((t*Rz + z)*Ry + y)*Rx + x,
+ * so the table has exactly one row per active vertex: no collision and no
+ * unused bucket.  With mask->bits == NULL every vertex is active and the slot
+ * is the F-Hash equation itself.  Level l owns rows
+ * [slot_offset[l], slot_offset[l+1]) of every table.
+ *
+ * fhash_index_dir_entries: number of 16-byte directory entries the grid needs
+ * (0 for a dense index is not implied: the size is for the active form).
+ * fhash_build_index: fills dir (device, dir_entries*16 bytes, caller-owned)
+ * and *out, and writes the per-level active-vertex counts to the HOST array
+ * slots_per_level[L].  This call synchronises `stream` (it returns counts).
+ * ws: device workspace (query with ws == NULL).  Returns FHASH_ERANGE if a
+ * level has 2^62 vertices or more. */
+int fhash_index_dir_entries(const fhash_grid_desc* grid, int64_t* entries);
+int fhash_build_index(const fhash_grid_desc* grid, const fhash_mask_desc* mask, void* dir,
+                      void* ws, size_t* ws_bytes, fhash_index* out, int64_t* slots_per_level,
+                      void* stream);
+/* Dense index (every vertex active): no device memory, no launch. */
+int fhash_dense_index(const fhash_grid_desc* grid, fhash_index* out, int64_t* slots_per_level);
+
+/* -------------------------------------------------------------- encoding ----
+ * Input encoding (Sec. 3.2.4): per level, locate the 4D cell containing the
+ * sample (u = p*(R-1) as one FP32 multiply, cell = min(floor(u), R-2),
+ * fraction = u - cell), look up the 16 corner slots, and blend the corner
+ * embeddings with quadrilinear weights prod_d (f_d or 1 - f_d).  Inactive
+ * corners contribute zero (no renormalisation).
+ * pos: device float4[n]; table: device [rows][F] of table_dt (FHASH_F32 master
+ * or FHASH_F16 shadow); enc: device float [n][L*F], level-major.
+ * FP32 accumulation. */
+int fhash_encode_fwd(const fhash_index* idx, const float* pos, int64_t n, const void* table,
+                     fhash_dtype table_dt, float* enc, void* stream);
+
+/* Adjoint of the encoding: d_table[slot][k] += w_c * d_enc[s][l*F + k] for every
+ * active corner c of every sample and level (FP32 atomics; summation order is
+ * not deterministic).  The corner weights are recomputed from pos, not stored.
+ * d_enc: device float [n][L*F]; d_table: device float [rows][F], accumulated. */
+int fhash_encode_bwd(const fhash_index* idx, const float* pos, int64_t n, const float* d_enc,
+                     float* d_table, void* stream);
+
+/* ------------------------------------------------------------------- MLP ----
+ * Shallow decoder (Sec. 3.2.4 end; 2 hidden layers of 64 in Sec. 4.2):
+ * width[0] = input (<= 64), n_layers-1 hidden layers of equal width H
+ * (16, 32 or 64) with ReLU, and a linear output of width 1; biases on.
+ * params: device float, packed per layer k as W_k[width[k+1]][width[k]]
+ * row-major then b_k[width[k+1]].  compute_dt: FHASH_F32 (FP32 MFMA) or
+ * FHASH_BF16 (BF16 MFMA on a bf16 copy of params, `shadow`, FP32 accumulate).
+ */
+typedef struct {
+  int32_t n_layers;
+  int32_t width[FHASH_MAX_LAYERS + 1];
+  fhash_dtype compute_dt;
+} fhash_mlp_desc;
+
+int64_t fhash_mlp_num_params(const fhash_mlp_desc* mlp);
+
+/* y[n] = MLP(x[n][width[0]]).  x, y: device float. */
+int fhash_mlp_fwd(const fhash_mlp_desc* mlp, const float* params, const void* shadow,
+                  const float* x, int64_t n, float* y, void* stream);
+
+/* Reverse mode of fhash_mlp_fwd (activations are recomputed from x):
+ * d_params (device float [P]) += dL/dparams, dx (device float [n][width[0]],
+ * may be NULL) = dL/dx, for dy = dL/dy (device float [n]).  The parameter
+ * gradient is reduced deterministically through the workspace. */
+int fhash_mlp_bwd(const fhash_mlp_desc* mlp, const float* params, const void* shadow,
+                  const float* x, const float* dy, int64_t n, float* d_params, float* dx,
+                  void* ws, size_t* ws_bytes, void* stream);
+
+/* ------------------------------------------------------------ fused path ----
+ * Encoding fused with the decoder.  fhash_fused_fwd: y = MLP(encode(pos)).
+ * fhash_fused_bwd: given dy, recompute the encoding and activations and
+ * accumulate d_table (atomics) and d_params (deterministic).
+ * fhash_fused_train: forward, MSE loss against target, backward in one pass:
+ *   dL/dy_s = loss_scale * 2 (y_s - target_s) / n,
+ * loss_sum (device double, accumulated) += sum_s (y_s - target_s)^2. */
+int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
+                    const void* table, fhash_dtype table_dt, const float* params,
+                    const void* shadow, float* y, void* stream);
+int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
+                    const void* table, fhash_dtype table_dt, const float* params,
+                    const void* shadow, const float* dy, float* d_table, float* d_params,
+                    void* ws, size_t* ws_bytes, void* stream);
+int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
+                      const float* target, int64_t n, const void* table, fhash_dtype table_dt,
+                      const float* params, const void* shadow, float loss_scale, float* d_table,
+                      float* d_params, double* loss_sum, void* ws, size_t* ws_bytes,
+                      void* stream);
+
+/* ------------------------------------------------------------ optimiser ----
+ * Adam (Sec. 5.1.3: Adam, lr 0.01; PyTorch semantics, bias-corrected, no
+ * weight decay), applied densely to every parameter:
+ *   g = grad * grad_scale;  m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= (lr / (1 - b1^step)) * m / (sqrt(v) / sqrt(1 - b2^step) + eps).
+ * grad is zeroed.  If found_inf (device int32, may be NULL) is non-zero the
+ * whole update is skipped (grad is still zeroed).  shadow (device, may be
+ * NULL) receives p rounded to shadow_dt (FHASH_F16 or FHASH_BF16, RNE).
+ * All arrays device float[n], 16-byte aligned. */
+typedef struct {
+  double lr, beta1, beta2, eps; /* the kernel uses FP32 roundings of b1, 1-b1, b2, 1-b2 */
+  int64_t step;                 /* 1-based */
+  double grad_scale;
+} fhash_adam_desc;
+
+int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
+               void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
+               void* stream);
+
+/* *found_inf |= any(!isfinite(grad[i])) over device float grad[n]. */
+int fhash_check_finite(const float* grad, int64_t n, int32_t* found_inf, void* stream);
+
+/* Round a device float array to a device f16/bf16 copy (RNE). */
+int fhash_cast(const float* src, void* dst, fhash_dtype dst_dt, int64_t n, void* stream);
+
+/* -------------------------------------------------------------- sampler ----
+ * Training batch from the coreset (Sec. 3.1, time-step concatenation): draw i
+ * of step `step` is voxel id floor(r * M / 2^64), r the 64-bit word out1:out0
+ * of Philox4x32-10 with counter (i, step) and key seed; the voxel is
+ * coreset[id] (device uint64 linear voxel ids) or id itself when coreset is
+ * NULL.  pos = (i/(Sx-1), j/(Sy-1), k/(Sz-1), n/(T-1)) in FP32 (IEEE
+ * division), target = field[voxel] (device float [T][Sz][Sy][Sx]).
+ * dims = (Sx, Sy, Sz, T). */
+int fhash_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset, uint64_t M,
+                 const int64_t dims[4], const float* field, float* pos, float* target,
+                 void* stream);
+
+/* ----------------------------------------------------------- reductions ----
+ * *sum (device double, accumulated) += sum_i (y[i] - v[i])^2 in FP64
+ * (the loss / PSNR reduction, PSNR = 10 log10(1/MSE), Sec. 5.1.2). */
+int fhash_sq_err_sum(const float* y, const float* v, int64_t n, double* sum, void* stream);
+
+/* MSE loss gradient of the unfused path (L = mean over the batch of (y_s - v_s)^2):
+ * dy[s] = loss_scale * 2 (y[s] - v[s]) / n; *loss_sum (device double, may be
+ * NULL, accumulated) += sum_s (y[s] - v[s])^2 in FP64. */
+int fhash_mse_grad(const float* y, const float* v, int64_t n, float loss_scale, float* dy,
+                   double* loss_sum, void* stream);
+
+/* ------------------------------------------------------------- rendering ----
+ * Volume rendering of the trained representation by ray marching with the
+ * adaptive marching pace (ARM) of Sec. 3.3, Algorithm 1.
+ *
+ * Geometry: the volume occupies the box [0, Sx-1] x [0, Sy-1] x [0, Sz-1] in
+ * voxel units.  Pixel (px, py) of a W x H image casts the ray from `eye` along
+ * normalize(fwd + u right + v up), u = (2 (px + 1/2)/W - 1) tan_half_fovy aspect,
+ * v = (1 - 2 (py + 1/2)/H) tan_half_fovy; the slab test gives [s_near, s_far].
+ * Samples sit on the lattice s_k = s_near + (k + 1/2) ds, p_k = fma(s_k, dir, eye)
+ * (FP32, IEEE operations, k < max_steps).  A sample is taken iff its voxel cell
+ * is occupied at time t (reading of the interpolated occupancy grid for a bit
+ * grid: one of the cell's 8 corner voxels is in the feature mask at floor(t)
+ * or ceil(t)); its value is the decoder output at (p / (S - 1), t / (T - 1)).
+ * The value is mapped through a 256-entry RGBA transfer function (value
+ * clamped to [0,1], linear interpolation) and composited front to back,
+ * C += (1 - A) a c, A += (1 - A) a, until A >= alpha_stop.
+ * ARM: while rays are alive, each alive ray emits up to
+ * pace = clamp(floor(budget / alive), 1, arm_max) occupied samples per
+ * iteration (budget = number of rays for a single request), all emitted samples
+ * are decoded in one batch, then composited.  The pace changes only the
+ * schedule: the image equals the pace-1 image.
+ * The view basis (fwd, right, up orthonormal, tan of half the vertical field of
+ * view, aspect = W / H) is an input; rgba: device float [H][W][4]. */
+typedef struct {
+  float eye[3], fwd[3], right[3], up[3];
+  float tan_half_fovy, aspect;
+} fhash_view;
+
+typedef struct {
+  float ds;          /* lattice step in voxel units (> 0) */
+  float alpha_stop;  /* early-termination opacity, e.g. 0.99 */
+  int32_t arm_max;   /* maximum pace, 64 in Algorithm 1; 1 disables ARM */
+  int32_t max_steps; /* lattice steps per ray */
+} fhash_render_opts;
+
+/* Per-request render state (host POD, owned by the caller). */
+typedef struct {
+  int32_t W, H;
+  float t;
+  int32_t cur;       /* current alive list */
+  int32_t n_alive;   /* alive rays */
+  int32_t pending;   /* samples emitted by the last march, not yet composited */
+  int64_t iterations, samples;
+  void* ws;
+  int64_t dims[4];
+} fhash_render_state;
+
+/* Device workspace of one request's ray state (W*H rays + occupancy bits). */
+int fhash_render_state_bytes(int32_t W, int32_t H, const int64_t dims[4], size_t* bytes);
+
+/* Set up rays and the occupancy at time t (fractional timestep in [0, T-1]),
+ * clear rgba.  Synchronises `stream` (returns the alive-ray count in *state). */
+int fhash_render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
+                       const uint64_t* mask_bits, const int64_t dims[4], void* ws,
+                       size_t ws_bytes, float* rgba, fhash_render_state* state, void* stream);
+
+/* pace = clamp(floor(budget / alive), 1, arm_max) (Algorithm 1). */
+int32_t fhash_render_pace(int64_t budget, int64_t alive, int32_t arm_max);
+
+/* Emit up to `pace` occupied samples per alive ray into pos_out (device
+ * float4[cap], model inputs); cap must be >= pace * alive.  Writes the number
+ * of samples to *n_samples.  Synchronises `stream`. */
+int fhash_render_march(fhash_render_state* state, const fhash_render_opts* opts, int32_t pace,
+                       float* pos_out, int64_t cap, int64_t* n_samples, void* stream);
+
+/* Composite the decoded values y (device float[n_samples], in the order of the
+ * last march) into the rays; finished rays write their pixel.  Synchronises
+ * `stream` (updates state->n_alive). */
+int fhash_render_composite(fhash_render_state* state, const float* y, const float* tf,
+                           const fhash_render_opts* opts, float* rgba, void* stream);
+
+typedef struct {
+  int64_t iterations, samples;
+} fhash_render_stats;
+
+/* Whole image for one request: begin, then march / fused decode / composite
+ * until no ray is alive.  ws: device workspace (query with ws == NULL).
+ * Synchronises `stream`. */
+int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* table,
+                 fhash_dtype table_dt, const float* params, const uint64_t* mask_bits,
+                 const int64_t dims[4], const fhash_view* view, float t, const float* tf,
+                 int32_t W, int32_t H, const fhash_render_opts* opts, float* rgba, void* ws,
+                 size_t* ws_bytes, fhash_render_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHASH_H */

@@ -70,6 +70,10 @@ def _declare(L):
     L.or_cell_activity.argtypes = [P, P, P, P]
     L.or_build_level_slots.restype = I64
     L.or_build_level_slots.argtypes = [P, P, P, P]
+    L.or_cell_active_bits.restype = C.c_int
+    L.or_cell_active_bits.argtypes = [P, P, P, P]
+    L.or_vertex_active_bits.restype = C.c_int
+    L.or_vertex_active_bits.argtypes = [P, P, P, P]
     L.or_locate.restype = None
     L.or_locate.argtypes = [C.c_float, I64, P, P]
     L.or_corners.restype = None
@@ -94,6 +98,13 @@ def _declare(L):
     L.or_philox4x32_10.argtypes = [P, P, P]
     L.or_sample_ids.restype = None
     L.or_sample_ids.argtypes = [U64, U64, I64, U64, P]
+    L.or_voxel_positions.restype = None
+    L.or_voxel_positions.argtypes = [P, I64, P, P]
+    L.or_occupied.restype = C.c_int
+    L.or_occupied.argtypes = [P, P, P, C.c_float]
+    L.or_render.restype = I64
+    L.or_render.argtypes = [P, P, C.c_int, P, P, P, P, P, C.c_float, P, C.c_int, C.c_int,
+                            C.c_float, C.c_float, C.c_int, P, P]
     L.or_sample_batch.restype = None
     L.or_sample_batch.argtypes = [U64, U64, I64, P, U64, P, P, P, P]
 
@@ -160,6 +171,16 @@ def level_slots(res4, mask):
         S = np.array([m.shape[3], m.shape[2], m.shape[1], m.shape[0]], np.int64)
         cnt = lib().or_build_level_slots(_p(r), _p(m), _p(S), _p(out))
     return out, int(cnt)
+
+
+def vertex_active_bits(res4, bits, dims, v):
+    """Activity of vertex v = (x, y, z, t) of a level, from a row-padded bit mask
+    (uint64 [T][Sz][Sy][ceil(Sx/64)]); dims = (Sx, Sy, Sz, T)."""
+    r = _c(res4, np.int64)
+    b = _c(bits, np.uint64)
+    S = _c(dims, np.int64)
+    vv = _c(v, np.int64)
+    return bool(lib().or_vertex_active_bits(_p(r), _p(b), _p(S), _p(vv)))
 
 
 class Grid:
@@ -310,6 +331,15 @@ def sample_ids(seed, step, n, M):
     return ids
 
 
+def voxel_positions(lin, dims):
+    """FP32 sample positions of linear voxel ids; dims = (Sx, Sy, Sz, T)."""
+    lin = _c(lin, np.uint64)
+    S = _c(dims, np.int64)
+    pos = np.zeros((lin.shape[0], 4), np.float32)
+    lib().or_voxel_positions(_p(lin), lin.shape[0], _p(S), _p(pos))
+    return pos
+
+
 def sample_batch(seed, step, n, field, coreset=None):
     """field: float32 [T][Sz][Sy][Sx].  Returns pos [n][4] f32, target [n] f32."""
     f = _c(field, np.float32)
@@ -324,3 +354,30 @@ def sample_batch(seed, step, n, field, coreset=None):
         M = int(cs.shape[0])
     lib().or_sample_batch(seed, step, n, _p(cs), M, _p(S), _p(f), _p(pos), _p(tgt))
     return pos, tgt
+
+
+
+# --------------------------------------------------------------------------- render
+def render(grid: Grid, table, width, params, mask, view14, t, tf, W, H, ds=0.5,
+           alpha_stop=0.99, max_steps=1 << 20):
+    """Oracle image [H][W][4] (FP64), ambiguity flags [H][W], evaluated samples."""
+    tab = _c(table, np.float64)
+    w = _c(width, np.int32)
+    prm = _c(params, np.float64)
+    m = _c(mask, np.uint8)
+    S = np.array([m.shape[3], m.shape[2], m.shape[1], m.shape[0]], np.int64)
+    cam = _c(view14, np.float32)
+    tfa = _c(tf, np.float32)
+    rgba = np.zeros((H, W, 4), np.float64)
+    amb = np.zeros((H, W), np.uint8)
+    ev = lib().or_render(grid.ref(), _p(tab), len(w) - 1, _p(w), _p(prm), _p(m), _p(S), _p(cam),
+                         C.c_float(t), _p(tfa), W, H, C.c_float(ds), C.c_float(alpha_stop),
+                         max_steps, _p(rgba), _p(amb))
+    return rgba, amb.astype(bool), int(ev)
+
+
+def occupied(mask, p3, t):
+    m = _c(mask, np.uint8)
+    S = np.array([m.shape[3], m.shape[2], m.shape[1], m.shape[0]], np.int64)
+    p = _c(p3, np.float32)
+    return bool(lib().or_occupied(_p(m), _p(S), _p(p), C.c_float(t)))

@@ -171,6 +171,60 @@ int64_t or_build_level_slots(const int64_t res[4], const uint8_t* mask, const in
   return count;
 }
 
+/* Activity of one vertex decided from a bit-packed mask, for volumes too large
+ * for the whole-level enumeration above.  Same definitions: the vertex is
+ * active iff one of the (up to 16) cells having it as a corner contains a
+ * masked voxel in its closed box.  bits: rows of W = ceil(Sx/64) words,
+ * [T][Sz][Sy][W], bit b of word w = voxel x = 64 w + b. */
+static int voxel_in_cell(int64_t i, int64_t S, int64_t R, int64_t c) {
+  int64_t lo, hi;
+  or_voxel_cells(i, S, R, &lo, &hi);
+  return lo <= c && c <= hi;
+}
+
+static int bit_set(const uint64_t* bits, const int64_t S[4], int64_t i, int64_t j, int64_t k,
+                   int64_t n) {
+  const int64_t W = (S[0] + 63) / 64;
+  return (int)((bits[((n * S[2] + k) * S[1] + j) * W + i / 64] >> (i % 64)) & 1u);
+}
+
+int or_cell_active_bits(const int64_t res[4], const uint64_t* bits, const int64_t S[4],
+                        const int64_t c[4]) {
+  int64_t lo[4], hi[4];
+  for (int d = 0; d < 4; ++d) {
+    if (c[d] < 0 || c[d] > res[d] - 2) return 0;
+    /* candidate voxels around the cell: i(R-1)/(S-1) within [c-1, c+2] */
+    lo[d] = (c[d] - 1) * (S[d] - 1) / (res[d] - 1) - 1;
+    hi[d] = (c[d] + 2) * (S[d] - 1) / (res[d] - 1) + 1;
+    if (lo[d] < 0) lo[d] = 0;
+    if (hi[d] > S[d] - 1) hi[d] = S[d] - 1;
+  }
+  for (int64_t n = lo[3]; n <= hi[3]; ++n) {
+    if (!voxel_in_cell(n, S[3], res[3], c[3])) continue;
+    for (int64_t k = lo[2]; k <= hi[2]; ++k) {
+      if (!voxel_in_cell(k, S[2], res[2], c[2])) continue;
+      for (int64_t j = lo[1]; j <= hi[1]; ++j) {
+        if (!voxel_in_cell(j, S[1], res[1], c[1])) continue;
+        for (int64_t i = lo[0]; i <= hi[0]; ++i) {
+          if (!voxel_in_cell(i, S[0], res[0], c[0])) continue;
+          if (bit_set(bits, S, i, j, k, n)) return 1;
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+int or_vertex_active_bits(const int64_t res[4], const uint64_t* bits, const int64_t S[4],
+                          const int64_t v[4]) {
+  for (int m = 0; m < 16; ++m) {
+    int64_t c[4];
+    for (int d = 0; d < 4; ++d) c[d] = v[d] - ((m >> d) & 1);
+    if (or_cell_active_bits(res, bits, S, c)) return 1;
+  }
+  return 0;
+}
+
 /* ========================================================================= */
 /* Cell location and the input encoding (Sec. 3.2.4)                        */
 /* ========================================================================= */
@@ -546,6 +600,22 @@ void or_sample_ids(uint64_t seed, uint64_t step, int64_t n, uint64_t M, uint64_t
   }
 }
 
+/* Sample positions of linear voxel ids: (i/(Sx-1), j/(Sy-1), k/(Sz-1), n/(T-1))
+ * in FP32 (the position part of the training sampler). */
+void or_voxel_positions(const uint64_t* lin, int64_t n, const int64_t S[4], float* pos) {
+  for (int64_t s = 0; s < n; ++s) {
+    uint64_t v = lin[s];
+    int64_t i = (int64_t)(v % (uint64_t)S[0]);
+    int64_t j = (int64_t)((v / (uint64_t)S[0]) % (uint64_t)S[1]);
+    int64_t k = (int64_t)((v / ((uint64_t)S[0] * S[1])) % (uint64_t)S[2]);
+    int64_t t = (int64_t)(v / ((uint64_t)S[0] * S[1] * S[2]));
+    pos[s * 4 + 0] = (float)i / (float)(S[0] - 1);
+    pos[s * 4 + 1] = (float)j / (float)(S[1] - 1);
+    pos[s * 4 + 2] = (float)k / (float)(S[2] - 1);
+    pos[s * 4 + 3] = (float)t / (float)(S[3] - 1);
+  }
+}
+
 /* One training batch (Sec. 3.1, time-step concatenation): each draw picks a
  * voxel, either from the coreset list (linear voxel ids) or, when coreset is
  * NULL, from the whole grid; the sample is the voxel position
@@ -569,4 +639,137 @@ void or_sample_batch(uint64_t seed, uint64_t step, int64_t n, const uint64_t* co
     target[s] = field[lin];
   }
   free(ids);
+}
+
+/* ========================================================================= */
+/* Rendering (Sec. 3.3, Algorithm 1)                                         */
+/* ========================================================================= */
+
+/* Occupancy of lattice position p (voxel units) at fractional timestep t
+ * (reading of the "linearly interpolated occupancy grid" for a bit grid): the
+ * sample counts as occupied iff one of the 8 corner voxels of its voxel cell
+ * is in the feature mask at floor(t) or at ceil(t).  mask: bytes [T][Sz][Sy][Sx]. */
+int or_occupied(const uint8_t* mask, const int64_t S[4], const float p[3], float t) {
+  int64_t c[3];
+  for (int d = 0; d < 3; ++d) {
+    int64_t i = (int64_t)floorf(p[d]);
+    if (i < 0) i = 0;
+    if (i > S[d] - 2) i = S[d] - 2;
+    c[d] = i;
+  }
+  int64_t t0 = (int64_t)floorf(t), t1 = (int64_t)ceilf(t);
+  if (t0 < 0) t0 = 0;
+  if (t1 > S[3] - 1) t1 = S[3] - 1;
+  if (t0 > S[3] - 1) t0 = S[3] - 1;
+  for (int64_t n = t0; n <= t1; ++n)
+    for (int m = 0; m < 8; ++m) {
+      int64_t x = c[0] + (m & 1), y = c[1] + ((m >> 1) & 1), z = c[2] + ((m >> 2) & 1);
+      if (mask[((n * S[2] + z) * S[1] + y) * S[0] + x]) return 1;
+    }
+  return 0;
+}
+
+/* Ray of pixel (px, py): pinhole camera with basis (fwd, right, up) already
+ * normalised on the host, tan_half = tan(fovy/2), aspect = W/H.  All FP32
+ * with the operation order below (no contraction). */
+static void pixel_ray(const float* cam, int W, int H, int px, int py, float org[3], float dir[3]) {
+  /* cam: eye[3], fwd[3], right[3], up[3], tan_half, aspect */
+  const float* eye = cam;
+  const float *fw = cam + 3, *rt = cam + 6, *up = cam + 9;
+  const float th = cam[12], asp = cam[13];
+  float u = (2.0f * ((float)px + 0.5f) / (float)W - 1.0f) * th * asp;
+  float v = (1.0f - 2.0f * ((float)py + 0.5f) / (float)H) * th;
+  float d[3];
+  for (int k = 0; k < 3; ++k) d[k] = fw[k] + u * rt[k] + v * up[k];
+  float nrm = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  for (int k = 0; k < 3; ++k) {
+    dir[k] = d[k] / nrm;
+    org[k] = eye[k];
+  }
+}
+
+/* Slab intersection with the box [0, S_d - 1]^3 (Kay & Kajiya 1986). */
+static int ray_box(const float org[3], const float dir[3], const int64_t S[4], float* s0,
+                   float* s1) {
+  float lo = 0.0f, hi = 3.0e38f;
+  for (int k = 0; k < 3; ++k) {
+    float a = (0.0f - org[k]) / dir[k];
+    float b = ((float)(S[k] - 1) - org[k]) / dir[k];
+    float mn = a < b ? a : b, mx = a < b ? b : a;
+    if (mn > lo) lo = mn;
+    if (mx < hi) hi = mx;
+  }
+  *s0 = lo;
+  *s1 = hi;
+  return lo < hi;
+}
+
+/* Transfer function: 256 RGBA entries, value clamped to [0,1], linear blend. */
+static void apply_tf(const float* tf, double v, double rgba[4]) {
+  if (!(v >= 0.0)) v = 0.0;
+  if (v > 1.0) v = 1.0;
+  double x = v * 255.0;
+  int i = (int)floor(x);
+  if (i > 254) i = 254;
+  double f = x - i;
+  for (int k = 0; k < 4; ++k) rgba[k] = (1.0 - f) * tf[i * 4 + k] + f * tf[(i + 1) * 4 + k];
+}
+
+/* Render one image: every pixel's ray walks the lattice s_k = s_near + (k+1/2) ds
+ * (p_k = fma(s_k, dir, org) per component, FP32); an occupied sample is
+ * evaluated by the model at (p / (S - 1), t / (T - 1)) in FP64, mapped through
+ * the transfer function and composited front to back
+ *   C += (1 - A) a c,  A += (1 - A) a,
+ * stopping after the first sample with A >= alpha_stop, or after max_steps
+ * lattice steps.  The adaptive marching pace of Algorithm 1 only changes
+ * which samples are evaluated together, never the image, so this walk is one
+ * sample at a time.  rgba: [H][W][4]; amb[H][W] flags pixels whose opacity came
+ * within 1e-5 of alpha_stop at some step (termination point rounding-sensitive).
+ * Returns the number of evaluated samples. */
+int64_t or_render(const or_grid* g, const double* table, int n_layers, const int32_t* width,
+                  const double* params, const uint8_t* mask, const int64_t S[4], const float* cam,
+                  float t, const float* tf, int W, int H, float ds, float alpha_stop,
+                  int max_steps, double* rgba, uint8_t* amb) {
+  int64_t evals = 0;
+  const int L = g->n_levels, F = g->n_features;
+  double* enc = (double*)malloc(sizeof(double) * L * F);
+  const float tn = t / (float)(S[3] - 1);
+  for (int py = 0; py < H; ++py)
+    for (int px = 0; px < W; ++px) {
+      double C[3] = {0, 0, 0}, A = 0.0;
+      int ambiguous = 0;
+      float org[3], dir[3], s0, s1;
+      pixel_ray(cam, W, H, px, py, org, dir);
+      if (ray_box(org, dir, S, &s0, &s1)) {
+        if (s0 < 0.0f) s0 = 0.0f;
+        for (int k = 0; k < max_steps; ++k) {
+          float sk = fmaf((float)k + 0.5f, ds, s0);
+          if (!(sk < s1)) break;
+          float p[3];
+          for (int d = 0; d < 3; ++d) p[d] = fmaf(sk, dir[d], org[d]);
+          if (!or_occupied(mask, S, p, t)) continue;
+          float q[4] = {p[0] / (float)(S[0] - 1), p[1] / (float)(S[1] - 1),
+                        p[2] / (float)(S[2] - 1), tn};
+          double y, ym;
+          or_encode_fwd(g, q, 1, table, enc, NULL);
+          or_mlp_fwd(n_layers, width, params, enc, 1, &y, NULL, NULL, &ym);
+          ++evals;
+          double c[4];
+          apply_tf(tf, y, c);
+          double a = c[3];
+          for (int d = 0; d < 3; ++d) C[d] += (1.0 - A) * a * c[d];
+          A += (1.0 - A) * a;
+          if (fabs(A - alpha_stop) < 1e-5) ambiguous = 1;
+          if (A >= alpha_stop) break;
+        }
+      }
+      double* o = rgba + ((int64_t)py * W + px) * 4;
+      o[0] = C[0];
+      o[1] = C[1];
+      o[2] = C[2];
+      o[3] = A;
+      if (amb) amb[(int64_t)py * W + px] = (uint8_t)ambiguous;
+    }
+  free(enc);
+  return evals;
 }

@@ -51,6 +51,11 @@ void or_cell_activity(const int64_t res[4], const uint8_t* mask, const int64_t S
 int64_t or_build_level_slots(const int64_t res[4], const uint8_t* mask, const int64_t S[4],
                              int64_t* slot_map_level);
 
+int or_cell_active_bits(const int64_t res[4], const uint64_t* bits, const int64_t S[4],
+                        const int64_t c[4]);
+int or_vertex_active_bits(const int64_t res[4], const uint64_t* bits, const int64_t S[4],
+                          const int64_t v[4]);
+
 /* ---- cell location and encoding ---------------------------------------- */
 void or_locate(float p, int64_t R, int64_t* cell, double* frac);
 int64_t or_vertex_slot(const or_grid* g, int l, const int64_t v[4]);
@@ -77,9 +82,17 @@ double or_psnr(double mse);
 /* ---- counter-based RNG and training sampler ----------------------------- */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void or_sample_ids(uint64_t seed, uint64_t step, int64_t n, uint64_t M, uint64_t* ids);
+void or_voxel_positions(const uint64_t* lin, int64_t n, const int64_t S[4], float* pos);
 void or_sample_batch(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset,
                      uint64_t M, const int64_t S[4], const float* field, float* pos,
                      float* target);
+
+/* ---- rendering --------------------------------------------------------- */
+int or_occupied(const uint8_t* mask, const int64_t S[4], const float p[3], float t);
+int64_t or_render(const or_grid* g, const double* table, int n_layers, const int32_t* width,
+                  const double* params, const uint8_t* mask, const int64_t S[4], const float* cam,
+                  float t, const float* tf, int W, int H, float ds, float alpha_stop,
+                  int max_steps, double* rgba, uint8_t* amb);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,392 @@
+"""ctypes binding of libfhash.so (the C ABI declared in include/fhash.h).
+
+Argument marshalling only: every function here has the name of the C entry
+point it calls, takes torch tensors for device buffers, passes their raw
+pointers and the current HIP stream, and raises FHashError on a non-zero
+status.  No computation happens in Python.  There is no CPU fallback: loading
+fails loudly when the HIP library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfhash.so")
+
+MAX_LEVELS = 24
+MAX_LAYERS = 8
+F32, F16, BF16 = 0, 1, 2
+OK, EINVAL, ENOMEM, EHIP, ERANGE, ENOTSUP = 0, -1, -2, -3, -4, -5
+_STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ERANGE: "ERANGE", ENOTSUP: "ENOTSUP"}
+
+
+class FHashError(RuntimeError):
+    def __init__(self, code: int, func: str, msg: str):
+        super().__init__(f"{func}: {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_features", C.c_int32),
+                ("res", (C.c_int32 * 4) * MAX_LEVELS)]
+
+
+class MaskDesc(C.Structure):
+    _fields_ = [("bits", C.c_void_p), ("dims", C.c_int64 * 4)]
+
+
+class Index(C.Structure):
+    _fields_ = [("grid", GridDesc), ("active", C.c_int32), ("reserved", C.c_int32),
+                ("dir", C.c_void_p), ("dir_offset", C.c_int64 * (MAX_LEVELS + 1)),
+                ("slot_offset", C.c_int64 * (MAX_LEVELS + 1))]
+
+
+class MlpDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("width", C.c_int32 * (MAX_LAYERS + 1)),
+                ("compute_dt", C.c_int32)]
+
+
+class AdamDesc(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("step", C.c_int64), ("grad_scale", C.c_double)]
+
+
+class View(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("fwd", C.c_float * 3), ("right", C.c_float * 3),
+                ("up", C.c_float * 3), ("tan_half_fovy", C.c_float), ("aspect", C.c_float)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("ds", C.c_float), ("alpha_stop", C.c_float), ("arm_max", C.c_int32),
+                ("max_steps", C.c_int32)]
+
+
+class RenderState(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("t", C.c_float), ("cur", C.c_int32),
+                ("n_alive", C.c_int32), ("pending", C.c_int32), ("iterations", C.c_int64),
+                ("samples", C.c_int64), ("ws", C.c_void_p), ("dims", C.c_int64 * 4)]
+
+
+class RenderStats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("samples", C.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libfhash.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "python -m paper_2507_03836_amd.build (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _declare(L):
+    P, I64, U64, I32, F = C.c_void_p, C.c_int64, C.c_uint64, C.c_int32, C.c_float
+    sig = {
+        "fhash_version": (C.c_int, []),
+        "fhash_last_error": (C.c_char_p, []),
+        "fhash_index_dir_entries": (C.c_int, [P, P]),
+        "fhash_build_index": (C.c_int, [P, P, P, P, P, P, P, P]),
+        "fhash_dense_index": (C.c_int, [P, P, P]),
+        "fhash_encode_fwd": (C.c_int, [P, P, I64, P, C.c_int, P, P]),
+        "fhash_encode_bwd": (C.c_int, [P, P, I64, P, P, P]),
+        "fhash_mlp_num_params": (I64, [P]),
+        "fhash_mlp_fwd": (C.c_int, [P, P, P, P, I64, P, P]),
+        "fhash_mlp_bwd": (C.c_int, [P, P, P, P, P, I64, P, P, P, P, P]),
+        "fhash_fused_fwd": (C.c_int, [P, P, P, I64, P, C.c_int, P, P, P, P]),
+        "fhash_fused_bwd": (C.c_int, [P, P, P, I64, P, C.c_int, P, P, P, P, P, P, P, P]),
+        "fhash_fused_train": (C.c_int, [P, P, P, P, I64, P, C.c_int, P, P, F, P, P, P, P, P, P]),
+        "fhash_step": (C.c_int, [P, P, P, P, P, P, C.c_int, I64, P, P]),
+        "fhash_check_finite": (C.c_int, [P, I64, P, P]),
+        "fhash_cast": (C.c_int, [P, P, C.c_int, I64, P]),
+        "fhash_sample": (C.c_int, [U64, U64, I64, P, U64, P, P, P, P, P]),
+        "fhash_sq_err_sum": (C.c_int, [P, P, I64, P, P]),
+        "fhash_mse_grad": (C.c_int, [P, P, I64, F, P, P, P]),
+        "fhash_render_state_bytes": (C.c_int, [I32, I32, P, P]),
+        "fhash_render_begin": (C.c_int, [P, F, I32, I32, P, P, P, C.c_size_t, P, P, P]),
+        "fhash_render_pace": (I32, [I64, I64, I32]),
+        "fhash_render_march": (C.c_int, [P, P, I32, P, I64, P, P]),
+        "fhash_render_composite": (C.c_int, [P, P, P, P, P, P]),
+        "fhash_render": (C.c_int, [P, P, P, C.c_int, P, P, P, P, F, P, I32, I32, P, P, P, P, P,
+                                   P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def exported_symbols() -> list[str]:
+    return ["fhash_version", "fhash_last_error", "fhash_index_dir_entries", "fhash_build_index",
+            "fhash_dense_index", "fhash_encode_fwd", "fhash_encode_bwd", "fhash_mlp_num_params",
+            "fhash_mlp_fwd", "fhash_mlp_bwd", "fhash_fused_fwd", "fhash_fused_bwd",
+            "fhash_fused_train", "fhash_step", "fhash_check_finite", "fhash_cast",
+            "fhash_sample", "fhash_sq_err_sum", "fhash_mse_grad", "fhash_render_state_bytes",
+            "fhash_render_begin", "fhash_render_pace", "fhash_render_march",
+            "fhash_render_composite", "fhash_render"]
+
+
+def _check(rc: int, func: str):
+    if rc != OK:
+        raise FHashError(rc, func, lib().fhash_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return C.c_void_p(t.data_ptr())
+    return t
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dt(t: torch.Tensor) -> int:
+    return {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}[t.dtype]
+
+
+# --------------------------------------------------------------------------- descriptors
+def grid_desc(res, n_features: int) -> GridDesc:
+    g = GridDesc()
+    g.n_levels = len(res)
+    g.n_features = n_features
+    for l, r in enumerate(res):
+        for d in range(4):
+            g.res[l][d] = int(r[d])
+    return g
+
+
+def mlp_desc(width, compute_dt: int = F32) -> MlpDesc:
+    m = MlpDesc()
+    m.n_layers = len(width) - 1
+    for k, w in enumerate(width):
+        m.width[k] = int(w)
+    m.compute_dt = compute_dt
+    return m
+
+
+# --------------------------------------------------------------------------- entry points
+def fhash_version() -> int:
+    return lib().fhash_version()
+
+
+def fhash_index_dir_entries(grid: GridDesc) -> int:
+    e = C.c_int64()
+    _check(lib().fhash_index_dir_entries(C.byref(grid), C.byref(e)), "fhash_index_dir_entries")
+    return e.value
+
+
+def fhash_dense_index(grid: GridDesc):
+    idx = Index()
+    slots = (C.c_int64 * MAX_LEVELS)()
+    _check(lib().fhash_dense_index(C.byref(grid), C.byref(idx), slots), "fhash_dense_index")
+    return idx, [slots[l] for l in range(grid.n_levels)]
+
+
+def fhash_build_index(grid: GridDesc, mask_bits: torch.Tensor | None, dims, dir_buf=None,
+                      ws=None):
+    """Build the index.  Returns (Index, slots_per_level, dir tensor, ws tensor).
+    dir/ws are allocated here with torch when not given (they must outlive the
+    index: the Index only points into dir)."""
+    L = lib()
+    m = MaskDesc()
+    m.bits = None if mask_bits is None else mask_bits.data_ptr()
+    for d in range(4):
+        m.dims[d] = int(dims[d])
+    if mask_bits is None:
+        return (*fhash_dense_index(grid), None, None)
+    dev = mask_bits.device
+    nb = C.c_size_t(0)
+    _check(L.fhash_build_index(C.byref(grid), C.byref(m), None, None, C.byref(nb), None, None,
+                               _stream()), "fhash_build_index")
+    if ws is None:
+        ws = torch.empty(max(int(nb.value), 16), dtype=torch.uint8, device=dev)
+    if dir_buf is None:
+        ents = fhash_index_dir_entries(grid)
+        dir_buf = torch.empty((ents, 2), dtype=torch.int64, device=dev)
+    idx = Index()
+    slots = (C.c_int64 * MAX_LEVELS)()
+    nb = C.c_size_t(ws.numel() * ws.element_size())
+    _check(L.fhash_build_index(C.byref(grid), C.byref(m), _ptr(dir_buf), _ptr(ws), C.byref(nb),
+                               C.byref(idx), slots, _stream()), "fhash_build_index")
+    return idx, [slots[l] for l in range(grid.n_levels)], dir_buf, ws
+
+
+def fhash_encode_fwd(idx: Index, pos, n, table, enc):
+    _check(lib().fhash_encode_fwd(C.byref(idx), _ptr(pos), n, _ptr(table), _dt(table), _ptr(enc),
+                                  _stream()), "fhash_encode_fwd")
+
+
+def fhash_encode_bwd(idx: Index, pos, n, d_enc, d_table):
+    _check(lib().fhash_encode_bwd(C.byref(idx), _ptr(pos), n, _ptr(d_enc), _ptr(d_table),
+                                  _stream()), "fhash_encode_bwd")
+
+
+def fhash_mlp_num_params(mlp: MlpDesc) -> int:
+    return int(lib().fhash_mlp_num_params(C.byref(mlp)))
+
+
+def fhash_mlp_fwd(mlp: MlpDesc, params, x, n, y, shadow=None):
+    _check(lib().fhash_mlp_fwd(C.byref(mlp), _ptr(params), _ptr(shadow), _ptr(x), n, _ptr(y),
+                               _stream()), "fhash_mlp_fwd")
+
+
+def _ws_query(fn, args_before_ws, name):
+    nb = C.c_size_t(0)
+    _check(fn(*args_before_ws, None, C.byref(nb), _stream()), name)
+    return int(nb.value)
+
+
+def fhash_mlp_bwd(mlp: MlpDesc, params, x, dy, n, d_params, dx=None, shadow=None, ws=None):
+    L = lib()
+    head = (C.byref(mlp), _ptr(params), _ptr(shadow), _ptr(x), _ptr(dy), n, _ptr(d_params),
+            _ptr(dx))
+    need = _ws_query(L.fhash_mlp_bwd, head, "fhash_mlp_bwd")
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(max(need, 16), dtype=torch.uint8, device=params.device)
+    nb = C.c_size_t(ws.numel() * ws.element_size())
+    _check(L.fhash_mlp_bwd(*head, _ptr(ws), C.byref(nb), _stream()), "fhash_mlp_bwd")
+    return ws
+
+
+def fhash_fused_fwd(idx: Index, mlp: MlpDesc, pos, n, table, params, y, shadow=None):
+    _check(lib().fhash_fused_fwd(C.byref(idx), C.byref(mlp), _ptr(pos), n, _ptr(table),
+                                 _dt(table), _ptr(params), _ptr(shadow), _ptr(y), _stream()),
+           "fhash_fused_fwd")
+
+
+def fhash_fused_bwd(idx: Index, mlp: MlpDesc, pos, n, table, params, dy, d_table, d_params,
+                    shadow=None, ws=None):
+    L = lib()
+    head = (C.byref(idx), C.byref(mlp), _ptr(pos), n, _ptr(table), _dt(table), _ptr(params),
+            _ptr(shadow), _ptr(dy), _ptr(d_table), _ptr(d_params))
+    need = _ws_query(L.fhash_fused_bwd, head, "fhash_fused_bwd")
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(max(need, 16), dtype=torch.uint8, device=params.device)
+    nb = C.c_size_t(ws.numel() * ws.element_size())
+    _check(L.fhash_fused_bwd(*head, _ptr(ws), C.byref(nb), _stream()), "fhash_fused_bwd")
+    return ws
+
+
+def fhash_fused_train(idx: Index, mlp: MlpDesc, pos, target, n, table, params, d_table,
+                      d_params, loss_sum=None, loss_scale=1.0, shadow=None, ws=None):
+    L = lib()
+    head = (C.byref(idx), C.byref(mlp), _ptr(pos), _ptr(target), n, _ptr(table), _dt(table),
+            _ptr(params), _ptr(shadow), C.c_float(loss_scale), _ptr(d_table), _ptr(d_params),
+            _ptr(loss_sum))
+    need = _ws_query(L.fhash_fused_train, head, "fhash_fused_train")
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(max(need, 16), dtype=torch.uint8, device=params.device)
+    nb = C.c_size_t(ws.numel() * ws.element_size())
+    _check(L.fhash_fused_train(*head, _ptr(ws), C.byref(nb), _stream()), "fhash_fused_train")
+    return ws
+
+
+def fhash_step(opt: AdamDesc, param, grad, m, v, shadow=None, found_inf=None):
+    sdt = F16 if shadow is None else _dt(shadow)
+    _check(lib().fhash_step(C.byref(opt), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
+                            _ptr(shadow), sdt, param.numel(), _ptr(found_inf), _stream()),
+           "fhash_step")
+
+
+def fhash_check_finite(grad, found_inf):
+    _check(lib().fhash_check_finite(_ptr(grad), grad.numel(), _ptr(found_inf), _stream()),
+           "fhash_check_finite")
+
+
+def fhash_cast(src, dst):
+    _check(lib().fhash_cast(_ptr(src), _ptr(dst), _dt(dst), src.numel(), _stream()), "fhash_cast")
+
+
+def fhash_sample(seed, step, n, coreset, M, dims, field, pos, target):
+    d = (C.c_int64 * 4)(*[int(x) for x in dims])
+    _check(lib().fhash_sample(seed, step, n, _ptr(coreset), M, d, _ptr(field), _ptr(pos),
+                              _ptr(target), _stream()), "fhash_sample")
+
+
+def fhash_sq_err_sum(y, v, n, out):
+    _check(lib().fhash_sq_err_sum(_ptr(y), _ptr(v), n, _ptr(out), _stream()), "fhash_sq_err_sum")
+
+
+def fhash_mse_grad(y, v, n, dy, loss_sum=None, loss_scale=1.0):
+    _check(lib().fhash_mse_grad(_ptr(y), _ptr(v), n, C.c_float(loss_scale), _ptr(dy),
+                                _ptr(loss_sum), _stream()), "fhash_mse_grad")
+
+
+# --------------------------------------------------------------------------- rendering
+def view_struct(v14) -> View:
+    """View from 14 floats: eye, fwd, right, up, tan_half_fovy, aspect."""
+    v = View()
+    for k in range(3):
+        v.eye[k], v.fwd[k], v.right[k], v.up[k] = (float(v14[k]), float(v14[3 + k]),
+                                                    float(v14[6 + k]), float(v14[9 + k]))
+    v.tan_half_fovy, v.aspect = float(v14[12]), float(v14[13])
+    return v
+
+
+def render_opts(ds=0.5, alpha_stop=0.99, arm_max=64, max_steps=1 << 20) -> RenderOpts:
+    o = RenderOpts()
+    o.ds, o.alpha_stop, o.arm_max, o.max_steps = ds, alpha_stop, arm_max, max_steps
+    return o
+
+
+def _dims(d):
+    return (C.c_int64 * 4)(*[int(x) for x in d])
+
+
+def fhash_render(idx, mlp, table, params, mask_bits, dims, view: View, t, tf, W, H,
+                 opts: RenderOpts, rgba, ws=None):
+    L = lib()
+    head = (C.byref(idx), C.byref(mlp), _ptr(table), _dt(table), _ptr(params), _ptr(mask_bits),
+            _dims(dims), C.byref(view), C.c_float(t), _ptr(tf), W, H, C.byref(opts), _ptr(rgba))
+    nb = C.c_size_t(0)
+    _check(L.fhash_render(*head, None, C.byref(nb), None, _stream()), "fhash_render")
+    if ws is None or ws.numel() < nb.value:
+        ws = torch.empty(max(int(nb.value), 16), dtype=torch.uint8, device=rgba.device)
+    nb = C.c_size_t(ws.numel())
+    st = RenderStats()
+    _check(L.fhash_render(*head, _ptr(ws), C.byref(nb), C.byref(st), _stream()), "fhash_render")
+    return st, ws
+
+
+def fhash_render_state_bytes(W, H, dims) -> int:
+    nb = C.c_size_t(0)
+    _check(lib().fhash_render_state_bytes(W, H, _dims(dims), C.byref(nb)),
+           "fhash_render_state_bytes")
+    return int(nb.value)
+
+
+def fhash_render_begin(view: View, t, W, H, mask_bits, dims, ws, rgba) -> RenderState:
+    st = RenderState()
+    _check(lib().fhash_render_begin(C.byref(view), C.c_float(t), W, H, _ptr(mask_bits),
+                                    _dims(dims), _ptr(ws), ws.numel() * ws.element_size(),
+                                    _ptr(rgba), C.byref(st), _stream()), "fhash_render_begin")
+    return st
+
+
+def fhash_render_pace(budget, alive, arm_max) -> int:
+    return int(lib().fhash_render_pace(int(budget), int(alive), int(arm_max)))
+
+
+def fhash_render_march(st: RenderState, opts: RenderOpts, pace, pos_out, cap) -> int:
+    ns = C.c_int64(0)
+    _check(lib().fhash_render_march(C.byref(st), C.byref(opts), pace, _ptr(pos_out), cap,
+                                    C.byref(ns), _stream()), "fhash_render_march")
+    return ns.value
+
+
+def fhash_render_composite(st: RenderState, y, tf, opts: RenderOpts, rgba):
+    _check(lib().fhash_render_composite(C.byref(st), _ptr(y), _ptr(tf), C.byref(opts), _ptr(rgba),
+                                        _stream()), "fhash_render_composite")

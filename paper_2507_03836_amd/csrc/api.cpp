@@ -1,0 +1,577 @@
+// C ABI of libfhash: host-side validation, workspace sizing and dispatch to the
+// HIP kernels.  No exception crosses this boundary; every entry point returns a
+// status code and records a message for fhash_last_error().
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.h"
+#include "fhash.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_status(hipError_t e, const char* where) {
+  if (e == hipSuccess) return FHASH_OK;
+  return fail(FHASH_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int check_grid(const fhash_grid_desc* g) {
+  if (g == nullptr) return fail(FHASH_EINVAL, "grid descriptor is NULL");
+  if (g->n_levels < 1 || g->n_levels > FHASH_MAX_LEVELS)
+    return fail(FHASH_EINVAL, "n_levels %d outside [1, %d]", g->n_levels, FHASH_MAX_LEVELS);
+  const int F = g->n_features;
+  if (F != 1 && F != 2 && F != 4 && F != 8)
+    return fail(FHASH_EINVAL, "n_features %d not in {1, 2, 4, 8}", F);
+  for (int l = 0; l < g->n_levels; ++l) {
+    double nv = 1.0;
+    for (int d = 0; d < 4; ++d) {
+      const int r = g->res[l][d];
+      if (r < 2 || r > (1 << 24))
+        return fail(FHASH_EINVAL, "res[%d][%d] = %d outside [2, 2^24]", l, d, r);
+      nv *= r;
+    }
+    if (nv >= 4.0e18) return fail(FHASH_ERANGE, "level %d has too many vertices", l);
+  }
+  return FHASH_OK;
+}
+
+int check_index(const fhash_index* idx) {
+  if (idx == nullptr) return fail(FHASH_EINVAL, "index is NULL");
+  int rc = check_grid(&idx->grid);
+  if (rc) return rc;
+  if (idx->active != 0 && idx->active != 1) return fail(FHASH_EINVAL, "index.active must be 0/1");
+  if (idx->active && idx->dir == nullptr) return fail(FHASH_EINVAL, "active index without dir");
+  for (int l = 0; l < idx->grid.n_levels; ++l)
+    if (idx->slot_offset[l + 1] < idx->slot_offset[l] || idx->slot_offset[l] < 0)
+      return fail(FHASH_EINVAL, "slot_offset not monotone at level %d", l);
+  return FHASH_OK;
+}
+
+int64_t total_rows(const fhash_index* idx) { return idx->slot_offset[idx->grid.n_levels]; }
+
+int check_table_dt(fhash_dtype dt) {
+  if (dt != FHASH_F32 && dt != FHASH_F16)
+    return fail(FHASH_ENOTSUP, "table dtype %d not supported (F32 or F16)", (int)dt);
+  return FHASH_OK;
+}
+
+// Decoder shape: width[0] input, hidden widths all equal H, output width 1.
+int check_mlp(const fhash_mlp_desc* m, int* H, int* NH) {
+  if (m == nullptr) return fail(FHASH_EINVAL, "mlp descriptor is NULL");
+  if (m->n_layers < 2 || m->n_layers > FHASH_MAX_LAYERS)
+    return fail(FHASH_EINVAL, "n_layers %d outside [2, %d]", m->n_layers, FHASH_MAX_LAYERS);
+  for (int k = 0; k <= m->n_layers; ++k)
+    if (m->width[k] < 1) return fail(FHASH_EINVAL, "width[%d] = %d", k, m->width[k]);
+  if (m->width[m->n_layers] != 1) return fail(FHASH_ENOTSUP, "output width must be 1");
+  const int h = m->width[1];
+  for (int k = 1; k < m->n_layers; ++k)
+    if (m->width[k] != h) return fail(FHASH_ENOTSUP, "hidden widths must be equal");
+  if (m->compute_dt != FHASH_F32)
+    return fail(FHASH_ENOTSUP, "mlp compute dtype %d not built", (int)m->compute_dt);
+  if (!fh::mlp_supported(m->width[0], h, m->n_layers - 1))
+    return fail(FHASH_ENOTSUP, "mlp shape in=%d hidden=%d x %d not built", m->width[0], h,
+                m->n_layers - 1);
+  *H = h;
+  *NH = m->n_layers - 1;
+  return FHASH_OK;
+}
+
+int64_t num_params(const fhash_mlp_desc* m) {
+  int64_t p = 0;
+  for (int k = 0; k < m->n_layers; ++k) p += (int64_t)m->width[k + 1] * m->width[k] + m->width[k + 1];
+  return p;
+}
+
+int ws_check(void* ws, size_t* ws_bytes, size_t need, bool* query) {
+  *query = false;
+  if (ws_bytes == nullptr) return fail(FHASH_EINVAL, "ws_bytes is NULL");
+  if (ws == nullptr) {
+    *ws_bytes = need;
+    *query = true;
+    return FHASH_OK;
+  }
+  if (*ws_bytes < need)
+    return fail(FHASH_ENOMEM, "workspace %zu bytes, need %zu", *ws_bytes, need);
+  if (!aligned16(ws)) return fail(FHASH_EINVAL, "workspace not 16-byte aligned");
+  return FHASH_OK;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+int fhash_version(void) { return FHASH_VERSION; }
+const char* fhash_last_error(void) { return g_err; }
+
+int fhash_index_dir_entries(const fhash_grid_desc* grid, int64_t* entries) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (entries == nullptr) return fail(FHASH_EINVAL, "entries is NULL");
+  int64_t e = 0;
+  for (int l = 0; l < grid->n_levels; ++l) e += fh::index_dir_words(grid, l);
+  *entries = e;
+  return FHASH_OK;
+}
+
+int fhash_dense_index(const fhash_grid_desc* grid, fhash_index* out, int64_t* slots_per_level) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (out == nullptr) return fail(FHASH_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  out->grid = *grid;
+  out->active = 0;
+  out->dir = nullptr;
+  int64_t off = 0;
+  for (int l = 0; l < grid->n_levels; ++l) {
+    const int32_t* r = grid->res[l];
+    const int64_t nv = (int64_t)r[0] * r[1] * r[2] * r[3];
+    out->slot_offset[l] = off;
+    if (slots_per_level) slots_per_level[l] = nv;
+    off += nv;
+  }
+  for (int l = grid->n_levels; l <= FHASH_MAX_LEVELS; ++l) out->slot_offset[l] = off;
+  return FHASH_OK;
+}
+
+int fhash_build_index(const fhash_grid_desc* grid, const fhash_mask_desc* mask, void* dir,
+                      void* ws, size_t* ws_bytes, fhash_index* out, int64_t* slots_per_level,
+                      void* stream) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (mask == nullptr) return fail(FHASH_EINVAL, "mask descriptor is NULL");
+  if (mask->bits == nullptr) {
+    if (ws == nullptr && ws_bytes != nullptr) {
+      *ws_bytes = 0;
+      return FHASH_OK;
+    }
+    return fhash_dense_index(grid, out, slots_per_level);
+  }
+  for (int d = 0; d < 4; ++d)
+    if (mask->dims[d] < 2 || mask->dims[d] > (int64_t)1 << 31)
+      return fail(FHASH_EINVAL, "mask dims[%d] = %lld outside [2, 2^31]", d,
+                  (long long)mask->dims[d]);
+  const size_t need = fh::index_workspace_bytes(grid, mask->dims);
+  bool query;
+  rc = ws_check(ws, ws_bytes, need, &query);
+  if (rc || query) return rc;
+  if (dir == nullptr || out == nullptr || slots_per_level == nullptr)
+    return fail(FHASH_EINVAL, "dir, out and slots_per_level must be non-NULL");
+  if (!aligned16(dir)) return fail(FHASH_EINVAL, "dir not 16-byte aligned");
+  std::memset(out, 0, sizeof(*out));
+  out->grid = *grid;
+  out->active = 1;
+  out->dir = dir;
+  int64_t e = 0;
+  for (int l = 0; l < grid->n_levels; ++l) {
+    out->dir_offset[l] = e;
+    e += fh::index_dir_words(grid, l);
+  }
+  for (int l = grid->n_levels; l <= FHASH_MAX_LEVELS; ++l) out->dir_offset[l] = e;
+  uint64_t counts[FHASH_MAX_LEVELS];
+  hipError_t he = fh::launch_build_index(grid, mask->bits, mask->dims,
+                                         reinterpret_cast<ulonglong2*>(dir), out->dir_offset, ws,
+                                         counts, S(stream));
+  if (he != hipSuccess) return hip_status(he, "fhash_build_index");
+  int64_t off = 0;
+  for (int l = 0; l < grid->n_levels; ++l) {
+    out->slot_offset[l] = off;
+    slots_per_level[l] = (int64_t)counts[l];
+    off += (int64_t)counts[l];
+  }
+  for (int l = grid->n_levels; l <= FHASH_MAX_LEVELS; ++l) out->slot_offset[l] = off;
+  return FHASH_OK;
+}
+
+int fhash_encode_fwd(const fhash_index* idx, const float* pos, int64_t n, const void* table,
+                     fhash_dtype table_dt, float* enc, void* stream) {
+  int rc = check_index(idx);
+  if (rc) return rc;
+  if ((rc = check_table_dt(table_dt))) return rc;
+  if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  if (n == 0) return FHASH_OK;
+  if (pos == nullptr || enc == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
+  if (!aligned16(pos)) return fail(FHASH_EINVAL, "pos not 16-byte aligned");
+  const int64_t L = idx->grid.n_levels, F = idx->grid.n_features;
+  if (total_rows(idx) == 0)
+    return hip_status(hipMemsetAsync(enc, 0, sizeof(float) * n * L * F, S(stream)),
+                      "fhash_encode_fwd");
+  if (table == nullptr) return fail(FHASH_EINVAL, "table is NULL");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  return hip_status(fh::launch_encode_fwd(g, pos, n, table, table_dt, enc, S(stream)),
+                    "fhash_encode_fwd");
+}
+
+int fhash_encode_bwd(const fhash_index* idx, const float* pos, int64_t n, const float* d_enc,
+                     float* d_table, void* stream) {
+  int rc = check_index(idx);
+  if (rc) return rc;
+  if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  if (n == 0 || total_rows(idx) == 0) return FHASH_OK;
+  if (pos == nullptr || d_enc == nullptr || d_table == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (!aligned16(pos)) return fail(FHASH_EINVAL, "pos not 16-byte aligned");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  return hip_status(fh::launch_encode_bwd(g, pos, n, d_enc, d_table, S(stream)),
+                    "fhash_encode_bwd");
+}
+
+int64_t fhash_mlp_num_params(const fhash_mlp_desc* mlp) {
+  if (mlp == nullptr || mlp->n_layers < 1 || mlp->n_layers > FHASH_MAX_LAYERS) return -1;
+  return num_params(mlp);
+}
+
+int fhash_mlp_fwd(const fhash_mlp_desc* mlp, const float* params, const void* shadow,
+                  const float* x, int64_t n, float* y, void* stream) {
+  (void)shadow;
+  int H, NH;
+  int rc = check_mlp(mlp, &H, &NH);
+  if (rc) return rc;
+  if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  if (n == 0) return FHASH_OK;
+  if (params == nullptr || x == nullptr || y == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
+  return hip_status(fh::launch_mlp_fwd(mlp->width[0], H, NH, params, x, n, y, S(stream)),
+                    "fhash_mlp_fwd");
+}
+
+int fhash_mlp_bwd(const fhash_mlp_desc* mlp, const float* params, const void* shadow,
+                  const float* x, const float* dy, int64_t n, float* d_params, float* dx,
+                  void* ws, size_t* ws_bytes, void* stream) {
+  (void)shadow;
+  int H, NH;
+  int rc = check_mlp(mlp, &H, &NH);
+  if (rc) return rc;
+  if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  const int64_t P = num_params(mlp);
+  bool query;
+  rc = ws_check(ws, ws_bytes, fh::mlp_bwd_ws_bytes(n, P), &query);
+  if (rc || query) return rc;
+  if (n == 0) return FHASH_OK;
+  if (params == nullptr || x == nullptr || dy == nullptr || d_params == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  return hip_status(
+      fh::launch_mlp_bwd(mlp->width[0], H, NH, params, x, dy, n, d_params, dx, ws, P, S(stream)),
+      "fhash_mlp_bwd");
+}
+
+static int check_fused(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
+                       int64_t n, const void* table, fhash_dtype tdt, const float* params,
+                       int* H, int* NH) {
+  int rc = check_index(idx);
+  if (rc) return rc;
+  if ((rc = check_mlp(mlp, H, NH))) return rc;
+  if ((rc = check_table_dt(tdt))) return rc;
+  const int in_w = idx->grid.n_levels * idx->grid.n_features;
+  if (mlp->width[0] != in_w)
+    return fail(FHASH_EINVAL, "mlp input width %d != L*F = %d", mlp->width[0], in_w);
+  if (!fh::fused_supported(idx->grid.n_features, in_w, *H, *NH))
+    return fail(FHASH_ENOTSUP, "fused path not built for F=%d in=%d hidden=%dx%d",
+                idx->grid.n_features, in_w, *H, *NH);
+  if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  if (n > 0 && (pos == nullptr || params == nullptr)) return fail(FHASH_EINVAL, "NULL pointer");
+  if (n > 0 && !aligned16(pos)) return fail(FHASH_EINVAL, "pos not 16-byte aligned");
+  if (n > 0 && total_rows(idx) == 0)
+    return fail(FHASH_EINVAL, "index has no active vertex (empty table)");
+  if (n > 0 && table == nullptr) return fail(FHASH_EINVAL, "table is NULL");
+  return FHASH_OK;
+}
+
+int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
+                    const void* table, fhash_dtype table_dt, const float* params,
+                    const void* shadow, float* y, void* stream) {
+  (void)shadow;
+  int H, NH;
+  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
+  if (rc) return rc;
+  if (n == 0) return FHASH_OK;
+  if (y == nullptr) return fail(FHASH_EINVAL, "y is NULL");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  return hip_status(
+      fh::launch_fused_fwd(g, H, NH, pos, n, table, table_dt, params, y, S(stream)),
+      "fhash_fused_fwd");
+}
+
+int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
+                    const void* table, fhash_dtype table_dt, const float* params,
+                    const void* shadow, const float* dy, float* d_table, float* d_params,
+                    void* ws, size_t* ws_bytes, void* stream) {
+  (void)shadow;
+  int H, NH;
+  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
+  if (rc) return rc;
+  const int64_t P = num_params(mlp);
+  bool query;
+  rc = ws_check(ws, ws_bytes, fh::fused_ws_bytes(n, P), &query);
+  if (rc || query) return rc;
+  if (n == 0) return FHASH_OK;
+  if (dy == nullptr || d_table == nullptr || d_params == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  return hip_status(fh::launch_fused_bwd(g, H, NH, pos, n, table, table_dt, params, dy, d_table,
+                                         d_params, ws, P, S(stream)),
+                    "fhash_fused_bwd");
+}
+
+int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
+                      const float* target, int64_t n, const void* table, fhash_dtype table_dt,
+                      const float* params, const void* shadow, float loss_scale, float* d_table,
+                      float* d_params, double* loss_sum, void* ws, size_t* ws_bytes,
+                      void* stream) {
+  (void)shadow;
+  int H, NH;
+  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
+  if (rc) return rc;
+  const int64_t P = num_params(mlp);
+  bool query;
+  rc = ws_check(ws, ws_bytes, fh::fused_ws_bytes(n, P), &query);
+  if (rc || query) return rc;
+  if (n == 0) return FHASH_OK;
+  if (target == nullptr || d_table == nullptr || d_params == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  return hip_status(fh::launch_fused_train(g, H, NH, pos, target, n, table, table_dt, params,
+                                           loss_scale, d_table, d_params, loss_sum, ws, P,
+                                           S(stream)),
+                    "fhash_fused_train");
+}
+
+int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
+               void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
+               void* stream) {
+  if (opt == nullptr) return fail(FHASH_EINVAL, "optimiser descriptor is NULL");
+  if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  if (opt->step < 1) return fail(FHASH_EINVAL, "step must be >= 1");
+  if (!(opt->lr >= 0.0) || !(opt->beta1 >= 0.0 && opt->beta1 < 1.0) ||
+      !(opt->beta2 >= 0.0 && opt->beta2 < 1.0) || !(opt->eps > 0.0))
+    return fail(FHASH_EINVAL, "bad Adam hyper-parameters");
+  if (n == 0) return FHASH_OK;
+  if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
+    return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
+  if (shadow != nullptr) {
+    if (shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
+      return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
+    if ((reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)
+      return fail(FHASH_EINVAL, "shadow must be 8-byte aligned");
+  }
+  return hip_status(
+      fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, n, found_inf, S(stream)),
+      "fhash_step");
+}
+
+int fhash_check_finite(const float* grad, int64_t n, int32_t* found_inf, void* stream) {
+  if (n < 0 || found_inf == nullptr || (n > 0 && grad == nullptr))
+    return fail(FHASH_EINVAL, "bad arguments");
+  return hip_status(fh::launch_check_finite(grad, n, found_inf, S(stream)), "fhash_check_finite");
+}
+
+int fhash_cast(const float* src, void* dst, fhash_dtype dst_dt, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (src == nullptr || dst == nullptr)))
+    return fail(FHASH_EINVAL, "bad arguments");
+  if (dst_dt != FHASH_F16 && dst_dt != FHASH_BF16)
+    return fail(FHASH_EINVAL, "cast target must be F16 or BF16");
+  return hip_status(fh::launch_cast(src, dst, dst_dt, n, S(stream)), "fhash_cast");
+}
+
+int fhash_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset, uint64_t M,
+                 const int64_t dims[4], const float* field, float* pos, float* target,
+                 void* stream) {
+  if (n < 0 || dims == nullptr) return fail(FHASH_EINVAL, "bad arguments");
+  for (int d = 0; d < 4; ++d)
+    if (dims[d] < 2 || dims[d] > (1 << 24))
+      return fail(FHASH_EINVAL, "dims[%d] outside [2, 2^24]", d);
+  const uint64_t nvox = (uint64_t)dims[0] * dims[1] * dims[2] * dims[3];
+  if (coreset == nullptr && M != nvox)
+    return fail(FHASH_EINVAL, "without a coreset M must be the voxel count");
+  if (n == 0) return FHASH_OK;
+  if (M == 0) return fail(FHASH_EINVAL, "M == 0");
+  if (field == nullptr || pos == nullptr || target == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (!aligned16(pos)) return fail(FHASH_EINVAL, "pos not 16-byte aligned");
+  return hip_status(
+      fh::launch_sample(seed, step, n, coreset, M, dims, field, pos, target, S(stream)),
+      "fhash_sample");
+}
+
+int fhash_sq_err_sum(const float* y, const float* v, int64_t n, double* sum, void* stream) {
+  if (n < 0 || sum == nullptr || (n > 0 && (y == nullptr || v == nullptr)))
+    return fail(FHASH_EINVAL, "bad arguments");
+  return hip_status(fh::launch_sq_err(y, v, n, sum, S(stream)), "fhash_sq_err_sum");
+}
+
+int fhash_mse_grad(const float* y, const float* v, int64_t n, float loss_scale, float* dy,
+                   double* loss_sum, void* stream) {
+  if (n < 0 || (n > 0 && (y == nullptr || v == nullptr || dy == nullptr)))
+    return fail(FHASH_EINVAL, "bad arguments");
+  const float coef = n > 0 ? (float)(2.0 * (double)loss_scale / (double)n) : 0.0f;
+  return hip_status(fh::launch_mse_grad(y, v, n, coef, dy, loss_sum, S(stream)), "fhash_mse_grad");
+}
+
+static int check_dims(const int64_t* dims) {
+  if (dims == nullptr) return fail(FHASH_EINVAL, "dims is NULL");
+  for (int d = 0; d < 4; ++d)
+    if (dims[d] < 2 || dims[d] > (1 << 24)) return fail(FHASH_EINVAL, "dims[%d] outside [2, 2^24]", d);
+  return FHASH_OK;
+}
+
+static int check_opts(const fhash_render_opts* o) {
+  if (o == nullptr) return fail(FHASH_EINVAL, "render options are NULL");
+  if (!(o->ds > 0.0f) || !(o->alpha_stop > 0.0f && o->alpha_stop <= 1.0f) || o->arm_max < 1 ||
+      o->max_steps < 1)
+    return fail(FHASH_EINVAL, "bad render options");
+  return FHASH_OK;
+}
+
+int fhash_render_state_bytes(int32_t W, int32_t H, const int64_t dims[4], size_t* bytes) {
+  int rc = check_dims(dims);
+  if (rc) return rc;
+  if (W < 1 || H < 1 || (int64_t)W * H > (int64_t)1 << 30 || bytes == nullptr)
+    return fail(FHASH_EINVAL, "bad image size");
+  *bytes = fh::render_ws_bytes((int64_t)W * H, dims);
+  return FHASH_OK;
+}
+
+int fhash_render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
+                       const uint64_t* mask_bits, const int64_t dims[4], void* ws,
+                       size_t ws_bytes, float* rgba, fhash_render_state* state, void* stream) {
+  size_t need;
+  int rc = fhash_render_state_bytes(W, H, dims, &need);
+  if (rc) return rc;
+  if (view == nullptr || mask_bits == nullptr || ws == nullptr || rgba == nullptr ||
+      state == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (ws_bytes < need) return fail(FHASH_ENOMEM, "render workspace %zu < %zu", ws_bytes, need);
+  if (!aligned16(ws) || !aligned16(rgba)) return fail(FHASH_EINVAL, "ws/rgba not 16-byte aligned");
+  if (!(t >= 0.0f) || t > (float)(dims[3] - 1)) return fail(FHASH_EINVAL, "t outside [0, T-1]");
+  std::memset(state, 0, sizeof(*state));
+  state->W = W;
+  state->H = H;
+  state->t = t;
+  state->ws = ws;
+  for (int d = 0; d < 4; ++d) state->dims[d] = dims[d];
+  int32_t na = 0;
+  hipError_t e = fh::launch_render_begin(view, W, H, mask_bits, dims, t, ws, &na, rgba, S(stream));
+  if (e != hipSuccess) return hip_status(e, "fhash_render_begin");
+  state->n_alive = na;
+  state->cur = 0;
+  return FHASH_OK;
+}
+
+int32_t fhash_render_pace(int64_t budget, int64_t alive, int32_t arm_max) {
+  if (alive <= 0) return 1;
+  int64_t p = budget / alive;
+  if (p > arm_max) p = arm_max;
+  if (p < 1) p = 1;
+  return (int32_t)p;
+}
+
+int fhash_render_march(fhash_render_state* state, const fhash_render_opts* opts, int32_t pace,
+                       float* pos_out, int64_t cap, int64_t* n_samples, void* stream) {
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (state == nullptr || state->ws == nullptr || n_samples == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (pace < 1 || pace > opts->arm_max) return fail(FHASH_EINVAL, "pace outside [1, arm_max]");
+  if (state->pending) return fail(FHASH_EINVAL, "previous samples not composited");
+  if ((int64_t)pace * state->n_alive > cap)
+    return fail(FHASH_EINVAL, "sample buffer %lld < pace * alive", (long long)cap);
+  if (state->n_alive > 0 && (pos_out == nullptr || !aligned16(pos_out)))
+    return fail(FHASH_EINVAL, "pos_out NULL or not 16-byte aligned");
+  int32_t ns = 0;
+  hipError_t e = fh::launch_render_march(state->ws, state->W, state->H, state->dims, state->t,
+                                         opts->ds, opts->max_steps, pace, state->cur,
+                                         state->n_alive, pos_out, &ns, S(stream));
+  if (e != hipSuccess) return hip_status(e, "fhash_render_march");
+  *n_samples = ns;
+  state->pending = 1;
+  state->samples += ns;
+  return FHASH_OK;
+}
+
+int fhash_render_composite(fhash_render_state* state, const float* y, const float* tf,
+                           const fhash_render_opts* opts, float* rgba, void* stream) {
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (state == nullptr || state->ws == nullptr || tf == nullptr || rgba == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (!state->pending) return fail(FHASH_EINVAL, "composite without a march");
+  int32_t na = 0;
+  hipError_t e = fh::launch_render_composite(state->ws, state->W, state->H, state->cur,
+                                             state->n_alive, y, tf, opts->alpha_stop, rgba, &na,
+                                             S(stream));
+  if (e != hipSuccess) return hip_status(e, "fhash_render_composite");
+  state->cur = 1 - state->cur;
+  state->n_alive = na;
+  state->pending = 0;
+  state->iterations += 1;
+  return FHASH_OK;
+}
+
+int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* table,
+                 fhash_dtype table_dt, const float* params, const uint64_t* mask_bits,
+                 const int64_t dims[4], const fhash_view* view, float t, const float* tf,
+                 int32_t W, int32_t H, const fhash_render_opts* opts, float* rgba, void* ws,
+                 size_t* ws_bytes, fhash_render_stats* stats, void* stream) {
+  size_t sbytes;
+  int rc = fhash_render_state_bytes(W, H, dims, &sbytes);
+  if (rc) return rc;
+  if ((rc = check_opts(opts))) return rc;
+  const int64_t NR = (int64_t)W * H;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t need = al(sbytes) + al(NR * 16) + al(NR * 4);
+  bool query;
+  rc = ws_check(ws, ws_bytes, need, &query);
+  if (rc || query) return rc;
+  int H_, NH;
+  if ((rc = check_fused(idx, mlp, nullptr, 0, table, table_dt, params, &H_, &NH))) return rc;
+  if (total_rows(idx) == 0) return fail(FHASH_EINVAL, "index has no active vertex");
+  char* p = static_cast<char*>(ws);
+  float* pos = reinterpret_cast<float*>(p + al(sbytes));
+  float* y = reinterpret_cast<float*>(p + al(sbytes) + al(NR * 16));
+  fhash_render_state st;
+  rc = fhash_render_begin(view, t, W, H, mask_bits, dims, ws, sbytes, rgba, &st, stream);
+  if (rc) return rc;
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  while (st.n_alive > 0) {
+    const int32_t pace = fhash_render_pace(NR, st.n_alive, opts->arm_max);
+    int64_t ns = 0;
+    rc = fhash_render_march(&st, opts, pace, pos, NR, &ns, stream);
+    if (rc) return rc;
+    if (ns > 0) {
+      hipError_t e = fh::launch_fused_fwd(g, H_, NH, pos, ns, table, table_dt, params, y, S(stream));
+      if (e != hipSuccess) return hip_status(e, "fhash_render decode");
+    }
+    rc = fhash_render_composite(&st, y, tf, opts, rgba, stream);
+    if (rc) return rc;
+  }
+  if (stats) {
+    stats->iterations = st.iterations;
+    stats->samples = st.samples;
+  }
+  return FHASH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal definitions shared by the HIP kernels and the C-ABI layer of libfhash.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fhash.h"
+
+namespace fh {
+
+// Per-level constants, passed by value in kernel arguments (wave-uniform loads).
+struct LevelDev {
+  int32_t rx, ry, rz, rt;  // vertex counts
+  float sx, sy, sz, st;    // (float)(R - 1), the FP32 scale of cell location
+  int32_t wv;              // directory words per vertex row: ceil(rx / 64)
+  int32_t pad0;
+  int64_t slot_off;        // first table row of the level
+  int64_t dir_off;         // first directory entry of the level
+  int64_t pad1;
+};
+static_assert(sizeof(LevelDev) == 64, "LevelDev layout");
+
+struct GridDev {
+  LevelDev lv[FHASH_MAX_LEVELS];
+  const ulonglong2* dir;  // {bits, rank-before-word}; NULL when dense
+  int32_t L, F;
+  int32_t active;
+  int32_t pad;
+};
+
+// Fill a GridDev from a public index descriptor (host).
+inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
+  const fhash_grid_desc& gd = idx->grid;
+  g->L = gd.n_levels;
+  g->F = gd.n_features;
+  g->active = idx->active;
+  g->dir = reinterpret_cast<const ulonglong2*>(idx->dir);
+  g->pad = 0;
+  for (int l = 0; l < FHASH_MAX_LEVELS; ++l) {
+    LevelDev& d = g->lv[l];
+    if (l < gd.n_levels) {
+      d.rx = gd.res[l][0];
+      d.ry = gd.res[l][1];
+      d.rz = gd.res[l][2];
+      d.rt = gd.res[l][3];
+      d.sx = (float)(d.rx - 1);
+      d.sy = (float)(d.ry - 1);
+      d.sz = (float)(d.rz - 1);
+      d.st = (float)(d.rt - 1);
+      d.wv = (d.rx + 63) / 64;
+      d.slot_off = idx->slot_offset[l];
+      d.dir_off = idx->dir_offset[l];
+    } else {
+      d = LevelDev{};
+    }
+    d.pad0 = 0;
+    d.pad1 = 0;
+  }
+}
+
+#ifdef __HIPCC__
+// Cell location along one dimension (Sec. 3.2.4 steps 1-2).  Clamp to [0,1]
+// (NaN -> 0 via IEEE maxNum), one FP32 multiply, floor, clamp to R-2, exact
+// fraction.  __fmul_rn / __fsub_rn keep the compiler from contracting.
+__device__ __forceinline__ void locate(float p, int R, float s, int& cell, float& frac) {
+  p = fminf(fmaxf(p, 0.0f), 1.0f);
+  float u = __fmul_rn(p, s);
+  int i = (int)floorf(u);
+  i = min(i, R - 2);
+  cell = i;
+  frac = __fsub_rn(u, (float)i);
+}
+
+// Slots of the vertex pair (x, x+1) on one vertex row of a level.  Dense: the
+// F-Hash equation; active: rank in the directory entry of the word holding x.
+__device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglong2* dir,
+                                               bool active, int64_t row, int x, int64_t& s0,
+                                               int64_t& s1, bool& v0, bool& v1) {
+  if (!active) {
+    s0 = d.slot_off + row * (int64_t)d.rx + x;
+    s1 = s0 + 1;
+    v0 = v1 = true;
+    return;
+  }
+  const int64_t w = d.dir_off + row * (int64_t)d.wv + (x >> 6);
+  const int b = x & 63;
+  const ulonglong2 e = dir[w];
+  const uint64_t below = (b == 0) ? 0ull : (e.x & ((1ull << b) - 1ull));
+  v0 = (e.x >> b) & 1ull;
+  s0 = d.slot_off + (int64_t)e.y + __popcll(below);
+  if (b < 63) {
+    v1 = (e.x >> (b + 1)) & 1ull;
+    s1 = s0 + (v0 ? 1 : 0);
+  } else {
+    const ulonglong2 e1 = dir[w + 1];
+    v1 = e1.x & 1ull;
+    s1 = d.slot_off + (int64_t)e1.y;
+  }
+}
+#endif
+
+}  // namespace fh

@@ -1,0 +1,99 @@
+// Multi-resolution tesseract encoding (Sec. 3.2.4): per level, locate the 4D cell,
+// look up the 16 corner slots through the per-level hash and blend the corner
+// embeddings with quadrilinear weights; and its adjoint (scatter-add).
+//
+// One thread per sample, levels in a wave-uniform loop (level constants come from
+// the kernel arguments, i.e. scalar registers).  The 16 corners are visited as 8
+// vertex rows (dy, dz, dt) of an x-pair (x, x+1): one directory entry serves both
+// vertices of a pair unless x sits on bit 63 of a word.
+#include "encode_dev.h"
+#include "kernels.h"
+
+namespace fh {
+
+namespace {
+
+template <int F, typename T>
+__global__ void __launch_bounds__(256)
+    encode_fwd_kernel(GridDev g, const float4* __restrict__ pos, int64_t n,
+                      const T* __restrict__ table, float* __restrict__ enc) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const float4 p = pos[s];
+  float* out = enc + s * (int64_t)g.L * F;
+  for (int l = 0; l < g.L; ++l) {
+    const LevelDev& d = g.lv[l];
+    encode_level<F, T>(d, g.dir, g.active != 0, p, table, out + l * F);
+  }
+}
+
+template <int F>
+__global__ void __launch_bounds__(256)
+    encode_bwd_kernel(GridDev g, const float4* __restrict__ pos, int64_t n,
+                      const float* __restrict__ d_enc, float* __restrict__ d_table) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const float4 p = pos[s];
+  const float* gin = d_enc + s * (int64_t)g.L * F;
+  for (int l = 0; l < g.L; ++l) {
+    const LevelDev& d = g.lv[l];
+    float gl[F];
+#pragma unroll
+    for (int k = 0; k < F; ++k) gl[k] = gin[l * F + k];
+    scatter_level<F>(d, g.dir, g.active != 0, p, gl, d_table);
+  }
+}
+
+template <int F>
+hipError_t launch_fwd_t(const GridDev& g, const float* pos, int64_t n, const void* table,
+                        fhash_dtype dt, float* enc, hipStream_t st) {
+  const int T = 256;
+  const int64_t blocks = (n + T - 1) / T;
+  if (dt == FHASH_F32)
+    hipLaunchKernelGGL((encode_fwd_kernel<F, float>), dim3((unsigned)blocks), dim3(T), 0, st, g,
+                       reinterpret_cast<const float4*>(pos), n,
+                       reinterpret_cast<const float*>(table), enc);
+  else
+    hipLaunchKernelGGL((encode_fwd_kernel<F, __half>), dim3((unsigned)blocks), dim3(T), 0, st, g,
+                       reinterpret_cast<const float4*>(pos), n,
+                       reinterpret_cast<const __half*>(table), enc);
+  return hipGetLastError();
+}
+
+template <int F>
+hipError_t launch_bwd_t(const GridDev& g, const float* pos, int64_t n, const float* d_enc,
+                        float* d_table, hipStream_t st) {
+  const int T = 256;
+  const int64_t blocks = (n + T - 1) / T;
+  hipLaunchKernelGGL((encode_bwd_kernel<F>), dim3((unsigned)blocks), dim3(T), 0, st, g,
+                     reinterpret_cast<const float4*>(pos), n, d_enc, d_table);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_encode_fwd(const GridDev& g, const float* pos, int64_t n, const void* table,
+                             fhash_dtype dt, float* enc, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  switch (g.F) {
+    case 1: return launch_fwd_t<1>(g, pos, n, table, dt, enc, st);
+    case 2: return launch_fwd_t<2>(g, pos, n, table, dt, enc, st);
+    case 4: return launch_fwd_t<4>(g, pos, n, table, dt, enc, st);
+    case 8: return launch_fwd_t<8>(g, pos, n, table, dt, enc, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_encode_bwd(const GridDev& g, const float* pos, int64_t n, const float* d_enc,
+                             float* d_table, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  switch (g.F) {
+    case 1: return launch_bwd_t<1>(g, pos, n, d_enc, d_table, st);
+    case 2: return launch_bwd_t<2>(g, pos, n, d_enc, d_table, st);
+    case 4: return launch_bwd_t<4>(g, pos, n, d_enc, d_table, st);
+    case 8: return launch_bwd_t<8>(g, pos, n, d_enc, d_table, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fh

@@ -1,0 +1,191 @@
+// Fused tesseract encoding + MLP decoder (forward, backward, and forward + MSE
+// + backward in one pass).
+//
+// A wave processes blocks of 16 samples.  Lane l = 16 g + s owns sample s of
+// the block and the embedding features 16 a + 4 g + i of it -- exactly the
+// features its MFMA B-operand registers carry -- so each lane gathers the
+// levels behind those features itself (4/F levels per 16-feature block), the
+// encoding lands directly in MLP input registers, and the encoding gradient
+// that the MLP backward leaves in the same registers is scattered by the same
+// lane for the same levels.  Corner weights are recomputed, never stored.
+#pragma once
+#include "encode_dev.h"
+#include "kernels.h"
+#include "mlp_dev.h"
+
+namespace fh {
+
+namespace fused_detail {
+
+constexpr int kWaves = 4;
+enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2 };
+
+struct FusedArgs {
+  const float4* pos;
+  const float* target;  // MODE_TRAIN
+  const float* dy;      // MODE_BWD
+  int64_t n;
+  const void* table;
+  const float* params;
+  float* y;        // MODE_FWD
+  float* d_table;  // MODE_BWD / TRAIN
+  float* part;     // per-wave parameter-gradient partials
+  double* loss_sum;
+  int64_t P;
+  float coef;  // dL/dy = coef * (y - target)
+  int in_w;    // L * F
+};
+
+template <int F, typename T, int INP>
+__device__ __forceinline__ void gather_block(const GridDev& g, const LevelDev* lv, float4 p,
+                                             bool valid, const T* table,
+                                             float (&xb)[INP / 16][4]) {
+  const int lane = threadIdx.x & 63, grp = lane >> 4;
+  constexpr int LPB = 4 / F;  // levels per lane per 16-feature block
+#pragma unroll
+  for (int a = 0; a < INP / 16; ++a)
+#pragma unroll
+    for (int j = 0; j < LPB; ++j) {
+      const int l = (16 * a + 4 * grp) / F + j;
+      float e[F];
+      if (valid && l < g.L) {
+        encode_level<F, T>(lv[l], g.dir, g.active != 0, p, table, e);
+      } else {
+#pragma unroll
+        for (int k = 0; k < F; ++k) e[k] = 0.0f;
+      }
+#pragma unroll
+      for (int k = 0; k < F; ++k) xb[a][j * F + k] = e[k];
+    }
+}
+
+template <int F, int INP>
+__device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* lv, float4 p,
+                                              bool valid, const float (&dx)[INP / 16][4],
+                                              float* d_table) {
+  const int lane = threadIdx.x & 63, grp = lane >> 4;
+  constexpr int LPB = 4 / F;
+  if (!valid) return;
+#pragma unroll
+  for (int a = 0; a < INP / 16; ++a)
+#pragma unroll
+    for (int j = 0; j < LPB; ++j) {
+      const int l = (16 * a + 4 * grp) / F + j;
+      if (l < g.L) {
+        float gl[F];
+#pragma unroll
+        for (int k = 0; k < F; ++k) gl[k] = dx[a][j * F + k];
+        scatter_level<F>(lv[l], g.dir, g.active != 0, p, gl, d_table);
+      }
+    }
+}
+
+template <int MODE, int F, typename T, int INP, int H, int NH>
+__global__ void __launch_bounds__(64 * kWaves) fused_kernel(GridDev g, FusedArgs A) {
+  using S = MlpShape<INP, H, NH>;
+  constexpr int WS = (MODE == MODE_FWD) ? 0 : mlp_wave_scratch<INP, H, NH>();
+  __shared__ __attribute__((aligned(16))) float lds[S::WFLOATS + kWaves * WS + 1];
+  __shared__ LevelDev lv[FHASH_MAX_LEVELS];
+  load_weights_lds<INP, H, NH>(lds, A.params, A.in_w);
+  for (int e = threadIdx.x; e < FHASH_MAX_LEVELS; e += blockDim.x) lv[e] = g.lv[e];
+  __syncthreads();
+  const T* table = reinterpret_cast<const T*>(A.table);
+  const int lane = threadIdx.x & 63, grp = lane >> 4, s = lane & 15;
+  const int wib = threadIdx.x >> 6;
+  float* scratch = lds + S::WFLOATS + wib * WS;
+  const int64_t nblk = (A.n + 15) / 16;
+  const int64_t nwav = (int64_t)gridDim.x * kWaves;
+  const int64_t wave = (int64_t)blockIdx.x * kWaves + wib;
+  MlpGrad<INP, H, NH> gr;
+  if (MODE != MODE_FWD) gr.zero();
+  double loss = 0.0;
+  for (int64_t b = wave; b < nblk; b += nwav) {
+    const int64_t smp = b * 16 + s;
+    const bool valid = smp < A.n;
+    const float4 p = valid ? A.pos[smp] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float xb[S::INB][4];
+    gather_block<F, T, INP>(g, lv, p, valid, table, xb);
+    if (MODE != MODE_FWD) mlp_stage_input<INP, H, NH>(scratch, xb);
+    float hs[NH][S::HB][4];
+    const float yv = mlp_block_fwd<INP, H, NH>(lds, xb, hs);
+    if (MODE == MODE_FWD) {
+      if (grp == 0 && valid) A.y[smp] = yv;
+      continue;
+    }
+    float dyv = 0.0f;
+    if (MODE == MODE_BWD) {
+      dyv = valid ? A.dy[smp] : 0.0f;
+    } else {
+      const float r = valid ? yv - A.target[smp] : 0.0f;
+      dyv = A.coef * r;
+      if (grp == 0) loss += (double)r * (double)r;
+    }
+    float dxb[S::INB][4];
+    mlp_block_bwd<INP, H, NH>(lds, scratch, hs, dyv, gr, dxb);
+    scatter_block<F, INP>(g, lv, p, valid, dxb, A.d_table);
+  }
+  if (MODE == MODE_FWD) return;
+  mlp_write_partial<INP, H, NH>(gr, A.in_w, A.part + wave * A.P);
+  if (MODE == MODE_TRAIN && A.loss_sum != nullptr) {
+    for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
+    if (lane == 0) unsafeAtomicAdd(A.loss_sum, loss);
+  }
+}
+
+inline int64_t fused_waves(int64_t n, int mode) {
+  int64_t nblk = (n + 15) / 16;
+  int64_t cap = (mode == MODE_FWD) ? 8192 : 2048;
+  int64_t w = nblk < cap ? nblk : cap;
+  w = ((w + kWaves - 1) / kWaves) * kWaves;
+  return w < kWaves ? kWaves : w;
+}
+
+template <int MODE, int F, typename T, int INP, int H, int NH>
+hipError_t fused_t(const GridDev& g, FusedArgs A, float* d_params, hipStream_t st) {
+  const int64_t nw = fused_waves(A.n, MODE);
+  hipLaunchKernelGGL((fused_kernel<MODE, F, T, INP, H, NH>), dim3((unsigned)(nw / kWaves)),
+                     dim3(64 * kWaves), 0, st, g, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || MODE == MODE_FWD) return e;
+  return launch_reduce_partials(A.part, nw, A.P, d_params, st);
+}
+
+template <int MODE, int F, typename T>
+hipError_t fused_shape(const GridDev& g, int H, int NH, FusedArgs A, float* d_params,
+                       hipStream_t st) {
+  const int inp = ((A.in_w + 15) / 16) * 16;
+  switch (inp * 1000 + H * 10 + NH) {
+#define FH_C(I, HH, N) \
+  case I * 1000 + HH * 10 + N: return fused_t<MODE, F, T, I, HH, N>(g, A, d_params, st);
+    FH_C(16, 32, 1) FH_C(16, 32, 2) FH_C(16, 32, 3)
+    FH_C(16, 64, 1) FH_C(16, 64, 2) FH_C(16, 64, 3)
+    FH_C(32, 32, 1) FH_C(32, 32, 2) FH_C(32, 32, 3)
+    FH_C(32, 64, 1) FH_C(32, 64, 2) FH_C(32, 64, 3)
+#undef FH_C
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int MODE>
+hipError_t fused_dispatch(const GridDev& g, int H, int NH, fhash_dtype tdt, FusedArgs A,
+                          float* d_params, hipStream_t st) {
+  if (A.n == 0) return hipSuccess;
+  if (tdt == FHASH_F32) {
+    switch (g.F) {
+      case 1: return fused_shape<MODE, 1, float>(g, H, NH, A, d_params, st);
+      case 2: return fused_shape<MODE, 2, float>(g, H, NH, A, d_params, st);
+      case 4: return fused_shape<MODE, 4, float>(g, H, NH, A, d_params, st);
+    }
+  } else {
+    switch (g.F) {
+      case 1: return fused_shape<MODE, 1, __half>(g, H, NH, A, d_params, st);
+      case 2: return fused_shape<MODE, 2, __half>(g, H, NH, A, d_params, st);
+      case 4: return fused_shape<MODE, 4, __half>(g, H, NH, A, d_params, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fused_detail
+
+}  // namespace fh

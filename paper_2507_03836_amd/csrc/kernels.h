@@ -1,0 +1,78 @@
+// Host launchers of the HIP kernels (internal to libfhash).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace fh {
+
+// index.hip
+int64_t index_dir_words(const fhash_grid_desc* g, int l);
+size_t index_workspace_bytes(const fhash_grid_desc* g, const int64_t* dims);
+hipError_t launch_build_index(const fhash_grid_desc* g, const uint64_t* mask, const int64_t* dims,
+                              ulonglong2* dir, const int64_t* dir_off, void* ws,
+                              uint64_t* counts_host, hipStream_t st);
+
+// encode.hip
+hipError_t launch_encode_fwd(const GridDev& g, const float* pos, int64_t n, const void* table,
+                             fhash_dtype dt, float* enc, hipStream_t st);
+hipError_t launch_encode_bwd(const GridDev& g, const float* pos, int64_t n, const float* d_enc,
+                             float* d_table, hipStream_t st);
+
+// mlp.hip
+bool mlp_supported(int in_w, int H, int NH);
+size_t mlp_bwd_ws_bytes(int64_t n, int64_t P);
+hipError_t launch_mlp_fwd(int in_w, int H, int NH, const float* params, const float* x, int64_t n,
+                          float* y, hipStream_t st);
+hipError_t launch_mlp_bwd(int in_w, int H, int NH, const float* params, const float* x,
+                          const float* dy, int64_t n, float* d_params, float* dx, void* ws,
+                          int64_t P, hipStream_t st);
+
+// fused.hip
+bool fused_supported(int F, int in_w, int H, int NH);
+size_t fused_ws_bytes(int64_t n, int64_t P);
+hipError_t launch_fused_fwd(const GridDev& g, int H, int NH, const float* pos, int64_t n,
+                            const void* table, fhash_dtype tdt, const float* params, float* y,
+                            hipStream_t st);
+hipError_t launch_fused_bwd(const GridDev& g, int H, int NH, const float* pos, int64_t n,
+                            const void* table, fhash_dtype tdt, const float* params,
+                            const float* dy, float* d_table, float* d_params, void* ws, int64_t P,
+                            hipStream_t st);
+hipError_t launch_fused_train(const GridDev& g, int H, int NH, const float* pos,
+                              const float* target, int64_t n, const void* table, fhash_dtype tdt,
+                              const float* params, float loss_scale, float* d_table,
+                              float* d_params, double* loss_sum, void* ws, int64_t P,
+                              hipStream_t st);
+
+// optim.hip
+hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
+                       void* shadow, fhash_dtype sdt, int64_t n, const int32_t* found_inf,
+                       hipStream_t st);
+hipError_t launch_reduce_partials(const float* part, int64_t nwav, int64_t P, float* d_params,
+                                  hipStream_t st);
+hipError_t launch_check_finite(const float* g, int64_t n, int32_t* found, hipStream_t st);
+hipError_t launch_cast(const float* src, void* dst, fhash_dtype dt, int64_t n, hipStream_t st);
+hipError_t launch_sq_err(const float* y, const float* v, int64_t n, double* sum, hipStream_t st);
+hipError_t launch_mse_grad(const float* y, const float* v, int64_t n, float coef, float* dy,
+                           double* sum, hipStream_t st);
+
+// sampler.hip
+hipError_t launch_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset,
+                         uint64_t M, const int64_t* dims, const float* field, float* pos,
+                         float* target, hipStream_t st);
+
+// render.hip
+size_t render_ws_bytes(int64_t NR, const int64_t* dims);
+hipError_t launch_render_begin(const fhash_view* v, int W, int H, const uint64_t* mask,
+                               const int64_t* dims, float t, void* ws, int32_t* n_alive_host,
+                               float* rgba, hipStream_t st);
+hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, float t, float ds,
+                               int32_t max_steps, int32_t pace, int cur, int32_t n_alive,
+                               float* pos_out, int32_t* n_samples_host, hipStream_t st);
+hipError_t launch_render_composite(void* ws, int W, int H, int cur, int32_t n_alive,
+                                   const float* y, const float* tf, float alpha_stop, float* rgba,
+                                   int32_t* n_alive_host, hipStream_t st);
+
+}  // namespace fh

@@ -1,0 +1,249 @@
+// Dense Adam step with loss-scale unscaling, overflow skip, low-precision
+// shadow write and gradient zeroing; finite check; casts; FP64 reductions.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace fh {
+
+namespace {
+
+__device__ __forceinline__ uint16_t to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ void store_shadow(void* sh, int dt, int64_t i, float x) {
+  if (dt == FHASH_F16)
+    reinterpret_cast<__half*>(sh)[i] = __float2half_rn(x);
+  else
+    reinterpret_cast<uint16_t*>(sh)[i] = to_bf16_rne(x);
+}
+
+struct AdamK {
+  float step_size, b1, omb1, b2, omb2, eps, inv_bc2_sqrt, gscale;
+};
+
+__device__ __forceinline__ void adam1(const AdamK& k, float g, float& p, float& m, float& v) {
+  const float gs = g * k.gscale;
+  m = k.b1 * m + k.omb1 * gs;
+  v = k.b2 * v + k.omb2 * gs * gs;
+  const float denom = sqrtf(v) * k.inv_bc2_sqrt + k.eps;
+  p -= k.step_size * (m / denom);
+}
+
+__global__ void __launch_bounds__(256)
+    adam_kernel(AdamK k, float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
+                float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t n,
+                const int32_t* __restrict__ found_inf) {
+  const bool skip = (found_inf != nullptr) && (*found_inf != 0);
+  const int64_t n4 = n >> 2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  float4* p4 = reinterpret_cast<float4*>(p);
+  float4* g4 = reinterpret_cast<float4*>(g);
+  float4* m4 = reinterpret_cast<float4*>(m);
+  float4* v4 = reinterpret_cast<float4*>(v);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += stride) {
+    const float4 gg = g4[i];
+    if (!skip) {
+      float4 pp = p4[i], mm = m4[i], vv = v4[i];
+      adam1(k, gg.x, pp.x, mm.x, vv.x);
+      adam1(k, gg.y, pp.y, mm.y, vv.y);
+      adam1(k, gg.z, pp.z, mm.z, vv.z);
+      adam1(k, gg.w, pp.w, mm.w, vv.w);
+      p4[i] = pp;
+      m4[i] = mm;
+      v4[i] = vv;
+      if (shadow != nullptr) {
+        if (sdt == FHASH_F16) {
+          __half2 a = __floats2half2_rn(pp.x, pp.y), b = __floats2half2_rn(pp.z, pp.w);
+          uint2 raw;
+          raw.x = *reinterpret_cast<uint32_t*>(&a);
+          raw.y = *reinterpret_cast<uint32_t*>(&b);
+          reinterpret_cast<uint2*>(shadow)[i] = raw;
+        } else {
+          uint2 raw;
+          raw.x = (uint32_t)to_bf16_rne(pp.x) | ((uint32_t)to_bf16_rne(pp.y) << 16);
+          raw.y = (uint32_t)to_bf16_rne(pp.z) | ((uint32_t)to_bf16_rne(pp.w) << 16);
+          reinterpret_cast<uint2*>(shadow)[i] = raw;
+        }
+      }
+    }
+    // Zero the gradient; untouched (already zero) gradients are not rewritten.
+    if (gg.x != 0.0f || gg.y != 0.0f || gg.z != 0.0f || gg.w != 0.0f)
+      g4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  // Tail (n not a multiple of 4).
+  const int64_t t = (n4 << 2) + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n && t < (n4 << 2) + 4) {
+    const float gg = g[t];
+    if (!skip) {
+      float pp = p[t], mm = m[t], vv = v[t];
+      adam1(k, gg, pp, mm, vv);
+      p[t] = pp;
+      m[t] = mm;
+      v[t] = vv;
+      if (shadow != nullptr) store_shadow(shadow, sdt, t, pp);
+    }
+    if (gg != 0.0f) g[t] = 0.0f;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    check_finite_kernel(const float* __restrict__ g, int64_t n, int32_t* __restrict__ found) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(g[i]);
+  bad = __syncthreads_or(bad);
+  if (bad && threadIdx.x == 0) atomicOr(found, 1);
+}
+
+__global__ void __launch_bounds__(256)
+    cast_kernel(const float* __restrict__ src, void* __restrict__ dst, int dt, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    store_shadow(dst, dt, i, src[i]);
+}
+
+__device__ __forceinline__ double block_sum_double(double v) {
+  __shared__ double sh[16];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  return r;
+}
+
+__global__ void __launch_bounds__(256)
+    sq_err_kernel(const float* __restrict__ y, const float* __restrict__ v, int64_t n,
+                  double* __restrict__ sum) {
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double r = (double)y[i] - (double)v[i];
+    acc += r * r;
+  }
+  const double tot = block_sum_double(acc);
+  if (threadIdx.x == 0) unsafeAtomicAdd(sum, tot);
+}
+
+__global__ void __launch_bounds__(256)
+    mse_grad_kernel(const float* __restrict__ y, const float* __restrict__ v, int64_t n,
+                    float coef, float* __restrict__ dy, double* __restrict__ sum) {
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float r = y[i] - v[i];
+    dy[i] = coef * r;
+    acc += (double)r * (double)r;
+  }
+  if (sum != nullptr) {
+    const double tot = block_sum_double(acc);
+    if (threadIdx.x == 0) unsafeAtomicAdd(sum, tot);
+  }
+}
+
+// d_params[p] += sum_w part[w][p]: 16 columns x 16 row groups per block, fixed
+// summation order (deterministic).
+__global__ void __launch_bounds__(256)
+    reduce_partials_kernel(const float* __restrict__ part, int64_t nwav, int64_t P,
+                           float* __restrict__ d_params) {
+  __shared__ float sh[16][17];
+  const int col = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  const int64_t p = blockIdx.x * 16 + col;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  if (p < P) {
+    int64_t w = rg;
+    for (; w + 48 < nwav; w += 64) {
+      a0 += part[w * P + p];
+      a1 += part[(w + 16) * P + p];
+      a2 += part[(w + 32) * P + p];
+      a3 += part[(w + 48) * P + p];
+    }
+    for (; w < nwav; w += 16) a0 += part[w * P + p];
+  }
+  sh[rg][col] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (rg == 0 && p < P) {
+    float s = 0.f;
+    for (int r = 0; r < 16; ++r) s += sh[r][col];
+    d_params[p] += s;
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int64_t per_thread) {
+  int64_t b = (n / per_thread + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
+                       void* shadow, fhash_dtype sdt, int64_t n, const int32_t* found_inf,
+                       hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  AdamK k;
+  const double bc1 = 1.0 - pow(o->beta1, (double)o->step);
+  const double bc2 = 1.0 - pow(o->beta2, (double)o->step);
+  k.step_size = (float)(o->lr / bc1);
+  k.inv_bc2_sqrt = (float)(1.0 / sqrt(bc2));
+  k.b1 = (float)o->beta1;
+  k.omb1 = (float)(1.0 - o->beta1);
+  k.b2 = (float)o->beta2;
+  k.omb2 = (float)(1.0 - o->beta2);
+  k.eps = (float)o->eps;
+  k.gscale = (float)o->grad_scale;
+  // One float4 per thread per iteration; enough blocks to fill 256 CUs deeply.
+  int64_t b = (n / 4 + 255) / 256;
+  if (b > 256 * 32) b = 256 * 32;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)b), dim3(256), 0, st, k, p, g, m, v, shadow,
+                     (int)sdt, n, found_inf);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const float* part, int64_t nwav, int64_t P, float* d_params,
+                                  hipStream_t st) {
+  if (P == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((P + 15) / 16)), dim3(256), 0, st,
+                     part, nwav, P, d_params);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float* g, int64_t n, int32_t* found, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(check_finite_kernel, dim3(blocks_for(n, 4)), dim3(256), 0, st, g, n, found);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(const float* src, void* dst, fhash_dtype dt, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cast_kernel, dim3(blocks_for(n, 4)), dim3(256), 0, st, src, dst, (int)dt, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sq_err(const float* y, const float* v, int64_t n, double* sum, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(sq_err_kernel, dim3(blocks_for(n, 8)), dim3(256), 0, st, y, v, n, sum);
+  return hipGetLastError();
+}
+
+hipError_t launch_mse_grad(const float* y, const float* v, int64_t n, float coef, float* dy,
+                           double* sum, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks_for(n, 8)), dim3(256), 0, st, y, v, n, coef, dy,
+                     sum);
+  return hipGetLastError();
+}
+
+}  // namespace fh

@@ -1,0 +1,165 @@
+"""F-Hash model state on the device and the training / inference steps.
+
+Everything numerical runs in libfhash (HIP); this module only owns the torch
+allocations (tables, MLP parameters, Adam moments, workspaces) and sequences
+the C-ABI calls of one training step:
+
+    fhash_sample -> fhash_fused_train -> fhash_step
+
+Parameter memory is one flat FP32 vector per quantity (parameters, gradients,
+Adam m and v): the embedding tables (rows x F, level after level) followed by
+the packed MLP parameters, so one dense Adam launch covers every parameter.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as fl
+
+
+@dataclasses.dataclass
+class FHashConfig:
+    res: list                 # per level (x, y, z, t) vertex counts, level 0 coarsest
+    n_features: int = 2
+    hidden: int = 64
+    n_hidden: int = 2
+    lr: float = 0.01
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.res)
+
+    @property
+    def width(self) -> list:
+        return [self.n_levels * self.n_features] + [self.hidden] * self.n_hidden + [1]
+
+
+def geometric_resolutions(L, rmin_s, rmax_s, rmin_t, rmax_t, dims):
+    """R_l = floor(Rmin * b^l + 0.5), b = (Rmax/Rmin)^(1/(L-1)), clamped to [2, S_d]."""
+    out = []
+    for l in range(L):
+        r = []
+        for d in range(4):
+            lo, hi = (rmin_s, rmax_s) if d < 3 else (rmin_t, rmax_t)
+            v = lo if L == 1 else lo * ((hi / lo) ** (1.0 / (L - 1))) ** l
+            R = int(np.floor(v + 0.5))
+            r.append(max(2, min(R, int(dims[d]))))
+        out.append(r)
+    return out
+
+
+class FHashModel:
+    """Device-resident F-Hash model (index + tables + decoder + Adam state)."""
+
+    def __init__(self, cfg: FHashConfig, mask_bits: torch.Tensor | None, dims, device="cuda",
+                 table_init: torch.Tensor | None = None, mlp_init: torch.Tensor | None = None,
+                 init_seed: int = 3000):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.grid = fl.grid_desc(cfg.res, cfg.n_features)
+        self.mlp = fl.mlp_desc(cfg.width)
+        self.index, self.slots_per_level, self._dir, _ws = fl.fhash_build_index(
+            self.grid, mask_bits, dims)
+        del _ws
+        self.rows = int(self.index.slot_offset[cfg.n_levels])
+        self.n_table = self.rows * cfg.n_features
+        self.n_mlp = fl.fhash_mlp_num_params(self.mlp)
+        # pad the table part to a multiple of 4 floats so the MLP part is 16-byte aligned
+        self.mlp_off = (self.n_table + 3) // 4 * 4
+        self.n_params = self.mlp_off + self.n_mlp
+        n_alloc = (self.n_params + 3) // 4 * 4
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.params = torch.zeros(n_alloc, **f32)
+        self.grads = torch.zeros(n_alloc, **f32)
+        self.m = torch.zeros(n_alloc, **f32)
+        self.v = torch.zeros(n_alloc, **f32)
+        if table_init is not None:
+            self.table.copy_(table_init.reshape(-1))
+        else:
+            g = torch.Generator(device=self.device)
+            g.manual_seed(init_seed)
+            self.table.uniform_(-1e-4, 1e-4, generator=g)
+        if mlp_init is not None:
+            self.mlp_params.copy_(mlp_init.reshape(-1))
+        else:
+            g = torch.Generator(device="cpu")
+            g.manual_seed(init_seed + 1)
+            parts = []
+            w = cfg.width
+            for k in range(len(w) - 1):
+                bound = 1.0 / np.sqrt(w[k])
+                parts.append(torch.empty(w[k + 1] * w[k]).uniform_(-bound, bound, generator=g))
+                parts.append(torch.empty(w[k + 1]).uniform_(-bound, bound, generator=g))
+            self.mlp_params.copy_(torch.cat(parts))
+        self.step_count = 0
+        self.loss_sum = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._ws = None
+
+    # views into the flat vectors
+    @property
+    def table(self) -> torch.Tensor:
+        return self.params[: self.n_table]
+
+    @property
+    def mlp_params(self) -> torch.Tensor:
+        return self.params[self.mlp_off: self.mlp_off + self.n_mlp]
+
+    @property
+    def d_table(self) -> torch.Tensor:
+        return self.grads[: self.n_table]
+
+    @property
+    def d_mlp(self) -> torch.Tensor:
+        return self.grads[self.mlp_off: self.mlp_off + self.n_mlp]
+
+    def adam_desc(self, step: int, grad_scale: float = 1.0) -> fl.AdamDesc:
+        c = self.cfg
+        o = fl.AdamDesc()
+        o.lr, o.beta1, o.beta2, o.eps = c.lr, c.beta1, c.beta2, c.eps
+        o.step = step
+        o.grad_scale = grad_scale
+        return o
+
+    def forward(self, pos: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+        n = pos.shape[0]
+        if y is None:
+            y = torch.empty(n, dtype=torch.float32, device=self.device)
+        fl.fhash_fused_fwd(self.index, self.mlp, pos, n, self.table, self.mlp_params, y)
+        return y
+
+    def fwd_bwd(self, pos: torch.Tensor, target: torch.Tensor, loss_scale: float = 1.0):
+        """Fused forward + MSE + backward; gradients accumulate into self.grads."""
+        n = pos.shape[0]
+        self._ws = fl.fhash_fused_train(self.index, self.mlp, pos, target, n, self.table,
+                                        self.mlp_params, self.d_table, self.d_mlp,
+                                        self.loss_sum, loss_scale, ws=self._ws)
+
+    def optimizer_step(self, grad_scale: float = 1.0, found_inf=None):
+        self.step_count += 1
+        fl.fhash_step(self.adam_desc(self.step_count, grad_scale), self.params[: self.n_params],
+                      self.grads[: self.n_params], self.m[: self.n_params],
+                      self.v[: self.n_params], found_inf=found_inf)
+
+    def train_step(self, pos: torch.Tensor, target: torch.Tensor):
+        self.fwd_bwd(pos, target)
+        self.optimizer_step()
+
+
+def psnr_on(model: FHashModel, pos: torch.Tensor, target: torch.Tensor, chunk: int = 1 << 20):
+    """Volume-space PSNR (data range 1): the decoder output on pos against
+    target, squared errors summed on the device in FP64 (fhash_sq_err_sum)."""
+    acc = torch.zeros(1, dtype=torch.float64, device=model.device)
+    y = torch.empty(min(chunk, pos.shape[0]), dtype=torch.float32, device=model.device)
+    for s in range(0, pos.shape[0], chunk):
+        e = min(s + chunk, pos.shape[0])
+        yy = y[: e - s]
+        model.forward(pos[s:e], yy)
+        fl.fhash_sq_err_sum(yy, target[s:e], e - s, acc)
+    mse = acc.item() / pos.shape[0]
+    return 10.0 * np.log10(1.0 / mse) if mse > 0 else float("inf")

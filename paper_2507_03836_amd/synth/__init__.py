@@ -25,6 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _HOST_LIB = os.path.join(_HERE, "libfhash_synth_host.so")
+_GPU_LIB = os.path.join(_HERE, "libfhash_synth_gpu.so")
 
 SEED_FIELD, SEED_SAMPLER, SEED_INIT, SEED_PROBE, SEED_ARRIVALS = 1000, 2000, 3000, 4000, 5000
 
@@ -36,7 +37,39 @@ def build_host(force: bool = True) -> str:
     return _HOST_LIB
 
 
+def build_gpu(force: bool = True) -> str:
+    if force or not os.path.exists(_GPU_LIB):
+        subprocess.run(["/opt/rocm/bin/hipcc", "-O3", "-fPIC", "-shared", "--offload-arch=gfx950",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                        "-o", _GPU_LIB, os.path.join(_HERE, "synth_gpu.hip")], check=True,
+                       capture_output=True)
+    return _GPU_LIB
+
+
 _lib = None
+_glib = None
+
+
+def _G():
+    global _glib
+    if _glib is None:
+        if not os.path.exists(_GPU_LIB):
+            raise ImportError(f"{_GPU_LIB} missing; run synth.build_gpu()")
+        L = C.CDLL(_GPU_LIB)
+        P, I64, U64, D = C.c_void_p, C.c_int64, C.c_uint64, C.c_double
+        L.sy_gpu_field.argtypes = [P, P, C.c_int, D, U64, C.c_int, P, P]
+        L.sy_gpu_normalise.argtypes = [P, I64, P, P]
+        L.sy_gpu_grad_mag.argtypes = [P, P, P, P]
+        L.sy_gpu_select.argtypes = [P, I64, I64, P, P, P]
+        L.sy_gpu_mask_bits.argtypes = [P, P, C.c_float, P, P]
+        L.sy_gpu_dilate.argtypes = [P, P, P, C.c_int, P]
+        L.sy_gpu_popcounts.argtypes = [P, I64, P, P]
+        L.sy_gpu_emit.argtypes = [P, P, P, P, P]
+        for n in ("sy_gpu_field", "sy_gpu_normalise", "sy_gpu_grad_mag", "sy_gpu_select",
+                  "sy_gpu_mask_bits", "sy_gpu_dilate", "sy_gpu_popcounts", "sy_gpu_emit"):
+            getattr(L, n).restype = C.c_int
+        _glib = L
+    return _glib
 
 
 def _L():
@@ -180,3 +213,86 @@ def probe_points(n, seed=SEED_PROBE):
     """Continuous probe positions U[0,1)^4 (x, y, z, t)."""
     rng = np.random.default_rng(seed)
     return rng.random((n, 4), dtype=np.float64).astype(np.float32)
+
+
+def production_volume_gpu(shape_xyzt, seed, n_blobs=64, quantile_q=0.8, radius=2,
+                          keep_field=True):
+    """Device version of production_volume_host (same definitions) for large shapes.
+
+    Returns dict(field=float32 [T][Sz][Sy][Sx] device tensor (or None),
+    bits=row-padded mask words (int64 view of uint64) [T][Sz][Sy][W],
+    coreset=int64 view of uint64 linear voxel ids (ascending), threshold)."""
+    import torch
+
+    G = _G()
+    Sx, Sy, Sz, T = shape_xyzt
+    dims = np.array(shape_xyzt, np.int64)
+    N = int(np.prod(dims))
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    blobs = torch.from_numpy(blob_params(seed, n_blobs, (0.02, 0.08), (0.5, 1.0), 0.004)).cuda()
+    f = torch.empty((T, Sz, Sy, Sx), dtype=torch.float32, device="cuda")
+    assert G.sy_gpu_field(_p(dims), C.c_void_p(blobs.data_ptr()), n_blobs, 0.25,
+                          seed * 7919 + 17, 0, C.c_void_p(f.data_ptr()), st) == 0
+    mm = torch.empty(2, dtype=torch.int32, device="cuda")
+    assert G.sy_gpu_normalise(C.c_void_p(f.data_ptr()), N, C.c_void_p(mm.data_ptr()), st) == 0
+    g = torch.empty_like(f)
+    assert G.sy_gpu_grad_mag(_p(dims), C.c_void_p(f.data_ptr()), C.c_void_p(g.data_ptr()), st) == 0
+    hist = torch.empty(4096, dtype=torch.int64, device="cuda")
+    thr = C.c_float()
+    rank = min(int(np.floor(quantile_q * N)), N - 1)
+    assert G.sy_gpu_select(C.c_void_p(g.data_ptr()), N, rank, C.c_void_p(hist.data_ptr()),
+                           C.byref(thr), st) == 0
+    W = (Sx + 63) // 64
+    bits = torch.empty((T, Sz, Sy, W), dtype=torch.int64, device="cuda")
+    assert G.sy_gpu_mask_bits(C.c_void_p(g.data_ptr()), _p(dims), thr, C.c_void_p(bits.data_ptr()),
+                              st) == 0
+    del g
+    tmp = torch.empty_like(bits)
+    assert G.sy_gpu_dilate(C.c_void_p(bits.data_ptr()), C.c_void_p(tmp.data_ptr()), _p(dims),
+                           radius, st) == 0
+    del tmp
+    cnt = torch.empty(bits.numel(), dtype=torch.int64, device="cuda")
+    assert G.sy_gpu_popcounts(C.c_void_p(bits.data_ptr()), bits.numel(),
+                              C.c_void_p(cnt.data_ptr()), st) == 0
+    incl = torch.cumsum(cnt, 0)
+    M = int(incl[-1].item())
+    excl = incl - cnt
+    del cnt, incl
+    ids = torch.empty(max(M, 1), dtype=torch.int64, device="cuda")
+    assert G.sy_gpu_emit(C.c_void_p(bits.data_ptr()), _p(dims), C.c_void_p(excl.data_ptr()),
+                         C.c_void_p(ids.data_ptr()), st) == 0
+    del excl
+    torch.cuda.synchronize()
+    return dict(field=f if keep_field else None, bits=bits, coreset=ids[:M], threshold=thr.value,
+                M=M, N=N)
+
+
+# --------------------------------------------------------------------------- render inputs
+def orbit_view(dims, azimuth, elevation, W, H, fovy_deg=45.0, dist_factor=2.0):
+    """Orbit camera around the volume box [0, S-1]^3 (voxel units): distance
+    dist_factor x the box half-diagonal from its centre, looking at the centre,
+    world z up.  Returns 14 float32: eye, fwd, right, up, tan(fovy/2), W/H
+    (basis in FP64, rounded once)."""
+    c = np.array([(dims[0] - 1) / 2.0, (dims[1] - 1) / 2.0, (dims[2] - 1) / 2.0])
+    r = dist_factor * float(np.linalg.norm(c))
+    ca, sa, ce, se = np.cos(azimuth), np.sin(azimuth), np.cos(elevation), np.sin(elevation)
+    eye = c + r * np.array([ce * ca, ce * sa, se])
+    fwd = c - eye
+    fwd = fwd / np.sqrt((fwd * fwd).sum())
+    wup = np.array([0.0, 0.0, 1.0])
+    right = np.cross(fwd, wup)
+    right = right / np.sqrt((right * right).sum())
+    up = np.cross(right, fwd)
+    v = np.concatenate([eye, fwd, right, up, [np.tan(np.radians(fovy_deg) / 2.0), W / H]])
+    return v.astype(np.float32)
+
+
+def transfer_function():
+    """Fixed 256-entry RGBA transfer function: a warm ramp in colour and an
+    opacity ramp that is transparent below 0.15 and reaches 0.4 at 1."""
+    v = np.arange(256) / 255.0
+    r = np.clip(1.5 * v, 0, 1)
+    g = np.clip(1.5 * v - 0.5, 0, 1)
+    b = np.clip(0.6 - v, 0, 1)
+    a = np.clip((v - 0.15) / 0.85, 0, 1) * 0.4
+    return np.stack([r, g, b, a], axis=1).astype(np.float32)

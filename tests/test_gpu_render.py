@@ -1,0 +1,104 @@
+"""GPU renderer parity: images against the oracle, ARM-invariance, the step API."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2507_03836_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
+
+
+@pytest.fixture(scope="module")
+def scene():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2507_03836_amd import _lib as fl
+    fl.lib()
+    f, mask = synth.tiny_volume()
+    T, Sz, Sy, Sx = mask.shape
+    dims = [Sx, Sy, Sz, T]
+    g = O.Grid(np.array(TINY_RES), 2, mask)
+    rng = np.random.default_rng(1)
+    table = rng.uniform(-1.0, 1.0, size=(g.total_slots, 2)).astype(np.float32)
+    width = [8, 32, 32, 1]
+    params = synth.mlp_init(width, seed=7)
+    params[-1] = 0.5  # centre the output in the transfer function's range
+    bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
+    idx, counts, dir_t, _ = fl.fhash_build_index(fl.grid_desc(TINY_RES, 2), bits, dims)
+    return dict(fl=fl, mask=mask, dims=dims, g=g, table=table, width=width, params=params,
+                bits=bits, idx=idx, dir=dir_t, tab_d=torch.from_numpy(table).cuda(),
+                prm_d=torch.from_numpy(params).cuda(), mlp=fl.mlp_desc(width),
+                tf=synth.transfer_function(), tf_d=torch.from_numpy(synth.transfer_function()).cuda())
+
+
+def _gpu_render(s, view14, t, W, H, arm_max=64, ds=0.5):
+    fl = s["fl"]
+    rgba = torch.empty(H, W, 4, device="cuda")
+    st, _ = fl.fhash_render(s["idx"], s["mlp"], s["tab_d"], s["prm_d"], s["bits"], s["dims"],
+                            fl.view_struct(view14), t, s["tf_d"], W, H,
+                            fl.render_opts(ds=ds, arm_max=arm_max), rgba)
+    return rgba.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("az,el,t,W,H", [(0.4, 0.3, 3.5, 48, 40), (2.2, -0.5, 0.0, 37, 29),
+                                         (4.0, 0.9, 7.0, 64, 16)])
+def test_render_matches_oracle(scene, az, el, t, W, H):
+    s = scene
+    view = synth.orbit_view(s["dims"], az, el, W, H)
+    img, st = _gpu_render(s, view, t, W, H)
+    ref, amb, ev = O.render(s["g"], s["table"].astype(np.float64), s["width"],
+                            s["params"].astype(np.float64), s["mask"], view, t, s["tf"], W, H)
+    ok = ~amb
+    err = np.abs(img - ref)[ok]
+    assert err.max() < 2e-4, float(err.max())
+    assert ref[..., 3].max() > 0.5  # the scene is not empty
+    if not amb.any():
+        assert st.samples == ev
+    else:
+        assert abs(st.samples - ev) <= 4 * int(amb.sum())
+
+
+def test_adaptive_pace_does_not_change_the_image(scene):
+    s = scene
+    view = synth.orbit_view(s["dims"], 1.1, 0.2, 64, 48)
+    a, sa = _gpu_render(s, view, 2.25, 64, 48, arm_max=64)
+    b, sb = _gpu_render(s, view, 2.25, 64, 48, arm_max=1)
+    np.testing.assert_array_equal(a, b)
+    assert sa.samples == sb.samples and sa.iterations < sb.iterations
+
+
+def test_step_api_equals_whole_render(scene):
+    s = scene
+    fl = s["fl"]
+    W, H = 40, 32
+    view = synth.orbit_view(s["dims"], 5.0, 0.1, W, H)
+    whole, _ = _gpu_render(s, view, 4.5, W, H)
+    ws = torch.empty(fl.fhash_render_state_bytes(W, H, s["dims"]), dtype=torch.uint8,
+                     device="cuda")
+    rgba = torch.empty(H, W, 4, device="cuda")
+    opts = fl.render_opts()
+    st = fl.fhash_render_begin(fl.view_struct(view), 4.5, W, H, s["bits"], s["dims"], ws, rgba)
+    pos = torch.empty(W * H, 4, device="cuda")
+    y = torch.empty(W * H, device="cuda")
+    while st.n_alive > 0:
+        pace = fl.fhash_render_pace(W * H, st.n_alive, opts.arm_max)
+        ns = fl.fhash_render_march(st, opts, pace, pos, W * H)
+        if ns:
+            fl.fhash_fused_fwd(s["idx"], s["mlp"], pos[:ns], ns, s["tab_d"], s["prm_d"], y)
+        fl.fhash_render_composite(st, y, s["tf_d"], opts, rgba)
+    np.testing.assert_array_equal(rgba.cpu().numpy(), whole)
+
+
+def test_render_empty_mask_is_transparent(scene):
+    s = scene
+    fl = s["fl"]
+    empty = torch.zeros_like(s["bits"])
+    W, H = 20, 20
+    rgba = torch.full((H, W, 4), 5.0, device="cuda")
+    view = synth.orbit_view(s["dims"], 0.0, 0.0, W, H)
+    st, _ = fl.fhash_render(s["idx"], s["mlp"], s["tab_d"], s["prm_d"], empty, s["dims"],
+                            fl.view_struct(view), 1.0, s["tf_d"], W, H, fl.render_opts(), rgba)
+    assert (rgba == 0).all() and st.samples == 0

@@ -1,0 +1,117 @@
+"""GPU: the differentiable wrapper, and what the trained decoder adds.
+
+- The torch.autograd.Function over the fused kernels (corner weights are
+  recomputed in the backward) matches the FP64 oracle gradient and central
+  finite differences of the loss it computes.
+- Learned-part test: the tiny workload trained by the project's own kernels
+  with the decoder trained versus the same tables trained behind a frozen
+  random-init decoder (the method without a learned network).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2507_03836_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2507_03836_amd import _lib as fl
+    fl.lib()
+    f, mask = synth.tiny_volume()
+    T, Sz, Sy, Sx = mask.shape
+    return fl, f, mask, [Sx, Sy, Sz, T]
+
+
+def test_autograd_function_vs_oracle_and_fd(env):
+    fl, f, mask, dims = env
+    from paper_2507_03836_amd.autograd import fhash_apply
+    bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
+    grid = fl.grid_desc(TINY_RES, 2)
+    idx, counts, dir_t, _ = fl.fhash_build_index(grid, bits, dims)
+    width = [8, 32, 32, 1]
+    mlp = fl.mlp_desc(width)
+    g = O.Grid(np.array(TINY_RES), 2, mask)
+    rng = np.random.default_rng(0)
+    table0 = rng.uniform(-0.5, 0.5, size=(g.total_slots, 2)).astype(np.float32)
+    params0 = synth.mlp_init(width)
+    n = 1500
+    pos_np, tgt_np = O.sample_batch(77, 1, n, f, synth.coreset(mask))
+    pos = torch.from_numpy(pos_np).cuda()
+    tgt = torch.from_numpy(tgt_np).cuda()
+    table = torch.from_numpy(table0).cuda().requires_grad_(True)
+    params = torch.from_numpy(params0).cuda().requires_grad_(True)
+    y = fhash_apply(pos, table, params, idx, mlp)
+    loss = ((y - tgt) ** 2).mean()
+    loss.backward()
+    # oracle gradient of the same loss
+    enc, emag = O.encode_fwd(g, pos_np, table0.astype(np.float64))
+    yo, acts, ymag = O.mlp_fwd(width, params0.astype(np.float64), enc, x_mag=emag)
+    L, dy = O.mse(yo[:, 0], tgt_np.astype(np.float64))
+    dym = 2.0 * (ymag[:, 0] + np.abs(tgt_np)) / n
+    dp, denc, dpm, dencm = O.mlp_bwd(width, params0.astype(np.float64), acts, dy.reshape(-1, 1),
+                                     n, dy_mag=dym.reshape(-1, 1), x_mag=emag)
+    dt, _ = O.encode_bwd(g, pos_np, denc)
+    _, dtm = O.encode_bwd(g, pos_np, dencm)
+    gt = table.grad.cpu().numpy().astype(np.float64)
+    gp = params.grad.cpu().numpy().astype(np.float64)
+    assert (np.abs(gt - dt) <= 1e-5 * dtm + 1e-12).all()
+    assert (np.abs(gp - dp) <= 1e-5 * dpm + 1e-12).all()
+    # central differences of the loss through the kernels (FP32 forward, FP64 sum)
+    def loss_at(tab):
+        with torch.no_grad():
+            yy = fhash_apply(pos, tab, params.detach(), idx, mlp)
+            return float(((yy.double() - tgt.double()) ** 2).mean())
+    big = np.argsort(-np.abs(dt.ravel()))[:8]
+    for j in big:
+        h = 1e-2
+        tp = torch.from_numpy(table0.copy()).cuda()
+        tm = tp.clone()
+        tp.view(-1)[j] += h
+        tm.view(-1)[j] -= h
+        fd = (loss_at(tp) - loss_at(tm)) / (2 * h)
+        assert abs(fd - gt.ravel()[j]) <= 2e-2 * abs(gt.ravel()[j]) + 1e-6, (j, fd, gt.ravel()[j])
+
+
+def _train(fl, f, mask, dims, train_mlp, steps=400, seed=5):
+    from paper_2507_03836_amd.model import FHashConfig, FHashModel, psnr_on
+    cfg = FHashConfig(res=TINY_RES, n_features=2, hidden=32, n_hidden=2)
+    bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
+    model = FHashModel(cfg, bits, dims, init_seed=seed)
+    cs = synth.coreset(mask)
+    csd = torch.from_numpy(cs.view(np.int64)).cuda()
+    fd = torch.from_numpy(f).cuda()
+    n = 4096
+    pos = torch.empty(n, 4, device="cuda")
+    tgt = torch.empty(n, device="cuda")
+    for k in range(1, steps + 1):
+        fl.fhash_sample(2001, k, n, csd, cs.size, dims, fd, pos, tgt)
+        model.fwd_bwd(pos, tgt)
+        if not train_mlp:
+            model.d_mlp.zero_()
+            model.step_count += 1
+            n_tab = model.mlp_off
+            fl.fhash_step(model.adam_desc(model.step_count), model.params[:n_tab],
+                          model.grads[:n_tab], model.m[:n_tab], model.v[:n_tab])
+        else:
+            model.optimizer_step()
+    # PSNR over every coreset voxel
+    allpos = torch.from_numpy(O.voxel_positions(cs, dims)).cuda()
+    alltgt = fd.view(-1)[csd]
+    return psnr_on(model, allpos, alltgt)
+
+
+def test_trained_decoder_gain(env):
+    fl, f, mask, dims = env
+    p_full = _train(fl, f, mask, dims, True)
+    p_frozen = _train(fl, f, mask, dims, False)
+    print(f"PSNR trained decoder {p_full:.2f} dB, frozen random decoder {p_frozen:.2f} dB")
+    assert p_full > 25.0
+    assert p_full > p_frozen + 2.0

@@ -1,0 +1,61 @@
+"""The C-ABI library loads on the host and exports every symbol the header declares."""
+import ctypes
+import os
+import re
+
+from paper_2507_03836_amd import _lib as fl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names.update(re.findall(r"\b(fhash_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("fhash_build_index", "fhash_encode_fwd", "fhash_encode_bwd", "fhash_mlp_fwd",
+              "fhash_mlp_bwd", "fhash_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(fl.LIB_PATH)
+    missing = [n for n in sorted(_declared()) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(fl.exported_symbols()) <= _declared()
+
+
+def test_version_and_host_validation():
+    L = fl.lib()
+    assert fl.fhash_version() == 1
+    # invalid grid: rejected on the host before any launch (no GPU needed)
+    g = fl.grid_desc([[1, 4, 4, 4]], 2)
+    e = ctypes.c_int64()
+    rc = L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e))
+    assert rc == fl.EINVAL and b"res[0][0]" in L.fhash_last_error()
+    g = fl.grid_desc([[4, 4, 4, 2], [8, 8, 8, 3]], 3)
+    assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.EINVAL
+    g = fl.grid_desc([[4, 4, 4, 2], [65, 8, 8, 3]], 2)
+    assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.OK
+    assert e.value == 4 * 4 * 2 * 1 + 8 * 8 * 3 * 2
+    idx, slots = fl.fhash_dense_index(g)
+    assert slots == [4 * 4 * 4 * 2, 65 * 8 * 8 * 3] and idx.active == 0
+    assert idx.slot_offset[2] == sum(slots)
+    m = fl.mlp_desc([32, 64, 64, 1])
+    assert fl.fhash_mlp_num_params(m) == 32 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+    # unsupported decoder shape reported as ENOTSUP
+    m2 = fl.mlp_desc([32, 48, 64, 1])
+    rc = L.fhash_mlp_fwd(ctypes.byref(m2), None, None, None, 10, None, None)
+    assert rc == fl.ENOTSUP
+    # workspace query of the MLP backward needs no device
+    nb = ctypes.c_size_t(0)
+    rc = L.fhash_mlp_bwd(ctypes.byref(m), None, None, None, None, 1 << 18, None, None, None,
+                         ctypes.byref(nb), None)
+    assert rc == fl.OK and nb.value > 0

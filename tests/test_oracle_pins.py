@@ -449,3 +449,19 @@ def test_adam_matches_torch_optim_float64():
         tp.grad = torch.tensor(g, dtype=torch.float64)
         opt.step()
     np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_one_by_one_vertex_activity_matches_enumeration():
+    from paper_2507_03836_amd import synth
+    rng = np.random.default_rng(16)
+    for trial in range(10):
+        S = rng.integers(2, 80, size=4)
+        S[3] = rng.integers(2, 7)
+        mask = (rng.random((S[3], S[2], S[1], S[0])) < rng.uniform(0.001, 0.2)).astype(np.uint8)
+        res = [int(rng.integers(2, 40)) for _ in range(3)] + [int(rng.integers(2, 8))]
+        bits = synth.pack_mask_rows(mask)
+        slots, _ = O.level_slots(res, mask)
+        Rx, Ry, Rz, Rt = res
+        for q in rng.choice(len(slots), min(50, len(slots)), replace=False):
+            v = [q % Rx, (q // Rx) % Ry, (q // (Rx * Ry)) % Rz, q // (Rx * Ry * Rz)]
+            assert O.vertex_active_bits(res, bits, list(S), v) == (slots[q] >= 0)
