@@ -55,10 +55,12 @@ def test_render_matches_oracle(scene, az, el, t, W, H):
     err = np.abs(img - ref)[ok]
     assert err.max() < 2e-4, float(err.max())
     assert ref[..., 3].max() > 0.5  # the scene is not empty
-    if not amb.any():
-        assert st.samples == ev
-    else:
-        assert abs(st.samples - ev) <= 4 * int(amb.sum())
+    # pace 1 evaluates exactly the composited samples; a larger pace may also
+    # decode samples past a ray's termination point in its last batch (discarded)
+    img1, st1 = _gpu_render(s, view, t, W, H, arm_max=1)
+    np.testing.assert_array_equal(img1, img)
+    assert abs(st1.samples - ev) <= 2 * int(amb.sum())
+    assert st.samples >= st1.samples
 
 
 def test_adaptive_pace_does_not_change_the_image(scene):
@@ -67,7 +69,7 @@ def test_adaptive_pace_does_not_change_the_image(scene):
     a, sa = _gpu_render(s, view, 2.25, 64, 48, arm_max=64)
     b, sb = _gpu_render(s, view, 2.25, 64, 48, arm_max=1)
     np.testing.assert_array_equal(a, b)
-    assert sa.samples == sb.samples and sa.iterations < sb.iterations
+    assert sa.samples >= sb.samples and sa.iterations < sb.iterations
 
 
 def test_step_api_equals_whole_render(scene):
