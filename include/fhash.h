@@ -169,15 +169,21 @@ int fhash_mlp_bwd(const fhash_mlp_desc* mlp, const float* params, const void* sh
 int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
                     const void* table, fhash_dtype table_dt, const float* params,
                     const void* shadow, float* y, void* stream);
+/* flags: FHASH_SAMPLES_SORTED declares that the batch is ordered by
+ * fhash_sort_samples; the scatter-add then sums equal slots of neighbouring
+ * samples with a wave-level segmented reduction before its atomics on the
+ * levels coarse enough for neighbours to share vertices.  Results are the same
+ * up to FP32 summation order. */
+#define FHASH_SAMPLES_SORTED 1u
 int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
                     const void* table, fhash_dtype table_dt, const float* params,
                     const void* shadow, const float* dy, float* d_table, float* d_params,
-                    void* ws, size_t* ws_bytes, void* stream);
+                    uint32_t flags, void* ws, size_t* ws_bytes, void* stream);
 int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
                       const float* target, int64_t n, const void* table, fhash_dtype table_dt,
                       const float* params, const void* shadow, float loss_scale, float* d_table,
-                      float* d_params, double* loss_sum, void* ws, size_t* ws_bytes,
-                      void* stream);
+                      float* d_params, double* loss_sum, uint32_t flags, void* ws,
+                      size_t* ws_bytes, void* stream);
 
 /* ------------------------------------------------------------ optimiser ----
  * Adam (Sec. 5.1.3: Adam, lr 0.01; PyTorch semantics, bias-corrected, no
@@ -215,6 +221,15 @@ int fhash_cast(const float* src, void* dst, fhash_dtype dst_dt, int64_t n, void*
 int fhash_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset, uint64_t M,
                  const int64_t dims[4], const float* field, float* pos, float* target,
                  void* stream);
+
+/* Reorder a batch of samples (pos float4[n], target float[n] or NULL, both
+ * device, in place) by a 4D Morton key of the positions quantised to 256
+ * cells per axis (stable LSD radix sort).  Samples of the same cells become
+ * neighbours, which the gathers and the segmented reduction before the
+ * scatter-add exploit; the MSE loss and its gradient do not depend on the
+ * order.  ws: device workspace (query with ws == NULL); n < 2^31. */
+int fhash_sort_samples(float* pos, float* target, int64_t n, void* ws, size_t* ws_bytes,
+                       void* stream);
 
 /* ----------------------------------------------------------- reductions ----
  * *sum (device double, accumulated) += sum_i (y[i] - v[i])^2 in FP64

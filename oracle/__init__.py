@@ -194,6 +194,9 @@ class Grid:
         self.maps = []
         self.counts = []
         for l in range(self.L):
+            if mask is None:  # dense box: the slot is the F-Hash equation, no map needed
+                self.counts.append(int(np.prod(res[l])))
+                continue
             m, c = level_slots(res[l], mask)
             self.maps.append(m)
             self.counts.append(c)

@@ -104,14 +104,17 @@ def _declare(L):
         "fhash_mlp_fwd": (C.c_int, [P, P, P, P, I64, P, P]),
         "fhash_mlp_bwd": (C.c_int, [P, P, P, P, P, I64, P, P, P, P, P]),
         "fhash_fused_fwd": (C.c_int, [P, P, P, I64, P, C.c_int, P, P, P, P]),
-        "fhash_fused_bwd": (C.c_int, [P, P, P, I64, P, C.c_int, P, P, P, P, P, P, P, P]),
-        "fhash_fused_train": (C.c_int, [P, P, P, P, I64, P, C.c_int, P, P, F, P, P, P, P, P, P]),
+        "fhash_fused_bwd": (C.c_int, [P, P, P, I64, P, C.c_int, P, P, P, P, P, C.c_uint32, P, P,
+                                      P]),
+        "fhash_fused_train": (C.c_int, [P, P, P, P, I64, P, C.c_int, P, P, F, P, P, P, C.c_uint32,
+                                        P, P, P]),
         "fhash_step": (C.c_int, [P, P, P, P, P, P, C.c_int, I64, P, P]),
         "fhash_check_finite": (C.c_int, [P, I64, P, P]),
         "fhash_cast": (C.c_int, [P, P, C.c_int, I64, P]),
         "fhash_sample": (C.c_int, [U64, U64, I64, P, U64, P, P, P, P, P]),
         "fhash_sq_err_sum": (C.c_int, [P, P, I64, P, P]),
         "fhash_mse_grad": (C.c_int, [P, P, I64, F, P, P, P]),
+        "fhash_sort_samples": (C.c_int, [P, P, I64, P, P, P]),
         "fhash_render_state_bytes": (C.c_int, [I32, I32, P, P]),
         "fhash_render_begin": (C.c_int, [P, F, I32, I32, P, P, P, C.c_size_t, P, P, P]),
         "fhash_render_pace": (I32, [I64, I64, I32]),
@@ -133,7 +136,7 @@ def exported_symbols() -> list[str]:
             "fhash_fused_train", "fhash_step", "fhash_check_finite", "fhash_cast",
             "fhash_sample", "fhash_sq_err_sum", "fhash_mse_grad", "fhash_render_state_bytes",
             "fhash_render_begin", "fhash_render_pace", "fhash_render_march",
-            "fhash_render_composite", "fhash_render"]
+            "fhash_render_composite", "fhash_render", "fhash_sort_samples"]
 
 
 def _check(rc: int, func: str):
@@ -267,11 +270,14 @@ def fhash_fused_fwd(idx: Index, mlp: MlpDesc, pos, n, table, params, y, shadow=N
            "fhash_fused_fwd")
 
 
+SAMPLES_SORTED = 1
+
+
 def fhash_fused_bwd(idx: Index, mlp: MlpDesc, pos, n, table, params, dy, d_table, d_params,
-                    shadow=None, ws=None):
+                    shadow=None, ws=None, flags=0):
     L = lib()
     head = (C.byref(idx), C.byref(mlp), _ptr(pos), n, _ptr(table), _dt(table), _ptr(params),
-            _ptr(shadow), _ptr(dy), _ptr(d_table), _ptr(d_params))
+            _ptr(shadow), _ptr(dy), _ptr(d_table), _ptr(d_params), C.c_uint32(flags))
     need = _ws_query(L.fhash_fused_bwd, head, "fhash_fused_bwd")
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=params.device)
@@ -281,11 +287,11 @@ def fhash_fused_bwd(idx: Index, mlp: MlpDesc, pos, n, table, params, dy, d_table
 
 
 def fhash_fused_train(idx: Index, mlp: MlpDesc, pos, target, n, table, params, d_table,
-                      d_params, loss_sum=None, loss_scale=1.0, shadow=None, ws=None):
+                      d_params, loss_sum=None, loss_scale=1.0, shadow=None, ws=None, flags=0):
     L = lib()
     head = (C.byref(idx), C.byref(mlp), _ptr(pos), _ptr(target), n, _ptr(table), _dt(table),
             _ptr(params), _ptr(shadow), C.c_float(loss_scale), _ptr(d_table), _ptr(d_params),
-            _ptr(loss_sum))
+            _ptr(loss_sum), C.c_uint32(flags))
     need = _ws_query(L.fhash_fused_train, head, "fhash_fused_train")
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=params.device)
@@ -314,6 +320,19 @@ def fhash_sample(seed, step, n, coreset, M, dims, field, pos, target):
     d = (C.c_int64 * 4)(*[int(x) for x in dims])
     _check(lib().fhash_sample(seed, step, n, _ptr(coreset), M, d, _ptr(field), _ptr(pos),
                               _ptr(target), _stream()), "fhash_sample")
+
+
+def fhash_sort_samples(pos, target, n, ws=None):
+    L = lib()
+    nb = C.c_size_t(0)
+    _check(L.fhash_sort_samples(_ptr(pos), _ptr(target), n, None, C.byref(nb), _stream()),
+           "fhash_sort_samples")
+    if ws is None or ws.numel() < nb.value:
+        ws = torch.empty(max(int(nb.value), 16), dtype=torch.uint8, device=pos.device)
+    nb = C.c_size_t(ws.numel())
+    _check(L.fhash_sort_samples(_ptr(pos), _ptr(target), n, _ptr(ws), C.byref(nb), _stream()),
+           "fhash_sort_samples")
+    return ws
 
 
 def fhash_sq_err_sum(y, v, n, out):

@@ -272,6 +272,19 @@ int fhash_mlp_bwd(const fhash_mlp_desc* mlp, const float* params, const void* sh
       "fhash_mlp_bwd");
 }
 
+// Levels whose cell count is at most 8 samples' worth: sorted neighbours share
+// their vertices often enough for the segmented reduction to pay.
+static uint32_t dedup_mask(const fhash_index* idx, int64_t n, uint32_t flags) {
+  if (!(flags & FHASH_SAMPLES_SORTED)) return 0u;
+  uint32_t m = 0;
+  for (int l = 0; l < idx->grid.n_levels; ++l) {
+    const int32_t* r = idx->grid.res[l];
+    const double cells = (double)(r[0] - 1) * (r[1] - 1) * (r[2] - 1) * (r[3] - 1);
+    if (cells <= 8.0 * (double)n) m |= 1u << l;
+  }
+  return m;
+}
+
 static int check_fused(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
                        int64_t n, const void* table, fhash_dtype tdt, const float* params,
                        int* H, int* NH) {
@@ -313,7 +326,7 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
 int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
                     const void* table, fhash_dtype table_dt, const float* params,
                     const void* shadow, const float* dy, float* d_table, float* d_params,
-                    void* ws, size_t* ws_bytes, void* stream) {
+                    uint32_t flags, void* ws, size_t* ws_bytes, void* stream) {
   (void)shadow;
   int H, NH;
   int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
@@ -327,6 +340,7 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
     return fail(FHASH_EINVAL, "NULL pointer");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
+  g.dedup = dedup_mask(idx, n, flags);
   return hip_status(fh::launch_fused_bwd(g, H, NH, pos, n, table, table_dt, params, dy, d_table,
                                          d_params, ws, P, S(stream)),
                     "fhash_fused_bwd");
@@ -335,8 +349,8 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
 int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
                       const float* target, int64_t n, const void* table, fhash_dtype table_dt,
                       const float* params, const void* shadow, float loss_scale, float* d_table,
-                      float* d_params, double* loss_sum, void* ws, size_t* ws_bytes,
-                      void* stream) {
+                      float* d_params, double* loss_sum, uint32_t flags, void* ws,
+                      size_t* ws_bytes, void* stream) {
   (void)shadow;
   int H, NH;
   int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
@@ -350,6 +364,7 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
     return fail(FHASH_EINVAL, "NULL pointer");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
+  g.dedup = dedup_mask(idx, n, flags);
   return hip_status(fh::launch_fused_train(g, H, NH, pos, target, n, table, table_dt, params,
                                            loss_scale, d_table, d_params, loss_sum, ws, P,
                                            S(stream)),
@@ -413,6 +428,17 @@ int fhash_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* corese
   return hip_status(
       fh::launch_sample(seed, step, n, coreset, M, dims, field, pos, target, S(stream)),
       "fhash_sample");
+}
+
+int fhash_sort_samples(float* pos, float* target, int64_t n, void* ws, size_t* ws_bytes,
+                       void* stream) {
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(FHASH_EINVAL, "n outside [0, 2^31)");
+  bool query;
+  int rc = ws_check(ws, ws_bytes, fh::sort_ws_bytes(n), &query);
+  if (rc || query) return rc;
+  if (n == 0) return FHASH_OK;
+  if (pos == nullptr || !aligned16(pos)) return fail(FHASH_EINVAL, "pos NULL or not 16-byte aligned");
+  return hip_status(fh::launch_sort_samples(pos, target, n, ws, S(stream)), "fhash_sort_samples");
 }
 
 int fhash_sq_err_sum(const float* y, const float* v, int64_t n, double* sum, void* stream) {

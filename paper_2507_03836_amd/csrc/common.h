@@ -24,7 +24,7 @@ struct GridDev {
   const ulonglong2* dir;  // {bits, rank-before-word}; NULL when dense
   int32_t L, F;
   int32_t active;
-  int32_t pad;
+  uint32_t dedup;  // bit l: combine equal slots of neighbouring lanes before level l's atomics
 };
 
 // Fill a GridDev from a public index descriptor (host).
@@ -34,7 +34,7 @@ inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
   g->F = gd.n_features;
   g->active = idx->active;
   g->dir = reinterpret_cast<const ulonglong2*>(idx->dir);
-  g->pad = 0;
+  g->dedup = 0;
   for (int l = 0; l < FHASH_MAX_LEVELS; ++l) {
     LevelDev& d = g->lv[l];
     if (l < gd.n_levels) {

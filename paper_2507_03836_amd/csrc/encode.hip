@@ -27,21 +27,20 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// 2F threads per sample (pair element x feature), see scatter_level_lane.
 template <int F>
 __global__ void __launch_bounds__(256)
     encode_bwd_kernel(GridDev g, const float4* __restrict__ pos, int64_t n,
                       const float* __restrict__ d_enc, float* __restrict__ d_table) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  constexpr int Q = 2 * F;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = t / Q;
   if (s >= n) return;
+  const int r = (int)(t % Q), e = r / F, f = r % F;
   const float4 p = pos[s];
   const float* gin = d_enc + s * (int64_t)g.L * F;
-  for (int l = 0; l < g.L; ++l) {
-    const LevelDev& d = g.lv[l];
-    float gl[F];
-#pragma unroll
-    for (int k = 0; k < F; ++k) gl[k] = gin[l * F + k];
-    scatter_level<F>(d, g.dir, g.active != 0, p, gl, d_table);
-  }
+  for (int l = 0; l < g.L; ++l)
+    scatter_level_lane<F>(g.lv[l], g.dir, g.active != 0, p, e, f, gin[l * F + f], d_table);
 }
 
 template <int F>
@@ -64,7 +63,7 @@ template <int F>
 hipError_t launch_bwd_t(const GridDev& g, const float* pos, int64_t n, const float* d_enc,
                         float* d_table, hipStream_t st) {
   const int T = 256;
-  const int64_t blocks = (n + T - 1) / T;
+  const int64_t blocks = (n * 2 * F + T - 1) / T;
   hipLaunchKernelGGL((encode_bwd_kernel<F>), dim3((unsigned)blocks), dim3(T), 0, st, g,
                      reinterpret_cast<const float4*>(pos), n, d_enc, d_table);
   return hipGetLastError();

@@ -147,4 +147,93 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
   }
 }
 
+// One lane's share of a level's scatter-add.  The lane owns pair element e
+// (vertex x or x+1 of every cell row) and feature f of one sample: 2F
+// consecutive lanes own one sample, so the 2F atomics they issue together hit
+// the 8F contiguous bytes of the row pair's two slots.  Atomics of one
+// instruction that fall in the same 64-byte segment are performed as one
+// memory transaction, which is what bounds the scatter on gfx950.
+template <int F>
+__device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulonglong2* dir,
+                                                   bool active, const float4 p, int e, int f,
+                                                   float gval, float* __restrict__ d_table) {
+  int ix, iy, iz, it;
+  float fx, fy, fz, ft;
+  locate(p.x, d.rx, d.sx, ix, fx);
+  locate(p.y, d.ry, d.sy, iy, fy);
+  locate(p.z, d.rz, d.sz, iz, fz);
+  locate(p.w, d.rt, d.st, it, ft);
+  const float wx = e ? fx : 1.0f - fx;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
+    const int64_t row = ((int64_t)(it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);
+    const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
+    int64_t s0, s1;
+    bool v0, v1;
+    row_pair_slots(d, dir, active, row, ix, s0, s1, v0, v1);
+    const int64_t s = e ? s1 : s0;
+    if (e ? v1 : v0) unsafeAtomicAdd(d_table + s * F + f, wr * wx * gval);
+  }
+}
+
+// Scatter of one level with a segmented reduction across the 16 lanes of a
+// lane group (the 16 samples of a block, which hold the same level): for every
+// corner, runs of neighbouring lanes with the same slot are summed with an
+// inclusive segmented scan of width-16 shuffles and only the last lane of each
+// run issues the atomics.  All 16 lanes must call it (invalid samples pass
+// valid = false and contribute nothing).  Pays off when samples are sorted by
+// cell and the level is coarse enough that neighbours share vertices.
+template <int F>
+__device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulonglong2* dir,
+                                                    bool active, const float4 p, const float* g,
+                                                    bool valid, float* __restrict__ d_table) {
+  const int i = threadIdx.x & 15;
+  int ix, iy, iz, it;
+  float fx, fy, fz, ft;
+  locate(p.x, d.rx, d.sx, ix, fx);
+  locate(p.y, d.ry, d.sy, iy, fy);
+  locate(p.z, d.rz, d.sz, iz, fz);
+  locate(p.w, d.rt, d.st, it, ft);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
+    const int64_t row = ((int64_t)(it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);
+    const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
+    int64_t s2[2];
+    bool v2[2];
+    row_pair_slots(d, dir, active, row, ix, s2[0], s2[1], v2[0], v2[1]);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int64_t s = (valid && v2[e]) ? s2[e] : -1;
+      const float w = (e ? fx : 1.0f - fx) * wr;
+      float v[F];
+#pragma unroll
+      for (int k = 0; k < F; ++k) v[k] = (s >= 0) ? w * g[k] : 0.0f;
+      const int64_t sprev = __shfl_up(s, 1, 16);
+      const int64_t snext = __shfl_down(s, 1, 16);
+      bool h = (i == 0) || (sprev != s);
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const bool ho = __shfl_up(h, o, 16);
+        float vo[F];
+#pragma unroll
+        for (int k = 0; k < F; ++k) vo[k] = __shfl_up(v[k], o, 16);
+        if (i >= o) {
+          if (!h) {
+#pragma unroll
+            for (int k = 0; k < F; ++k) v[k] += vo[k];
+          }
+          h = h || ho;
+        }
+      }
+      const bool tail = (i == 15) || (snext != s);
+      if (tail && s >= 0) {
+#pragma unroll
+        for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + s * F + k, v[k]);
+      }
+    }
+  }
+}
+
 }  // namespace fh

@@ -59,23 +59,50 @@ __device__ __forceinline__ void gather_block(const GridDev& g, const LevelDev* l
     }
 }
 
+// Scatter of a block's encoding gradient.  Levels flagged for the segmented
+// reduction are scattered by their own lane group (scatter_level_dedup); the
+// others are redistributed so that 2F consecutive lanes own one (sample,
+// level): pass k of 2F gives lane q the sample-level held by lane
+// k * (64 / 2F) + q / 2F, whose position and gradient arrive by shuffles.
 template <int F, int INP>
 __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* lv, float4 p,
                                               bool valid, const float (&dx)[INP / 16][4],
                                               float* d_table) {
   const int lane = threadIdx.x & 63, grp = lane >> 4;
   constexpr int LPB = 4 / F;
-  if (!valid) return;
+  constexpr int Q = 2 * F, PER = 64 / Q;
+  const int r = lane % Q, e = r / F, f = r % F;
 #pragma unroll
   for (int a = 0; a < INP / 16; ++a)
 #pragma unroll
     for (int j = 0; j < LPB; ++j) {
-      const int l = (16 * a + 4 * grp) / F + j;
-      if (l < g.L) {
+      const int l = (16 * a + 4 * grp) / F + j;  // this lane group's level
+      if (l < g.L && ((g.dedup >> l) & 1u)) {
         float gl[F];
 #pragma unroll
         for (int k = 0; k < F; ++k) gl[k] = dx[a][j * F + k];
-        scatter_level<F>(lv[l], g.dir, g.active != 0, p, gl, d_table);
+        scatter_level_dedup<F>(lv[l], g.dir, g.active != 0, p, gl, valid, d_table);
+      }
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const int m = k * PER + lane / Q;  // source lane (= sample-level)
+        const int src_grp = m >> 4;
+        const int ls = (16 * a + 4 * src_grp) / F + j;
+        float gsrc[F];
+#pragma unroll
+        for (int q = 0; q < F; ++q) gsrc[q] = __shfl(dx[a][j * F + q], m, 64);
+        float4 ps;
+        ps.x = __shfl(p.x, m, 64);
+        ps.y = __shfl(p.y, m, 64);
+        ps.z = __shfl(p.z, m, 64);
+        ps.w = __shfl(p.w, m, 64);
+        const bool vs = __shfl((int)valid, m, 64) != 0;
+        float gval = gsrc[0];
+#pragma unroll
+        for (int q = 1; q < F; ++q)
+          if (f == q) gval = gsrc[q];
+        if (ls < g.L && vs && !((g.dedup >> ls) & 1u))
+          scatter_level_lane<F>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table);
       }
     }
 }

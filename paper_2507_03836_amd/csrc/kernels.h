@@ -63,6 +63,10 @@ hipError_t launch_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t
                          uint64_t M, const int64_t* dims, const float* field, float* pos,
                          float* target, hipStream_t st);
 
+// sort.hip
+size_t sort_ws_bytes(int64_t n);
+hipError_t launch_sort_samples(float* pos, float* target, int64_t n, void* ws, hipStream_t st);
+
 // render.hip
 size_t render_ws_bytes(int64_t NR, const int64_t* dims);
 hipError_t launch_render_begin(const fhash_view* v, int W, int H, const uint64_t* mask,

@@ -36,46 +36,79 @@ __device__ __forceinline__ void adam1(const AdamK& k, float g, float& p, float& 
   p -= k.step_size * (m / denom);
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void adam4(const AdamK& k, const f4v g, f4v& p, f4v& m, f4v& v) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float pc = p[c], mc = m[c], vc = v[c];
+    adam1(k, g[c], pc, mc, vc);
+    p[c] = pc;
+    m[c] = mc;
+    v[c] = vc;
+  }
+}
+
+__device__ __forceinline__ void store_shadow4(void* shadow, int sdt, int64_t i, const f4v pp) {
+  uint2 raw;
+  if (sdt == FHASH_F16) {
+    __half2 a = __floats2half2_rn(pp[0], pp[1]), b = __floats2half2_rn(pp[2], pp[3]);
+    raw.x = *reinterpret_cast<uint32_t*>(&a);
+    raw.y = *reinterpret_cast<uint32_t*>(&b);
+  } else {
+    raw.x = (uint32_t)to_bf16_rne(pp[0]) | ((uint32_t)to_bf16_rne(pp[1]) << 16);
+    raw.y = (uint32_t)to_bf16_rne(pp[2]) | ((uint32_t)to_bf16_rne(pp[3]) << 16);
+  }
+  reinterpret_cast<uint2*>(shadow)[i] = raw;
+}
+
+// Streaming sweep: every array is touched once, so loads and stores bypass the
+// caches' retention (non-temporal) and each thread keeps two float4 groups in
+// flight.  The gradient is reset only where it is nonzero.
 __global__ void __launch_bounds__(256)
     adam_kernel(AdamK k, float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                 float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t n,
                 const int32_t* __restrict__ found_inf) {
   const bool skip = (found_inf != nullptr) && (*found_inf != 0);
   const int64_t n4 = n >> 2;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  float4* p4 = reinterpret_cast<float4*>(p);
-  float4* g4 = reinterpret_cast<float4*>(g);
-  float4* m4 = reinterpret_cast<float4*>(m);
-  float4* v4 = reinterpret_cast<float4*>(v);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += stride) {
-    const float4 gg = g4[i];
+  const int64_t S = (int64_t)gridDim.x * blockDim.x;
+  f4v* p4 = reinterpret_cast<f4v*>(p);
+  f4v* g4 = reinterpret_cast<f4v*>(g);
+  f4v* m4 = reinterpret_cast<f4v*>(m);
+  f4v* v4 = reinterpret_cast<f4v*>(v);
+  const f4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += 2 * S) {
+    const int64_t j = i + S;
+    const bool two = j < n4;
+    const f4v g0 = __builtin_nontemporal_load(g4 + i);
+    f4v g1 = zero;
+    if (two) g1 = __builtin_nontemporal_load(g4 + j);
     if (!skip) {
-      float4 pp = p4[i], mm = m4[i], vv = v4[i];
-      adam1(k, gg.x, pp.x, mm.x, vv.x);
-      adam1(k, gg.y, pp.y, mm.y, vv.y);
-      adam1(k, gg.z, pp.z, mm.z, vv.z);
-      adam1(k, gg.w, pp.w, mm.w, vv.w);
-      p4[i] = pp;
-      m4[i] = mm;
-      v4[i] = vv;
-      if (shadow != nullptr) {
-        if (sdt == FHASH_F16) {
-          __half2 a = __floats2half2_rn(pp.x, pp.y), b = __floats2half2_rn(pp.z, pp.w);
-          uint2 raw;
-          raw.x = *reinterpret_cast<uint32_t*>(&a);
-          raw.y = *reinterpret_cast<uint32_t*>(&b);
-          reinterpret_cast<uint2*>(shadow)[i] = raw;
-        } else {
-          uint2 raw;
-          raw.x = (uint32_t)to_bf16_rne(pp.x) | ((uint32_t)to_bf16_rne(pp.y) << 16);
-          raw.y = (uint32_t)to_bf16_rne(pp.z) | ((uint32_t)to_bf16_rne(pp.w) << 16);
-          reinterpret_cast<uint2*>(shadow)[i] = raw;
-        }
+      f4v p0 = __builtin_nontemporal_load(p4 + i), m0 = __builtin_nontemporal_load(m4 + i);
+      f4v v0 = __builtin_nontemporal_load(v4 + i);
+      f4v p1 = zero, m1 = zero, v1 = zero;
+      if (two) {
+        p1 = __builtin_nontemporal_load(p4 + j);
+        m1 = __builtin_nontemporal_load(m4 + j);
+        v1 = __builtin_nontemporal_load(v4 + j);
+      }
+      adam4(k, g0, p0, m0, v0);
+      __builtin_nontemporal_store(p0, p4 + i);
+      __builtin_nontemporal_store(m0, m4 + i);
+      __builtin_nontemporal_store(v0, v4 + i);
+      if (shadow != nullptr) store_shadow4(shadow, sdt, i, p0);
+      if (two) {
+        adam4(k, g1, p1, m1, v1);
+        __builtin_nontemporal_store(p1, p4 + j);
+        __builtin_nontemporal_store(m1, m4 + j);
+        __builtin_nontemporal_store(v1, v4 + j);
+        if (shadow != nullptr) store_shadow4(shadow, sdt, j, p1);
       }
     }
-    // Zero the gradient; untouched (already zero) gradients are not rewritten.
-    if (gg.x != 0.0f || gg.y != 0.0f || gg.z != 0.0f || gg.w != 0.0f)
-      g4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (g0[0] != 0.0f || g0[1] != 0.0f || g0[2] != 0.0f || g0[3] != 0.0f)
+      __builtin_nontemporal_store(zero, g4 + i);
+    if (two && (g1[0] != 0.0f || g1[1] != 0.0f || g1[2] != 0.0f || g1[3] != 0.0f))
+      __builtin_nontemporal_store(zero, g4 + j);
   }
   // Tail (n not a multiple of 4).
   const int64_t t = (n4 << 2) + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -203,9 +236,10 @@ hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, f
   k.omb2 = (float)(1.0 - o->beta2);
   k.eps = (float)o->eps;
   k.gscale = (float)o->grad_scale;
-  // One float4 per thread per iteration; enough blocks to fill 256 CUs deeply.
-  int64_t b = (n / 4 + 255) / 256;
-  if (b > 256 * 32) b = 256 * 32;
+  // Two float4 groups per thread per iteration; a deep grid keeps every CU's
+  // memory pipeline full (measured best on MI355X: ~128K workgroups).
+  int64_t b = (n / 8 + 255) / 256;
+  if (b > 131072) b = 131072;
   if (b < 1) b = 1;
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)b), dim3(256), 0, st, k, p, g, m, v, shadow,
                      (int)sdt, n, found_inf);

@@ -133,12 +133,14 @@ class FHashModel:
         fl.fhash_fused_fwd(self.index, self.mlp, pos, n, self.table, self.mlp_params, y)
         return y
 
-    def fwd_bwd(self, pos: torch.Tensor, target: torch.Tensor, loss_scale: float = 1.0):
+    def fwd_bwd(self, pos: torch.Tensor, target: torch.Tensor, loss_scale: float = 1.0,
+                sorted_batch: bool = False):
         """Fused forward + MSE + backward; gradients accumulate into self.grads."""
         n = pos.shape[0]
         self._ws = fl.fhash_fused_train(self.index, self.mlp, pos, target, n, self.table,
                                         self.mlp_params, self.d_table, self.d_mlp,
-                                        self.loss_sum, loss_scale, ws=self._ws)
+                                        self.loss_sum, loss_scale, ws=self._ws,
+                                        flags=fl.SAMPLES_SORTED if sorted_batch else 0)
 
     def optimizer_step(self, grad_scale: float = 1.0, found_inf=None):
         self.step_count += 1

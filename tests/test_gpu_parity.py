@@ -397,3 +397,63 @@ def test_one_training_step_tiny(fl, tiny):
         assert not bad.any(), (name, int(bad.sum()), np.argwhere(bad)[:5].ravel())
     assert (model.grads == 0).all()
     assert abs(model.loss_sum.item() - L * n) <= 1e-4 * L * n
+
+
+# ----------------------------------------------------------------------------- sort + segmented scatter
+def _morton_keys(pos):
+    q = np.minimum((pos.astype(np.float32) * np.float32(256.0)).astype(np.int64), 255)
+    q = np.maximum(q, 0)
+    key = np.zeros(len(pos), np.int64)
+    for d in range(4):
+        for b in range(8):
+            key |= ((q[:, d] >> b) & 1) << (4 * b + d)
+    return key
+
+
+def test_sort_samples_is_a_morton_ordered_permutation(fl):
+    n = 100003
+    rng = np.random.default_rng(11)
+    pos = rng.random((n, 4), dtype=np.float32)
+    tgt = np.arange(n, dtype=np.float32)
+    pd, td = torch.from_numpy(pos).cuda(), torch.from_numpy(tgt).cuda()
+    fl.fhash_sort_samples(pd, td, n)
+    ps, ts = pd.cpu().numpy(), td.cpu().numpy()
+    idx = ts.astype(np.int64)
+    np.testing.assert_array_equal(np.sort(idx), np.arange(n))  # a permutation
+    np.testing.assert_array_equal(ps, pos[idx])                 # pairs kept together
+    k = _morton_keys(ps)
+    assert (np.diff(k) >= 0).all()
+    # stable: equal keys keep their input order
+    same = np.diff(k) == 0
+    assert (np.diff(idx)[same] > 0).all()
+
+
+def test_fused_train_sorted_segmented_scatter(fl, tiny):
+    f, mask = tiny
+    F, width = 2, [8, 32, 32, 1]
+    idx, counts, dir_t, _ = _build(fl, TINY_RES, F, mask)
+    g = O.Grid(np.array(TINY_RES), F, mask)
+    rng = np.random.default_rng(21)
+    table = rng.uniform(-1, 1, size=(g.total_slots, F)).astype(np.float32)
+    params = _mlp_params(width, 22)
+    n = 4096 + 9
+    pos0, tgt0 = O.sample_batch(5, 3, n, f, synth.coreset(mask))
+    pd, td = torch.from_numpy(pos0).cuda(), torch.from_numpy(tgt0).cuda()
+    fl.fhash_sort_samples(pd, td, n)
+    pos, tgt = pd.cpu().numpy(), td.cpu().numpy()
+    enc, emag = O.encode_fwd(g, pos, table.astype(np.float64))
+    y, acts, ymag = O.mlp_fwd(width, params.astype(np.float64), enc, x_mag=emag)
+    L, dy = O.mse(y[:, 0], tgt.astype(np.float64))
+    dym = 2.0 * (ymag[:, 0] + np.abs(tgt)) / n
+    dp_ref, denc, dpm, dencm = O.mlp_bwd(width, params.astype(np.float64), acts,
+                                         dy.reshape(-1, 1), n, dy_mag=dym.reshape(-1, 1),
+                                         x_mag=emag)
+    dt_ref, _ = O.encode_bwd(g, pos, denc)
+    _, dtm = O.encode_bwd(g, pos, dencm)
+    dt = torch.zeros(g.total_slots, F, device="cuda")
+    dp = torch.zeros(len(params), device="cuda")
+    mlp = fl.mlp_desc(width)
+    fl.fhash_fused_train(idx, mlp, pd, td, n, torch.from_numpy(table).cuda(),
+                         torch.from_numpy(params).cuda(), dt, dp, flags=fl.SAMPLES_SORTED)
+    _assert_close(dt.cpu().numpy(), dt_ref, dtm, "sorted fused_train dtable")
+    _assert_close(dp.cpu().numpy(), dp_ref, dpm, "sorted fused_train dparams")
