@@ -1,0 +1,109 @@
+"""Continuous-batching server on the device: every result of a mixed stream
+(two resident models, one with FP16 tables; renders of uneven sizes and
+times; point-query batches) equals, bit for bit, the same request served
+alone through the plain entry points (fhash_render, fhash_fused_fwd)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2507_03836_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
+
+
+@pytest.fixture(scope="module")
+def server_models():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd.serving import GpuExecutor, ResidentModel
+    fl.lib()
+    f, mask = synth.tiny_volume()
+    T, Sz, Sy, Sx = mask.shape
+    dims = [Sx, Sy, Sz, T]
+    bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
+    idx, counts, dir_t, _ = fl.fhash_build_index(fl.grid_desc(TINY_RES, 2), bits, dims)
+    rows = int(idx.slot_offset[len(TINY_RES)])
+    width = [8, 32, 32, 1]
+    tf = torch.from_numpy(synth.transfer_function()).cuda()
+    models = {}
+    for k, (seed, dt) in enumerate([(11, torch.float32), (12, torch.float16)]):
+        rng = np.random.default_rng(seed)
+        table = torch.from_numpy(rng.uniform(-1, 1, (rows, 2)).astype(np.float32)).cuda()
+        params = synth.mlp_init(width, seed=seed)
+        params[-1] = 0.5
+        models[f"m{k}"] = ResidentModel(index=idx, mlp=fl.mlp_desc(width), table=table.to(dt),
+                                        params=torch.from_numpy(params).cuda(), mask_bits=bits,
+                                        dims=dims, tf=tf, keep=(dir_t,))
+    return fl, models, dims
+
+
+def _requests(dims, rng):
+    from paper_2507_03836_amd.serving import Request
+    reqs = []
+    sizes = [(40, 32), (17, 23), (64, 48), (8, 8), (33, 1)]
+    for j in range(14):
+        m = f"m{j % 2}"
+        if j % 3 != 2:
+            W, H = sizes[j % len(sizes)]
+            view = synth.orbit_view(dims, rng.uniform(0, 2 * np.pi), rng.uniform(-1, 1), W, H)
+            t = float(rng.uniform(0, dims[3] - 1)) if j != 4 else 0.0
+            reqs.append(Request(model=m, kind="render", view=view, t=t, W=W, H=H,
+                                arrival=j * 2e-4))
+        else:
+            n = [1, 1000, 4097, 0][j % 4]
+            pos = torch.from_numpy(rng.uniform(0, 1, (n, 4)).astype(np.float32)).cuda()
+            reqs.append(Request(model=m, kind="points", pos=pos, n=n, arrival=j * 2e-4))
+    return reqs
+
+
+@pytest.mark.parametrize("budget,max_active", [(1 << 14, 64), (6000, 2)])
+def test_mixed_stream_equals_alone(server_models, budget, max_active):
+    fl, models, dims = server_models
+    from paper_2507_03836_amd.serving import GpuExecutor, Scheduler
+    ex = GpuExecutor(sample_budget=budget)
+    for k, m in models.items():
+        ex.add_model(k, m)
+    sch = Scheduler(ex, sample_budget=budget, mem_budget=1 << 30, max_active=max_active)
+    reqs = _requests(dims, np.random.default_rng(budget))
+    done = sch.run(reqs, realtime=True)
+    assert len(done) == len(reqs)
+    assert sch.peak_active <= max_active
+    opts = fl.render_opts()
+    for r in reqs:
+        m = models[r.model]
+        if r.kind == "render":
+            alone = torch.empty(r.H, r.W, 4, device="cuda")
+            fl.fhash_render(m.index, m.mlp, m.table, m.params, m.mask_bits, dims,
+                            fl.view_struct(r.view), r.t, m.tf, r.W, r.H, opts, alone)
+            assert torch.equal(alone, r.result), (r.rid, r.W, r.H, r.t)
+        else:
+            alone = torch.empty(r.n, device="cuda")
+            if r.n:
+                fl.fhash_fused_fwd(m.index, m.mlp, r.pos, r.n, m.table, m.params, alone)
+            assert torch.equal(alone, r.result), (r.rid, r.n)
+    assert any(float(r.result[..., 3].max()) > 0.3 for r in reqs if r.kind == "render")
+
+
+def test_served_render_matches_oracle(server_models):
+    """One served render of the FP32 model against the oracle's renderer."""
+    fl, models, dims = server_models
+    from paper_2507_03836_amd.serving import GpuExecutor, Request, Scheduler
+    m = models["m0"]
+    ex = GpuExecutor(sample_budget=1 << 13)
+    ex.add_model("m0", m)
+    sch = Scheduler(ex, sample_budget=1 << 13)
+    W, H, t = 36, 28, 2.75
+    view = synth.orbit_view(dims, 0.9, 0.35, W, H)
+    r = Request(model="m0", kind="render", view=view, t=t, W=W, H=H)
+    sch.run([r], realtime=False)
+    f, mask = synth.tiny_volume()
+    g = O.Grid(np.array(TINY_RES), 2, mask)
+    ref, amb, _ = O.render(g, m.table.cpu().numpy().astype(np.float64), [8, 32, 32, 1],
+                           m.params.cpu().numpy().astype(np.float64), mask, view, t,
+                           synth.transfer_function(), W, H)
+    err = np.abs(r.result.cpu().numpy() - ref)[~amb]
+    assert err.max() < 2e-4, float(err.max())
