@@ -48,6 +48,21 @@ def parse():
     ap.add_argument("--levels", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=1 << 12)
+    ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32",
+                    help="mixed: FP16 table reads (Adam-written shadow) + dynamic loss scaling")
+    ap.add_argument("--hidden-layers", type=int, default=2)
+    ap.add_argument("--field-seed", type=int, default=1002)
+    ap.add_argument("--sampler-seed", type=int, default=2002)
+    ap.add_argument("--psnr-target", type=float, default=0.0,
+                    help="after the timed steps, keep training until the probe PSNR reaches this")
+    ap.add_argument("--max-steps", type=int, default=2000)
+    ap.add_argument("--eval-every", type=int, default=100)
+    ap.add_argument("--serve", action="store_true",
+                    help="render-serving benchmark instead of training (p50/p99 at 3 rates)")
+    ap.add_argument("--serve-shape", type=str, default="432,432,432,60")
+    ap.add_argument("--serve-train-steps", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-sizes", type=str, default="256,512,1024")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 4 GiB device copy first (counter calibration)")
     return ap.parse_args()
@@ -101,6 +116,157 @@ def cpu_baseline(model, gen, dims, batch, n_cpu, seed):
                        "dense-box index, FP64, single thread")}
 
 
+def time_to_psnr(args, model, step, gen, dims, t_train0):
+    """Keep training after the timed steps until the probe PSNR reaches the
+    target (or max steps).  Probe: 2^22 coreset draws (sampler seed + 2000).
+    Wall time counts every training step since the first warm-up step plus
+    the probe evaluations."""
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd.model import psnr_on
+    P = 1 << 22
+    ppos = torch.empty(P, 4, device="cuda")
+    ptgt = torch.empty(P, device="cuda")
+    fl.fhash_sample(args.sampler_seed + 2000, 1, P, gen["coreset"], gen["M"], dims,
+                    gen["field"], ppos, ptgt)
+    k = args.warmup + args.steps
+    hist = []
+    reached = None
+    while True:
+        if k % args.eval_every == 0 or k >= args.max_steps:
+            ps = psnr_on(model, ppos, ptgt)
+            el = time.perf_counter() - t_train0
+            hist.append((k, round(el, 3), round(ps, 3)))
+            log(f"[bench] step {k}: probe PSNR {ps:.3f} dB at {el:.1f} s")
+            if ps >= args.psnr_target:
+                reached = (k, el, ps)
+                break
+            if k >= args.max_steps:
+                break
+        k += 1
+        step(k)
+    return {"target_db": args.psnr_target, "reached": reached is not None,
+            "steps": reached[0] if reached else None,
+            "seconds": reached[1] if reached else None,
+            "final_psnr_db": hist[-1][2], "history": hist,
+            "probe": "2^22 coreset draws, PSNR over data range 1, FP64 sum on the device"}
+
+
+def serve_bench(args):
+    """Render serving: a trained model (432^3 x 60 volume, 16 levels, MLP
+    32-64-64-64-1, FP16 tables) answers ray-march requests of sizes uniform
+    over {256^2, 512^2, 1024^2}, t ~ U[0, T-1] (fractional), orbit cameras
+    (azimuth U[0, 2pi), elevation U[-60, 60] deg, distance 2x the half
+    diagonal, fovy 45 deg), ds = 1/2 voxel, alpha stop 0.99, ARM max 64.
+
+    Saturation: every request submitted at once, continuous batching.  Then
+    Poisson arrivals at 0.25 / 0.5 / 0.9 x the saturation request rate, served
+    by continuous batching and by a one-request-at-a-time server (same
+    arrivals).  ARM off (pace 1) is timed at saturation too."""
+    import numpy as np
+
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd import synth
+    from paper_2507_03836_amd.model import FHashConfig, FHashModel, geometric_resolutions, psnr_on
+    from paper_2507_03836_amd.serving import (GpuExecutor, Request, ResidentModel, Scheduler,
+                                              latency_stats, poisson_arrivals)
+
+    fl.lib()
+    torch.cuda.set_device(0)
+    dims = [int(x) for x in args.serve_shape.split(",")]
+    t0 = time.time()
+    gen = synth.production_volume_gpu(dims, seed=1003)
+    log(f"[serve] volume {dims} in {time.time() - t0:.1f} s; coreset {gen['M']}")
+    res = geometric_resolutions(16, 16, 512, 4, dims[3], dims)
+    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3)
+    model = FHashModel(cfg, gen["bits"], dims, init_seed=3003)
+    log(f"[serve] model: {model.rows} active vertices, {model.n_params} params")
+    B = 1 << 20
+    pos = torch.empty(B, 4, device="cuda")
+    tgt = torch.empty(B, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for k in range(args.serve_train_steps):
+        fl.fhash_sample(2003, k + 1, B, gen["coreset"], gen["M"], dims, gen["field"], pos, tgt)
+        model.fwd_bwd(pos, tgt)
+        model.optimizer_step()
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    probe = 1 << 22
+    ppos = torch.empty(probe, 4, device="cuda")
+    ptgt = torch.empty(probe, device="cuda")
+    fl.fhash_sample(4003, 1, probe, gen["coreset"], gen["M"], dims, gen["field"], ppos, ptgt)
+    psnr = psnr_on(model, ppos, ptgt)
+    log(f"[serve] trained {args.serve_train_steps} steps in {t_train:.1f} s; probe PSNR {psnr:.2f} dB")
+    table16 = torch.empty(model.n_table, dtype=torch.float16, device="cuda")
+    fl.fhash_cast(model.table, table16)
+    params = model.mlp_params.clone()
+    bits = gen["bits"]
+    del gen, pos, tgt, ppos, ptgt
+    model.params = model.grads = model.m = model.v = None
+    torch.cuda.empty_cache()
+    tf = torch.from_numpy(synth.transfer_function()).cuda()
+    rm = ResidentModel(index=model.index, mlp=model.mlp, table=table16, params=params,
+                       mask_bits=bits, dims=dims, tf=tf, keep=(model._dir,))
+    C = 1 << 22
+    sizes = [int(x) for x in args.serve_sizes.split(",")]
+    rng = np.random.default_rng(5004)
+    spec = []
+    for i in range(args.serve_requests):
+        S = int(rng.choice(sizes))
+        az = float(rng.uniform(0, 2 * np.pi))
+        el = float(rng.uniform(-np.pi / 3, np.pi / 3))
+        t = float(rng.uniform(0, dims[3] - 1))
+        spec.append((S, synth.orbit_view(dims, az, el, S, S), t))
+
+    def requests(arr):
+        return [Request(model="m", kind="render", view=v, t=t, W=S, H=S, arrival=float(a))
+                for (S, v, t), a in zip(spec, arr)]
+
+    def serve(reqs, realtime, max_active=64, arm_max=64, policy="oldest_first"):
+        ex = GpuExecutor(sample_budget=C, arm_max=arm_max)
+        ex.add_model("m", rm)
+        free, _ = torch.cuda.mem_get_info()
+        sch = Scheduler(ex, sample_budget=C, mem_budget=int(free * 0.8), max_active=max_active,
+                        arm_max=arm_max, policy=policy)
+        torch.cuda.synchronize()
+        done = sch.run(reqs, realtime=realtime)
+        st = latency_stats(done)
+        st["iterations"] = sch.iterations
+        st["samples"] = sch.samples
+        st["peak_active"] = sch.peak_active
+        return st
+
+    serve(requests([0.0] * 2), realtime=False)  # warm-up
+    sat = serve(requests([0.0] * len(spec)), realtime=False)
+    log(f"[serve] saturation: {sat}")
+    rate_sat = sat["requests_per_s"]
+    arm_off = serve(requests([0.0] * len(spec)), realtime=False, arm_max=1)
+    log(f"[serve] ARM off: {arm_off}")
+    rates = []
+    for frac in (0.25, 0.5, 0.9):
+        rate = frac * rate_sat
+        arr = poisson_arrivals(rate, len(spec), seed=5004)
+        cb = serve(requests(arr), realtime=True)
+        sh = serve(requests(arr), realtime=True, policy="shared")
+        one = serve(requests(arr), realtime=True, max_active=1)
+        log(f"[serve] rate {rate:.3f}/s: oldest-first {cb}; shared pace {sh}; one-at-a-time {one}")
+        rates.append({"rate_frac": frac, "rate_per_s": rate, "continuous": cb,
+                      "continuous_shared_pace": sh, "one_at_a_time": one})
+    out = {
+        "metric": "render p50/p99 ms at 0.25/0.5/0.9 x saturation (Poisson), rays/s at saturation",
+        "value": sat["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f16 tables, f32 MLP",
+        "data": "synthetic",
+        "config": {"workload": f"render serving, {'x'.join(map(str, dims))} volume, 16 levels, "
+                   "MLP 32-64-64-64-1, images {" + ",".join(f"{x}^2" for x in sizes) + "}",
+                   "requests_per_rate": len(spec), "sample_budget": C,
+                   "train_steps": args.serve_train_steps, "probe_psnr_db": psnr,
+                   "params": model.n_params},
+        "saturation": sat, "arm_off_saturation": arm_off, "rates": rates,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -111,6 +277,9 @@ def main():
     import numpy as np
     import torch
 
+    if args.serve:
+        return serve_bench(args)
+
     from paper_2507_03836_amd import _lib as fl
     from paper_2507_03836_amd import synth
     from paper_2507_03836_amd.model import FHashConfig, FHashModel, geometric_resolutions
@@ -119,13 +288,14 @@ def main():
     torch.cuda.set_device(0)
     dims = [int(x) for x in args.shape.split(",")]
     t0 = time.time()
-    gen = synth.production_volume_gpu(dims, seed=1002)
+    gen = synth.production_volume_gpu(dims, seed=args.field_seed)
     log(f"[bench] volume {dims} generated in {time.time() - t0:.1f} s; coreset {gen['M']} "
         f"of {gen['N']} voxels ({gen['M'] / gen['N']:.3f}), threshold {gen['threshold']:.4g}")
-    res = geometric_resolutions(args.levels, 16, 512, 4, 100, dims)
-    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=2)
+    res = geometric_resolutions(args.levels, 16, 512, 4, dims[3], dims)
+    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers)
     t0 = time.time()
-    model = FHashModel(cfg, gen["bits"], dims)
+    model = FHashModel(cfg, gen["bits"], dims, init_seed=3000 + args.field_seed - 1000,
+                       precision=args.precision)
     torch.cuda.synchronize()
     dense = sum(int(np.prod(r)) for r in res)
     log(f"[bench] index built in {time.time() - t0:.1f} s: {model.rows} active vertices of "
@@ -145,7 +315,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(k, ev=None):
-        fl.fhash_sample(2002, k, B, coreset, M, dims, field, pos, tgt)
+        fl.fhash_sample(args.sampler_seed, k, B, coreset, M, dims, field, pos, tgt)
         if ev is not None:
             ev[0].record(stream)
         model.fwd_bwd(pos, tgt)
@@ -155,6 +325,7 @@ def main():
         if ev is not None:
             ev[2].record(stream)
 
+    t_train0 = time.perf_counter()
     for k in range(args.warmup):
         step(k + 1)
     torch.cuda.synchronize()
@@ -169,17 +340,20 @@ def main():
     adam_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     loss = model.loss_sum.item() / (B * (args.warmup + args.steps))
     ms = wall * 1e3 / args.steps
-    adam_bytes = ADAM_BYTES_PER_PARAM * model.n_params
+    mixed = args.precision == "mixed"
+    adam_bytes = (ADAM_BYTES_PER_PARAM + (2 if mixed else 0)) * model.n_params
     achieved = adam_bytes / (adam_ms * 1e-3) / 1e9
     import hashlib
     src = os.path.join(ROOT, "paper_2507_03836_amd", "csrc", "optim.hip")
     same_src = hashlib.md5(open(src, "rb").read()).hexdigest() == ADAM_TRAFFIC["source_md5"]
-    traffic = ADAM_TRAFFIC["bytes"] if same_src and model.n_params == ADAM_TRAFFIC["params"] \
-        else None
+    traffic = ADAM_TRAFFIC["bytes"] if (same_src and not mixed and
+                                        model.n_params == ADAM_TRAFFIC["params"]) else None
     log(f"[bench] step {ms:.3f} ms: fused fwd+bwd {fb_ms:.3f} ms, adam {adam_ms:.3f} ms; "
         f"mean loss {loss:.4g}")
     out = {
-        "metric": "train samples/s fwd+bwd (FP32 path), whole training step incl. dense Adam",
+        "metric": ("train samples/s fwd+bwd (" + ("FP16 table reads, FP32 master"
+                                                  if mixed else "FP32 path")
+                   + "), whole training step incl. dense Adam"),
         "value": B / (ms * 1e-3),
         "unit": "samples/s",
         "n_gpus": 1,
@@ -189,10 +363,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16 table reads, f32 math" if mixed else "f32",
         "data": "synthetic",
-        "config": {"workload": "F-Hash training, 480x720x120x100 synthetic volume, 16 levels "
-                   "x 2 features, MLP 32-64-64-1, batch 2^18 coreset draws",
+        "config": {"workload": (f"F-Hash training, {'x'.join(map(str, dims))} synthetic volume, "
+                                f"{args.levels} levels x 2 features, MLP "
+                                + "-".join(map(str, cfg.width))
+                                + f", batch 2^{int(np.log2(B))} coreset draws"),
                    "shape": dims, "levels": args.levels, "batch": B,
                    "active_vertices": model.rows, "params": model.n_params,
                    "coreset": M},
@@ -202,6 +378,11 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": adam_bytes},
     }
+    if mixed:
+        out["loss_scale"] = model.loss_scale
+        out["skipped_steps"] = model.skipped
+    if args.psnr_target > 0:
+        out["time_to_psnr"] = time_to_psnr(args, model, step, gen, dims, t_train0)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(model, gen, dims, B, args.cpu_samples, 2002)

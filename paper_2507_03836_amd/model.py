@@ -9,6 +9,14 @@ the C-ABI calls of one training step:
 Parameter memory is one flat FP32 vector per quantity (parameters, gradients,
 Adam m and v): the embedding tables (rows x F, level after level) followed by
 the packed MLP parameters, so one dense Adam launch covers every parameter.
+
+Mixed precision (precision="mixed"): the fused kernels read an FP16 copy of
+the tables that the Adam sweep rewrites from the FP32 master values (the
+shadow); gradients, Adam moments and the decoder stay FP32.  The loss is
+scaled by a dynamic factor (start 2^16, doubled after `scale_window` clean
+steps, halved with the step skipped when a decoder gradient is not finite:
+the output-bias gradient is the sum of every sample's output gradient, so a
+non-finite sample gradient shows up there).
 """
 from __future__ import annotations
 
@@ -59,8 +67,12 @@ class FHashModel:
 
     def __init__(self, cfg: FHashConfig, mask_bits: torch.Tensor | None, dims, device="cuda",
                  table_init: torch.Tensor | None = None, mlp_init: torch.Tensor | None = None,
-                 init_seed: int = 3000):
+                 init_seed: int = 3000, precision: str = "fp32", loss_scale: float = 2.0 ** 16,
+                 scale_window: int = 2000):
+        if precision not in ("fp32", "mixed"):
+            raise ValueError(f"precision must be 'fp32' or 'mixed', not {precision!r}")
         self.cfg = cfg
+        self.precision = precision
         self.device = torch.device(device)
         self.grid = fl.grid_desc(cfg.res, cfg.n_features)
         self.mlp = fl.mlp_desc(cfg.width)
@@ -100,11 +112,26 @@ class FHashModel:
         self.step_count = 0
         self.loss_sum = torch.zeros(1, dtype=torch.float64, device=self.device)
         self._ws = None
+        self.shadow = None
+        self.loss_scale = 1.0
+        if precision == "mixed":
+            self.shadow = torch.empty(n_alloc, dtype=torch.float16, device=self.device)
+            fl.fhash_cast(self.params, self.shadow)
+            self.found_inf = torch.zeros(1, dtype=torch.int32, device=self.device)
+            self.loss_scale = float(loss_scale)
+            self.scale_window = int(scale_window)
+            self._clean = 0
+            self.skipped = 0
 
     # views into the flat vectors
     @property
     def table(self) -> torch.Tensor:
         return self.params[: self.n_table]
+
+    @property
+    def read_table(self) -> torch.Tensor:
+        """The table the fused kernels read: the FP16 shadow or the FP32 master."""
+        return self.shadow[: self.n_table] if self.shadow is not None else self.table
 
     @property
     def mlp_params(self) -> torch.Tensor:
@@ -130,23 +157,47 @@ class FHashModel:
         n = pos.shape[0]
         if y is None:
             y = torch.empty(n, dtype=torch.float32, device=self.device)
-        fl.fhash_fused_fwd(self.index, self.mlp, pos, n, self.table, self.mlp_params, y)
+        fl.fhash_fused_fwd(self.index, self.mlp, pos, n, self.read_table, self.mlp_params, y)
         return y
 
-    def fwd_bwd(self, pos: torch.Tensor, target: torch.Tensor, loss_scale: float = 1.0,
+    def fwd_bwd(self, pos: torch.Tensor, target: torch.Tensor, loss_scale: float | None = None,
                 sorted_batch: bool = False):
-        """Fused forward + MSE + backward; gradients accumulate into self.grads."""
+        """Fused forward + MSE + backward; gradients accumulate into self.grads
+        (multiplied by the loss scale; the model's own scale when None)."""
         n = pos.shape[0]
-        self._ws = fl.fhash_fused_train(self.index, self.mlp, pos, target, n, self.table,
+        s = self.loss_scale if loss_scale is None else loss_scale
+        self._ws = fl.fhash_fused_train(self.index, self.mlp, pos, target, n, self.read_table,
                                         self.mlp_params, self.d_table, self.d_mlp,
-                                        self.loss_sum, loss_scale, ws=self._ws,
+                                        self.loss_sum, s, ws=self._ws,
                                         flags=fl.SAMPLES_SORTED if sorted_batch else 0)
 
-    def optimizer_step(self, grad_scale: float = 1.0, found_inf=None):
+    def optimizer_step(self, grad_scale: float | None = None, found_inf=None) -> bool:
+        """Dense Adam over every parameter; gradients are reset.  The mixed path
+        unscales, skips the update on a non-finite gradient and adapts the
+        loss scale.  Returns whether the parameters were updated."""
+        if self.shadow is None:
+            self.step_count += 1
+            fl.fhash_step(self.adam_desc(self.step_count, 1.0 if grad_scale is None else grad_scale),
+                          self.params[: self.n_params], self.grads[: self.n_params],
+                          self.m[: self.n_params], self.v[: self.n_params], found_inf=found_inf)
+            return True
+        self.found_inf.zero_()
+        fl.fhash_check_finite(self.d_mlp, self.found_inf)
+        opt = self.adam_desc(self.step_count + 1, 1.0 / self.loss_scale)
+        fl.fhash_step(opt, self.params[: self.n_params], self.grads[: self.n_params],
+                      self.m[: self.n_params], self.v[: self.n_params],
+                      shadow=self.shadow[: self.n_params], found_inf=self.found_inf)
+        if int(self.found_inf.item()):
+            self.loss_scale *= 0.5
+            self._clean = 0
+            self.skipped += 1
+            return False
         self.step_count += 1
-        fl.fhash_step(self.adam_desc(self.step_count, grad_scale), self.params[: self.n_params],
-                      self.grads[: self.n_params], self.m[: self.n_params],
-                      self.v[: self.n_params], found_inf=found_inf)
+        self._clean += 1
+        if self._clean >= self.scale_window:
+            self.loss_scale *= 2.0
+            self._clean = 0
+        return True
 
     def train_step(self, pos: torch.Tensor, target: torch.Tensor):
         self.fwd_bwd(pos, target)

@@ -1,8 +1,9 @@
 """Continuous-batching request server for trained F-Hash models.
 
 Rendering a trained representation is ray marching whose samples are decoded
-by the encoding + MLP (Sec. 4.3), with the adaptive pace of Sec. 4.3 (ARM):
-every iteration a sample budget is divided over the rays still alive.  This
+by the encoding + MLP, with the adaptive marching pace of Sec. 3.3 (ARM,
+Algorithm 1): every iteration a sample budget is divided over the rays still
+alive.  This
 module serves many such renders, and batches of point queries (x, y, z, t),
 against models that stay resident on the device:
 
@@ -11,10 +12,15 @@ against models that stay resident on the device:
   state + image, or query outputs) fits the memory budget next to the
   resident models; it then joins the running batch at the next iteration, so
   work of requests that arrived at different times overlaps on the device;
-* one iteration marches every admitted render request with one shared ARM
-  pace (the budget over all alive rays of all requests), appends a chunk of
+* one iteration marches every admitted render request, appends a chunk of
   pending point queries, and decodes all samples of one model with a single
-  fused encode + MLP launch; then every render composites its own samples;
+  fused encode + MLP launch; then every render composites its own samples.
+  The iteration's sample budget is handed out oldest request first: each
+  render takes the ARM pace that the budget left after it (one sample per
+  alive ray of every younger render stays reserved) allows, so the oldest
+  request advances at full pace and younger ones still make progress
+  ("shared" instead gives every render the pace of the budget over all alive
+  rays);
 * a request leaves the batch when its last ray terminates or its last point
   is decoded, and its latency (arrival to completion) is recorded.
 
@@ -36,7 +42,7 @@ from collections import deque
 import numpy as np
 
 
-@dataclasses.dataclass
+@dataclasses.dataclass(eq=False)   # requests compare by identity
 class Request:
     """A render request (view, t, W, H) or a point-query request (pos)."""
     model: str
@@ -81,12 +87,16 @@ class Scheduler:
                    >= 1 always fits and point queries always get a share
     mem_budget     device bytes available to requests (after resident models)
     max_active     request slots
+    policy         "oldest_first" or "shared" division of the sample budget
     """
 
     def __init__(self, executor, sample_budget: int = 1 << 22, mem_budget: int = 1 << 36,
-                 max_active: int = 64, arm_max: int = 64):
+                 max_active: int = 64, arm_max: int = 64, policy: str = "oldest_first"):
         if sample_budget < 2:
             raise ValueError("sample budget must be at least 2")
+        if policy not in ("oldest_first", "shared"):
+            raise ValueError(f"unknown policy {policy!r}")
+        self.policy = policy
         self.ex = executor
         self.C = int(sample_budget)
         self.mem_budget = int(mem_budget)
@@ -158,12 +168,23 @@ class Scheduler:
         self.finished.append(r)
 
     # ------------------------------------------------------------- iteration
-    def pace(self) -> int:
-        """ARM pace shared by all admitted renders this iteration."""
-        alive = sum(r.alive for r in self.active if r.kind == "render")
+    def paces(self) -> list[int]:
+        """ARM pace of every admitted render (admission order) this iteration."""
+        renders = [r for r in self.active if r.kind == "render"]
         pending = sum(r.n - r.done for r in self.active if r.kind == "points")
         budget = self.C - min(pending, self.C // 2)
-        return self.ex.pace(budget, alive, self.arm_max)
+        alive = sum(r.alive for r in renders)
+        if self.policy == "shared":
+            p = self.ex.pace(budget, alive, self.arm_max)
+            return [p] * len(renders)
+        out = []
+        reserve = alive
+        for r in renders:
+            reserve -= r.alive
+            p = self.ex.pace(budget - reserve, r.alive, self.arm_max)
+            out.append(p)
+            budget -= p * r.alive
+        return out
 
     def step(self) -> int:
         """One iteration over the running batch; returns samples decoded."""
@@ -172,10 +193,11 @@ class Scheduler:
             return 0
         renders = [r for r in self.active if r.kind == "render"]
         points = [r for r in self.active if r.kind == "points"]
-        alive = sum(r.alive for r in renders)
-        pace = self.pace()
-        assert pace * alive <= self.C
-        pt_budget = self.C - pace * alive
+        paces = self.paces()
+        used = sum(p * r.alive for p, r in zip(paces, renders))
+        assert used <= self.C
+        pt_budget = self.C - used
+        pace_of = {id(r): p for p, r in zip(paces, renders)}
         models = list(dict.fromkeys(r.model for r in self.active))
         off = 0
         for m in models:
@@ -184,7 +206,7 @@ class Scheduler:
                 if r.model != m:
                     continue
                 r.y_off = off
-                ns = self.ex.march(r, pace, off, self.C - off)
+                ns = self.ex.march(r, pace_of[id(r)], off, self.C - off)
                 r.samples += ns
                 off += ns
             for r in points:

@@ -1,0 +1,165 @@
+"""Mixed-precision training path: FP16 table reads (the shadow the Adam sweep
+writes), FP32 master tables, moments and decoder, dynamic loss scaling.
+
+- with the FP16-rounded table as the oracle's table, the scaled gradients and
+  the first Adam step meet the FP32 path's tolerance, and the shadow is the
+  round-to-nearest-even FP16 of the updated master values, bit for bit;
+- a non-finite gradient skips the update (parameters, moments and step count
+  unchanged), resets the gradients and halves the scale;
+- against the FP64 oracle on the FP32 tables (2^14 probe points) the encoding
+  error stays inside the FP16 rounding bound 2^-11 * sum|w E| and the decoder
+  output error inside that bound pushed through |W| of every layer.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2507_03836_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
+RTOL, ATOL = 1e-5, 1e-12
+U16 = 2.0 ** -11  # unit roundoff of binary16 round-to-nearest
+
+
+@pytest.fixture(scope="module")
+def fl():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2507_03836_amd import _lib as fl
+    fl.lib()
+    return fl
+
+
+def _dims(mask):
+    T, Sz, Sy, Sx = mask.shape
+    return [Sx, Sy, Sz, T]
+
+
+def _model(mask, table0, mlp0, precision, **kw):
+    from paper_2507_03836_amd.model import FHashConfig, FHashModel
+    cfg = FHashConfig(res=TINY_RES, n_features=2, hidden=32, n_hidden=2)
+    bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
+    return cfg, FHashModel(cfg, bits, _dims(mask), table_init=torch.from_numpy(table0),
+                           mlp_init=torch.from_numpy(mlp0), precision=precision, **kw)
+
+
+def _close(got, ref, mag, what, scale=1.0):
+    err = np.abs(np.asarray(got, np.float64) - scale * ref)
+    tol = scale * (RTOL * mag) + ATOL
+    assert (err <= tol).all(), (what, float((err - tol).max()))
+
+
+def test_mixed_step_matches_oracle_on_fp16_values(fl):
+    f, mask = synth.tiny_volume()
+    g = O.Grid(np.array(TINY_RES), 2, mask)
+    rng = np.random.default_rng(21)
+    table0 = rng.uniform(-0.5, 0.5, (g.total_slots, 2)).astype(np.float32)
+    mlp0 = synth.mlp_init([8, 32, 32, 1], seed=22)
+    S = 2.0 ** 16
+    cfg, model = _model(mask, table0, mlp0, "mixed", loss_scale=S)
+    t16 = table0.astype(np.float16)
+    assert np.array_equal(model.shadow[: model.n_table].cpu().numpy(), t16.ravel())
+    n = 4096
+    pos = torch.empty(n, 4, device="cuda")
+    tgt = torch.empty(n, device="cuda")
+    fl.fhash_sample(2001, 1, n, None, f.size, _dims(mask), torch.from_numpy(f).cuda(), pos, tgt)
+    model.fwd_bwd(pos, tgt)
+    pos_r, tgt_r = O.sample_batch(2001, 1, n, f)
+    tab = t16.astype(np.float64)
+    enc, emag = O.encode_fwd(g, pos_r, tab)
+    y, acts, ymag = O.mlp_fwd(cfg.width, mlp0.astype(np.float64), enc, x_mag=emag)
+    L, dy = O.mse(y[:, 0], tgt_r.astype(np.float64))
+    dym = 2.0 * (ymag[:, 0] + np.abs(tgt_r)) / n
+    dp, denc, dpm, dencm = O.mlp_bwd(cfg.width, mlp0.astype(np.float64), acts, dy.reshape(-1, 1),
+                                     n, dy_mag=dym.reshape(-1, 1), x_mag=emag)
+    dt, _ = O.encode_bwd(g, pos_r, denc)
+    _, dtm = O.encode_bwd(g, pos_r, dencm)
+    _close(model.d_table.cpu().numpy(), dt.ravel(), dtm.ravel(), "scaled d_table", S)
+    _close(model.d_mlp.cpu().numpy(), dp, dpm, "scaled d_mlp", S)
+    assert abs(model.loss_sum.item() - L * n) <= 1e-4 * L * n
+    g_tab = model.d_table.cpu().numpy().astype(np.float64) / S
+    assert model.optimizer_step()
+    assert model.step_count == 1 and (model.grads == 0).all()
+    # first Adam step: update = -lr * g / (|g| + eps) on the unscaled gradient
+    # (the unscale by 2^-16 is exact)
+    p1 = model.table.cpu().numpy().astype(np.float64)
+    exp = table0.ravel().astype(np.float64) - cfg.lr * g_tab / (np.abs(g_tab) + cfg.eps)
+    assert np.abs(p1 - exp).max() <= 2.4e-7 * (np.abs(table0).max() + cfg.lr) + 1e-12
+    sh = model.shadow[: model.n_params].cpu()
+    assert torch.equal(sh, model.params[: model.n_params].cpu().to(torch.float16))
+
+
+def test_overflow_skips_step_and_halves_scale(fl):
+    f, mask = synth.tiny_volume()
+    g = O.Grid(np.array(TINY_RES), 2, mask)
+    table0 = synth.table_init(g.total_slots, 2)
+    mlp0 = synth.mlp_init([8, 32, 32, 1], seed=23)
+    _, a = _model(mask, table0, mlp0, "mixed", loss_scale=float("inf"))
+    _, b = _model(mask, table0, mlp0, "mixed", loss_scale=2.0 ** 10)
+    n = 2048
+    pos = torch.empty(n, 4, device="cuda")
+    tgt = torch.empty(n, device="cuda")
+    fl.fhash_sample(2001, 3, n, None, f.size, _dims(mask), torch.from_numpy(f).cuda(), pos, tgt)
+    p0, m0, sh0 = a.params.clone(), a.m.clone(), a.shadow.clone()
+    a.fwd_bwd(pos, tgt)
+    assert not a.optimizer_step()
+    assert a.skipped == 1 and a.step_count == 0 and a.loss_scale == float("inf")
+    assert torch.equal(a.params, p0) and torch.equal(a.m, m0) and torch.equal(a.shadow, sh0)
+    assert (a.grads == 0).all()
+    # after the skip the model steps like one that never overflowed (up to the
+    # summation order of the table gradient's atomics)
+    a.loss_scale = 2.0 ** 10
+    for mdl in (a, b):
+        mdl.fwd_bwd(pos, tgt)
+        assert mdl.optimizer_step()
+    assert a.step_count == b.step_count == 1
+    for x, y in ((a.params, b.params), (a.m, b.m), (a.v, b.v)):
+        assert torch.allclose(x, y, rtol=1e-5, atol=1e-7)
+    assert torch.equal(a.params.half(), a.shadow) and torch.equal(b.params.half(), b.shadow)
+    # scale growth after a clean window
+    _, c = _model(mask, table0, mlp0, "mixed", loss_scale=4.0, scale_window=2)
+    for _ in range(2):
+        c.fwd_bwd(pos, tgt)
+        c.optimizer_step()
+    assert c.loss_scale == 8.0
+
+
+def test_mixed_error_against_fp64_probe(fl):
+    f, mask = synth.tiny_volume()
+    g = O.Grid(np.array(TINY_RES), 2, mask)
+    rng = np.random.default_rng(31)
+    table0 = rng.uniform(-1, 1, (g.total_slots, 2)).astype(np.float32)
+    width = [8, 32, 32, 1]
+    mlp0 = synth.mlp_init(width, seed=32)
+    _, mixed = _model(mask, table0, mlp0, "mixed")
+    _, full = _model(mask, table0, mlp0, "fp32")
+    n = 1 << 14
+    pos = synth.probe_points(n, 4003).astype(np.float32)
+    pd = torch.from_numpy(pos).cuda()
+    enc, emag = O.encode_fwd(g, pos, table0.astype(np.float64))
+    y64, _, ymag = O.mlp_fwd(width, mlp0.astype(np.float64), enc, x_mag=emag)
+    # encoding through the FP16 table
+    e16 = torch.empty(n, 8, device="cuda")
+    fl.fhash_encode_fwd(mixed.index, pd, n, mixed.read_table, e16)
+    err_e = np.abs(e16.cpu().numpy() - enc)
+    bound_e = U16 * emag + RTOL * emag + ATOL
+    assert (err_e <= bound_e).all(), float((err_e - bound_e).max())
+    # decoder output: the encoding bound through |W| of each layer (ReLU is 1-Lipschitz)
+    b = U16 * emag
+    off = 0
+    for k in range(len(width) - 1):
+        W = mlp0[off: off + width[k + 1] * width[k]].reshape(width[k + 1], width[k])
+        off += width[k + 1] * width[k] + width[k + 1]
+        b = b @ np.abs(W.astype(np.float64)).T
+    ym = mixed.forward(pd).cpu().numpy()
+    yf = full.forward(pd).cpu().numpy()
+    err_m = np.abs(ym - y64[:, 0])
+    err_f = np.abs(yf - y64[:, 0])
+    assert (err_f <= RTOL * ymag[:, 0] + ATOL).all()
+    assert (err_m <= b[:, 0] + RTOL * ymag[:, 0] + ATOL).all()
+    rel = float(np.abs(ym - y64[:, 0]).max() / np.abs(y64[:, 0]).max())
+    print(f"\nmixed vs FP64: enc max abs err {err_e.max():.3e}, y max abs err {err_m.max():.3e} "
+          f"(rel to max|y| {rel:.3e}); FP32 y max abs err {err_f.max():.3e}")

@@ -60,7 +60,7 @@ def _requests(dims, rng):
     return reqs
 
 
-@pytest.mark.parametrize("budget,max_active", [(1 << 14, 64), (6000, 2)])
+@pytest.mark.parametrize("budget,max_active", [(1 << 14, 64), (7000, 2)])
 def test_mixed_stream_equals_alone(server_models, budget, max_active):
     fl, models, dims = server_models
     from paper_2507_03836_amd.serving import GpuExecutor, Scheduler

@@ -212,20 +212,48 @@ def test_submit_validation():
         Scheduler(ex, sample_budget=1)
 
 
-def test_shared_pace_and_point_share():
+def test_pace_policies_and_point_share():
     ex = HostExecutor(100)
-    sch = Scheduler(ex, sample_budget=100, arm_max=64)
+    sch = Scheduler(ex, sample_budget=100, arm_max=64, policy="shared")
     a = sch.submit(Request(model="m0", kind="render", W=5, H=2))
     b = sch.submit(Request(model="m1", kind="render", W=4, H=2))
     sch._admit()
     alive = a.alive + b.alive
-    assert sch.pace() == min(64, 100 // alive)
+    assert sch.paces() == [min(64, 100 // alive)] * 2
+    sch.policy = "oldest_first"
+    pa = min(64, (100 - b.alive) // a.alive)
+    pb = min(64, max(1, (100 - pa * a.alive) // b.alive))
+    assert sch.paces() == [pa, pb]
     # pending points take up to half of the budget away from the renders
     p = sch.submit(Request(model="m0", kind="points", n=300, pos=np.zeros(300)))
     sch._admit()
-    assert sch.pace() == min(64, max(1, 50 // alive))
+    pa = min(64, (50 - b.alive) // a.alive)
+    pb = min(64, max(1, (50 - pa * a.alive) // b.alive))
+    assert sch.paces() == [pa, pb]
+    used = pa * a.alive + pb * b.alive
     sch.step()
-    assert p.done == 100 - sch.pace() * alive or p.done >= 50
+    assert p.done == 100 - used
+    with pytest.raises(ValueError):
+        Scheduler(ex, policy="lifo")
+
+
+@pytest.mark.parametrize("policy", ["oldest_first", "shared"])
+def test_oldest_first_never_starves_and_budget_holds(policy):
+    rng = np.random.default_rng(77)
+    reqs = _mixed_requests(rng, 25)
+    ex = HostExecutor(120)
+    sch = Scheduler(ex, sample_budget=120, arm_max=16, policy=policy)
+    real = ex.march
+
+    def march(r, pace, off, cap):
+        assert pace >= 1
+        return real(r, pace, off, cap)
+
+    ex.march = march
+    sch.run(reqs, realtime=True)
+    for r in reqs:
+        exp = _expected_render(r) if r.kind == "render" else _expected_points(r)
+        np.testing.assert_allclose(r.result, exp, rtol=0, atol=1e-12)
 
 
 def test_large_point_request_is_chunked():
@@ -249,3 +277,13 @@ def test_poisson_arrivals_and_stats():
     s = latency_stats(reqs)
     assert abs(s["p50_ms"] - 5.5) < 1e-9 and s["requests"] == 10
     assert abs(s["rays_per_s"] - 40 / 9.01) < 1e-9
+
+
+def test_requests_with_array_fields_retire_in_any_order():
+    # requests compare by identity, so array-valued fields never reach ==
+    ex = HostExecutor(400)
+    sch = Scheduler(ex, sample_budget=400)
+    reqs = [Request(model="m0", kind="render", W=9 - k, H=3, view=np.arange(14.0))
+            for k in range(5)]
+    sch.run(reqs, realtime=False)
+    assert len(sch.finished) == 5
