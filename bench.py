@@ -56,13 +56,15 @@ def parse():
     ap.add_argument("--psnr-target", type=float, default=0.0,
                     help="after the timed steps, keep training until the probe PSNR reaches this")
     ap.add_argument("--max-steps", type=int, default=2000)
-    ap.add_argument("--eval-every", type=int, default=100)
+    ap.add_argument("--eval-every", type=int, default=10)
     ap.add_argument("--serve", action="store_true",
                     help="render-serving benchmark instead of training (p50/p99 at 3 rates)")
     ap.add_argument("--serve-shape", type=str, default="432,432,432,60")
     ap.add_argument("--serve-train-steps", type=int, default=300)
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-sizes", type=str, default="256,512,1024")
+    ap.add_argument("--serve-rates", type=str, default="0.25,0.5,0.9",
+                    help="Poisson rates as fractions of the saturation request rate")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 4 GiB device copy first (counter calibration)")
     return ap.parse_args()
@@ -132,7 +134,7 @@ def time_to_psnr(args, model, step, gen, dims, t_train0):
     hist = []
     reached = None
     while True:
-        if k % args.eval_every == 0 or k >= args.max_steps:
+        if (k - args.warmup - args.steps) % args.eval_every == 0 or k >= args.max_steps:
             ps = psnr_on(model, ppos, ptgt)
             el = time.perf_counter() - t_train0
             hist.append((k, round(el, 3), round(ps, 3)))
@@ -242,16 +244,21 @@ def serve_bench(args):
     rate_sat = sat["requests_per_s"]
     arm_off = serve(requests([0.0] * len(spec)), realtime=False, arm_max=1)
     log(f"[serve] ARM off: {arm_off}")
+    sat_one = serve(requests([0.0] * len(spec)), realtime=False, max_active=1)
+    log(f"[serve] one at a time, all submitted at once: {sat_one}")
     rates = []
-    for frac in (0.25, 0.5, 0.9):
+    for frac in [float(x) for x in args.serve_rates.split(",") if x]:
         rate = frac * rate_sat
         arr = poisson_arrivals(rate, len(spec), seed=5004)
-        cb = serve(requests(arr), realtime=True)
-        sh = serve(requests(arr), realtime=True, policy="shared")
-        one = serve(requests(arr), realtime=True, max_active=1)
-        log(f"[serve] rate {rate:.3f}/s: oldest-first {cb}; shared pace {sh}; one-at-a-time {one}")
-        rates.append({"rate_frac": frac, "rate_per_s": rate, "continuous": cb,
-                      "continuous_shared_pace": sh, "one_at_a_time": one})
+        row = {"rate_frac": frac, "rate_per_s": rate}
+        for name, kw in (("continuous_oldest_first", {}),
+                         ("continuous_shared_pace", {"policy": "shared"}),
+                         ("continuous_backfill", {"policy": "backfill"}),
+                         ("one_at_a_time", {"max_active": 1})):
+            row[name] = serve(requests(arr), realtime=True, **kw)
+            log(f"[serve] rate {rate:.3f}/s {name}: p50 {row[name]['p50_ms']:.1f} ms, "
+                f"p99 {row[name]['p99_ms']:.1f} ms, {row[name]['rays_per_s'] / 1e6:.2f} Mrays/s")
+        rates.append(row)
     out = {
         "metric": "render p50/p99 ms at 0.25/0.5/0.9 x saturation (Poisson), rays/s at saturation",
         "value": sat["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
@@ -262,7 +269,8 @@ def serve_bench(args):
                    "requests_per_rate": len(spec), "sample_budget": C,
                    "train_steps": args.serve_train_steps, "probe_psnr_db": psnr,
                    "params": model.n_params},
-        "saturation": sat, "arm_off_saturation": arm_off, "rates": rates,
+        "saturation": sat, "arm_off_saturation": arm_off, "one_at_a_time_saturation": sat_one,
+        "rates": rates,
     }
     print(json.dumps(out), flush=True)
 

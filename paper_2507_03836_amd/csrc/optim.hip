@@ -59,7 +59,9 @@ __device__ __forceinline__ void store_shadow4(void* shadow, int sdt, int64_t i, 
     raw.x = (uint32_t)to_bf16_rne(pp[0]) | ((uint32_t)to_bf16_rne(pp[1]) << 16);
     raw.y = (uint32_t)to_bf16_rne(pp[2]) | ((uint32_t)to_bf16_rne(pp[3]) << 16);
   }
-  reinterpret_cast<uint2*>(shadow)[i] = raw;
+  // streamed like the other arrays: a non-temporal 8-byte store
+  const uint64_t word = (uint64_t)raw.x | ((uint64_t)raw.y << 32);
+  __builtin_nontemporal_store(word, reinterpret_cast<uint64_t*>(shadow) + i);
 }
 
 // Streaming sweep: every array is touched once, so loads and stores bypass the

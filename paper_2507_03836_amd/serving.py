@@ -20,7 +20,9 @@ against models that stay resident on the device:
   alive ray of every younger render stays reserved) allows, so the oldest
   request advances at full pace and younger ones still make progress
   ("shared" instead gives every render the pace of the budget over all alive
-  rays);
+  rays; "backfill" gives the oldest render the whole budget and younger ones
+  only what it leaves, so they wait for a turn when that is less than one
+  sample per alive ray);
 * a request leaves the batch when its last ray terminates or its last point
   is decoded, and its latency (arrival to completion) is recorded.
 
@@ -87,14 +89,14 @@ class Scheduler:
                    >= 1 always fits and point queries always get a share
     mem_budget     device bytes available to requests (after resident models)
     max_active     request slots
-    policy         "oldest_first" or "shared" division of the sample budget
+    policy         "oldest_first", "shared" or "backfill" division of the sample budget
     """
 
     def __init__(self, executor, sample_budget: int = 1 << 22, mem_budget: int = 1 << 36,
                  max_active: int = 64, arm_max: int = 64, policy: str = "oldest_first"):
         if sample_budget < 2:
             raise ValueError("sample budget must be at least 2")
-        if policy not in ("oldest_first", "shared"):
+        if policy not in ("oldest_first", "shared", "backfill"):
             raise ValueError(f"unknown policy {policy!r}")
         self.policy = policy
         self.ex = executor
@@ -178,6 +180,13 @@ class Scheduler:
             p = self.ex.pace(budget, alive, self.arm_max)
             return [p] * len(renders)
         out = []
+        if self.policy == "backfill":
+            for i, r in enumerate(renders):
+                p = 0 if (i > 0 and budget < r.alive) else self.ex.pace(budget, r.alive,
+                                                                         self.arm_max)
+                out.append(p)
+                budget -= p * r.alive
+            return out
         reserve = alive
         for r in renders:
             reserve -= r.alive
@@ -198,6 +207,7 @@ class Scheduler:
         assert used <= self.C
         pt_budget = self.C - used
         pace_of = {id(r): p for p, r in zip(paces, renders)}
+        renders = [r for r in renders if pace_of[id(r)] > 0]  # the others wait a turn
         models = list(dict.fromkeys(r.model for r in self.active))
         off = 0
         for m in models:

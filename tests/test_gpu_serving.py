@@ -60,14 +60,17 @@ def _requests(dims, rng):
     return reqs
 
 
-@pytest.mark.parametrize("budget,max_active", [(1 << 14, 64), (7000, 2)])
-def test_mixed_stream_equals_alone(server_models, budget, max_active):
+@pytest.mark.parametrize("budget,max_active,policy", [(1 << 14, 64, "oldest_first"),
+                                                      (7000, 2, "shared"),
+                                                      (1 << 13, 64, "backfill")])
+def test_mixed_stream_equals_alone(server_models, budget, max_active, policy):
     fl, models, dims = server_models
     from paper_2507_03836_amd.serving import GpuExecutor, Scheduler
     ex = GpuExecutor(sample_budget=budget)
     for k, m in models.items():
         ex.add_model(k, m)
-    sch = Scheduler(ex, sample_budget=budget, mem_budget=1 << 30, max_active=max_active)
+    sch = Scheduler(ex, sample_budget=budget, mem_budget=1 << 30, max_active=max_active,
+                    policy=policy)
     reqs = _requests(dims, np.random.default_rng(budget))
     done = sch.run(reqs, realtime=True)
     assert len(done) == len(reqs)

@@ -233,11 +233,17 @@ def test_pace_policies_and_point_share():
     used = pa * a.alive + pb * b.alive
     sch.step()
     assert p.done == 100 - used
+    # backfill: the oldest takes what it can use alone, younger ones the rest or wait
+    sch.policy = "backfill"
+    pa = min(64, 50 // a.alive)
+    left = 50 - pa * a.alive
+    pb = 0 if left < b.alive else min(64, left // b.alive)
+    assert sch.paces() == [pa, pb]
     with pytest.raises(ValueError):
         Scheduler(ex, policy="lifo")
 
 
-@pytest.mark.parametrize("policy", ["oldest_first", "shared"])
+@pytest.mark.parametrize("policy", ["oldest_first", "shared", "backfill"])
 def test_oldest_first_never_starves_and_budget_holds(policy):
     rng = np.random.default_rng(77)
     reqs = _mixed_requests(rng, 25)
