@@ -31,7 +31,7 @@ ADAM_BYTES_PER_PARAM = 28  # read p, g, m, v; write p, m, v (gradient reset not 
 # (x2.000) and WRITE_SIZE (x1.000) passes, scaled by a plain streaming copy of known size;
 # valid only for the parameter count and the optimizer source they were taken on.
 ADAM_TRAFFIC = {"bytes": 179.33e9, "params": 6390343593,
-                "source_md5": "24b6c98a519b406c345b253a42521331"}
+                "source_md5": "e4efccb9193df9835bcc3a2873f7e4bf"}
 
 
 def log(*a):
@@ -224,7 +224,7 @@ def serve_bench(args):
         return [Request(model="m", kind="render", view=v, t=t, W=S, H=S, arrival=float(a))
                 for (S, v, t), a in zip(spec, arr)]
 
-    def serve(reqs, realtime, max_active=64, arm_max=64, policy="oldest_first"):
+    def serve(reqs, realtime, max_active=64, arm_max=64, policy="backfill"):
         ex = GpuExecutor(sample_budget=C, arm_max=arm_max)
         ex.add_model("m", rm)
         free, _ = torch.cuda.mem_get_info()
@@ -251,14 +251,60 @@ def serve_bench(args):
         rate = frac * rate_sat
         arr = poisson_arrivals(rate, len(spec), seed=5004)
         row = {"rate_frac": frac, "rate_per_s": rate}
-        for name, kw in (("continuous_oldest_first", {}),
+        for name, kw in (("continuous_oldest_first", {"policy": "oldest_first"}),
                          ("continuous_shared_pace", {"policy": "shared"}),
-                         ("continuous_backfill", {"policy": "backfill"}),
+                         ("continuous_backfill", {}),
                          ("one_at_a_time", {"max_active": 1})):
             row[name] = serve(requests(arr), realtime=True, **kw)
             log(f"[serve] rate {rate:.3f}/s {name}: p50 {row[name]['p50_ms']:.1f} ms, "
                 f"p99 {row[name]['p99_ms']:.1f} ms, {row[name]['rays_per_s'] / 1e6:.2f} Mrays/s")
         rates.append(row)
+
+    # mixed stream: every 4th request a render, the others point-query batches of
+    # 2^k points, k ~ U{10..20}, positions U[0,1)^4
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5005)
+    krng = np.random.default_rng(5005)
+    pts = [torch.rand(1 << int(krng.integers(10, 21)), 4, device="cuda", generator=g)
+           for _ in range(3 * len(spec))]
+
+    def mixed(arr):
+        reqs, j = [], 0
+        for i, a in enumerate(arr):
+            if i % 4 == 0:
+                S, v, t = spec[(i // 4) % len(spec)]
+                reqs.append(Request(model="m", kind="render", view=v, t=t, W=S, H=S,
+                                    arrival=float(a)))
+            else:
+                reqs.append(Request(model="m", kind="points", pos=pts[j], n=pts[j].shape[0],
+                                    arrival=float(a)))
+                j += 1
+        return reqs
+
+    def serve_mixed(arr, realtime, **kw):
+        ex = GpuExecutor(sample_budget=C)
+        ex.add_model("m", rm)
+        free, _ = torch.cuda.mem_get_info()
+        sch = Scheduler(ex, sample_budget=C, mem_budget=int(free * 0.8), **kw)
+        torch.cuda.synchronize()
+        done = sch.run(mixed(arr), realtime=realtime)
+        return {"all": latency_stats(done),
+                "render": latency_stats([r for r in done if r.kind == "render"]),
+                "points": latency_stats([r for r in done if r.kind == "points"]),
+                "iterations": sch.iterations}
+
+    n_mix = 4 * len(spec)
+    mix_sat = serve_mixed([0.0] * n_mix, realtime=False)
+    mix_rate = 0.5 * mix_sat["all"]["requests_per_s"]
+    arr = poisson_arrivals(mix_rate, n_mix, seed=5006)
+    mix = {"saturation": mix_sat, "rate_per_s": mix_rate,
+           "continuous_backfill": serve_mixed(arr, realtime=True),
+           "one_at_a_time": serve_mixed(arr, realtime=True, max_active=1)}
+    for name in ("continuous_backfill", "one_at_a_time"):
+        m = mix[name]
+        log(f"[serve] mixed {mix_rate:.2f}/s {name}: render p50 {m['render']['p50_ms']:.1f} "
+            f"p99 {m['render']['p99_ms']:.1f} ms; points p50 {m['points']['p50_ms']:.1f} "
+            f"p99 {m['points']['p99_ms']:.1f} ms")
     out = {
         "metric": "render p50/p99 ms at 0.25/0.5/0.9 x saturation (Poisson), rays/s at saturation",
         "value": sat["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
@@ -270,7 +316,7 @@ def serve_bench(args):
                    "train_steps": args.serve_train_steps, "probe_psnr_db": psnr,
                    "params": model.n_params},
         "saturation": sat, "arm_off_saturation": arm_off, "one_at_a_time_saturation": sat_one,
-        "rates": rates,
+        "rates": rates, "mixed_points_and_renders": mix,
     }
     print(json.dumps(out), flush=True)
 

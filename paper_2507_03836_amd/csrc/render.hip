@@ -241,6 +241,13 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// One thread per alive ray (the kernels have no grid-stride loop): at most
+// 2^30 rays, i.e. 2^22 blocks, well inside the grid limit.
+inline unsigned blocks_exact(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
 inline unsigned blocks(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -325,7 +332,7 @@ hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, floa
   hipError_t e = hipMemsetAsync(w.counters + 2, 0, 4, st);
   if (e != hipSuccess) return e;
   if (n_alive > 0)
-    hipLaunchKernelGGL(march_kernel, dim3(blocks(n_alive)), dim3(256), 0, st, a, w.rays,
+    hipLaunchKernelGGL(march_kernel, dim3(blocks_exact(n_alive)), dim3(256), 0, st, a, w.rays,
                        w.alive[cur], n_alive, reinterpret_cast<float4*>(pos_out), w.counters + 2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -343,7 +350,7 @@ hipError_t launch_render_composite(void* ws, int W, int H, int cur, int32_t n_al
   hipError_t e = hipMemsetAsync(w.counters + nxt, 0, 4, st);
   if (e != hipSuccess) return e;
   if (n_alive > 0)
-    hipLaunchKernelGGL(composite_kernel, dim3(blocks(n_alive)), dim3(256), 0, st, w.rays,
+    hipLaunchKernelGGL(composite_kernel, dim3(blocks_exact(n_alive)), dim3(256), 0, st, w.rays,
                        w.alive[cur], n_alive, y, reinterpret_cast<const float4*>(tf), alpha_stop,
                        reinterpret_cast<float4*>(rgba), w.alive[nxt], w.counters + nxt);
   e = hipGetLastError();

@@ -15,14 +15,13 @@ against models that stay resident on the device:
 * one iteration marches every admitted render request, appends a chunk of
   pending point queries, and decodes all samples of one model with a single
   fused encode + MLP launch; then every render composites its own samples.
-  The iteration's sample budget is handed out oldest request first: each
-  render takes the ARM pace that the budget left after it (one sample per
-  alive ray of every younger render stays reserved) allows, so the oldest
-  request advances at full pace and younger ones still make progress
-  ("shared" instead gives every render the pace of the budget over all alive
-  rays; "backfill" gives the oldest render the whole budget and younger ones
-  only what it leaves, so they wait for a turn when that is less than one
-  sample per alive ray);
+  The iteration's sample budget is handed out oldest request first.  Default
+  ("backfill"): the oldest render takes the ARM pace the whole budget allows,
+  younger ones only what it leaves, and a render waits for a turn when that
+  is less than one sample per alive ray.  "oldest_first" reserves one sample
+  per alive ray of every younger render, so all of them move every
+  iteration; "shared" gives every render the pace of the budget over all
+  alive rays;
 * a request leaves the batch when its last ray terminates or its last point
   is decoded, and its latency (arrival to completion) is recorded.
 
@@ -93,7 +92,7 @@ class Scheduler:
     """
 
     def __init__(self, executor, sample_budget: int = 1 << 22, mem_budget: int = 1 << 36,
-                 max_active: int = 64, arm_max: int = 64, policy: str = "oldest_first"):
+                 max_active: int = 64, arm_max: int = 64, policy: str = "backfill"):
         if sample_budget < 2:
             raise ValueError("sample budget must be at least 2")
         if policy not in ("oldest_first", "shared", "backfill"):
