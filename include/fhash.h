@@ -289,7 +289,8 @@ typedef struct {
   int64_t dims[4];
 } fhash_render_state;
 
-/* Device workspace of one request's ray state (W*H rays + occupancy bits). */
+/* Device workspace of one request's ray state (W*H rays + occupancy bits).
+ * W, H >= 1 and W * H <= 2^30, else FHASH_EINVAL. */
 int fhash_render_state_bytes(int32_t W, int32_t H, const int64_t dims[4], size_t* bytes);
 
 /* Set up rays and the occupancy at time t (fractional timestep in [0, T-1]),
@@ -302,8 +303,9 @@ int fhash_render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
 int32_t fhash_render_pace(int64_t budget, int64_t alive, int32_t arm_max);
 
 /* Emit up to `pace` occupied samples per alive ray into pos_out (device
- * float4[cap], model inputs); cap must be >= pace * alive.  Writes the number
- * of samples to *n_samples.  Synchronises `stream`. */
+ * float4[cap], model inputs); cap must be >= pace * alive and pace * alive
+ * <= 2^31 - 1 (FHASH_EINVAL otherwise).  Writes the number of samples to
+ * *n_samples.  Synchronises `stream`. */
 int fhash_render_march(fhash_render_state* state, const fhash_render_opts* opts, int32_t pace,
                        float* pos_out, int64_t cap, int64_t* n_samples, void* stream);
 

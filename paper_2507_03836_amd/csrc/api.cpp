@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 
@@ -523,6 +524,8 @@ int fhash_render_march(fhash_render_state* state, const fhash_render_opts* opts,
   if (state->pending) return fail(FHASH_EINVAL, "previous samples not composited");
   if ((int64_t)pace * state->n_alive > cap)
     return fail(FHASH_EINVAL, "sample buffer %lld < pace * alive", (long long)cap);
+  if ((int64_t)pace * state->n_alive > (int64_t)INT32_MAX)
+    return fail(FHASH_EINVAL, "pace * alive exceeds 2^31 - 1 samples per march");
   if (state->n_alive > 0 && (pos_out == nullptr || !aligned16(pos_out)))
     return fail(FHASH_EINVAL, "pos_out NULL or not 16-byte aligned");
   int32_t ns = 0;

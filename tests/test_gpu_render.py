@@ -104,3 +104,26 @@ def test_render_empty_mask_is_transparent(scene):
     st, _ = fl.fhash_render(s["idx"], s["mlp"], s["tab_d"], s["prm_d"], empty, s["dims"],
                             fl.view_struct(view), 1.0, s["tf_d"], W, H, fl.render_opts(), rgba)
     assert (rgba == 0).all() and st.samples == 0
+
+
+def test_more_rays_than_one_grid_of_65536_blocks(scene):
+    """4200 x 4100 = 17.2e6 rays, more than 65536 blocks of 256 threads: with
+    a fully occupied volume, a decoder whose output is the constant 0.6 (TF
+    opacity 0.21) and a narrow field of view through the volume's centre,
+    every pixel must composite."""
+    s = scene
+    fl = s["fl"]
+    full = torch.from_numpy(
+        synth.pack_mask_rows(np.ones_like(s["mask"])).view(np.int64)).cuda()
+    params = np.zeros_like(s["params"])
+    params[-1] = 0.6
+    W, H = 4200, 4100
+    view = synth.orbit_view(s["dims"], 0.7, 0.3, W, H, fovy_deg=4.0)
+    rgba = torch.empty(H, W, 4, device="cuda")
+    st, ws = fl.fhash_render(s["idx"], s["mlp"], s["tab_d"], torch.from_numpy(params).cuda(),
+                             full, s["dims"], fl.view_struct(view), 2.5, s["tf_d"], W, H,
+                             fl.render_opts(), rgba)
+    del ws
+    a = rgba[..., 3]
+    assert bool((a >= 0.99).all()), int((a < 0.99).sum())
+    assert st.samples >= W * H
