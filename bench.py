@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32",
                     help="mixed: FP16 table reads (Adam-written shadow) + dynamic loss scaling")
     ap.add_argument("--hidden-layers", type=int, default=2)
+    ap.add_argument("--sort", action="store_true",
+                    help="sort each batch by a 4D Morton key before the fused step")
     ap.add_argument("--field-seed", type=int, default=1002)
     ap.add_argument("--sampler-seed", type=int, default=2002)
     ap.add_argument("--psnr-target", type=float, default=0.0,
@@ -65,6 +67,8 @@ def parse():
     ap.add_argument("--serve-sizes", type=str, default="256,512,1024")
     ap.add_argument("--serve-rates", type=str, default="0.25,0.5,0.9",
                     help="Poisson rates as fractions of the saturation request rate")
+    ap.add_argument("--serve-multi", action="store_true",
+                    help="multi-model serving: 6 resident models, mixed renders + point queries")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 4 GiB device copy first (counter calibration)")
     return ap.parse_args()
@@ -151,6 +155,131 @@ def time_to_psnr(args, model, step, gen, dims, t_train0):
             "seconds": reached[1] if reached else None,
             "final_psnr_db": hist[-1][2], "history": hist,
             "probe": "2^22 coreset draws, PSNR over data range 1, FP64 sum on the device"}
+
+
+def serve_multi_bench(args):
+    """Six resident models (480x720x120x100, 640x256x256x100 and 432^3x60, two
+    field seeds each; 16 levels, MLP 32-64-64-64-1, FP16 tables), each trained
+    for --serve-train-steps steps at batch 2^20, then a Poisson stream of
+    requests to random models: every 4th a render (side uniform over
+    {256, 512, 1024}, fractional t, orbit camera), the others point-query
+    batches of 2^k points, k ~ U{10..20}.  Requests are admitted by device
+    bytes next to the resident models.  Continuous batching (backfill) vs one
+    request at a time, same arrivals, at 0.5 x the saturation rate."""
+    import numpy as np
+
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd import synth
+    from paper_2507_03836_amd.model import FHashConfig, FHashModel, geometric_resolutions, psnr_on
+    from paper_2507_03836_amd.serving import (GpuExecutor, Request, ResidentModel, Scheduler,
+                                              latency_stats, poisson_arrivals)
+
+    fl.lib()
+    torch.cuda.set_device(0)
+    C = 1 << 22
+    shapes = [[480, 720, 120, 100], [640, 256, 256, 100], [432, 432, 432, 60]]
+    tf = torch.from_numpy(synth.transfer_function()).cuda()
+    models, info = {}, []
+    for i, dims in enumerate(shapes):
+        for seed in (1005 + 10 * i, 1006 + 10 * i):
+            t0 = time.time()
+            gen = synth.production_volume_gpu(dims, seed=seed)
+            res = geometric_resolutions(16, 16, 512, 4, dims[3], dims)
+            cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3)
+            model = FHashModel(cfg, gen["bits"], dims, init_seed=seed + 2000)
+            B = 1 << 20
+            pos = torch.empty(B, 4, device="cuda")
+            tgt = torch.empty(B, device="cuda")
+            for k in range(args.serve_train_steps):
+                fl.fhash_sample(seed + 1000, k + 1, B, gen["coreset"], gen["M"], dims,
+                                gen["field"], pos, tgt)
+                model.fwd_bwd(pos, tgt)
+                model.optimizer_step()
+            fl.fhash_sample(seed + 3000, 1, B, gen["coreset"], gen["M"], dims, gen["field"],
+                            pos, tgt)
+            psnr = psnr_on(model, pos, tgt)
+            table16 = torch.empty(model.n_table, dtype=torch.float16, device="cuda")
+            fl.fhash_cast(model.table, table16)
+            name = f"{'x'.join(map(str, dims))}/s{seed}"
+            models[name] = ResidentModel(index=model.index, mlp=model.mlp, table=table16,
+                                         params=model.mlp_params.clone(), mask_bits=gen["bits"],
+                                         dims=dims, tf=tf, keep=(model._dir,))
+            info.append({"model": name, "params": model.n_params, "probe_psnr_db": psnr,
+                         "resident_bytes": models[name].nbytes()})
+            del gen, pos, tgt
+            model.params = model.grads = model.m = model.v = None
+            del model
+            torch.cuda.empty_cache()
+            log(f"[multi] {name}: {info[-1]['params']} params, PSNR {psnr:.1f} dB, resident "
+                f"{info[-1]['resident_bytes'] / 2**30:.1f} GiB ({time.time() - t0:.1f} s)")
+    names = list(models)
+    rng = np.random.default_rng(5007)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5007)
+    sizes = [int(x) for x in args.serve_sizes.split(",")]
+    n_req = 4 * args.serve_requests
+    spec = []
+    for i in range(n_req):
+        m = names[int(rng.integers(0, len(names)))]
+        dims = models[m].dims
+        if i % 4 == 0:
+            S = int(rng.choice(sizes))
+            view = synth.orbit_view(dims, float(rng.uniform(0, 2 * np.pi)),
+                                    float(rng.uniform(-np.pi / 3, np.pi / 3)), S, S)
+            spec.append(("render", m, S, view, float(rng.uniform(0, dims[3] - 1))))
+        else:
+            n = 1 << int(rng.integers(10, 21))
+            spec.append(("points", m, torch.rand(n, 4, device="cuda", generator=g)))
+
+    def requests(arr):
+        out = []
+        for sp, a in zip(spec, arr):
+            if sp[0] == "render":
+                _, m, S, v, t = sp
+                out.append(Request(model=m, kind="render", view=v, t=t, W=S, H=S,
+                                   arrival=float(a)))
+            else:
+                out.append(Request(model=sp[1], kind="points", pos=sp[2], n=sp[2].shape[0],
+                                   arrival=float(a)))
+        return out
+
+    def serve(arr, realtime, **kw):
+        ex = GpuExecutor(sample_budget=C)
+        for k, m in models.items():
+            ex.add_model(k, m)
+        free, _ = torch.cuda.mem_get_info()
+        sch = Scheduler(ex, sample_budget=C, mem_budget=int(free * 0.8), **kw)
+        torch.cuda.synchronize()
+        done = sch.run(requests(arr), realtime=realtime)
+        return {"all": latency_stats(done),
+                "render": latency_stats([r for r in done if r.kind == "render"]),
+                "points": latency_stats([r for r in done if r.kind == "points"]),
+                "iterations": sch.iterations, "peak_active": sch.peak_active,
+                "peak_request_bytes": sch.peak_mem, "mem_budget": sch.mem_budget,
+                "resident_bytes": ex.resident_bytes()}
+
+    serve([0.0] * 4, realtime=False)  # warm-up (first 4 requests)
+    sat = serve([0.0] * n_req, realtime=False)
+    rate = 0.5 * sat["all"]["requests_per_s"]
+    arr = poisson_arrivals(rate, n_req, seed=5008)
+    cb = serve(arr, realtime=True)
+    one = serve(arr, realtime=True, max_active=1)
+    for name, x in (("continuous_backfill", cb), ("one_at_a_time", one)):
+        log(f"[multi] {rate:.2f}/s {name}: render p50 {x['render']['p50_ms']:.1f} p99 "
+            f"{x['render']['p99_ms']:.1f} ms; points p50 {x['points']['p50_ms']:.1f} p99 "
+            f"{x['points']['p99_ms']:.1f} ms")
+    out = {
+        "metric": "multi-model serving p50/p99 ms (renders and point queries), 0.5 x saturation",
+        "value": sat["all"]["requests_per_s"], "unit": "requests/s at saturation", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f16 tables, f32 MLP",
+        "data": "synthetic",
+        "config": {"workload": "6 resident models (480x720x120x100, 640x256x256x100, "
+                   "432x432x432x60; 2 seeds each), 16 levels, MLP 32-64-64-64-1, FP16 tables; "
+                   "1 in 4 requests a render, the rest 2^10-2^20 point queries",
+                   "requests": n_req, "sample_budget": C, "models": info},
+        "saturation": sat, "rate_per_s": rate, "continuous_backfill": cb, "one_at_a_time": one,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def serve_bench(args):
@@ -331,6 +460,8 @@ def main():
     import numpy as np
     import torch
 
+    if args.serve_multi:
+        return serve_multi_bench(args)
     if args.serve:
         return serve_bench(args)
 
@@ -368,11 +499,15 @@ def main():
     coreset, M, field = gen["coreset"], gen["M"], gen["field"]
     stream = torch.cuda.current_stream()
 
+    sort_ws = [None]
+
     def step(k, ev=None):
         fl.fhash_sample(args.sampler_seed, k, B, coreset, M, dims, field, pos, tgt)
+        if args.sort:
+            sort_ws[0] = fl.fhash_sort_samples(pos, tgt, B, sort_ws[0])
         if ev is not None:
             ev[0].record(stream)
-        model.fwd_bwd(pos, tgt)
+        model.fwd_bwd(pos, tgt, sorted_batch=args.sort)
         if ev is not None:
             ev[1].record(stream)
         model.optimizer_step()
@@ -422,12 +557,14 @@ def main():
         "config": {"workload": (f"F-Hash training, {'x'.join(map(str, dims))} synthetic volume, "
                                 f"{args.levels} levels x 2 features, MLP "
                                 + "-".join(map(str, cfg.width))
-                                + f", batch 2^{int(np.log2(B))} coreset draws"),
+                                + f", batch 2^{int(np.log2(B))} coreset draws"
+                                + (", Morton-sorted batches" if args.sort else "")),
                    "shape": dims, "levels": args.levels, "batch": B,
                    "active_vertices": model.rows, "params": model.n_params,
                    "coreset": M},
         "breakdown_ms": {"fused_fwd_bwd": fb_ms, "adam": adam_ms,
-                         "sampler_and_other": ms - fb_ms - adam_ms},
+                         ("sampler_sort_and_other" if args.sort else "sampler_and_other"):
+                         ms - fb_ms - adam_ms},
         "roofline": {"kernel": "adam_kernel", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": adam_bytes},
