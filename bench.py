@@ -26,12 +26,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ADAM_BYTES_PER_PARAM = 28  # read p, g, m, v; write p, m, v (gradient reset not counted)
-# HBM bytes of one adam_kernel launch at the default workload, from rocprofv3 FETCH_SIZE
-# (x2.000) and WRITE_SIZE (x1.000) passes, scaled by a plain streaming copy of known size;
-# valid only for the parameter count and the optimizer source they were taken on.
-ADAM_TRAFFIC = {"bytes": 179.33e9, "params": 6390343593,
-                "source_md5": "e4efccb9193df9835bcc3a2873f7e4bf"}
+# Dense Adam moves 24 B per parameter (read p, m, v; write p, m, v), plus 4 B for every
+# gradient float it must read: all of them untracked, only those in flagged 64-B segments
+# under touched-segment tracking (plus one flag byte per tracked segment); the gradient
+# reset is not counted.  The FP16 shadow adds 2 B per parameter.
+ADAM_RW_BYTES_PER_PARAM = 24
+# HBM bytes of one adam_kernel launch at the default workload (FP32, tracked), from
+# rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) passes scaled by a plain streaming
+# copy of known size; valid only for the parameter count and optimizer source they were
+# taken on.
+ADAM_TRAFFIC = {"bytes": 156.90e9, "params": 6390343593,
+                "source_md5": "d602a578d7be1d0da4b2643ea2ed6c36"}
 
 
 def log(*a):
@@ -122,7 +127,7 @@ def cpu_baseline(model, gen, dims, batch, n_cpu, seed):
                        "dense-box index, FP64, single thread")}
 
 
-def time_to_psnr(args, model, step, gen, dims, t_train0):
+def time_to_psnr(args, model, step, gen, dims, t_train0, k_done):
     """Keep training after the timed steps until the probe PSNR reaches the
     target (or max steps).  Probe: 2^22 coreset draws (sampler seed + 2000).
     Wall time counts every training step since the first warm-up step plus
@@ -134,11 +139,11 @@ def time_to_psnr(args, model, step, gen, dims, t_train0):
     ptgt = torch.empty(P, device="cuda")
     fl.fhash_sample(args.sampler_seed + 2000, 1, P, gen["coreset"], gen["M"], dims,
                     gen["field"], ppos, ptgt)
-    k = args.warmup + args.steps
+    k = k_done
     hist = []
     reached = None
     while True:
-        if (k - args.warmup - args.steps) % args.eval_every == 0 or k >= args.max_steps:
+        if (k - k_done) % args.eval_every == 0 or k >= args.max_steps:
             ps = psnr_on(model, ppos, ptgt)
             el = time.perf_counter() - t_train0
             hist.append((k, round(el, 3), round(ps, 3)))
@@ -530,12 +535,29 @@ def main():
     loss = model.loss_sum.item() / (B * (args.warmup + args.steps))
     ms = wall * 1e3 / args.steps
     mixed = args.precision == "mixed"
-    adam_bytes = (ADAM_BYTES_PER_PARAM + (2 if mixed else 0)) * model.n_params
+    P = model.n_params
+    k_done = args.warmup + args.steps
+    per = ADAM_RW_BYTES_PER_PARAM + (2 if mixed else 0)
+    flagged = None
+    if model.touch is None:
+        adam_bytes = (per + 4) * P
+    else:
+        # one more step outside the timed region, to count the flagged segments
+        k_done += 1
+        fl.fhash_sample(args.sampler_seed, k_done, B, coreset, M, dims, field, pos, tgt)
+        if args.sort:
+            sort_ws[0] = fl.fhash_sort_samples(pos, tgt, B, sort_ws[0])
+        model.fwd_bwd(pos, tgt, sorted_batch=args.sort)
+        flagged = int((model._touch_flags != 0).sum().item())
+        model.optimizer_step()
+        T = model.touch.end - model.touch.begin
+        adam_bytes = per * P + 4 * (P - T) + 4 * fl.TOUCH_FLOATS * flagged + T // fl.TOUCH_FLOATS
     achieved = adam_bytes / (adam_ms * 1e-3) / 1e9
     import hashlib
     src = os.path.join(ROOT, "paper_2507_03836_amd", "csrc", "optim.hip")
     same_src = hashlib.md5(open(src, "rb").read()).hexdigest() == ADAM_TRAFFIC["source_md5"]
-    traffic = ADAM_TRAFFIC["bytes"] if (same_src and not mixed and
+    traffic = ADAM_TRAFFIC["bytes"] if (same_src and not mixed and model.touch is not None and
+                                        not args.sort and
                                         model.n_params == ADAM_TRAFFIC["params"]) else None
     log(f"[bench] step {ms:.3f} ms: fused fwd+bwd {fb_ms:.3f} ms, adam {adam_ms:.3f} ms; "
         f"mean loss {loss:.4g}")
@@ -567,13 +589,14 @@ def main():
                          ms - fb_ms - adam_ms},
         "roofline": {"kernel": "adam_kernel", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes": adam_bytes},
+                     "traffic": traffic, "algorithmic_bytes": adam_bytes,
+                     "flagged_segments": flagged},
     }
     if mixed:
         out["loss_scale"] = model.loss_scale
         out["skipped_steps"] = model.skipped
     if args.psnr_target > 0:
-        out["time_to_psnr"] = time_to_psnr(args, model, step, gen, dims, t_train0)
+        out["time_to_psnr"] = time_to_psnr(args, model, step, gen, dims, t_train0, k_done)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(model, gen, dims, B, args.cpu_samples, 2002)

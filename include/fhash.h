@@ -124,20 +124,37 @@ int fhash_dense_index(const fhash_grid_desc* grid, fhash_index* out, int64_t* sl
 int fhash_encode_fwd(const fhash_index* idx, const float* pos, int64_t n, const void* table,
                      fhash_dtype table_dt, float* enc, void* stream);
 
+/* Touched-segment tracking of a table gradient (an optimisation of the dense
+ * Adam sweep, not part of the method): the gradient is viewed as segments of
+ * FHASH_TOUCH_FLOATS floats; flags (device uint8, one per segment of the
+ * whole table, i.e. ceil(rows * F / FHASH_TOUCH_FLOATS) bytes, caller-owned,
+ * all zero before the first tracked write) gets a nonzero byte for every
+ * segment at or after float index `begin` that a scatter-add wrote.  fhash_step then reads the gradient in [begin, end) only
+ * where the segment is flagged (elsewhere it is zero by construction) and
+ * clears the flags it read.  begin: a multiple of FHASH_TOUCH_FLOATS;
+ * 0 <= begin <= end <= the gradient length.  Every writer of the gradient in
+ * [begin, end) between two steps must be given the same descriptor. */
+#define FHASH_TOUCH_FLOATS 16
+typedef struct {
+  uint8_t* flags;
+  int64_t begin, end;
+} fhash_touch;
+
 /* Adjoint of the encoding: d_table[slot][k] += w_c * d_enc[s][l*F + k] for every
  * active corner c of every sample and level (FP32 atomics; summation order is
  * not deterministic).  The corner weights are recomputed from pos, not stored.
- * d_enc: device float [n][L*F]; d_table: device float [rows][F], accumulated. */
+ * d_enc: device float [n][L*F]; d_table: device float [rows][F], accumulated.
+ * touch: NULL, or segment flags to set (see fhash_touch). */
 int fhash_encode_bwd(const fhash_index* idx, const float* pos, int64_t n, const float* d_enc,
-                     float* d_table, void* stream);
+                     float* d_table, const fhash_touch* touch, void* stream);
 
 /* ------------------------------------------------------------------- MLP ----
  * Shallow decoder (Sec. 3.2.4 end; 2 hidden layers of 64 in Sec. 4.2):
  * width[0] = input (<= 64), n_layers-1 hidden layers of equal width H
  * (16, 32 or 64) with ReLU, and a linear output of width 1; biases on.
  * params: device float, packed per layer k as W_k[width[k+1]][width[k]]
- * row-major then b_k[width[k+1]].  compute_dt: FHASH_F32 (FP32 MFMA) or
- * FHASH_BF16 (BF16 MFMA on a bf16 copy of params, `shadow`, FP32 accumulate).
+ * row-major then b_k[width[k+1]].  compute_dt: FHASH_F32 (FP32 MFMA); other
+ * values return FHASH_ENOTSUP.  `shadow` is reserved (pass NULL).
  */
 typedef struct {
   int32_t n_layers;
@@ -173,17 +190,19 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
  * fhash_sort_samples; the scatter-add then sums equal slots of neighbouring
  * samples with a wave-level segmented reduction before its atomics on the
  * levels coarse enough for neighbours to share vertices.  Results are the same
- * up to FP32 summation order. */
+ * up to FP32 summation order.  touch: NULL, or segment flags of d_table to set
+ * (see fhash_touch). */
 #define FHASH_SAMPLES_SORTED 1u
 int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
                     const void* table, fhash_dtype table_dt, const float* params,
                     const void* shadow, const float* dy, float* d_table, float* d_params,
-                    uint32_t flags, void* ws, size_t* ws_bytes, void* stream);
+                    uint32_t flags, const fhash_touch* touch, void* ws, size_t* ws_bytes,
+                    void* stream);
 int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
                       const float* target, int64_t n, const void* table, fhash_dtype table_dt,
                       const float* params, const void* shadow, float loss_scale, float* d_table,
-                      float* d_params, double* loss_sum, uint32_t flags, void* ws,
-                      size_t* ws_bytes, void* stream);
+                      float* d_params, double* loss_sum, uint32_t flags, const fhash_touch* touch,
+                      void* ws, size_t* ws_bytes, void* stream);
 
 /* ------------------------------------------------------------ optimiser ----
  * Adam (Sec. 5.1.3: Adam, lr 0.01; PyTorch semantics, bias-corrected, no
@@ -193,6 +212,10 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
  * grad is zeroed.  If found_inf (device int32, may be NULL) is non-zero the
  * whole update is skipped (grad is still zeroed).  shadow (device, may be
  * NULL) receives p rounded to shadow_dt (FHASH_F16 or FHASH_BF16, RNE).
+ * touch (may be NULL): the gradient in [touch->begin, touch->end) is read only
+ * in flagged segments and taken as zero elsewhere; the flags of that range are
+ * cleared.  Results are bit for bit those of the untracked call whenever the
+ * gradient is zero in every unflagged segment.
  * All arrays device float[n], 16-byte aligned. */
 typedef struct {
   double lr, beta1, beta2, eps; /* the kernel uses FP32 roundings of b1, 1-b1, b2, 1-b2 */
@@ -202,7 +225,7 @@ typedef struct {
 
 int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
                void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
-               void* stream);
+               const fhash_touch* touch, void* stream);
 
 /* *found_inf |= any(!isfinite(grad[i])) over device float grad[n]. */
 int fhash_check_finite(const float* grad, int64_t n, int32_t* found_inf, void* stream);

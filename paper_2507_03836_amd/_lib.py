@@ -74,6 +74,25 @@ class RenderStats(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("samples", C.c_int64)]
 
 
+class Touch(C.Structure):
+    _fields_ = [("flags", C.c_void_p), ("begin", C.c_int64), ("end", C.c_int64)]
+
+
+TOUCH_FLOATS = 16
+
+
+def touch_desc(flags: torch.Tensor, begin: int, end: int) -> Touch:
+    """Touched-segment descriptor over a uint8 flag tensor (kept alive by the caller)."""
+    t = Touch()
+    t.flags = flags.data_ptr()
+    t.begin, t.end = int(begin), int(end)
+    return t
+
+
+def _touch(t):
+    return None if t is None else C.byref(t)
+
+
 _lib = None
 
 
@@ -99,16 +118,16 @@ def _declare(L):
         "fhash_build_index": (C.c_int, [P, P, P, P, P, P, P, P]),
         "fhash_dense_index": (C.c_int, [P, P, P]),
         "fhash_encode_fwd": (C.c_int, [P, P, I64, P, C.c_int, P, P]),
-        "fhash_encode_bwd": (C.c_int, [P, P, I64, P, P, P]),
+        "fhash_encode_bwd": (C.c_int, [P, P, I64, P, P, P, P]),
         "fhash_mlp_num_params": (I64, [P]),
         "fhash_mlp_fwd": (C.c_int, [P, P, P, P, I64, P, P]),
         "fhash_mlp_bwd": (C.c_int, [P, P, P, P, P, I64, P, P, P, P, P]),
         "fhash_fused_fwd": (C.c_int, [P, P, P, I64, P, C.c_int, P, P, P, P]),
         "fhash_fused_bwd": (C.c_int, [P, P, P, I64, P, C.c_int, P, P, P, P, P, C.c_uint32, P, P,
-                                      P]),
+                                      P, P]),
         "fhash_fused_train": (C.c_int, [P, P, P, P, I64, P, C.c_int, P, P, F, P, P, P, C.c_uint32,
-                                        P, P, P]),
-        "fhash_step": (C.c_int, [P, P, P, P, P, P, C.c_int, I64, P, P]),
+                                        P, P, P, P]),
+        "fhash_step": (C.c_int, [P, P, P, P, P, P, C.c_int, I64, P, P, P]),
         "fhash_check_finite": (C.c_int, [P, I64, P, P]),
         "fhash_cast": (C.c_int, [P, P, C.c_int, I64, P]),
         "fhash_sample": (C.c_int, [U64, U64, I64, P, U64, P, P, P, P, P]),
@@ -232,9 +251,9 @@ def fhash_encode_fwd(idx: Index, pos, n, table, enc):
                                   _stream()), "fhash_encode_fwd")
 
 
-def fhash_encode_bwd(idx: Index, pos, n, d_enc, d_table):
+def fhash_encode_bwd(idx: Index, pos, n, d_enc, d_table, touch=None):
     _check(lib().fhash_encode_bwd(C.byref(idx), _ptr(pos), n, _ptr(d_enc), _ptr(d_table),
-                                  _stream()), "fhash_encode_bwd")
+                                  _touch(touch), _stream()), "fhash_encode_bwd")
 
 
 def fhash_mlp_num_params(mlp: MlpDesc) -> int:
@@ -274,10 +293,11 @@ SAMPLES_SORTED = 1
 
 
 def fhash_fused_bwd(idx: Index, mlp: MlpDesc, pos, n, table, params, dy, d_table, d_params,
-                    shadow=None, ws=None, flags=0):
+                    shadow=None, ws=None, flags=0, touch=None):
     L = lib()
     head = (C.byref(idx), C.byref(mlp), _ptr(pos), n, _ptr(table), _dt(table), _ptr(params),
-            _ptr(shadow), _ptr(dy), _ptr(d_table), _ptr(d_params), C.c_uint32(flags))
+            _ptr(shadow), _ptr(dy), _ptr(d_table), _ptr(d_params), C.c_uint32(flags),
+            _touch(touch))
     need = _ws_query(L.fhash_fused_bwd, head, "fhash_fused_bwd")
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=params.device)
@@ -287,11 +307,12 @@ def fhash_fused_bwd(idx: Index, mlp: MlpDesc, pos, n, table, params, dy, d_table
 
 
 def fhash_fused_train(idx: Index, mlp: MlpDesc, pos, target, n, table, params, d_table,
-                      d_params, loss_sum=None, loss_scale=1.0, shadow=None, ws=None, flags=0):
+                      d_params, loss_sum=None, loss_scale=1.0, shadow=None, ws=None, flags=0,
+                      touch=None):
     L = lib()
     head = (C.byref(idx), C.byref(mlp), _ptr(pos), _ptr(target), n, _ptr(table), _dt(table),
             _ptr(params), _ptr(shadow), C.c_float(loss_scale), _ptr(d_table), _ptr(d_params),
-            _ptr(loss_sum), C.c_uint32(flags))
+            _ptr(loss_sum), C.c_uint32(flags), _touch(touch))
     need = _ws_query(L.fhash_fused_train, head, "fhash_fused_train")
     if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(max(need, 16), dtype=torch.uint8, device=params.device)
@@ -300,11 +321,11 @@ def fhash_fused_train(idx: Index, mlp: MlpDesc, pos, target, n, table, params, d
     return ws
 
 
-def fhash_step(opt: AdamDesc, param, grad, m, v, shadow=None, found_inf=None):
+def fhash_step(opt: AdamDesc, param, grad, m, v, shadow=None, found_inf=None, touch=None):
     sdt = F16 if shadow is None else _dt(shadow)
     _check(lib().fhash_step(C.byref(opt), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
-                            _ptr(shadow), sdt, param.numel(), _ptr(found_inf), _stream()),
-           "fhash_step")
+                            _ptr(shadow), sdt, param.numel(), _ptr(found_inf), _touch(touch),
+                            _stream()), "fhash_step")
 
 
 def fhash_check_finite(grad, found_inf):

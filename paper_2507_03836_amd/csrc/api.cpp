@@ -116,6 +116,21 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
 
+// Validate a touched-segment descriptor against a gradient of `len` floats and
+// install it in g (NULL: not tracked).
+static int apply_touch(const fhash_touch* t, int64_t len, fh::GridDev* g) {
+  if (t == nullptr) return FHASH_OK;
+  if (t->flags == nullptr) return fail(FHASH_EINVAL, "touch flags are NULL");
+  if (t->begin < 0 || t->begin % FHASH_TOUCH_FLOATS != 0 || t->end < t->begin || t->end > len)
+    return fail(FHASH_EINVAL, "touch range [%lld, %lld) invalid for %lld floats",
+                (long long)t->begin, (long long)t->end, (long long)len);
+  if (g != nullptr) {
+    g->touch = t->flags;
+    g->touch_begin = t->begin;
+  }
+  return FHASH_OK;
+}
+
 extern "C" {
 
 int fhash_version(void) { return FHASH_VERSION; }
@@ -221,16 +236,17 @@ int fhash_encode_fwd(const fhash_index* idx, const float* pos, int64_t n, const 
 }
 
 int fhash_encode_bwd(const fhash_index* idx, const float* pos, int64_t n, const float* d_enc,
-                     float* d_table, void* stream) {
+                     float* d_table, const fhash_touch* touch, void* stream) {
   int rc = check_index(idx);
   if (rc) return rc;
   if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
   if (n == 0 || total_rows(idx) == 0) return FHASH_OK;
   if (pos == nullptr || d_enc == nullptr || d_table == nullptr)
     return fail(FHASH_EINVAL, "NULL pointer");
   if (!aligned16(pos)) return fail(FHASH_EINVAL, "pos not 16-byte aligned");
-  fh::GridDev g;
-  fh::make_grid_dev(idx, &g);
   return hip_status(fh::launch_encode_bwd(g, pos, n, d_enc, d_table, S(stream)),
                     "fhash_encode_bwd");
 }
@@ -327,7 +343,8 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
 int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
                     const void* table, fhash_dtype table_dt, const float* params,
                     const void* shadow, const float* dy, float* d_table, float* d_params,
-                    uint32_t flags, void* ws, size_t* ws_bytes, void* stream) {
+                    uint32_t flags, const fhash_touch* touch, void* ws, size_t* ws_bytes,
+                    void* stream) {
   (void)shadow;
   int H, NH;
   int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
@@ -342,6 +359,7 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
   g.dedup = dedup_mask(idx, n, flags);
+  if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
   return hip_status(fh::launch_fused_bwd(g, H, NH, pos, n, table, table_dt, params, dy, d_table,
                                          d_params, ws, P, S(stream)),
                     "fhash_fused_bwd");
@@ -350,8 +368,8 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
 int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
                       const float* target, int64_t n, const void* table, fhash_dtype table_dt,
                       const float* params, const void* shadow, float loss_scale, float* d_table,
-                      float* d_params, double* loss_sum, uint32_t flags, void* ws,
-                      size_t* ws_bytes, void* stream) {
+                      float* d_params, double* loss_sum, uint32_t flags,
+                      const fhash_touch* touch, void* ws, size_t* ws_bytes, void* stream) {
   (void)shadow;
   int H, NH;
   int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
@@ -366,6 +384,7 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
   g.dedup = dedup_mask(idx, n, flags);
+  if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
   return hip_status(fh::launch_fused_train(g, H, NH, pos, target, n, table, table_dt, params,
                                            loss_scale, d_table, d_params, loss_sum, ws, P,
                                            S(stream)),
@@ -374,7 +393,7 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
 
 int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
                void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
-               void* stream) {
+               const fhash_touch* touch, void* stream) {
   if (opt == nullptr) return fail(FHASH_EINVAL, "optimiser descriptor is NULL");
   if (n < 0) return fail(FHASH_EINVAL, "n < 0");
   if (opt->step < 1) return fail(FHASH_EINVAL, "step must be >= 1");
@@ -392,8 +411,10 @@ int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, 
     if ((reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)
       return fail(FHASH_EINVAL, "shadow must be 8-byte aligned");
   }
+  int rc = apply_touch(touch, n, nullptr);
+  if (rc) return rc;
   return hip_status(
-      fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, n, found_inf, S(stream)),
+      fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, n, found_inf, touch, S(stream)),
       "fhash_step");
 }
 

@@ -25,6 +25,8 @@ struct GridDev {
   int32_t L, F;
   int32_t active;
   uint32_t dedup;  // bit l: combine equal slots of neighbouring lanes before level l's atomics
+  uint8_t* touch;  // touched-segment flags of the table gradient (NULL: not tracked)
+  int64_t touch_begin;  // first tracked float (a multiple of FHASH_TOUCH_FLOATS)
 };
 
 // Fill a GridDev from a public index descriptor (host).
@@ -35,6 +37,8 @@ inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
   g->active = idx->active;
   g->dir = reinterpret_cast<const ulonglong2*>(idx->dir);
   g->dedup = 0;
+  g->touch = nullptr;
+  g->touch_begin = 0;
   for (int l = 0; l < FHASH_MAX_LEVELS; ++l) {
     LevelDev& d = g->lv[l];
     if (l < gd.n_levels) {

@@ -40,7 +40,8 @@ __global__ void __launch_bounds__(256)
   const float4 p = pos[s];
   const float* gin = d_enc + s * (int64_t)g.L * F;
   for (int l = 0; l < g.L; ++l)
-    scatter_level_lane<F>(g.lv[l], g.dir, g.active != 0, p, e, f, gin[l * F + f], d_table);
+    scatter_level_lane<F>(g.lv[l], g.dir, g.active != 0, p, e, f, gin[l * F + f], d_table,
+                          g.touch, g.touch_begin);
 }
 
 template <int F>

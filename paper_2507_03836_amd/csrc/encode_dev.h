@@ -115,12 +115,20 @@ __device__ __forceinline__ void encode_level(const LevelDev& d, const ulonglong2
   for (int k = 0; k < F; ++k) out[k] = acc[k];
 }
 
+// Touched-segment flag of a gradient write at float index fidx: the segment of
+// FHASH_TOUCH_FLOATS floats that holds it is flagged (a plain byte store; all
+// writers store the same value).  Only floats at or after `tbeg` are tracked.
+__device__ __forceinline__ void mark_touched(uint8_t* touch, int64_t tbeg, int64_t fidx) {
+  if (touch != nullptr && fidx >= tbeg) touch[fidx / FHASH_TOUCH_FLOATS] = 1;
+}
+
 // Adjoint of encode_level: d_table[slot_c][k] += w_c g[k] with FP32 hardware
 // atomics (no return value).  Weights are recomputed from the position.
 template <int F>
 __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong2* dir,
                                               bool active, const float4 p, const float* g,
-                                              float* __restrict__ d_table) {
+                                              float* __restrict__ d_table, uint8_t* touch,
+                                              int64_t tbeg) {
   int ix, iy, iz, it;
   float fx, fy, fz, ft;
   locate(p.x, d.rx, d.sx, ix, fx);
@@ -139,10 +147,12 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
     if (v0) {
 #pragma unroll
       for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + s0 * F + k, w0 * g[k]);
+      mark_touched(touch, tbeg, s0 * F);
     }
     if (v1) {
 #pragma unroll
       for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + s1 * F + k, w1 * g[k]);
+      mark_touched(touch, tbeg, s1 * F);
     }
   }
 }
@@ -156,7 +166,8 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
 template <int F>
 __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulonglong2* dir,
                                                    bool active, const float4 p, int e, int f,
-                                                   float gval, float* __restrict__ d_table) {
+                                                   float gval, float* __restrict__ d_table,
+                                                   uint8_t* touch, int64_t tbeg) {
   int ix, iy, iz, it;
   float fx, fy, fz, ft;
   locate(p.x, d.rx, d.sx, ix, fx);
@@ -173,7 +184,10 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
     bool v0, v1;
     row_pair_slots(d, dir, active, row, ix, s0, s1, v0, v1);
     const int64_t s = e ? s1 : s0;
-    if (e ? v1 : v0) unsafeAtomicAdd(d_table + s * F + f, wr * wx * gval);
+    if (e ? v1 : v0) {
+      unsafeAtomicAdd(d_table + s * F + f, wr * wx * gval);
+      if (f == 0) mark_touched(touch, tbeg, s * F);  // F divides the segment: one flag per slot
+    }
   }
 }
 
@@ -187,7 +201,8 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
 template <int F>
 __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulonglong2* dir,
                                                     bool active, const float4 p, const float* g,
-                                                    bool valid, float* __restrict__ d_table) {
+                                                    bool valid, float* __restrict__ d_table,
+                                                    uint8_t* touch, int64_t tbeg) {
   const int i = threadIdx.x & 15;
   int ix, iy, iz, it;
   float fx, fy, fz, ft;
@@ -231,6 +246,7 @@ __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulo
       if (tail && s >= 0) {
 #pragma unroll
         for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + s * F + k, v[k]);
+        mark_touched(touch, tbeg, s * F);
       }
     }
   }

@@ -81,7 +81,8 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
         float gl[F];
 #pragma unroll
         for (int k = 0; k < F; ++k) gl[k] = dx[a][j * F + k];
-        scatter_level_dedup<F>(lv[l], g.dir, g.active != 0, p, gl, valid, d_table);
+        scatter_level_dedup<F>(lv[l], g.dir, g.active != 0, p, gl, valid, d_table, g.touch,
+                               g.touch_begin);
       }
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
@@ -102,7 +103,8 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
         for (int q = 1; q < F; ++q)
           if (f == q) gval = gsrc[q];
         if (ls < g.L && vs && !((g.dedup >> ls) & 1u))
-          scatter_level_lane<F>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table);
+          scatter_level_lane<F>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table, g.touch,
+                                g.touch_begin);
       }
     }
 }

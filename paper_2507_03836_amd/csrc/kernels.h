@@ -49,7 +49,7 @@ hipError_t launch_fused_train(const GridDev& g, int H, int NH, const float* pos,
 // optim.hip
 hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
                        void* shadow, fhash_dtype sdt, int64_t n, const int32_t* found_inf,
-                       hipStream_t st);
+                       const fhash_touch* touch, hipStream_t st);
 hipError_t launch_reduce_partials(const float* part, int64_t nwav, int64_t P, float* d_params,
                                   hipStream_t st);
 hipError_t launch_check_finite(const float* g, int64_t n, int32_t* found, hipStream_t st);

@@ -67,10 +67,33 @@ __device__ __forceinline__ void store_shadow4(void* shadow, int sdt, int64_t i, 
 // Streaming sweep: every array is touched once, so loads and stores bypass the
 // caches' retention (non-temporal) and each thread keeps two float4 groups in
 // flight.  The gradient is reset only where it is nonzero.
+// Gradient read of float4 group i under touched-segment tracking: a group that
+// lies inside [tb, te) is read only when its segment is flagged (otherwise the
+// gradient is zero there); a group that opens a segment in the range clears
+// its flag after the read.  The 4 groups of a segment are 4 consecutive lanes
+// of one wave, so all of them have read the flag before the clearing store.
+__device__ __forceinline__ void tracked_load(const f4v* __restrict__ g4, int64_t i,
+                                             uint8_t* __restrict__ touch, int64_t tb, int64_t te,
+                                             f4v& out) {
+  const int64_t f = i << 2;
+  if (touch == nullptr || f < tb || f >= te) {
+    out = __builtin_nontemporal_load(g4 + i);
+    return;
+  }
+  const int64_t seg = f / FHASH_TOUCH_FLOATS;
+  if (f + 4 <= te && touch[seg] == 0) {
+    out = (f4v){0.0f, 0.0f, 0.0f, 0.0f};
+  } else {
+    out = __builtin_nontemporal_load(g4 + i);
+  }
+  if ((f % FHASH_TOUCH_FLOATS) == 0) touch[seg] = 0;
+}
+
 __global__ void __launch_bounds__(256)
     adam_kernel(AdamK k, float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                 float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t n,
-                const int32_t* __restrict__ found_inf) {
+                const int32_t* __restrict__ found_inf, uint8_t* __restrict__ touch, int64_t tb,
+                int64_t te) {
   const bool skip = (found_inf != nullptr) && (*found_inf != 0);
   const int64_t n4 = n >> 2;
   const int64_t S = (int64_t)gridDim.x * blockDim.x;
@@ -82,9 +105,9 @@ __global__ void __launch_bounds__(256)
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += 2 * S) {
     const int64_t j = i + S;
     const bool two = j < n4;
-    const f4v g0 = __builtin_nontemporal_load(g4 + i);
-    f4v g1 = zero;
-    if (two) g1 = __builtin_nontemporal_load(g4 + j);
+    f4v g0, g1 = zero;
+    tracked_load(g4, i, touch, tb, te, g0);
+    if (two) tracked_load(g4, j, touch, tb, te, g1);
     if (!skip) {
       f4v p0 = __builtin_nontemporal_load(p4 + i), m0 = __builtin_nontemporal_load(m4 + i);
       f4v v0 = __builtin_nontemporal_load(v4 + i);
@@ -225,7 +248,7 @@ inline unsigned blocks_for(int64_t n, int64_t per_thread) {
 
 hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
                        void* shadow, fhash_dtype sdt, int64_t n, const int32_t* found_inf,
-                       hipStream_t st) {
+                       const fhash_touch* touch, hipStream_t st) {
   if (n == 0) return hipSuccess;
   AdamK k;
   const double bc1 = 1.0 - pow(o->beta1, (double)o->step);
@@ -243,8 +266,10 @@ hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, f
   int64_t b = (n / 8 + 255) / 256;
   if (b > 131072) b = 131072;
   if (b < 1) b = 1;
+  uint8_t* tf = touch ? touch->flags : nullptr;
+  const int64_t tb = touch ? touch->begin : 0, te = touch ? touch->end : 0;
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)b), dim3(256), 0, st, k, p, g, m, v, shadow,
-                     (int)sdt, n, found_inf);
+                     (int)sdt, n, found_inf, tf, tb, te);
   return hipGetLastError();
 }
 

@@ -17,6 +17,13 @@ scaled by a dynamic factor (start 2^16, doubled after `scale_window` clean
 steps, halved with the step skipped when a decoder gradient is not finite:
 the output-bias gradient is the sum of every sample's output gradient, so a
 non-finite sample gradient shows up there).
+
+Touched-segment tracking (on by default): a step's scatter-add writes only a
+small part of the fine levels' gradient, so the scatter flags every 64-byte
+gradient segment it writes from the first level of at least 2^21 segments
+(128 MiB of FP32 table) on, and the Adam sweep reads the gradient only in
+flagged segments there (zero elsewhere).  The update is the dense Adam update
+of every parameter either way.
 """
 from __future__ import annotations
 
@@ -68,7 +75,7 @@ class FHashModel:
     def __init__(self, cfg: FHashConfig, mask_bits: torch.Tensor | None, dims, device="cuda",
                  table_init: torch.Tensor | None = None, mlp_init: torch.Tensor | None = None,
                  init_seed: int = 3000, precision: str = "fp32", loss_scale: float = 2.0 ** 16,
-                 scale_window: int = 2000):
+                 scale_window: int = 2000, track_touched: bool = True):
         if precision not in ("fp32", "mixed"):
             raise ValueError(f"precision must be 'fp32' or 'mixed', not {precision!r}")
         self.cfg = cfg
@@ -114,6 +121,17 @@ class FHashModel:
         self._ws = None
         self.shadow = None
         self.loss_scale = 1.0
+        self.touch = None
+        self._touch_flags = None
+        if track_touched:
+            F, seg = cfg.n_features, fl.TOUCH_FLOATS
+            first = next((l for l in range(cfg.n_levels)
+                          if self.slots_per_level[l] * F // seg >= (1 << 21)), None)
+            if first is not None:
+                begin = int(self.index.slot_offset[first]) * F // seg * seg
+                self._touch_flags = torch.zeros((self.n_table + seg - 1) // seg,
+                                                dtype=torch.uint8, device=self.device)
+                self.touch = fl.touch_desc(self._touch_flags, begin, self.n_table)
         if precision == "mixed":
             self.shadow = torch.empty(n_alloc, dtype=torch.float16, device=self.device)
             fl.fhash_cast(self.params, self.shadow)
@@ -169,7 +187,8 @@ class FHashModel:
         self._ws = fl.fhash_fused_train(self.index, self.mlp, pos, target, n, self.read_table,
                                         self.mlp_params, self.d_table, self.d_mlp,
                                         self.loss_sum, s, ws=self._ws,
-                                        flags=fl.SAMPLES_SORTED if sorted_batch else 0)
+                                        flags=fl.SAMPLES_SORTED if sorted_batch else 0,
+                                        touch=self.touch)
 
     def optimizer_step(self, grad_scale: float | None = None, found_inf=None) -> bool:
         """Dense Adam over every parameter; gradients are reset.  The mixed path
@@ -179,14 +198,16 @@ class FHashModel:
             self.step_count += 1
             fl.fhash_step(self.adam_desc(self.step_count, 1.0 if grad_scale is None else grad_scale),
                           self.params[: self.n_params], self.grads[: self.n_params],
-                          self.m[: self.n_params], self.v[: self.n_params], found_inf=found_inf)
+                          self.m[: self.n_params], self.v[: self.n_params], found_inf=found_inf,
+                          touch=self.touch)
             return True
         self.found_inf.zero_()
         fl.fhash_check_finite(self.d_mlp, self.found_inf)
         opt = self.adam_desc(self.step_count + 1, 1.0 / self.loss_scale)
         fl.fhash_step(opt, self.params[: self.n_params], self.grads[: self.n_params],
                       self.m[: self.n_params], self.v[: self.n_params],
-                      shadow=self.shadow[: self.n_params], found_inf=self.found_inf)
+                      shadow=self.shadow[: self.n_params], found_inf=self.found_inf,
+                      touch=self.touch)
         if int(self.found_inf.item()):
             self.loss_scale *= 0.5
             self._clean = 0

@@ -303,6 +303,91 @@ def test_adam_step(fl):
     assert torch.equal(before, pd) and (gd == 0).all()
 
 
+# ----------------------------------------------------------------------------- touched segments
+@pytest.mark.parametrize("path", ["fused_train", "fused_bwd", "encode_bwd"])
+def test_touched_segment_flags_are_exact(fl, tiny, path):
+    """Flags are set exactly for the segments (16 floats) holding a slot that an
+    active corner of some sample wrote, at or after float `begin` (from the
+    oracle's corner slots)."""
+    f, mask = tiny
+    F = 2
+    idx, counts, dir_t, _ = _build(fl, TINY_RES, F, mask)
+    g = O.Grid(np.array(TINY_RES), F, mask)
+    rows = g.total_slots
+    begin = int(g.slot_offset[2]) * F // 16 * 16 - 16
+    nseg = (rows * F + 15) // 16
+    flags = torch.zeros(nseg, dtype=torch.uint8, device="cuda")
+    t = fl.touch_desc(flags, begin, rows * F)
+    n = 777
+    pos = _probe_positions(n, 91)
+    pos_d = torch.from_numpy(pos).cuda()
+    width = [8, 32, 32, 1]
+    prm = torch.from_numpy(_mlp_params(width, 3)).cuda()
+    tab = torch.from_numpy(np.random.default_rng(4).uniform(-1, 1, (rows, F))
+                           .astype(np.float32)).cuda()
+    dt = torch.zeros(rows, F, device="cuda")
+    dp = torch.zeros(prm.numel(), device="cuda")
+    mlp = fl.mlp_desc(width)
+    if path == "fused_train":
+        tgt = torch.rand(n, device="cuda")
+        fl.fhash_fused_train(idx, mlp, pos_d, tgt, n, tab, prm, dt, dp, touch=t)
+    elif path == "fused_bwd":
+        dy = torch.randn(n, device="cuda")
+        fl.fhash_fused_bwd(idx, mlp, pos_d, n, tab, prm, dy, dt, dp, touch=t)
+    else:
+        de = torch.randn(n, len(TINY_RES) * F, device="cuda")
+        fl.fhash_encode_bwd(idx, pos_d, n, de, dt, touch=t)
+    slots, _ = O.corners(g, pos)
+    sl = slots[slots >= 0] * F
+    exp = np.zeros(nseg, bool)
+    exp[np.unique(sl[sl >= begin] // 16)] = True
+    got = flags.cpu().numpy() != 0
+    assert np.array_equal(got, exp), (int((got != exp).sum()), int(exp.sum()))
+    # every nonzero gradient float at or after begin lies in a flagged segment
+    nz = np.flatnonzero(dt.cpu().numpy().ravel() != 0)
+    nz = nz[nz >= begin]
+    assert got[nz // 16].all()
+
+
+def test_tracked_adam_equals_untracked(fl):
+    """A tracked step (gradient read only in flagged segments of [begin, end),
+    always read outside) gives bit for bit the untracked step when the gradient
+    is zero in every unflagged segment; it resets the gradient and the flags."""
+    rng = np.random.default_rng(8)
+    n = 4 * 65536 + 3
+    begin, end = 16 * 1000, n - 4093
+    nseg = (end + 15) // 16
+    seg_on = rng.random(nseg) < 0.1
+    g = (rng.normal(size=n) * np.logspace(-6, 1, n)).astype(np.float32)
+    fidx = np.arange(n)
+    in_range = (fidx >= begin) & (fidx < end)
+    off = in_range & ~seg_on[np.minimum(fidx // 16, nseg - 1)]
+    g[off] = 0.0
+    g[::13] = 0.0
+    p = rng.normal(size=n).astype(np.float32)
+    m = (rng.normal(size=n) * 0.01).astype(np.float32)
+    v = (rng.random(n) * 1e-4).astype(np.float32)
+    o = fl.AdamDesc()
+    o.lr, o.beta1, o.beta2, o.eps, o.step, o.grad_scale = 0.01, 0.9, 0.999, 1e-8, 3, 0.5
+    outs = []
+    for tracked in (False, True):
+        pd, gd, md, vd = [torch.from_numpy(a.copy()).cuda() for a in (p, g, m, v)]
+        sh = torch.empty(n, dtype=torch.float16, device="cuda")
+        touch = None
+        if tracked:
+            flags = torch.from_numpy(seg_on.astype(np.uint8)).cuda()
+            flags[: begin // 16] = 1   # outside the range: must stay untouched
+            touch = fl.touch_desc(flags, begin, end)
+        fl.fhash_step(o, pd, gd, md, vd, shadow=sh, touch=touch)
+        assert (gd == 0).all()
+        if tracked:
+            fc = flags.cpu().numpy()
+            assert (fc[begin // 16:] == 0).all() and (fc[: begin // 16] == 1).all()
+        outs.append([x.cpu() for x in (pd, md, vd, sh)])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
 def test_check_finite_and_cast(fl):
     x = torch.randn(10007, device="cuda")
     flag = torch.zeros(1, dtype=torch.int32, device="cuda")

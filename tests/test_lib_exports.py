@@ -59,3 +59,21 @@ def test_version_and_host_validation():
     rc = L.fhash_mlp_bwd(ctypes.byref(m), None, None, None, None, 1 << 18, None, None, None,
                          ctypes.byref(nb), None)
     assert rc == fl.OK and nb.value > 0
+
+
+def test_touch_descriptor_validated_before_any_launch():
+    """fhash_step rejects a malformed touched-segment range on the host."""
+    L = fl.lib()
+    o = fl.AdamDesc()
+    o.lr, o.beta1, o.beta2, o.eps, o.step, o.grad_scale = 0.01, 0.9, 0.999, 1e-8, 1, 1.0
+    fake = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: validation fails first
+    flags = ctypes.c_void_p(1 << 21)
+    for begin, end, fl_ptr, why in ((8, 64, flags, b"touch range"),
+                                    (16, 1 << 30, flags, b"touch range"),
+                                    (32, 16, flags, b"touch range"),
+                                    (0, 64, None, b"NULL")):
+        t = fl.Touch()
+        t.flags, t.begin, t.end = fl_ptr, begin, end
+        rc = L.fhash_step(ctypes.byref(o), fake, fake, fake, fake, None, fl.F16, 1024, None,
+                          ctypes.byref(t), None)
+        assert rc == fl.EINVAL and why in L.fhash_last_error(), (begin, end)
