@@ -458,8 +458,8 @@ def serve_bench(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part "
-                          "of it (see DESIGN.md for how the path would shard)"}))
+        print(json.dumps({"error": "one GPU only: multi-GPU runs are not supported (the path "
+                          "would shard by slabs of the fine levels)"}))
         sys.exit(2)
     global torch
     import numpy as np
