@@ -425,7 +425,7 @@ def serve_bench(args):
         return {"all": latency_stats(done),
                 "render": latency_stats([r for r in done if r.kind == "render"]),
                 "points": latency_stats([r for r in done if r.kind == "points"]),
-                "iterations": sch.iterations}
+                "iterations": sch.iterations, "samples": sch.samples}
 
     n_mix = 4 * len(spec)
     mix_sat = serve_mixed([0.0] * n_mix, realtime=False)

@@ -52,7 +52,9 @@ enum {
 typedef enum { FHASH_F32 = 0, FHASH_F16 = 1, FHASH_BF16 = 2 } fhash_dtype;
 
 /* Level structure of the multi-resolution tesseract grid (Sec. 3.2.1-3.2.2).
- * res[l] = vertex counts (x, y, z, t) of level l, each in [2, 2^24].
+ * res[l] = vertex counts (x, y, z, t) of level l, each in [2, 2^24], with
+ * y * z * t * ceil(x / 64) < 2^31 per level (FHASH_ERANGE otherwise: the
+ * kernels index a level's vertex rows and directory words in 32 bits).
  * n_features = F, the embedding size of a vertex (Sec. 4.1): 1, 2, 4 or 8. */
 typedef struct {
   int32_t n_levels;

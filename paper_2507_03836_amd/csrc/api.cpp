@@ -47,6 +47,11 @@ int check_grid(const fhash_grid_desc* g) {
       nv *= r;
     }
     if (nv >= 4.0e18) return fail(FHASH_ERANGE, "level %d has too many vertices", l);
+    // the kernels index a level's vertex rows and directory words in 32 bits
+    const double words = (double)g->res[l][1] * g->res[l][2] * g->res[l][3] *
+                         (double)((g->res[l][0] + 63) / 64);
+    if (words >= 2147483648.0)
+      return fail(FHASH_ERANGE, "level %d has 2^31 directory words or more", l);
   }
   return FHASH_OK;
 }

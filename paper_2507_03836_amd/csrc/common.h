@@ -76,16 +76,18 @@ __device__ __forceinline__ void locate(float p, int R, float s, int& cell, float
 
 // Slots of the vertex pair (x, x+1) on one vertex row of a level.  Dense: the
 // F-Hash equation; active: rank in the directory entry of the word holding x.
+// The row (t, z, y) and the word within the level's directory are 32-bit: the
+// host rejects levels with 2^31 directory words or more.
 __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglong2* dir,
-                                               bool active, int64_t row, int x, int64_t& s0,
+                                               bool active, int32_t row, int x, int64_t& s0,
                                                int64_t& s1, bool& v0, bool& v1) {
   if (!active) {
-    s0 = d.slot_off + row * (int64_t)d.rx + x;
+    s0 = d.slot_off + (int64_t)row * d.rx + x;
     s1 = s0 + 1;
     v0 = v1 = true;
     return;
   }
-  const int64_t w = d.dir_off + row * (int64_t)d.wv + (x >> 6);
+  const int64_t w = d.dir_off + (int64_t)(row * d.wv + (x >> 6));
   const int b = x & 63;
   const ulonglong2 e = dir[w];
   const uint64_t below = (b == 0) ? 0ull : (e.x & ((1ull << b) - 1ull));

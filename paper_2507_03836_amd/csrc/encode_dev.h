@@ -98,7 +98,7 @@ __device__ __forceinline__ void encode_level(const LevelDev& d, const ulonglong2
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int64_t row = ((int64_t)(it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);
+    const int32_t row = ((it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);  // < 2^31 (host check)
     const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
     int64_t s0, s1;
     bool v0, v1;
@@ -138,7 +138,7 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int64_t row = ((int64_t)(it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);
+    const int32_t row = ((it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);  // < 2^31 (host check)
     const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
     int64_t s0, s1;
     bool v0, v1;
@@ -178,7 +178,7 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int64_t row = ((int64_t)(it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);
+    const int32_t row = ((it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);  // < 2^31 (host check)
     const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
     int64_t s0, s1;
     bool v0, v1;
@@ -213,7 +213,7 @@ __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulo
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int64_t row = ((int64_t)(it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);
+    const int32_t row = ((it + dt) * d.rz + (iz + dz)) * d.ry + (iy + dy);  // < 2^31 (host check)
     const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
     int64_t s2[2];
     bool v2[2];

@@ -111,7 +111,6 @@ struct MarchArgs {
   const uint64_t* occ;
   int64_t Sx, Sy, Sz;
   int64_t Wc;
-  float invx, invy, invz;  // unused (positions divide by S-1 exactly)
   float fx, fy, fz;        // (float)(S - 1)
   float tn;                // t / (T - 1)
   float ds;
@@ -119,23 +118,28 @@ struct MarchArgs {
   int32_t pace;
 };
 
+// Cell of a coordinate: floor clamped to [0, S-2].  Sample positions lie in
+// the volume box up to rounding, so the conversion stays in range.
+template <typename I>
+__device__ __forceinline__ I cell_of(float p, int64_t S) {
+  I i = (I)floorf(p);
+  i = i < 0 ? 0 : i;
+  return i > (I)(S - 2) ? (I)(S - 2) : i;
+}
+
+// Occupancy bit of the cell holding (px, py, pz).  I: index type of the bit
+// grid (32-bit whenever every word index fits, which the host checks).
+template <typename I>
 __device__ __forceinline__ bool occupied(const MarchArgs& a, float px, float py, float pz) {
-  int64_t c[3];
-  const float p[3] = {px, py, pz};
-  const int64_t S[3] = {a.Sx, a.Sy, a.Sz};
-  for (int d = 0; d < 3; ++d) {
-    int64_t i = (int64_t)floorf(p[d]);
-    i = i < 0 ? 0 : i;
-    i = i > S[d] - 2 ? S[d] - 2 : i;
-    c[d] = i;
-  }
-  const uint64_t wv = a.occ[(c[2] * (a.Sy - 1) + c[1]) * a.Wc + (c[0] >> 6)];
-  return (wv >> (c[0] & 63)) & 1ull;
+  const I cx = cell_of<I>(px, a.Sx), cy = cell_of<I>(py, a.Sy), cz = cell_of<I>(pz, a.Sz);
+  const I word = (cz * (I)(a.Sy - 1) + cy) * (I)a.Wc + (cx >> 6);
+  return (a.occ[word] >> (cx & 63)) & 1ull;
 }
 
 // Walk an alive ray's lattice from its cursor, emitting up to `pace` occupied
 // samples: pass 0 counts, a wave-wide reservation gives each ray a contiguous
 // output range, pass 1 writes the model inputs.
+template <typename I>
 __global__ void __launch_bounds__(256)
     march_kernel(MarchArgs a, Ray* __restrict__ rays, const int32_t* __restrict__ alive,
                  int32_t n_alive, float4* __restrict__ out, int32_t* __restrict__ counter) {
@@ -160,7 +164,7 @@ __global__ void __launch_bounds__(256)
       const float px = __fmaf_rn(sk, ray.dx, ray.ox);
       const float py = __fmaf_rn(sk, ray.dy, ray.oy);
       const float pz = __fmaf_rn(sk, ray.dz, ray.oz);
-      if (occupied(a, px, py, pz)) ++cnt;
+      if (occupied<I>(a, px, py, pz)) ++cnt;
       ++k;
     }
     k_end = k;
@@ -184,7 +188,7 @@ __global__ void __launch_bounds__(256)
     const float px = __fmaf_rn(sk, ray.dx, ray.ox);
     const float py = __fmaf_rn(sk, ray.dy, ray.oy);
     const float pz = __fmaf_rn(sk, ray.dz, ray.oz);
-    if (occupied(a, px, py, pz)) {
+    if (occupied<I>(a, px, py, pz)) {
       out[off + w] = make_float4(fdiv(px, a.fx), fdiv(py, a.fy), fdiv(pz, a.fz), a.tn);
       ++w;
     }
@@ -321,7 +325,6 @@ hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, floa
   a.Sy = dims[1];
   a.Sz = dims[2];
   a.Wc = (dims[0] - 1 + 63) / 64;
-  a.invx = a.invy = a.invz = 0.0f;
   a.fx = (float)(dims[0] - 1);
   a.fy = (float)(dims[1] - 1);
   a.fz = (float)(dims[2] - 1);
@@ -331,9 +334,15 @@ hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, floa
   a.pace = pace;
   hipError_t e = hipMemsetAsync(w.counters + 2, 0, 4, st);
   if (e != hipSuccess) return e;
-  if (n_alive > 0)
-    hipLaunchKernelGGL(march_kernel, dim3(blocks_exact(n_alive)), dim3(256), 0, st, a, w.rays,
-                       w.alive[cur], n_alive, reinterpret_cast<float4*>(pos_out), w.counters + 2);
+  if (n_alive > 0) {
+    float4* out = reinterpret_cast<float4*>(pos_out);
+    if ((dims[2] - 1) * (dims[1] - 1) * a.Wc < ((int64_t)1 << 31))
+      hipLaunchKernelGGL(march_kernel<int32_t>, dim3(blocks_exact(n_alive)), dim3(256), 0, st, a,
+                         w.rays, w.alive[cur], n_alive, out, w.counters + 2);
+    else
+      hipLaunchKernelGGL(march_kernel<int64_t>, dim3(blocks_exact(n_alive)), dim3(256), 0, st, a,
+                         w.rays, w.alive[cur], n_alive, out, w.counters + 2);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(n_samples_host, w.counters + 2, 4, hipMemcpyDeviceToHost, st);

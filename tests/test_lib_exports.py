@@ -77,3 +77,13 @@ def test_touch_descriptor_validated_before_any_launch():
         rc = L.fhash_step(ctypes.byref(o), fake, fake, fake, fake, None, fl.F16, 1024, None,
                           ctypes.byref(t), None)
         assert rc == fl.EINVAL and why in L.fhash_last_error(), (begin, end)
+
+
+def test_level_row_limit_reported_as_erange():
+    """A level whose vertex rows times directory words reach 2^31 is refused."""
+    L = fl.lib()
+    e = ctypes.c_int64()
+    g = fl.grid_desc([[64, 2048, 2048, 512]], 2)      # 2^31 rows x 1 word
+    assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.ERANGE
+    g = fl.grid_desc([[64, 2048, 2048, 511]], 2)      # just below
+    assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.OK
