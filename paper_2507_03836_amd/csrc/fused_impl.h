@@ -129,6 +129,10 @@ __global__ void __launch_bounds__(64 * kWaves) fused_kernel(GridDev g, FusedArgs
   if (MODE != MODE_FWD) gr.zero();
   double loss = 0.0;
   for (int64_t b = wave; b < nblk; b += nwav) {
+    // Keep the decoder weights in LDS rather than in registers across blocks:
+    // the compiler would otherwise hoist every layer's weight fragments out of
+    // this loop (64 registers per 64x64 layer) and cut the waves per SIMD.
+    __asm__ volatile("" ::: "memory");
     const int64_t smp = b * 16 + s;
     const bool valid = smp < A.n;
     const float4 p = valid ? A.pos[smp] : make_float4(0.f, 0.f, 0.f, 0.f);
