@@ -17,7 +17,9 @@ namespace fh {
 
 namespace fused_detail {
 
-constexpr int kWaves = 4;
+// Waves per workgroup: the forward keeps only the decoder weights in LDS, so
+// more waves share one copy; the backward modes also need per-wave tiles.
+constexpr int waves_per_block(int mode) { return mode == 0 ? 8 : 4; }
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2 };
 
 struct FusedArgs {
@@ -110,7 +112,9 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
 }
 
 template <int MODE, int F, typename T, int INP, int H, int NH>
-__global__ void __launch_bounds__(64 * kWaves) fused_kernel(GridDev g, FusedArgs A) {
+__global__ void __launch_bounds__(64 * waves_per_block(MODE)) fused_kernel(GridDev g,
+                                                                          FusedArgs A) {
+  constexpr int kWaves = waves_per_block(MODE);
   using S = MlpShape<INP, H, NH>;
   constexpr int WS = (MODE == MODE_FWD) ? 0 : mlp_wave_scratch<INP, H, NH>();
   __shared__ __attribute__((aligned(16))) float lds[S::WFLOATS + kWaves * WS + 1];
@@ -166,6 +170,7 @@ __global__ void __launch_bounds__(64 * kWaves) fused_kernel(GridDev g, FusedArgs
 }
 
 inline int64_t fused_waves(int64_t n, int mode) {
+  const int kWaves = waves_per_block(mode);
   int64_t nblk = (n + 15) / 16;
   int64_t cap = (mode == MODE_FWD) ? 8192 : 2048;
   int64_t w = nblk < cap ? nblk : cap;
@@ -175,6 +180,7 @@ inline int64_t fused_waves(int64_t n, int mode) {
 
 template <int MODE, int F, typename T, int INP, int H, int NH>
 hipError_t fused_t(const GridDev& g, FusedArgs A, float* d_params, hipStream_t st) {
+  constexpr int kWaves = waves_per_block(MODE);
   const int64_t nw = fused_waves(A.n, MODE);
   hipLaunchKernelGGL((fused_kernel<MODE, F, T, INP, H, NH>), dim3((unsigned)(nw / kWaves)),
                      dim3(64 * kWaves), 0, st, g, A);
