@@ -112,7 +112,8 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
 }
 
 template <int MODE, int F, typename T, int INP, int H, int NH>
-__global__ void __launch_bounds__(64 * waves_per_block(MODE)) fused_kernel(GridDev g,
+__global__ void __launch_bounds__(64 * waves_per_block(MODE))
+    __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 1 : 2))) fused_kernel(GridDev g,
                                                                           FusedArgs A) {
   constexpr int kWaves = waves_per_block(MODE);
   using S = MlpShape<INP, H, NH>;
