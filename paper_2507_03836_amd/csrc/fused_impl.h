@@ -111,10 +111,13 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
     }
 }
 
+// The backward modes hold the decoder's gradient accumulators in registers;
+// up to two hidden layers they fit the 256 registers of two waves per SIMD
+// (without the hint the compiler spends more and runs one wave per SIMD).
 template <int MODE, int F, typename T, int INP, int H, int NH>
 __global__ void __launch_bounds__(64 * waves_per_block(MODE))
-    __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 1 : 2))) fused_kernel(GridDev g,
-                                                                          FusedArgs A) {
+    __attribute__((amdgpu_waves_per_eu(MODE != 0 && NH <= 2 ? 2 : 1)))
+    fused_kernel(GridDev g, FusedArgs A) {
   constexpr int kWaves = waves_per_block(MODE);
   using S = MlpShape<INP, H, NH>;
   constexpr int WS = (MODE == MODE_FWD) ? 0 : mlp_wave_scratch<INP, H, NH>();

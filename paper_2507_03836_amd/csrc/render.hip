@@ -128,12 +128,19 @@ __device__ __forceinline__ I cell_of(float p, int64_t S) {
 }
 
 // Occupancy bit of the cell holding (px, py, pz).  I: index type of the bit
-// grid (32-bit whenever every word index fits, which the host checks).
+// grid (32-bit whenever every word index fits, which the host checks).  The
+// caller's one-word cache (w_idx, w_val) skips the load while consecutive
+// samples stay in the same 64-cell word (w_idx starts at -1).
 template <typename I>
-__device__ __forceinline__ bool occupied(const MarchArgs& a, float px, float py, float pz) {
+__device__ __forceinline__ bool occupied(const MarchArgs& a, float px, float py, float pz,
+                                         I& w_idx, uint64_t& w_val) {
   const I cx = cell_of<I>(px, a.Sx), cy = cell_of<I>(py, a.Sy), cz = cell_of<I>(pz, a.Sz);
   const I word = (cz * (I)(a.Sy - 1) + cy) * (I)a.Wc + (cx >> 6);
-  return (a.occ[word] >> (cx & 63)) & 1ull;
+  if (word != w_idx) {
+    w_idx = word;
+    w_val = a.occ[word];
+  }
+  return (w_val >> (cx & 63)) & 1ull;
 }
 
 // Walk an alive ray's lattice from its cursor, emitting up to `pace` occupied
@@ -148,6 +155,8 @@ __global__ void __launch_bounds__(256)
   Ray ray;
   int32_t k_end = 0, cnt = 0;
   bool exh = false;
+  I w_idx = -1;
+  uint64_t w_val = 0;
   if (act) {
     ray = rays[alive[i]];
     int32_t k = ray.k;
@@ -164,7 +173,7 @@ __global__ void __launch_bounds__(256)
       const float px = __fmaf_rn(sk, ray.dx, ray.ox);
       const float py = __fmaf_rn(sk, ray.dy, ray.oy);
       const float pz = __fmaf_rn(sk, ray.dz, ray.oz);
-      if (occupied<I>(a, px, py, pz)) ++cnt;
+      if (occupied<I>(a, px, py, pz, w_idx, w_val)) ++cnt;
       ++k;
     }
     k_end = k;
@@ -183,12 +192,13 @@ __global__ void __launch_bounds__(256)
   if (!act) return;
   const int32_t off = base + incl - cnt;
   int32_t k = ray.k, w = 0;
+  w_idx = -1;
   while (w < cnt) {
     const float sk = __fmaf_rn(fadd((float)k, 0.5f), a.ds, ray.s0);
     const float px = __fmaf_rn(sk, ray.dx, ray.ox);
     const float py = __fmaf_rn(sk, ray.dy, ray.oy);
     const float pz = __fmaf_rn(sk, ray.dz, ray.oz);
-    if (occupied<I>(a, px, py, pz)) {
+    if (occupied<I>(a, px, py, pz, w_idx, w_val)) {
       out[off + w] = make_float4(fdiv(px, a.fx), fdiv(py, a.fy), fdiv(pz, a.fz), a.tn);
       ++w;
     }
