@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--serve-sizes", type=str, default="256,512,1024")
     ap.add_argument("--serve-rates", type=str, default="0.25,0.5,0.9",
                     help="Poisson rates as fractions of the saturation request rate")
+    ap.add_argument("--serve-decoder", choices=["f32", "f16"], default="f32",
+                    help="decoder arithmetic of the served models (FP32 or FP16 MFMA)")
     ap.add_argument("--serve-multi", action="store_true",
                     help="multi-model serving: 6 resident models, mixed renders + point queries")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -206,7 +208,8 @@ def serve_multi_bench(args):
             table16 = torch.empty(model.n_table, dtype=torch.float16, device="cuda")
             fl.fhash_cast(model.table, table16)
             name = f"{'x'.join(map(str, dims))}/s{seed}"
-            models[name] = ResidentModel(index=model.index, mlp=model.mlp, table=table16,
+            mlp = fl.mlp_desc(cfg.width, fl.F16 if args.serve_decoder == "f16" else fl.F32)
+            models[name] = ResidentModel(index=model.index, mlp=mlp, table=table16,
                                          params=model.mlp_params.clone(), mask_bits=gen["bits"],
                                          dims=dims, tf=tf, keep=(model._dir,))
             info.append({"model": name, "params": model.n_params, "probe_psnr_db": psnr,
@@ -276,8 +279,8 @@ def serve_multi_bench(args):
     out = {
         "metric": "multi-model serving p50/p99 ms (renders and point queries), 0.5 x saturation",
         "value": sat["all"]["requests_per_s"], "unit": "requests/s at saturation", "n_gpus": 1,
-        "higher_is_better": True, "vs_baseline": None, "dtype": "f16 tables, f32 MLP",
-        "data": "synthetic",
+        "higher_is_better": True, "vs_baseline": None,
+        "dtype": f"f16 tables, {args.serve_decoder} MLP", "data": "synthetic",
         "config": {"workload": "6 resident models (480x720x120x100, 640x256x256x100, "
                    "432x432x432x60; 2 seeds each), 16 levels, MLP 32-64-64-64-1, FP16 tables; "
                    "1 in 4 requests a render, the rest 2^10-2^20 point queries",
@@ -341,7 +344,8 @@ def serve_bench(args):
     model.params = model.grads = model.m = model.v = None
     torch.cuda.empty_cache()
     tf = torch.from_numpy(synth.transfer_function()).cuda()
-    rm = ResidentModel(index=model.index, mlp=model.mlp, table=table16, params=params,
+    mlp = fl.mlp_desc(cfg.width, fl.F16 if args.serve_decoder == "f16" else fl.F32)
+    rm = ResidentModel(index=model.index, mlp=mlp, table=table16, params=params,
                        mask_bits=bits, dims=dims, tf=tf, keep=(model._dir,))
     C = 1 << 22
     sizes = [int(x) for x in args.serve_sizes.split(",")]
@@ -442,8 +446,8 @@ def serve_bench(args):
     out = {
         "metric": "render p50/p99 ms at 0.25/0.5/0.9 x saturation (Poisson), rays/s at saturation",
         "value": sat["rays_per_s"], "unit": "rays/s", "n_gpus": 1,
-        "higher_is_better": True, "vs_baseline": None, "dtype": "f16 tables, f32 MLP",
-        "data": "synthetic",
+        "higher_is_better": True, "vs_baseline": None,
+        "dtype": f"f16 tables, {args.serve_decoder} MLP", "data": "synthetic",
         "config": {"workload": f"render serving, {'x'.join(map(str, dims))} volume, 16 levels, "
                    "MLP 32-64-64-64-1, images {" + ",".join(f"{x}^2" for x in sizes) + "}",
                    "requests_per_rate": len(spec), "sample_budget": C,

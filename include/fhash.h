@@ -155,8 +155,11 @@ int fhash_encode_bwd(const fhash_index* idx, const float* pos, int64_t n, const 
  * width[0] = input (<= 64), n_layers-1 hidden layers of equal width H
  * (16, 32 or 64) with ReLU, and a linear output of width 1; biases on.
  * params: device float, packed per layer k as W_k[width[k+1]][width[k]]
- * row-major then b_k[width[k+1]].  compute_dt: FHASH_F32 (FP32 MFMA); other
- * values return FHASH_ENOTSUP.  `shadow` is reserved (pass NULL).
+ * row-major then b_k[width[k+1]].  compute_dt: FHASH_F32 (FP32 MFMA) for
+ * every call; FHASH_F16 (weights and hidden-layer inputs rounded to FP16 (RNE),
+ * FP16 MFMA with FP32 accumulation, FP32 biases and output layer) for the
+ * forward-only calls fhash_fused_fwd and fhash_render; other combinations
+ * return FHASH_ENOTSUP.  `shadow` is reserved (pass NULL).
  */
 typedef struct {
   int32_t n_layers;

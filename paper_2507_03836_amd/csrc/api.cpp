@@ -77,7 +77,8 @@ int check_table_dt(fhash_dtype dt) {
 }
 
 // Decoder shape: width[0] input, hidden widths all equal H, output width 1.
-int check_mlp(const fhash_mlp_desc* m, int* H, int* NH) {
+// allow_f16: the FP16-MFMA decoder is built for the forward-only calls.
+int check_mlp(const fhash_mlp_desc* m, int* H, int* NH, bool allow_f16 = false) {
   if (m == nullptr) return fail(FHASH_EINVAL, "mlp descriptor is NULL");
   if (m->n_layers < 2 || m->n_layers > FHASH_MAX_LAYERS)
     return fail(FHASH_EINVAL, "n_layers %d outside [2, %d]", m->n_layers, FHASH_MAX_LAYERS);
@@ -87,8 +88,9 @@ int check_mlp(const fhash_mlp_desc* m, int* H, int* NH) {
   const int h = m->width[1];
   for (int k = 1; k < m->n_layers; ++k)
     if (m->width[k] != h) return fail(FHASH_ENOTSUP, "hidden widths must be equal");
-  if (m->compute_dt != FHASH_F32)
-    return fail(FHASH_ENOTSUP, "mlp compute dtype %d not built", (int)m->compute_dt);
+  if (m->compute_dt != FHASH_F32 && !(allow_f16 && m->compute_dt == FHASH_F16))
+    return fail(FHASH_ENOTSUP, "mlp compute dtype %d not built for this call",
+                (int)m->compute_dt);
   if (!fh::mlp_supported(m->width[0], h, m->n_layers - 1))
     return fail(FHASH_ENOTSUP, "mlp shape in=%d hidden=%d x %d not built", m->width[0], h,
                 m->n_layers - 1);
@@ -309,10 +311,10 @@ static uint32_t dedup_mask(const fhash_index* idx, int64_t n, uint32_t flags) {
 
 static int check_fused(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
                        int64_t n, const void* table, fhash_dtype tdt, const float* params,
-                       int* H, int* NH) {
+                       int* H, int* NH, bool allow_f16 = false) {
   int rc = check_index(idx);
   if (rc) return rc;
-  if ((rc = check_mlp(mlp, H, NH))) return rc;
+  if ((rc = check_mlp(mlp, H, NH, allow_f16))) return rc;
   if ((rc = check_table_dt(tdt))) return rc;
   const int in_w = idx->grid.n_levels * idx->grid.n_features;
   if (mlp->width[0] != in_w)
@@ -334,15 +336,17 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
                     const void* shadow, float* y, void* stream) {
   (void)shadow;
   int H, NH;
-  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
+  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
   if (rc) return rc;
   if (n == 0) return FHASH_OK;
   if (y == nullptr) return fail(FHASH_EINVAL, "y is NULL");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
-  return hip_status(
-      fh::launch_fused_fwd(g, H, NH, pos, n, table, table_dt, params, y, S(stream)),
-      "fhash_fused_fwd");
+  const hipError_t e =
+      mlp->compute_dt == FHASH_F16
+          ? fh::launch_fused_fwd16(g, H, NH, pos, n, table, table_dt, params, y, S(stream))
+          : fh::launch_fused_fwd(g, H, NH, pos, n, table, table_dt, params, y, S(stream));
+  return hip_status(e, "fhash_fused_fwd");
 }
 
 int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
@@ -600,7 +604,8 @@ int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* 
   rc = ws_check(ws, ws_bytes, need, &query);
   if (rc || query) return rc;
   int H_, NH;
-  if ((rc = check_fused(idx, mlp, nullptr, 0, table, table_dt, params, &H_, &NH))) return rc;
+  if ((rc = check_fused(idx, mlp, nullptr, 0, table, table_dt, params, &H_, &NH, true)))
+    return rc;
   if (total_rows(idx) == 0) return fail(FHASH_EINVAL, "index has no active vertex");
   char* p = static_cast<char*>(ws);
   float* pos = reinterpret_cast<float*>(p + al(sbytes));
@@ -616,7 +621,10 @@ int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* 
     rc = fhash_render_march(&st, opts, pace, pos, NR, &ns, stream);
     if (rc) return rc;
     if (ns > 0) {
-      hipError_t e = fh::launch_fused_fwd(g, H_, NH, pos, ns, table, table_dt, params, y, S(stream));
+      hipError_t e =
+          mlp->compute_dt == FHASH_F16
+              ? fh::launch_fused_fwd16(g, H_, NH, pos, ns, table, table_dt, params, y, S(stream))
+              : fh::launch_fused_fwd(g, H_, NH, pos, ns, table, table_dt, params, y, S(stream));
       if (e != hipSuccess) return hip_status(e, "fhash_render decode");
     }
     rc = fhash_render_composite(&st, y, tf, opts, rgba, stream);

@@ -19,8 +19,10 @@ namespace fused_detail {
 
 // Waves per workgroup: the forward keeps only the decoder weights in LDS, so
 // more waves share one copy; the backward modes also need per-wave tiles.
-constexpr int waves_per_block(int mode) { return mode == 0 ? 8 : 4; }
-enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2 };
+// MODE_FWD16: the forward with the FP16-MFMA decoder (inference only).
+enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2, MODE_FWD16 = 3 };
+constexpr bool is_forward(int mode) { return mode == MODE_FWD || mode == MODE_FWD16; }
+constexpr int waves_per_block(int mode) { return is_forward(mode) ? 8 : 4; }
 
 struct FusedArgs {
   const float4* pos;
@@ -116,14 +118,20 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
 // (without the hint the compiler spends more and runs one wave per SIMD).
 template <int MODE, int F, typename T, int INP, int H, int NH>
 __global__ void __launch_bounds__(64 * waves_per_block(MODE))
-    __attribute__((amdgpu_waves_per_eu(MODE != 0 && NH <= 2 ? 2 : 1)))
+    __attribute__((amdgpu_waves_per_eu(!is_forward(MODE) && NH <= 2 ? 2 : 1)))
     fused_kernel(GridDev g, FusedArgs A) {
   constexpr int kWaves = waves_per_block(MODE);
+  constexpr bool FWD = is_forward(MODE);
   using S = MlpShape<INP, H, NH>;
-  constexpr int WS = (MODE == MODE_FWD) ? 0 : mlp_wave_scratch<INP, H, NH>();
-  __shared__ __attribute__((aligned(16))) float lds[S::WFLOATS + kWaves * WS + 1];
+  constexpr int WS = FWD ? 0 : mlp_wave_scratch<INP, H, NH>();
+  constexpr int LDSF = (MODE == MODE_FWD16) ? MlpShapeH<INP, H, NH>::TOTAL_FLOATS
+                                            : S::WFLOATS + kWaves * WS + 1;
+  __shared__ __attribute__((aligned(16))) float lds[LDSF];
   __shared__ LevelDev lv[FHASH_MAX_LEVELS];
-  load_weights_lds<INP, H, NH>(lds, A.params, A.in_w);
+  if constexpr (MODE == MODE_FWD16)
+    load_weights_lds_h<INP, H, NH>(lds, A.params, A.in_w);
+  else
+    load_weights_lds<INP, H, NH>(lds, A.params, A.in_w);
   for (int e = threadIdx.x; e < FHASH_MAX_LEVELS; e += blockDim.x) lv[e] = g.lv[e];
   __syncthreads();
   const T* table = reinterpret_cast<const T*>(A.table);
@@ -134,7 +142,7 @@ __global__ void __launch_bounds__(64 * waves_per_block(MODE))
   const int64_t nwav = (int64_t)gridDim.x * kWaves;
   const int64_t wave = (int64_t)blockIdx.x * kWaves + wib;
   MlpGrad<INP, H, NH> gr;
-  if (MODE != MODE_FWD) gr.zero();
+  if (!FWD) gr.zero();
   double loss = 0.0;
   for (int64_t b = wave; b < nblk; b += nwav) {
     // Keep the decoder weights in LDS rather than in registers across blocks:
@@ -146,10 +154,14 @@ __global__ void __launch_bounds__(64 * waves_per_block(MODE))
     const float4 p = valid ? A.pos[smp] : make_float4(0.f, 0.f, 0.f, 0.f);
     float xb[S::INB][4];
     gather_block<F, T, INP>(g, lv, p, valid, table, xb);
-    if (MODE != MODE_FWD) mlp_stage_input<INP, H, NH>(scratch, xb);
+    if (!FWD) mlp_stage_input<INP, H, NH>(scratch, xb);
     float hs[NH][S::HB][4];
-    const float yv = mlp_block_fwd<INP, H, NH>(lds, xb, hs);
-    if (MODE == MODE_FWD) {
+    float yv;
+    if constexpr (MODE == MODE_FWD16)
+      yv = mlp_block_fwd_h<INP, H, NH>(lds, xb);
+    else
+      yv = mlp_block_fwd<INP, H, NH>(lds, xb, hs);
+    if (FWD) {
       if (grp == 0 && valid) A.y[smp] = yv;
       continue;
     }
@@ -165,7 +177,7 @@ __global__ void __launch_bounds__(64 * waves_per_block(MODE))
     mlp_block_bwd<INP, H, NH>(lds, scratch, hs, dyv, gr, dxb);
     scatter_block<F, INP>(g, lv, p, valid, dxb, A.d_table);
   }
-  if (MODE == MODE_FWD) return;
+  if (FWD) return;
   mlp_write_partial<INP, H, NH>(gr, A.in_w, A.part + wave * A.P);
   if (MODE == MODE_TRAIN && A.loss_sum != nullptr) {
     for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
@@ -176,7 +188,7 @@ __global__ void __launch_bounds__(64 * waves_per_block(MODE))
 inline int64_t fused_waves(int64_t n, int mode) {
   const int kWaves = waves_per_block(mode);
   int64_t nblk = (n + 15) / 16;
-  int64_t cap = (mode == MODE_FWD) ? 8192 : 2048;
+  int64_t cap = is_forward(mode) ? 8192 : 2048;
   int64_t w = nblk < cap ? nblk : cap;
   w = ((w + kWaves - 1) / kWaves) * kWaves;
   return w < kWaves ? kWaves : w;
@@ -189,7 +201,7 @@ hipError_t fused_t(const GridDev& g, FusedArgs A, float* d_params, hipStream_t s
   hipLaunchKernelGGL((fused_kernel<MODE, F, T, INP, H, NH>), dim3((unsigned)(nw / kWaves)),
                      dim3(64 * kWaves), 0, st, g, A);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || MODE == MODE_FWD) return e;
+  if (e != hipSuccess || is_forward(MODE)) return e;
   return launch_reduce_partials(A.part, nw, A.P, d_params, st);
 }
 

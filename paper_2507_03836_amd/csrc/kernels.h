@@ -36,6 +36,10 @@ size_t fused_ws_bytes(int64_t n, int64_t P);
 hipError_t launch_fused_fwd(const GridDev& g, int H, int NH, const float* pos, int64_t n,
                             const void* table, fhash_dtype tdt, const float* params, float* y,
                             hipStream_t st);
+// fused_fwd16.hip: the same forward with the FP16-MFMA decoder
+hipError_t launch_fused_fwd16(const GridDev& g, int H, int NH, const float* pos, int64_t n,
+                              const void* table, fhash_dtype tdt, const float* params, float* y,
+                              hipStream_t st);
 hipError_t launch_fused_bwd(const GridDev& g, int H, int NH, const float* pos, int64_t n,
                             const void* table, fhash_dtype tdt, const float* params,
                             const float* dy, float* d_table, float* d_params, void* ws, int64_t P,

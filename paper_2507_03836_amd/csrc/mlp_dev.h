@@ -218,6 +218,122 @@ __device__ __forceinline__ float mlp_block_fwd(const float* lds, const float (&x
   return sum_groups(y) + lds[S::BOUT];
 }
 
+// ---------------------------------------------------------------------------
+// FP16 decoder for inference (v_mfma_f32_16x16x16_f16, FP32 accumulation).
+// Same register layout as the FP32 engine: the accumulator of a layer holds,
+// in lane 16 g + s, features 16 a + 4 g + i of sample s, and those 4 values
+// rounded to FP16 are exactly the B operand of a 16-deep K block of the next
+// layer (B lane (g, s) supplies k = 4 g + i); the A operand of that block is
+// the 4 consecutive FP16 weights W[16 ob + m][16 a + 4 g .. + 3] (one 8-byte
+// LDS read).  One instruction covers what four FP32 16x16x4 steps did.
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4v mfma16h(h4v a, h4v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// LDS image of the FP16 decoder: FP32 biases and output layer first, then the
+// FP16 weight matrices (rows padded by 8 halves against bank conflicts).
+template <int INP, int H, int NH>
+struct MlpShapeH {
+  static constexpr int INB = INP / 16;
+  static constexpr int HB = H / 16;
+  // float part
+  static constexpr int B0 = 0;                      // b_0 [H]
+  static constexpr int BK = B0 + H;                 // b_k [NH-1][H]
+  static constexpr int WOUT = BK + (NH - 1) * H;    // output weights [H]
+  static constexpr int BOUT = WOUT + H;             // output bias
+  static constexpr int FLOATS = (BOUT + 1 + 3) / 4 * 4;
+  // half part (offsets in halves, from the end of the float part)
+  static constexpr int LD0 = INP + 8;
+  static constexpr int LDH = H + 8;
+  static constexpr int W0 = 0;
+  static constexpr int WK = W0 + H * LD0;
+  static constexpr int HALVES = WK + (NH - 1) * H * LDH;
+  static constexpr int TOTAL_FLOATS = FLOATS + (HALVES + 1) / 2 + 4;
+};
+
+// Round the packed FP32 parameters into the FP16 LDS image (RNE; W0 columns
+// beyond in_w are zero).  Whole workgroup; caller syncs.
+template <int INP, int H, int NH>
+__device__ void load_weights_lds_h(float* lds, const float* __restrict__ params, int in_w) {
+  using S = MlpShapeH<INP, H, NH>;
+  _Float16* wh = reinterpret_cast<_Float16*>(lds + S::FLOATS);
+  for (int e = threadIdx.x; e < H * INP; e += blockDim.x) {
+    const int o = e / INP, i = e % INP;
+    wh[S::W0 + o * S::LD0 + i] = (_Float16)((i < in_w) ? params[o * in_w + i] : 0.0f);
+  }
+  const float* p = params + H * in_w;
+  for (int e = threadIdx.x; e < H; e += blockDim.x) lds[S::B0 + e] = p[e];
+  p += H;
+  for (int k = 1; k < NH; ++k) {
+    _Float16* wk = wh + S::WK + (k - 1) * H * S::LDH;
+    for (int e = threadIdx.x; e < H * H; e += blockDim.x)
+      wk[(e / H) * S::LDH + e % H] = (_Float16)p[e];
+    p += H * H;
+    for (int e = threadIdx.x; e < H; e += blockDim.x) lds[S::BK + (k - 1) * H + e] = p[e];
+    p += H;
+  }
+  for (int e = threadIdx.x; e < H; e += blockDim.x) lds[S::WOUT + e] = p[e];
+  if (threadIdx.x == 0) lds[S::BOUT] = p[H];
+}
+
+// out = act(W in + b) with FP16 operands and FP32 accumulation.
+template <int INB, int HB>
+__device__ __forceinline__ void fwd_layer_h(const _Float16* W, int ld, const float* b,
+                                            const float (&in)[INB][4], float (&out)[HB][4],
+                                            bool relu) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
+  h4v bin[INB];
+#pragma unroll
+  for (int a = 0; a < INB; ++a)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bin[a][i] = (_Float16)in[a][i];
+  f4v c[HB];
+#pragma unroll
+  for (int ob = 0; ob < HB; ++ob)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[ob][i] = b[16 * ob + 4 * g + i];
+#pragma unroll
+  for (int a = 0; a < INB; ++a)
+#pragma unroll
+    for (int ob = 0; ob < HB; ++ob) {
+      const h4v w = *reinterpret_cast<const h4v*>(W + (16 * ob + m) * ld + 16 * a + 4 * g);
+      c[ob] = mfma16h(w, bin[a], c[ob]);
+    }
+#pragma unroll
+  for (int ob = 0; ob < HB; ++ob)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[ob][i] = relu ? fmaxf(c[ob][i], 0.0f) : c[ob][i];
+}
+
+// Forward of one 16-sample block through the FP16 decoder; the output layer
+// (a dot product of width H) runs in FP32 on the FP32 hidden activations.
+template <int INP, int H, int NH>
+__device__ __forceinline__ float mlp_block_fwd_h(const float* lds, const float (&xb)[INP / 16][4]) {
+  using S = MlpShapeH<INP, H, NH>;
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const _Float16* wh = reinterpret_cast<const _Float16*>(lds + S::FLOATS);
+  float h[S::HB][4];
+  fwd_layer_h<S::INB, S::HB>(wh + S::W0, S::LD0, lds + S::B0, xb, h, true);
+#pragma unroll
+  for (int k = 1; k < NH; ++k) {
+    float h2[S::HB][4];
+    fwd_layer_h<S::HB, S::HB>(wh + S::WK + (k - 1) * H * S::LDH, S::LDH, lds + S::BK + (k - 1) * H,
+                              h, h2, true);
+#pragma unroll
+    for (int a = 0; a < S::HB; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[a][i] = h2[a][i];
+  }
+  float y = 0.0f;
+#pragma unroll
+  for (int a = 0; a < S::HB; ++a)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y += lds[S::WOUT + 16 * a + 4 * g + i] * h[a][i];
+  return sum_groups(y) + lds[S::BOUT];
+}
+
 // Backward of one block given dy (per sample column, 0 for padding samples),
 // the block input xb (B layout), its transposed copy in xtile (per-wave LDS,
 // [INP][17], written by the caller) and the hidden activations.  Accumulates

@@ -163,3 +163,53 @@ def test_mixed_error_against_fp64_probe(fl):
     rel = float(np.abs(ym - y64[:, 0]).max() / np.abs(y64[:, 0]).max())
     print(f"\nmixed vs FP64: enc max abs err {err_e.max():.3e}, y max abs err {err_m.max():.3e} "
           f"(rel to max|y| {rel:.3e}); FP32 y max abs err {err_f.max():.3e}")
+
+
+@pytest.mark.parametrize("width", [[8, 32, 32, 1], [8, 64, 64, 64, 1]])
+def test_fp16_decoder_forward_within_rounding_bound(fl, width):
+    """Forward with the FP16-MFMA decoder (compute_dt FHASH_F16) against the FP64
+    oracle: the error stays inside the bound built layer by layer from binary16
+    rounding of every weight and hidden-layer input (relative 2^-11, absolute
+    2^-25 below the normal range), FP32 accumulation and the 1-Lipschitz ReLU."""
+    f, mask = synth.tiny_volume()
+    g = O.Grid(np.array(TINY_RES), 2, mask)
+    rng = np.random.default_rng(41)
+    table = rng.uniform(-1, 1, (g.total_slots, 2)).astype(np.float32)
+    params = synth.mlp_init(width, seed=42)
+    bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
+    idx, _, dir_t, _ = fl.fhash_build_index(fl.grid_desc(TINY_RES, 2), bits, _dims(mask))
+    n = 1 << 14
+    pos = synth.probe_points(n, 4003).astype(np.float32)
+    pd = torch.from_numpy(pos).cuda()
+    tab_d, prm_d = torch.from_numpy(table).cuda(), torch.from_numpy(params).cuda()
+    y16 = torch.empty(n, device="cuda")
+    y32 = torch.empty(n, device="cuda")
+    fl.fhash_fused_fwd(idx, fl.mlp_desc(width, fl.F16), pd, n, tab_d, prm_d, y16)
+    fl.fhash_fused_fwd(idx, fl.mlp_desc(width), pd, n, tab_d, prm_d, y32)
+    enc, emag = O.encode_fwd(g, pos, table.astype(np.float64))
+    y64, _, ymag = O.mlp_fwd(width, params.astype(np.float64), enc, x_mag=emag)
+    # error bound (test-side arithmetic on magnitudes only)
+    e = RTOL * emag + ATOL            # encoding (FP32)
+    m = np.abs(enc) + e               # |h_0| bound
+    off = 0
+    for k in range(len(width) - 1):
+        W = params[off: off + width[k + 1] * width[k]].astype(np.float64).reshape(width[k + 1],
+                                                                                 width[k])
+        b = params[off + width[k + 1] * width[k]: off + width[k + 1] * (width[k] + 1)]
+        off += width[k + 1] * (width[k] + 1)
+        aW, ab = np.abs(W), np.abs(b.astype(np.float64))
+        mag_next = m @ aW.T + ab
+        if k < len(width) - 2:        # FP16 layer: inputs and weights rounded
+            e = (e * (1 + 2 * U16) + 2 * U16 * m + 2.0 ** -25) @ aW.T + \
+                2.0 ** -25 * m.sum(axis=1, keepdims=True) + RTOL * mag_next
+        else:                         # FP32 output layer
+            e = e @ aW.T + RTOL * mag_next
+        m = mag_next + e
+    got = y16.cpu().numpy().astype(np.float64)
+    err = np.abs(got - y64[:, 0])
+    assert (err <= e[:, 0] + ATOL).all(), float((err - e[:, 0]).max())
+    # the FP16 path really ran: it differs from the FP32 decoder somewhere
+    assert not torch.equal(y16, y32)
+    rel = float(err.max() / np.abs(y64[:, 0]).max())
+    print(f"\nFP16 decoder {width}: max abs err {err.max():.3e} (rel to max|y| {rel:.3e}), "
+          f"bound median {np.median(e):.3e}")

@@ -1,7 +1,8 @@
 """Continuous-batching server on the device: every result of a mixed stream
-(two resident models, one with FP16 tables; renders of uneven sizes and
-times; point-query batches) equals, bit for bit, the same request served
-alone through the plain entry points (fhash_render, fhash_fused_fwd)."""
+(three resident models: FP32, FP16 tables, FP16 tables with the FP16 decoder;
+renders of uneven sizes and times; point-query batches) equals, bit for bit,
+the same request served alone through the plain entry points (fhash_render,
+fhash_fused_fwd)."""
 import numpy as np
 import pytest
 import torch
@@ -30,12 +31,15 @@ def server_models():
     width = [8, 32, 32, 1]
     tf = torch.from_numpy(synth.transfer_function()).cuda()
     models = {}
-    for k, (seed, dt) in enumerate([(11, torch.float32), (12, torch.float16)]):
+    for k, (seed, dt, mdt) in enumerate([(11, torch.float32, fl.F32),
+                                         (12, torch.float16, fl.F32),
+                                         (13, torch.float16, fl.F16)]):
         rng = np.random.default_rng(seed)
         table = torch.from_numpy(rng.uniform(-1, 1, (rows, 2)).astype(np.float32)).cuda()
         params = synth.mlp_init(width, seed=seed)
         params[-1] = 0.5
-        models[f"m{k}"] = ResidentModel(index=idx, mlp=fl.mlp_desc(width), table=table.to(dt),
+        models[f"m{k}"] = ResidentModel(index=idx, mlp=fl.mlp_desc(width, mdt),
+                                        table=table.to(dt),
                                         params=torch.from_numpy(params).cuda(), mask_bits=bits,
                                         dims=dims, tf=tf, keep=(dir_t,))
     return fl, models, dims
@@ -46,7 +50,7 @@ def _requests(dims, rng):
     reqs = []
     sizes = [(40, 32), (17, 23), (64, 48), (8, 8), (33, 1)]
     for j in range(14):
-        m = f"m{j % 2}"
+        m = f"m{j % 3}"
         if j % 3 != 2:
             W, H = sizes[j % len(sizes)]
             view = synth.orbit_view(dims, rng.uniform(0, 2 * np.pi), rng.uniform(-1, 1), W, H)
