@@ -100,6 +100,12 @@ const char* fhash_last_error(void);
  * is the F-Hash equation itself.  Level l owns rows
  * [slot_offset[l], slot_offset[l+1]) of every table.
  *
+ * Directory of an active index (per level, from dir_offset[l]): one 16-byte
+ * entry {uint64 bits, uint64 rank} per 64-vertex word w of every vertex row
+ * (t, z, y): bit b of `bits` is vertex x = 64 w + b, `rank` the number of
+ * active vertices before that word in F-Hash order; the entry sits at
+ * ((t*Rz + z)*ceil(Rx/64) + w)*Ry + y, so rows y and y+1 are neighbours.
+ *
  * fhash_index_dir_entries: number of 16-byte directory entries the grid needs
  * (0 for a dense index is not implied: the size is for the active form).
  * fhash_build_index: fills dir (device, dir_entries*16 bytes, caller-owned)

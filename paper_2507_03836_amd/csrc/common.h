@@ -74,20 +74,21 @@ __device__ __forceinline__ void locate(float p, int R, float s, int& cell, float
   frac = __fsub_rn(u, (float)i);
 }
 
-// Slots of the vertex pair (x, x+1) on one vertex row of a level.  Dense: the
-// F-Hash equation; active: rank in the directory entry of the word holding x.
-// The row (t, z, y) and the word within the level's directory are 32-bit: the
-// host rejects levels with 2^31 directory words or more.
+// Slots of the vertex pair (x, x+1) on vertex row (tz = t*Rz + z, y) of a
+// level.  Dense: the F-Hash equation; active: rank in the directory entry of
+// the word holding x.  Directory entries are stored ((tz*Wv + word)*Ry + y)
+// (rows y and y+1 of a cell are neighbours); the row and word indices are
+// 32-bit: the host rejects levels with 2^31 directory words or more.
 __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglong2* dir,
-                                               bool active, int32_t row, int x, int64_t& s0,
-                                               int64_t& s1, bool& v0, bool& v1) {
+                                               bool active, int32_t tz, int32_t y, int x,
+                                               int64_t& s0, int64_t& s1, bool& v0, bool& v1) {
   if (!active) {
-    s0 = d.slot_off + (int64_t)row * d.rx + x;
+    s0 = d.slot_off + ((int64_t)tz * d.ry + y) * d.rx + x;
     s1 = s0 + 1;
     v0 = v1 = true;
     return;
   }
-  const int64_t w = d.dir_off + (int64_t)(row * d.wv + (x >> 6));
+  const int64_t w = d.dir_off + (int64_t)((tz * d.wv + (x >> 6)) * d.ry + y);
   const int b = x & 63;
   const ulonglong2 e = dir[w];
   const uint64_t below = (b == 0) ? 0ull : (e.x & ((1ull << b) - 1ull));
@@ -97,7 +98,7 @@ __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglon
     v1 = (e.x >> (b + 1)) & 1ull;
     s1 = s0 + (v0 ? 1 : 0);
   } else {
-    const ulonglong2 e1 = dir[w + 1];
+    const ulonglong2 e1 = dir[w + d.ry];  // next word of the same row
     v1 = e1.x & 1ull;
     s1 = d.slot_off + (int64_t)e1.y;
   }

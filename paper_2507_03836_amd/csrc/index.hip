@@ -111,6 +111,22 @@ __global__ void vert_x_kernel(const uint64_t* __restrict__ in, ulonglong2* __res
   }
 }
 
+// Store order of the directory: the entries of one x word for all y of a
+// (t, z) row block are adjacent, index ((t*Rz + z)*Wv + w)*Ry + y, so the
+// y and y+1 rows of a cell read neighbouring 16-byte entries (one line).
+// Ranks are computed in F-Hash order first (row-major, src) and then moved.
+__global__ void dir_interleave_kernel(const ulonglong2* __restrict__ src,
+                                      ulonglong2* __restrict__ dst, int64_t rows, int64_t ry,
+                                      int64_t wv) {
+  const int64_t total = rows * wv;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = e % wv, row = e / wv;
+    const int64_t tz = row / ry, y = row % ry;
+    dst[(tz * wv + w) * ry + y] = src[e];
+  }
+}
+
 constexpr int kScanThreads = 256;
 constexpr int kScanPerThread = 8;
 constexpr int64_t kScanBlockWords = kScanThreads * kScanPerThread;
@@ -247,7 +263,10 @@ size_t index_workspace_bytes(const fhash_grid_desc* g, const int64_t* dims) {
     b1 = std::max(b1, std::max(std::max(s.B, s.cell), s.D2));
     nb = std::max(nb, s.nb);
   }
-  return align256(b0 * 8) + align256(b1 * 8) + align256(nb * 8) + align256(8 * FHASH_MAX_LEVELS);
+  int64_t words = 1;
+  for (int l = 0; l < g->n_levels; ++l) words = std::max(words, level_sizes(g->res[l], dims).words);
+  return align256(b0 * 8) + align256(b1 * 8) + align256(nb * 8) + align256(8 * FHASH_MAX_LEVELS) +
+         align256(words * 16);
 }
 
 hipError_t launch_build_index(const fhash_grid_desc* g, const uint64_t* mask,
@@ -268,6 +287,8 @@ hipError_t launch_build_index(const fhash_grid_desc* g, const uint64_t* mask,
   uint64_t* partial = reinterpret_cast<uint64_t*>(p);
   p += align256(nbmax * 8);
   uint64_t* counts = reinterpret_cast<uint64_t*>(p);
+  p += align256(8 * FHASH_MAX_LEVELS);
+  ulonglong2* rowmajor = reinterpret_cast<ulonglong2*>(p);  // one level's directory, F-Hash order
 
   const int T = 256;
   const int64_t Sx = dims[0], Sy = dims[1], Sz = dims[2], St = dims[3];
@@ -290,7 +311,7 @@ hipError_t launch_build_index(const fhash_grid_desc* g, const uint64_t* mask,
                        (int64_t)r[3], s.Cz, s.Cy * s.Wc);
     hipLaunchKernelGGL(dilate_axis_kernel, dim3(grid_for(s.D3, T)), dim3(T), 0, st, buf1, buf0,
                        (int64_t)r[3] * r[2], s.Cy, s.Wc);
-    ulonglong2* d = dir + dir_off[l];
+    ulonglong2* d = rowmajor;
     hipLaunchKernelGGL(vert_x_kernel, dim3(grid_for(s.words, T)), dim3(T), 0, st, buf0, d,
                        (int64_t)r[3] * r[2] * r[1], s.Wc, s.Wv);
     // Ranks: exclusive prefix sum of popcounts.
@@ -300,6 +321,8 @@ hipError_t launch_build_index(const fhash_grid_desc* g, const uint64_t* mask,
                        counts + l);
     hipLaunchKernelGGL(write_ranks_kernel, dim3((unsigned)s.nb), dim3(kScanThreads), 0, st, d,
                        s.words, partial);
+    hipLaunchKernelGGL(dir_interleave_kernel, dim3(grid_for(s.words, T)), dim3(T), 0, st, d,
+                       dir + dir_off[l], (int64_t)r[3] * r[2] * r[1], (int64_t)r[1], s.Wv);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -54,10 +54,13 @@ def test_directory_is_exact_prefix_sum(prod):
     idx, dir_t, res, counts = prod["idx"], prod["dir"], prod["res"], prod["counts"]
     for l, (Rx, Ry, Rz, Rt) in enumerate(res):
         lo, hi = int(idx.dir_offset[l]), int(idx.dir_offset[l + 1])
+        Wv = (Rx + 63) // 64
+        # stored ((t*Rz + z)*Wv + word)*Ry + y; ranks follow row-major (t, z, y, word)
+        rm = dir_t[lo:hi].view(Rt * Rz, Wv, Ry, 2).permute(0, 2, 1, 3).reshape(-1, 2)
         run = 0
-        for s in range(lo, hi, 1 << 24):
-            e = min(s + (1 << 24), hi)
-            ent = dir_t[s:e]
+        for s in range(0, hi - lo, 1 << 24):
+            e = min(s + (1 << 24), hi - lo)
+            ent = rm[s:e]
             pc = _popcount64(ent[:, 0])
             rank = ent[:, 1]
             assert int(rank[0]) == run
@@ -67,11 +70,15 @@ def test_directory_is_exact_prefix_sum(prod):
         assert int(idx.slot_offset[l + 1] - idx.slot_offset[l]) == counts[l]
 
 
-def _vertex_bit(dir_np_level, res, v):
+def _entry(res, v):
+    """Directory entry of vertex v = (x, y, z, t): ((t*Rz + z)*Wv + x//64)*Ry + y."""
     Rx, Ry, Rz, Rt = res
     Wv = (Rx + 63) // 64
-    row = (v[3] * Rz + v[2]) * Ry + v[1]
-    word = int(dir_np_level[row * Wv + v[0] // 64, 0])
+    return ((v[3] * Rz + v[2]) * Wv + v[0] // 64) * Ry + v[1]
+
+
+def _vertex_bit(dir_np_level, res, v):
+    word = int(dir_np_level[_entry(res, v), 0])
     return (word >> (v[0] % 64)) & 1
 
 
@@ -129,8 +136,7 @@ def test_fused_forward_sampled_against_oracle(prod):
                     enc_mag[s, 2 * l] += w[s, l, c] * abs(hv)
                     enc_mag[s, 2 * l + 1] += w[s, l, c] * abs(0.5 - hv)
                     # the test (not the oracle) places h at the vertex's slot
-                    row = (v[3] * Rz + v[2]) * Ry + v[1]
-                    ent = dl[row * Wv + v[0] // 64]
+                    ent = dl[_entry(r, v)]
                     below = int(ent[0]) & ((1 << (v[0] % 64)) - 1)
                     slot = int(idx.slot_offset[l]) + int(ent[1]) + bin(below).count("1")
                     slot_list.append(slot)

@@ -66,13 +66,16 @@ def _build(fl, res, F, mask):
 
 
 def _decode_dir(idx, dir_t, res):
-    """Vertex -> slot maps from the directory (row-padded bitmap + rank words)."""
+    """Vertex -> slot maps from the directory (row-padded bitmap + rank words,
+    entries of one x word adjacent over y)."""
     d = dir_t.cpu().numpy().view(np.uint64)
     maps = []
     for l, (Rx, Ry, Rz, Rt) in enumerate(res):
         Wv = (Rx + 63) // 64
         off = int(idx.dir_offset[l])
-        ent = d[off: off + Rt * Rz * Ry * Wv].reshape(Rt * Rz * Ry, Wv, 2)
+        # stored ((t*Rz + z)*Wv + word)*Ry + y: bring it to row-major (t, z, y), word
+        ent = d[off: off + Rt * Rz * Ry * Wv].reshape(Rt * Rz, Wv, Ry, 2)
+        ent = ent.transpose(0, 2, 1, 3).reshape(Rt * Rz * Ry, Wv, 2)
         bits, rank = ent[..., 0], ent[..., 1]
         x = np.arange(Rx)
         w, b = x // 64, (x % 64).astype(np.uint64)
