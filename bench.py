@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--cpu-samples", type=int, default=1 << 12)
     ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32",
                     help="mixed: FP16 table reads (Adam-written shadow) + dynamic loss scaling")
+    ap.add_argument("--optimizer", choices=["lazy", "tracked", "dense"], default="tracked",
+                    help="Adam over the large levels: deferred (same values, bit for bit), "
+                         "dense with touched-segment gradient reads, or plain dense")
     ap.add_argument("--hidden-layers", type=int, default=2)
     ap.add_argument("--sort", action="store_true",
                     help="sort each batch by a 4D Morton key before the fused step")
@@ -489,7 +492,9 @@ def main():
     cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers)
     t0 = time.time()
     model = FHashModel(cfg, gen["bits"], dims, init_seed=3000 + args.field_seed - 1000,
-                       precision=args.precision)
+                       precision=args.precision, track_touched=args.optimizer == "tracked",
+                       lazy=args.optimizer == "lazy",
+                       max_steps=max(args.max_steps, args.warmup + args.steps) + 64)
     torch.cuda.synchronize()
     dense = sum(int(np.prod(r)) for r in res)
     log(f"[bench] index built in {time.time() - t0:.1f} s: {model.rows} active vertices of "
@@ -516,26 +521,36 @@ def main():
             sort_ws[0] = fl.fhash_sort_samples(pos, tgt, B, sort_ws[0])
         if ev is not None:
             ev[0].record(stream)
-        model.fwd_bwd(pos, tgt, sorted_batch=args.sort)
+        model.prepare(pos)
         if ev is not None:
             ev[1].record(stream)
-        model.optimizer_step()
+        model.fwd_bwd(pos, tgt, sorted_batch=args.sort, prepared=True)
         if ev is not None:
             ev[2].record(stream)
+        model.optimizer_step()
+        if ev is not None:
+            ev[3].record(stream)
 
     t_train0 = time.perf_counter()
     for k in range(args.warmup):
         step(k + 1)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    fev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(args.warmup + k + 1, evs[k])
+    # deferred Adam: the timed work ends with every parameter up to date
+    fev[0].record(stream)
+    model.flush()
+    fev[1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    fb_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    adam_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    prep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    fb_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    adam_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    flush_ms = fev[0].elapsed_time(fev[1])
     loss = model.loss_sum.item() / (B * (args.warmup + args.steps))
     ms = wall * 1e3 / args.steps
     mixed = args.precision == "mixed"
@@ -563,8 +578,8 @@ def main():
     traffic = ADAM_TRAFFIC["bytes"] if (same_src and not mixed and model.touch is not None and
                                         not args.sort and
                                         model.n_params == ADAM_TRAFFIC["params"]) else None
-    log(f"[bench] step {ms:.3f} ms: fused fwd+bwd {fb_ms:.3f} ms, adam {adam_ms:.3f} ms; "
-        f"mean loss {loss:.4g}")
+    log(f"[bench] step {ms:.3f} ms: prepare {prep_ms:.3f} ms, fused fwd+bwd {fb_ms:.3f} ms, "
+        f"adam {adam_ms:.3f} ms, final flush {flush_ms:.3f} ms; mean loss {loss:.4g}")
     out = {
         "metric": ("train samples/s fwd+bwd (" + ("FP16 table reads, FP32 master"
                                                   if mixed else "FP32 path")
@@ -588,9 +603,11 @@ def main():
                    "shape": dims, "levels": args.levels, "batch": B,
                    "active_vertices": model.rows, "params": model.n_params,
                    "coreset": M},
-        "breakdown_ms": {"fused_fwd_bwd": fb_ms, "adam": adam_ms,
+        "breakdown_ms": {"lazy_prepare": prep_ms, "fused_fwd_bwd": fb_ms, "adam": adam_ms,
+                         "final_flush_per_step": flush_ms / args.steps,
                          ("sampler_sort_and_other" if args.sort else "sampler_and_other"):
-                         ms - fb_ms - adam_ms},
+                         ms - fb_ms - adam_ms - prep_ms - flush_ms / args.steps},
+        "optimizer": args.optimizer,
         "roofline": {"kernel": "adam_kernel", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": adam_bytes,

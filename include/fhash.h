@@ -219,7 +219,9 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
  * Adam (Sec. 5.1.3: Adam, lr 0.01; PyTorch semantics, bias-corrected, no
  * weight decay), applied densely to every parameter:
  *   g = grad * grad_scale;  m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
- *   p -= (lr / (1 - b1^step)) * m / (sqrt(v) / sqrt(1 - b2^step) + eps).
+ *   p -= (lr / (1 - b1^step)) * m / (sqrt(v) / sqrt(1 - b2^step) + eps)
+ * in FP32, the square root and the reciprocal of the denominator from the
+ * hardware (within 1 ulp each).
  * grad is zeroed.  If found_inf (device int32, may be NULL) is non-zero the
  * whole update is skipped (grad is still zeroed).  shadow (device, may be
  * NULL) receives p rounded to shadow_dt (FHASH_F16 or FHASH_BF16, RNE).
@@ -237,6 +239,77 @@ typedef struct {
 int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
                void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
                const fhash_touch* touch, void* stream);
+
+/* ------------------------------------------------ deferred (lazy) Adam ----
+ * An optimisation of the memory traffic of the dense update above, not part
+ * of the method.  On a float range [begin, end) of the parameter vector (the
+ * large table levels; the table starts at float 0 of the vector) no step is
+ * applied when it happens.  Every segment of FHASH_LAZY_FLOATS floats records
+ * the last step it has received and the step it was last enrolled in, the
+ * constants of every step are kept, and the steps a segment missed are
+ * replayed with the dense update's own per-parameter arithmetic the next time
+ * the segment is prepared, or by fhash_lazy_flush: the step it was enrolled in
+ * with its gradient (which is then zeroed), all others with a zero gradient
+ * (there its gradient was zero).  A value read after its segment was
+ * prepared, or after a flush, equals bit for bit what fhash_step applied to
+ * every parameter at every step would hold there.  (A parameter with m and v
+ * both +0 and no pending gradient is a fixed point of such a replay.)
+ *
+ * Per step: fhash_lazy_prepare with the positions of every sample whose
+ * encoding or encoding gradient the step computes (any number of calls), then
+ * those calls, then fhash_step_lazy.  Before the whole table is read (render,
+ * checkpoint, export) or the table gradient is inspected, fhash_lazy_flush.
+ * Reading a segment of the range that was not prepared gives a stale value;
+ * between a step and the segment's next prepare or flush, the gradient of an
+ * enrolled segment still holds that step's (unapplied) gradient.
+ *
+ * ws: device memory of fhash_lazy_workspace_bytes(end - begin, max_steps)
+ * bytes, 16-byte aligned, caller-owned (8 bytes of state and 8 of list per
+ * segment, 16 bytes of constants per step).  begin: a multiple of
+ * FHASH_LAZY_FLOATS; end: a multiple of 4; fewer than 2^32 segments.  steps:
+ * the number of fhash_step_lazy calls so far (0 after fhash_lazy_init, one
+ * more after each; at most max_steps < 2^32 - 1).  beta1, beta2, eps: recorded
+ * by the first step, which every later step must repeat (FHASH_EINVAL
+ * otherwise); lr and grad_scale may change from step to step.  The library
+ * writes steps and the recorded constants; the caller sets the rest before
+ * fhash_lazy_init.  Calls that share one descriptor must be ordered on one
+ * stream. */
+#define FHASH_LAZY_FLOATS 16
+typedef struct {
+  void* ws;
+  int64_t begin, end;
+  int64_t max_steps;
+  int64_t steps;
+  double beta1, beta2, eps;
+} fhash_lazy;
+
+size_t fhash_lazy_workspace_bytes(int64_t range_floats, int64_t max_steps);
+
+/* Zero the workspace (a fill kernel on `stream`), steps = 0. */
+int fhash_lazy_init(fhash_lazy* lz, void* stream);
+
+/* Enrol for step steps+1 every segment of [begin, end) that the samples pos
+ * (device float4 [n], 16-byte aligned) read through the corner rows of their
+ * cells (Sec. 3.2.4) at idx, and bring those segments up to step `steps`:
+ * param, m, v (and shadow, when not NULL, rounded to shadow_dt as by
+ * fhash_step) are updated in place, applied gradients in grad are zeroed. */
+int fhash_lazy_prepare(const fhash_index* idx, const float* pos, int64_t n, fhash_lazy* lz,
+                       float* param, float* grad, float* m, float* v, void* shadow,
+                       fhash_dtype shadow_dt, void* stream);
+
+/* fhash_step with the range [begin, end) deferred: the dense update on
+ * [0, begin) and [end, n); the step's constants (and whether found_inf skipped
+ * it) are recorded for the range; steps += 1.  FHASH_ERANGE when
+ * steps == max_steps. */
+int fhash_step_lazy(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
+                    void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
+                    fhash_lazy* lz, void* stream);
+
+/* Bring every segment of the range up to step `steps` (a pass over the whole
+ * range: replays what each segment missed, applies and zeroes pending
+ * gradients). */
+int fhash_lazy_flush(fhash_lazy* lz, float* param, float* grad, float* m, float* v,
+                     void* shadow, fhash_dtype shadow_dt, void* stream);
 
 /* *found_inf |= any(!isfinite(grad[i])) over device float grad[n]. */
 int fhash_check_finite(const float* grad, int64_t n, int32_t* found_inf, void* stream);

@@ -93,6 +93,34 @@ def _touch(t):
     return None if t is None else C.byref(t)
 
 
+class Lazy(C.Structure):
+    _fields_ = [("ws", C.c_void_p), ("begin", C.c_int64), ("end", C.c_int64),
+                ("max_steps", C.c_int64), ("steps", C.c_int64), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
+
+
+LAZY_FLOATS = 16
+
+
+class LazyState:
+    """A deferred-Adam descriptor with its device workspace (see fhash_lazy_init)."""
+
+    def __init__(self, begin: int, end: int, max_steps: int, device="cuda"):
+        nb = lib().fhash_lazy_workspace_bytes(int(end) - int(begin), int(max_steps))
+        if nb == 0:
+            raise ValueError("bad lazy range or max_steps")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        self.desc = Lazy()
+        self.desc.ws = self.ws.data_ptr()
+        self.desc.begin, self.desc.end = int(begin), int(end)
+        self.desc.max_steps = int(max_steps)
+        _check(lib().fhash_lazy_init(C.byref(self.desc), _stream()), "fhash_lazy_init")
+
+    @property
+    def steps(self) -> int:
+        return int(self.desc.steps)
+
+
 _lib = None
 
 
@@ -128,6 +156,11 @@ def _declare(L):
         "fhash_fused_train": (C.c_int, [P, P, P, P, I64, P, C.c_int, P, P, F, P, P, P, C.c_uint32,
                                         P, P, P, P]),
         "fhash_step": (C.c_int, [P, P, P, P, P, P, C.c_int, I64, P, P, P]),
+        "fhash_lazy_workspace_bytes": (C.c_size_t, [I64, I64]),
+        "fhash_lazy_init": (C.c_int, [P, P]),
+        "fhash_lazy_prepare": (C.c_int, [P, P, I64, P, P, P, P, P, P, C.c_int, P]),
+        "fhash_step_lazy": (C.c_int, [P, P, P, P, P, P, C.c_int, I64, P, P, P]),
+        "fhash_lazy_flush": (C.c_int, [P, P, P, P, P, P, C.c_int, P]),
         "fhash_check_finite": (C.c_int, [P, I64, P, P]),
         "fhash_cast": (C.c_int, [P, P, C.c_int, I64, P]),
         "fhash_sample": (C.c_int, [U64, U64, I64, P, U64, P, P, P, P, P]),
@@ -155,7 +188,9 @@ def exported_symbols() -> list[str]:
             "fhash_fused_train", "fhash_step", "fhash_check_finite", "fhash_cast",
             "fhash_sample", "fhash_sq_err_sum", "fhash_mse_grad", "fhash_render_state_bytes",
             "fhash_render_begin", "fhash_render_pace", "fhash_render_march",
-            "fhash_render_composite", "fhash_render", "fhash_sort_samples"]
+            "fhash_render_composite", "fhash_render", "fhash_sort_samples",
+            "fhash_lazy_workspace_bytes", "fhash_lazy_init", "fhash_lazy_prepare",
+            "fhash_step_lazy", "fhash_lazy_flush"]
 
 
 def _check(rc: int, func: str):
@@ -326,6 +361,27 @@ def fhash_step(opt: AdamDesc, param, grad, m, v, shadow=None, found_inf=None, to
     _check(lib().fhash_step(C.byref(opt), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
                             _ptr(shadow), sdt, param.numel(), _ptr(found_inf), _touch(touch),
                             _stream()), "fhash_step")
+
+
+def fhash_lazy_prepare(idx: Index, pos, n, lazy: LazyState, param, grad, m, v, shadow=None):
+    sdt = F16 if shadow is None else _dt(shadow)
+    _check(lib().fhash_lazy_prepare(C.byref(idx), _ptr(pos), n, C.byref(lazy.desc), _ptr(param),
+                                    _ptr(grad), _ptr(m), _ptr(v), _ptr(shadow), sdt, _stream()),
+           "fhash_lazy_prepare")
+
+
+def fhash_step_lazy(opt: AdamDesc, param, grad, m, v, lazy: LazyState, shadow=None,
+                    found_inf=None):
+    sdt = F16 if shadow is None else _dt(shadow)
+    _check(lib().fhash_step_lazy(C.byref(opt), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
+                                 _ptr(shadow), sdt, param.numel(), _ptr(found_inf),
+                                 C.byref(lazy.desc), _stream()), "fhash_step_lazy")
+
+
+def fhash_lazy_flush(lazy: LazyState, param, grad, m, v, shadow=None):
+    sdt = F16 if shadow is None else _dt(shadow)
+    _check(lib().fhash_lazy_flush(C.byref(lazy.desc), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
+                                  _ptr(shadow), sdt, _stream()), "fhash_lazy_flush")
 
 
 def fhash_check_finite(grad, found_inf):

@@ -1,0 +1,66 @@
+// The Adam update of one parameter, shared by the dense sweep and the deferred
+// (lazy) update kernels so that both apply bit-identical arithmetic.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fhash.h"
+
+namespace fh {
+
+// FP32 constants of one step.  step_size = lr / (1 - b1^t) and
+// inv_bc2_sqrt = 1 / sqrt(1 - b2^t) are formed in double on the host.
+struct AdamK {
+  float step_size, b1, omb1, b2, omb2, eps, inv_bc2_sqrt, gscale;
+};
+
+// Host: the constants of a step from its descriptor.
+inline AdamK make_adam_k(const fhash_adam_desc* o) {
+  AdamK k;
+  const double bc1 = 1.0 - pow(o->beta1, (double)o->step);
+  const double bc2 = 1.0 - pow(o->beta2, (double)o->step);
+  k.step_size = (float)(o->lr / bc1);
+  k.inv_bc2_sqrt = (float)(1.0 / sqrt(bc2));
+  k.b1 = (float)o->beta1;
+  k.omb1 = (float)(1.0 - o->beta1);
+  k.b2 = (float)o->beta2;
+  k.omb2 = (float)(1.0 - o->beta2);
+  k.eps = (float)o->eps;
+  k.gscale = (float)o->grad_scale;
+  return k;
+}
+
+#ifdef __HIPCC__
+// One Adam step (PyTorch semantics, bias-corrected, no weight decay) with
+// every rounding spelled out, so that no kernel contracts it differently:
+//   gs = g * gscale;  m = b1 m + (1-b1) gs;  v = b2 v + (1-b2) gs^2;
+//   p -= step_size * m * (1 / (sqrt(v) * inv_bc2_sqrt + eps)).
+// The square root and the reciprocal are the hardware's (v_sqrt_f32,
+// v_rcp_f32: within 1 ulp, deterministic); the quotient is not correctly
+// rounded, which stays far inside the FP32 tolerance against the FP64 update.
+__device__ __forceinline__ void adam1(const AdamK& k, float g, float& p, float& m, float& v) {
+  const float gs = __fmul_rn(g, k.gscale);
+  m = __fmaf_rn(k.b1, m, __fmul_rn(k.omb1, gs));
+  v = __fmaf_rn(k.b2, v, __fmul_rn(__fmul_rn(k.omb2, gs), gs));
+  const float denom = __fmaf_rn(__builtin_amdgcn_sqrtf(v), k.inv_bc2_sqrt, k.eps);
+  p = __fsub_rn(p, __fmul_rn(k.step_size, __fmul_rn(m, __builtin_amdgcn_rcpf(denom))));
+}
+
+__device__ __forceinline__ uint16_t to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ void store_shadow(void* sh, int dt, int64_t i, float x) {
+  if (dt == FHASH_F16)
+    reinterpret_cast<__half*>(sh)[i] = __float2half_rn(x);
+  else
+    reinterpret_cast<uint16_t*>(sh)[i] = to_bf16_rne(x);
+}
+#endif
+
+}  // namespace fh

@@ -400,9 +400,9 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
                     "fhash_fused_train");
 }
 
-int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
-               void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
-               const fhash_touch* touch, void* stream) {
+static int check_step(const fhash_adam_desc* opt, const float* param, const float* grad,
+                      const float* m, const float* v, const void* shadow, fhash_dtype shadow_dt,
+                      int64_t n) {
   if (opt == nullptr) return fail(FHASH_EINVAL, "optimiser descriptor is NULL");
   if (n < 0) return fail(FHASH_EINVAL, "n < 0");
   if (opt->step < 1) return fail(FHASH_EINVAL, "step must be >= 1");
@@ -420,11 +420,133 @@ int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, 
     if ((reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)
       return fail(FHASH_EINVAL, "shadow must be 8-byte aligned");
   }
-  int rc = apply_touch(touch, n, nullptr);
+  return FHASH_OK;
+}
+
+int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
+               void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
+               const fhash_touch* touch, void* stream) {
+  int rc = check_step(opt, param, grad, m, v, shadow, shadow_dt, n);
   if (rc) return rc;
+  if (n == 0) return FHASH_OK;
+  if ((rc = apply_touch(touch, n, nullptr))) return rc;
   return hip_status(
       fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, n, found_inf, touch, S(stream)),
       "fhash_step");
+}
+
+size_t fhash_lazy_workspace_bytes(int64_t range_floats, int64_t max_steps) {
+  if (range_floats < 0 || max_steps < 0) return 0;
+  return fh::lazy_ws_bytes(range_floats, max_steps);
+}
+
+static int check_lazy(const fhash_lazy* lz) {
+  if (lz == nullptr) return fail(FHASH_EINVAL, "lazy descriptor is NULL");
+  if (lz->ws == nullptr || !aligned16(lz->ws))
+    return fail(FHASH_EINVAL, "lazy workspace is NULL or not 16-byte aligned");
+  if (lz->begin < 0 || lz->begin % FHASH_LAZY_FLOATS != 0 || lz->end < lz->begin ||
+      lz->end % 4 != 0)
+    return fail(FHASH_EINVAL, "lazy range [%lld, %lld): begin must be a multiple of %d, end of 4",
+                (long long)lz->begin, (long long)lz->end, FHASH_LAZY_FLOATS);
+  if (fh::lazy_num_segments(lz->end - lz->begin) >= (int64_t)UINT32_MAX)
+    return fail(FHASH_ERANGE, "lazy range has 2^32 segments or more");
+  if (lz->max_steps < 0 || lz->max_steps >= (int64_t)UINT32_MAX)
+    return fail(FHASH_ERANGE, "max_steps outside [0, 2^32 - 1)");
+  if (lz->steps < 0 || lz->steps > lz->max_steps)
+    return fail(FHASH_EINVAL, "steps %lld outside [0, max_steps]", (long long)lz->steps);
+  return FHASH_OK;
+}
+
+int fhash_lazy_init(fhash_lazy* lz, void* stream) {
+  if (lz == nullptr) return fail(FHASH_EINVAL, "lazy descriptor is NULL");
+  lz->steps = 0;
+  int rc = check_lazy(lz);
+  if (rc) return rc;
+  lz->beta1 = lz->beta2 = lz->eps = -1.0;  // recorded by the first step
+  return hip_status(fh::launch_lazy_init(lz, S(stream)), "fhash_lazy_init");
+}
+
+// The levels whose table floats intersect [begin, end).
+static void lazy_levels(const fhash_index* idx, const fhash_lazy* lz, int* l0, int* l1) {
+  const int L = idx->grid.n_levels, F = idx->grid.n_features;
+  *l0 = L;
+  *l1 = 0;
+  for (int l = 0; l < L; ++l) {
+    const int64_t a = idx->slot_offset[l] * F, b = idx->slot_offset[l + 1] * F;
+    if (b > lz->begin && a < lz->end && a < b) {
+      if (l < *l0) *l0 = l;
+      *l1 = l + 1;
+    }
+  }
+  if (*l0 > *l1) *l0 = *l1;
+}
+
+int fhash_lazy_prepare(const fhash_index* idx, const float* pos, int64_t n, fhash_lazy* lz,
+                       float* param, float* grad, float* m, float* v, void* shadow,
+                       fhash_dtype shadow_dt, void* stream) {
+  int rc = check_index(idx);
+  if (rc) return rc;
+  if ((rc = check_lazy(lz))) return rc;
+  if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  if (lz->end > total_rows(idx) * idx->grid.n_features + 3)
+    return fail(FHASH_EINVAL, "lazy range ends past the table");
+  if (n > 0 && (pos == nullptr || !aligned16(pos)))
+    return fail(FHASH_EINVAL, "pos is NULL or not 16-byte aligned");
+  if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
+    return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  int l0, l1;
+  lazy_levels(idx, lz, &l0, &l1);
+  return hip_status(fh::launch_lazy_prepare(g, l0, l1, pos, n, lz, param, grad, m, v, shadow,
+                                            shadow_dt, S(stream)),
+                    "fhash_lazy_prepare");
+}
+
+int fhash_step_lazy(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
+                    void* shadow, fhash_dtype shadow_dt, int64_t n, const int32_t* found_inf,
+                    fhash_lazy* lz, void* stream) {
+  int rc = check_step(opt, param, grad, m, v, shadow, shadow_dt, n);
+  if (rc) return rc;
+  if ((rc = check_lazy(lz))) return rc;
+  if (lz->end > n) return fail(FHASH_EINVAL, "lazy range ends past the parameters");
+  if (lz->steps + 1 > lz->max_steps)
+    return fail(FHASH_ERANGE, "lazy record full (%lld steps)", (long long)lz->max_steps);
+  if (lz->beta1 < 0.0) {
+    lz->beta1 = opt->beta1;
+    lz->beta2 = opt->beta2;
+    lz->eps = opt->eps;
+  } else if (lz->beta1 != opt->beta1 || lz->beta2 != opt->beta2 || lz->eps != opt->eps) {
+    return fail(FHASH_EINVAL, "beta1, beta2 and eps must not change under lazy updates");
+  }
+  hipStream_t st = S(stream);
+  // dense part: [0, begin) and [end, n)
+  hipError_t e = fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, lz->begin, found_inf,
+                                 nullptr, st);
+  if (e == hipSuccess) {
+    void* sh_tail = shadow ? static_cast<void*>(static_cast<uint16_t*>(shadow) + lz->end) : nullptr;
+    e = fh::launch_adam(opt, param + lz->end, grad + lz->end, m + lz->end, v + lz->end, sh_tail,
+                        shadow_dt, n - lz->end, found_inf, nullptr, st);
+  }
+  if (e == hipSuccess)
+    e = fh::launch_lazy_step(opt, lz, found_inf, st);
+  if (e != hipSuccess) return hip_status(e, "fhash_step_lazy");
+  lz->steps += 1;
+  return FHASH_OK;
+}
+
+int fhash_lazy_flush(fhash_lazy* lz, float* param, float* grad, float* m, float* v, void* shadow,
+                     fhash_dtype shadow_dt, void* stream) {
+  int rc = check_lazy(lz);
+  if (rc) return rc;
+  if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
+    return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
+  return hip_status(fh::launch_lazy_flush(lz, param, grad, m, v, shadow, shadow_dt, S(stream)),
+                    "fhash_lazy_flush");
 }
 
 int fhash_check_finite(const float* grad, int64_t n, int32_t* found_inf, void* stream) {

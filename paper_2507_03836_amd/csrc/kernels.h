@@ -62,6 +62,18 @@ hipError_t launch_sq_err(const float* y, const float* v, int64_t n, double* sum,
 hipError_t launch_mse_grad(const float* y, const float* v, int64_t n, float coef, float* dy,
                            double* sum, hipStream_t st);
 
+// lazy.hip: deferred Adam over a table range
+int64_t lazy_num_segments(int64_t range_floats);
+size_t lazy_ws_bytes(int64_t range_floats, int64_t max_steps);
+hipError_t launch_lazy_init(const fhash_lazy* lz, hipStream_t st);
+hipError_t launch_lazy_prepare(const GridDev& g, int l0, int l1, const float* pos, int64_t n,
+                               const fhash_lazy* lz, float* p, float* gr, float* m, float* v,
+                               void* shadow, fhash_dtype sdt, hipStream_t st);
+hipError_t launch_lazy_step(const fhash_adam_desc* o, const fhash_lazy* lz,
+                            const int32_t* found_inf, hipStream_t st);
+hipError_t launch_lazy_flush(const fhash_lazy* lz, float* p, float* gr, float* m, float* v,
+                             void* shadow, fhash_dtype sdt, hipStream_t st);
+
 // sampler.hip
 hipError_t launch_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset,
                          uint64_t M, const int64_t* dims, const float* field, float* pos,

@@ -3,38 +3,13 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include "adam_dev.h"
 #include "common.h"
 #include "kernels.h"
 
 namespace fh {
 
 namespace {
-
-__device__ __forceinline__ uint16_t to_bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ void store_shadow(void* sh, int dt, int64_t i, float x) {
-  if (dt == FHASH_F16)
-    reinterpret_cast<__half*>(sh)[i] = __float2half_rn(x);
-  else
-    reinterpret_cast<uint16_t*>(sh)[i] = to_bf16_rne(x);
-}
-
-struct AdamK {
-  float step_size, b1, omb1, b2, omb2, eps, inv_bc2_sqrt, gscale;
-};
-
-__device__ __forceinline__ void adam1(const AdamK& k, float g, float& p, float& m, float& v) {
-  const float gs = g * k.gscale;
-  m = k.b1 * m + k.omb1 * gs;
-  v = k.b2 * v + k.omb2 * gs * gs;
-  const float denom = sqrtf(v) * k.inv_bc2_sqrt + k.eps;
-  p -= k.step_size * (m / denom);
-}
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -250,17 +225,7 @@ hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, f
                        void* shadow, fhash_dtype sdt, int64_t n, const int32_t* found_inf,
                        const fhash_touch* touch, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  AdamK k;
-  const double bc1 = 1.0 - pow(o->beta1, (double)o->step);
-  const double bc2 = 1.0 - pow(o->beta2, (double)o->step);
-  k.step_size = (float)(o->lr / bc1);
-  k.inv_bc2_sqrt = (float)(1.0 / sqrt(bc2));
-  k.b1 = (float)o->beta1;
-  k.omb1 = (float)(1.0 - o->beta1);
-  k.b2 = (float)o->beta2;
-  k.omb2 = (float)(1.0 - o->beta2);
-  k.eps = (float)o->eps;
-  k.gscale = (float)o->grad_scale;
+  const AdamK k = make_adam_k(o);
   // Two float4 groups per thread per iteration; a deep grid keeps every CU's
   // memory pipeline full (measured best on MI355X: ~128K workgroups).
   int64_t b = (n / 8 + 255) / 256;

@@ -75,7 +75,8 @@ class FHashModel:
     def __init__(self, cfg: FHashConfig, mask_bits: torch.Tensor | None, dims, device="cuda",
                  table_init: torch.Tensor | None = None, mlp_init: torch.Tensor | None = None,
                  init_seed: int = 3000, precision: str = "fp32", loss_scale: float = 2.0 ** 16,
-                 scale_window: int = 2000, track_touched: bool = True):
+                 scale_window: int = 2000, track_touched: bool = True, lazy: bool = False,
+                 max_steps: int = 1 << 16):
         if precision not in ("fp32", "mixed"):
             raise ValueError(f"precision must be 'fp32' or 'mixed', not {precision!r}")
         self.cfg = cfg
@@ -123,15 +124,20 @@ class FHashModel:
         self.loss_scale = 1.0
         self.touch = None
         self._touch_flags = None
-        if track_touched:
-            F, seg = cfg.n_features, fl.TOUCH_FLOATS
-            first = next((l for l in range(cfg.n_levels)
-                          if self.slots_per_level[l] * F // seg >= (1 << 21)), None)
-            if first is not None:
-                begin = int(self.index.slot_offset[first]) * F // seg * seg
-                self._touch_flags = torch.zeros((self.n_table + seg - 1) // seg,
-                                                dtype=torch.uint8, device=self.device)
-                self.touch = fl.touch_desc(self._touch_flags, begin, self.n_table)
+        self.lazy = None
+        # large levels (2^21 segments of 16 floats or more): tracked or deferred
+        F, seg = cfg.n_features, fl.TOUCH_FLOATS
+        first = next((l for l in range(cfg.n_levels)
+                      if self.slots_per_level[l] * F // seg >= (1 << 21)), None)
+        begin = None if first is None else int(self.index.slot_offset[first]) * F // seg * seg
+        if lazy:
+            # deferred Adam on [begin, end of the padded table); dense elsewhere
+            self.lazy = fl.LazyState(0 if begin is None else begin, self.mlp_off, max_steps,
+                                     device=self.device)
+        elif track_touched and begin is not None:
+            self._touch_flags = torch.zeros((self.n_table + seg - 1) // seg,
+                                            dtype=torch.uint8, device=self.device)
+            self.touch = fl.touch_desc(self._touch_flags, begin, self.n_table)
         if precision == "mixed":
             self.shadow = torch.empty(n_alloc, dtype=torch.float16, device=self.device)
             fl.fhash_cast(self.params, self.shadow)
@@ -171,19 +177,37 @@ class FHashModel:
         o.grad_scale = grad_scale
         return o
 
+    def prepare(self, pos: torch.Tensor):
+        """Under deferred Adam: bring the table rows that pos reads up to date
+        (and enrol them in the next step)."""
+        if self.lazy is not None:
+            fl.fhash_lazy_prepare(self.index, pos, pos.shape[0], self.lazy, self.params,
+                                  self.grads, self.m, self.v, shadow=self.shadow)
+
+    def flush(self):
+        """Under deferred Adam: bring every parameter up to date and apply the
+        pending gradients (before the whole table is read: rendering, export)."""
+        if self.lazy is not None:
+            fl.fhash_lazy_flush(self.lazy, self.params, self.grads, self.m, self.v,
+                                shadow=self.shadow)
+
     def forward(self, pos: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
         n = pos.shape[0]
+        self.prepare(pos)
         if y is None:
             y = torch.empty(n, dtype=torch.float32, device=self.device)
         fl.fhash_fused_fwd(self.index, self.mlp, pos, n, self.read_table, self.mlp_params, y)
         return y
 
     def fwd_bwd(self, pos: torch.Tensor, target: torch.Tensor, loss_scale: float | None = None,
-                sorted_batch: bool = False):
+                sorted_batch: bool = False, prepared: bool = False):
         """Fused forward + MSE + backward; gradients accumulate into self.grads
-        (multiplied by the loss scale; the model's own scale when None)."""
+        (multiplied by the loss scale; the model's own scale when None).
+        prepared: the caller has already called prepare(pos)."""
         n = pos.shape[0]
         s = self.loss_scale if loss_scale is None else loss_scale
+        if not prepared:
+            self.prepare(pos)
         self._ws = fl.fhash_fused_train(self.index, self.mlp, pos, target, n, self.read_table,
                                         self.mlp_params, self.d_table, self.d_mlp,
                                         self.loss_sum, s, ws=self._ws,
@@ -191,23 +215,19 @@ class FHashModel:
                                         touch=self.touch)
 
     def optimizer_step(self, grad_scale: float | None = None, found_inf=None) -> bool:
-        """Dense Adam over every parameter; gradients are reset.  The mixed path
+        """Adam over every parameter (dense, or deferred on the large levels
+        with the same results); gradients are reset.  The mixed path
         unscales, skips the update on a non-finite gradient and adapts the
         loss scale.  Returns whether the parameters were updated."""
         if self.shadow is None:
             self.step_count += 1
-            fl.fhash_step(self.adam_desc(self.step_count, 1.0 if grad_scale is None else grad_scale),
-                          self.params[: self.n_params], self.grads[: self.n_params],
-                          self.m[: self.n_params], self.v[: self.n_params], found_inf=found_inf,
-                          touch=self.touch)
+            self._step(self.adam_desc(self.step_count, 1.0 if grad_scale is None else grad_scale),
+                       None, found_inf)
             return True
         self.found_inf.zero_()
         fl.fhash_check_finite(self.d_mlp, self.found_inf)
         opt = self.adam_desc(self.step_count + 1, 1.0 / self.loss_scale)
-        fl.fhash_step(opt, self.params[: self.n_params], self.grads[: self.n_params],
-                      self.m[: self.n_params], self.v[: self.n_params],
-                      shadow=self.shadow[: self.n_params], found_inf=self.found_inf,
-                      touch=self.touch)
+        self._step(opt, self.shadow[: self.n_params], self.found_inf)
         if int(self.found_inf.item()):
             self.loss_scale *= 0.5
             self._clean = 0
@@ -219,6 +239,14 @@ class FHashModel:
             self.loss_scale *= 2.0
             self._clean = 0
         return True
+
+    def _step(self, opt, shadow, found_inf):
+        args = (opt, self.params[: self.n_params], self.grads[: self.n_params],
+                self.m[: self.n_params], self.v[: self.n_params])
+        if self.lazy is not None:
+            fl.fhash_step_lazy(*args, self.lazy, shadow=shadow, found_inf=found_inf)
+        else:
+            fl.fhash_step(*args, shadow=shadow, found_inf=found_inf, touch=self.touch)
 
     def train_step(self, pos: torch.Tensor, target: torch.Tensor):
         self.fwd_bwd(pos, target)

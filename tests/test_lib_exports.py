@@ -87,3 +87,31 @@ def test_level_row_limit_reported_as_erange():
     assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.ERANGE
     g = fl.grid_desc([[64, 2048, 2048, 511]], 2)      # just below
     assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.OK
+
+
+def test_lazy_descriptor_validated_before_any_launch():
+    """The deferred-Adam calls size their workspace and reject malformed
+    descriptors on the host (no device needed)."""
+    L = fl.lib()
+    # state 8 B + list 8 B per 16-float segment, 256 B counters, 16 B per step (+1)
+    nb = L.fhash_lazy_workspace_bytes(16 * 1000, 100)
+    assert nb == 8192 + 8192 + 256 + 1792
+    assert L.fhash_lazy_workspace_bytes(-1, 10) == 0
+    fake = ctypes.c_void_p(1 << 20)
+    o = fl.AdamDesc()
+    o.lr, o.beta1, o.beta2, o.eps, o.step, o.grad_scale = 0.01, 0.9, 0.999, 1e-8, 1, 1.0
+    for ws, begin, end, max_steps, steps, code, why in (
+            (None, 0, 64, 10, 0, fl.EINVAL, b"workspace"),
+            (fake, 8, 64, 10, 0, fl.EINVAL, b"multiple"),
+            (fake, 0, 66, 10, 0, fl.EINVAL, b"multiple"),
+            (fake, 64, 32, 10, 0, fl.EINVAL, b"multiple"),
+            (fake, 0, 64, 1 << 32, 0, fl.ERANGE, b"max_steps"),
+            (fake, 0, 64, 10, 10, fl.ERANGE, b"lazy record full"),
+            (fake, 0, 2048, 10, 0, fl.EINVAL, b"past the parameters")):
+        lz = fl.Lazy()
+        lz.ws, lz.begin, lz.end, lz.max_steps, lz.steps = ws, begin, end, max_steps, steps
+        lz.beta1 = lz.beta2 = lz.eps = -1.0
+        rc = L.fhash_step_lazy(ctypes.byref(o), fake, fake, fake, fake, None, fl.F16, 1024,
+                               None, ctypes.byref(lz), None)
+        assert rc == code and why in L.fhash_last_error(), (begin, end, max_steps, steps)
+        assert lz.steps == steps
