@@ -281,6 +281,7 @@ typedef struct {
   int64_t max_steps;
   int64_t steps;
   double beta1, beta2, eps;
+  int64_t flags; /* library-owned: bit 0, a step with a non-finite grad_scale was recorded */
 } fhash_lazy;
 
 size_t fhash_lazy_workspace_bytes(int64_t range_floats, int64_t max_steps);
@@ -290,12 +291,24 @@ int fhash_lazy_init(fhash_lazy* lz, void* stream);
 
 /* Enrol for step steps+1 every segment of [begin, end) that the samples pos
  * (device float4 [n], 16-byte aligned) read through the corner rows of their
- * cells (Sec. 3.2.4) at idx, and bring those segments up to step `steps`:
- * param, m, v (and shadow, when not NULL, rounded to shadow_dt as by
- * fhash_step) are updated in place, applied gradients in grad are zeroed. */
+ * cells (Sec. 3.2.4) at idx (phase FHASH_LAZY_MARK), and bring the segments
+ * enrolled since the last catch-up up to step `steps` (phase
+ * FHASH_LAZY_CATCH_UP): param, m, v (and shadow, when not NULL, rounded to
+ * shadow_dt as by fhash_step) are updated in place, applied gradients in grad
+ * are zeroed.  phases: FHASH_LAZY_PREPARE for both; a mark must be followed by
+ * a catch-up before the enrolled segments are read and before the step. */
+#define FHASH_LAZY_MARK 1u
+#define FHASH_LAZY_CATCH_UP 2u
+#define FHASH_LAZY_PREPARE 3u
 int fhash_lazy_prepare(const fhash_index* idx, const float* pos, int64_t n, fhash_lazy* lz,
                        float* param, float* grad, float* m, float* v, void* shadow,
-                       fhash_dtype shadow_dt, void* stream);
+                       fhash_dtype shadow_dt, uint32_t phases, void* stream);
+
+/* Workload counters accumulated by the catch-ups since fhash_lazy_init
+ * (copied to host; synchronises `stream`): stats[0] segments caught up,
+ * stats[1] of them with data to load (stepped before), stats[2] with a pending
+ * gradient, stats[3] segment-steps replayed. */
+int fhash_lazy_stats(const fhash_lazy* lz, int64_t stats[4], void* stream);
 
 /* fhash_step with the range [begin, end) deferred: the dense update on
  * [0, begin) and [end, n); the step's constants (and whether found_inf skipped

@@ -96,7 +96,7 @@ def _touch(t):
 class Lazy(C.Structure):
     _fields_ = [("ws", C.c_void_p), ("begin", C.c_int64), ("end", C.c_int64),
                 ("max_steps", C.c_int64), ("steps", C.c_int64), ("beta1", C.c_double),
-                ("beta2", C.c_double), ("eps", C.c_double)]
+                ("beta2", C.c_double), ("eps", C.c_double), ("flags", C.c_int64)]
 
 
 LAZY_FLOATS = 16
@@ -158,7 +158,8 @@ def _declare(L):
         "fhash_step": (C.c_int, [P, P, P, P, P, P, C.c_int, I64, P, P, P]),
         "fhash_lazy_workspace_bytes": (C.c_size_t, [I64, I64]),
         "fhash_lazy_init": (C.c_int, [P, P]),
-        "fhash_lazy_prepare": (C.c_int, [P, P, I64, P, P, P, P, P, P, C.c_int, P]),
+        "fhash_lazy_prepare": (C.c_int, [P, P, I64, P, P, P, P, P, P, C.c_int, C.c_uint32, P]),
+        "fhash_lazy_stats": (C.c_int, [P, P, P]),
         "fhash_step_lazy": (C.c_int, [P, P, P, P, P, P, C.c_int, I64, P, P, P]),
         "fhash_lazy_flush": (C.c_int, [P, P, P, P, P, P, C.c_int, P]),
         "fhash_check_finite": (C.c_int, [P, I64, P, P]),
@@ -190,7 +191,7 @@ def exported_symbols() -> list[str]:
             "fhash_render_begin", "fhash_render_pace", "fhash_render_march",
             "fhash_render_composite", "fhash_render", "fhash_sort_samples",
             "fhash_lazy_workspace_bytes", "fhash_lazy_init", "fhash_lazy_prepare",
-            "fhash_step_lazy", "fhash_lazy_flush"]
+            "fhash_step_lazy", "fhash_lazy_flush", "fhash_lazy_stats"]
 
 
 def _check(rc: int, func: str):
@@ -363,11 +364,21 @@ def fhash_step(opt: AdamDesc, param, grad, m, v, shadow=None, found_inf=None, to
                             _stream()), "fhash_step")
 
 
-def fhash_lazy_prepare(idx: Index, pos, n, lazy: LazyState, param, grad, m, v, shadow=None):
+LAZY_MARK, LAZY_CATCH_UP, LAZY_PREPARE = 1, 2, 3
+
+
+def fhash_lazy_prepare(idx: Index, pos, n, lazy: LazyState, param, grad, m, v, shadow=None,
+                       phases=LAZY_PREPARE):
     sdt = F16 if shadow is None else _dt(shadow)
     _check(lib().fhash_lazy_prepare(C.byref(idx), _ptr(pos), n, C.byref(lazy.desc), _ptr(param),
-                                    _ptr(grad), _ptr(m), _ptr(v), _ptr(shadow), sdt, _stream()),
-           "fhash_lazy_prepare")
+                                    _ptr(grad), _ptr(m), _ptr(v), _ptr(shadow), sdt,
+                                    C.c_uint32(phases), _stream()), "fhash_lazy_prepare")
+
+
+def fhash_lazy_stats(lazy: LazyState) -> dict:
+    out = (C.c_int64 * 4)()
+    _check(lib().fhash_lazy_stats(C.byref(lazy.desc), out, _stream()), "fhash_lazy_stats")
+    return {"segments": out[0], "loaded": out[1], "pending": out[2], "segment_steps": out[3]}
 
 
 def fhash_step_lazy(opt: AdamDesc, param, grad, m, v, lazy: LazyState, shadow=None,

@@ -34,18 +34,32 @@ inline AdamK make_adam_k(const fhash_adam_desc* o) {
 
 #ifdef __HIPCC__
 // One Adam step (PyTorch semantics, bias-corrected, no weight decay) with
-// every rounding spelled out, so that no kernel contracts it differently:
+// every rounding spelled out and contraction off, so that every kernel that
+// inlines it computes the same bits:
 //   gs = g * gscale;  m = b1 m + (1-b1) gs;  v = b2 v + (1-b2) gs^2;
-//   p -= step_size * m * (1 / (sqrt(v) * inv_bc2_sqrt + eps)).
+//   p = fma(-step_size, m * (1 / (sqrt(v) * inv_bc2_sqrt + eps)), p).
 // The square root and the reciprocal are the hardware's (v_sqrt_f32,
 // v_rcp_f32: within 1 ulp, deterministic); the quotient is not correctly
 // rounded, which stays far inside the FP32 tolerance against the FP64 update.
 __device__ __forceinline__ void adam1(const AdamK& k, float g, float& p, float& m, float& v) {
-  const float gs = __fmul_rn(g, k.gscale);
-  m = __fmaf_rn(k.b1, m, __fmul_rn(k.omb1, gs));
-  v = __fmaf_rn(k.b2, v, __fmul_rn(__fmul_rn(k.omb2, gs), gs));
+#pragma clang fp contract(off)
+  const float gs = g * k.gscale;
+  m = __fmaf_rn(k.b1, m, k.omb1 * gs);
+  v = __fmaf_rn(k.b2, v, (k.omb2 * gs) * gs);
   const float denom = __fmaf_rn(__builtin_amdgcn_sqrtf(v), k.inv_bc2_sqrt, k.eps);
-  p = __fsub_rn(p, __fmul_rn(k.step_size, __fmul_rn(m, __builtin_amdgcn_rcpf(denom))));
+  p = __fmaf_rn(-k.step_size, m * __builtin_amdgcn_rcpf(denom), p);
+}
+
+// adam1 with g = +0 and a finite gscale: gs is a zero, so (1-b1) gs and
+// (1-b2) gs^2 are zeros and the two fused multiply-adds reduce to the plain
+// products fl(b1 m) and fl(b2 v) (m and v are never -0: both start at +0, and
+// an fma returns -0 only from two -0 terms).  Same bits as adam1(k, +0, ...).
+__device__ __forceinline__ void adam0(const AdamK& k, float& p, float& m, float& v) {
+#pragma clang fp contract(off)
+  m = k.b1 * m;
+  v = k.b2 * v;
+  const float denom = __fmaf_rn(__builtin_amdgcn_sqrtf(v), k.inv_bc2_sqrt, k.eps);
+  p = __fmaf_rn(-k.step_size, m * __builtin_amdgcn_rcpf(denom), p);
 }
 
 __device__ __forceinline__ uint16_t to_bf16_rne(float x) {

@@ -3,6 +3,7 @@
 // status code and records a message for fhash_last_error().
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -463,6 +464,7 @@ int fhash_lazy_init(fhash_lazy* lz, void* stream) {
   int rc = check_lazy(lz);
   if (rc) return rc;
   lz->beta1 = lz->beta2 = lz->eps = -1.0;  // recorded by the first step
+  lz->flags = 0;
   return hip_status(fh::launch_lazy_init(lz, S(stream)), "fhash_lazy_init");
 }
 
@@ -483,17 +485,21 @@ static void lazy_levels(const fhash_index* idx, const fhash_lazy* lz, int* l0, i
 
 int fhash_lazy_prepare(const fhash_index* idx, const float* pos, int64_t n, fhash_lazy* lz,
                        float* param, float* grad, float* m, float* v, void* shadow,
-                       fhash_dtype shadow_dt, void* stream) {
+                       fhash_dtype shadow_dt, uint32_t phases, void* stream) {
   int rc = check_index(idx);
   if (rc) return rc;
   if ((rc = check_lazy(lz))) return rc;
   if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  if (phases == 0 || (phases & ~(uint32_t)(FHASH_LAZY_MARK | FHASH_LAZY_CATCH_UP)) != 0)
+    return fail(FHASH_EINVAL, "phases must be a nonempty set of FHASH_LAZY_MARK, FHASH_LAZY_CATCH_UP");
   if (lz->end > total_rows(idx) * idx->grid.n_features + 3)
     return fail(FHASH_EINVAL, "lazy range ends past the table");
   if (n > 0 && (pos == nullptr || !aligned16(pos)))
     return fail(FHASH_EINVAL, "pos is NULL or not 16-byte aligned");
   if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
     return fail(FHASH_EINVAL, "NULL pointer");
+  if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
+    return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
   if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
     return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
   fh::GridDev g;
@@ -501,7 +507,7 @@ int fhash_lazy_prepare(const fhash_index* idx, const float* pos, int64_t n, fhas
   int l0, l1;
   lazy_levels(idx, lz, &l0, &l1);
   return hip_status(fh::launch_lazy_prepare(g, l0, l1, pos, n, lz, param, grad, m, v, shadow,
-                                            shadow_dt, S(stream)),
+                                            shadow_dt, phases, S(stream)),
                     "fhash_lazy_prepare");
 }
 
@@ -533,8 +539,16 @@ int fhash_step_lazy(const fhash_adam_desc* opt, float* param, float* grad, float
   if (e == hipSuccess)
     e = fh::launch_lazy_step(opt, lz, found_inf, st);
   if (e != hipSuccess) return hip_status(e, "fhash_step_lazy");
+  if (!std::isfinite((float)opt->grad_scale)) lz->flags |= 1;
   lz->steps += 1;
   return FHASH_OK;
+}
+
+int fhash_lazy_stats(const fhash_lazy* lz, int64_t stats[4], void* stream) {
+  int rc = check_lazy(lz);
+  if (rc) return rc;
+  if (stats == nullptr) return fail(FHASH_EINVAL, "stats is NULL");
+  return hip_status(fh::lazy_read_stats(lz, stats, S(stream)), "fhash_lazy_stats");
 }
 
 int fhash_lazy_flush(fhash_lazy* lz, float* param, float* grad, float* m, float* v, void* shadow,
@@ -543,6 +557,8 @@ int fhash_lazy_flush(fhash_lazy* lz, float* param, float* grad, float* m, float*
   if (rc) return rc;
   if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
     return fail(FHASH_EINVAL, "NULL pointer");
+  if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
+    return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
   if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
     return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
   return hip_status(fh::launch_lazy_flush(lz, param, grad, m, v, shadow, shadow_dt, S(stream)),

@@ -68,7 +68,8 @@ size_t lazy_ws_bytes(int64_t range_floats, int64_t max_steps);
 hipError_t launch_lazy_init(const fhash_lazy* lz, hipStream_t st);
 hipError_t launch_lazy_prepare(const GridDev& g, int l0, int l1, const float* pos, int64_t n,
                                const fhash_lazy* lz, float* p, float* gr, float* m, float* v,
-                               void* shadow, fhash_dtype sdt, hipStream_t st);
+                               void* shadow, fhash_dtype sdt, uint32_t phases, hipStream_t st);
+hipError_t lazy_read_stats(const fhash_lazy* lz, int64_t* out, hipStream_t st);
 hipError_t launch_lazy_step(const fhash_adam_desc* o, const fhash_lazy* lz,
                             const int32_t* found_inf, hipStream_t st);
 hipError_t launch_lazy_flush(const fhash_lazy* lz, float* p, float* gr, float* m, float* v,

@@ -15,10 +15,11 @@
 // State word per segment: {done, stamp}.  Prepare for step S+1 stores S+1
 // into stamp (atomic max; the first claimer appends {segment, old stamp} to
 // the step's list), then replays steps done+1..S of the new list entries; the
-// step's gradient is written by the caller's backward.  The step call only
-// records the constants (and whether found_inf skipped the step), runs the
-// dense update outside the range and empties the list; the gradient step of an
-// enrolled segment is applied by its next catch-up or by the flush.
+// step's gradient is written by the caller's backward; every catch-up empties
+// the list.  The step call only records the constants (and whether found_inf
+// skipped the step) and runs the dense update outside the range; the gradient
+// step of an enrolled segment is applied by its next catch-up or by the flush
+// (which lists every segment behind the last step and catches them up).
 #include "adam_dev.h"
 #include "common.h"
 #include "kernels.h"
@@ -28,11 +29,15 @@ namespace fh {
 namespace {
 
 constexpr int kSeg = FHASH_LAZY_FLOATS;
-static_assert(kSeg == 16, "one segment per 16 lanes");
-constexpr int kChunk = 1024;  // list entries a workgroup sorts by gap in LDS
+static_assert(kSeg == 16, "segments of 16 floats");
+constexpr int kChunk = 512;  // list entries a workgroup sorts by gap in LDS
 constexpr int kBins = 32;
 
-// Per-step record: {step_size, inv_bc2_sqrt, gscale, skipped (0 or 1)}.
+// Per-step record: {step_size, inv_bc2_sqrt, gscale, kind}; kind 0: a step
+// whose zero-gradient form is adam0 (finite gscale), 1: skipped (found_inf),
+// 2: applied with a non-finite gscale (zero-gradient form: adam1 itself).
+constexpr float kStep = 0.0f, kSkipped = 1.0f, kOddScale = 2.0f;
+
 __device__ __forceinline__ AdamK step_k(const float4 c, const AdamK& base) {
   AdamK k = base;
   k.step_size = c.x;
@@ -63,49 +68,118 @@ __device__ __forceinline__ int wave_excl_scan(int x, int& total) {
   return s - x;
 }
 
-// Bring one parameter per lane from step `done` to step `upto`.  `pend` (0:
-// none) is the step whose gradient `gg` is still to be applied; every other
-// missing step has a zero gradient.  A parameter with m = v = +0 and no
-// pending gradient is a fixed point of the replay (m, v stay +0 and
-// p - step_size * (+0 * 1/eps) == p) and is marked inactive by the caller.
-// The loop runs over steps in wave-uniform order, so each step's constants
-// are one uniform load; lanes whose segment starts later wait.
-__device__ __forceinline__ void replay(const float4* __restrict__ rec, const AdamK& base,
-                                       bool active, uint32_t done, uint32_t pend, uint32_t upto,
-                                       float gg, float& p, float& m, float& v) {
-  const uint32_t j0 = wave_min_u32(active ? done + 1 : 0xffffffffu);
-  for (uint32_t j = j0; j <= upto; ++j) {
-    const float4 c = rec[j];
-    if (active && j > done && c.w == 0.0f) adam1(step_k(c, base), j == pend ? gg : 0.0f, p, m, v);
+// Four parameters per lane (a float4), four lanes per segment.
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kLanesPerSeg = kSeg / 4;
+
+__device__ __forceinline__ void adam1_4(const AdamK& k, f4v g, f4v& p, f4v& m, f4v& v) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float pc = p[c], mc = m[c], vc = v[c];
+    adam1(k, g[c], pc, mc, vc);
+    p[c] = pc, m[c] = mc, v[c] = vc;
   }
 }
 
-// Catch-up of one segment by its 16 lanes (`sub`): loads, replay, stores,
-// gradient reset and the state's `done`.  stale: done < upto.
-__device__ __forceinline__ void catch_up_lanes(
-    uint32_t seg, uint32_t done, uint32_t pend, bool stale, int sub, const float4* rec,
-    const AdamK& base, float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
-    float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t begin, int64_t end,
-    uint32_t upto) {
-  const int64_t f = begin + (int64_t)seg * kSeg + sub;
-  // a segment never stepped (done == 0, nothing pending) holds m = v = 0
-  const bool work = stale && f < end && !(pend == 0 && done == 0);
-  float pp = 0.f, mm = 0.f, vv = 0.f, gg = 0.f;
-  if (work) {
-    pp = p[f];
-    mm = m[f];
-    vv = v[f];
-    if (pend != 0) gg = g[f];
+__device__ __forceinline__ void adam0_4(const AdamK& k, f4v& p, f4v& m, f4v& v) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float pc = p[c], mc = m[c], vc = v[c];
+    adam0(k, pc, mc, vc);
+    p[c] = pc, m[c] = mc, v[c] = vc;
   }
-  const bool active = work && (pend != 0 || (__float_as_uint(mm) | __float_as_uint(vv)) != 0u);
-  replay(rec, base, active, done, pend, upto, gg, pp, mm, vv);
+}
+
+// Bring a lane's four parameters from step `done` to step `upto`.  `pend`
+// (0: none; else done + 1) is the step whose gradient `g` is still to be
+// applied; every other missing step has a zero gradient.  Parameters with
+// m = v = +0 and no pending gradient are fixed points of such steps (m, v stay
+// +0 and fma(-step_size, +0, p) == p), so a lane whose four are all of that
+// kind is marked inactive by the caller.  The zero-gradient steps run in
+// wave-uniform order, so each step's record is one uniform load; lanes whose
+// segment starts later wait.
+template <bool ODD>
+__device__ __forceinline__ void replay(const float4* __restrict__ rec, const AdamK& base,
+                                       bool active, uint32_t done, uint32_t pend, uint32_t upto,
+                                       f4v g, f4v& p, f4v& m, f4v& v) {
+  if (active && pend != 0) {
+    const float4 c = rec[pend];
+    if (c.w != kSkipped) adam1_4(step_k(c, base), g, p, m, v);
+    done = pend;
+  }
+  const uint32_t j0 = wave_min_u32(active ? done + 1 : 0xffffffffu);
+  for (uint32_t j = j0; j <= upto; ++j) {
+    const float4 c = rec[j];
+    if (c.w == kStep) {
+      if (active && j > done) adam0_4(step_k(c, base), p, m, v);
+    } else if (ODD && c.w == kOddScale) {
+      if (active && j > done) adam1_4(step_k(c, base), (f4v){0.f, 0.f, 0.f, 0.f}, p, m, v);
+    }
+  }
+}
+
+// Catch-up of one segment by its 4 lanes (`sub`), in two parts so that the
+// loads of the next segments are in flight while these replay.
+struct Lane {
+  int64_t f;  // first of the lane's four floats
+  uint32_t seg, done, pend;
+  bool stale, work;
+  f4v p, m, v, g;
+};
+
+// Loads.  stale: done < upto.  A segment never stepped (done == 0, nothing
+// pending) holds m = v = 0 and needs no loads.  begin is a multiple of 16 and
+// end of 4, so a lane's four floats are all inside the range or all outside.
+__device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t pend, bool stale,
+                                           int sub, const float* __restrict__ p,
+                                           const float* __restrict__ g,
+                                           const float* __restrict__ m,
+                                           const float* __restrict__ v, int64_t begin,
+                                           int64_t end) {
+  Lane L;
+  L.seg = seg;
+  L.done = done;
+  L.pend = pend;
+  L.stale = stale;
+  L.f = begin + (int64_t)seg * kSeg + 4 * sub;
+  L.work = stale && L.f < end && !(pend == 0 && done == 0);
+  const f4v z = {0.f, 0.f, 0.f, 0.f};
+  L.p = L.m = L.v = L.g = z;
+  if (L.work) {
+    L.p = *reinterpret_cast<const f4v*>(p + L.f);
+    L.m = *reinterpret_cast<const f4v*>(m + L.f);
+    L.v = *reinterpret_cast<const f4v*>(v + L.f);
+    if (pend != 0) L.g = *reinterpret_cast<const f4v*>(g + L.f);
+  }
+  return L;
+}
+
+__device__ __forceinline__ bool nonzero_state(const f4v m, const f4v v) {
+  uint32_t b = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) b |= __float_as_uint(m[c]) | __float_as_uint(v[c]);
+  return b != 0u;
+}
+
+// Replay, stores, gradient reset.  ODD: some recorded step has a non-finite
+// gscale (its zero-gradient form is adam1).
+template <bool ODD>
+__device__ __forceinline__ bool finish_lanes(Lane L, const float4* rec, const AdamK& base,
+                                             float* __restrict__ p, float* __restrict__ g,
+                                             float* __restrict__ m, float* __restrict__ v,
+                                             void* __restrict__ shadow, int sdt, uint32_t upto) {
+  const bool active = L.work && (L.pend != 0 || nonzero_state(L.m, L.v));
+  replay<ODD>(rec, base, active, L.done, L.pend, upto, L.g, L.p, L.m, L.v);
   if (active) {
-    p[f] = pp;
-    m[f] = mm;
-    v[f] = vv;
-    if (shadow != nullptr) store_shadow(shadow, sdt, f, pp);
+    *reinterpret_cast<f4v*>(p + L.f) = L.p;
+    *reinterpret_cast<f4v*>(m + L.f) = L.m;
+    *reinterpret_cast<f4v*>(v + L.f) = L.v;
+    if (shadow != nullptr)
+      for (int c = 0; c < 4; ++c) store_shadow(shadow, sdt, L.f + c, L.p[c]);
   }
-  if (work && pend != 0 && gg != 0.0f) g[f] = 0.0f;
+  if (L.work && L.pend != 0 && (L.g[0] != 0.f || L.g[1] != 0.f || L.g[2] != 0.f || L.g[3] != 0.f))
+    *reinterpret_cast<f4v*>(g + L.f) = (f4v){0.f, 0.f, 0.f, 0.f};
+  return active;
 }
 
 // Every segment of [begin, end) that the forward or backward of a sample reads
@@ -116,7 +190,7 @@ __global__ void __launch_bounds__(256)
     lazy_mark_kernel(GridDev g, int l0, int l1, const float4* __restrict__ pos, int64_t n,
                      uint2* __restrict__ state, uint2* __restrict__ list,
                      unsigned long long* __restrict__ count, int64_t begin, int64_t end,
-                     uint32_t target) {
+                     uint32_t target, unsigned long long cap) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int F = g.F;
   // the loop bound is wave-uniform: every lane takes part in the appends
@@ -173,7 +247,12 @@ __global__ void __launch_bounds__(256)
       at = __shfl(at, 0, 64) + off;
 #pragma unroll
       for (int c = 0; c < 16; ++c)
-        if (won & (1u << c)) list[at++] = make_uint2(cand[c], prev[c]);
+        if (won & (1u << c)) {
+          // the bound always holds: the list has one entry per segment, and a
+          // segment is listed at most once between two catch-ups
+          if (at < cap) list[at] = make_uint2(cand[c], prev[c]);
+          ++at;
+        }
     }
   }
 }
@@ -186,20 +265,27 @@ __device__ __forceinline__ int gap_bin(uint32_t gap) {  // gap >= 1
   return b < kBins ? b : kBins - 1;
 }
 
-// Catch-up of the list entries [ctr[1], ctr[0]) to step `upto`.  Each
+// Catch-up of the list entries [ctr[1], ctr[0]) to step `upto`; ctr[2..5]
+// accumulate the segments caught up, those that loaded data, those with a
+// pending gradient and the segment-steps replayed (workload statistics).  Each
 // workgroup takes chunks of kChunk entries, sorts them by the number of steps
 // to replay (counting sort in LDS) and runs them 16 at a time, so that the
 // four segments of a wave replay about as many steps.
+template <bool ODD>
 __global__ void __launch_bounds__(256)
-    lazy_catchup_kernel(const uint2* __restrict__ list, const unsigned long long* ctr,
+    lazy_catchup_kernel(const uint2* __restrict__ list, unsigned long long* ctr,
                         uint2* __restrict__ state, const float4* __restrict__ rec, AdamK base,
                         float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                         float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t begin,
-                        int64_t end, uint32_t upto) {
+                        int64_t end, uint32_t upto, int64_t cap) {
   __shared__ uint4 srt[kChunk];
   __shared__ int hist[kBins], boff[kBins];
-  const int64_t lo = (int64_t)ctr[1], hi = (int64_t)ctr[0];
-  const int sub = threadIdx.x & (kSeg - 1);
+  __shared__ unsigned long long tally[4];
+  if (threadIdx.x < 4) tally[threadIdx.x] = 0ull;
+  unsigned long long n_stale = 0, n_work = 0, n_pend = 0, n_steps = 0;
+  const int64_t lo = (int64_t)ctr[1];
+  const int64_t hi = (int64_t)ctr[0] < cap ? (int64_t)ctr[0] : cap;
+  const int sub = threadIdx.x & (kLanesPerSeg - 1);
   for (int64_t c0 = lo + (int64_t)blockIdx.x * kChunk; c0 < hi; c0 += (int64_t)gridDim.x * kChunk) {
     const int nloc = (int)((hi - c0) < kChunk ? (hi - c0) : kChunk);
     if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
@@ -232,59 +318,74 @@ __global__ void __launch_bounds__(256)
     for (int k = 0; k < kChunk / 256; ++k)
       if (bin[k] >= 0) srt[boff[bin[k]] + rank[k]] = ent[k];
     __syncthreads();
-    for (int r0 = 0; r0 < nloc; r0 += 256 / kSeg) {
-      const int e = r0 + (int)(threadIdx.x / kSeg);
+    // software-pipelined rounds of 64 segments: load round r+1, replay round r
+    auto fetch = [&](int r0) {
+      const int e = r0 + (int)(threadIdx.x / kLanesPerSeg);
       const uint4 en = e < nloc ? srt[e] : make_uint4(0u, upto, 0u, 0u);
-      const bool stale = e < nloc && en.y < upto;
-      catch_up_lanes(en.x, en.y, en.z, stale, sub, rec, base, p, g, m, v, shadow, sdt, begin,
-                     end, upto);
-      if (stale && sub == 0) state[en.x].x = upto;
+      return load_lanes(en.x, en.y, en.z, e < nloc && en.y < upto, sub, p, g, m, v, begin, end);
+    };
+    Lane cur = fetch(0);
+    for (int r0 = 0; r0 < nloc; r0 += 256 / kLanesPerSeg) {
+      const Lane nxt = fetch(r0 + 256 / kLanesPerSeg);
+      const bool active = finish_lanes<ODD>(cur, rec, base, p, g, m, v, shadow, sdt, upto);
+      if (cur.stale && sub == 0) {
+        state[cur.seg].x = upto;
+        n_stale += 1;
+        n_work += cur.work;
+        n_pend += cur.work && cur.pend != 0;
+        if (active) n_steps += upto - cur.done;
+      }
+      cur = nxt;
     }
     __syncthreads();  // srt and hist are reused by the next chunk
   }
+  if (n_stale) {
+    atomicAdd(&tally[0], n_stale);
+    atomicAdd(&tally[1], n_work);
+    atomicAdd(&tally[2], n_pend);
+    atomicAdd(&tally[3], n_steps);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 && tally[threadIdx.x] != 0ull) atomicAdd(&ctr[2 + threadIdx.x], tally[threadIdx.x]);
 }
 
-// Every segment up to step `upto` (a pass over all state words).  A segment
-// enrolled in the open step (stamp == upto + 1) keeps its stamp.
+// Flush, first part: append every segment behind step `upto` to the list as
+// {segment, stamp} (its stamp <= upto: a segment enrolled in the open step is
+// already at upto), one counter atomic per wave.  The catch-up kernel then
+// applies its pending gradient step (stamp > done) and replays the rest.
 __global__ void __launch_bounds__(256)
-    lazy_flush_kernel(int64_t nseg, uint2* __restrict__ state, const float4* __restrict__ rec,
-                      AdamK base, float* __restrict__ p, float* __restrict__ g,
-                      float* __restrict__ m, float* __restrict__ v, void* __restrict__ shadow,
-                      int sdt, int64_t begin, int64_t end, uint32_t upto) {
-  const int sub = threadIdx.x & (kSeg - 1);
-  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kSeg);
-  // wave-uniform trip count: every lane reaches the replay's shuffles
-  const int64_t first = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSeg;
-  const int64_t wave_first = first - (threadIdx.x & 63) / kSeg;
-  for (int64_t base_seg = wave_first; base_seg < nseg; base_seg += groups) {
-    const int64_t seg = base_seg + (threadIdx.x & 63) / kSeg;
-    const bool in = seg < nseg;
-    const uint2 st = in ? state[seg] : make_uint2(upto, upto);
-    const uint32_t pend = (st.y > st.x && st.y <= upto) ? st.y : 0u;
-    const bool stale = in && st.x < upto;
-    catch_up_lanes((uint32_t)seg, st.x, pend, stale, sub, rec, base, p, g, m, v, shadow, sdt,
-                   begin, end, upto);
-    if (stale && sub == 0) state[seg] = make_uint2(upto, st.y > upto ? st.y : upto);
+    lazy_compact_kernel(int64_t nseg, const uint2* __restrict__ state, uint2* __restrict__ list,
+                        unsigned long long* __restrict__ count, uint32_t upto) {
+  // runs on an empty list (the flush catches up first): at most nseg entries
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nseg; base += stride) {
+    const int64_t seg = base + threadIdx.x;
+    const uint2 st = seg < nseg ? state[seg] : make_uint2(upto, upto);
+    const bool stale = st.x < upto;
+    const unsigned long long mask = __ballot(stale);
+    if (mask == 0ull) continue;
+    unsigned long long at = 0;
+    if (lane == 0) at = atomicAdd(count, (unsigned long long)__popcll(mask));
+    at = __shfl(at, 0, 64) + __popcll(mask & ((1ull << lane) - 1ull));
+    if (stale && at < (unsigned long long)nseg) list[at] = make_uint2((uint32_t)seg, st.y);
   }
 }
 
 __global__ void lazy_record_kernel(float4* rec, int64_t t, float step_size, float inv_bc2_sqrt,
                                    float gscale, const int32_t* found_inf) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const float skipped = (found_inf != nullptr && *found_inf != 0) ? 1.0f : 0.0f;
-    rec[t] = make_float4(step_size, inv_bc2_sqrt, gscale, skipped);
+    const bool skipped = found_inf != nullptr && *found_inf != 0;
+    const float kind = skipped ? kSkipped : (isfinite(gscale) ? kStep : kOddScale);
+    rec[t] = make_float4(step_size, inv_bc2_sqrt, gscale, kind);
   }
 }
 
-// ctr[1] = ctr[0] (entries caught up), or both = 0 (list emptied).
-__global__ void lazy_counters_kernel(unsigned long long* ctr, int empty) {
+// Empty the list (after a catch-up every entry has been consumed).
+__global__ void lazy_empty_list_kernel(unsigned long long* ctr) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (empty) {
-      ctr[0] = 0ull;
-      ctr[1] = 0ull;
-    } else {
-      ctr[1] = ctr[0];
-    }
+    ctr[0] = 0ull;
+    ctr[1] = 0ull;
   }
 }
 
@@ -332,6 +433,18 @@ AdamK lazy_base(const fhash_lazy* lz) {
 // device): grid-strided over chunks.
 constexpr unsigned kListBlocks = 2048;
 
+// Catch up the listed segments to step `steps`, then empty the list.
+void launch_catch_up(const fhash_lazy* lz, const LazyWs& w, float* p, float* gr, float* m,
+                     float* v, void* shadow, fhash_dtype sdt, hipStream_t st) {
+  const int64_t nseg = lazy_num_segments(lz->end - lz->begin);
+  const bool odd = (lz->flags & 1) != 0;
+  hipLaunchKernelGGL(odd ? lazy_catchup_kernel<true> : lazy_catchup_kernel<false>,
+                     dim3(kListBlocks), dim3(256), 0, st, w.list, w.ctr, w.state, w.rec,
+                     lazy_base(lz), p, gr, m, v, shadow, (int)sdt, lz->begin, lz->end,
+                     (uint32_t)lz->steps, nseg);
+  hipLaunchKernelGGL(lazy_empty_list_kernel, dim3(1), dim3(64), 0, st, w.ctr);
+}
+
 }  // namespace
 
 int64_t lazy_num_segments(int64_t range_floats) { return (range_floats + kSeg - 1) / kSeg; }
@@ -355,20 +468,18 @@ hipError_t launch_lazy_init(const fhash_lazy* lz, hipStream_t st) {
 
 hipError_t launch_lazy_prepare(const GridDev& g, int l0, int l1, const float* pos, int64_t n,
                                const fhash_lazy* lz, float* p, float* gr, float* m, float* v,
-                               void* shadow, fhash_dtype sdt, hipStream_t st) {
+                               void* shadow, fhash_dtype sdt, uint32_t phases, hipStream_t st) {
   const LazyWs w = carve(lz);
   const uint32_t S = (uint32_t)lz->steps;
-  if (n > 0 && l0 < l1) {
+  const int64_t nseg = lazy_num_segments(lz->end - lz->begin);
+  if ((phases & FHASH_LAZY_MARK) && n > 0 && l0 < l1) {
     int64_t b = (n + 255) / 256;
     if (b > 4096) b = 4096;
     hipLaunchKernelGGL(lazy_mark_kernel, dim3((unsigned)b), dim3(256), 0, st, g, l0, l1,
                        reinterpret_cast<const float4*>(pos), n, w.state, w.list, w.ctr,
-                       lz->begin, lz->end, S + 1);
+                       lz->begin, lz->end, S + 1, (unsigned long long)nseg);
   }
-  hipLaunchKernelGGL(lazy_catchup_kernel, dim3(kListBlocks), dim3(256), 0, st, w.list, w.ctr,
-                     w.state, w.rec, lazy_base(lz), p, gr, m, v, shadow, (int)sdt, lz->begin,
-                     lz->end, S);
-  hipLaunchKernelGGL(lazy_counters_kernel, dim3(1), dim3(64), 0, st, w.ctr, 0);
+  if (phases & FHASH_LAZY_CATCH_UP) launch_catch_up(lz, w, p, gr, m, v, shadow, sdt, st);
   return hipGetLastError();
 }
 
@@ -378,8 +489,17 @@ hipError_t launch_lazy_step(const fhash_adam_desc* o, const fhash_lazy* lz, cons
   const AdamK k = make_adam_k(o);
   hipLaunchKernelGGL(lazy_record_kernel, dim3(1), dim3(64), 0, st, w.rec, lz->steps + 1,
                      k.step_size, k.inv_bc2_sqrt, k.gscale, found_inf);
-  hipLaunchKernelGGL(lazy_counters_kernel, dim3(1), dim3(64), 0, st, w.ctr, 1);
   return hipGetLastError();
+}
+
+hipError_t lazy_read_stats(const fhash_lazy* lz, int64_t* out, hipStream_t st) {
+  const LazyWs w = carve(lz);
+  unsigned long long h[4];
+  hipError_t e = hipMemcpyAsync(h, w.ctr + 2, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess)
+    for (int i = 0; i < 4; ++i) out[i] = (int64_t)h[i];
+  return e;
 }
 
 hipError_t launch_lazy_flush(const fhash_lazy* lz, float* p, float* gr, float* m, float* v,
@@ -387,11 +507,13 @@ hipError_t launch_lazy_flush(const fhash_lazy* lz, float* p, float* gr, float* m
   const LazyWs w = carve(lz);
   const int64_t nseg = lazy_num_segments(lz->end - lz->begin);
   if (nseg == 0 || lz->steps == 0) return hipSuccess;
-  int64_t b = (nseg * kSeg + 255) / 256;
+  // segments marked without their catch-up first: the list is then empty
+  launch_catch_up(lz, w, p, gr, m, v, shadow, sdt, st);
+  int64_t b = (nseg + 255) / 256;
   if (b > 65536) b = 65536;
-  hipLaunchKernelGGL(lazy_flush_kernel, dim3((unsigned)b), dim3(256), 0, st, nseg, w.state, w.rec,
-                     lazy_base(lz), p, gr, m, v, shadow, (int)sdt, lz->begin, lz->end,
-                     (uint32_t)lz->steps);
+  hipLaunchKernelGGL(lazy_compact_kernel, dim3((unsigned)b), dim3(256), 0, st, nseg, w.state,
+                     w.list, w.ctr, (uint32_t)lz->steps);
+  launch_catch_up(lz, w, p, gr, m, v, shadow, sdt, st);
   return hipGetLastError();
 }
 

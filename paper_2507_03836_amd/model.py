@@ -177,12 +177,12 @@ class FHashModel:
         o.grad_scale = grad_scale
         return o
 
-    def prepare(self, pos: torch.Tensor):
+    def prepare(self, pos: torch.Tensor, phases: int = fl.LAZY_PREPARE):
         """Under deferred Adam: bring the table rows that pos reads up to date
         (and enrol them in the next step)."""
         if self.lazy is not None:
             fl.fhash_lazy_prepare(self.index, pos, pos.shape[0], self.lazy, self.params,
-                                  self.grads, self.m, self.v, shadow=self.shadow)
+                                  self.grads, self.m, self.v, shadow=self.shadow, phases=phases)
 
     def flush(self):
         """Under deferred Adam: bring every parameter up to date and apply the

@@ -134,6 +134,10 @@ def test_lazy_replay_is_exercised(fl):
         lazy.optimizer_step()
     n = dense.n_table
     assert not torch.equal(lazy.params[:n], dense.params[:n])
+    st = fl.fhash_lazy_stats(lazy.lazy)
+    # the 8-sample steps re-read some step-1 rows: loaded, pending, replayed
+    assert 0 < st["pending"] <= st["loaded"] <= st["segments"]
+    assert st["segment_steps"] >= st["pending"]
     lazy.flush()
     _same(lazy.params[:n], dense.params[:n], "params after flush")
     _same(lazy.m[:n], dense.m[:n], "m after flush")
@@ -161,3 +165,30 @@ def test_lazy_limits(fl):
         fl.fhash_step_lazy(opt, lazy.params[: lazy.n_params], lazy.grads[: lazy.n_params],
                            lazy.m[: lazy.n_params], lazy.v[: lazy.n_params], lz2)
     assert e.value.code == fl.EINVAL
+    with pytest.raises(fl.FHashError) as e:
+        fl.fhash_lazy_prepare(lazy.index, pos, 16, lz2, lazy.params, lazy.grads, lazy.m, lazy.v,
+                              phases=4)
+    assert e.value.code == fl.EINVAL
+
+
+def test_split_phases_equal_one_call(fl):
+    """Mark and catch-up called separately (as the benchmark times them), once
+    with a flush in between, give the same trajectory as the combined prepare."""
+    _, _, b = _pair("fp32", 0)
+    _, _, c = _pair("fp32", 0)
+    g = torch.Generator().manual_seed(9)
+    for s in range(6):
+        pos = torch.rand(200, 4, generator=g).cuda()
+        tgt = torch.rand(200, generator=g).cuda()
+        b.fwd_bwd(pos, tgt)  # combined prepare, then the fused backward
+        c.prepare(pos, fl.LAZY_MARK)
+        if s == 3:
+            c.flush()  # between a mark and its catch-up: the flush catches up first
+        c.prepare(pos, fl.LAZY_CATCH_UP)
+        c.grads.copy_(b.grads)  # the same gradient (no second summation order)
+        b.optimizer_step()
+        c.optimizer_step()
+    b.flush()
+    c.flush()
+    for name in ("params", "m", "v", "grads"):
+        _same(getattr(b, name), getattr(c, name), name)
