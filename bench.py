@@ -47,8 +47,8 @@ LAZY_ENTRY_BYTES, LAZY_LOADED_BYTES, LAZY_PENDING_BYTES, LAZY_SHADOW_BYTES = 16,
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (copy-calibrated, per launch, averaged
 # over the timed steps); valid only for the sources, parameter count, batch and step count
 # they were taken on.
-CATCHUP_TRAFFIC = {"bytes": None, "params": 6390343593, "batch": 1 << 18, "steps": 200,
-                   "source_md5": ""}
+CATCHUP_TRAFFIC = {"bytes": 12.98e9, "params": 6390343593, "batch": 1 << 18, "steps": 200,
+                   "source_md5": "d01071dd2a7bd0897c4702bafb05c1c5"}
 
 
 def log(*a):

@@ -502,6 +502,8 @@ int fhash_lazy_prepare(const fhash_index* idx, const float* pos, int64_t n, fhas
     return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
   if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
     return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
+  if (shadow != nullptr && (reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)
+    return fail(FHASH_EINVAL, "shadow must be 8-byte aligned");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
   int l0, l1;
@@ -561,6 +563,8 @@ int fhash_lazy_flush(fhash_lazy* lz, float* param, float* grad, float* m, float*
     return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
   if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
     return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
+  if (shadow != nullptr && (reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)
+    return fail(FHASH_EINVAL, "shadow must be 8-byte aligned");
   return hip_status(fh::launch_lazy_flush(lz, param, grad, m, v, shadow, shadow_dt, S(stream)),
                     "fhash_lazy_flush");
 }

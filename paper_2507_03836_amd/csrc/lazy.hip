@@ -154,6 +154,20 @@ __device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t
   return L;
 }
 
+// The four shadow values of a lane in one 8-byte store (f: a multiple of 4).
+__device__ __forceinline__ void store_shadow_group(void* shadow, int sdt, int64_t f, const f4v x) {
+  uint32_t lo, hi;
+  if (sdt == FHASH_F16) {
+    const __half2 a = __floats2half2_rn(x[0], x[1]), b = __floats2half2_rn(x[2], x[3]);
+    lo = *reinterpret_cast<const uint32_t*>(&a);
+    hi = *reinterpret_cast<const uint32_t*>(&b);
+  } else {
+    lo = (uint32_t)to_bf16_rne(x[0]) | ((uint32_t)to_bf16_rne(x[1]) << 16);
+    hi = (uint32_t)to_bf16_rne(x[2]) | ((uint32_t)to_bf16_rne(x[3]) << 16);
+  }
+  reinterpret_cast<uint2*>(shadow)[f / 4] = make_uint2(lo, hi);
+}
+
 __device__ __forceinline__ bool nonzero_state(const f4v m, const f4v v) {
   uint32_t b = 0;
 #pragma unroll
@@ -174,8 +188,7 @@ __device__ __forceinline__ bool finish_lanes(Lane L, const float4* rec, const Ad
     *reinterpret_cast<f4v*>(p + L.f) = L.p;
     *reinterpret_cast<f4v*>(m + L.f) = L.m;
     *reinterpret_cast<f4v*>(v + L.f) = L.v;
-    if (shadow != nullptr)
-      for (int c = 0; c < 4; ++c) store_shadow(shadow, sdt, L.f + c, L.p[c]);
+    if (shadow != nullptr) store_shadow_group(shadow, sdt, L.f, L.p);
   }
   if (L.work && L.pend != 0 && (L.g[0] != 0.f || L.g[1] != 0.f || L.g[2] != 0.f || L.g[3] != 0.f))
     *reinterpret_cast<f4v*>(g + L.f) = (f4v){0.f, 0.f, 0.f, 0.f};

@@ -62,17 +62,22 @@ def _same(a, b, what):
                        b.view(torch.int32) if b.dtype == torch.float32 else b), what
 
 
-def _fresh_grad(lazy):
-    """The gradient the open step's backward wrote: in the deferred range only
-    the segments enrolled in that step (others may still hold an earlier
-    step's gradient, applied at their next catch-up), all of it elsewhere."""
+def _fresh_mask(lazy):
+    """Where the open step's backward writes: in the deferred range only the
+    segments enrolled in that step (others may still hold an earlier step's
+    gradient, applied at their next catch-up), everywhere else."""
     lz = lazy.lazy
     b, e = lz.desc.begin, lz.desc.end
     nseg = (e - b + 15) // 16
     stamp = lz.ws[: nseg * 8].view(torch.int32).view(nseg, 2)[:, 1]
     mask = torch.ones(lazy.grads.numel(), dtype=torch.bool, device=lazy.grads.device)
     mask[b:e] = (stamp == lz.steps + 1).repeat_interleave(16)[: e - b]
-    return torch.where(mask, lazy.grads, torch.zeros_like(lazy.grads))
+    return mask
+
+
+def _fresh_grad(lazy):
+    """The gradient the open step's backward wrote."""
+    return torch.where(_fresh_mask(lazy), lazy.grads, torch.zeros_like(lazy.grads))
 
 
 def _run(fl, dense, lazy, steps, batch, flush_at=(), inf_at=()):
@@ -185,7 +190,9 @@ def test_split_phases_equal_one_call(fl):
         if s == 3:
             c.flush()  # between a mark and its catch-up: the flush catches up first
         c.prepare(pos, fl.LAZY_CATCH_UP)
-        c.grads.copy_(b.grads)  # the same gradient (no second summation order)
+        # the same fresh gradient (no second summation order); c keeps its own
+        # pending gradients, which its flush may already have applied
+        c.grads.copy_(torch.where(_fresh_mask(b), b.grads, c.grads))
         b.optimizer_step()
         c.optimizer_step()
     b.flush()
