@@ -70,6 +70,10 @@ def parse():
     ap.add_argument("--optimizer", choices=["lazy", "tracked", "dense"], default="lazy",
                     help="Adam over the large levels: deferred (same values, bit for bit), "
                          "dense with touched-segment gradient reads, or plain dense")
+    ap.add_argument("--dense-index", action="store_true",
+                    help="index every vertex of the box (the F-Hash equation, no feature mask) "
+                         "instead of the vertices of active cells; samples still come from "
+                         "the coreset")
     ap.add_argument("--hidden-layers", type=int, default=2)
     ap.add_argument("--sort", action="store_true",
                     help="sort each batch by a 4D Morton key before the fused step")
@@ -507,7 +511,8 @@ def main():
     res = geometric_resolutions(args.levels, 16, 512, 4, dims[3], dims)
     cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers)
     t0 = time.time()
-    model = FHashModel(cfg, gen["bits"], dims, init_seed=3000 + args.field_seed - 1000,
+    model = FHashModel(cfg, None if args.dense_index else gen["bits"], dims,
+                       init_seed=3000 + args.field_seed - 1000,
                        precision=args.precision, track_touched=args.optimizer == "tracked",
                        lazy=args.optimizer == "lazy",
                        max_steps=max(args.max_steps, args.warmup + args.steps) + 64)
@@ -645,7 +650,9 @@ def main():
                                 f"{args.levels} levels x 2 features, MLP "
                                 + "-".join(map(str, cfg.width))
                                 + f", batch 2^{int(np.log2(B))} coreset draws"
-                                + (", Morton-sorted batches" if args.sort else "")),
+                                + (", Morton-sorted batches" if args.sort else "")
+                                + (", dense index (every box vertex)" if args.dense_index
+                                   else "")),
                    "shape": dims, "levels": args.levels, "batch": B,
                    "active_vertices": model.rows, "params": model.n_params,
                    "coreset": M},
