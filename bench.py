@@ -70,6 +70,10 @@ def parse():
     ap.add_argument("--optimizer", choices=["lazy", "tracked", "dense"], default="lazy",
                     help="Adam over the large levels: deferred (same values, bit for bit), "
                          "dense with touched-segment gradient reads, or plain dense")
+    ap.add_argument("--key-frames", type=int, default=0,
+                    help="K > 1: train on every K-th timestep only (finest temporal "
+                         "resolution = number of key frames) and report PSNR on seen and "
+                         "unseen frames next to a model trained on every frame")
     ap.add_argument("--dense-index", action="store_true",
                     help="index every vertex of the box (the F-Hash equation, no feature mask) "
                          "instead of the vertices of active cells; samples still come from "
@@ -181,6 +185,72 @@ def time_to_psnr(args, model, step, gen, dims, t_train0, k_done):
             "seconds": reached[1] if reached else None,
             "final_psnr_db": hist[-1][2], "history": hist,
             "probe": "2^22 coreset draws, PSNR over data range 1, FP64 sum on the device"}
+
+
+def key_frame_bench(args):
+    """Key-frame training with temporal super-resolution: samples only from the voxels of
+    every K-th timestep, the finest temporal resolution equal to the number of key frames;
+    PSNR on coreset draws at the key frames (seen) and at the frames between them
+    (unseen), next to the same model trained on every frame for the same steps."""
+    import numpy as np
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd import synth
+    from paper_2507_03836_amd.model import (FHashConfig, FHashModel, geometric_resolutions,
+                                            psnr_on)
+    fl.lib()
+    dims = [int(x) for x in args.shape.split(",")]
+    K = args.key_frames
+    gen = synth.production_volume_gpu(dims, seed=args.field_seed)
+    core = gen["coreset"]
+    frame = core // (dims[0] * dims[1] * dims[2])
+    key = core[frame % K == 0].contiguous()
+    unseen = core[frame % K != 0].contiguous()
+    del frame
+    n_kf = (dims[3] - 1) // K + 1
+    P = 1 << 22
+    probes = {}
+    for name, c, seed in (("seen", key, 7001), ("unseen", unseen, 7002)):
+        pp = torch.empty(P, 4, device="cuda")
+        pt = torch.empty(P, device="cuda")
+        fl.fhash_sample(seed, 1, P, c, c.numel(), dims, gen["field"], pp, pt)
+        probes[name] = (pp, pt)
+    B = args.batch
+    pos = torch.empty(B, 4, device="cuda")
+    tgt = torch.empty(B, device="cuda")
+    out = {"metric": "probe PSNR (dB) on seen and unseen frames after key-frame training",
+           "unit": "dB", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"F-Hash key-frame training, {'x'.join(map(str, dims))} "
+                                  f"synthetic volume, every {K}th of {dims[3]} timesteps "
+                                  f"({n_kf} key frames), batch 2^{int(np.log2(B))}, "
+                                  f"{args.steps} steps",
+                      "key_frames": n_kf, "key_voxels": int(key.numel()),
+                      "unseen_voxels": int(unseen.numel())},
+           "runs": {}}
+    for label, c, rt in (("key_frames", key, n_kf), ("all_frames", core, dims[3])):
+        res = geometric_resolutions(args.levels, 16, 512, 4, rt, dims)
+        cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers)
+        model = FHashModel(cfg, gen["bits"], dims, init_seed=3000, lazy=True,
+                           max_steps=args.steps + 8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            fl.fhash_sample(args.sampler_seed, k + 1, B, c, c.numel(), dims, gen["field"], pos,
+                            tgt)
+            model.fwd_bwd(pos, tgt)
+            model.optimizer_step()
+        model.flush()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        r = {"train_s": secs, "params": model.n_params, "temporal_res_finest": res[-1][3]}
+        for name, (pp, pt) in probes.items():
+            r[f"psnr_{name}_db"] = psnr_on(model, pp, pt)
+        out["runs"][label] = r
+        log(f"[keyframes] {label}: {r}")
+        model.params = model.grads = model.m = model.v = None
+        del model
+        torch.cuda.empty_cache()
+    out["value"] = out["runs"]["key_frames"]["psnr_unseen_db"]
+    print(json.dumps(out), flush=True)
 
 
 def serve_multi_bench(args):
@@ -494,6 +564,8 @@ def main():
 
     if args.serve_multi:
         return serve_multi_bench(args)
+    if args.key_frames > 1:
+        return key_frame_bench(args)
     if args.serve:
         return serve_bench(args)
 
