@@ -74,6 +74,9 @@ def parse():
                     help="K > 1: train on every K-th timestep only (finest temporal "
                          "resolution = number of key frames) and report PSNR on seen and "
                          "unseen frames next to a model trained on every frame")
+    ap.add_argument("--hash-bits", type=int, default=0,
+                    help="b > 0: the spatial-hash comparison index instead of F-Hash (levels "
+                         "of more than 2^b vertices hash into 2^b rows, collisions allowed)")
     ap.add_argument("--dense-index", action="store_true",
                     help="index every vertex of the box (the F-Hash equation, no feature mask) "
                          "instead of the vertices of active cells; samples still come from "
@@ -584,7 +587,7 @@ def main():
     cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers)
     t0 = time.time()
     model = FHashModel(cfg, None if args.dense_index else gen["bits"], dims,
-                       init_seed=3000 + args.field_seed - 1000,
+                       hash_bits=args.hash_bits, init_seed=3000 + args.field_seed - 1000,
                        precision=args.precision, track_touched=args.optimizer == "tracked",
                        lazy=args.optimizer == "lazy",
                        max_steps=max(args.max_steps, args.warmup + args.steps) + 64)
@@ -724,7 +727,9 @@ def main():
                                 + f", batch 2^{int(np.log2(B))} coreset draws"
                                 + (", Morton-sorted batches" if args.sort else "")
                                 + (", dense index (every box vertex)" if args.dense_index
-                                   else "")),
+                                   else "")
+                                + (f", spatial-hash index (2^{args.hash_bits} rows per large "
+                                   "level)" if args.hash_bits else "")),
                    "shape": dims, "levels": args.levels, "batch": B,
                    "active_vertices": model.rows, "params": model.n_params,
                    "coreset": M},

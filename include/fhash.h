@@ -77,7 +77,8 @@ typedef struct {
 typedef struct {
   fhash_grid_desc grid;
   int32_t active;   /* 0: dense box, every vertex has a slot; 1: active vertices only */
-  int32_t reserved;
+  int32_t hash_bits; /* 0, or b (dense box only): levels of more than 2^b vertices hash
+                        into 2^b rows (fhash_hash_index) */
   const void* dir;  /* device rank directory (16-byte entries), NULL when dense */
   int64_t dir_offset[FHASH_MAX_LEVELS + 1];  /* first directory entry of each level */
   int64_t slot_offset[FHASH_MAX_LEVELS + 1]; /* first table row of each level; [L] = rows */
@@ -119,6 +120,17 @@ int fhash_build_index(const fhash_grid_desc* grid, const fhash_mask_desc* mask, 
                       void* stream);
 /* Dense index (every vertex active): no device memory, no launch. */
 int fhash_dense_index(const fhash_grid_desc* grid, fhash_index* out, int64_t* slots_per_level);
+
+/* Comparison index, not the method: a 4D spatial hash in the manner of
+ * multiresolution hash encodings (the alternative discussed around Fig. 5 of
+ * Sec. 3.2.3), on the same kernels.  Levels of at most 2^hash_bits vertices
+ * keep the F-Hash equation (collision-free); a larger level has 2^hash_bits
+ * rows and vertex (x, y, z, t) lives in row
+ *   (x ^ y*2654435761 ^ z*805459861 ^ t*3674653429) mod 2^32 mod 2^hash_bits
+ * (32-bit unsigned products), so distinct vertices may share a row and every
+ * row may be used.  hash_bits in [4, 31].  Host only, no device memory. */
+int fhash_hash_index(const fhash_grid_desc* grid, int32_t hash_bits, fhash_index* out,
+                     int64_t* slots_per_level);
 
 /* -------------------------------------------------------------- encoding ----
  * Input encoding (Sec. 3.2.4): per level, locate the 4D cell containing the

@@ -183,10 +183,34 @@ def vertex_active_bits(res4, bits, dims, v):
     return bool(lib().or_vertex_active_bits(_p(r), _p(b), _p(S), _p(vv)))
 
 
-class Grid:
-    """Oracle-side level structure + (optional) active-vertex slot maps."""
+HASH_PRIMES = (1, 2654435761, 805459861, 3674653429)
 
-    def __init__(self, res, n_features, mask=None):
+
+def spatial_hash_slots(res4, bits: int):
+    """Comparison index (not the method; parity unpinned as values, pinned by
+    properties in tests/test_oracle_hash.py): the row of every vertex of a level
+    under the 4D spatial hash of multiresolution hash encodings, written from
+    its definition: with the F-Hash order lin = ((t Rz + z) Ry + y) Rx + x, row
+    = (x*1 XOR y*2654435761 XOR z*805459861 XOR t*3674653429) mod 2^32 mod
+    2^bits, products taken mod 2^32.  A level of at most 2^bits vertices keeps
+    the F-Hash equation (row = lin)."""
+    Rx, Ry, Rz, Rt = (int(v) for v in res4)
+    nv = Rx * Ry * Rz * Rt
+    lin = np.arange(nv, dtype=np.uint64)
+    if nv <= (1 << bits):
+        return lin.astype(np.int64), nv
+    coord = [lin % Rx, (lin // Rx) % Ry, (lin // (Rx * Ry)) % Rz, lin // (Rx * Ry * Rz)]
+    h = np.zeros(nv, np.uint64)
+    for c, prime in zip(coord, HASH_PRIMES):
+        h ^= (c * np.uint64(prime)) % np.uint64(1 << 32)
+    return (h % np.uint64(1 << bits)).astype(np.int64), 1 << bits
+
+
+class Grid:
+    """Oracle-side level structure + (optional) active-vertex slot maps.
+    hash_bits > 0 (no mask): the spatial-hash comparison index."""
+
+    def __init__(self, res, n_features, mask=None, hash_bits: int = 0):
         res = np.asarray(res, np.int64).reshape(-1, 4)
         self.res = res
         self.L = res.shape[0]
@@ -194,13 +218,18 @@ class Grid:
         self.maps = []
         self.counts = []
         for l in range(self.L):
+            if hash_bits:
+                m, c = spatial_hash_slots(res[l], hash_bits)
+                self.maps.append(m)
+                self.counts.append(c)
+                continue
             if mask is None:  # dense box: the slot is the F-Hash equation, no map needed
                 self.counts.append(int(np.prod(res[l])))
                 continue
             m, c = level_slots(res[l], mask)
             self.maps.append(m)
             self.counts.append(c)
-        self.dense = mask is None
+        self.dense = mask is None and not hash_bits
         self.slot_offset = np.zeros(self.L + 1, np.int64)
         self.slot_offset[1:] = np.cumsum(self.counts)
         self.vtx_offset = np.zeros(self.L + 1, np.int64)

@@ -39,7 +39,7 @@ class MaskDesc(C.Structure):
 
 
 class Index(C.Structure):
-    _fields_ = [("grid", GridDesc), ("active", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("grid", GridDesc), ("active", C.c_int32), ("hash_bits", C.c_int32),
                 ("dir", C.c_void_p), ("dir_offset", C.c_int64 * (MAX_LEVELS + 1)),
                 ("slot_offset", C.c_int64 * (MAX_LEVELS + 1))]
 
@@ -145,6 +145,7 @@ def _declare(L):
         "fhash_index_dir_entries": (C.c_int, [P, P]),
         "fhash_build_index": (C.c_int, [P, P, P, P, P, P, P, P]),
         "fhash_dense_index": (C.c_int, [P, P, P]),
+        "fhash_hash_index": (C.c_int, [P, I32, P, P]),
         "fhash_encode_fwd": (C.c_int, [P, P, I64, P, C.c_int, P, P]),
         "fhash_encode_bwd": (C.c_int, [P, P, I64, P, P, P, P]),
         "fhash_mlp_num_params": (I64, [P]),
@@ -184,7 +185,7 @@ def _declare(L):
 
 def exported_symbols() -> list[str]:
     return ["fhash_version", "fhash_last_error", "fhash_index_dir_entries", "fhash_build_index",
-            "fhash_dense_index", "fhash_encode_fwd", "fhash_encode_bwd", "fhash_mlp_num_params",
+            "fhash_dense_index", "fhash_hash_index", "fhash_encode_fwd", "fhash_encode_bwd", "fhash_mlp_num_params",
             "fhash_mlp_fwd", "fhash_mlp_bwd", "fhash_fused_fwd", "fhash_fused_bwd",
             "fhash_fused_train", "fhash_step", "fhash_check_finite", "fhash_cast",
             "fhash_sample", "fhash_sq_err_sum", "fhash_mse_grad", "fhash_render_state_bytes",
@@ -244,6 +245,15 @@ def fhash_index_dir_entries(grid: GridDesc) -> int:
     e = C.c_int64()
     _check(lib().fhash_index_dir_entries(C.byref(grid), C.byref(e)), "fhash_index_dir_entries")
     return e.value
+
+
+def fhash_hash_index(grid: GridDesc, hash_bits: int):
+    """Spatial-hash comparison index (host only): (index, rows per level)."""
+    idx = Index()
+    slots = (C.c_int64 * MAX_LEVELS)()
+    _check(lib().fhash_hash_index(C.byref(grid), int(hash_bits), C.byref(idx), slots),
+           "fhash_hash_index")
+    return idx, [int(slots[l]) for l in range(grid.n_levels)]
 
 
 def fhash_dense_index(grid: GridDesc):

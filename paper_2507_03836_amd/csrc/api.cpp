@@ -62,6 +62,8 @@ int check_index(const fhash_index* idx) {
   int rc = check_grid(&idx->grid);
   if (rc) return rc;
   if (idx->active != 0 && idx->active != 1) return fail(FHASH_EINVAL, "index.active must be 0/1");
+  if (idx->hash_bits != 0 && (idx->active || idx->hash_bits < 4 || idx->hash_bits > 31))
+    return fail(FHASH_EINVAL, "index.hash_bits must be 0, or in [4, 31] with a dense index");
   if (idx->active && idx->dir == nullptr) return fail(FHASH_EINVAL, "active index without dir");
   for (int l = 0; l < idx->grid.n_levels; ++l)
     if (idx->slot_offset[l + 1] < idx->slot_offset[l] || idx->slot_offset[l] < 0)
@@ -169,6 +171,25 @@ int fhash_dense_index(const fhash_grid_desc* grid, fhash_index* out, int64_t* sl
     out->slot_offset[l] = off;
     if (slots_per_level) slots_per_level[l] = nv;
     off += nv;
+  }
+  for (int l = grid->n_levels; l <= FHASH_MAX_LEVELS; ++l) out->slot_offset[l] = off;
+  return FHASH_OK;
+}
+
+int fhash_hash_index(const fhash_grid_desc* grid, int32_t hash_bits, fhash_index* out,
+                     int64_t* slots_per_level) {
+  if (hash_bits < 4 || hash_bits > 31) return fail(FHASH_EINVAL, "hash_bits %d outside [4, 31]", hash_bits);
+  int rc = fhash_dense_index(grid, out, nullptr);
+  if (rc) return rc;
+  out->hash_bits = hash_bits;
+  int64_t off = 0;
+  for (int l = 0; l < grid->n_levels; ++l) {
+    const int32_t* r = grid->res[l];
+    const int64_t nv = (int64_t)r[0] * r[1] * r[2] * r[3];
+    const int64_t rows = nv > (1ll << hash_bits) ? (1ll << hash_bits) : nv;
+    out->slot_offset[l] = off;
+    if (slots_per_level) slots_per_level[l] = rows;
+    off += rows;
   }
   for (int l = grid->n_levels; l <= FHASH_MAX_LEVELS; ++l) out->slot_offset[l] = off;
   return FHASH_OK;

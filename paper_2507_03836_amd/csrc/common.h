@@ -12,7 +12,7 @@ struct LevelDev {
   int32_t rx, ry, rz, rt;  // vertex counts
   float sx, sy, sz, st;    // (float)(R - 1), the FP32 scale of cell location
   int32_t wv;              // directory words per vertex row: ceil(rx / 64)
-  int32_t pad0;
+  int32_t hash_bits;       // 0, or b: the level's vertices hash into 2^b rows
   int64_t slot_off;        // first table row of the level
   int64_t dir_off;         // first directory entry of the level
   int64_t pad1;
@@ -53,10 +53,11 @@ inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
       d.wv = (d.rx + 63) / 64;
       d.slot_off = idx->slot_offset[l];
       d.dir_off = idx->dir_offset[l];
+      const double nv = (double)d.rx * d.ry * d.rz * d.rt;
+      d.hash_bits = (idx->hash_bits > 0 && nv > (double)(1ll << idx->hash_bits)) ? idx->hash_bits : 0;
     } else {
       d = LevelDev{};
     }
-    d.pad0 = 0;
     d.pad1 = 0;
   }
 }
@@ -79,9 +80,23 @@ __device__ __forceinline__ void locate(float p, int R, float s, int& cell, float
 // the word holding x.  Directory entries are stored ((tz*Wv + word)*Ry + y)
 // (rows y and y+1 of a cell are neighbours); the row and word indices are
 // 32-bit: the host rejects levels with 2^31 directory words or more.
+// Row of vertex (x, y, z, t) in a hashed level (see fhash_hash_index).
+__device__ __forceinline__ uint32_t spatial_hash(uint32_t x, uint32_t yzt, uint32_t mask) {
+  return (x ^ yzt) & mask;
+}
+
 __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglong2* dir,
                                                bool active, int32_t tz, int32_t y, int x,
                                                int64_t& s0, int64_t& s1, bool& v0, bool& v1) {
+  if (d.hash_bits) {
+    const uint32_t t = (uint32_t)tz / (uint32_t)d.rz, z = (uint32_t)tz - t * (uint32_t)d.rz;
+    const uint32_t yzt = (uint32_t)y * 2654435761u ^ z * 805459861u ^ t * 3674653429u;
+    const uint32_t mask = (d.hash_bits >= 32) ? 0xffffffffu : ((1u << d.hash_bits) - 1u);
+    s0 = d.slot_off + spatial_hash((uint32_t)x, yzt, mask);
+    s1 = d.slot_off + spatial_hash((uint32_t)x + 1u, yzt, mask);
+    v0 = v1 = true;
+    return;
+  }
   if (!active) {
     s0 = d.slot_off + ((int64_t)tz * d.ry + y) * d.rx + x;
     s1 = s0 + 1;

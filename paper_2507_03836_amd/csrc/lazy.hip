@@ -231,24 +231,26 @@ __global__ void __launch_bounds__(256)
         cand[2 * r] = cand[2 * r + 1] = 0;
         prev[2 * r] = prev[2 * r + 1] = 0;
         if (live && (v0 || v1)) {
-          // valid slots of a pair are consecutive: one float run of F or 2F
-          int64_t lo = (v0 ? s0 : s1) * F, hi = (v1 ? s1 : s0) * F + F - 1;
-          lo = lo < begin ? begin : lo;
-          hi = hi >= end ? end - 1 : hi;
-          if (lo <= hi) {
-            const uint32_t a = (uint32_t)((lo - begin) / kSeg), b = (uint32_t)((hi - begin) / kSeg);
-            cand[2 * r] = a;
-            cand[2 * r + 1] = b;
+          // F divides 16 and begin is a multiple of 16, so the F floats of a slot
+          // lie in one segment; the two slots of a pair are consecutive rows
+          // (active or dense index) or two hashed rows
+          const int64_t fa = (v0 ? s0 : s1) * F, fb = (v1 ? s1 : s0) * F;
+          const bool ina = fa >= begin && fa < end, inb = fb >= begin && fb < end;
+          const uint32_t a = ina ? (uint32_t)((fa - begin) / kSeg) : 0u;
+          const uint32_t b = inb ? (uint32_t)((fb - begin) / kSeg) : 0u;
+          cand[2 * r] = a;
+          cand[2 * r + 1] = b;
+          if (ina) {
             uint32_t* sa = reinterpret_cast<uint32_t*>(state + a) + 1;
             const uint32_t oa = atomicMax(sa, target);
             prev[2 * r] = oa;
             if (oa < target) won |= 1u << (2 * r);
-            if (b != a) {
-              uint32_t* sb = reinterpret_cast<uint32_t*>(state + b) + 1;
-              const uint32_t ob = atomicMax(sb, target);
-              prev[2 * r + 1] = ob;
-              if (ob < target) won |= 1u << (2 * r + 1);
-            }
+          }
+          if (inb && !(ina && b == a)) {
+            uint32_t* sb = reinterpret_cast<uint32_t*>(state + b) + 1;
+            const uint32_t ob = atomicMax(sb, target);
+            prev[2 * r + 1] = ob;
+            if (ob < target) won |= 1u << (2 * r + 1);
           }
         }
       }

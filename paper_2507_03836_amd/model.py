@@ -76,7 +76,7 @@ class FHashModel:
                  table_init: torch.Tensor | None = None, mlp_init: torch.Tensor | None = None,
                  init_seed: int = 3000, precision: str = "fp32", loss_scale: float = 2.0 ** 16,
                  scale_window: int = 2000, track_touched: bool = True, lazy: bool = False,
-                 max_steps: int = 1 << 16):
+                 max_steps: int = 1 << 16, hash_bits: int = 0):
         if precision not in ("fp32", "mixed"):
             raise ValueError(f"precision must be 'fp32' or 'mixed', not {precision!r}")
         self.cfg = cfg
@@ -84,9 +84,13 @@ class FHashModel:
         self.device = torch.device(device)
         self.grid = fl.grid_desc(cfg.res, cfg.n_features)
         self.mlp = fl.mlp_desc(cfg.width)
-        self.index, self.slots_per_level, self._dir, _ws = fl.fhash_build_index(
-            self.grid, mask_bits, dims)
-        del _ws
+        if hash_bits:  # spatial-hash comparison index (mask not used)
+            self.index, self.slots_per_level = fl.fhash_hash_index(self.grid, hash_bits)
+            self._dir = None
+        else:
+            self.index, self.slots_per_level, self._dir, _ws = fl.fhash_build_index(
+                self.grid, mask_bits, dims)
+            del _ws
         self.rows = int(self.index.slot_offset[cfg.n_levels])
         self.n_table = self.rows * cfg.n_features
         self.n_mlp = fl.fhash_mlp_num_params(self.mlp)

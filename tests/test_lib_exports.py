@@ -115,3 +115,17 @@ def test_lazy_descriptor_validated_before_any_launch():
                                None, ctypes.byref(lz), None)
         assert rc == code and why in L.fhash_last_error(), (begin, end, max_steps, steps)
         assert lz.steps == steps
+
+
+def test_hash_index_host_only():
+    """The spatial-hash comparison index is built on the host: row offsets are
+    the per-level min(vertices, 2^b); b outside [4, 31] is refused."""
+    L = fl.lib()
+    res = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5]]
+    idx, rows = fl.fhash_hash_index(fl.grid_desc(res, 2), 9)
+    assert rows == [128, 512, 512] and idx.hash_bits == 9 and idx.active == 0
+    assert [idx.slot_offset[l] for l in range(4)] == [0, 128, 640, 1152]
+    out = fl.Index()
+    g = fl.grid_desc(res, 2)
+    assert L.fhash_hash_index(ctypes.byref(g), 3, ctypes.byref(out), None) == fl.EINVAL
+    assert L.fhash_hash_index(ctypes.byref(g), 32, ctypes.byref(out), None) == fl.EINVAL
