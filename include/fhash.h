@@ -298,7 +298,9 @@ typedef struct {
 
 size_t fhash_lazy_workspace_bytes(int64_t range_floats, int64_t max_steps);
 
-/* Zero the workspace (a fill kernel on `stream`), steps = 0. */
+/* Zero the workspace (a fill kernel on `stream`), steps = 0.  The deferred
+ * update starts a fresh optimiser: m and v of the range must be zero (as Adam
+ * starts), since segments never enrolled are not read or replayed. */
 int fhash_lazy_init(fhash_lazy* lz, void* stream);
 
 /* Enrol for step steps+1 every segment of [begin, end) that the samples pos

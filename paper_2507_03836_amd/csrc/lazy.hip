@@ -364,26 +364,51 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x < 4 && tally[threadIdx.x] != 0ull) atomicAdd(&ctr[2 + threadIdx.x], tally[threadIdx.x]);
 }
 
-// Flush, first part: append every segment behind step `upto` to the list as
-// {segment, stamp} (its stamp <= upto: a segment enrolled in the open step is
-// already at upto), one counter atomic per wave.  The catch-up kernel then
-// applies its pending gradient step (stamp > done) and replays the rest.
+// Flush, first part: append every segment behind step `upto` that was ever
+// enrolled to the list as {segment, stamp} (its stamp <= upto: a segment
+// enrolled in the open step is already at upto).  A workgroup takes 4096 segments (16 per thread, coalesced),
+// ranks its stale ones with a workgroup scan and reserves their list entries
+// with one counter atomic.
+constexpr int kCompactPerThread = 16;
+
 __global__ void __launch_bounds__(256)
     lazy_compact_kernel(int64_t nseg, const uint2* __restrict__ state, uint2* __restrict__ list,
                         unsigned long long* __restrict__ count, uint32_t upto) {
   // runs on an empty list (the flush catches up first): at most nseg entries
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int lane = threadIdx.x & 63;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nseg; base += stride) {
-    const int64_t seg = base + threadIdx.x;
-    const uint2 st = seg < nseg ? state[seg] : make_uint2(upto, upto);
-    const bool stale = st.x < upto;
-    const unsigned long long mask = __ballot(stale);
-    if (mask == 0ull) continue;
-    unsigned long long at = 0;
-    if (lane == 0) at = atomicAdd(count, (unsigned long long)__popcll(mask));
-    at = __shfl(at, 0, 64) + __popcll(mask & ((1ull << lane) - 1ull));
-    if (stale && at < (unsigned long long)nseg) list[at] = make_uint2((uint32_t)seg, st.y);
+  __shared__ int wave_total[4];
+  __shared__ unsigned long long block_base;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t tile = 256 * kCompactPerThread;
+  for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < nseg; t0 += (int64_t)gridDim.x * tile) {
+    uint32_t mask = 0, stamp[kCompactPerThread];
+#pragma unroll
+    for (int k = 0; k < kCompactPerThread; ++k) {
+      const int64_t seg = t0 + k * 256 + threadIdx.x;
+      const uint2 st = seg < nseg ? state[seg] : make_uint2(upto, upto);
+      stamp[k] = st.y;
+      // never enrolled (done == stamp == 0): m = v = 0 and p is a fixed point of
+      // every missed step, so its state already is the dense state at any step
+      if (st.x < upto && (st.x | st.y) != 0u) mask |= 1u << k;
+    }
+    int wtot;
+    const int off = wave_excl_scan(__popc(mask), wtot);
+    if (lane == 0) wave_total[wid] = wtot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int tot = wave_total[0] + wave_total[1] + wave_total[2] + wave_total[3];
+      block_base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long at = block_base + off;
+    for (int w = 0; w < wid; ++w) at += wave_total[w];
+#pragma unroll
+    for (int k = 0; k < kCompactPerThread; ++k)
+      if (mask & (1u << k)) {
+        if (at < (unsigned long long)nseg)
+          list[at] = make_uint2((uint32_t)(t0 + k * 256 + threadIdx.x), stamp[k]);
+        ++at;
+      }
+    __syncthreads();  // wave_total and block_base are reused by the next tile
   }
 }
 
@@ -524,7 +549,7 @@ hipError_t launch_lazy_flush(const fhash_lazy* lz, float* p, float* gr, float* m
   if (nseg == 0 || lz->steps == 0) return hipSuccess;
   // segments marked without their catch-up first: the list is then empty
   launch_catch_up(lz, w, p, gr, m, v, shadow, sdt, st);
-  int64_t b = (nseg + 255) / 256;
+  int64_t b = (nseg + 256 * kCompactPerThread - 1) / (256 * kCompactPerThread);
   if (b > 65536) b = 65536;
   hipLaunchKernelGGL(lazy_compact_kernel, dim3((unsigned)b), dim3(256), 0, st, nseg, w.state,
                      w.list, w.ctr, (uint32_t)lz->steps);
