@@ -60,9 +60,10 @@ def dilate(mask: np.ndarray, r: int) -> np.ndarray:
     m = np.asarray(mask, bool)
     T, Z, Y, X = m.shape
     out = np.zeros_like(m)
-    for dz in range(-r, r + 1):
-        for dy in range(-r, r + 1):
-            for dx in range(-r, r + 1):
+    # offsets of a whole dimension or more reach no voxel (and would wrap the slices)
+    for dz in range(-min(r, Z - 1), min(r, Z - 1) + 1):
+        for dy in range(-min(r, Y - 1), min(r, Y - 1) + 1):
+            for dx in range(-min(r, X - 1), min(r, X - 1) + 1):
                 src = m[:, max(dz, 0):Z + min(dz, 0), max(dy, 0):Y + min(dy, 0),
                         max(dx, 0):X + min(dx, 0)]
                 out[:, max(-dz, 0):Z + min(-dz, 0), max(-dy, 0):Y + min(-dy, 0),

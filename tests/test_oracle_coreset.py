@@ -69,6 +69,18 @@ def test_dilation_is_scipy_cube_dilation_per_frame(r):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("r", [4, 8])
+def test_dilation_radius_beyond_the_volume(r):
+    """A radius at or above a dimension fills that dimension (scipy, cube)."""
+    m = np.zeros((2, 3, 5, 70), bool)
+    m[0, 1, 2, 30] = True
+    got = OC.dilate(m, r)
+    cube = np.ones((1, 2 * r + 1, 2 * r + 1, 2 * r + 1), bool)
+    assert np.array_equal(got, ndi.binary_dilation(m, structure=cube))
+    assert got[0, :, :, 30 - r:31 + r].all()
+    assert not got[1].any()
+
+
 def test_dilation_of_a_single_voxel_is_a_clipped_cube():
     m = np.zeros((2, 6, 6, 6), bool)
     m[1, 0, 2, 5] = True
