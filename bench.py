@@ -102,6 +102,9 @@ def parse():
                     help="decoder arithmetic of the served models (FP32 or FP16 MFMA)")
     ap.add_argument("--serve-multi", action="store_true",
                     help="multi-model serving: 6 resident models, mixed renders + point queries")
+    ap.add_argument("--coreset", action="store_true",
+                    help="coreset-selection benchmark: feature extraction, dilation, boxes, "
+                         "occupancy grid and coreset list over the whole volume")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 4 GiB device copy first (counter calibration)")
     return ap.parse_args()
@@ -555,6 +558,99 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def coreset_bench(args):
+    """Feature-based coreset selection (Sec. 3.1) over the whole production
+    volume: gradient-magnitude interval feature, dilation by 2, per-frame boxes
+    and FBB, Morton occupancy grid, coreset ids.  Each call is timed with HIP
+    events on the stream it runs on, over `--steps` repetitions."""
+    import ctypes as C
+
+    import numpy as np
+
+    from oracle import coreset as OC
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd import synth
+
+    fl.lib()
+    torch.cuda.set_device(0)
+    dims = [int(x) for x in args.shape.split(",")]
+    Sx, Sy, Sz, T = dims
+    N = Sx * Sy * Sz * T
+    gen = synth.production_volume_gpu(dims, seed=args.field_seed)
+    g = torch.empty_like(gen["field"])
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert synth._G().sy_gpu_grad_mag(synth._p(np.array(dims, np.int64)),
+                                      C.c_void_p(gen["field"].data_ptr()),
+                                      C.c_void_p(g.data_ptr()), st) == 0
+    thr = gen["threshold"]
+    del gen["field"]
+    words = fl.mask_words(dims) * 8
+    feat = torch.empty(words // 8, dtype=torch.int64, device="cuda")
+    dil = torch.empty_like(feat)
+    occ = torch.empty(fl.fhash_occupancy_words(dims), dtype=torch.int64, device="cuda")
+    box = torch.empty((T + 1, 6), dtype=torch.int32, device="cuda")
+    calls = {
+        "feature_mask": (lambda: fl.fhash_feature_mask(g, dims, fl.FEATURE_INTERVAL, thr,
+                                                       float("inf"), feat), 4 * N + words),
+        "dilate_r2": (lambda: fl.fhash_dilate_mask(feat, dims, 2, dil), 2 * words),
+        "feature_boxes": (lambda: fl.fhash_feature_boxes(dil, dims, box), words),
+        "occupancy_grid": (lambda: fl.fhash_occupancy_grid(dil, dims, occ), words + occ.numel() * 8),
+    }
+    out = {}
+    for name, (fn, nbytes) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out[name] = {"ms": ms, "algorithmic_bytes": nbytes, "GB_s": nbytes / ms / 1e6,
+                     "frac": nbytes / ms / 1e6 / 8000.0}
+        log(f"[coreset] {name}: {ms:.3f} ms, {nbytes / ms / 1e6:.0f} GB/s")
+    assert torch.equal(dil, gen["bits"].reshape(-1)), "dilated mask differs from the generator's"
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ids = fl.fhash_coreset(dil, dims)
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    M = ids.numel()
+    assert M == gen["M"] and torch.equal(ids, gen["coreset"])
+    out["coreset_ids"] = {"ms": ms, "algorithmic_bytes": 2 * words + 8 * M,
+                          "GB_s": (2 * words + 8 * M) / ms / 1e6, "note": "wall clock, 3 calls "
+                          "(size query, count, emit) with two host synchronisations"}
+    log(f"[coreset] coreset ids: {ms:.3f} ms ({M} voxels)")
+    total_ms = sum(v["ms"] for v in out.values())
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on one timestep of the same volume (one thread of numpy)
+        f1 = g[0].cpu().numpy()
+        t0 = time.perf_counter()
+        m1 = OC.dilate(OC.feature_interval(f1[None], thr, np.inf), 2)
+        OC.feature_boxes(m1)
+        OC.occupancy_grid(m1)
+        OC.coreset_ids(m1)
+        sec = time.perf_counter() - t0
+        cpu = {"value": f1.size / sec, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+               "sample": f"one timestep ({f1.size} voxels) through the numpy oracle, {sec:.2f} s"}
+    dom = out["feature_mask"]
+    print(json.dumps({
+        "metric": "coreset selection voxels/s (feature mask, dilation, boxes, occupancy, ids)",
+        "value": N / (total_ms / 1e3), "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": total_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"coreset selection, {Sx}x{Sy}x{Sz}x{T} synthetic volume, "
+                               "gradient-magnitude feature above its 80th percentile, "
+                               "dilation by 2", "shape": dims, "coreset": M},
+        "breakdown": out,
+        "roofline": {"kernel": "classify_kernel", "bound": "hbm", "achieved": dom["GB_s"],
+                     "peak": 8000.0, "unit": "GB/s", "frac": dom["frac"], "traffic": None,
+                     "algorithmic_bytes": dom["algorithmic_bytes"], "kernel_ms": dom["ms"]},
+        "cpu_baseline": cpu}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -571,6 +667,8 @@ def main():
         return key_frame_bench(args)
     if args.serve:
         return serve_bench(args)
+    if args.coreset:
+        return coreset_bench(args)
 
     from paper_2507_03836_amd import _lib as fl
     from paper_2507_03836_amd import synth

@@ -344,6 +344,55 @@ int fhash_check_finite(const float* grad, int64_t n, int32_t* found_inf, void* s
 /* Round a device float array to a device f16/bf16 copy (RNE). */
 int fhash_cast(const float* src, void* dst, fhash_dtype dst_dt, int64_t n, void* stream);
 
+/* -------------------------------------------------------------- coreset ----
+ * Feature-based coreset selection (Sec. 3.1: feature extraction, feature
+ * dilation with the occupancy grid, bounding boxes and temporal fusion into
+ * the FBB, and the coreset union of Eq. (3)).  Every call works on a voxel
+ * mask in the layout of fhash_mask_desc ([T][Sz][Sy][ceil(Sx/64)] uint64
+ * words, bit b of word w = voxel x = 64 w + b, padding bits zero) over a field
+ * of dims = (Sx, Sy, Sz, T), each in [2, 2^31 - 1] with T <= 65535 and fewer
+ * than 2^46 mask words.  Outputs are device buffers owned by the caller.
+ *
+ * fhash_feature_mask: feature extraction per timestep from the device field
+ * float [T][Sz][Sy][Sx] into bits (mask words, every word written).
+ *   FHASH_FEATURE_INTERVAL: voxel set iff lo < v <= hi (a value-range feature).
+ *   FHASH_FEATURE_ISOSURFACE: the vertices needed to interpolate the level
+ *   set v = lo inside each frame: a spatial cell (8 voxels, within one
+ *   timestep) is crossed iff some corner has v >= lo and some corner v < lo;
+ *   a voxel is set iff it is a corner of a crossed cell.  hi is unused.
+ *   ws: device workspace of *ws_bytes (one mask for the isosurface, 0 for the
+ *   interval); with ws == NULL only *ws_bytes is written.
+ * fhash_dilate_mask: feature dilation inside each timestep by a cube of
+ * radius r in [0, 63]: out voxel set iff an in voxel of the same timestep lies
+ * within r voxels along each of x, y and z.  in and out must not overlap.
+ * fhash_feature_boxes: box (int32 [T + 1][6], device) row k = bounding box
+ * b_k of timestep k as (xmin, ymin, zmin, xmax, ymax, zmax), inclusive voxel
+ * indices; row T = the FBB, the smallest box containing every b_k (temporal
+ * fusion).  An empty timestep (or an empty mask, row T) reads
+ * (Sx, Sy, Sz, -1, -1, -1).
+ * fhash_occupancy_grid: occupancy bits for rendering, Morton order inside
+ * 4x4x4 bricks: occ (uint64, fhash_occupancy_words(dims) words, device) holds
+ * one word per brick, bricks in [T][ceil(Sz/4)][ceil(Sy/4)][ceil(Sx/4)] order;
+ * voxel (4bx + lx, 4by + ly, 4bz + lz) is bit
+ *   (lx&1) | (ly&1)<<1 | (lz&1)<<2 | (lx>>1)<<3 | (ly>>1)<<4 | (lz>>1)<<5.
+ * Voxels outside the volume read 0.
+ * fhash_coreset: the coreset of Eq. (3) as linear voxel ids
+ * ((t Sz + z) Sy + y) Sx + x of the set voxels, in increasing order, the form
+ * fhash_sample draws from.  Writes the count to the HOST *count and, when ids
+ * != NULL and count <= capacity, the ids (device uint64[count]); synchronises
+ * `stream`.  ws: device workspace (query with ws == NULL). */
+enum { FHASH_FEATURE_INTERVAL = 0, FHASH_FEATURE_ISOSURFACE = 1 };
+int fhash_feature_mask(const float* field, const int64_t dims[4], int32_t kind, float lo,
+                       float hi, uint64_t* bits, void* ws, size_t* ws_bytes, void* stream);
+int fhash_dilate_mask(const uint64_t* in, const int64_t dims[4], int32_t r, uint64_t* out,
+                      void* stream);
+int fhash_feature_boxes(const uint64_t* bits, const int64_t dims[4], int32_t* box, void* stream);
+int64_t fhash_occupancy_words(const int64_t dims[4]);
+int fhash_occupancy_grid(const uint64_t* bits, const int64_t dims[4], uint64_t* occ,
+                         void* stream);
+int fhash_coreset(const uint64_t* bits, const int64_t dims[4], uint64_t* ids, int64_t capacity,
+                  void* ws, size_t* ws_bytes, int64_t* count, void* stream);
+
 /* -------------------------------------------------------------- sampler ----
  * Training batch from the coreset (Sec. 3.1, time-step concatenation): draw i
  * of step `step` is voxel id floor(r * M / 2^64), r the 64-bit word out1:out0

@@ -169,6 +169,12 @@ def _declare(L):
         "fhash_sq_err_sum": (C.c_int, [P, P, I64, P, P]),
         "fhash_mse_grad": (C.c_int, [P, P, I64, F, P, P, P]),
         "fhash_sort_samples": (C.c_int, [P, P, I64, P, P, P]),
+        "fhash_feature_mask": (C.c_int, [P, P, I32, F, F, P, P, P, P]),
+        "fhash_dilate_mask": (C.c_int, [P, P, I32, P, P]),
+        "fhash_feature_boxes": (C.c_int, [P, P, P, P]),
+        "fhash_occupancy_words": (I64, [P]),
+        "fhash_occupancy_grid": (C.c_int, [P, P, P, P]),
+        "fhash_coreset": (C.c_int, [P, P, P, I64, P, P, P, P]),
         "fhash_render_state_bytes": (C.c_int, [I32, I32, P, P]),
         "fhash_render_begin": (C.c_int, [P, F, I32, I32, P, P, P, C.c_size_t, P, P, P]),
         "fhash_render_pace": (I32, [I64, I64, I32]),
@@ -192,7 +198,9 @@ def exported_symbols() -> list[str]:
             "fhash_render_begin", "fhash_render_pace", "fhash_render_march",
             "fhash_render_composite", "fhash_render", "fhash_sort_samples",
             "fhash_lazy_workspace_bytes", "fhash_lazy_init", "fhash_lazy_prepare",
-            "fhash_step_lazy", "fhash_lazy_flush", "fhash_lazy_stats"]
+            "fhash_step_lazy", "fhash_lazy_flush", "fhash_lazy_stats", "fhash_feature_mask",
+            "fhash_dilate_mask", "fhash_feature_boxes", "fhash_occupancy_words",
+            "fhash_occupancy_grid", "fhash_coreset"]
 
 
 def _check(rc: int, func: str):
@@ -418,6 +426,86 @@ def fhash_sample(seed, step, n, coreset, M, dims, field, pos, target):
     d = (C.c_int64 * 4)(*[int(x) for x in dims])
     _check(lib().fhash_sample(seed, step, n, _ptr(coreset), M, d, _ptr(field), _ptr(pos),
                               _ptr(target), _stream()), "fhash_sample")
+
+
+FEATURE_INTERVAL, FEATURE_ISOSURFACE = 0, 1
+
+
+def _dims(dims):
+    return (C.c_int64 * 4)(*[int(x) for x in dims])
+
+
+def mask_words(dims) -> int:
+    return int(dims[3]) * int(dims[2]) * int(dims[1]) * ((int(dims[0]) + 63) // 64)
+
+
+def fhash_feature_mask(field, dims, kind, lo, hi=0.0, bits=None):
+    """Feature extraction into mask words (int64 tensor [T][Sz][Sy][ceil(Sx/64)],
+    allocated here when not given; the isosurface workspace too)."""
+    L = lib()
+    d = _dims(dims)
+    if bits is None:
+        bits = torch.empty(mask_words(dims), dtype=torch.int64, device=field.device)
+    nb = C.c_size_t(0)
+    _check(L.fhash_feature_mask(_ptr(field), d, kind, lo, hi, None, None, C.byref(nb), None),
+           "fhash_feature_mask")
+    ws = None
+    if nb.value:
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=field.device)
+    _check(L.fhash_feature_mask(_ptr(field), d, kind, lo, hi, _ptr(bits), _ptr(ws),
+                                None if ws is None else C.byref(nb), _stream()),
+           "fhash_feature_mask")
+    return bits
+
+
+def fhash_dilate_mask(bits_in, dims, r, out=None):
+    if out is None:
+        out = torch.empty_like(bits_in)
+    _check(lib().fhash_dilate_mask(_ptr(bits_in), _dims(dims), r, _ptr(out), _stream()),
+           "fhash_dilate_mask")
+    return out
+
+
+def fhash_feature_boxes(bits, dims, box=None):
+    if box is None:
+        box = torch.empty((int(dims[3]) + 1, 6), dtype=torch.int32, device=bits.device)
+    _check(lib().fhash_feature_boxes(_ptr(bits), _dims(dims), _ptr(box), _stream()),
+           "fhash_feature_boxes")
+    return box
+
+
+def fhash_occupancy_words(dims) -> int:
+    n = lib().fhash_occupancy_words(_dims(dims))
+    if n < 0:
+        raise FHashError(EINVAL, "fhash_occupancy_words", lib().fhash_last_error().decode())
+    return int(n)
+
+
+def fhash_occupancy_grid(bits, dims, occ=None):
+    if occ is None:
+        occ = torch.empty(fhash_occupancy_words(dims), dtype=torch.int64, device=bits.device)
+    _check(lib().fhash_occupancy_grid(_ptr(bits), _dims(dims), _ptr(occ), _stream()),
+           "fhash_occupancy_grid")
+    return occ
+
+
+def fhash_coreset(bits, dims, ws=None):
+    """Coreset voxel ids (int64 view of uint64, increasing).  Synchronises."""
+    L = lib()
+    d = _dims(dims)
+    nb = C.c_size_t(0)
+    cnt = C.c_int64(0)
+    _check(L.fhash_coreset(_ptr(bits), d, None, 0, None, C.byref(nb), C.byref(cnt), None),
+           "fhash_coreset")
+    if ws is None or ws.numel() < nb.value:
+        ws = torch.empty(max(int(nb.value), 16), dtype=torch.uint8, device=bits.device)
+    nb = C.c_size_t(ws.numel())
+    _check(L.fhash_coreset(_ptr(bits), d, None, 0, _ptr(ws), C.byref(nb), C.byref(cnt),
+                           _stream()), "fhash_coreset")
+    ids = torch.empty(max(cnt.value, 1), dtype=torch.int64, device=bits.device)
+    _check(L.fhash_coreset(_ptr(bits), d, _ptr(ids), cnt.value, _ptr(ws), C.byref(nb),
+                           C.byref(cnt), _stream()), "fhash_coreset")
+    return ids[:cnt.value]
 
 
 def fhash_sort_samples(pos, target, n, ws=None):

@@ -800,4 +800,80 @@ int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* 
   return FHASH_OK;
 }
 
+// ------------------------------------------------------------------ coreset
+
+static int check_mask_dims(const int64_t dims[4]) {
+  if (dims == nullptr) return fail(FHASH_EINVAL, "dims is NULL");
+  for (int d = 0; d < 4; ++d)
+    if (dims[d] < 2 || dims[d] > 0x7fffffffLL)
+      return fail(FHASH_EINVAL, "dims[%d] = %lld outside [2, 2^31 - 1]", d, (long long)dims[d]);
+  if (dims[3] > 65535) return fail(FHASH_EINVAL, "T = %lld above 65535", (long long)dims[3]);
+  const double words = (double)dims[3] * dims[2] * dims[1] * ((dims[0] + 63) / 64);
+  if (words >= 70368744177664.0) return fail(FHASH_ERANGE, "2^46 mask words or more");
+  return FHASH_OK;
+}
+
+int fhash_feature_mask(const float* field, const int64_t dims[4], int32_t kind, float lo,
+                       float hi, uint64_t* bits, void* ws, size_t* ws_bytes, void* stream) {
+  if (int rc = check_mask_dims(dims)) return rc;
+  if (kind != FHASH_FEATURE_INTERVAL && kind != FHASH_FEATURE_ISOSURFACE)
+    return fail(FHASH_EINVAL, "unknown feature kind %d", kind);
+  const size_t need = fh::feature_ws_bytes(dims, kind);
+  if (ws == nullptr && ws_bytes != nullptr) {
+    *ws_bytes = need;
+    return FHASH_OK;
+  }
+  if (need > 0) {
+    bool query;
+    if (int rc = ws_check(ws, ws_bytes, need, &query)) return rc;
+  }
+  if (field == nullptr || bits == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
+  if (kind == FHASH_FEATURE_ISOSURFACE && (ws == bits || ws == field))
+    return fail(FHASH_EINVAL, "workspace overlaps an argument");
+  return hip_status(fh::launch_feature_mask(field, dims, kind, lo, hi, bits, ws, S(stream)),
+                    "fhash_feature_mask");
+}
+
+int fhash_dilate_mask(const uint64_t* in, const int64_t dims[4], int32_t r, uint64_t* out,
+                      void* stream) {
+  if (int rc = check_mask_dims(dims)) return rc;
+  if (r < 0 || r > 63) return fail(FHASH_EINVAL, "radius %d outside [0, 63]", r);
+  if (in == nullptr || out == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
+  const uint64_t* oend = out + fh::mask_words(dims);
+  const uint64_t* iend = in + fh::mask_words(dims);
+  if (in < oend && out < iend) return fail(FHASH_EINVAL, "in and out overlap");
+  return hip_status(fh::launch_dilate_mask(in, dims, r, out, S(stream)), "fhash_dilate_mask");
+}
+
+int fhash_feature_boxes(const uint64_t* bits, const int64_t dims[4], int32_t* box, void* stream) {
+  if (int rc = check_mask_dims(dims)) return rc;
+  if (bits == nullptr || box == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
+  return hip_status(fh::launch_feature_boxes(bits, dims, box, S(stream)), "fhash_feature_boxes");
+}
+
+int64_t fhash_occupancy_words(const int64_t dims[4]) {
+  if (check_mask_dims(dims)) return -1;
+  return fh::occupancy_words(dims);
+}
+
+int fhash_occupancy_grid(const uint64_t* bits, const int64_t dims[4], uint64_t* occ,
+                         void* stream) {
+  if (int rc = check_mask_dims(dims)) return rc;
+  if (bits == nullptr || occ == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
+  return hip_status(fh::launch_occupancy_morton(bits, dims, occ, S(stream)),
+                    "fhash_occupancy_grid");
+}
+
+int fhash_coreset(const uint64_t* bits, const int64_t dims[4], uint64_t* ids, int64_t capacity,
+                  void* ws, size_t* ws_bytes, int64_t* count, void* stream) {
+  if (int rc = check_mask_dims(dims)) return rc;
+  bool query;
+  if (int rc = ws_check(ws, ws_bytes, fh::coreset_ws_bytes(dims), &query)) return rc;
+  if (query) return FHASH_OK;
+  if (bits == nullptr || count == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
+  if (ids != nullptr && capacity < 0) return fail(FHASH_EINVAL, "negative capacity");
+  return hip_status(fh::launch_coreset(bits, dims, ws, ids, capacity, count, S(stream)),
+                    "fhash_coreset");
+}
+
 }  // extern "C"

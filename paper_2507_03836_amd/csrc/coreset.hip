@@ -1,0 +1,399 @@
+// Feature-based coreset selection on the GPU (Sec. 3.1): feature extraction
+// into voxel mask bits, feature dilation, per-frame bounding boxes and their
+// temporal fusion (the FBB), the Morton-ordered occupancy grid, and the list
+// of coreset voxels that the training sampler draws from.
+//
+// Every kernel works on the mask's 64-voxel words ([T][Sz][Sy][W], W =
+// ceil(Sx/64)), so a word is one wave's ballot in the extraction pass and one
+// thread's unit of work everywhere else: a dilation or a cell-crossing test
+// is a handful of shifts, ANDs and ORs over neighbouring words.
+#include "common.h"
+#include "kernels.h"
+
+namespace fh {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWordsPerThread = 16;                  // coreset count / emit
+constexpr int64_t kChunk = (int64_t)kBlock * kWordsPerThread;
+
+__device__ __forceinline__ uint64_t valid_bits(int64_t Sx, int64_t w) {
+  const int64_t left = Sx - 64 * w;  // voxels of this word inside the row
+  return left >= 64 ? ~0ull : left <= 0 ? 0ull : ((1ull << left) - 1ull);
+}
+
+// Pass 1: one wave per word; lane b decides voxel x = 64 w + b and the wave's
+// ballot is the word.  Interval: lo < v <= hi.  Sign (isosurface pass 1):
+// v >= lo.
+__global__ void __launch_bounds__(kBlock)
+    classify_kernel(const float* __restrict__ field, int64_t Sx, int64_t W, int64_t n_words,
+                    int kind, float lo, float hi, uint64_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t q = blockIdx.x * (int64_t)(kBlock / 64) + (threadIdx.x >> 6); q < n_words;
+       q += waves) {
+    const int64_t row = q / W, w = q - row * W;
+    const int64_t x = 64 * w + lane;
+    bool p = false;
+    if (x < Sx) {
+      const float v = field[row * Sx + x];
+      p = kind == FHASH_FEATURE_INTERVAL ? (v > lo && v <= hi) : (v >= lo);
+    }
+    const uint64_t b = __ballot(p);
+    if (lane == 0) out[q] = b;
+  }
+}
+
+// Cells of x-row (z, y) pairs crossed by the isosurface, for the 64 cells
+// cx = 64 w .. 64 w + 63 of cell row (cz, cy): some corner at or above the
+// level and some below it.  sign = pass-1 bits (padding bits zero).
+__device__ __forceinline__ uint64_t crossed_cells(const uint64_t* __restrict__ sign, int64_t Sx,
+                                                  int64_t Sy, int64_t W, int64_t frame_row0,
+                                                  int64_t cz, int64_t cy, int64_t w) {
+  uint64_t all = ~0ull, any = 0;
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+      const uint64_t* r = sign + ((frame_row0 + (cz + dz) * Sy + (cy + dy)) * W);
+      const uint64_t s = r[w];
+      const uint64_t nx = w + 1 < W ? r[w + 1] : 0ull;
+      const uint64_t s1 = (s >> 1) | (nx << 63);  // corner x + 1
+      all &= s & s1;
+      any |= s | s1;
+    }
+  // cells exist for cx <= Sx - 2
+  return (any & ~all) & valid_bits(Sx - 1, w);
+}
+
+// Pass 2 of the isosurface feature: a voxel belongs to the feature iff it is a
+// corner of a crossed cell, i.e. cell (x or x-1, y or y-1, z or z-1) is crossed.
+__global__ void __launch_bounds__(kBlock)
+    iso_kernel(const uint64_t* __restrict__ sign, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
+               int64_t n_words, uint64_t* __restrict__ out) {
+  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < n_words;
+       q += (int64_t)gridDim.x * kBlock) {
+    const int64_t w = q % W;
+    const int64_t row = q / W;
+    const int64_t y = row % Sy;
+    const int64_t z = (row / Sy) % Sz;
+    const int64_t frame_row0 = (row / (Sy * Sz)) * Sz * Sy;
+    uint64_t f = 0;
+    for (int64_t cz = z - 1; cz <= z; ++cz) {
+      if (cz < 0 || cz > Sz - 2) continue;
+      for (int64_t cy = y - 1; cy <= y; ++cy) {
+        if (cy < 0 || cy > Sy - 2) continue;
+        const uint64_t c = crossed_cells(sign, Sx, Sy, W, frame_row0, cz, cy, w);
+        const uint64_t cp = w > 0 ? crossed_cells(sign, Sx, Sy, W, frame_row0, cz, cy, w - 1) : 0;
+        f |= c | (c << 1) | (cp >> 63);
+      }
+    }
+    out[q] = f & valid_bits(Sx, w);
+  }
+}
+
+// Cube dilation of radius r (0 <= r <= 63) inside each frame: a voxel is set
+// iff some set voxel lies within r along each of x, y and z.
+__global__ void __launch_bounds__(kBlock)
+    dilate_kernel(const uint64_t* __restrict__ in, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
+                  int64_t n_words, int r, uint64_t* __restrict__ out) {
+  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < n_words;
+       q += (int64_t)gridDim.x * kBlock) {
+    const int64_t w = q % W;
+    const int64_t row = q / W;
+    const int64_t y = row % Sy;
+    const int64_t z = (row / Sy) % Sz;
+    const int64_t frame_row0 = (row / (Sy * Sz)) * Sz * Sy;
+    uint64_t f = 0;
+    const int64_t z0 = z - r < 0 ? 0 : z - r, z1 = z + r > Sz - 1 ? Sz - 1 : z + r;
+    const int64_t y0 = y - r < 0 ? 0 : y - r, y1 = y + r > Sy - 1 ? Sy - 1 : y + r;
+    for (int64_t c = z0; c <= z1; ++c)
+      for (int64_t b = y0; b <= y1; ++b) {
+        const uint64_t* rw = in + (frame_row0 + c * Sy + b) * W;
+        const uint64_t s = rw[w];
+        const uint64_t pv = w > 0 ? rw[w - 1] : 0ull;
+        const uint64_t nx = w + 1 < W ? rw[w + 1] : 0ull;
+        uint64_t d = s;
+        for (int k = 1; k <= r; ++k) {
+          d |= (s << k) | (pv >> (64 - k));  // set voxel k to the left
+          d |= (s >> k) | (nx << (64 - k));  // set voxel k to the right
+        }
+        f |= d;
+      }
+    out[q] = f & valid_bits(Sx, w);
+  }
+}
+
+__global__ void box_init_kernel(int32_t* box, int64_t rows, int32_t Sx, int32_t Sy, int32_t Sz) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < rows) {
+    box[6 * i + 0] = Sx;
+    box[6 * i + 1] = Sy;
+    box[6 * i + 2] = Sz;
+    box[6 * i + 3] = -1;
+    box[6 * i + 4] = -1;
+    box[6 * i + 5] = -1;
+  }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Per-frame bounding boxes: blockIdx.y is the frame, so every workgroup
+// reduces words of one frame and issues 12 atomics (frame row + fused row T).
+__global__ void __launch_bounds__(kBlock)
+    box_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
+               int64_t T, int32_t* __restrict__ box) {
+  const int64_t t = blockIdx.y;
+  const int64_t per_frame = Sz * Sy * W;
+  const uint64_t* fb = bits + t * per_frame;
+  int mn[3] = {(int)Sx, (int)Sy, (int)Sz}, mx[3] = {-1, -1, -1};
+  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < per_frame;
+       q += (int64_t)gridDim.x * kBlock) {
+    const uint64_t b = fb[q] & valid_bits(Sx, q % W);
+    if (b == 0) continue;
+    const int64_t w = q % W, row = q / W;
+    const int x0 = (int)(64 * w + __builtin_ctzll(b));
+    const int x1 = (int)(64 * w + 63 - __builtin_clzll(b));
+    const int y = (int)(row % Sy), z = (int)(row / Sy);
+    mn[0] = min(mn[0], x0);
+    mx[0] = max(mx[0], x1);
+    mn[1] = min(mn[1], y);
+    mx[1] = max(mx[1], y);
+    mn[2] = min(mn[2], z);
+    mx[2] = max(mx[2], z);
+  }
+  __shared__ int red[kBlock / 64][6];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int a = wave_min(mn[d]), b = wave_max(mx[d]);
+    if (lane == 0) {
+      red[wid][d] = a;
+      red[wid][3 + d] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int d = threadIdx.x;
+    int v = red[0][d];
+    for (int k = 1; k < kBlock / 64; ++k) v = d < 3 ? min(v, red[k][d]) : max(v, red[k][d]);
+    if (d < 3 ? v < (int)(d == 0 ? Sx : d == 1 ? Sy : Sz) : v >= 0) {
+      if (d < 3) {
+        atomicMin(&box[6 * t + d], v);
+        atomicMin(&box[6 * T + d], v);
+      } else {
+        atomicMax(&box[6 * t + d], v);
+        atomicMax(&box[6 * T + d], v);
+      }
+    }
+  }
+}
+
+// Occupancy grid: one word per 4x4x4 brick, bricks row-major (bx fastest),
+// voxel (lx, ly, lz) of a brick at bit lx0 | ly0<<1 | lz0<<2 | lx1<<3 | ly1<<4 |
+// lz1<<5 (Morton order inside the brick).  Voxels outside the volume are 0.
+__global__ void __launch_bounds__(kBlock)
+    morton_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
+                  int64_t Bx, int64_t By, int64_t Bz, int64_t n_bricks,
+                  uint64_t* __restrict__ occ) {
+  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < n_bricks;
+       q += (int64_t)gridDim.x * kBlock) {
+    const int64_t bx = q % Bx;
+    const int64_t by = (q / Bx) % By;
+    const int64_t bz = (q / (Bx * By)) % Bz;
+    const int64_t t = q / (Bx * By * Bz);
+    const int64_t x0 = 4 * bx, w = x0 >> 6, sh = x0 & 63;  // 4 | 64: a nibble never straddles
+    uint64_t o = 0;
+    for (int lz = 0; lz < 4; ++lz) {
+      const int64_t z = 4 * bz + lz;
+      if (z >= Sz) break;
+      for (int ly = 0; ly < 4; ++ly) {
+        const int64_t y = 4 * by + ly;
+        if (y >= Sy) break;
+        const uint64_t nib = (bits[((t * Sz + z) * Sy + y) * W + w] >> sh) & 0xFull;
+        for (int lx = 0; lx < 4; ++lx)
+          if (((nib >> lx) & 1ull) && x0 + lx < Sx) {
+            const int m = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2) | ((lx >> 1) << 3) |
+                          ((ly >> 1) << 4) | ((lz >> 1) << 5);
+            o |= 1ull << m;
+          }
+      }
+    }
+    occ[q] = o;
+  }
+}
+
+// Coreset, step 1: set voxels per chunk of kChunk words.
+__global__ void __launch_bounds__(kBlock)
+    chunk_count_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t W, int64_t n_words,
+                       int64_t* __restrict__ chunk) {
+  const int64_t base = blockIdx.x * kChunk;
+  int64_t c = 0;
+  for (int k = 0; k < kWordsPerThread; ++k) {
+    const int64_t q = base + (int64_t)k * kBlock + threadIdx.x;
+    if (q < n_words) c += __popcll(bits[q] & valid_bits(Sx, q % W));
+  }
+  __shared__ int64_t red[kBlock];
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) chunk[blockIdx.x] = red[0];
+}
+
+// Step 2: exclusive scan of the chunk counts in one workgroup; chunk[n] = total.
+__global__ void __launch_bounds__(1024) chunk_scan_kernel(int64_t* chunk, int64_t n) {
+  __shared__ int64_t s[1024];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < n; b0 += 1024) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = i < n ? chunk[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan
+      const int64_t a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+      __syncthreads();
+      s[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (i < n) chunk[i] = carry + s[threadIdx.x] - v;
+    const int64_t tot = s[1023];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) chunk[n] = carry;
+}
+
+// Step 3: write the linear ids of the set voxels in increasing order.  A
+// thread owns kWordsPerThread consecutive words of its chunk.
+__global__ void __launch_bounds__(kBlock)
+    chunk_emit_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t W, int64_t n_words,
+                      const int64_t* __restrict__ chunk, uint64_t* __restrict__ ids) {
+  const int64_t q0 = blockIdx.x * kChunk + (int64_t)threadIdx.x * kWordsPerThread;
+  int64_t c = 0;
+  for (int k = 0; k < kWordsPerThread; ++k) {
+    const int64_t q = q0 + k;
+    if (q < n_words) c += __popcll(bits[q] & valid_bits(Sx, q % W));
+  }
+  __shared__ int64_t s[kBlock];
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    const int64_t a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += a;
+    __syncthreads();
+  }
+  int64_t at = chunk[blockIdx.x] + s[threadIdx.x] - c;
+  for (int k = 0; k < kWordsPerThread; ++k) {
+    const int64_t q = q0 + k;
+    if (q >= n_words) break;
+    const int64_t w = q % W, row = q / W;
+    uint64_t b = bits[q] & valid_bits(Sx, w);
+    while (b) {
+      const int i = __builtin_ctzll(b);
+      b &= b - 1;
+      ids[at++] = (uint64_t)(row * Sx + 64 * w + i);
+    }
+  }
+}
+
+unsigned grid_for(int64_t items, int64_t per_block) {
+  const int64_t g = (items + per_block - 1) / per_block;
+  return (unsigned)(g < 1 ? 1 : g > 65536 ? 65536 : g);
+}
+
+}  // namespace
+
+int64_t mask_words(const int64_t* dims) { return dims[3] * dims[2] * dims[1] * ((dims[0] + 63) / 64); }
+
+size_t feature_ws_bytes(const int64_t* dims, int kind) {
+  return kind == FHASH_FEATURE_ISOSURFACE ? (size_t)mask_words(dims) * 8 : 0;
+}
+
+hipError_t launch_feature_mask(const float* field, const int64_t* dims, int kind, float lo,
+                               float hi, uint64_t* bits, void* ws, hipStream_t st) {
+  const int64_t W = (dims[0] + 63) / 64, n = mask_words(dims);
+  if (kind == FHASH_FEATURE_INTERVAL) {
+    classify_kernel<<<grid_for(n, kBlock / 64), kBlock, 0, st>>>(field, dims[0], W, n, kind, lo,
+                                                                  hi, bits);
+    return hipGetLastError();
+  }
+  uint64_t* sign = static_cast<uint64_t*>(ws);
+  classify_kernel<<<grid_for(n, kBlock / 64), kBlock, 0, st>>>(field, dims[0], W, n, kind, lo, hi,
+                                                                sign);
+  iso_kernel<<<grid_for(n, kBlock), kBlock, 0, st>>>(sign, dims[0], dims[1], dims[2], W, n, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_dilate_mask(const uint64_t* in, const int64_t* dims, int r, uint64_t* out,
+                              hipStream_t st) {
+  const int64_t W = (dims[0] + 63) / 64, n = mask_words(dims);
+  dilate_kernel<<<grid_for(n, kBlock), kBlock, 0, st>>>(in, dims[0], dims[1], dims[2], W, n, r,
+                                                         out);
+  return hipGetLastError();
+}
+
+hipError_t launch_feature_boxes(const uint64_t* bits, const int64_t* dims, int32_t* box,
+                                hipStream_t st) {
+  const int64_t W = (dims[0] + 63) / 64, T = dims[3];
+  box_init_kernel<<<grid_for(T + 1, kBlock), kBlock, 0, st>>>(box, T + 1, (int32_t)dims[0],
+                                                               (int32_t)dims[1], (int32_t)dims[2]);
+  const int64_t per_frame = dims[2] * dims[1] * W;
+  const int64_t gx = (per_frame + kBlock - 1) / kBlock;
+  dim3 grid((unsigned)(gx < 1 ? 1 : gx > 1024 ? 1024 : gx), (unsigned)T);
+  box_kernel<<<grid, kBlock, 0, st>>>(bits, dims[0], dims[1], dims[2], W, T, box);
+  return hipGetLastError();
+}
+
+int64_t occupancy_words(const int64_t* dims) {
+  return dims[3] * ((dims[2] + 3) / 4) * ((dims[1] + 3) / 4) * ((dims[0] + 3) / 4);
+}
+
+hipError_t launch_occupancy_morton(const uint64_t* bits, const int64_t* dims, uint64_t* occ,
+                                   hipStream_t st) {
+  const int64_t W = (dims[0] + 63) / 64;
+  const int64_t Bx = (dims[0] + 3) / 4, By = (dims[1] + 3) / 4, Bz = (dims[2] + 3) / 4;
+  const int64_t n = occupancy_words(dims);
+  morton_kernel<<<grid_for(n, kBlock), kBlock, 0, st>>>(bits, dims[0], dims[1], dims[2], W, Bx,
+                                                         By, Bz, n, occ);
+  return hipGetLastError();
+}
+
+size_t coreset_ws_bytes(const int64_t* dims) {
+  const int64_t chunks = (mask_words(dims) + kChunk - 1) / kChunk;
+  return (size_t)(chunks + 1) * sizeof(int64_t);
+}
+
+hipError_t launch_coreset(const uint64_t* bits, const int64_t* dims, void* ws, uint64_t* ids,
+                          int64_t capacity, int64_t* count, hipStream_t st) {
+  const int64_t W = (dims[0] + 63) / 64, n = mask_words(dims);
+  const int64_t chunks = (n + kChunk - 1) / kChunk;
+  if (chunks > 0x7fffffffLL) return hipErrorInvalidValue;
+  int64_t* chunk = static_cast<int64_t*>(ws);
+  chunk_count_kernel<<<(unsigned)chunks, kBlock, 0, st>>>(bits, dims[0], W, n, chunk);
+  chunk_scan_kernel<<<1, 1024, 0, st>>>(chunk, chunks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(count, chunk + chunks, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  if (ids == nullptr || *count > capacity) return hipSuccess;
+  chunk_emit_kernel<<<(unsigned)chunks, kBlock, 0, st>>>(bits, dims[0], W, n, chunk, ids);
+  return hipGetLastError();
+}
+
+}  // namespace fh

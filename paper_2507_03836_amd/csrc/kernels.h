@@ -96,4 +96,20 @@ hipError_t launch_render_composite(void* ws, int W, int H, int cur, int32_t n_al
                                    const float* y, const float* tf, float alpha_stop, float* rgba,
                                    int32_t* n_alive_host, hipStream_t st);
 
+// coreset.hip: feature extraction, dilation, boxes, occupancy, coreset list
+int64_t mask_words(const int64_t* dims);
+size_t feature_ws_bytes(const int64_t* dims, int kind);
+hipError_t launch_feature_mask(const float* field, const int64_t* dims, int kind, float lo,
+                               float hi, uint64_t* bits, void* ws, hipStream_t st);
+hipError_t launch_dilate_mask(const uint64_t* in, const int64_t* dims, int r, uint64_t* out,
+                              hipStream_t st);
+hipError_t launch_feature_boxes(const uint64_t* bits, const int64_t* dims, int32_t* box,
+                                hipStream_t st);
+int64_t occupancy_words(const int64_t* dims);
+hipError_t launch_occupancy_morton(const uint64_t* bits, const int64_t* dims, uint64_t* occ,
+                                   hipStream_t st);
+size_t coreset_ws_bytes(const int64_t* dims);
+hipError_t launch_coreset(const uint64_t* bits, const int64_t* dims, void* ws, uint64_t* ids,
+                          int64_t capacity, int64_t* count, hipStream_t st);
+
 }  // namespace fh
