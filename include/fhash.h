@@ -350,8 +350,10 @@ int fhash_cast(const float* src, void* dst, fhash_dtype dst_dt, int64_t n, void*
  * the FBB, and the coreset union of Eq. (3)).  Every call works on a voxel
  * mask in the layout of fhash_mask_desc ([T][Sz][Sy][ceil(Sx/64)] uint64
  * words, bit b of word w = voxel x = 64 w + b, padding bits zero) over a field
- * of dims = (Sx, Sy, Sz, T), each in [2, 2^31 - 1] with T <= 65535 and fewer
- * than 2^46 mask words.  Outputs are device buffers owned by the caller.
+ * of dims = (Sx, Sy, Sz, T), each in [2, 2^31 - 1] with T <= 65535, fewer
+ * than 2^46 mask words, and T Sz, Sy ceil(Sx/64) and ceil(Sy/4) ceil(Sx/4)
+ * each below 2^31 (FHASH_ERANGE otherwise).  Outputs are device buffers owned
+ * by the caller.
  *
  * fhash_feature_mask: feature extraction per timestep from the device field
  * float [T][Sz][Sy][Sx] into bits (mask words, every word written).

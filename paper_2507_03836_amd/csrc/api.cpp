@@ -810,6 +810,11 @@ static int check_mask_dims(const int64_t dims[4]) {
   if (dims[3] > 65535) return fail(FHASH_EINVAL, "T = %lld above 65535", (long long)dims[3]);
   const double words = (double)dims[3] * dims[2] * dims[1] * ((dims[0] + 63) / 64);
   if (words >= 70368744177664.0) return fail(FHASH_ERANGE, "2^46 mask words or more");
+  // one workgroup per (t, z) slice, 32-bit word index inside a slice
+  if ((double)dims[3] * dims[2] >= 2147483648.0 ||
+      (double)dims[1] * ((dims[0] + 63) / 64) >= 2147483648.0 ||
+      (double)((dims[1] + 3) / 4) * ((dims[0] + 3) / 4) >= 2147483648.0)
+    return fail(FHASH_ERANGE, "T Sz, or the words or bricks of one slice, reach 2^31");
   return FHASH_OK;
 }
 

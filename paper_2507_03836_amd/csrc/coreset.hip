@@ -25,23 +25,33 @@ __device__ __forceinline__ uint64_t valid_bits(int64_t Sx, int64_t w) {
 
 // Pass 1: one wave per word; lane b decides voxel x = 64 w + b and the wave's
 // ballot is the word.  Interval: lo < v <= hi.  Sign (isosurface pass 1):
-// v >= lo.
+// v >= lo.  A wave takes kUnroll consecutive words per iteration and issues
+// their loads before the ballots, so each wave keeps 1 KiB of reads in flight.
+constexpr int kUnroll = 4;
 __global__ void __launch_bounds__(kBlock)
     classify_kernel(const float* __restrict__ field, int64_t Sx, int64_t W, int64_t n_words,
                     int kind, float lo, float hi, uint64_t* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
-  for (int64_t q = blockIdx.x * (int64_t)(kBlock / 64) + (threadIdx.x >> 6); q < n_words;
-       q += waves) {
-    const int64_t row = q / W, w = q - row * W;
-    const int64_t x = 64 * w + lane;
-    bool p = false;
-    if (x < Sx) {
-      const float v = field[row * Sx + x];
-      p = kind == FHASH_FEATURE_INTERVAL ? (v > lo && v <= hi) : (v >= lo);
+  const int64_t step = (int64_t)gridDim.x * (kBlock / 64) * kUnroll;
+  for (int64_t q0 = (blockIdx.x * (int64_t)(kBlock / 64) + (threadIdx.x >> 6)) * kUnroll;
+       q0 < n_words; q0 += step) {
+    float v[kUnroll];
+    bool in[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t q = q0 + u;
+      const int64_t row = q / W, w = q - row * W;
+      const int64_t x = 64 * w + lane;
+      in[u] = q < n_words && x < Sx;
+      v[u] = in[u] ? __builtin_nontemporal_load(field + row * Sx + x) : 0.0f;
     }
-    const uint64_t b = __ballot(p);
-    if (lane == 0) out[q] = b;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool p = in[u] && (kind == FHASH_FEATURE_INTERVAL ? (v[u] > lo && v[u] <= hi)
+                                                              : (v[u] >= lo));
+      const uint64_t b = __ballot(p);
+      if (lane == 0 && q0 + u < n_words) out[q0 + u] = b;
+    }
   }
 }
 
@@ -69,16 +79,18 @@ __device__ __forceinline__ uint64_t crossed_cells(const uint64_t* __restrict__ s
 
 // Pass 2 of the isosurface feature: a voxel belongs to the feature iff it is a
 // corner of a crossed cell, i.e. cell (x or x-1, y or y-1, z or z-1) is crossed.
+// One workgroup per (t, z) slice (blockIdx.x = t Sz + z): the words of a
+// slice are indexed in 32 bits (Sy W < 2^31, checked by the host).
 __global__ void __launch_bounds__(kBlock)
     iso_kernel(const uint64_t* __restrict__ sign, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
-               int64_t n_words, uint64_t* __restrict__ out) {
-  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < n_words;
-       q += (int64_t)gridDim.x * kBlock) {
-    const int64_t w = q % W;
-    const int64_t row = q / W;
-    const int64_t y = row % Sy;
-    const int64_t z = (row / Sy) % Sz;
-    const int64_t frame_row0 = (row / (Sy * Sz)) * Sz * Sy;
+               uint64_t* __restrict__ out) {
+  const int64_t slice = blockIdx.x;
+  const int64_t z = slice % Sz;
+  const int64_t frame_row0 = (slice - z) * Sy;
+  const uint32_t per_slice = (uint32_t)(Sy * W), Wu = (uint32_t)W;
+  for (uint32_t i = threadIdx.x; i < per_slice; i += kBlock) {
+    const int64_t y = i / Wu, w = i - (uint32_t)y * Wu;
+    const int64_t q = slice * per_slice + i;
     uint64_t f = 0;
     for (int64_t cz = z - 1; cz <= z; ++cz) {
       if (cz < 0 || cz > Sz - 2) continue;
@@ -95,16 +107,17 @@ __global__ void __launch_bounds__(kBlock)
 
 // Cube dilation of radius r (0 <= r <= 63) inside each frame: a voxel is set
 // iff some set voxel lies within r along each of x, y and z.
+// One workgroup per (t, z) slice, as the isosurface pass.
 __global__ void __launch_bounds__(kBlock)
     dilate_kernel(const uint64_t* __restrict__ in, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
-                  int64_t n_words, int r, uint64_t* __restrict__ out) {
-  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < n_words;
-       q += (int64_t)gridDim.x * kBlock) {
-    const int64_t w = q % W;
-    const int64_t row = q / W;
-    const int64_t y = row % Sy;
-    const int64_t z = (row / Sy) % Sz;
-    const int64_t frame_row0 = (row / (Sy * Sz)) * Sz * Sy;
+                  int r, uint64_t* __restrict__ out) {
+  const int64_t slice = blockIdx.x;
+  const int64_t z = slice % Sz;
+  const int64_t frame_row0 = (slice - z) * Sy;
+  const uint32_t per_slice = (uint32_t)(Sy * W), Wu = (uint32_t)W;
+  for (uint32_t i = threadIdx.x; i < per_slice; i += kBlock) {
+    const int64_t y = i / Wu, w = i - (uint32_t)y * Wu;
+    const int64_t q = slice * per_slice + i;
     uint64_t f = 0;
     const int64_t z0 = z - r < 0 ? 0 : z - r, z1 = z + r > Sz - 1 ? Sz - 1 : z + r;
     const int64_t y0 = y - r < 0 ? 0 : y - r, y1 = y + r > Sy - 1 ? Sy - 1 : y + r;
@@ -148,29 +161,28 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// Per-frame bounding boxes: blockIdx.y is the frame, so every workgroup
-// reduces words of one frame and issues 12 atomics (frame row + fused row T).
+// Per-frame bounding boxes: one workgroup per (t, z) slice reduces its words
+// and issues at most 12 atomics (frame row t and the fused row T).
 __global__ void __launch_bounds__(kBlock)
     box_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
                int64_t T, int32_t* __restrict__ box) {
-  const int64_t t = blockIdx.y;
-  const int64_t per_frame = Sz * Sy * W;
-  const uint64_t* fb = bits + t * per_frame;
+  const int64_t slice = blockIdx.x;
+  const int64_t z = slice % Sz, t = slice / Sz;
+  const uint32_t per_slice = (uint32_t)(Sy * W), Wu = (uint32_t)W;
+  const uint64_t* fb = bits + slice * per_slice;
   int mn[3] = {(int)Sx, (int)Sy, (int)Sz}, mx[3] = {-1, -1, -1};
-  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < per_frame;
-       q += (int64_t)gridDim.x * kBlock) {
-    const uint64_t b = fb[q] & valid_bits(Sx, q % W);
+  for (uint32_t i = threadIdx.x; i < per_slice; i += kBlock) {
+    const uint32_t y = i / Wu, w = i - y * Wu;
+    const uint64_t b = fb[i] & valid_bits(Sx, w);
     if (b == 0) continue;
-    const int64_t w = q % W, row = q / W;
     const int x0 = (int)(64 * w + __builtin_ctzll(b));
     const int x1 = (int)(64 * w + 63 - __builtin_clzll(b));
-    const int y = (int)(row % Sy), z = (int)(row / Sy);
     mn[0] = min(mn[0], x0);
     mx[0] = max(mx[0], x1);
-    mn[1] = min(mn[1], y);
-    mx[1] = max(mx[1], y);
-    mn[2] = min(mn[2], z);
-    mx[2] = max(mx[2], z);
+    mn[1] = min(mn[1], (int)y);
+    mx[1] = max(mx[1], (int)y);
+    mn[2] = (int)z;
+    mx[2] = (int)z;
   }
   __shared__ int red[kBlock / 64][6];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -187,31 +199,46 @@ __global__ void __launch_bounds__(kBlock)
     const int d = threadIdx.x;
     int v = red[0][d];
     for (int k = 1; k < kBlock / 64; ++k) v = d < 3 ? min(v, red[k][d]) : max(v, red[k][d]);
-    if (d < 3 ? v < (int)(d == 0 ? Sx : d == 1 ? Sy : Sz) : v >= 0) {
-      if (d < 3) {
-        atomicMin(&box[6 * t + d], v);
-        atomicMin(&box[6 * T + d], v);
-      } else {
-        atomicMax(&box[6 * t + d], v);
-        atomicMax(&box[6 * T + d], v);
-      }
+    // A plain read first: the stored bound only moves towards the answer, so
+    // when it is already at least as tight, the atomic cannot change it.
+    int* dst = &box[6 * t + d];
+    const int cur = __atomic_load_n(dst, __ATOMIC_RELAXED);
+    if (d < 3 ? v < cur : v > cur) {
+      if (d < 3)
+        atomicMin(dst, v);
+      else
+        atomicMax(dst, v);
     }
+  }
+}
+
+// Temporal fusion: row T = the smallest box containing rows 0..T-1 (empty
+// rows carry (Sx, Sy, Sz, -1, -1, -1) and so never widen it).
+__global__ void __launch_bounds__(64) fuse_boxes_kernel(int32_t* box, int64_t T) {
+  const int lane = threadIdx.x;
+  int v[6];
+  for (int d = 0; d < 6; ++d) v[d] = box[6 * T + d];  // the empty box
+  for (int64_t k = lane; k < T; k += 64)
+    for (int d = 0; d < 6; ++d) v[d] = d < 3 ? min(v[d], box[6 * k + d]) : max(v[d], box[6 * k + d]);
+  for (int d = 0; d < 6; ++d) {
+    const int r = d < 3 ? wave_min(v[d]) : wave_max(v[d]);
+    if (lane == 0) box[6 * T + d] = r;
   }
 }
 
 // Occupancy grid: one word per 4x4x4 brick, bricks row-major (bx fastest),
 // voxel (lx, ly, lz) of a brick at bit lx0 | ly0<<1 | lz0<<2 | lx1<<3 | ly1<<4 |
 // lz1<<5 (Morton order inside the brick).  Voxels outside the volume are 0.
+// One workgroup per (t, bz) slab of bricks (blockIdx.x = t Bz + bz).
 __global__ void __launch_bounds__(kBlock)
     morton_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
-                  int64_t Bx, int64_t By, int64_t Bz, int64_t n_bricks,
-                  uint64_t* __restrict__ occ) {
-  for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < n_bricks;
-       q += (int64_t)gridDim.x * kBlock) {
-    const int64_t bx = q % Bx;
-    const int64_t by = (q / Bx) % By;
-    const int64_t bz = (q / (Bx * By)) % Bz;
-    const int64_t t = q / (Bx * By * Bz);
+                  int64_t Bx, int64_t By, int64_t Bz, uint64_t* __restrict__ occ) {
+  const int64_t slab = blockIdx.x;
+  const int64_t bz = slab % Bz, t = slab / Bz;
+  const uint32_t per_slab = (uint32_t)(By * Bx), Bxu = (uint32_t)Bx;
+  for (uint32_t i = threadIdx.x; i < per_slab; i += kBlock) {
+    const int64_t by = i / Bxu, bx = i - (uint32_t)by * Bxu;
+    const int64_t q = slab * per_slab + i;
     const int64_t x0 = 4 * bx, w = x0 >> 6, sh = x0 & 63;  // 4 | 64: a nibble never straddles
     uint64_t o = 0;
     for (int lz = 0; lz < 4; ++lz) {
@@ -276,37 +303,56 @@ __global__ void __launch_bounds__(1024) chunk_scan_kernel(int64_t* chunk, int64_
   if (threadIdx.x == 0) chunk[n] = carry;
 }
 
-// Step 3: write the linear ids of the set voxels in increasing order.  A
-// thread owns kWordsPerThread consecutive words of its chunk.
+// Step 3: write the linear ids of the set voxels in increasing order.  Each
+// wave owns a quarter of its workgroup's chunk; it takes 64 words at a time
+// (one per lane), scans their counts across the wave, and then writes the ids
+// of one word after another with all 64 lanes, so every store instruction
+// writes up to 64 consecutive ids.
 __global__ void __launch_bounds__(kBlock)
     chunk_emit_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t W, int64_t n_words,
                       const int64_t* __restrict__ chunk, uint64_t* __restrict__ ids) {
-  const int64_t q0 = blockIdx.x * kChunk + (int64_t)threadIdx.x * kWordsPerThread;
-  int64_t c = 0;
-  for (int k = 0; k < kWordsPerThread; ++k) {
-    const int64_t q = q0 + k;
+  constexpr int kWaves = kBlock / 64;
+  constexpr int64_t kPerWave = kChunk / kWaves;  // 1024 words, 16 groups of 64
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t w0 = blockIdx.x * kChunk + wid * kPerWave;
+  int c = 0;
+  for (int g = 0; g < (int)(kPerWave / 64); ++g) {
+    const int64_t q = w0 + g * 64 + lane;
     if (q < n_words) c += __popcll(bits[q] & valid_bits(Sx, q % W));
   }
-  __shared__ int64_t s[kBlock];
-  s[threadIdx.x] = c;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  __shared__ int64_t wave_total[kWaves];
+  if (lane == 0) wave_total[wid] = c;
   __syncthreads();
-  for (int o = 1; o < kBlock; o <<= 1) {
-    const int64_t a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
-    __syncthreads();
-    s[threadIdx.x] += a;
-    __syncthreads();
-  }
-  int64_t at = chunk[blockIdx.x] + s[threadIdx.x] - c;
-  for (int k = 0; k < kWordsPerThread; ++k) {
-    const int64_t q = q0 + k;
-    if (q >= n_words) break;
-    const int64_t w = q % W, row = q / W;
-    uint64_t b = bits[q] & valid_bits(Sx, w);
-    while (b) {
-      const int i = __builtin_ctzll(b);
-      b &= b - 1;
-      ids[at++] = (uint64_t)(row * Sx + 64 * w + i);
+  int64_t at = chunk[blockIdx.x];
+  for (int k = 0; k < wid; ++k) at += wave_total[k];
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));  // lanes under this one
+  for (int g = 0; g < (int)(kPerWave / 64); ++g) {
+    const int64_t q = w0 + g * 64 + lane;
+    uint64_t b = 0;
+    int64_t id0 = 0;
+    if (q < n_words) {
+      const int64_t row = q / W, w = q - row * W;
+      b = bits[q] & valid_bits(Sx, w);
+      id0 = row * Sx + 64 * w;
     }
+    const int pc = __popcll(b);
+    int incl = pc;  // inclusive scan of the counts over the lanes
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(incl, o);
+      if (lane >= o) incl += u;
+    }
+    const int excl = incl - pc;
+    uint64_t any = __ballot(b != 0);
+    while (any) {
+      const int k = __builtin_ctzll(any);
+      any &= any - 1;
+      const uint64_t bk = __shfl(b, k);
+      const int64_t ik = __shfl(id0, k);
+      const int ek = __shfl(excl, k);
+      if ((bk >> lane) & 1ull) ids[at + ek + __popcll(bk & below)] = (uint64_t)(ik + lane);
+    }
+    at += __shfl(incl, 63);
   }
 }
 
@@ -327,22 +373,24 @@ hipError_t launch_feature_mask(const float* field, const int64_t* dims, int kind
                                float hi, uint64_t* bits, void* ws, hipStream_t st) {
   const int64_t W = (dims[0] + 63) / 64, n = mask_words(dims);
   if (kind == FHASH_FEATURE_INTERVAL) {
-    classify_kernel<<<grid_for(n, kBlock / 64), kBlock, 0, st>>>(field, dims[0], W, n, kind, lo,
-                                                                  hi, bits);
+    classify_kernel<<<grid_for(n, kBlock / 64 * kUnroll), kBlock, 0, st>>>(field, dims[0], W, n,
+                                                                            kind, lo, hi, bits);
     return hipGetLastError();
   }
   uint64_t* sign = static_cast<uint64_t*>(ws);
-  classify_kernel<<<grid_for(n, kBlock / 64), kBlock, 0, st>>>(field, dims[0], W, n, kind, lo, hi,
-                                                                sign);
-  iso_kernel<<<grid_for(n, kBlock), kBlock, 0, st>>>(sign, dims[0], dims[1], dims[2], W, n, bits);
+  classify_kernel<<<grid_for(n, kBlock / 64 * kUnroll), kBlock, 0, st>>>(field, dims[0], W, n,
+                                                                          kind, lo, hi, sign);
+  iso_kernel<<<(unsigned)(dims[3] * dims[2]), kBlock, 0, st>>>(sign, dims[0], dims[1], dims[2], W,
+                                                               bits);
   return hipGetLastError();
 }
 
 hipError_t launch_dilate_mask(const uint64_t* in, const int64_t* dims, int r, uint64_t* out,
                               hipStream_t st) {
   const int64_t W = (dims[0] + 63) / 64, n = mask_words(dims);
-  dilate_kernel<<<grid_for(n, kBlock), kBlock, 0, st>>>(in, dims[0], dims[1], dims[2], W, n, r,
-                                                         out);
+  (void)n;
+  dilate_kernel<<<(unsigned)(dims[3] * dims[2]), kBlock, 0, st>>>(in, dims[0], dims[1], dims[2], W,
+                                                                  r, out);
   return hipGetLastError();
 }
 
@@ -351,10 +399,8 @@ hipError_t launch_feature_boxes(const uint64_t* bits, const int64_t* dims, int32
   const int64_t W = (dims[0] + 63) / 64, T = dims[3];
   box_init_kernel<<<grid_for(T + 1, kBlock), kBlock, 0, st>>>(box, T + 1, (int32_t)dims[0],
                                                                (int32_t)dims[1], (int32_t)dims[2]);
-  const int64_t per_frame = dims[2] * dims[1] * W;
-  const int64_t gx = (per_frame + kBlock - 1) / kBlock;
-  dim3 grid((unsigned)(gx < 1 ? 1 : gx > 1024 ? 1024 : gx), (unsigned)T);
-  box_kernel<<<grid, kBlock, 0, st>>>(bits, dims[0], dims[1], dims[2], W, T, box);
+  box_kernel<<<(unsigned)(T * dims[2]), kBlock, 0, st>>>(bits, dims[0], dims[1], dims[2], W, T, box);
+  fuse_boxes_kernel<<<1, 64, 0, st>>>(box, T);
   return hipGetLastError();
 }
 
@@ -366,9 +412,8 @@ hipError_t launch_occupancy_morton(const uint64_t* bits, const int64_t* dims, ui
                                    hipStream_t st) {
   const int64_t W = (dims[0] + 63) / 64;
   const int64_t Bx = (dims[0] + 3) / 4, By = (dims[1] + 3) / 4, Bz = (dims[2] + 3) / 4;
-  const int64_t n = occupancy_words(dims);
-  morton_kernel<<<grid_for(n, kBlock), kBlock, 0, st>>>(bits, dims[0], dims[1], dims[2], W, Bx,
-                                                         By, Bz, n, occ);
+  morton_kernel<<<(unsigned)(dims[3] * Bz), kBlock, 0, st>>>(bits, dims[0], dims[1], dims[2], W, Bx,
+                                                             By, Bz, occ);
   return hipGetLastError();
 }
 
