@@ -55,6 +55,72 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Bits 0..15 of x moved to bits 0, 4, 8, ..., 60.
+__device__ __forceinline__ uint64_t spread4(uint64_t x) {
+  x &= 0xFFFFull;
+  x = (x | (x << 24)) & 0x000000FF000000FFull;
+  x = (x | (x << 12)) & 0x000F000F000F000Full;
+  x = (x | (x << 6)) & 0x0303030303030303ull;
+  x = (x | (x << 3)) & 0x1111111111111111ull;
+  return x;
+}
+
+// Pass 1 for rows of a multiple of 4 voxels on a 16-byte aligned field: a wave
+// takes a segment of 4 words (256 voxels) of one row, lane l loads voxels
+// 4l..4l+3 as one float4, and four ballots (one per component) hold the
+// segment's bits; word k of the segment is bits 16k..16k+15 of the four
+// ballots interleaved, which lane k assembles and stores.
+__global__ void __launch_bounds__(kBlock)
+    classify4_kernel(const float* __restrict__ field, int64_t Sx, int64_t W, int64_t n_seg,
+                     int kind, float lo, float hi, uint64_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t SW = (W + 3) / 4;
+  const int64_t step = (int64_t)gridDim.x * (kBlock / 64) * kUnroll;
+  for (int64_t q0 = (blockIdx.x * (int64_t)(kBlock / 64) + (threadIdx.x >> 6)) * kUnroll;
+       q0 < n_seg; q0 += step) {
+    f32x4 v[kUnroll];
+    bool in[kUnroll];
+    int64_t row[kUnroll], sw[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t q = q0 + u;
+      row[u] = q / SW;
+      sw[u] = q - row[u] * SW;
+      const int64_t x = 256 * sw[u] + 4 * lane;
+      in[u] = q < n_seg && x < Sx;
+      v[u] = in[u] ? __builtin_nontemporal_load(
+                         reinterpret_cast<const f32x4*>(field + row[u] * Sx + x))
+                   : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const f32x4 a = v[u];
+      bool p0, p1, p2, p3;
+      if (kind == FHASH_FEATURE_INTERVAL) {
+        p0 = a.x > lo && a.x <= hi;
+        p1 = a.y > lo && a.y <= hi;
+        p2 = a.z > lo && a.z <= hi;
+        p3 = a.w > lo && a.w <= hi;
+      } else {
+        p0 = a.x >= lo;
+        p1 = a.y >= lo;
+        p2 = a.z >= lo;
+        p3 = a.w >= lo;
+      }
+      const uint64_t b0 = __ballot(in[u] && p0), b1 = __ballot(in[u] && p1);
+      const uint64_t b2 = __ballot(in[u] && p2), b3 = __ballot(in[u] && p3);
+      const int64_t w = 4 * sw[u] + lane;
+      if (lane < 4 && q0 + u < n_seg && w < W) {
+        const int sh = 16 * lane;
+        out[row[u] * W + w] = spread4(b0 >> sh) | (spread4(b1 >> sh) << 1) |
+                              (spread4(b2 >> sh) << 2) | (spread4(b3 >> sh) << 3);
+      }
+    }
+  }
+}
+
 // Cells of x-row (z, y) pairs crossed by the isosurface, for the 64 cells
 // cx = 64 w .. 64 w + 63 of cell row (cz, cy): some corner at or above the
 // level and some below it.  sign = pass-1 bits (padding bits zero).
@@ -135,6 +201,47 @@ __global__ void __launch_bounds__(kBlock)
         f |= d;
       }
     out[q] = f & valid_bits(Sx, w);
+  }
+}
+
+// The same dilation, separable inside a workgroup: pass 1 ORs the x-dilated
+// rows of the z window into an LDS copy of the slice ((2r+1) x 3 word loads
+// per word), pass 2 ORs the y window out of LDS, so a word costs 6r + 3 global
+// loads instead of 3 (2r+1)^2.  Used when a slice fits kDilateLdsWords.
+constexpr int kDilateLdsWords = 8192;  // 64 KiB of LDS
+__global__ void __launch_bounds__(kBlock)
+    dilate_lds_kernel(const uint64_t* __restrict__ in, int64_t Sx, int64_t Sy, int64_t Sz,
+                      int64_t W, int r, uint64_t* __restrict__ out) {
+  extern __shared__ uint64_t zx[];  // [Sy][W]
+  const int64_t slice = blockIdx.x;
+  const int64_t z = slice % Sz;
+  const int64_t frame_row0 = (slice - z) * Sy;
+  const uint32_t per_slice = (uint32_t)(Sy * W), Wu = (uint32_t)W;
+  const int64_t z0 = z - r < 0 ? 0 : z - r, z1 = z + r > Sz - 1 ? Sz - 1 : z + r;
+  for (uint32_t i = threadIdx.x; i < per_slice; i += kBlock) {
+    const int64_t y = i / Wu, w = i - (uint32_t)y * Wu;
+    uint64_t f = 0;
+    for (int64_t c = z0; c <= z1; ++c) {
+      const uint64_t* rw = in + (frame_row0 + c * Sy + y) * W;
+      const uint64_t s = rw[w];
+      const uint64_t pv = w > 0 ? rw[w - 1] : 0ull;
+      const uint64_t nx = w + 1 < W ? rw[w + 1] : 0ull;
+      uint64_t d = s;
+      for (int k = 1; k <= r; ++k) {
+        d |= (s << k) | (pv >> (64 - k));
+        d |= (s >> k) | (nx << (64 - k));
+      }
+      f |= d;
+    }
+    zx[i] = f;
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < per_slice; i += kBlock) {
+    const int64_t y = i / Wu, w = i - (uint32_t)y * Wu;
+    const int64_t y0 = y - r < 0 ? 0 : y - r, y1 = y + r > Sy - 1 ? Sy - 1 : y + r;
+    uint64_t f = 0;
+    for (int64_t b = y0; b <= y1; ++b) f |= zx[b * W + w];
+    out[slice * per_slice + i] = f & valid_bits(Sx, w);
   }
 }
 
@@ -369,17 +476,28 @@ size_t feature_ws_bytes(const int64_t* dims, int kind) {
   return kind == FHASH_FEATURE_ISOSURFACE ? (size_t)mask_words(dims) * 8 : 0;
 }
 
+// Extraction pass into `out`: the float4 form when every row starts 16-byte aligned.
+static void classify(const float* field, const int64_t* dims, int64_t W, int64_t n, int kind, float lo,
+              float hi, uint64_t* out, hipStream_t st) {
+  if (dims[0] % 4 == 0 && (reinterpret_cast<uintptr_t>(field) & 15u) == 0) {
+    const int64_t n_seg = dims[3] * dims[2] * dims[1] * ((W + 3) / 4);
+    classify4_kernel<<<grid_for(n_seg, kBlock / 64 * kUnroll), kBlock, 0, st>>>(
+        field, dims[0], W, n_seg, kind, lo, hi, out);
+  } else {
+    classify_kernel<<<grid_for(n, kBlock / 64 * kUnroll), kBlock, 0, st>>>(field, dims[0], W, n,
+                                                                            kind, lo, hi, out);
+  }
+}
+
 hipError_t launch_feature_mask(const float* field, const int64_t* dims, int kind, float lo,
                                float hi, uint64_t* bits, void* ws, hipStream_t st) {
   const int64_t W = (dims[0] + 63) / 64, n = mask_words(dims);
   if (kind == FHASH_FEATURE_INTERVAL) {
-    classify_kernel<<<grid_for(n, kBlock / 64 * kUnroll), kBlock, 0, st>>>(field, dims[0], W, n,
-                                                                            kind, lo, hi, bits);
+    classify(field, dims, W, n, kind, lo, hi, bits, st);
     return hipGetLastError();
   }
   uint64_t* sign = static_cast<uint64_t*>(ws);
-  classify_kernel<<<grid_for(n, kBlock / 64 * kUnroll), kBlock, 0, st>>>(field, dims[0], W, n,
-                                                                          kind, lo, hi, sign);
+  classify(field, dims, W, n, kind, lo, hi, sign, st);
   iso_kernel<<<(unsigned)(dims[3] * dims[2]), kBlock, 0, st>>>(sign, dims[0], dims[1], dims[2], W,
                                                                bits);
   return hipGetLastError();
@@ -389,8 +507,13 @@ hipError_t launch_dilate_mask(const uint64_t* in, const int64_t* dims, int r, ui
                               hipStream_t st) {
   const int64_t W = (dims[0] + 63) / 64, n = mask_words(dims);
   (void)n;
-  dilate_kernel<<<(unsigned)(dims[3] * dims[2]), kBlock, 0, st>>>(in, dims[0], dims[1], dims[2], W,
-                                                                  r, out);
+  if (dims[1] * W <= kDilateLdsWords) {
+    dilate_lds_kernel<<<(unsigned)(dims[3] * dims[2]), kBlock, (size_t)(dims[1] * W) * 8, st>>>(
+        in, dims[0], dims[1], dims[2], W, r, out);
+  } else {
+    dilate_kernel<<<(unsigned)(dims[3] * dims[2]), kBlock, 0, st>>>(in, dims[0], dims[1], dims[2],
+                                                                    W, r, out);
+  }
   return hipGetLastError();
 }
 

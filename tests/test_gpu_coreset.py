@@ -12,6 +12,10 @@ from oracle import coreset as OC
 from paper_2507_03836_amd import synth
 
 SHAPES = [(70, 5, 3, 2), (130, 9, 4, 3), (64, 4, 4, 2), (65, 3, 2, 2), (2, 2, 2, 2)]
+# rows of a multiple of 4 voxels take the float4 extraction pass: a partial
+# 256-voxel segment (300: words 4..7 of the second segment, only word 4 real),
+# whole segments (256, 512) and more words than one segment (1028)
+SHAPES4 = [(300, 7, 5, 3), (256, 3, 2, 2), (512, 2, 3, 2), (1028, 3, 2, 2), (4, 3, 3, 2)]
 
 
 def _fl():
@@ -41,7 +45,7 @@ def _mask_dev(mask):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("dims", SHAPES + SHAPES4)
 def test_feature_interval_parity(fl, dims):
     print(f"[coreset] interval {dims}", flush=True)
     f = _np_field(dims, 1)
@@ -54,7 +58,7 @@ def test_feature_interval_parity(fl, dims):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("dims", SHAPES + SHAPES4)
 def test_feature_isosurface_parity(fl, dims):
     print(f"[coreset] isosurface {dims}", flush=True)
     f = _np_field(dims, 2)
@@ -76,6 +80,20 @@ def test_dilate_parity(fl, dims, r):
     out = fl.fhash_dilate_mask(_mask_dev(m), dims, r)
     torch.cuda.synchronize()
     assert np.array_equal(_words(out), OC.pack_rows(OC.dilate(m, r)).ravel())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("r", [1, 2])
+def test_dilate_parity_large_slice(fl, r):
+    """A (t, z) slice of 130 rows x 64 words (8,320 words, above the 8,192 that
+    the LDS form holds) takes the direct form; 128 rows x 64 words the LDS form."""
+    for dims in [(4096, 130, 3, 2), (4096, 128, 3, 2)]:
+        print(f"[coreset] dilate {dims} r={r}", flush=True)
+        Sx, Sy, Sz, T = dims
+        m = np.random.default_rng(30 + r).random((T, Sz, Sy, Sx)) < 0.001
+        out = fl.fhash_dilate_mask(_mask_dev(m), dims, r)
+        torch.cuda.synchronize()
+        assert np.array_equal(_words(out), OC.pack_rows(OC.dilate(m, r)).ravel())
 
 
 @pytest.mark.gpu
