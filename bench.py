@@ -645,7 +645,8 @@ def coreset_bench(args):
                                "gradient-magnitude feature above its 80th percentile, "
                                "dilation by 2", "shape": dims, "coreset": M},
         "breakdown": out,
-        "roofline": {"kernel": "classify_kernel", "bound": "hbm", "achieved": dom["GB_s"],
+        "roofline": {"kernel": "classify4_kernel" if Sx % 4 == 0 else "classify_kernel",
+                     "bound": "hbm", "achieved": dom["GB_s"],
                      "peak": 8000.0, "unit": "GB/s", "frac": dom["frac"], "traffic": None,
                      "algorithmic_bytes": dom["algorithmic_bytes"], "kernel_ms": dom["ms"]},
         "cpu_baseline": cpu}))
