@@ -336,34 +336,44 @@ __global__ void __launch_bounds__(64) fuse_boxes_kernel(int32_t* box, int64_t T)
 // Occupancy grid: one word per 4x4x4 brick, bricks row-major (bx fastest),
 // voxel (lx, ly, lz) of a brick at bit lx0 | ly0<<1 | lz0<<2 | lx1<<3 | ly1<<4 |
 // lz1<<5 (Morton order inside the brick).  Voxels outside the volume are 0.
-// One workgroup per (t, bz) slab of bricks (blockIdx.x = t Bz + bz).
+// One workgroup per (t, bz) slab of bricks (blockIdx.x = t Bz + bz).  A thread
+// takes one mask word w of one brick row by: it loads the word from each of
+// the brick row's 16 voxel rows (4 z x 4 y) once and writes the 16 bricks
+// bx = 16 w .. 16 w + 15 that those words cover.
 __global__ void __launch_bounds__(kBlock)
     morton_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
                   int64_t Bx, int64_t By, int64_t Bz, uint64_t* __restrict__ occ) {
   const int64_t slab = blockIdx.x;
   const int64_t bz = slab % Bz, t = slab / Bz;
-  const uint32_t per_slab = (uint32_t)(By * Bx), Bxu = (uint32_t)Bx;
+  const uint32_t per_slab = (uint32_t)(By * W), Wu = (uint32_t)W;
   for (uint32_t i = threadIdx.x; i < per_slab; i += kBlock) {
-    const int64_t by = i / Bxu, bx = i - (uint32_t)by * Bxu;
-    const int64_t q = slab * per_slab + i;
-    const int64_t x0 = 4 * bx, w = x0 >> 6, sh = x0 & 63;  // 4 | 64: a nibble never straddles
-    uint64_t o = 0;
-    for (int lz = 0; lz < 4; ++lz) {
-      const int64_t z = 4 * bz + lz;
-      if (z >= Sz) break;
+    const int64_t by = i / Wu, w = i - (uint32_t)by * Wu;
+    const uint64_t valid = valid_bits(Sx, w);
+    uint64_t r[4][4];
+#pragma unroll
+    for (int lz = 0; lz < 4; ++lz)
+#pragma unroll
       for (int ly = 0; ly < 4; ++ly) {
-        const int64_t y = 4 * by + ly;
-        if (y >= Sy) break;
-        const uint64_t nib = (bits[((t * Sz + z) * Sy + y) * W + w] >> sh) & 0xFull;
-        for (int lx = 0; lx < 4; ++lx)
-          if (((nib >> lx) & 1ull) && x0 + lx < Sx) {
-            const int m = (lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2) | ((lx >> 1) << 3) |
-                          ((ly >> 1) << 4) | ((lz >> 1) << 5);
-            o |= 1ull << m;
-          }
+        const int64_t z = 4 * bz + lz, y = 4 * by + ly;
+        r[lz][ly] = (z < Sz && y < Sy) ? bits[((t * Sz + z) * Sy + y) * W + w] & valid : 0ull;
       }
+    uint64_t* dst = occ + (slab * By + by) * Bx;
+    for (int j = 0; j < 16; ++j) {
+      const int64_t bx = 16 * w + j;
+      if (bx >= Bx) break;
+      uint64_t o = 0;
+#pragma unroll
+      for (int lz = 0; lz < 4; ++lz)
+#pragma unroll
+        for (int ly = 0; ly < 4; ++ly) {
+          const uint64_t nib = (r[lz][ly] >> (4 * j)) & 0xFull;  // voxels lx = 0..3
+          // lx bit 0 -> Morton bit 0, lx bit 1 -> Morton bit 3
+          const uint64_t xs = (nib & 0x3ull) | ((nib & 0xCull) << 6);
+          const int base = ((ly & 1) << 1) | ((lz & 1) << 2) | ((ly >> 1) << 4) | ((lz >> 1) << 5);
+          o |= xs << base;
+        }
+      dst[bx] = o;
     }
-    occ[q] = o;
   }
 }
 
