@@ -363,7 +363,8 @@ int fhash_cast(const float* src, void* dst, fhash_dtype dst_dt, int64_t n, void*
  *   timestep) is crossed iff some corner has v >= lo and some corner v < lo;
  *   a voxel is set iff it is a corner of a crossed cell.  hi is unused.
  *   ws: device workspace of *ws_bytes (one mask for the isosurface, 0 for the
- *   interval); with ws == NULL only *ws_bytes is written.
+ *   interval); with ws == NULL and ws_bytes != NULL only *ws_bytes is written
+ *   (a size query); the interval kind runs with ws == NULL and ws_bytes == NULL.
  * fhash_dilate_mask: feature dilation inside each timestep by a cube of
  * radius r in [0, 63]: out voxel set iff an in voxel of the same timestep lies
  * within r voxels along each of x, y and z.  in and out must not overlap.
@@ -372,6 +373,8 @@ int fhash_cast(const float* src, void* dst, fhash_dtype dst_dt, int64_t n, void*
  * indices; row T = the FBB, the smallest box containing every b_k (temporal
  * fusion).  An empty timestep (or an empty mask, row T) reads
  * (Sx, Sy, Sz, -1, -1, -1).
+ * fhash_occupancy_words: words of the occupancy grid of dims (-1 if dims are
+ * invalid).
  * fhash_occupancy_grid: occupancy bits for rendering, Morton order inside
  * 4x4x4 bricks: occ (uint64, fhash_occupancy_words(dims) words, device) holds
  * one word per brick, bricks in [T][ceil(Sz/4)][ceil(Sy/4)][ceil(Sx/4)] order;
