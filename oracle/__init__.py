@@ -104,7 +104,7 @@ def _declare(L):
     L.or_occupied.argtypes = [P, P, P, C.c_float]
     L.or_render.restype = I64
     L.or_render.argtypes = [P, P, C.c_int, P, P, P, P, P, C.c_float, P, C.c_int, C.c_int,
-                            C.c_float, C.c_float, C.c_int, P, P]
+                            C.c_float, C.c_float, C.c_int, P, P, P]
     L.or_sample_batch.restype = None
     L.or_sample_batch.argtypes = [U64, U64, I64, P, U64, P, P, P, P]
 
@@ -391,8 +391,10 @@ def sample_batch(seed, step, n, field, coreset=None):
 
 # --------------------------------------------------------------------------- render
 def render(grid: Grid, table, width, params, mask, view14, t, tf, W, H, ds=0.5,
-           alpha_stop=0.99, max_steps=1 << 20):
-    """Oracle image [H][W][4] (FP64), ambiguity flags [H][W], evaluated samples."""
+           alpha_stop=0.99, max_steps=1 << 20, pixel_stats=False):
+    """Oracle image [H][W][4] (FP64), ambiguity flags [H][W], evaluated samples;
+    with pixel_stats also [H][W][3]: composited samples, sum of their output
+    magnitudes, smallest |A - alpha_stop| over the composited steps."""
     tab = _c(table, np.float64)
     w = _c(width, np.int32)
     prm = _c(params, np.float64)
@@ -402,9 +404,12 @@ def render(grid: Grid, table, width, params, mask, view14, t, tf, W, H, ds=0.5,
     tfa = _c(tf, np.float32)
     rgba = np.zeros((H, W, 4), np.float64)
     amb = np.zeros((H, W), np.uint8)
+    pix = np.zeros((H, W, 3), np.float64)
     ev = lib().or_render(grid.ref(), _p(tab), len(w) - 1, _p(w), _p(prm), _p(m), _p(S), _p(cam),
                          C.c_float(t), _p(tfa), W, H, C.c_float(ds), C.c_float(alpha_stop),
-                         max_steps, _p(rgba), _p(amb))
+                         max_steps, _p(rgba), _p(amb), _p(pix))
+    if pixel_stats:
+        return rgba, amb.astype(bool), int(ev), pix
     return rgba, amb.astype(bool), int(ev)
 
 

@@ -725,18 +725,23 @@ static void apply_tf(const float* tf, double v, double rgba[4]) {
  * which samples are evaluated together, never the image, so this walk is one
  * sample at a time.  rgba: [H][W][4]; amb[H][W] flags pixels whose opacity came
  * within 1e-5 of alpha_stop at some step (termination point rounding-sensitive).
+ * pix (may be NULL): per pixel [H][W][3] the number of composited samples, the
+ * sum of their decoder-output magnitudes (sum of |terms| of each output) and
+ * the smallest |A - alpha_stop| over the composited steps (1 when none), the
+ * quantities an error bound of another evaluation order needs.
  * Returns the number of evaluated samples. */
 int64_t or_render(const or_grid* g, const double* table, int n_layers, const int32_t* width,
                   const double* params, const uint8_t* mask, const int64_t S[4], const float* cam,
                   float t, const float* tf, int W, int H, float ds, float alpha_stop,
-                  int max_steps, double* rgba, uint8_t* amb) {
+                  int max_steps, double* rgba, uint8_t* amb, double* pix) {
   int64_t evals = 0;
   const int L = g->n_levels, F = g->n_features;
-  double* enc = (double*)malloc(sizeof(double) * L * F);
+  double* enc = (double*)malloc(sizeof(double) * L * F * 2);
   const float tn = t / (float)(S[3] - 1);
   for (int py = 0; py < H; ++py)
     for (int px = 0; px < W; ++px) {
       double C[3] = {0, 0, 0}, A = 0.0;
+      double n_comp = 0.0, ymag_sum = 0.0, margin = 1.0;
       int ambiguous = 0;
       float org[3], dir[3], s0, s1;
       pixel_ray(cam, W, H, px, py, org, dir);
@@ -751,15 +756,19 @@ int64_t or_render(const or_grid* g, const double* table, int n_layers, const int
           float q[4] = {p[0] / (float)(S[0] - 1), p[1] / (float)(S[1] - 1),
                         p[2] / (float)(S[2] - 1), tn};
           double y, ym;
-          or_encode_fwd(g, q, 1, table, enc, NULL);
-          or_mlp_fwd(n_layers, width, params, enc, 1, &y, NULL, NULL, &ym);
+          double* encm = enc + L * F;
+          or_encode_fwd(g, q, 1, table, enc, encm);
+          or_mlp_fwd(n_layers, width, params, enc, 1, &y, NULL, encm, &ym);
           ++evals;
+          n_comp += 1.0;
+          ymag_sum += ym;
           double c[4];
           apply_tf(tf, y, c);
           double a = c[3];
           for (int d = 0; d < 3; ++d) C[d] += (1.0 - A) * a * c[d];
           A += (1.0 - A) * a;
           if (fabs(A - alpha_stop) < 1e-5) ambiguous = 1;
+          if (fabs(A - alpha_stop) < margin) margin = fabs(A - alpha_stop);
           if (A >= alpha_stop) break;
         }
       }
@@ -769,6 +778,12 @@ int64_t or_render(const or_grid* g, const double* table, int n_layers, const int
       o[2] = C[2];
       o[3] = A;
       if (amb) amb[(int64_t)py * W + px] = (uint8_t)ambiguous;
+      if (pix) {
+        double* q = pix + ((int64_t)py * W + px) * 3;
+        q[0] = n_comp;
+        q[1] = ymag_sum;
+        q[2] = margin;
+      }
     }
   free(enc);
   return evals;

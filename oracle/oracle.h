@@ -92,7 +92,7 @@ int or_occupied(const uint8_t* mask, const int64_t S[4], const float p[3], float
 int64_t or_render(const or_grid* g, const double* table, int n_layers, const int32_t* width,
                   const double* params, const uint8_t* mask, const int64_t S[4], const float* cam,
                   float t, const float* tf, int W, int H, float ds, float alpha_stop,
-                  int max_steps, double* rgba, uint8_t* amb);
+                  int max_steps, double* rgba, uint8_t* amb, double* pix);
 
 #ifdef __cplusplus
 }
