@@ -1,8 +1,11 @@
 """Seeded synthetic inputs shaped like the paper's time-varying volumes.
 
-This module produces inputs only (fields, feature masks, coresets, initial
-parameters, probe points); it holds none of the method's arithmetic and is the
-one place that both the HIP path and the CPU oracle take their inputs from.
+This module produces inputs only (fields, the gradient-magnitude attribute
+and the threshold value that define the feature, initial parameters, probe
+points, cameras); it holds none of the method's arithmetic and is the one
+place that both the HIP path and the CPU oracle take their inputs from.  The
+feature masks and coresets are computed from these inputs by the method's own
+code: the coreset-selection calls on the GPU, oracle/coreset.py in the tests.
 
 Workload recipe (shapes/distributions of the paper's datasets, which are not
 available: scalar float32 fields normalised to [0,1], sparse moving features,
@@ -10,10 +13,10 @@ hundreds of voxels per side, tens to a hundred timesteps):
 
 * tiny     : 32^3 x 8, 8 advected Gaussian blobs (centre U[0,1]^3, sigma
              U[0.05,0.15], amplitude U[0.5,1], velocity U[-0.05,0.05]^3 per
-             step), clipped to [0,1]; mask = value > 0.1, dilated by 1.
+             step), clipped to [0,1]; feature = value > 0.1, dilated by 1.
 * production: 64 blobs (sigma U[0.02,0.08], amplitude U[0.5,1], velocity
              U[-0.004,0.004]^3) + 0.25 * 3-octave 4D value noise, min-max
-             normalised; mask = |grad| > 80th percentile, dilated by 2.
+             normalised; feature = |grad| > its 80th percentile, dilated by 2.
 """
 from __future__ import annotations
 
@@ -61,12 +64,7 @@ def _G():
         L.sy_gpu_normalise.argtypes = [P, I64, P, P]
         L.sy_gpu_grad_mag.argtypes = [P, P, P, P]
         L.sy_gpu_select.argtypes = [P, I64, I64, P, P, P]
-        L.sy_gpu_mask_bits.argtypes = [P, P, C.c_float, P, P]
-        L.sy_gpu_dilate.argtypes = [P, P, P, C.c_int, P]
-        L.sy_gpu_popcounts.argtypes = [P, I64, P, P]
-        L.sy_gpu_emit.argtypes = [P, P, P, P, P]
-        for n in ("sy_gpu_field", "sy_gpu_normalise", "sy_gpu_grad_mag", "sy_gpu_select",
-                  "sy_gpu_mask_bits", "sy_gpu_dilate", "sy_gpu_popcounts", "sy_gpu_emit"):
+        for n in ("sy_gpu_field", "sy_gpu_normalise", "sy_gpu_grad_mag", "sy_gpu_select"):
             getattr(L, n).restype = C.c_int
         _glib = L
     return _glib
@@ -91,12 +89,6 @@ def _L():
         L.sy_grad_mag.argtypes = [P, P, P]
         L.sy_quantile.restype = C.c_float
         L.sy_quantile.argtypes = [P, I64, D]
-        L.sy_threshold.restype = None
-        L.sy_threshold.argtypes = [P, I64, C.c_float, P]
-        L.sy_dilate.restype = None
-        L.sy_dilate.argtypes = [P, P, C.c_int, P]
-        L.sy_coreset.restype = I64
-        L.sy_coreset.argtypes = [P, I64, P]
         _lib = L
     return _lib
 
@@ -135,30 +127,6 @@ def quantile(v, q):
     return float(_L().sy_quantile(_p(v), v.size, q))
 
 
-def threshold(v, thr):
-    v = np.ascontiguousarray(v, np.float32)
-    m = np.zeros(v.shape, np.uint8)
-    _L().sy_threshold(_p(v), v.size, thr, _p(m))
-    return m
-
-
-def dilate(mask, r):
-    m = np.ascontiguousarray(mask, np.uint8)
-    T, Sz, Sy, Sx = m.shape
-    S = np.array([Sx, Sy, Sz, T], np.int64)
-    out = np.zeros_like(m)
-    _L().sy_dilate(_p(S), _p(m), r, _p(out))
-    return out
-
-
-def coreset(mask):
-    m = np.ascontiguousarray(mask, np.uint8).ravel()
-    n = _L().sy_coreset(_p(m), m.size, None)
-    ids = np.zeros(n, np.uint64)
-    _L().sy_coreset(_p(m), m.size, _p(ids))
-    return ids
-
-
 def pack_mask_rows(mask) -> np.ndarray:
     """Byte mask [T][Sz][Sy][Sx] -> bit words [T][Sz][Sy][ceil(Sx/64)] (uint64),
     bit b of word w of a row = voxel x = 64*w + b; padding bits are zero."""
@@ -172,23 +140,27 @@ def pack_mask_rows(mask) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------- workloads
-def tiny_volume(seed=SEED_FIELD + 1, shape=(32, 32, 32, 8), n_blobs=8):
-    """The tiny parity workload: field, dilated feature mask (value > 0.1, r = 1)."""
+TINY_FEATURE_LO, TINY_DILATION = 0.1, 1
+PRODUCTION_QUANTILE, PRODUCTION_DILATION = 0.8, 2
+
+
+def tiny_field(seed=SEED_FIELD + 1, shape=(32, 32, 32, 8), n_blobs=8):
+    """The tiny parity workload's field; its feature is value > TINY_FEATURE_LO,
+    dilated by TINY_DILATION."""
     blobs = blob_params(seed, n_blobs, (0.05, 0.15), (0.5, 1.0), 0.05)
-    f = field(shape, blobs, clip01=True)
-    mask = dilate(threshold(f, 0.1), 1)
-    return f, mask
+    return field(shape, blobs, clip01=True)
 
 
-def production_volume_host(shape, seed, n_blobs=64):
-    """Host version of the production-shape generator (small shapes only)."""
+def production_field_host(shape, seed, n_blobs=64):
+    """Host version of the production-shape generator (small shapes only):
+    field, gradient-magnitude attribute, and the feature threshold value (its
+    PRODUCTION_QUANTILE order statistic); the feature is |grad| > threshold,
+    dilated by PRODUCTION_DILATION."""
     blobs = blob_params(seed, n_blobs, (0.02, 0.08), (0.5, 1.0), 0.004)
     f = field(shape, blobs, turb_amp=0.25, noise_seed=seed * 7919 + 17, clip01=False,
               normalise=True)
     g = grad_mag(f)
-    thr = quantile(g, 0.8)
-    mask = dilate(threshold(g, thr), 2)
-    return f, mask
+    return f, g, quantile(g, PRODUCTION_QUANTILE)
 
 
 def table_init(n_slots, n_features, seed=SEED_INIT, scale=1e-4):
@@ -215,13 +187,13 @@ def probe_points(n, seed=SEED_PROBE):
     return rng.random((n, 4), dtype=np.float64).astype(np.float32)
 
 
-def production_volume_gpu(shape_xyzt, seed, n_blobs=64, quantile_q=0.8, radius=2,
-                          keep_field=True):
-    """Device version of production_volume_host (same definitions) for large shapes.
+def production_field_gpu(shape_xyzt, seed, n_blobs=64, quantile_q=PRODUCTION_QUANTILE,
+                         keep_field=True):
+    """Device version of production_field_host (same definitions) for large shapes.
 
     Returns dict(field=float32 [T][Sz][Sy][Sx] device tensor (or None),
-    bits=row-padded mask words (int64 view of uint64) [T][Sz][Sy][W],
-    coreset=int64 view of uint64 linear voxel ids (ascending), threshold)."""
+    grad=its gradient magnitude (device), threshold=the quantile_q order
+    statistic of grad, N=voxel count)."""
     import torch
 
     G = _G()
@@ -242,29 +214,11 @@ def production_volume_gpu(shape_xyzt, seed, n_blobs=64, quantile_q=0.8, radius=2
     rank = min(int(np.floor(quantile_q * N)), N - 1)
     assert G.sy_gpu_select(C.c_void_p(g.data_ptr()), N, rank, C.c_void_p(hist.data_ptr()),
                            C.byref(thr), st) == 0
-    W = (Sx + 63) // 64
-    bits = torch.empty((T, Sz, Sy, W), dtype=torch.int64, device="cuda")
-    assert G.sy_gpu_mask_bits(C.c_void_p(g.data_ptr()), _p(dims), thr, C.c_void_p(bits.data_ptr()),
-                              st) == 0
-    del g
-    tmp = torch.empty_like(bits)
-    assert G.sy_gpu_dilate(C.c_void_p(bits.data_ptr()), C.c_void_p(tmp.data_ptr()), _p(dims),
-                           radius, st) == 0
-    del tmp
-    cnt = torch.empty(bits.numel(), dtype=torch.int64, device="cuda")
-    assert G.sy_gpu_popcounts(C.c_void_p(bits.data_ptr()), bits.numel(),
-                              C.c_void_p(cnt.data_ptr()), st) == 0
-    incl = torch.cumsum(cnt, 0)
-    M = int(incl[-1].item())
-    excl = incl - cnt
-    del cnt, incl
-    ids = torch.empty(max(M, 1), dtype=torch.int64, device="cuda")
-    assert G.sy_gpu_emit(C.c_void_p(bits.data_ptr()), _p(dims), C.c_void_p(excl.data_ptr()),
-                         C.c_void_p(ids.data_ptr()), st) == 0
-    del excl
+    if not keep_field:
+        del f
+        f = None
     torch.cuda.synchronize()
-    return dict(field=f if keep_field else None, bits=bits, coreset=ids[:M], threshold=thr.value,
-                M=M, N=N)
+    return dict(field=f, grad=g, threshold=thr.value, N=N)
 
 
 # --------------------------------------------------------------------------- render inputs

@@ -1,9 +1,12 @@
 /*
  * Seeded synthetic inputs for F-Hash: time-varying scalar volumes shaped like
  * the paper's workloads (sparse moving features in a [0,1]-normalised 4D
- * field), their feature masks and coresets.  This module holds none of the
- * method's arithmetic; it only produces inputs that both the HIP path and the
- * CPU oracle consume.  Host code, FP64 evaluation, FP32 storage.
+ * field), the gradient-magnitude attribute that the production feature is
+ * defined on, and the order statistic that sets its threshold value.  This
+ * module holds none of the method's arithmetic (feature masks, dilation and
+ * coresets are computed from these inputs by the method's own code); it only
+ * produces inputs that both the HIP path and the CPU oracle consume.  Host
+ * code, FP64 evaluation, FP32 storage.
  *
  * Volume layout: [T][Sz][Sy][Sx], x fastest.  Voxel (i,j,k) of any timestep
  * sits at p = (i/(Sx-1), j/(Sy-1), k/(Sz-1)); timestep n at n/(T-1).
@@ -158,45 +161,4 @@ float sy_quantile(const float* v, int64_t N, double q) {
   float out = c[r];
   free(c);
   return out;
-}
-
-/* mask[q] = v[q] > thr (strict). */
-void sy_threshold(const float* v, int64_t N, float thr, uint8_t* mask) {
-  for (int64_t q = 0; q < N; ++q) mask[q] = v[q] > thr ? 1 : 0;
-}
-
-/* Dilation by a Chebyshev cube of radius r within each timestep. */
-void sy_dilate(const int64_t S[4], const uint8_t* in, int r, uint8_t* out) {
-  const int64_t Sx = S[0], Sy = S[1], Sz = S[2], T = S[3];
-  for (int64_t n = 0; n < T; ++n)
-    for (int64_t k = 0; k < Sz; ++k)
-      for (int64_t j = 0; j < Sy; ++j)
-        for (int64_t i = 0; i < Sx; ++i) {
-          uint8_t m = 0;
-          for (int64_t c = k - r; c <= k + r && !m; ++c) {
-            if (c < 0 || c >= Sz) continue;
-            for (int64_t b = j - r; b <= j + r && !m; ++b) {
-              if (b < 0 || b >= Sy) continue;
-              for (int64_t a = i - r; a <= i + r; ++a) {
-                if (a < 0 || a >= Sx) continue;
-                if (in[((n * Sz + c) * Sy + b) * Sx + a]) {
-                  m = 1;
-                  break;
-                }
-              }
-            }
-          }
-          out[((n * Sz + k) * Sy + j) * Sx + i] = m;
-        }
-}
-
-/* Coreset: linear ids of the masked voxels in increasing order.  Returns the count. */
-int64_t sy_coreset(const uint8_t* mask, int64_t N, uint64_t* ids) {
-  int64_t c = 0;
-  for (int64_t q = 0; q < N; ++q)
-    if (mask[q]) {
-      if (ids) ids[c] = (uint64_t)q;
-      ++c;
-    }
-  return c;
 }

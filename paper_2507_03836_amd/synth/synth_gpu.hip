@@ -1,8 +1,9 @@
 // Device version of the seeded synthetic-input generator (same definitions as
 // synth.c, evaluated in FP64 on the GPU) for production-shape volumes that are
-// too large to generate on the host: field, min-max normalisation, gradient
-// magnitude, order-statistic threshold, bit mask, per-timestep cube dilation
-// and the coreset id list.  Inputs only: none of the method's arithmetic.
+// too large to generate on the host: the field, its min-max normalisation, the
+// gradient-magnitude attribute and the order statistic that sets the feature
+// threshold value.  Inputs only: the feature mask, its dilation and the
+// coreset are computed from these by the method's own calls.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -149,85 +150,6 @@ __global__ void hist_kernel(const float* __restrict__ v, int64_t N, int shift, u
     if (h[b]) atomicAdd(&hist[b], (unsigned long long)h[b]);
 }
 
-// Row-padded bit mask: bit x of row (n,k,j) = v[n][k][j][x] > thr.
-__global__ void mask_bits_kernel(const float* __restrict__ v, int64_t Sx, int64_t rows,
-                                 int64_t W, float thr, unsigned long long* __restrict__ bits) {
-  const int64_t total = rows * W;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t w = e % W, r = e / W;
-    unsigned long long m = 0;
-    for (int b = 0; b < 64; ++b) {
-      const int64_t x = w * 64 + b;
-      if (x < Sx && v[r * Sx + x] > thr) m |= 1ull << b;
-    }
-    bits[e] = m;
-  }
-}
-
-// Dilation along x within rows (shift-OR by -r..r with carries across words).
-__global__ void dilate_x_kernel(const unsigned long long* __restrict__ in,
-                                unsigned long long* __restrict__ out, int64_t rows, int64_t W,
-                                int64_t Sx, int r) {
-  const int64_t total = rows * W;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t w = e % W, row = e / W;
-    const unsigned long long* p = in + row * W;
-    const unsigned long long cur = p[w], prv = w > 0 ? p[w - 1] : 0ull,
-                             nxt = w + 1 < W ? p[w + 1] : 0ull;
-    unsigned long long m = cur;
-    for (int s = 1; s <= r; ++s) {
-      m |= (cur << s) | (prv >> (64 - s));  // voxel x-s set -> x set
-      m |= (cur >> s) | (nxt << (64 - s));  // voxel x+s set -> x set
-    }
-    const int64_t valid = Sx - w * 64;
-    if (valid < 64) m &= (valid <= 0) ? 0ull : ((1ull << valid) - 1ull);
-    out[e] = m;
-  }
-}
-
-// Dilation along an outer axis: out[o][a][q] = OR_{|d|<=r} in[o][a+d][q].
-__global__ void dilate_axis_kernel(const unsigned long long* __restrict__ in,
-                                   unsigned long long* __restrict__ out, int64_t outer,
-                                   int64_t A, int64_t inner, int r) {
-  const int64_t total = outer * A * inner;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t q = e % inner, a = (e / inner) % A, o = e / (inner * A);
-    unsigned long long m = 0;
-    for (int64_t d = -r; d <= r; ++d) {
-      const int64_t b = a + d;
-      if (b >= 0 && b < A) m |= in[(o * A + b) * inner + q];
-    }
-    out[e] = m;
-  }
-}
-
-__global__ void popc_kernel(const unsigned long long* __restrict__ bits, int64_t nw,
-                            long long* __restrict__ cnt) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nw;
-       e += (int64_t)gridDim.x * blockDim.x)
-    cnt[e] = __popcll(bits[e]);
-}
-
-// Emit linear voxel ids of set bits; excl[w] = number of set bits before word w.
-__global__ void emit_kernel(const unsigned long long* __restrict__ bits, int64_t nw, int64_t W,
-                            int64_t Sx, const long long* __restrict__ excl,
-                            unsigned long long* __restrict__ ids) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nw;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    unsigned long long m = bits[e];
-    long long o = excl[e];
-    const int64_t row = e / W, w = e % W;
-    while (m) {
-      const int b = __ffsll((long long)m) - 1;
-      ids[o++] = (unsigned long long)(row * Sx + w * 64 + b);
-      m &= m - 1;
-    }
-  }
-}
-
 inline unsigned nblk(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -289,43 +211,6 @@ int sy_gpu_select(const float* v, int64_t N, int64_t rank, unsigned long long* h
   memcpy(&fv, &prefix, sizeof(fv));
   *out = fv;
   return 0;
-}
-
-int sy_gpu_mask_bits(const float* v, const int64_t* dims, float thr, unsigned long long* bits,
-                     void* stream) {
-  const int64_t rows = dims[1] * dims[2] * dims[3], W = (dims[0] + 63) / 64;
-  hipLaunchKernelGGL(mask_bits_kernel, dim3(nblk(rows * W)), dim3(256), 0, (hipStream_t)stream, v,
-                     dims[0], rows, W, thr, bits);
-  return (int)hipGetLastError();
-}
-
-// Cube dilation of radius r within each timestep; tmp has the size of bits.
-int sy_gpu_dilate(unsigned long long* bits, unsigned long long* tmp, const int64_t* dims, int r,
-                  void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t Sy = dims[1], Sz = dims[2], T = dims[3], W = (dims[0] + 63) / 64;
-  const int64_t rows = Sy * Sz * T, nw = rows * W;
-  hipLaunchKernelGGL(dilate_x_kernel, dim3(nblk(nw)), dim3(256), 0, st, bits, tmp, rows, W,
-                     dims[0], r);
-  hipLaunchKernelGGL(dilate_axis_kernel, dim3(nblk(nw)), dim3(256), 0, st, tmp, bits, Sz * T, Sy,
-                     W, r);
-  hipLaunchKernelGGL(dilate_axis_kernel, dim3(nblk(nw)), dim3(256), 0, st, bits, tmp, T, Sz,
-                     Sy * W, r);
-  hipMemcpyAsync(bits, tmp, sizeof(unsigned long long) * nw, hipMemcpyDeviceToDevice, st);
-  return (int)hipGetLastError();
-}
-
-int sy_gpu_popcounts(const unsigned long long* bits, int64_t nw, long long* cnt, void* stream) {
-  hipLaunchKernelGGL(popc_kernel, dim3(nblk(nw)), dim3(256), 0, (hipStream_t)stream, bits, nw, cnt);
-  return (int)hipGetLastError();
-}
-
-int sy_gpu_emit(const unsigned long long* bits, const int64_t* dims, const long long* excl,
-                unsigned long long* ids, void* stream) {
-  const int64_t W = (dims[0] + 63) / 64, nw = dims[1] * dims[2] * dims[3] * W;
-  hipLaunchKernelGGL(emit_kernel, dim3(nblk(nw)), dim3(256), 0, (hipStream_t)stream, bits, nw, W,
-                     dims[0], excl, ids);
-  return (int)hipGetLastError();
 }
 
 }  // extern "C"

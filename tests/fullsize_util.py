@@ -1,0 +1,114 @@
+"""Sampled oracle checks of the fused kernels at production shapes (shared by
+the full-size GPU tests): levels too large for the oracle to enumerate are
+checked at the corners of a few picked samples of a full batch."""
+import numpy as np
+import torch
+
+import oracle as O
+from paper_2507_03836_amd import synth
+
+
+def _entry(res, v):
+    """Directory entry of vertex v = (x, y, z, t): ((t*Rz + z)*Wv + x//64)*Ry + y."""
+    Rx, Ry, Rz, Rt = res
+    Wv = (Rx + 63) // 64
+    return ((v[3] * Rz + v[2]) * Wv + v[0] // 64) * Ry + v[1]
+
+
+def _h(lin):
+    return np.sin(0.6180339887 * np.asarray(lin, np.float64) + 0.25) * 0.5
+
+
+def sampled_fused_check(fl, gen, res, idx, dir_t, dims, width, B, seed, n_pick=48):
+    """Full batch of B coreset draws through fhash_fused_fwd and fhash_fused_bwd
+    (the launch shape the benchmark times).  Every active vertex touched by the
+    picked samples holds h(vertex id) (placed by the test through the
+    directory), so the oracle computes the picked outputs from vertex
+    coordinates alone; dy is nonzero only at the picked samples, so the table
+    gradient is nonzero only at their corner rows, where it must equal the
+    oracle's sum over the picked samples, and the decoder gradient equals the
+    oracle's.  Tolerance |gpu - oracle| <= 1e-5 * mag + 1e-9."""
+    L = len(res)
+    F = 2
+    params = synth.mlp_init(width, seed=9)
+    pos = torch.empty(B, 4, device="cuda")
+    tgt = torch.empty(B, device="cuda")
+    fl.fhash_sample(seed, 7, B, gen["coreset"], gen["M"], dims, gen["field"], pos, tgt)
+    pick = np.sort(np.random.default_rng(3).choice(B, n_pick, replace=False))
+    pick_d = torch.from_numpy(pick).cuda()
+    pos_np = pos[pick_d].cpu().numpy()
+    dense = O.Grid(np.array(res), F, None)          # slots = vertex linear ids
+    lin, w = O.corners(dense, pos_np)               # [n_pick][L][16]
+    bits = gen["bits"].cpu().numpy().view(np.uint64)
+    rows = int(idx.slot_offset[L])
+    enc_ref = np.zeros((n_pick, L * F))
+    enc_mag = np.zeros((n_pick, L * F))
+    corner_slot = np.full((n_pick, L, 16), -1, np.int64)
+    slot_val = {}
+    for l, r in enumerate(res):
+        Rx, Ry, Rz, Rt = r
+        lo, hi = int(idx.dir_offset[l]), int(idx.dir_offset[l + 1])
+        dl = dir_t[lo:hi].view(torch.int64)
+        for s in range(n_pick):
+            for c in range(16):
+                v_lin = int(lin[s, l, c] - dense.slot_offset[l])
+                v = [v_lin % Rx, (v_lin // Rx) % Ry, (v_lin // (Rx * Ry)) % Rz,
+                     v_lin // (Rx * Ry * Rz)]
+                if not O.vertex_active_bits(r, bits, dims, v):
+                    continue
+                hv = float(_h(v_lin + 1000003 * l))
+                enc_ref[s, 2 * l] += w[s, l, c] * hv
+                enc_ref[s, 2 * l + 1] += w[s, l, c] * (0.5 - hv)
+                enc_mag[s, 2 * l] += w[s, l, c] * abs(hv)
+                enc_mag[s, 2 * l + 1] += w[s, l, c] * abs(0.5 - hv)
+                # the test (not the oracle) places h at the vertex's slot
+                ent = dl[_entry(r, v)].cpu().numpy().view(np.uint64)
+                below = int(ent[0]) & ((1 << (v[0] % 64)) - 1)
+                slot = int(idx.slot_offset[l]) + int(ent[1]) + bin(below).count("1")
+                corner_slot[s, l, c] = slot
+                slot_val[slot] = (hv, 0.5 - hv)
+    sl = torch.tensor(list(slot_val.keys()), device="cuda")
+    table = torch.zeros(rows, F, device="cuda")
+    table[sl] = torch.tensor(list(slot_val.values()), dtype=torch.float32, device="cuda")
+    prm = torch.from_numpy(params).cuda()
+    mlp = fl.mlp_desc(width)
+    y = torch.empty(B, device="cuda")
+    fl.fhash_fused_fwd(idx, mlp, pos, B, table.view(-1), prm, y)
+    y_ref, acts, ymag = O.mlp_fwd(width, params.astype(np.float64), enc_ref, x_mag=enc_mag)
+    got = y[pick_d].cpu().numpy().astype(np.float64)
+    err = np.abs(got - y_ref[:, 0])
+    assert (err <= 1e-5 * ymag[:, 0] + 1e-9).all(), ("forward", float(err.max()))
+    # backward: dy only at the picked samples
+    dy_np = np.random.default_rng(5).normal(size=n_pick).astype(np.float32)
+    dy = torch.zeros(B, device="cuda")
+    dy[pick_d] = torch.from_numpy(dy_np).cuda()
+    d_table = torch.zeros(rows, F, device="cuda")
+    d_par = torch.zeros(len(params), device="cuda")
+    fl.fhash_fused_bwd(idx, mlp, pos, B, table.view(-1), prm, dy, d_table, d_par)
+    dp_ref, denc, dpm, dencm = O.mlp_bwd(width, params.astype(np.float64), acts,
+                                         dy_np.astype(np.float64).reshape(-1, 1), n_pick,
+                                         x_mag=enc_mag)
+    dp = d_par.cpu().numpy().astype(np.float64)
+    assert (np.abs(dp - dp_ref) <= 1e-5 * dpm + 1e-9).all(), ("d_params",
+                                                              float(np.abs(dp - dp_ref).max()))
+    ref, mag = {}, {}
+    for s in range(n_pick):
+        for l in range(L):
+            for c in range(16):
+                slot = int(corner_slot[s, l, c])
+                if slot < 0:
+                    continue
+                a = ref.setdefault(slot, np.zeros(F))
+                m = mag.setdefault(slot, np.zeros(F))
+                for k in range(F):
+                    a[k] += w[s, l, c] * denc[s, l * F + k]
+                    m[k] += w[s, l, c] * dencm[s, l * F + k]
+    keys = np.array(sorted(ref))
+    got = d_table[torch.from_numpy(keys).cuda()].cpu().numpy().astype(np.float64)
+    want = np.array([ref[k] for k in keys])
+    tol = 1e-5 * np.array([mag[k] for k in keys]) + 1e-9
+    assert (np.abs(got - want) <= tol).all(), ("d_table", float(np.abs(got - want).max()))
+    # nothing else was written
+    nz = torch.nonzero(d_table.abs().sum(1)).view(-1).cpu().numpy()
+    assert set(nz.tolist()) <= set(keys.tolist())
+    return dict(rows=rows, touched=len(keys))

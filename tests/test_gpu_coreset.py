@@ -11,6 +11,8 @@ import torch
 from oracle import coreset as OC
 from paper_2507_03836_amd import synth
 
+from workloads import coreset_ids, tiny_volume
+
 SHAPES = [(70, 5, 3, 2), (130, 9, 4, 3), (64, 4, 4, 2), (65, 3, 2, 2), (2, 2, 2, 2)]
 # rows of a multiple of 4 voxels take the float4 extraction pass: a partial
 # 256-voxel segment (300: words 4..7 of the second segment, only word 4 real),
@@ -143,7 +145,7 @@ def test_pipeline_reproduces_the_tiny_workload(fl):
     """Feature value > 0.1 dilated by one voxel: the tiny workload's mask and
     coreset, from the product calls alone."""
     print("[coreset] tiny pipeline", flush=True)
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     dims = (f.shape[3], f.shape[2], f.shape[1], f.shape[0])
     feat = fl.fhash_feature_mask(torch.from_numpy(f).cuda(), dims, fl.FEATURE_INTERVAL, 0.1,
                                  float("inf"))
@@ -159,33 +161,30 @@ def test_pipeline_reproduces_the_tiny_workload(fl):
 @pytest.mark.gpu
 def test_pipeline_at_production_shape(fl):
     """480 x 720 x 120 spatial, 4 timesteps (166 M voxels): gradient magnitude
-    above its 80th percentile, dilated by 2, through the product calls, equals
-    the generator's mask and coreset bit for bit; the occupancy grid holds the
-    same number of voxels; the FBB contains every frame box."""
+    above its 80th percentile, dilated by 2, through the product calls
+    (paper_2507_03836_amd.volume), against oracle/coreset.py on the same
+    attribute field: mask, coreset ids, frame boxes + FBB and occupancy grid
+    bit for bit."""
+    import time
+    from paper_2507_03836_amd import volume
     dims = (480, 720, 120, 4)
     print(f"[coreset] production pipeline {dims}", flush=True)
-    vol = synth.production_volume_gpu(dims, seed=5)
-    G = synth._G()
-    g = torch.empty_like(vol["field"])
-    dd = np.array(dims, np.int64)
-    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
-    assert G.sy_gpu_grad_mag(synth._p(dd), C.c_void_p(vol["field"].data_ptr()),
-                             C.c_void_p(g.data_ptr()), st) == 0
-    feat = fl.fhash_feature_mask(g, dims, fl.FEATURE_INTERVAL, vol["threshold"], float("inf"))
-    del g
-    d = fl.fhash_dilate_mask(feat, dims, 2)
-    assert torch.equal(d, vol["bits"].reshape(-1))
-    ids = fl.fhash_coreset(d, dims)
-    assert ids.numel() == vol["M"] and torch.equal(ids, vol["coreset"])
+    gen = synth.production_field_gpu(dims, seed=5, keep_field=False)
+    attr, thr = gen.pop("grad"), gen["threshold"]
+    sel = volume.select_coreset(attr, dims, thr, radius=synth.PRODUCTION_DILATION)
+    d = sel["bits"].reshape(-1)
     occ = fl.fhash_occupancy_grid(d, dims)
-    pop = torch.zeros((), dtype=torch.int64, device="cuda")
-    for sh in range(64):
-        pop += ((occ >> sh) & 1).sum()
-    assert int(pop) == vol["M"]
-    box = fl.fhash_feature_boxes(d, dims).cpu().numpy()
-    fbb = box[-1]
-    assert (box[:-1, :3] >= fbb[:3]).all() and (box[:-1, 3:] <= fbb[3:]).all()
-    assert list(fbb[:3]) == list(box[:-1, :3].min(0)) and list(fbb[3:]) == list(box[:-1, 3:].max(0))
+    box = fl.fhash_feature_boxes(d, dims)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    g = attr.cpu().numpy()
+    del attr
+    m = OC.dilate(OC.feature_interval(g, thr, np.inf), synth.PRODUCTION_DILATION)
+    print(f"[coreset] oracle mask in {time.time() - t0:.1f} s", flush=True)
+    assert np.array_equal(_words(d), OC.pack_rows(m).ravel())
+    assert np.array_equal(_words(sel["coreset"]), OC.coreset_ids(m))
+    assert np.array_equal(box.cpu().numpy().astype(np.int64), OC.feature_boxes(m))
+    assert np.array_equal(_words(occ), OC.occupancy_grid(m).ravel())
 
 
 def test_coreset_calls_reject_bad_arguments():

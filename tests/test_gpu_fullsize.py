@@ -10,7 +10,10 @@ the oracle computes one by one.
   (closed-box cells, corner rule) says so;
 - the fused forward over a full 2^18 batch reproduces, for sampled samples, the
   oracle's value computed from vertex coordinates alone: every touched active
-  vertex's row holds h(vertex id), so a wrong slot would read a wrong h.
+  vertex's row holds h(vertex id), so a wrong slot would read a wrong h; the
+  fused backward of the same launch, with dy nonzero only at the sampled
+  samples, writes exactly the oracle's table gradient at their corner rows
+  and the oracle's decoder gradient.
 """
 import numpy as np
 import pytest
@@ -40,9 +43,10 @@ def prod():
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd import volume
     from paper_2507_03836_amd.model import geometric_resolutions
     fl.lib()
-    gen = synth.production_volume_gpu(DIMS, seed=1002)
+    gen = volume.production_volume(DIMS, seed=1002)
     res = geometric_resolutions(16, 16, 512, 4, 100, DIMS)
     grid = fl.grid_desc(res, 2)
     idx, counts, dir_t, ws = fl.fhash_build_index(grid, gen["bits"], DIMS)
@@ -96,58 +100,7 @@ def test_sampled_vertex_activity_matches_oracle(prod):
             assert _vertex_bit(dl, r, v) == int(exp), (l, v)
 
 
-def _h(lin):
-    return np.sin(0.6180339887 * lin.astype(np.float64) + 0.25) * 0.5
-
-
-def test_fused_forward_sampled_against_oracle(prod):
-    fl, gen, res, idx, dir_t = prod["fl"], prod["gen"], prod["res"], prod["idx"], prod["dir"]
-    B = 1 << 18
-    width = [32, 64, 64, 1]
-    params = synth.mlp_init(width, seed=9)
-    pos = torch.empty(B, 4, device="cuda")
-    tgt = torch.empty(B, device="cuda")
-    fl.fhash_sample(2002, 7, B, gen["coreset"], gen["M"], DIMS, gen["field"], pos, tgt)
-    pick = np.random.default_rng(3).choice(B, 48, replace=False)
-    pos_np = pos[torch.from_numpy(pick).cuda()].cpu().numpy()
-    dense = O.Grid(np.array(res), 2, None)          # slots = vertex linear ids
-    lin, w = O.corners(dense, pos_np)               # [48][L][16]
-    bits = gen["bits"].cpu().numpy().view(np.uint64)
-    rows = int(idx.slot_offset[len(res)])
-    table = torch.zeros(rows, 2, device="cuda")
-    enc_ref = np.zeros((48, 32))
-    enc_mag = np.zeros((48, 32))
-    slot_list, val_list = [], []
-    for l, r in enumerate(res):
-        Rx, Ry, Rz, Rt = r
-        lo, hi = int(idx.dir_offset[l]), int(idx.dir_offset[l + 1])
-        dl = dir_t[lo:hi].cpu().numpy().view(np.uint64)
-        Wv = (Rx + 63) // 64
-        for s in range(48):
-            for c in range(16):
-                v_lin = int(lin[s, l, c] - dense.slot_offset[l])
-                v = [v_lin % Rx, (v_lin // Rx) % Ry, (v_lin // (Rx * Ry)) % Rz,
-                     v_lin // (Rx * Ry * Rz)]
-                act = O.vertex_active_bits(r, bits, DIMS, v)
-                hv = _h(np.array([v_lin + 1000003 * l]))[0]
-                if act:
-                    enc_ref[s, 2 * l] += w[s, l, c] * hv
-                    enc_ref[s, 2 * l + 1] += w[s, l, c] * (0.5 - hv)
-                    enc_mag[s, 2 * l] += w[s, l, c] * abs(hv)
-                    enc_mag[s, 2 * l + 1] += w[s, l, c] * abs(0.5 - hv)
-                    # the test (not the oracle) places h at the vertex's slot
-                    ent = dl[_entry(r, v)]
-                    below = int(ent[0]) & ((1 << (v[0] % 64)) - 1)
-                    slot = int(idx.slot_offset[l]) + int(ent[1]) + bin(below).count("1")
-                    slot_list.append(slot)
-                    val_list.append((hv, 0.5 - hv))
-    sl = torch.tensor(slot_list, device="cuda")
-    table[sl] = torch.tensor(val_list, dtype=torch.float32, device="cuda")
-    y = torch.empty(B, device="cuda")
-    fl.fhash_fused_fwd(idx, fl.mlp_desc(width), pos, B, table.view(-1),
-                       torch.from_numpy(params).cuda(), y)
-    y_ref, _, ymag = O.mlp_fwd(width, params.astype(np.float64), enc_ref,
-                               x_mag=enc_mag)
-    got = y[torch.from_numpy(pick).cuda()].cpu().numpy().astype(np.float64)
-    err = np.abs(got - y_ref[:, 0])
-    assert (err <= 1e-5 * ymag[:, 0] + 1e-9).all(), float(err.max())
+def test_fused_forward_backward_sampled_against_oracle(prod):
+    from fullsize_util import sampled_fused_check
+    sampled_fused_check(prod["fl"], prod["gen"], prod["res"], prod["idx"], prod["dir"], DIMS,
+                        width=[32, 64, 64, 1], B=1 << 18, seed=2002)

@@ -11,6 +11,8 @@ import torch
 import oracle as O
 from paper_2507_03836_amd import synth
 
+from workloads import coreset_ids, tiny_volume
+
 pytestmark = pytest.mark.gpu
 
 TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
@@ -52,7 +54,7 @@ def test_hash_index_rows(fl):
 
 @pytest.mark.parametrize("F", [2, 4])
 def test_encode_and_fused_train_against_oracle(fl, F):
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     idx, _ = fl.fhash_hash_index(fl.grid_desc(TINY_RES, F), BITS)
     g = O.Grid(np.array(TINY_RES), F, hash_bits=BITS)
     rng = np.random.default_rng(30 + F)
@@ -89,7 +91,7 @@ def test_encode_and_fused_train_against_oracle(fl, F):
 
 def test_lazy_adam_on_hashed_table_equals_dense(fl):
     from paper_2507_03836_amd.model import FHashConfig, FHashModel
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     T, Sz, Sy, Sx = mask.shape
     dims = [Sx, Sy, Sz, T]
     cfg = FHashConfig(res=TINY_RES, n_features=2, hidden=32, n_hidden=2)

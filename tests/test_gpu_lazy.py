@@ -19,6 +19,8 @@ import torch
 
 from paper_2507_03836_amd import synth
 
+from workloads import coreset_ids, tiny_volume
+
 pytestmark = pytest.mark.gpu
 
 TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
@@ -36,7 +38,7 @@ def fl():
 def _pair(precision, begin_level, **kw):
     from paper_2507_03836_amd import _lib as fl
     from paper_2507_03836_amd.model import FHashConfig, FHashModel
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     T, Sz, Sy, Sx = mask.shape
     dims = [Sx, Sy, Sz, T]
     cfg = FHashConfig(res=TINY_RES, n_features=2, hidden=32, n_hidden=2)

@@ -17,6 +17,8 @@ import torch
 import oracle as O
 from paper_2507_03836_amd import synth
 
+from workloads import coreset_ids, tiny_volume
+
 pytestmark = pytest.mark.gpu
 
 TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
@@ -53,7 +55,7 @@ def _close(got, ref, mag, what, scale=1.0):
 
 
 def test_mixed_step_matches_oracle_on_fp16_values(fl):
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     g = O.Grid(np.array(TINY_RES), 2, mask)
     rng = np.random.default_rng(21)
     table0 = rng.uniform(-0.5, 0.5, (g.total_slots, 2)).astype(np.float32)
@@ -93,7 +95,7 @@ def test_mixed_step_matches_oracle_on_fp16_values(fl):
 
 
 def test_overflow_skips_step_and_halves_scale(fl):
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     g = O.Grid(np.array(TINY_RES), 2, mask)
     table0 = synth.table_init(g.total_slots, 2)
     mlp0 = synth.mlp_init([8, 32, 32, 1], seed=23)
@@ -128,7 +130,7 @@ def test_overflow_skips_step_and_halves_scale(fl):
 
 
 def test_mixed_error_against_fp64_probe(fl):
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     g = O.Grid(np.array(TINY_RES), 2, mask)
     rng = np.random.default_rng(31)
     table0 = rng.uniform(-1, 1, (g.total_slots, 2)).astype(np.float32)
@@ -171,7 +173,7 @@ def test_fp16_decoder_forward_within_rounding_bound(fl, width):
     oracle: the error stays inside the bound built layer by layer from binary16
     rounding of every weight and hidden-layer input (relative 2^-11, absolute
     2^-25 below the normal range), FP32 accumulation and the 1-Lipschitz ReLU."""
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     g = O.Grid(np.array(TINY_RES), 2, mask)
     rng = np.random.default_rng(41)
     table = rng.uniform(-1, 1, (g.total_slots, 2)).astype(np.float32)

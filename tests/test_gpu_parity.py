@@ -12,6 +12,8 @@ import torch
 import oracle as O
 from paper_2507_03836_amd import synth
 
+from workloads import coreset_ids, tiny_volume
+
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-5
@@ -48,7 +50,7 @@ TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
 
 @pytest.fixture(scope="module")
 def tiny():
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     return f, mask
 
 
@@ -409,7 +411,7 @@ def test_check_finite_and_cast(fl):
 @pytest.mark.parametrize("use_coreset", [True, False])
 def test_sampler_bit_exact(fl, tiny, use_coreset):
     f, mask = tiny
-    cs = synth.coreset(mask) if use_coreset else None
+    cs = coreset_ids(mask) if use_coreset else None
     n = 4096 + 3
     pos_r, tgt_r = O.sample_batch(2001, 17, n, f, cs)
     fd = torch.from_numpy(f).cuda()
@@ -525,7 +527,7 @@ def test_fused_train_sorted_segmented_scatter(fl, tiny):
     table = rng.uniform(-1, 1, size=(g.total_slots, F)).astype(np.float32)
     params = _mlp_params(width, 22)
     n = 4096 + 9
-    pos0, tgt0 = O.sample_batch(5, 3, n, f, synth.coreset(mask))
+    pos0, tgt0 = O.sample_batch(5, 3, n, f, coreset_ids(mask))
     pd, td = torch.from_numpy(pos0).cuda(), torch.from_numpy(tgt0).cuda()
     fl.fhash_sort_samples(pd, td, n)
     pos, tgt = pd.cpu().numpy(), td.cpu().numpy()

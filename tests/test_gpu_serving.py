@@ -10,6 +10,8 @@ import torch
 import oracle as O
 from paper_2507_03836_amd import synth
 
+from workloads import coreset_ids, render_bound, tiny_volume
+
 pytestmark = pytest.mark.gpu
 
 TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
@@ -22,7 +24,7 @@ def server_models():
     from paper_2507_03836_amd import _lib as fl
     from paper_2507_03836_amd.serving import GpuExecutor, ResidentModel
     fl.lib()
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     T, Sz, Sy, Sx = mask.shape
     dims = [Sx, Sy, Sz, T]
     bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
@@ -107,10 +109,14 @@ def test_served_render_matches_oracle(server_models):
     view = synth.orbit_view(dims, 0.9, 0.35, W, H)
     r = Request(model="m0", kind="render", view=view, t=t, W=W, H=H)
     sch.run([r], realtime=False)
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     g = O.Grid(np.array(TINY_RES), 2, mask)
-    ref, amb, _ = O.render(g, m.table.cpu().numpy().astype(np.float64), [8, 32, 32, 1],
-                           m.params.cpu().numpy().astype(np.float64), mask, view, t,
-                           synth.transfer_function(), W, H)
-    err = np.abs(r.result.cpu().numpy() - ref)[~amb]
-    assert err.max() < 2e-4, float(err.max())
+    tf = synth.transfer_function()
+    ref, amb, _, pix = O.render(g, m.table.cpu().numpy().astype(np.float64), [8, 32, 32, 1],
+                                m.params.cpu().numpy().astype(np.float64), mask, view, t, tf, W,
+                                H, pixel_stats=True)
+    bound, amb = render_bound(pix, tf)
+    err = np.abs(r.result.cpu().numpy() - ref)
+    ok = ~amb
+    assert (err[ok] <= np.broadcast_to(bound, err.shape)[ok]).all(), \
+        float((err - bound)[ok].max())

@@ -14,6 +14,8 @@ import torch
 import oracle as O
 from paper_2507_03836_amd import synth
 
+from workloads import coreset_ids, tiny_volume
+
 pytestmark = pytest.mark.gpu
 
 TINY_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5], [32, 32, 32, 8]]
@@ -25,7 +27,7 @@ def env():
         pytest.skip("no HIP device")
     from paper_2507_03836_amd import _lib as fl
     fl.lib()
-    f, mask = synth.tiny_volume()
+    f, mask = tiny_volume()
     T, Sz, Sy, Sx = mask.shape
     return fl, f, mask, [Sx, Sy, Sz, T]
 
@@ -43,7 +45,7 @@ def test_autograd_function_vs_oracle_and_fd(env):
     table0 = rng.uniform(-0.5, 0.5, size=(g.total_slots, 2)).astype(np.float32)
     params0 = synth.mlp_init(width)
     n = 1500
-    pos_np, tgt_np = O.sample_batch(77, 1, n, f, synth.coreset(mask))
+    pos_np, tgt_np = O.sample_batch(77, 1, n, f, coreset_ids(mask))
     pos = torch.from_numpy(pos_np).cuda()
     tgt = torch.from_numpy(tgt_np).cuda()
     table = torch.from_numpy(table0).cuda().requires_grad_(True)
@@ -85,7 +87,7 @@ def _train(fl, f, mask, dims, train_mlp, steps=400, seed=5):
     cfg = FHashConfig(res=TINY_RES, n_features=2, hidden=32, n_hidden=2)
     bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
     model = FHashModel(cfg, bits, dims, init_seed=seed)
-    cs = synth.coreset(mask)
+    cs = coreset_ids(mask)
     csd = torch.from_numpy(cs.view(np.int64)).cuda()
     fd = torch.from_numpy(f).cuda()
     n = 4096
