@@ -285,7 +285,7 @@ def encode_bwd(grid: Grid, pos, d_enc):
     de = _c(d_enc, np.float64)
     n = pos.shape[0]
     dt = np.zeros((grid.total_slots, grid.F), np.float64)
-    mag = np.zeros_like(dt)
+    mag = np.zeros((grid.total_slots, grid.F), np.float64)  # zero pages, committed where written
     lib().or_encode_bwd(grid.ref(), _p(pos), n, _p(de), _p(dt), _p(mag))
     return dt, mag
 
