@@ -1,17 +1,34 @@
 #!/usr/bin/env python3
-"""Training-throughput benchmark of the F-Hash hot path on one MI355X.
+"""Benchmarks of the F-Hash hot path on one MI355X.
 
-Workload (the production-shape training configuration): a seeded synthetic
-480 x 720 x 120 x 100 float32 volume (64 advected Gaussian blobs + 3-octave
-value-noise turbulence, min-max normalised), feature mask |grad| > 80th
-percentile dilated by 2, coreset = masked voxels; 16 levels (spatial 16..512,
-temporal 4..100, geometric, clamped to the volume), 2 features per level,
-decoder 32 -> 64 -> 64 -> 1, batch 2^18 coreset draws per step.
+Default (the headline metric: training samples/s fwd+bwd, FP32 vs mixed
+precision at equal PSNR, and render p50/p99): the differentiated
+mixed-precision training workload.  A seeded synthetic 432^3 x 60 float32
+volume (64 advected Gaussian blobs + 3-octave value-noise turbulence, min-max
+normalised), feature = gradient magnitude above its 80th percentile, dilated
+by 2, coreset = feature voxels (all through the coreset-selection calls);
+16 levels (spatial 16..512 clamped to 432, temporal 4..60), 2 features per
+level, decoder 32-64-64-64-1, batch 2^20 coreset draws per step, Adam lr 0.01.
 
-One step = sampler (Philox draw from the coreset, positions, labels) ->
-fused encoding + decoder forward, MSE, backward (scatter-add into the tables,
-decoder gradients) -> dense Adam over every parameter.  Inputs are resident in
-HBM before timing starts.  Prints ONE JSON line on stdout.
+* FP32 path: FP32 tables and FP32-MFMA decoder; mixed path: FP16 table reads
+  (shadow written by Adam), BF16-MFMA decoder with FP32 accumulation, FP32
+  master tables / moments, dynamic loss scaling.  Each path: W warm-up steps,
+  K timed steps (HIP events per phase on the launch stream), then training on
+  to the common probe-PSNR target (40 dB on 2^22 coreset draws), wall time from
+  the first step.
+* Render serving with the mixed model (FP16 tables, BF16 decoder): requests of
+  side 256/512/1024, fractional t, orbit cameras, ds = 1/2 voxel, ARM max 64,
+  alpha stop 0.99; saturation, then Poisson arrivals at 0.25/0.5/0.9 x
+  saturation, continuous batching against one request at a time.
+* roofline: the dominant kernel of the reported path's step (the fused
+  training kernel), with the algorithmic bytes per sample and the compulsory
+  128-byte lines of the timed batch (directory, table and gradient lines its
+  corners touch, counted with fhash_corner_rows).
+
+Other modes: --workload train (the 480 x 720 x 120 x 100 training
+configuration and its variants), --serve, --serve-multi, --key-frames,
+--coreset.  Inputs are resident in HBM before timing starts.  Prints ONE JSON
+line on stdout.
 """
 from __future__ import annotations
 
@@ -63,8 +80,11 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["headline", "train"], default="headline",
+                    help="headline: 432^3 x 60 FP32 vs mixed + render serving; train: the "
+                         "single-path training benchmark selected by the options below")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=1 << 18)
     ap.add_argument("--shape", type=str, default="480,720,120,100")
     ap.add_argument("--levels", type=int, default=16)
@@ -94,12 +114,12 @@ def parse():
     ap.add_argument("--psnr-target", type=float, default=0.0,
                     help="after the timed steps, keep training until the probe PSNR reaches this")
     ap.add_argument("--max-steps", type=int, default=2000)
-    ap.add_argument("--eval-every", type=int, default=10)
+    ap.add_argument("--eval-every", type=int, default=5)
     ap.add_argument("--serve", action="store_true",
                     help="render-serving benchmark instead of training (p50/p99 at 3 rates)")
     ap.add_argument("--serve-shape", type=str, default="432,432,432,60")
     ap.add_argument("--serve-train-steps", type=int, default=300)
-    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-sizes", type=str, default="256,512,1024")
     ap.add_argument("--serve-rates", type=str, default="0.25,0.5,0.9",
                     help="Poisson rates as fractions of the saturation request rate")
@@ -655,6 +675,371 @@ def coreset_bench(args):
         "cpu_baseline": cpu}))
 
 
+# ------------------------------------------------------------------ headline
+HEADLINE_DIMS = [432, 432, 432, 60]
+# HBM bytes of one fused training launch (mixed path, 432^3 x 60, batch 2^20)
+# from rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) passes scaled by a
+# plain streaming copy of known size; valid only while the kernel sources
+# hashed in _fused_src_md5() are unchanged.
+FUSED_TRAFFIC = {"bytes": None, "source_md5": None}
+
+
+def _fused_src_md5():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2507_03836_amd", "csrc")
+    names = ("fused_impl.h", "encode_dev.h", "mlp_dev.h", "mlp_train_dev.h", "common.h",
+             "fused_train.hip", "fused_train16.hip")
+    return hashlib.md5(b"".join(open(os.path.join(csrc, n), "rb").read()
+                                for n in names)).hexdigest()
+
+
+def _cpu_worker(task):
+    """One process of the all-core CPU baseline: the FP64 oracle, as it
+    stands, on its share of the sample draws (fwd+bwd) or on an Adam chunk."""
+    import numpy as np
+
+    import oracle as O
+    kind = task[0]
+    if kind == "fb":
+        _, res, F, width, params, pos, tgt = task
+        g = O.Grid(np.array(res), F, None)
+        table = np.zeros((g.total_slots, F))  # zero pages, committed only where written
+        t0 = time.perf_counter()
+        enc, _ = O.encode_fwd(g, pos, table)
+        y, acts, _ = O.mlp_fwd(width, params, enc)
+        L, dy = O.mse(y[:, 0], tgt.astype(np.float64))
+        dp, denc, _, _ = O.mlp_bwd(width, params, acts, dy.reshape(-1, 1), pos.shape[0])
+        dt, _ = O.encode_bwd(g, pos, denc)
+        return time.perf_counter() - t0
+    _, n = task
+    rng = np.random.default_rng(n)
+    p, gr, m, v = np.zeros(n), rng.normal(size=n), np.zeros(n), np.zeros(n)
+    t0 = time.perf_counter()
+    O.adam(p, gr, m, v, 0.01, 0.9, 0.999, 1e-8, 1)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(model, gen, dims, batch, n_cpu, seed):
+    """The FP64 oracle, as it stands, on every host core the box gives this
+    job (one process per core, at most 16): n_cpu coreset draws split over the
+    processes through the oracle's encoding, decoder, MSE and backward with the
+    same level structure (dense-box index, same 16 x 16 corner work per
+    sample), and the oracle's Adam on one 2^21-parameter chunk per process.
+    Scaled to one full step: wall time of the parallel fwd+bwd x batch/n_cpu +
+    wall time of the parallel Adam x parameters / (processes x chunk)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle as O
+    nproc = os.cpu_count() or 1
+    workers = max(1, min(16, nproc))
+    ids = O.sample_ids(seed, 1, n_cpu, gen["M"])
+    ids_t = torch.from_numpy(ids.view(np.int64)).cuda()
+    lin = gen["coreset"][ids_t].cpu().numpy().view(np.uint64)
+    tgt = gen["field"].view(-1)[torch.from_numpy(lin.view(np.int64)).cuda()].cpu().numpy()
+    pos = O.voxel_positions(lin, dims)
+    cfg = model.cfg
+    params = model.mlp_params.double().cpu().numpy()
+    chunks = np.array_split(np.arange(n_cpu), workers)
+    fb = [("fb", cfg.res, cfg.n_features, cfg.width, params, pos[c], tgt[c]) for c in chunks]
+    chunk = 1 << 21
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ctx = mp.get_context("spawn")
+    log(f"[cpu] oracle on {workers} processes ({nproc} host CPUs, {cpu_model})")
+    with ctx.Pool(workers) as pool:
+        pool.map(_cpu_worker, [("adam", 1024)] * workers)  # start-up outside the timing
+        t0 = time.perf_counter()
+        pool.map(_cpu_worker, fb)
+        t_fb = time.perf_counter() - t0
+        log(f"[cpu] fwd+bwd of {n_cpu} draws: {t_fb:.2f} s")
+        t0 = time.perf_counter()
+        pool.map(_cpu_worker, [("adam", chunk)] * workers)
+        t_adam = time.perf_counter() - t0
+        log(f"[cpu] Adam on {workers} x {chunk} parameters: {t_adam:.3f} s")
+    t_step = t_fb * batch / n_cpu + t_adam * model.n_params / (workers * chunk)
+    return {"value": batch / t_step, "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "nproc": nproc, "cpu_model": cpu_model,
+            "sample": (f"{n_cpu} coreset draws fwd+bwd over {workers} processes ({t_fb:.2f} s "
+                       f"wall) scaled to {batch}, + Adam on {workers} x {chunk} params "
+                       f"({t_adam:.3f} s wall) scaled to {model.n_params}; dense-box index, "
+                       "FP64, one process per core")}
+
+
+def _train_timed(model, gen, dims, B, steps, warmup, sampler_seed, pos, tgt):
+    """warmup + steps training steps; per-phase HIP events on the launch stream
+    over the timed steps; the timed region ends with the deferred update
+    flushed.  Returns the breakdown and the step closure."""
+    import numpy as np
+
+    from paper_2507_03836_amd import _lib as fl
+    stream = torch.cuda.current_stream()
+    coreset, M, field = gen["coreset"], gen["M"], gen["field"]
+
+    def step(k, ev=None):
+        fl.fhash_sample(sampler_seed, k, B, coreset, M, dims, field, pos, tgt)
+        if ev is not None:
+            ev[0].record(stream)
+        model.prepare(pos, fl.LAZY_MARK)
+        if ev is not None:
+            ev[1].record(stream)
+        model.prepare(pos, fl.LAZY_CATCH_UP)
+        if ev is not None:
+            ev[2].record(stream)
+        model.fwd_bwd(pos, tgt, prepared=True)
+        if ev is not None:
+            ev[3].record(stream)
+        model.optimizer_step()
+        if ev is not None:
+            ev[4].record(stream)
+
+    t_first = time.perf_counter()
+    for k in range(warmup):
+        step(k + 1)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    fev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    st0 = fl.fhash_lazy_stats(model.lazy)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(warmup + k + 1, evs[k])
+    st1 = fl.fhash_lazy_stats(model.lazy)
+    fev[0].record(stream)
+    model.flush()
+    fev[1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mean = lambda i, j: float(np.mean([e[i].elapsed_time(e[j]) for e in evs]))
+    out = {"ms_per_step": wall * 1e3 / steps, "samples_per_s": B / (wall / steps),
+           "breakdown_ms": {"lazy_mark": mean(0, 1), "lazy_catch_up": mean(1, 2),
+                            "fused_fwd_bwd": mean(2, 3), "adam_dense_part": mean(3, 4),
+                            "final_flush_per_step": fev[0].elapsed_time(fev[1]) / steps},
+           "lazy_per_step": {k: (st1[k] - st0[k]) / steps for k in st1},
+           "mean_loss": model.loss_sum.item() / (B * (warmup + steps))}
+    out["breakdown_ms"]["sampler_and_other"] = out["ms_per_step"] - sum(
+        out["breakdown_ms"].values())
+    return out, step, t_first
+
+
+def _to_psnr(model, step, k_done, t_first, ppos, ptgt, target, eval_every, max_steps):
+    from paper_2507_03836_amd.model import psnr_on
+    k, hist, reached = k_done, [], None
+    while True:
+        if (k - k_done) % eval_every == 0 or k >= max_steps:
+            ps = psnr_on(model, ppos, ptgt)
+            el = time.perf_counter() - t_first
+            hist.append((k, round(el, 3), round(ps, 3)))
+            log(f"[headline] step {k}: probe PSNR {ps:.3f} dB at {el:.2f} s")
+            if ps >= target:
+                reached = (k, el, ps)
+                break
+            if k >= max_steps:
+                break
+        k += 1
+        step(k)
+    return {"target_db": target, "reached": reached is not None,
+            "steps": reached[0] if reached else None,
+            "seconds": reached[1] if reached else None,
+            "final_psnr_db": hist[-1][2], "history": hist}
+
+
+def compulsory_lines(model, pos, line=128):
+    """Distinct `line`-byte lines of directory, table and table gradient that
+    the fused training kernel must move for this batch (the corners of every
+    sample at every level, fhash_corner_rows), in bytes: directory and table
+    lines are read once, gradient lines read and written once; plus 20 bytes
+    of sample I/O per sample."""
+    from paper_2507_03836_amd import _lib as fl
+    n = pos.shape[0]
+    F = model.cfg.n_features
+    tb = 2 if model.shadow is not None else 4
+    dir_lines, tab_lines, grad_lines = [], [], []
+    for s in range(0, n, 1 << 16):
+        e = min(n, s + (1 << 16))
+        d, sl = fl.fhash_corner_rows(model.index, pos[s:e], e - s)
+        d = d.view(-1)
+        d = d[d >= 0]
+        dir_lines.append(torch.unique(d * 16 // line))
+        sl = sl.view(-1)
+        sl = sl[sl >= 0]
+        tab_lines.append(torch.unique(sl * (F * tb) // line))
+        grad_lines.append(torch.unique(sl * (F * 4) // line))
+        del d, sl
+    u = lambda xs: int(torch.unique(torch.cat(xs)).numel())
+    nd, nt, ng = u(dir_lines), u(tab_lines), u(grad_lines)
+    return {"line_bytes": line, "directory_lines": nd, "table_lines": nt, "gradient_lines": ng,
+            "bytes": line * (nd + nt + 2 * ng) + 20 * n}
+
+
+def _serve_sub(model, gen, dims, args, n_req):
+    """Render p50/p99 of the trained mixed model (FP16 tables, its 16-bit
+    decoder) at saturation and three Poisson rates: continuous batching
+    (backfill) against one request at a time, same arrivals."""
+    import numpy as np
+
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd import synth
+    from paper_2507_03836_amd.serving import (GpuExecutor, Request, ResidentModel, Scheduler,
+                                              latency_stats, poisson_arrivals)
+    table16 = torch.empty(model.n_table, dtype=torch.float16, device="cuda")
+    fl.fhash_cast(model.table, table16)
+    tf = torch.from_numpy(synth.transfer_function()).cuda()
+    rm = ResidentModel(index=model.index, mlp=model.mlp, table=table16,
+                       params=model.mlp_params.clone(), mask_bits=gen["bits"], dims=dims, tf=tf,
+                       keep=(model._dir,))
+    C = 1 << 22
+    rng = np.random.default_rng(5004)
+    spec = []
+    for i in range(n_req):
+        S = int(rng.choice([256, 512, 1024]))
+        spec.append((S, synth.orbit_view(dims, float(rng.uniform(0, 2 * np.pi)),
+                                         float(rng.uniform(-np.pi / 3, np.pi / 3)), S, S),
+                     float(rng.uniform(0, dims[3] - 1))))
+
+    def reqs(arr):
+        return [Request(model="m", kind="render", view=v, t=t, W=S, H=S, arrival=float(a))
+                for (S, v, t), a in zip(spec, arr)]
+
+    def serve(arr, realtime, **kw):
+        ex = GpuExecutor(sample_budget=C)
+        ex.add_model("m", rm)
+        free, _ = torch.cuda.mem_get_info()
+        sch = Scheduler(ex, sample_budget=C, mem_budget=int(free * 0.8), **kw)
+        torch.cuda.synchronize()
+        return latency_stats(sch.run(reqs(arr), realtime=realtime))
+
+    serve([0.0] * 2, realtime=False)
+    sat = serve([0.0] * n_req, realtime=False)
+    sat_one = serve([0.0] * n_req, realtime=False, max_active=1)
+    rates = []
+    for frac in (0.25, 0.5, 0.9):
+        rate = frac * sat["requests_per_s"]
+        arr = poisson_arrivals(rate, n_req, seed=5004)
+        row = {"rate_frac": frac, "rate_per_s": rate,
+               "continuous_backfill": serve(arr, realtime=True),
+               "one_at_a_time": serve(arr, realtime=True, max_active=1)}
+        log(f"[headline] render {rate:.1f}/s: batched p50 "
+            f"{row['continuous_backfill']['p50_ms']:.1f} p99 "
+            f"{row['continuous_backfill']['p99_ms']:.1f} ms; one at a time p50 "
+            f"{row['one_at_a_time']['p50_ms']:.1f} p99 {row['one_at_a_time']['p99_ms']:.1f} ms")
+        rates.append(row)
+    return {"workload": "render requests of side 256/512/1024 (uniform), t ~ U[0, 59], orbit "
+                        "cameras, ds = 1/2 voxel, ARM max 64, alpha stop 0.99, FP16 tables, "
+                        f"{model.decoder} decoder", "requests_per_rate": n_req,
+            "sample_budget": C, "saturation": sat, "one_at_a_time_saturation": sat_one,
+            "rates": rates}
+
+
+def headline_bench(args):
+    import numpy as np
+
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd import volume
+    from paper_2507_03836_amd.model import FHashConfig, FHashModel, geometric_resolutions
+
+    fl.lib()
+    torch.cuda.set_device(0)
+    dims = HEADLINE_DIMS
+    B = 1 << 20
+    t0 = time.time()
+    gen = volume.production_volume(dims, seed=1003)
+    log(f"[headline] volume {dims} in {time.time() - t0:.1f} s; coreset {gen['M']} of "
+        f"{gen['N']} voxels")
+    res = geometric_resolutions(16, 16, 512, 4, dims[3], dims)
+    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3)
+    P = 1 << 22
+    ppos = torch.empty(P, 4, device="cuda")
+    ptgt = torch.empty(P, device="cuda")
+    fl.fhash_sample(4003, 1, P, gen["coreset"], gen["M"], dims, gen["field"], ppos, ptgt)
+    pos = torch.empty(B, 4, device="cuda")
+    tgt = torch.empty(B, device="cuda")
+    paths, keep = {}, None
+    for prec in ("fp32", "mixed"):
+        model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, precision=prec, lazy=True,
+                           max_steps=args.max_steps + args.warmup + args.steps + 8)
+        r, step, t_first = _train_timed(model, gen, dims, B, args.steps, args.warmup, 2003, pos,
+                                        tgt)
+        log(f"[headline] {prec}: {r['ms_per_step']:.2f} ms/step ({r['samples_per_s'] / 1e6:.1f}"
+            f" M samples/s): {r['breakdown_ms']}")
+        # the timed batch's compulsory lines (the batch of the last timed step)
+        fl.fhash_sample(2003, args.warmup + args.steps, B, gen["coreset"], gen["M"], dims,
+                        gen["field"], pos, tgt)
+        r["compulsory"] = compulsory_lines(model, pos)
+        r["time_to_psnr"] = _to_psnr(model, step, args.warmup + args.steps, t_first, ppos, ptgt,
+                                     args.psnr_target or 40.0, args.eval_every, args.max_steps)
+        r["params"] = model.n_params
+        r["decoder"] = model.decoder
+        r["table_reads"] = "f16" if model.shadow is not None else "f32"
+        if prec == "mixed":
+            r["loss_scale"] = model.loss_scale
+            r["skipped_steps"] = model.skipped
+        paths[prec] = r
+        model.flush()
+        if prec == "mixed":
+            keep = model
+        else:
+            cpu = None
+            if not args.no_cpu_baseline:
+                try:
+                    cpu = cpu_baseline_all_cores(model, gen, dims, B, args.cpu_samples, 2003)
+                except Exception as e:  # reported, never hidden
+                    cpu = {"error": repr(e)}
+            model.params = model.grads = model.m = model.v = model.lazy = None
+            del model
+            torch.cuda.empty_cache()
+    model = keep
+    model.grads = model.m = model.v = None
+    model.lazy = None
+    torch.cuda.empty_cache()
+    serve = _serve_sub(model, gen, dims, args, args.serve_requests)
+    mx, fp = paths["mixed"], paths["fp32"]
+    fused_ms = mx["breakdown_ms"]["fused_fwd_bwd"]
+    alg = 3092 * B  # FP16 gather 1024 + FP32 scatter read-modify-write 2048 + 20 B I/O
+    comp = mx["compulsory"]["bytes"]
+    same = FUSED_TRAFFIC["source_md5"] == _fused_src_md5()
+    roof = {"kernel": "fused_kernel<TRAIN, F=2, FP16 table, 32-64-64-64-1, BF16 decoder>",
+            "bound": "hbm", "achieved": alg / (fused_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": alg / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": FUSED_TRAFFIC["bytes"] if same else None,
+            "algorithmic_bytes": alg, "kernel_ms": fused_ms,
+            "compulsory_bytes": comp,
+            "compulsory_GB_s": comp / (fused_ms * 1e-3) / 1e9,
+            "compulsory_frac": comp / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "compulsory_detail": mx["compulsory"]}
+    ttp_m, ttp_f = mx["time_to_psnr"], fp["time_to_psnr"]
+    out = {
+        "metric": "train samples/s fwd+bwd (FP32 vs FP16/BF16) at equal PSNR; render p50/p99 ms",
+        "value": mx["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": mx["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 decoder MFMA, f16 table reads, f32 master/Adam/accumulation",
+        "data": "synthetic",
+        "config": {"workload": "F-Hash differentiated mixed-precision training, 432x432x432x60 "
+                               "synthetic volume, 16 levels x 2 features, MLP 32-64-64-64-1, "
+                               "batch 2^20 coreset draws, Adam with deferred large-level "
+                               "updates (equal to the dense update bit for bit)",
+                   "shape": dims, "levels": 16, "batch": B, "params": mx["params"],
+                   "coreset": gen["M"]},
+        "paths": {"mixed": mx, "fp32": fp},
+        "mixed_over_fp32_samples_per_s": mx["samples_per_s"] / fp["samples_per_s"],
+        "equal_psnr": {"target_db": ttp_m["target_db"],
+                       "mixed_s": ttp_m["seconds"], "fp32_s": ttp_f["seconds"],
+                       "mixed_steps": ttp_m["steps"], "fp32_steps": ttp_f["steps"]},
+        "render": serve,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -667,6 +1052,9 @@ def main():
 
     if args.serve_multi:
         return serve_multi_bench(args)
+    if (args.workload == "headline" and args.key_frames <= 1 and not args.serve and
+            not args.coreset):
+        return headline_bench(args)
     if args.key_frames > 1:
         return key_frame_bench(args)
     if args.serve:

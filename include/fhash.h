@@ -144,6 +144,18 @@ int fhash_hash_index(const fhash_grid_desc* grid, int32_t hash_bits, fhash_index
 int fhash_encode_fwd(const fhash_index* idx, const float* pos, int64_t n, const void* table,
                      fhash_dtype table_dt, float* enc, void* stream);
 
+/* Instrumentation, not part of the method: the memory one encoding (or its
+ * adjoint) touches.  For sample s, level l and corner row r of the cell (the
+ * vertex pair (x, x+1) at (y + (r & 1), z + (r >> 1 & 1), t + (r >> 2))):
+ * out_dir[((s L + l) 8 + r) 2 + j] = the global index of the 16-byte directory
+ * entry read (j = 0; j = 1 holds the next word's entry when x sits on bit 63
+ * of its word, else -1; both -1 for a dense or hashed level), out_slot[... + e]
+ * = the table row of vertex x + e (global, i.e. including slot_offset), -1
+ * when the vertex is inactive.  Both device int64 [n][L][8][2].  Positions are
+ * located exactly as fhash_encode_fwd does. */
+int fhash_corner_rows(const fhash_index* idx, const float* pos, int64_t n, int64_t* out_dir,
+                      int64_t* out_slot, void* stream);
+
 /* Touched-segment tracking of a table gradient (an optimisation of the dense
  * Adam sweep, not part of the method): the gradient is viewed as segments of
  * FHASH_TOUCH_FLOATS floats; flags (device uint8, one per segment of the

@@ -148,6 +148,7 @@ def _declare(L):
         "fhash_hash_index": (C.c_int, [P, I32, P, P]),
         "fhash_encode_fwd": (C.c_int, [P, P, I64, P, C.c_int, P, P]),
         "fhash_encode_bwd": (C.c_int, [P, P, I64, P, P, P, P]),
+        "fhash_corner_rows": (C.c_int, [P, P, I64, P, P, P]),
         "fhash_mlp_num_params": (I64, [P]),
         "fhash_mlp_fwd": (C.c_int, [P, P, P, P, I64, P, P]),
         "fhash_mlp_bwd": (C.c_int, [P, P, P, P, P, I64, P, P, P, P, P]),
@@ -308,6 +309,19 @@ def fhash_encode_fwd(idx: Index, pos, n, table, enc):
 def fhash_encode_bwd(idx: Index, pos, n, d_enc, d_table, touch=None):
     _check(lib().fhash_encode_bwd(C.byref(idx), _ptr(pos), n, _ptr(d_enc), _ptr(d_table),
                                   _touch(touch), _stream()), "fhash_encode_bwd")
+
+
+def fhash_corner_rows(idx: Index, pos, n, out_dir=None, out_slot=None):
+    """Directory entries and table rows the encoding of each sample touches
+    (instrumentation): two int64 tensors [n][L][8][2]."""
+    L = idx.grid.n_levels
+    if out_dir is None:
+        out_dir = torch.empty((n, L, 8, 2), dtype=torch.int64, device=pos.device)
+    if out_slot is None:
+        out_slot = torch.empty((n, L, 8, 2), dtype=torch.int64, device=pos.device)
+    _check(lib().fhash_corner_rows(C.byref(idx), _ptr(pos), n, _ptr(out_dir), _ptr(out_slot),
+                                   _stream()), "fhash_corner_rows")
+    return out_dir, out_slot
 
 
 def fhash_mlp_num_params(mlp: MlpDesc) -> int:

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfhash.so")
-SOURCES = ["fused_train.hip", "fused_bwd.hip", "fused.hip", "fused_fwd16.hip", "mlp.hip", "api.cpp",
+SOURCES = ["fused_train.hip", "fused_train16.hip", "fused_bwd.hip", "fused_bwd16.hip", "fused.hip",
+           "fused_fwd16.hip", "mlp.hip", "api.cpp",
            "index.hip",
            "encode.hip", "optim.hip", "lazy.hip", "sampler.hip", "render.hip", "sort.hip", "coreset.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

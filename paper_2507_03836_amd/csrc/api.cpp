@@ -91,7 +91,8 @@ int check_mlp(const fhash_mlp_desc* m, int* H, int* NH, bool allow_f16 = false) 
   const int h = m->width[1];
   for (int k = 1; k < m->n_layers; ++k)
     if (m->width[k] != h) return fail(FHASH_ENOTSUP, "hidden widths must be equal");
-  if (m->compute_dt != FHASH_F32 && !(allow_f16 && m->compute_dt == FHASH_F16))
+  if (m->compute_dt != FHASH_F32 &&
+      !(allow_f16 && (m->compute_dt == FHASH_F16 || m->compute_dt == FHASH_BF16)))
     return fail(FHASH_ENOTSUP, "mlp compute dtype %d not built for this call",
                 (int)m->compute_dt);
   if (!fh::mlp_supported(m->width[0], h, m->n_layers - 1))
@@ -264,6 +265,22 @@ int fhash_encode_fwd(const fhash_index* idx, const float* pos, int64_t n, const 
                     "fhash_encode_fwd");
 }
 
+int fhash_corner_rows(const fhash_index* idx, const float* pos, int64_t n, int64_t* out_dir,
+                      int64_t* out_slot, void* stream) {
+  int rc = check_index(idx);
+  if (rc) return rc;
+  if (n < 0) return fail(FHASH_EINVAL, "n < 0");
+  if (n == 0) return FHASH_OK;
+  if (pos == nullptr || out_dir == nullptr || out_slot == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (!aligned16(pos)) return fail(FHASH_EINVAL, "pos not 16-byte aligned");
+  if (n > (int64_t)1 << 40) return fail(FHASH_ERANGE, "n too large");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  return hip_status(fh::launch_corner_rows(g, pos, n, out_dir, out_slot, S(stream)),
+                    "fhash_corner_rows");
+}
+
 int fhash_encode_bwd(const fhash_index* idx, const float* pos, int64_t n, const float* d_enc,
                      float* d_table, const fhash_touch* touch, void* stream) {
   int rc = check_index(idx);
@@ -333,10 +350,16 @@ static uint32_t dedup_mask(const fhash_index* idx, int64_t n, uint32_t flags) {
 
 static int check_fused(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
                        int64_t n, const void* table, fhash_dtype tdt, const float* params,
-                       int* H, int* NH, bool allow_f16 = false) {
+                       int* H, int* NH, bool backward) {
   int rc = check_index(idx);
   if (rc) return rc;
-  if ((rc = check_mlp(mlp, H, NH, allow_f16))) return rc;
+  if ((rc = check_mlp(mlp, H, NH, true))) return rc;
+  // 16-bit decoders: FP16 forward for every feature count; BF16, and every
+  // 16-bit backward, for two features per level
+  if (mlp->compute_dt != FHASH_F32 && idx->grid.n_features != 2 &&
+      (backward || mlp->compute_dt == FHASH_BF16))
+    return fail(FHASH_ENOTSUP, "16-bit decoder dtype %d not built for F=%d%s",
+                (int)mlp->compute_dt, idx->grid.n_features, backward ? " (backward)" : "");
   if ((rc = check_table_dt(tdt))) return rc;
   const int in_w = idx->grid.n_levels * idx->grid.n_features;
   if (mlp->width[0] != in_w)
@@ -358,15 +381,16 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
                     const void* shadow, float* y, void* stream) {
   (void)shadow;
   int H, NH;
-  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
+  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, false);
   if (rc) return rc;
   if (n == 0) return FHASH_OK;
   if (y == nullptr) return fail(FHASH_EINVAL, "y is NULL");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
   const hipError_t e =
-      mlp->compute_dt == FHASH_F16
-          ? fh::launch_fused_fwd16(g, H, NH, pos, n, table, table_dt, params, y, S(stream))
+      mlp->compute_dt != FHASH_F32
+          ? fh::launch_fused_fwd16(g, H, NH, mlp->compute_dt, pos, n, table, table_dt, params, y,
+                                   S(stream))
           : fh::launch_fused_fwd(g, H, NH, pos, n, table, table_dt, params, y, S(stream));
   return hip_status(e, "fhash_fused_fwd");
 }
@@ -378,7 +402,7 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
                     void* stream) {
   (void)shadow;
   int H, NH;
-  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
+  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
   if (rc) return rc;
   const int64_t P = num_params(mlp);
   bool query;
@@ -391,8 +415,8 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
   fh::make_grid_dev(idx, &g);
   g.dedup = dedup_mask(idx, n, flags);
   if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
-  return hip_status(fh::launch_fused_bwd(g, H, NH, pos, n, table, table_dt, params, dy, d_table,
-                                         d_params, ws, P, S(stream)),
+  return hip_status(fh::launch_fused_bwd(g, H, NH, mlp->compute_dt, pos, n, table, table_dt,
+                                         params, dy, d_table, d_params, ws, P, S(stream)),
                     "fhash_fused_bwd");
 }
 
@@ -403,7 +427,7 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
                       const fhash_touch* touch, void* ws, size_t* ws_bytes, void* stream) {
   (void)shadow;
   int H, NH;
-  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH);
+  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
   if (rc) return rc;
   const int64_t P = num_params(mlp);
   bool query;
@@ -416,7 +440,8 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
   fh::make_grid_dev(idx, &g);
   g.dedup = dedup_mask(idx, n, flags);
   if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
-  return hip_status(fh::launch_fused_train(g, H, NH, pos, target, n, table, table_dt, params,
+  return hip_status(fh::launch_fused_train(g, H, NH, mlp->compute_dt, pos, target, n, table,
+                                           table_dt, params,
                                            loss_scale, d_table, d_params, loss_sum, ws, P,
                                            S(stream)),
                     "fhash_fused_train");
@@ -767,7 +792,7 @@ int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* 
   rc = ws_check(ws, ws_bytes, need, &query);
   if (rc || query) return rc;
   int H_, NH;
-  if ((rc = check_fused(idx, mlp, nullptr, 0, table, table_dt, params, &H_, &NH, true)))
+  if ((rc = check_fused(idx, mlp, nullptr, 0, table, table_dt, params, &H_, &NH, false)))
     return rc;
   if (total_rows(idx) == 0) return fail(FHASH_EINVAL, "index has no active vertex");
   char* p = static_cast<char*>(ws);
@@ -785,8 +810,9 @@ int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* 
     if (rc) return rc;
     if (ns > 0) {
       hipError_t e =
-          mlp->compute_dt == FHASH_F16
-              ? fh::launch_fused_fwd16(g, H_, NH, pos, ns, table, table_dt, params, y, S(stream))
+          mlp->compute_dt != FHASH_F32
+              ? fh::launch_fused_fwd16(g, H_, NH, mlp->compute_dt, pos, ns, table, table_dt,
+                                       params, y, S(stream))
               : fh::launch_fused_fwd(g, H_, NH, pos, ns, table, table_dt, params, y, S(stream));
       if (e != hipSuccess) return hip_status(e, "fhash_render decode");
     }

@@ -44,6 +44,43 @@ __global__ void __launch_bounds__(256)
                           g.touch, g.touch_begin);
 }
 
+// Instrumentation: per (sample, level) the directory entries and table rows the
+// 8 corner rows (dy, dz, dt) = (r & 1, r >> 1 & 1, r >> 2) of its cell touch.
+__global__ void __launch_bounds__(256)
+    corner_rows_kernel(GridDev g, const float4* __restrict__ pos, int64_t n,
+                       long long* __restrict__ out_dir, long long* __restrict__ out_slot) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * g.L) return;
+  const int64_t s = t / g.L;
+  const int l = (int)(t % g.L);
+  const LevelDev& d = g.lv[l];
+  const float4 p = pos[s];
+  int ix, iy, iz, it;
+  float fx, fy, fz, ft;
+  locate(p.x, d.rx, d.sx, ix, fx);
+  locate(p.y, d.ry, d.sy, iy, fy);
+  locate(p.z, d.rz, d.sz, iz, fz);
+  locate(p.w, d.rt, d.st, it, ft);
+  const bool active = g.active != 0 && d.hash_bits == 0;
+  for (int r = 0; r < 8; ++r) {
+    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
+    const int32_t tz = (it + dt) * d.rz + (iz + dz);
+    int64_t s0, s1;
+    bool v0, v1;
+    row_pair_slots(d, g.dir, g.active != 0, tz, iy + dy, ix, s0, s1, v0, v1);
+    const int64_t o = (t * 8 + r) * 2;
+    long long w0 = -1, w1 = -1;
+    if (active) {
+      w0 = d.dir_off + (int64_t)((tz * d.wv + (ix >> 6)) * d.ry + iy + dy);
+      if ((ix & 63) == 63) w1 = w0 + d.ry;
+    }
+    out_dir[o] = w0;
+    out_dir[o + 1] = w1;
+    out_slot[o] = v0 ? s0 : -1;
+    out_slot[o + 1] = v1 ? s1 : -1;
+  }
+}
+
 template <int F>
 hipError_t launch_fwd_t(const GridDev& g, const float* pos, int64_t n, const void* table,
                         fhash_dtype dt, float* enc, hipStream_t st) {
@@ -82,6 +119,16 @@ hipError_t launch_encode_fwd(const GridDev& g, const float* pos, int64_t n, cons
     case 8: return launch_fwd_t<8>(g, pos, n, table, dt, enc, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_corner_rows(const GridDev& g, const float* pos, int64_t n, int64_t* out_dir,
+                              int64_t* out_slot, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n * g.L + 255) / 256;
+  hipLaunchKernelGGL(corner_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g,
+                     reinterpret_cast<const float4*>(pos), n,
+                     reinterpret_cast<long long*>(out_dir), reinterpret_cast<long long*>(out_slot));
+  return hipGetLastError();
 }
 
 hipError_t launch_encode_bwd(const GridDev& g, const float* pos, int64_t n, const float* d_enc,

@@ -13,8 +13,10 @@ bool fused_supported(int F, int in_w, int H, int NH) {
 }
 
 size_t fused_ws_bytes(int64_t n, int64_t P) {
-  return (size_t)fused_waves(n, MODE_BWD) * (size_t)P * 4;
+  return (size_t)fused_blocks(n, MODE_BWD) * (size_t)P * 4;
 }
+
+int64_t fused_partials(int64_t n) { return fused_blocks(n, MODE_BWD); }
 
 hipError_t launch_fused_fwd(const GridDev& g, int H, int NH, const float* pos, int64_t n,
                             const void* table, fhash_dtype tdt, const float* params, float* y,
@@ -26,7 +28,7 @@ hipError_t launch_fused_fwd(const GridDev& g, int H, int NH, const float* pos, i
   A.params = params;
   A.y = y;
   A.in_w = g.L * g.F;
-  return fused_dispatch<MODE_FWD>(g, H, NH, tdt, A, nullptr, st);
+  return fused_dispatch<MODE_FWD, float>(g, H, NH, tdt, A, nullptr, st);
 }
 
 }  // namespace fh

@@ -9,20 +9,24 @@
 // that the MLP backward leaves in the same registers is scattered by the same
 // lane for the same levels.  Corner weights are recomputed, never stored.
 #pragma once
+#include <type_traits>
+
 #include "encode_dev.h"
 #include "kernels.h"
 #include "mlp_dev.h"
+#include "mlp_train_dev.h"
 
 namespace fh {
 
 namespace fused_detail {
 
-// Waves per workgroup: the forward keeps only the decoder weights in LDS, so
-// more waves share one copy; the backward modes also need per-wave tiles.
-// MODE_FWD16: the forward with the FP16-MFMA decoder (inference only).
+// Waves per workgroup: eight in every mode.  The forward keeps only the
+// decoder weights in LDS; the backward modes also hold the workgroup's
+// gradient image and per-wave tiles.  MODE_FWD16: the forward with a 16-bit
+// MFMA decoder (inference).
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_TRAIN = 2, MODE_FWD16 = 3 };
 constexpr bool is_forward(int mode) { return mode == MODE_FWD || mode == MODE_FWD16; }
-constexpr int waves_per_block(int mode) { return is_forward(mode) ? 8 : 4; }
+constexpr int waves_per_block(int mode) { return (void)mode, 8; }
 
 struct FusedArgs {
   const float4* pos;
@@ -33,7 +37,7 @@ struct FusedArgs {
   const float* params;
   float* y;        // MODE_FWD
   float* d_table;  // MODE_BWD / TRAIN
-  float* part;     // per-wave parameter-gradient partials
+  float* part;     // per-workgroup parameter-gradient partials
   double* loss_sum;
   int64_t P;
   float coef;  // dL/dy = coef * (y - target)
@@ -113,36 +117,46 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
     }
 }
 
-// The backward modes hold the decoder's gradient accumulators in registers;
-// up to two hidden layers they fit the 256 registers of two waves per SIMD
-// (without the hint the compiler spends more and runs one wave per SIMD).
-template <int MODE, int F, typename T, int INP, int H, int NH>
+// One workgroup per CU in the backward modes: the decoder weights, the FP32
+// gradient image of the workgroup (mlp_train_dev.h) and eight waves' tiles
+// share its LDS.  D is the decoder arithmetic: float (FP32 MFMA) or a 16-bit
+// type (_Float16 / __bf16 MFMA with FP32 accumulation); the FP32-decoder
+// forward is MODE_FWD, the 16-bit one MODE_FWD16.
+template <int MODE, int F, typename T, int INP, int H, int NH, typename D>
 __global__ void __launch_bounds__(64 * waves_per_block(MODE))
-    __attribute__((amdgpu_waves_per_eu(!is_forward(MODE) && NH <= 2 ? 2 : 1)))
+    __attribute__((amdgpu_waves_per_eu(is_forward(MODE) ? 1 : 2)))
     fused_kernel(GridDev g, FusedArgs A) {
   constexpr int kWaves = waves_per_block(MODE);
   constexpr bool FWD = is_forward(MODE);
+  constexpr bool D32 = std::is_same<D, float>::value;
   using S = MlpShape<INP, H, NH>;
-  constexpr int WS = FWD ? 0 : mlp_wave_scratch<INP, H, NH>();
-  constexpr int LDSF = (MODE == MODE_FWD16) ? MlpShapeH<INP, H, NH>::TOTAL_FLOATS
-                                            : S::WFLOATS + kWaves * WS + 1;
-  __shared__ __attribute__((aligned(16))) float lds[LDSF];
+  using G = GradLds<INP, H, NH>;
+  constexpr int WFL = (MODE == MODE_FWD16) ? MlpShapeH<INP, H, NH>::TOTAL_FLOATS
+                      : D32               ? S::WFLOATS
+                                          : MlpShapeT<INP, H, NH>::TOTAL_FLOATS;
+  constexpr int GFL = FWD ? 0 : G::FLOATS;
+  constexpr int WS = FWD ? 0
+                     : D32 ? train_wave_scratch_f32<INP, H, NH>()
+                           : train_wave_scratch_t<INP, H, NH>();
+  __shared__ __attribute__((aligned(16))) float lds[WFL + GFL + kWaves * WS + 1];
   __shared__ LevelDev lv[FHASH_MAX_LEVELS];
   if constexpr (MODE == MODE_FWD16)
-    load_weights_lds_h<INP, H, NH>(lds, A.params, A.in_w);
-  else
+    load_weights_lds_h<INP, H, NH, D>(lds, A.params, A.in_w);
+  else if constexpr (D32)
     load_weights_lds<INP, H, NH>(lds, A.params, A.in_w);
+  else
+    load_weights_lds_t<INP, H, NH, D>(lds, A.params, A.in_w);
+  float* grad = lds + WFL;
+  if constexpr (!FWD) grad_lds_zero<INP, H, NH>(grad);
   for (int e = threadIdx.x; e < FHASH_MAX_LEVELS; e += blockDim.x) lv[e] = g.lv[e];
   __syncthreads();
   const T* table = reinterpret_cast<const T*>(A.table);
   const int lane = threadIdx.x & 63, grp = lane >> 4, s = lane & 15;
   const int wib = threadIdx.x >> 6;
-  float* scratch = lds + S::WFLOATS + wib * WS;
+  float* scratch = lds + WFL + GFL + wib * WS;
   const int64_t nblk = (A.n + 15) / 16;
   const int64_t nwav = (int64_t)gridDim.x * kWaves;
   const int64_t wave = (int64_t)blockIdx.x * kWaves + wib;
-  MlpGrad<INP, H, NH> gr;
-  if (!FWD) gr.zero();
   double loss = 0.0;
   for (int64_t b = wave; b < nblk; b += nwav) {
     // Keep the decoder weights in LDS rather than in registers across blocks:
@@ -154,34 +168,42 @@ __global__ void __launch_bounds__(64 * waves_per_block(MODE))
     const float4 p = valid ? A.pos[smp] : make_float4(0.f, 0.f, 0.f, 0.f);
     float xb[S::INB][4];
     gather_block<F, T, INP>(g, lv, p, valid, table, xb);
-    if (!FWD) mlp_stage_input<INP, H, NH>(scratch, xb);
     float hs[NH][S::HB][4];
     float yv;
     if constexpr (MODE == MODE_FWD16)
-      yv = mlp_block_fwd_h<INP, H, NH>(lds, xb);
-    else
+      yv = mlp_block_fwd_h<INP, H, NH, D>(lds, xb);
+    else if constexpr (D32)
       yv = mlp_block_fwd<INP, H, NH>(lds, xb, hs);
-    if (FWD) {
+    else
+      yv = mlp_block_fwd_t<INP, H, NH, D>(lds, xb, hs);
+    if constexpr (FWD) {
       if (grp == 0 && valid) A.y[smp] = yv;
       continue;
-    }
-    float dyv = 0.0f;
-    if (MODE == MODE_BWD) {
-      dyv = valid ? A.dy[smp] : 0.0f;
     } else {
-      const float r = valid ? yv - A.target[smp] : 0.0f;
-      dyv = A.coef * r;
-      if (grp == 0) loss += (double)r * (double)r;
+      float dyv = 0.0f;
+      if (MODE == MODE_BWD) {
+        dyv = valid ? A.dy[smp] : 0.0f;
+      } else {
+        const float r = valid ? yv - A.target[smp] : 0.0f;
+        dyv = A.coef * r;
+        if (grp == 0) loss += (double)r * (double)r;
+      }
+      float dxb[S::INB][4];
+      if constexpr (D32)
+        mlp_block_bwd_lds<INP, H, NH>(lds, grad, scratch, xb, hs, dyv, dxb);
+      else
+        mlp_block_bwd_t<INP, H, NH, D>(lds, grad, reinterpret_cast<D*>(scratch), xb, hs, dyv,
+                                       dxb);
+      scatter_block<F, INP>(g, lv, p, valid, dxb, A.d_table);
     }
-    float dxb[S::INB][4];
-    mlp_block_bwd<INP, H, NH>(lds, scratch, hs, dyv, gr, dxb);
-    scatter_block<F, INP>(g, lv, p, valid, dxb, A.d_table);
   }
-  if (FWD) return;
-  mlp_write_partial<INP, H, NH>(gr, A.in_w, A.part + wave * A.P);
-  if (MODE == MODE_TRAIN && A.loss_sum != nullptr) {
-    for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
-    if (lane == 0) unsafeAtomicAdd(A.loss_sum, loss);
+  if constexpr (!FWD) {
+    __syncthreads();
+    grad_lds_write<INP, H, NH>(grad, A.in_w, A.part + (int64_t)blockIdx.x * A.P);
+    if (MODE == MODE_TRAIN && A.loss_sum != nullptr) {
+      for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
+      if (lane == 0) unsafeAtomicAdd(A.loss_sum, loss);
+    }
   }
 }
 
@@ -194,24 +216,29 @@ inline int64_t fused_waves(int64_t n, int mode) {
   return w < kWaves ? kWaves : w;
 }
 
-template <int MODE, int F, typename T, int INP, int H, int NH>
+// Workgroups of a launch (= decoder-gradient partials of a backward launch).
+inline int64_t fused_blocks(int64_t n, int mode) {
+  return fused_waves(n, mode) / waves_per_block(mode);
+}
+
+template <int MODE, int F, typename T, int INP, int H, int NH, typename D>
 hipError_t fused_t(const GridDev& g, FusedArgs A, float* d_params, hipStream_t st) {
   constexpr int kWaves = waves_per_block(MODE);
-  const int64_t nw = fused_waves(A.n, MODE);
-  hipLaunchKernelGGL((fused_kernel<MODE, F, T, INP, H, NH>), dim3((unsigned)(nw / kWaves)),
+  const int64_t nb = fused_blocks(A.n, MODE);
+  hipLaunchKernelGGL((fused_kernel<MODE, F, T, INP, H, NH, D>), dim3((unsigned)nb),
                      dim3(64 * kWaves), 0, st, g, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || is_forward(MODE)) return e;
-  return launch_reduce_partials(A.part, nw, A.P, d_params, st);
+  return launch_reduce_partials(A.part, nb, A.P, d_params, st);
 }
 
-template <int MODE, int F, typename T>
+template <int MODE, int F, typename T, typename D>
 hipError_t fused_shape(const GridDev& g, int H, int NH, FusedArgs A, float* d_params,
                        hipStream_t st) {
   const int inp = ((A.in_w + 15) / 16) * 16;
   switch (inp * 1000 + H * 10 + NH) {
 #define FH_C(I, HH, N) \
-  case I * 1000 + HH * 10 + N: return fused_t<MODE, F, T, I, HH, N>(g, A, d_params, st);
+  case I * 1000 + HH * 10 + N: return fused_t<MODE, F, T, I, HH, N, D>(g, A, d_params, st);
     FH_C(16, 32, 1) FH_C(16, 32, 2) FH_C(16, 32, 3)
     FH_C(16, 64, 1) FH_C(16, 64, 2) FH_C(16, 64, 3)
     FH_C(32, 32, 1) FH_C(32, 32, 2) FH_C(32, 32, 3)
@@ -221,24 +248,35 @@ hipError_t fused_shape(const GridDev& g, int H, int NH, FusedArgs A, float* d_pa
   return hipErrorInvalidValue;
 }
 
-template <int MODE>
+// Every feature count, FP32 or FP16 table, decoder arithmetic D.
+template <int MODE, typename D>
 hipError_t fused_dispatch(const GridDev& g, int H, int NH, fhash_dtype tdt, FusedArgs A,
                           float* d_params, hipStream_t st) {
   if (A.n == 0) return hipSuccess;
   if (tdt == FHASH_F32) {
     switch (g.F) {
-      case 1: return fused_shape<MODE, 1, float>(g, H, NH, A, d_params, st);
-      case 2: return fused_shape<MODE, 2, float>(g, H, NH, A, d_params, st);
-      case 4: return fused_shape<MODE, 4, float>(g, H, NH, A, d_params, st);
+      case 1: return fused_shape<MODE, 1, float, D>(g, H, NH, A, d_params, st);
+      case 2: return fused_shape<MODE, 2, float, D>(g, H, NH, A, d_params, st);
+      case 4: return fused_shape<MODE, 4, float, D>(g, H, NH, A, d_params, st);
     }
   } else {
     switch (g.F) {
-      case 1: return fused_shape<MODE, 1, __half>(g, H, NH, A, d_params, st);
-      case 2: return fused_shape<MODE, 2, __half>(g, H, NH, A, d_params, st);
-      case 4: return fused_shape<MODE, 4, __half>(g, H, NH, A, d_params, st);
+      case 1: return fused_shape<MODE, 1, __half, D>(g, H, NH, A, d_params, st);
+      case 2: return fused_shape<MODE, 2, __half, D>(g, H, NH, A, d_params, st);
+      case 4: return fused_shape<MODE, 4, __half, D>(g, H, NH, A, d_params, st);
     }
   }
   return hipErrorInvalidValue;
+}
+
+// Two features per level only (the production configurations).
+template <int MODE, typename D>
+hipError_t fused_dispatch_f2(const GridDev& g, int H, int NH, fhash_dtype tdt, FusedArgs A,
+                             float* d_params, hipStream_t st) {
+  if (A.n == 0) return hipSuccess;
+  if (g.F != 2) return hipErrorInvalidValue;
+  if (tdt == FHASH_F32) return fused_shape<MODE, 2, float, D>(g, H, NH, A, d_params, st);
+  return fused_shape<MODE, 2, __half, D>(g, H, NH, A, d_params, st);
 }
 
 }  // namespace fused_detail

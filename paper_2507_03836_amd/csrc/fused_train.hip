@@ -1,15 +1,18 @@
-// Fused encoding + MLP: forward + MSE loss + backward in one pass.
+// Fused encoding + MLP: forward + MSE loss + backward in one pass, FP32 decoder.
 #include "fused_impl.h"
 
 namespace fh {
 
 using namespace fused_detail;
 
-hipError_t launch_fused_train(const GridDev& g, int H, int NH, const float* pos,
+hipError_t launch_fused_train(const GridDev& g, int H, int NH, fhash_dtype ddt, const float* pos,
                               const float* target, int64_t n, const void* table, fhash_dtype tdt,
                               const float* params, float loss_scale, float* d_table,
                               float* d_params, double* loss_sum, void* ws, int64_t P,
                               hipStream_t st) {
+  if (ddt != FHASH_F32)
+    return launch_fused_train16(g, H, NH, ddt, pos, target, n, table, tdt, params, loss_scale,
+                                d_table, d_params, loss_sum, ws, P, st);
   FusedArgs A{};
   A.pos = reinterpret_cast<const float4*>(pos);
   A.target = target;
@@ -22,7 +25,7 @@ hipError_t launch_fused_train(const GridDev& g, int H, int NH, const float* pos,
   A.P = P;
   A.coef = (float)(2.0 * (double)loss_scale / (double)n);
   A.in_w = g.L * g.F;
-  return fused_dispatch<MODE_TRAIN>(g, H, NH, tdt, A, d_params, st);
+  return fused_dispatch<MODE_TRAIN, float>(g, H, NH, tdt, A, d_params, st);
 }
 
 }  // namespace fh

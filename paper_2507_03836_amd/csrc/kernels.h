@@ -20,6 +20,8 @@ hipError_t launch_encode_fwd(const GridDev& g, const float* pos, int64_t n, cons
                              fhash_dtype dt, float* enc, hipStream_t st);
 hipError_t launch_encode_bwd(const GridDev& g, const float* pos, int64_t n, const float* d_enc,
                              float* d_table, hipStream_t st);
+hipError_t launch_corner_rows(const GridDev& g, const float* pos, int64_t n, int64_t* out_dir,
+                              int64_t* out_slot, hipStream_t st);
 
 // mlp.hip
 bool mlp_supported(int in_w, int H, int NH);
@@ -30,25 +32,36 @@ hipError_t launch_mlp_bwd(int in_w, int H, int NH, const float* params, const fl
                           const float* dy, int64_t n, float* d_params, float* dx, void* ws,
                           int64_t P, hipStream_t st);
 
-// fused.hip
+// fused*.hip.  ddt: decoder arithmetic (FHASH_F32: FP32 MFMA; FHASH_F16 /
+// FHASH_BF16: 16-bit MFMA with FP32 accumulation; 16-bit backward and BF16
+// forward for two features per level only).
 bool fused_supported(int F, int in_w, int H, int NH);
 size_t fused_ws_bytes(int64_t n, int64_t P);
+int64_t fused_partials(int64_t n);
 hipError_t launch_fused_fwd(const GridDev& g, int H, int NH, const float* pos, int64_t n,
                             const void* table, fhash_dtype tdt, const float* params, float* y,
                             hipStream_t st);
-// fused_fwd16.hip: the same forward with the FP16-MFMA decoder
-hipError_t launch_fused_fwd16(const GridDev& g, int H, int NH, const float* pos, int64_t n,
-                              const void* table, fhash_dtype tdt, const float* params, float* y,
-                              hipStream_t st);
-hipError_t launch_fused_bwd(const GridDev& g, int H, int NH, const float* pos, int64_t n,
-                            const void* table, fhash_dtype tdt, const float* params,
+hipError_t launch_fused_fwd16(const GridDev& g, int H, int NH, fhash_dtype ddt, const float* pos,
+                              int64_t n, const void* table, fhash_dtype tdt, const float* params,
+                              float* y, hipStream_t st);
+hipError_t launch_fused_bwd(const GridDev& g, int H, int NH, fhash_dtype ddt, const float* pos,
+                            int64_t n, const void* table, fhash_dtype tdt, const float* params,
                             const float* dy, float* d_table, float* d_params, void* ws, int64_t P,
                             hipStream_t st);
-hipError_t launch_fused_train(const GridDev& g, int H, int NH, const float* pos,
+hipError_t launch_fused_bwd16(const GridDev& g, int H, int NH, fhash_dtype ddt, const float* pos,
+                              int64_t n, const void* table, fhash_dtype tdt, const float* params,
+                              const float* dy, float* d_table, float* d_params, void* ws,
+                              int64_t P, hipStream_t st);
+hipError_t launch_fused_train(const GridDev& g, int H, int NH, fhash_dtype ddt, const float* pos,
                               const float* target, int64_t n, const void* table, fhash_dtype tdt,
                               const float* params, float loss_scale, float* d_table,
                               float* d_params, double* loss_sum, void* ws, int64_t P,
                               hipStream_t st);
+hipError_t launch_fused_train16(const GridDev& g, int H, int NH, fhash_dtype ddt,
+                                const float* pos, const float* target, int64_t n,
+                                const void* table, fhash_dtype tdt, const float* params,
+                                float loss_scale, float* d_table, float* d_params,
+                                double* loss_sum, void* ws, int64_t P, hipStream_t st);
 
 // optim.hip
 hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,

@@ -219,21 +219,42 @@ __device__ __forceinline__ float mlp_block_fwd(const float* lds, const float (&x
 }
 
 // ---------------------------------------------------------------------------
-// FP16 decoder for inference (v_mfma_f32_16x16x16_f16, FP32 accumulation).
-// Same register layout as the FP32 engine: the accumulator of a layer holds,
-// in lane 16 g + s, features 16 a + 4 g + i of sample s, and those 4 values
-// rounded to FP16 are exactly the B operand of a 16-deep K block of the next
-// layer (B lane (g, s) supplies k = 4 g + i); the A operand of that block is
-// the 4 consecutive FP16 weights W[16 ob + m][16 a + 4 g .. + 3] (one 8-byte
-// LDS read).  One instruction covers what four FP32 16x16x4 steps did.
-typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+// 16-bit decoder (FP16 or BF16 operands, v_mfma_f32_16x16x16_{f16,bf16} with
+// FP32 accumulation).  Same register layout as the FP32 engine: the
+// accumulator of a layer holds, in lane 16 g + s, features 16 a + 4 g + i of
+// sample s, and those 4 values rounded to the 16-bit type are exactly the B
+// operand of a 16-deep K block of the next layer (B lane (g, s) supplies
+// k = 4 g + i); the A operand of that block is the 4 consecutive rounded
+// weights W[16 ob + m][16 a + 4 g .. + 3] (one 8-byte LDS read).  One
+// instruction covers what four FP32 16x16x4 steps did.
+template <typename T>
+struct Vec4T;
+template <>
+struct Vec4T<_Float16> {
+  typedef _Float16 type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec4T<__bf16> {
+  typedef __bf16 type __attribute__((ext_vector_type(4)));
+};
 
-__device__ __forceinline__ f4v mfma16h(h4v a, h4v b, f4v c) {
+template <typename T>
+__device__ __forceinline__ f4v mfma16t(typename Vec4T<T>::type a, typename Vec4T<T>::type b,
+                                       f4v c);
+template <>
+__device__ __forceinline__ f4v mfma16t<_Float16>(Vec4T<_Float16>::type a,
+                                                 Vec4T<_Float16>::type b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
+template <>
+__device__ __forceinline__ f4v mfma16t<__bf16>(Vec4T<__bf16>::type a, Vec4T<__bf16>::type b,
+                                               f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
 
-// LDS image of the FP16 decoder: FP32 biases and output layer first, then the
-// FP16 weight matrices (rows padded by 8 halves against bank conflicts).
+// LDS image of the 16-bit inference decoder: FP32 biases and output layer
+// first, then the rounded weight matrices (rows padded by 8 elements against
+// bank conflicts).
 template <int INP, int H, int NH>
 struct MlpShapeH {
   static constexpr int INB = INP / 16;
@@ -244,7 +265,7 @@ struct MlpShapeH {
   static constexpr int WOUT = BK + (NH - 1) * H;    // output weights [H]
   static constexpr int BOUT = WOUT + H;             // output bias
   static constexpr int FLOATS = (BOUT + 1 + 3) / 4 * 4;
-  // half part (offsets in halves, from the end of the float part)
+  // 16-bit part (offsets in elements, from the end of the float part)
   static constexpr int LD0 = INP + 8;
   static constexpr int LDH = H + 8;
   static constexpr int W0 = 0;
@@ -253,23 +274,22 @@ struct MlpShapeH {
   static constexpr int TOTAL_FLOATS = FLOATS + (HALVES + 1) / 2 + 4;
 };
 
-// Round the packed FP32 parameters into the FP16 LDS image (RNE; W0 columns
+// Round the packed FP32 parameters into the 16-bit LDS image (RNE; W0 columns
 // beyond in_w are zero).  Whole workgroup; caller syncs.
-template <int INP, int H, int NH>
+template <int INP, int H, int NH, typename T>
 __device__ void load_weights_lds_h(float* lds, const float* __restrict__ params, int in_w) {
   using S = MlpShapeH<INP, H, NH>;
-  _Float16* wh = reinterpret_cast<_Float16*>(lds + S::FLOATS);
+  T* wh = reinterpret_cast<T*>(lds + S::FLOATS);
   for (int e = threadIdx.x; e < H * INP; e += blockDim.x) {
     const int o = e / INP, i = e % INP;
-    wh[S::W0 + o * S::LD0 + i] = (_Float16)((i < in_w) ? params[o * in_w + i] : 0.0f);
+    wh[S::W0 + o * S::LD0 + i] = (T)((i < in_w) ? params[o * in_w + i] : 0.0f);
   }
   const float* p = params + H * in_w;
   for (int e = threadIdx.x; e < H; e += blockDim.x) lds[S::B0 + e] = p[e];
   p += H;
   for (int k = 1; k < NH; ++k) {
-    _Float16* wk = wh + S::WK + (k - 1) * H * S::LDH;
-    for (int e = threadIdx.x; e < H * H; e += blockDim.x)
-      wk[(e / H) * S::LDH + e % H] = (_Float16)p[e];
+    T* wk = wh + S::WK + (k - 1) * H * S::LDH;
+    for (int e = threadIdx.x; e < H * H; e += blockDim.x) wk[(e / H) * S::LDH + e % H] = (T)p[e];
     p += H * H;
     for (int e = threadIdx.x; e < H; e += blockDim.x) lds[S::BK + (k - 1) * H + e] = p[e];
     p += H;
@@ -278,17 +298,17 @@ __device__ void load_weights_lds_h(float* lds, const float* __restrict__ params,
   if (threadIdx.x == 0) lds[S::BOUT] = p[H];
 }
 
-// out = act(W in + b) with FP16 operands and FP32 accumulation.
-template <int INB, int HB>
-__device__ __forceinline__ void fwd_layer_h(const _Float16* W, int ld, const float* b,
-                                            const float (&in)[INB][4], float (&out)[HB][4],
-                                            bool relu) {
+// out = relu(W round(in) + b) with 16-bit operands and FP32 accumulation.
+template <typename T, int INB, int HB>
+__device__ __forceinline__ void fwd_layer_t(const T* W, int ld, const float* b,
+                                            const float (&in)[INB][4], float (&out)[HB][4]) {
+  using V = typename Vec4T<T>::type;
   const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
-  h4v bin[INB];
+  V bin[INB];
 #pragma unroll
   for (int a = 0; a < INB; ++a)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bin[a][i] = (_Float16)in[a][i];
+    for (int i = 0; i < 4; ++i) bin[a][i] = (T)in[a][i];
   f4v c[HB];
 #pragma unroll
   for (int ob = 0; ob < HB; ++ob)
@@ -298,29 +318,29 @@ __device__ __forceinline__ void fwd_layer_h(const _Float16* W, int ld, const flo
   for (int a = 0; a < INB; ++a)
 #pragma unroll
     for (int ob = 0; ob < HB; ++ob) {
-      const h4v w = *reinterpret_cast<const h4v*>(W + (16 * ob + m) * ld + 16 * a + 4 * g);
-      c[ob] = mfma16h(w, bin[a], c[ob]);
+      const V w = *reinterpret_cast<const V*>(W + (16 * ob + m) * ld + 16 * a + 4 * g);
+      c[ob] = mfma16t<T>(w, bin[a], c[ob]);
     }
 #pragma unroll
   for (int ob = 0; ob < HB; ++ob)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) out[ob][i] = relu ? fmaxf(c[ob][i], 0.0f) : c[ob][i];
+    for (int i = 0; i < 4; ++i) out[ob][i] = fmaxf(c[ob][i], 0.0f);
 }
 
-// Forward of one 16-sample block through the FP16 decoder; the output layer
+// Forward of one 16-sample block through the 16-bit decoder; the output layer
 // (a dot product of width H) runs in FP32 on the FP32 hidden activations.
-template <int INP, int H, int NH>
+template <int INP, int H, int NH, typename T>
 __device__ __forceinline__ float mlp_block_fwd_h(const float* lds, const float (&xb)[INP / 16][4]) {
   using S = MlpShapeH<INP, H, NH>;
   const int lane = threadIdx.x & 63, g = lane >> 4;
-  const _Float16* wh = reinterpret_cast<const _Float16*>(lds + S::FLOATS);
+  const T* wh = reinterpret_cast<const T*>(lds + S::FLOATS);
   float h[S::HB][4];
-  fwd_layer_h<S::INB, S::HB>(wh + S::W0, S::LD0, lds + S::B0, xb, h, true);
+  fwd_layer_t<T, S::INB, S::HB>(wh + S::W0, S::LD0, lds + S::B0, xb, h);
 #pragma unroll
   for (int k = 1; k < NH; ++k) {
     float h2[S::HB][4];
-    fwd_layer_h<S::HB, S::HB>(wh + S::WK + (k - 1) * H * S::LDH, S::LDH, lds + S::BK + (k - 1) * H,
-                              h, h2, true);
+    fwd_layer_t<T, S::HB, S::HB>(wh + S::WK + (k - 1) * H * S::LDH, S::LDH,
+                                 lds + S::BK + (k - 1) * H, h, h2);
 #pragma unroll
     for (int a = 0; a < S::HB; ++a)
 #pragma unroll

@@ -12,11 +12,12 @@ the packed MLP parameters, so one dense Adam launch covers every parameter.
 
 Mixed precision (precision="mixed"): the fused kernels read an FP16 copy of
 the tables that the Adam sweep rewrites from the FP32 master values (the
-shadow); gradients, Adam moments and the decoder stay FP32.  The loss is
-scaled by a dynamic factor (start 2^16, doubled after `scale_window` clean
-steps, halved with the step skipped when a decoder gradient is not finite:
-the output-bias gradient is the sum of every sample's output gradient, so a
-non-finite sample gradient shows up there).
+shadow) and run the decoder on 16-bit MFMA (BF16 by default, `decoder`),
+accumulating in FP32; gradients, Adam moments and master weights stay FP32.
+The loss is scaled by a dynamic factor (start 2^16, doubled after
+`scale_window` clean steps, halved with the step skipped when a gradient is
+not finite: the output-bias gradient is the sum of every sample's output
+gradient, so a non-finite sample gradient shows up there).
 
 Touched-segment tracking (on by default): a step's scatter-add writes only a
 small part of the fine levels' gradient, so the scatter flags every 64-byte
@@ -76,14 +77,19 @@ class FHashModel:
                  table_init: torch.Tensor | None = None, mlp_init: torch.Tensor | None = None,
                  init_seed: int = 3000, precision: str = "fp32", loss_scale: float = 2.0 ** 16,
                  scale_window: int = 2000, track_touched: bool = True, lazy: bool = False,
-                 max_steps: int = 1 << 16, hash_bits: int = 0):
+                 max_steps: int = 1 << 16, hash_bits: int = 0, decoder: str | None = None):
         if precision not in ("fp32", "mixed"):
             raise ValueError(f"precision must be 'fp32' or 'mixed', not {precision!r}")
+        if decoder is None:
+            decoder = "bf16" if precision == "mixed" else "f32"
+        if decoder not in ("f32", "f16", "bf16"):
+            raise ValueError(f"decoder must be 'f32', 'f16' or 'bf16', not {decoder!r}")
         self.cfg = cfg
         self.precision = precision
+        self.decoder = decoder
         self.device = torch.device(device)
         self.grid = fl.grid_desc(cfg.res, cfg.n_features)
-        self.mlp = fl.mlp_desc(cfg.width)
+        self.mlp = fl.mlp_desc(cfg.width, {"f32": fl.F32, "f16": fl.F16, "bf16": fl.BF16}[decoder])
         if hash_bits:  # spatial-hash comparison index (mask not used)
             self.index, self.slots_per_level = fl.fhash_hash_index(self.grid, hash_bits)
             self._dir = None

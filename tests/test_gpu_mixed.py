@@ -40,12 +40,15 @@ def _dims(mask):
     return [Sx, Sy, Sz, T]
 
 
-def _model(mask, table0, mlp0, precision, **kw):
+def _model(mask, table0, mlp0, precision, decoder="f32", **kw):
+    """Mixed precision with the FP32 decoder by default: these tests isolate the
+    FP16 table reads and the loss scaling (the 16-bit decoder has its own tests)."""
     from paper_2507_03836_amd.model import FHashConfig, FHashModel
     cfg = FHashConfig(res=TINY_RES, n_features=2, hidden=32, n_hidden=2)
     bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
     return cfg, FHashModel(cfg, bits, _dims(mask), table_init=torch.from_numpy(table0),
-                           mlp_init=torch.from_numpy(mlp0), precision=precision, **kw)
+                           mlp_init=torch.from_numpy(mlp0), precision=precision,
+                           decoder=decoder, **kw)
 
 
 def _close(got, ref, mag, what, scale=1.0):

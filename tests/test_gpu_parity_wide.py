@@ -283,3 +283,28 @@ def test_lazy_equals_dense_wide(fl, vol):
     n = dense.n_params
     for name in ("params", "m", "v", "grads"):
         same(getattr(lazy, name)[:n], getattr(dense, name)[:n], name)
+
+
+def test_corner_rows_match_oracle_corners(fl, vol):
+    """fhash_corner_rows (the instrumentation behind the benchmark's
+    compulsory-line count): table rows equal the oracle's corner slots (corner
+    c = x-bit | row << 1), directory entries follow the documented layout
+    ((t Rz + z) ceil(Rx/64) + x // 64) Ry + y of the oracle's cell."""
+    idx, dir_t, g, _ = _setup(fl, vol, WIDE16, 2, "f32")
+    n = 1000
+    pos = _positions(n, 61)
+    d_dir, d_slot = fl.fhash_corner_rows(idx, torch.from_numpy(pos).cuda(), n)
+    slots, _ = O.corners(g, pos)
+    got = d_slot.cpu().numpy().reshape(n, 16, 8, 2)
+    want = slots.reshape(n, 16, 8, 2)  # c = e + 2 r
+    np.testing.assert_array_equal(got, want)
+    dd = d_dir.cpu().numpy()
+    for s in range(0, n, 37):
+        for l, (Rx, Ry, Rz, Rt) in enumerate(WIDE16):
+            cell = [O.locate(float(pos[s, d]), WIDE16[l][d])[0] for d in range(4)]
+            Wv = (Rx + 63) // 64
+            for r in range(8):
+                y, z, t = cell[1] + (r & 1), cell[2] + ((r >> 1) & 1), cell[3] + (r >> 2)
+                w0 = int(idx.dir_offset[l]) + ((t * Rz + z) * Wv + cell[0] // 64) * Ry + y
+                assert dd[s, l, r, 0] == w0
+                assert dd[s, l, r, 1] == (w0 + Ry if cell[0] % 64 == 63 else -1)

@@ -55,11 +55,9 @@ def test_render_matches_oracle(scene, az, el, t, W, H):
                                  s["params"].astype(np.float64), s["mask"], view, t, s["tf"], W,
                                  H, pixel_stats=True)
     bound, amb = render_bound(pix, s["tf"])
-    ok = ~amb
     err = np.abs(img - ref)
-    assert (err[ok] <= np.broadcast_to(bound, err.shape)[ok]).all(), \
-        float((err - bound)[ok].max())
-    assert ok.mean() > 0.95
+    assert (err <= bound).all(), float((err - bound).max())
+    assert amb.mean() < 0.5
     assert ref[..., 3].max() > 0.5  # the scene is not empty
     # pace 1 evaluates exactly the composited samples; a larger pace may also
     # decode samples past a ray's termination point in its last batch (discarded)

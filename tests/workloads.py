@@ -29,7 +29,7 @@ def coreset_ids(mask):
     return OC.coreset_ids(np.asarray(mask, bool))
 
 
-def render_bound(pix, tf, rtol=1e-5, atol=1e-12):
+def render_bound(pix, tf, rtol=1e-5, atol=1e-12, alpha_stop=0.99):
     """Per-pixel bound on |image - oracle image| for a renderer that decodes in
     FP32 and composites in FP32, from the oracle's per-pixel statistics pix
     ([H][W][3]: composited samples n, sum of their output magnitudes, smallest
@@ -41,12 +41,16 @@ def render_bound(pix, tf, rtol=1e-5, atol=1e-12):
     opacity are at most 1 in magnitude) adds the per-sample changes of opacity
     twice and of colour once, plus four FP32 roundings per step.  Pixels whose
     opacity came within the opacity bound of alpha_stop may stop one sample
-    apart and are returned as ambiguous.  Returns (bound, ambiguous)."""
+    apart (ambiguous): the sample composited by one side and not the other
+    adds (1 - A) a c <= 1 - alpha_stop + (the opacity bound) to each channel,
+    which their bound includes.  Returns (bound [H][W][1], ambiguous [H][W])."""
     u = 2.0 ** -24
     tf = np.asarray(tf, np.float64)
     s = 255.0 * np.abs(np.diff(tf, axis=0)).max()
     n, ymag, margin = pix[..., 0], pix[..., 1], pix[..., 2]
     dval = s * (rtol * ymag + atol * n) + 3 * u * n
+    d_alpha = dval + 4 * u * n
     bound = 3 * dval + 4 * u * n + 1e-7
-    ambiguous = margin <= dval + 4 * u * n
+    ambiguous = margin <= d_alpha
+    bound = np.where(ambiguous, bound + (1.0 - float(np.float32(alpha_stop))) + d_alpha, bound)
     return bound[..., None], ambiguous
