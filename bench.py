@@ -68,9 +68,27 @@ CATCHUP_TRAFFIC = {"bytes": 12.98e9, "params": 6390343593, "batch": 1 << 18, "st
                    "source_md5": "05dcf65c0c53af2e83bb86cbf74a280c"}
 
 # HBM bytes of one feature-extraction launch on the 480x720x120x100 volume from the two
-# counter passes (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the copy-calibrated factors)
+# counter passes (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the copy-calibrated factors);
+# valid only while the source text of classify4_kernel (hashed alone by _kernel_md5) and
+# the volume shape equal those the counters were taken on.
 CLASSIFY_TRAFFIC = {"bytes": 17141931808.0, "shape": [480, 720, 120, 100],
-                    "source_md5": "a44d562c1bed5106ebd1e5acdedd3048"}
+                    "kernel_md5": "069f488afcee6ec399a6892a53ef8c05"}
+
+
+def _kernel_md5(path, name):
+    """md5 of one kernel's source text: from the line holding `name(` back to
+    the preceding __global__, through the brace that closes its body."""
+    import hashlib
+    src = open(path).read()
+    i = src.index(name + "(")
+    i = src.rindex("__global__", 0, i)
+    j = src.index("{", src.index(name + "(", i))
+    depth = 0
+    for k in range(j, len(src)):
+        depth += {"{": 1, "}": -1}.get(src[k], 0)
+        if depth == 0:
+            return hashlib.md5(src[i:k + 1].encode()).hexdigest()
+    raise ValueError(name)
 
 
 def log(*a):
@@ -96,12 +114,14 @@ def parse():
                     help="Adam over the large levels: deferred (same values, bit for bit), "
                          "dense with touched-segment gradient reads, or plain dense")
     ap.add_argument("--key-frames", type=int, default=0,
-                    help="K > 1: train on every K-th timestep only (finest temporal "
-                         "resolution = number of key frames) and report PSNR on seen and "
+                    help="K > 1: train on K key frames evenly spaced over the timesteps "
+                         "(finest temporal resolution = K) and report PSNR on seen and "
                          "unseen frames next to a model trained on every frame")
     ap.add_argument("--hash-bits", type=int, default=0,
                     help="b > 0: the spatial-hash comparison index instead of F-Hash (levels "
                          "of more than 2^b vertices hash into 2^b rows, collisions allowed)")
+    ap.add_argument("--fold-sweep", action="store_true",
+                    help="dense FBB model with fold-policy levels: embedding size x fold sweep")
     ap.add_argument("--dense-index", action="store_true",
                     help="index every vertex of the box (the F-Hash equation, no feature mask) "
                          "instead of the vertices of active cells; samples still come from "
@@ -219,45 +239,50 @@ def time_to_psnr(args, model, step, gen, dims, t_train0, k_done):
 
 
 def key_frame_bench(args):
-    """Key-frame training with temporal super-resolution: samples only from the voxels of
-    every K-th timestep, the finest temporal resolution equal to the number of key frames;
-    PSNR on coreset draws at the key frames (seen) and at the frames between them
-    (unseen), next to the same model trained on every frame for the same steps."""
+    """Key-frame training with temporal super-resolution (Sec. 3.2.2): n_kf key
+    frames evenly spaced over the T frames (first and last included, frame
+    round(k (T-1) / (n_kf-1))); samples only from their coreset
+    (fhash_coreset_frames); the time coordinate of every frame from
+    fhash_key_frame_times, so key frames sit on the vertices of the finest
+    temporal level (n_kf vertices, geometric temporal range 4..n_kf); PSNR on
+    coreset draws at the key frames (seen) and at the other frames (unseen,
+    reached only through the temporal interpolation), next to the same model
+    trained on every frame (finest temporal level T) for the same steps."""
     import numpy as np
     from paper_2507_03836_amd import _lib as fl
-    from paper_2507_03836_amd import synth, volume
+    from paper_2507_03836_amd import volume
     from paper_2507_03836_amd.model import (FHashConfig, FHashModel, geometric_resolutions,
                                             psnr_on)
     fl.lib()
     dims = [int(x) for x in args.shape.split(",")]
-    K = args.key_frames
+    T = dims[3]
+    n_kf = args.key_frames
+    key = sorted({int(round(k * (T - 1) / (n_kf - 1))) for k in range(n_kf)})
+    unseen = [n for n in range(T) if n not in key]
     gen = volume.production_volume(dims, seed=args.field_seed)
-    core = gen["coreset"]
-    frame = core // (dims[0] * dims[1] * dims[2])
-    key = core[frame % K == 0].contiguous()
-    unseen = core[frame % K != 0].contiguous()
-    del frame
-    n_kf = (dims[3] - 1) // K + 1
+    frame_t = torch.from_numpy(fl.fhash_key_frame_times(T, key)).cuda()
+    cs_key = fl.fhash_coreset_frames(gen["bits"], dims, key)
+    cs_unseen = fl.fhash_coreset_frames(gen["bits"], dims, unseen)
     P = 1 << 22
-    probes = {}
-    for name, c, seed in (("seen", key, 7001), ("unseen", unseen, 7002)):
-        pp = torch.empty(P, 4, device="cuda")
-        pt = torch.empty(P, device="cuda")
-        fl.fhash_sample(seed, 1, P, c, c.numel(), dims, gen["field"], pp, pt)
-        probes[name] = (pp, pt)
     B = args.batch
-    pos = torch.empty(B, 4, device="cuda")
-    tgt = torch.empty(B, device="cuda")
     out = {"metric": "probe PSNR (dB) on seen and unseen frames after key-frame training",
            "unit": "dB", "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
            "config": {"workload": f"F-Hash key-frame training, {'x'.join(map(str, dims))} "
-                                  f"synthetic volume, every {K}th of {dims[3]} timesteps "
-                                  f"({n_kf} key frames), batch 2^{int(np.log2(B))}, "
-                                  f"{args.steps} steps",
-                      "key_frames": n_kf, "key_voxels": int(key.numel()),
-                      "unseen_voxels": int(unseen.numel())},
+                                  f"synthetic volume, {len(key)} key frames of {T}, batch "
+                                  f"2^{int(np.log2(B))}, {args.steps} steps",
+                      "key_frames": key, "key_voxels": int(cs_key.numel()),
+                      "unseen_voxels": int(cs_unseen.numel())},
            "runs": {}}
-    for label, c, rt in (("key_frames", key, n_kf), ("all_frames", core, dims[3])):
+    pos = torch.empty(B, 4, device="cuda")
+    tgt = torch.empty(B, device="cuda")
+    for label, cs, rt, ft in (("key_frames", cs_key, len(key), frame_t),
+                              ("all_frames", gen["coreset"], T, None)):
+        probes = {}
+        for name, c, seed in (("seen", cs_key, 7001), ("unseen", cs_unseen, 7002)):
+            pp = torch.empty(P, 4, device="cuda")
+            pt = torch.empty(P, device="cuda")
+            fl.fhash_sample(seed, 1, P, c, c.numel(), dims, gen["field"], pp, pt, frame_t=ft)
+            probes[name] = (pp, pt)
         res = geometric_resolutions(args.levels, 16, 512, 4, rt, dims)
         cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers)
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3000, lazy=True,
@@ -265,8 +290,8 @@ def key_frame_bench(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            fl.fhash_sample(args.sampler_seed, k + 1, B, c, c.numel(), dims, gen["field"], pos,
-                            tgt)
+            fl.fhash_sample(args.sampler_seed, k + 1, B, cs, cs.numel(), dims, gen["field"], pos,
+                            tgt, frame_t=ft)
             model.fwd_bwd(pos, tgt)
             model.optimizer_step()
         model.flush()
@@ -278,9 +303,101 @@ def key_frame_bench(args):
         out["runs"][label] = r
         log(f"[keyframes] {label}: {r}")
         model.params = model.grads = model.m = model.v = None
-        del model
+        del model, probes
         torch.cuda.empty_cache()
     out["value"] = out["runs"]["key_frames"]["psnr_unseen_db"]
+    print(json.dumps(out), flush=True)
+
+
+def fold_sweep_bench(args):
+    """The paper's published mode on the product path: a dense model over the
+    feature bounding box (Sec. 3.1: FBB of the key frames' feature, positions
+    translated and scaled to it), fold-policy levels (Sec. 3.2.1-3.2.2:
+    fhash_fold_resolutions of the FBB size and the key-frame count), trained on
+    the key frames' coreset; embedding size F in {1, 2, 4} x fold in {2, 4, 6}
+    (the shape of the paper's Table 1).  Per cell: levels, parameters, ms per
+    step with the deferred Adam (batch as --batch), the fused kernel's share,
+    one dense Adam sweep over every parameter, and probe PSNR after --steps
+    steps.  Cells whose decoder input L x F exceeds 32 are not built for the
+    fused kernels and are reported as such."""
+    import numpy as np
+    from paper_2507_03836_amd import _lib as fl
+    from paper_2507_03836_amd import volume
+    from paper_2507_03836_amd.model import FHashConfig, FHashModel, psnr_on
+    fl.lib()
+    dims = [int(x) for x in args.shape.split(",")]
+    T = dims[3]
+    n_kf = 10
+    key = sorted({int(round(k * (T - 1) / (n_kf - 1))) for k in range(n_kf)})
+    gen = volume.production_volume(dims, seed=args.field_seed)
+    boxes = fl.fhash_feature_boxes(gen["bits"], dims).cpu().numpy()[key]
+    fbb = [int(boxes[:, d].min()) for d in range(3)] + [int(boxes[:, 3 + d].max())
+                                                        for d in range(3)]
+    size = [fbb[3 + d] - fbb[d] + 1 for d in range(3)] + [len(key)]
+    frame_t = torch.from_numpy(fl.fhash_key_frame_times(T, key)).cuda()
+    cs = fl.fhash_coreset_frames(gen["bits"], dims, key)
+    B = args.batch
+    pos = torch.empty(B, 4, device="cuda")
+    tgt = torch.empty(B, device="cuda")
+    P = 1 << 21
+    ppos = torch.empty(P, 4, device="cuda")
+    ptgt = torch.empty(P, device="cuda")
+    fl.fhash_sample(7003, 1, P, cs, cs.numel(), dims, gen["field"], ppos, ptgt, frame_t=frame_t,
+                    box=fbb)
+    stream = torch.cuda.current_stream()
+    cells = []
+    for fold in (2, 4, 6):
+        res = fl.fhash_fold_resolutions(size, fold)
+        for F in (1, 2, 4):
+            cell = {"fold": fold, "F": F, "levels": len(res), "res_finest": res[-1]}
+            if len(res) * F > 32:
+                cell["built"] = False
+                cells.append(cell)
+                log(f"[fold] fold {fold} F {F}: {len(res)} levels x {F} > 32 inputs, not built")
+                continue
+            cfg = FHashConfig(res=res, n_features=F, hidden=64, n_hidden=2)
+            model = FHashModel(cfg, None, dims, init_seed=3000, lazy=True,
+                               max_steps=args.steps + 8)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            fb_ms = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                fl.fhash_sample(args.sampler_seed, k + 1, B, cs, cs.numel(), dims, gen["field"],
+                                pos, tgt, frame_t=frame_t, box=fbb)
+                model.prepare(pos)
+                ev[0].record(stream)
+                model.fwd_bwd(pos, tgt, prepared=True)
+                ev[1].record(stream)
+                model.optimizer_step()
+                ev[1].synchronize()
+                fb_ms.append(ev[0].elapsed_time(ev[1]))
+            model.flush()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            psnr = psnr_on(model, ppos, ptgt)
+            # one dense Adam sweep over every parameter (the optimiser of the paper)
+            opt = model.adam_desc(args.steps + 1)
+            n = model.n_params
+            ev[2].record(stream)
+            fl.fhash_step(opt, model.params[:n], model.grads[:n], model.m[:n], model.v[:n])
+            ev[3].record(stream)
+            torch.cuda.synchronize()
+            cell.update({"built": True, "params": n, "ms_per_step": ms,
+                         "fused_fwd_bwd_ms": float(np.median(fb_ms)),
+                         "dense_adam_ms": ev[2].elapsed_time(ev[3]), "psnr_db": psnr})
+            cells.append(cell)
+            log(f"[fold] fold {fold} F {F}: {cell}")
+            model.params = model.grads = model.m = model.v = model.lazy = None
+            del model
+            torch.cuda.empty_cache()
+    out = {"metric": "training ms/step and probe PSNR over embedding size x fold (dense FBB)",
+           "unit": "ms/step", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"F-Hash dense FBB model, {'x'.join(map(str, dims))} synthetic "
+                                  f"volume, {len(key)} key frames, FBB {size[:3]}, decoder "
+                                  f"L*F-64-64-1, batch 2^{int(np.log2(B))}, {args.steps} steps",
+                      "key_frames": key, "fbb": fbb, "coreset": int(cs.numel())},
+           "cells": cells}
     print(json.dumps(out), flush=True)
 
 
@@ -654,9 +771,8 @@ def coreset_bench(args):
         cpu = {"value": f1.size / sec, "unit": "voxels/s", "cores": 1, "kind": "oracle",
                "sample": f"one timestep ({f1.size} voxels) through the numpy oracle, {sec:.2f} s"}
     dom = out["feature_mask"]
-    import hashlib
     src = os.path.join(ROOT, "paper_2507_03836_amd", "csrc", "coreset.hip")
-    same = (hashlib.md5(open(src, "rb").read()).hexdigest() == CLASSIFY_TRAFFIC["source_md5"]
+    same = (_kernel_md5(src, "classify4_kernel") == CLASSIFY_TRAFFIC["kernel_md5"]
             and dims == CLASSIFY_TRAFFIC["shape"] and Sx % 4 == 0)
     print(json.dumps({
         "metric": "coreset selection voxels/s (feature mask, dilation, boxes, occupancy, ids)",
@@ -961,6 +1077,20 @@ def headline_bench(args):
     fl.fhash_sample(4003, 1, P, gen["coreset"], gen["M"], dims, gen["field"], ppos, ptgt)
     pos = torch.empty(B, 4, device="cuda")
     tgt = torch.empty(B, device="cuda")
+    # load every kernel of both paths once (code-object loading and first-launch
+    # costs stay out of both paths' timings)
+    for prec in ("fp32", "mixed"):
+        small = FHashModel(FHashConfig(res=[[4, 4, 4, 2]] * 16, n_features=2, hidden=64,
+                                       n_hidden=3), None, dims, precision=prec, lazy=True,
+                           max_steps=4)
+        fl.fhash_sample(1, 1, 4096, gen["coreset"], gen["M"], dims, gen["field"], pos, tgt)
+        small.prepare(pos[:4096])
+        small.fwd_bwd(pos[:4096], tgt[:4096], prepared=True)
+        small.optimizer_step()
+        small.flush()
+        small.forward(pos[:4096])
+        del small
+    torch.cuda.synchronize()
     paths, keep = {}, None
     for prec in ("fp32", "mixed"):
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, precision=prec, lazy=True,
@@ -1052,6 +1182,8 @@ def main():
 
     if args.serve_multi:
         return serve_multi_bench(args)
+    if args.fold_sweep:
+        return fold_sweep_bench(args)
     if (args.workload == "headline" and args.key_frames <= 1 and not args.serve and
             not args.coreset):
         return headline_bench(args)

@@ -132,6 +132,28 @@ int fhash_dense_index(const fhash_grid_desc* grid, fhash_index* out, int64_t* sl
 int fhash_hash_index(const fhash_grid_desc* grid, int32_t hash_bits, fhash_index* out,
                      int64_t* slots_per_level);
 
+/* Level resolutions by the fold policy (Sec. 3.2.1 spatial, Sec. 3.2.2
+ * temporal), host only.  size = (Sx, Sy, Sz, n_kf): the vertex counts of the
+ * finest level, i.e. the FBB size in voxels and the number of key frames, each
+ * in [2, 2^24]; fold >= 2.  Per dimension the finest level has `size`
+ * vertices and each coarser level ceil(R / fold) while R > fold, else 2 (the
+ * tail); the level count is the largest over the four dimensions of the
+ * smallest L with fold^L >= size.  res (HOST int32 [FHASH_MAX_LEVELS][4]) row l
+ * = level l, coarsest first (the fhash_grid_desc order); *n_levels = L.
+ * FHASH_ERANGE when L > FHASH_MAX_LEVELS. */
+int fhash_fold_resolutions(const int64_t size[4], int32_t fold, int32_t* res, int32_t* n_levels);
+
+/* Time coordinate of every frame under key-frame training (Sec. 3.2.2), host
+ * only: key frame k (frames: HOST int32[n_frames], strictly increasing, in
+ * [0, T), n_frames >= 2) sits on vertex k of a temporal level of n_frames
+ * vertices, tau = k / (n_frames - 1); a frame n between key frames k and k+1
+ * gets tau = (k + (n - frames[k]) / (frames[k+1] - frames[k])) / (n_frames - 1)
+ * (linear in the frame index between neighbouring key frames), frames before
+ * the first key frame 0, after the last 1.  Evaluated in FP64, rounded to
+ * FP32 into frame_t (HOST float[T]); the sampler and the renderer take these
+ * as the model's time coordinate. */
+int fhash_key_frame_times(int64_t T, const int32_t* frames, int32_t n_frames, float* frame_t);
+
 /* -------------------------------------------------------------- encoding ----
  * Input encoding (Sec. 3.2.4): per level, locate the 4D cell containing the
  * sample (u = p*(R-1) as one FP32 multiply, cell = min(floor(u), R-2),
@@ -410,17 +432,35 @@ int fhash_occupancy_grid(const uint64_t* bits, const int64_t dims[4], uint64_t* 
 int fhash_coreset(const uint64_t* bits, const int64_t dims[4], uint64_t* ids, int64_t capacity,
                   void* ws, size_t* ws_bytes, int64_t* count, void* stream);
 
+/* fhash_coreset_frames: the coreset of the listed frames only (key-frame
+ * training, Sec. 3.1 and 3.2.2): frames (HOST int32[n_frames], strictly
+ * increasing, each in [0, T)); ids as fhash_coreset (linear voxel ids of the
+ * whole volume, increasing).  *count (host) = their number; when ids != NULL
+ * and the count exceeds capacity, ids holds those of the leading frames that
+ * fit.  Synchronises `stream` once per frame.  ws: device workspace (query
+ * with ws == NULL). */
+int fhash_coreset_frames(const uint64_t* bits, const int64_t dims[4], const int32_t* frames,
+                         int32_t n_frames, uint64_t* ids, int64_t capacity, void* ws,
+                         size_t* ws_bytes, int64_t* count, void* stream);
+
 /* -------------------------------------------------------------- sampler ----
  * Training batch from the coreset (Sec. 3.1, time-step concatenation): draw i
  * of step `step` is voxel id floor(r * M / 2^64), r the 64-bit word out1:out0
  * of Philox4x32-10 with counter (i, step) and key seed; the voxel is
  * coreset[id] (device uint64 linear voxel ids) or id itself when coreset is
- * NULL.  pos = (i/(Sx-1), j/(Sy-1), k/(Sz-1), n/(T-1)) in FP32 (IEEE
- * division), target = field[voxel] (device float [T][Sz][Sy][Sx]).
+ * NULL.  pos = (i/(Sx-1), j/(Sy-1), k/(Sz-1), tau(n)) in FP32 (IEEE
+ * division), target = field[voxel] (device float [T][Sz][Sy][Sx]); tau(n) =
+ * n/(T-1), or frame_t[n] when frame_t (device float [T]) is given: the time
+ * coordinate of each frame under key-frame training (Sec. 3.2.2), see
+ * fhash_key_frame_times.  box (HOST int32[6] = xmin, ymin, zmin, xmax, ymax,
+ * zmax, inclusive voxel bounds with min < max < S, e.g. the FBB row of
+ * fhash_feature_boxes; or NULL): the spatial coordinates become those of the
+ * box, ((i - xmin)/(xmax - xmin), ...) (Sec. 3.1, position translation and
+ * scaling to the FBB, on [0,1]); every drawn voxel must lie in the box.
  * dims = (Sx, Sy, Sz, T). */
 int fhash_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset, uint64_t M,
-                 const int64_t dims[4], const float* field, float* pos, float* target,
-                 void* stream);
+                 const int64_t dims[4], const float* field, const float* frame_t,
+                 const int32_t* box, float* pos, float* target, void* stream);
 
 /* Reorder a batch of samples (pos float4[n], target float[n] or NULL, both
  * device, in place) by a 4D Morton key of the positions quantised to 256
@@ -487,6 +527,10 @@ typedef struct {
   int64_t iterations, samples;
   void* ws;
   int64_t dims[4];
+  float t01;         /* the model's time coordinate of the samples; begin sets
+                        t / (T - 1); a model trained on key frames takes its
+                        frame time (fhash_key_frame_times, interpolated at t),
+                        set by the caller before the first march */
 } fhash_render_state;
 
 /* Device workspace of one request's ray state (W*H rays + occupancy bits).

@@ -103,8 +103,8 @@ def _declare(L):
     L.or_occupied.restype = C.c_int
     L.or_occupied.argtypes = [P, P, P, C.c_float]
     L.or_render.restype = I64
-    L.or_render.argtypes = [P, P, C.c_int, P, P, P, P, P, C.c_float, P, C.c_int, C.c_int,
-                            C.c_float, C.c_float, C.c_int, P, P, P]
+    L.or_render.argtypes = [P, P, C.c_int, P, P, P, P, P, C.c_float, C.c_float, P, C.c_int,
+                            C.c_int, C.c_float, C.c_float, C.c_int, P, P, P]
     L.or_sample_batch.restype = None
     L.or_sample_batch.argtypes = [U64, U64, I64, P, U64, P, P, P, P]
 
@@ -389,12 +389,64 @@ def sample_batch(seed, step, n, field, coreset=None):
 
 
 
+# --------------------------------------------------------------------------- key frames
+def key_frame_times(T: int, frames) -> np.ndarray:
+    """Time coordinate of every frame of a model trained on key frames (Sec.
+    3.2.2: the temporal resolution of the finest level is the number of key
+    frames, so key frame k is vertex k of that level, at k / (n_kf - 1)).
+    Reading for the frames between key frames: linear in the frame index
+    between the two neighbouring key frames; before the first key frame 0,
+    after the last 1.  Exact rationals, rounded once to FP32."""
+    from fractions import Fraction
+    fr = [int(x) for x in frames]
+    K = len(fr)
+    out = np.zeros(int(T), np.float32)
+    for n in range(int(T)):
+        if n <= fr[0]:
+            tau = Fraction(0)
+        elif n >= fr[-1]:
+            tau = Fraction(1)
+        else:
+            k = max(i for i in range(K) if fr[i] <= n)
+            tau = (k + Fraction(n - fr[k], fr[k + 1] - fr[k])) / (K - 1)
+        out[n] = np.float32(float(tau))  # the double nearest the rational, then to FP32
+    return out
+
+
+def sample_batch_frames(seed, step, n, field, coreset, frame_t=None, box=None):
+    """The training batch of or_sample_batch with the time coordinate of frame
+    t taken from frame_t[t] (key-frame training), and the spatial coordinates
+    those of the box (xmin, ymin, zmin, xmax, ymax, zmax) when given (Sec. 3.1,
+    position translation and scaling to the FBB, on [0,1]).  FP32 IEEE
+    division, as or_voxel_positions."""
+    f = _c(field, np.float32)
+    T, Sz, Sy, Sx = f.shape
+    cs = _c(coreset, np.uint64) if coreset is not None else None
+    M = int(cs.shape[0]) if cs is not None else int(f.size)
+    ids = sample_ids(seed, step, n, M)
+    lin = cs[ids.astype(np.int64)] if cs is not None else ids
+    lin = lin.astype(np.int64)
+    t, z, y, x = np.unravel_index(lin, (T, Sz, Sy, Sx))
+    lo = np.zeros(3, np.int64) if box is None else np.asarray(box[:3], np.int64)
+    ext = (np.array([Sx, Sy, Sz]) - 1) if box is None else (np.asarray(box[3:], np.int64) - lo)
+    pos = np.zeros((n, 4), np.float32)
+    for d, c in enumerate((x, y, z)):
+        pos[:, d] = (c - lo[d]).astype(np.float32) / np.float32(ext[d])
+    if frame_t is None:
+        pos[:, 3] = t.astype(np.float32) / np.float32(T - 1)
+    else:
+        pos[:, 3] = np.asarray(frame_t, np.float32)[t]
+    return pos, f.ravel()[lin]
+
+
 # --------------------------------------------------------------------------- render
 def render(grid: Grid, table, width, params, mask, view14, t, tf, W, H, ds=0.5,
-           alpha_stop=0.99, max_steps=1 << 20, pixel_stats=False):
+           alpha_stop=0.99, max_steps=1 << 20, pixel_stats=False, t01=None):
     """Oracle image [H][W][4] (FP64), ambiguity flags [H][W], evaluated samples;
     with pixel_stats also [H][W][3]: composited samples, sum of their output
-    magnitudes, smallest |A - alpha_stop| over the composited steps."""
+    magnitudes, smallest |A - alpha_stop| over the composited steps.  t01: the
+    model's time coordinate of the samples (default t / (T - 1); a model
+    trained on key frames takes its frame time)."""
     tab = _c(table, np.float64)
     w = _c(width, np.int32)
     prm = _c(params, np.float64)
@@ -406,8 +458,9 @@ def render(grid: Grid, table, width, params, mask, view14, t, tf, W, H, ds=0.5,
     amb = np.zeros((H, W), np.uint8)
     pix = np.zeros((H, W, 3), np.float64)
     ev = lib().or_render(grid.ref(), _p(tab), len(w) - 1, _p(w), _p(prm), _p(m), _p(S), _p(cam),
-                         C.c_float(t), _p(tfa), W, H, C.c_float(ds), C.c_float(alpha_stop),
-                         max_steps, _p(rgba), _p(amb), _p(pix))
+                         C.c_float(t), C.c_float(-1.0 if t01 is None else t01), _p(tfa), W, H,
+                         C.c_float(ds), C.c_float(alpha_stop), max_steps, _p(rgba), _p(amb),
+                         _p(pix))
     if pixel_stats:
         return rgba, amb.astype(bool), int(ev), pix
     return rgba, amb.astype(bool), int(ev)

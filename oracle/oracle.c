@@ -732,12 +732,12 @@ static void apply_tf(const float* tf, double v, double rgba[4]) {
  * Returns the number of evaluated samples. */
 int64_t or_render(const or_grid* g, const double* table, int n_layers, const int32_t* width,
                   const double* params, const uint8_t* mask, const int64_t S[4], const float* cam,
-                  float t, const float* tf, int W, int H, float ds, float alpha_stop,
+                  float t, float t01, const float* tf, int W, int H, float ds, float alpha_stop,
                   int max_steps, double* rgba, uint8_t* amb, double* pix) {
   int64_t evals = 0;
   const int L = g->n_levels, F = g->n_features;
   double* enc = (double*)malloc(sizeof(double) * L * F * 2);
-  const float tn = t / (float)(S[3] - 1);
+  const float tn = t01 >= 0.0f ? t01 : t / (float)(S[3] - 1);
   for (int py = 0; py < H; ++py)
     for (int px = 0; px < W; ++px) {
       double C[3] = {0, 0, 0}, A = 0.0;

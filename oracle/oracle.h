@@ -91,7 +91,7 @@ void or_sample_batch(uint64_t seed, uint64_t step, int64_t n, const uint64_t* co
 int or_occupied(const uint8_t* mask, const int64_t S[4], const float p[3], float t);
 int64_t or_render(const or_grid* g, const double* table, int n_layers, const int32_t* width,
                   const double* params, const uint8_t* mask, const int64_t S[4], const float* cam,
-                  float t, const float* tf, int W, int H, float ds, float alpha_stop,
+                  float t, float t01, const float* tf, int W, int H, float ds, float alpha_stop,
                   int max_steps, double* rgba, uint8_t* amb, double* pix);
 
 #ifdef __cplusplus

@@ -67,7 +67,8 @@ class RenderOpts(C.Structure):
 class RenderState(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("t", C.c_float), ("cur", C.c_int32),
                 ("n_alive", C.c_int32), ("pending", C.c_int32), ("iterations", C.c_int64),
-                ("samples", C.c_int64), ("ws", C.c_void_p), ("dims", C.c_int64 * 4)]
+                ("samples", C.c_int64), ("ws", C.c_void_p), ("dims", C.c_int64 * 4),
+                ("t01", C.c_float)]
 
 
 class RenderStats(C.Structure):
@@ -166,7 +167,10 @@ def _declare(L):
         "fhash_lazy_flush": (C.c_int, [P, P, P, P, P, P, C.c_int, P]),
         "fhash_check_finite": (C.c_int, [P, I64, P, P]),
         "fhash_cast": (C.c_int, [P, P, C.c_int, I64, P]),
-        "fhash_sample": (C.c_int, [U64, U64, I64, P, U64, P, P, P, P, P]),
+        "fhash_sample": (C.c_int, [U64, U64, I64, P, U64, P, P, P, P, P, P, P]),
+        "fhash_coreset_frames": (C.c_int, [P, P, P, I32, P, I64, P, P, P, P]),
+        "fhash_fold_resolutions": (C.c_int, [P, I32, P, P]),
+        "fhash_key_frame_times": (C.c_int, [I64, P, I32, P]),
         "fhash_sq_err_sum": (C.c_int, [P, P, I64, P, P]),
         "fhash_mse_grad": (C.c_int, [P, P, I64, F, P, P, P]),
         "fhash_sort_samples": (C.c_int, [P, P, I64, P, P, P]),
@@ -436,10 +440,53 @@ def fhash_cast(src, dst):
     _check(lib().fhash_cast(_ptr(src), _ptr(dst), _dt(dst), src.numel(), _stream()), "fhash_cast")
 
 
-def fhash_sample(seed, step, n, coreset, M, dims, field, pos, target):
+def fhash_sample(seed, step, n, coreset, M, dims, field, pos, target, frame_t=None, box=None):
+    """frame_t: device float [T] frame times (key-frame training) or None;
+    box: 6 ints (inclusive voxel bounds of the spatial frame) or None."""
     d = (C.c_int64 * 4)(*[int(x) for x in dims])
-    _check(lib().fhash_sample(seed, step, n, _ptr(coreset), M, d, _ptr(field), _ptr(pos),
-                              _ptr(target), _stream()), "fhash_sample")
+    b = None if box is None else (C.c_int32 * 6)(*[int(x) for x in box])
+    _check(lib().fhash_sample(seed, step, n, _ptr(coreset), M, d, _ptr(field), _ptr(frame_t),
+                              b, _ptr(pos), _ptr(target), _stream()), "fhash_sample")
+
+
+def fhash_coreset_frames(bits, dims, frames, ws=None):
+    """Coreset ids (int64 view of uint64, increasing) of the listed frames
+    only.  Synchronises."""
+    L = lib()
+    d = _dims(dims)
+    fr = (C.c_int32 * max(1, len(frames)))(*[int(x) for x in frames])
+    nb = C.c_size_t(0)
+    cnt = C.c_int64(0)
+    _check(L.fhash_coreset_frames(_ptr(bits), d, fr, len(frames), None, 0, None, C.byref(nb),
+                                  C.byref(cnt), None), "fhash_coreset_frames")
+    if ws is None or ws.numel() < nb.value:
+        ws = torch.empty(max(int(nb.value), 16), dtype=torch.uint8, device=bits.device)
+    nb = C.c_size_t(ws.numel())
+    _check(L.fhash_coreset_frames(_ptr(bits), d, fr, len(frames), None, 0, _ptr(ws), C.byref(nb),
+                                  C.byref(cnt), _stream()), "fhash_coreset_frames")
+    ids = torch.empty(max(cnt.value, 1), dtype=torch.int64, device=bits.device)
+    _check(L.fhash_coreset_frames(_ptr(bits), d, fr, len(frames), _ptr(ids), cnt.value, _ptr(ws),
+                                  C.byref(nb), C.byref(cnt), _stream()), "fhash_coreset_frames")
+    return ids[:cnt.value]
+
+
+def fhash_fold_resolutions(size, fold):
+    """Level resolutions (list of [x, y, z, t], coarsest first) by the fold policy."""
+    s = (C.c_int64 * 4)(*[int(x) for x in size])
+    res = (C.c_int32 * (4 * MAX_LEVELS))()
+    L = C.c_int32(0)
+    _check(lib().fhash_fold_resolutions(s, fold, res, C.byref(L)), "fhash_fold_resolutions")
+    return [[res[4 * l + d] for d in range(4)] for l in range(L.value)]
+
+
+def fhash_key_frame_times(T, frames):
+    """FP32 time coordinate of every frame (numpy float32 [T]) under key-frame training."""
+    import numpy as np
+    fr = (C.c_int32 * len(frames))(*[int(x) for x in frames])
+    out = np.zeros(int(T), np.float32)
+    _check(lib().fhash_key_frame_times(int(T), fr, len(frames), out.ctypes.data_as(C.c_void_p)),
+           "fhash_key_frame_times")
+    return out
 
 
 FEATURE_INTERVAL, FEATURE_ISOSURFACE = 0, 1

@@ -630,8 +630,8 @@ int fhash_cast(const float* src, void* dst, fhash_dtype dst_dt, int64_t n, void*
 }
 
 int fhash_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset, uint64_t M,
-                 const int64_t dims[4], const float* field, float* pos, float* target,
-                 void* stream) {
+                 const int64_t dims[4], const float* field, const float* frame_t,
+                 const int32_t* box, float* pos, float* target, void* stream) {
   if (n < 0 || dims == nullptr) return fail(FHASH_EINVAL, "bad arguments");
   for (int d = 0; d < 4; ++d)
     if (dims[d] < 2 || dims[d] > (1 << 24))
@@ -644,9 +644,14 @@ int fhash_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* corese
   if (field == nullptr || pos == nullptr || target == nullptr)
     return fail(FHASH_EINVAL, "NULL pointer");
   if (!aligned16(pos)) return fail(FHASH_EINVAL, "pos not 16-byte aligned");
-  return hip_status(
-      fh::launch_sample(seed, step, n, coreset, M, dims, field, pos, target, S(stream)),
-      "fhash_sample");
+  if (box != nullptr)
+    for (int d = 0; d < 3; ++d)
+      if (box[d] < 0 || box[d + 3] <= box[d] || box[d + 3] >= dims[d])
+        return fail(FHASH_EINVAL, "box axis %d [%d, %d] not inside [0, %lld) with two voxels",
+                    d, box[d], box[d + 3], (long long)dims[d]);
+  return hip_status(fh::launch_sample(seed, step, n, coreset, M, dims, field, frame_t, box, pos,
+                                      target, S(stream)),
+                    "fhash_sample");
 }
 
 int fhash_sort_samples(float* pos, float* target, int64_t n, void* ws, size_t* ws_bytes,
@@ -714,6 +719,7 @@ int fhash_render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
   state->W = W;
   state->H = H;
   state->t = t;
+  state->t01 = t / (float)(dims[3] - 1);
   state->ws = ws;
   for (int d = 0; d < 4; ++d) state->dims[d] = dims[d];
   int32_t na = 0;
@@ -747,7 +753,7 @@ int fhash_render_march(fhash_render_state* state, const fhash_render_opts* opts,
   if (state->n_alive > 0 && (pos_out == nullptr || !aligned16(pos_out)))
     return fail(FHASH_EINVAL, "pos_out NULL or not 16-byte aligned");
   int32_t ns = 0;
-  hipError_t e = fh::launch_render_march(state->ws, state->W, state->H, state->dims, state->t,
+  hipError_t e = fh::launch_render_march(state->ws, state->W, state->H, state->dims, state->t01,
                                          opts->ds, opts->max_steps, pace, state->cur,
                                          state->n_alive, pos_out, &ns, S(stream));
   if (e != hipSuccess) return hip_status(e, "fhash_render_march");
@@ -844,6 +850,12 @@ static int check_mask_dims(const int64_t dims[4]) {
   return FHASH_OK;
 }
 
+// Byte ranges [a, a + na) and [b, b + nb) share a byte.
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return na > 0 && nb > 0 && pa < pb + nb && pb < pa + na;
+}
+
 int fhash_feature_mask(const float* field, const int64_t dims[4], int32_t kind, float lo,
                        float hi, uint64_t* bits, void* ws, size_t* ws_bytes, void* stream) {
   if (int rc = check_mask_dims(dims)) return rc;
@@ -859,7 +871,12 @@ int fhash_feature_mask(const float* field, const int64_t dims[4], int32_t kind, 
     if (int rc = ws_check(ws, ws_bytes, need, &query)) return rc;
   }
   if (field == nullptr || bits == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
-  if (kind == FHASH_FEATURE_ISOSURFACE && (ws == bits || ws == field))
+  const size_t mask_bytes = (size_t)fh::mask_words(dims) * 8;
+  const size_t field_bytes = (size_t)dims[0] * dims[1] * dims[2] * dims[3] * sizeof(float);
+  if (ranges_overlap(bits, mask_bytes, field, field_bytes))
+    return fail(FHASH_EINVAL, "bits overlap the field");
+  if (kind == FHASH_FEATURE_ISOSURFACE &&
+      (ranges_overlap(ws, need, bits, mask_bytes) || ranges_overlap(ws, need, field, field_bytes)))
     return fail(FHASH_EINVAL, "workspace overlaps an argument");
   return hip_status(fh::launch_feature_mask(field, dims, kind, lo, hi, bits, ws, S(stream)),
                     "fhash_feature_mask");
@@ -903,8 +920,100 @@ int fhash_coreset(const uint64_t* bits, const int64_t dims[4], uint64_t* ids, in
   if (query) return FHASH_OK;
   if (bits == nullptr || count == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
   if (ids != nullptr && capacity < 0) return fail(FHASH_EINVAL, "negative capacity");
+  const size_t mask_bytes = (size_t)fh::mask_words(dims) * 8;
+  if (ranges_overlap(ws, fh::coreset_ws_bytes(dims), bits, mask_bytes))
+    return fail(FHASH_EINVAL, "workspace overlaps the mask");
+  if (ids != nullptr && (ranges_overlap(ids, (size_t)capacity * 8, bits, mask_bytes) ||
+                         ranges_overlap(ids, (size_t)capacity * 8, ws,
+                                        fh::coreset_ws_bytes(dims))))
+    return fail(FHASH_EINVAL, "ids overlap the mask or the workspace");
   return hip_status(fh::launch_coreset(bits, dims, ws, ids, capacity, count, S(stream)),
                     "fhash_coreset");
+}
+
+int fhash_coreset_frames(const uint64_t* bits, const int64_t dims[4], const int32_t* frames,
+                         int32_t n_frames, uint64_t* ids, int64_t capacity, void* ws,
+                         size_t* ws_bytes, int64_t* count, void* stream) {
+  if (int rc = check_mask_dims(dims)) return rc;
+  bool query;
+  if (int rc = ws_check(ws, ws_bytes, fh::coreset_frames_ws_bytes(dims), &query)) return rc;
+  if (query) return FHASH_OK;
+  if (bits == nullptr || count == nullptr) return fail(FHASH_EINVAL, "NULL pointer");
+  if (n_frames < 0 || (n_frames > 0 && frames == nullptr))
+    return fail(FHASH_EINVAL, "bad frame list");
+  for (int32_t k = 0; k < n_frames; ++k) {
+    if (frames[k] < 0 || frames[k] >= dims[3])
+      return fail(FHASH_EINVAL, "frame %d outside [0, %lld)", frames[k], (long long)dims[3]);
+    if (k > 0 && frames[k] <= frames[k - 1])
+      return fail(FHASH_EINVAL, "frames must be strictly increasing");
+  }
+  if (ids != nullptr && capacity < 0) return fail(FHASH_EINVAL, "negative capacity");
+  const size_t mask_bytes = (size_t)fh::mask_words(dims) * 8;
+  const size_t ws_need = fh::coreset_frames_ws_bytes(dims);
+  if (ranges_overlap(ws, ws_need, bits, mask_bytes))
+    return fail(FHASH_EINVAL, "workspace overlaps the mask");
+  if (ids != nullptr && (ranges_overlap(ids, (size_t)capacity * 8, bits, mask_bytes) ||
+                         ranges_overlap(ids, (size_t)capacity * 8, ws, ws_need)))
+    return fail(FHASH_EINVAL, "ids overlap the mask or the workspace");
+  return hip_status(fh::launch_coreset_frames(bits, dims, frames, n_frames, ws, ids, capacity,
+                                              count, S(stream)),
+                    "fhash_coreset_frames");
+}
+
+int fhash_fold_resolutions(const int64_t size[4], int32_t fold, int32_t* res,
+                           int32_t* n_levels) {
+  if (size == nullptr || res == nullptr || n_levels == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (fold < 2) return fail(FHASH_EINVAL, "fold %d < 2", fold);
+  // levels of each dimension: the smallest L with fold^L >= S (exact integers)
+  int32_t L = 0;
+  for (int d = 0; d < 4; ++d) {
+    if (size[d] < 2 || size[d] > (1 << 24))
+      return fail(FHASH_EINVAL, "size[%d] = %lld outside [2, 2^24]", d, (long long)size[d]);
+    int32_t Ld = 0;
+    for (int64_t p = 1; p < size[d]; p *= fold) ++Ld;
+    if (Ld > L) L = Ld;
+  }
+  if (L > FHASH_MAX_LEVELS)
+    return fail(FHASH_ERANGE, "%d levels exceed FHASH_MAX_LEVELS", L);
+  // paper level 1 (finest) = the native size; each coarser level divides by the
+  // fold (rounding up) while above it, else the tail resolution 2.  Stored
+  // coarsest first: row L - 1 is the native size.
+  for (int d = 0; d < 4; ++d) {
+    int64_t r = size[d];
+    for (int32_t l = 0; l < L; ++l) {
+      res[(L - 1 - l) * 4 + d] = (int32_t)r;
+      r = (r > fold) ? (r + fold - 1) / fold : 2;
+    }
+  }
+  *n_levels = L;
+  return FHASH_OK;
+}
+
+int fhash_key_frame_times(int64_t T, const int32_t* frames, int32_t n_frames, float* frame_t) {
+  if (T < 2 || frames == nullptr || frame_t == nullptr || n_frames < 2)
+    return fail(FHASH_EINVAL, "need T >= 2 and at least two key frames");
+  for (int32_t k = 0; k < n_frames; ++k) {
+    if (frames[k] < 0 || frames[k] >= T)
+      return fail(FHASH_EINVAL, "key frame %d outside [0, %lld)", frames[k], (long long)T);
+    if (k > 0 && frames[k] <= frames[k - 1])
+      return fail(FHASH_EINVAL, "key frames must be strictly increasing");
+  }
+  const double last = (double)(n_frames - 1);
+  int32_t k = 0;
+  for (int64_t n = 0; n < T; ++n) {
+    double tau;
+    if (n <= frames[0]) {
+      tau = 0.0;
+    } else if (n >= frames[n_frames - 1]) {
+      tau = 1.0;
+    } else {
+      while (frames[k + 1] <= n) ++k;
+      tau = ((double)k + (double)(n - frames[k]) / (double)(frames[k + 1] - frames[k])) / last;
+    }
+    frame_t[n] = (float)tau;
+  }
+  return FHASH_OK;
 }
 
 }  // extern "C"

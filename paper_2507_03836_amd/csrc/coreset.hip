@@ -269,7 +269,8 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // Per-frame bounding boxes: one workgroup per (t, z) slice reduces its words
-// and issues at most 12 atomics (frame row t and the fused row T).
+// and issues at most 6 atomics, all to frame row t (the fused row T is formed
+// afterwards by fuse_boxes_kernel).
 __global__ void __launch_bounds__(kBlock)
     box_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t Sy, int64_t Sz, int64_t W,
                int64_t T, int32_t* __restrict__ box) {
@@ -427,7 +428,8 @@ __global__ void __launch_bounds__(1024) chunk_scan_kernel(int64_t* chunk, int64_
 // writes up to 64 consecutive ids.
 __global__ void __launch_bounds__(kBlock)
     chunk_emit_kernel(const uint64_t* __restrict__ bits, int64_t Sx, int64_t W, int64_t n_words,
-                      const int64_t* __restrict__ chunk, uint64_t* __restrict__ ids) {
+                      const int64_t* __restrict__ chunk, uint64_t* __restrict__ ids,
+                      int64_t id_base) {
   constexpr int kWaves = kBlock / 64;
   constexpr int64_t kPerWave = kChunk / kWaves;  // 1024 words, 16 groups of 64
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -451,7 +453,7 @@ __global__ void __launch_bounds__(kBlock)
     if (q < n_words) {
       const int64_t row = q / W, w = q - row * W;
       b = bits[q] & valid_bits(Sx, w);
-      id0 = row * Sx + 64 * w;
+      id0 = id_base + row * Sx + 64 * w;
     }
     const int pc = __popcll(b);
     int incl = pc;  // inclusive scan of the counts over the lanes
@@ -570,8 +572,49 @@ hipError_t launch_coreset(const uint64_t* bits, const int64_t* dims, void* ws, u
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
   if (ids == nullptr || *count > capacity) return hipSuccess;
-  chunk_emit_kernel<<<(unsigned)chunks, kBlock, 0, st>>>(bits, dims[0], W, n, chunk, ids);
+  chunk_emit_kernel<<<(unsigned)chunks, kBlock, 0, st>>>(bits, dims[0], W, n, chunk, ids, 0);
   return hipGetLastError();
+}
+
+// Coreset of a subset of the frames (key-frame training, Sec. 3.2.2): the
+// count / scan / emit passes of launch_coreset run on each listed frame's
+// mask words, the ids of a frame offset by its first voxel id and written
+// after those of the frames before it.  Frames must be increasing.
+size_t coreset_frames_ws_bytes(const int64_t* dims) {
+  const int64_t frame_words = dims[2] * dims[1] * ((dims[0] + 63) / 64);
+  return (size_t)((frame_words + kChunk - 1) / kChunk + 1) * sizeof(int64_t);
+}
+
+hipError_t launch_coreset_frames(const uint64_t* bits, const int64_t* dims, const int32_t* frames,
+                                 int32_t n_frames, void* ws, uint64_t* ids, int64_t capacity,
+                                 int64_t* count, hipStream_t st) {
+  const int64_t W = (dims[0] + 63) / 64, fw = dims[2] * dims[1] * W;
+  const int64_t fvox = dims[0] * dims[1] * dims[2];
+  const int64_t chunks = (fw + kChunk - 1) / kChunk;
+  if (chunks > 0x7fffffffLL) return hipErrorInvalidValue;
+  int64_t* chunk = static_cast<int64_t*>(ws);
+  int64_t total = 0;
+  for (int32_t k = 0; k < n_frames; ++k) {
+    const uint64_t* fb = bits + (int64_t)frames[k] * fw;
+    chunk_count_kernel<<<(unsigned)chunks, kBlock, 0, st>>>(fb, dims[0], W, fw, chunk);
+    chunk_scan_kernel<<<1, 1024, 0, st>>>(chunk, chunks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t c = 0;
+    e = hipMemcpyAsync(&c, chunk + chunks, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    if (ids != nullptr && total + c <= capacity) {
+      chunk_emit_kernel<<<(unsigned)chunks, kBlock, 0, st>>>(fb, dims[0], W, fw, chunk,
+                                                             ids + total, frames[k] * fvox);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    total += c;
+  }
+  *count = total;
+  return hipSuccess;
 }
 
 }  // namespace fh

@@ -90,8 +90,9 @@ hipError_t launch_lazy_flush(const fhash_lazy* lz, float* p, float* gr, float* m
 
 // sampler.hip
 hipError_t launch_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset,
-                         uint64_t M, const int64_t* dims, const float* field, float* pos,
-                         float* target, hipStream_t st);
+                         uint64_t M, const int64_t* dims, const float* field,
+                         const float* frame_t, const int32_t* box, float* pos, float* target,
+                         hipStream_t st);
 
 // sort.hip
 size_t sort_ws_bytes(int64_t n);
@@ -102,7 +103,7 @@ size_t render_ws_bytes(int64_t NR, const int64_t* dims);
 hipError_t launch_render_begin(const fhash_view* v, int W, int H, const uint64_t* mask,
                                const int64_t* dims, float t, void* ws, int32_t* n_alive_host,
                                float* rgba, hipStream_t st);
-hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, float t, float ds,
+hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, float t01, float ds,
                                int32_t max_steps, int32_t pace, int cur, int32_t n_alive,
                                float* pos_out, int32_t* n_samples_host, hipStream_t st);
 hipError_t launch_render_composite(void* ws, int W, int H, int cur, int32_t n_alive,
@@ -122,6 +123,10 @@ int64_t occupancy_words(const int64_t* dims);
 hipError_t launch_occupancy_morton(const uint64_t* bits, const int64_t* dims, uint64_t* occ,
                                    hipStream_t st);
 size_t coreset_ws_bytes(const int64_t* dims);
+size_t coreset_frames_ws_bytes(const int64_t* dims);
+hipError_t launch_coreset_frames(const uint64_t* bits, const int64_t* dims, const int32_t* frames,
+                                 int32_t n_frames, void* ws, uint64_t* ids, int64_t capacity,
+                                 int64_t* count, hipStream_t st);
 hipError_t launch_coreset(const uint64_t* bits, const int64_t* dims, void* ws, uint64_t* ids,
                           int64_t capacity, int64_t* count, hipStream_t st);
 

@@ -324,7 +324,7 @@ hipError_t launch_render_begin(const fhash_view* v, int W, int H, const uint64_t
   return hipStreamSynchronize(st);
 }
 
-hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, float t, float ds,
+hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, float t01, float ds,
                                int32_t max_steps, int32_t pace, int cur, int32_t n_alive,
                                float* pos_out, int32_t* n_samples_host, hipStream_t st) {
   const int64_t NR = (int64_t)W * H;
@@ -338,7 +338,7 @@ hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, floa
   a.fx = (float)(dims[0] - 1);
   a.fy = (float)(dims[1] - 1);
   a.fz = (float)(dims[2] - 1);
-  a.tn = t / (float)(dims[3] - 1);
+  a.tn = t01;
   a.ds = ds;
   a.max_steps = max_steps;
   a.pace = pace;

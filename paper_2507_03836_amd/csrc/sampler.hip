@@ -1,5 +1,9 @@
 // Training sampler: Philox4x32-10 counter-based draws -> coreset voxel -> FP32
-// position and label (Sec. 3.1, time-step concatenation).
+// position and label (Sec. 3.1, time-step concatenation).  The time coordinate
+// of a frame is n / (T - 1), or frame_t[n] when the caller gives a frame-time
+// table (key-frame training, Sec. 3.2.2).  The spatial coordinates are those of
+// the whole volume, or of the feature bounding box (Sec. 3.1, position
+// translation and scaling) when the caller gives one.
 #include "common.h"
 #include "kernels.h"
 
@@ -24,7 +28,8 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint2 k) {
 __global__ void __launch_bounds__(256)
     sample_kernel(uint64_t seed, uint64_t step, int64_t n, const uint64_t* __restrict__ coreset,
                   uint64_t M, int64_t Sx, int64_t Sy, int64_t Sz, int64_t St,
-                  const float* __restrict__ field, float4* __restrict__ pos,
+                  const float* __restrict__ field, const float* __restrict__ frame_t,
+                  int4 box_lo, int4 box_ext, float4* __restrict__ pos,
                   float* __restrict__ target) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -39,10 +44,10 @@ __global__ void __launch_bounds__(256)
     const uint64_t z = (lin / ((uint64_t)Sx * Sy)) % (uint64_t)Sz;
     const uint64_t t = lin / ((uint64_t)Sx * Sy * Sz);
     float4 p;
-    p.x = __fdiv_rn((float)x, (float)(Sx - 1));
-    p.y = __fdiv_rn((float)y, (float)(Sy - 1));
-    p.z = __fdiv_rn((float)z, (float)(Sz - 1));
-    p.w = __fdiv_rn((float)t, (float)(St - 1));
+    p.x = __fdiv_rn((float)((int64_t)x - box_lo.x), (float)box_ext.x);
+    p.y = __fdiv_rn((float)((int64_t)y - box_lo.y), (float)box_ext.y);
+    p.z = __fdiv_rn((float)((int64_t)z - box_lo.z), (float)box_ext.z);
+    p.w = frame_t ? frame_t[t] : __fdiv_rn((float)t, (float)(St - 1));
     pos[i] = p;
     target[i] = field[lin];
   }
@@ -51,14 +56,22 @@ __global__ void __launch_bounds__(256)
 }  // namespace
 
 hipError_t launch_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* coreset,
-                         uint64_t M, const int64_t* dims, const float* field, float* pos,
-                         float* target, hipStream_t st) {
+                         uint64_t M, const int64_t* dims, const float* field,
+                         const float* frame_t, const int32_t* box, float* pos, float* target,
+                         hipStream_t st) {
   if (n == 0) return hipSuccess;
+  // spatial frame: the whole volume [0, S - 1], or the box [lo, hi] (inclusive)
+  int4 lo = make_int4(0, 0, 0, 0);
+  int4 ext = make_int4((int)(dims[0] - 1), (int)(dims[1] - 1), (int)(dims[2] - 1), 0);
+  if (box != nullptr) {
+    lo = make_int4(box[0], box[1], box[2], 0);
+    ext = make_int4(box[3] - box[0], box[4] - box[1], box[5] - box[2], 0);
+  }
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
   hipLaunchKernelGGL(sample_kernel, dim3((unsigned)b), dim3(256), 0, st, seed, step, n, coreset, M,
-                     dims[0], dims[1], dims[2], dims[3], field, reinterpret_cast<float4*>(pos),
-                     target);
+                     dims[0], dims[1], dims[2], dims[3], field, frame_t, lo, ext,
+                     reinterpret_cast<float4*>(pos), target);
   return hipGetLastError();
 }
 
