@@ -261,6 +261,26 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
                       float* d_params, double* loss_sum, uint32_t flags, const fhash_touch* touch,
                       void* ws, size_t* ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving and training loops, harnesses that forbid
+ * hipMalloc): fhash_fused_train with no workspace argument.  The decoder-
+ * gradient partials go to a scratch array owned by the library, one copy per
+ * GPU (FHASH_STATIC_SCRATCH_BYTES = 10,813,440 bytes, held until the process
+ * ends); its device address is resolved on the first call on each device, and
+ * the call allocates nothing.  Every partial the reduction reads is written by
+ * the same call, so nothing has to start at zero.  All calls on one GPU share
+ * the array: calls that overlap on one GPU (different streams, or threads
+ * without ordering) race and give wrong d_params.  Otherwise the arguments,
+ * results and errors are those of fhash_fused_train; FHASH_ENOMEM if the
+ * partials of a launch would exceed the array (never for the decoders the
+ * fused path is built for). */
+#define FHASH_STATIC_SCRATCH_BYTES 10813440
+int fhash_fused_train_static(const fhash_index* idx, const fhash_mlp_desc* mlp,
+                             const float* pos, const float* target, int64_t n, const void* table,
+                             fhash_dtype table_dt, const float* params, const void* shadow,
+                             float loss_scale, float* d_table, float* d_params, double* loss_sum,
+                             uint32_t flags, const fhash_touch* touch, void* stream);
+
 /* ------------------------------------------------------------ optimiser ----
  * Adam (Sec. 5.1.3: Adam, lr 0.01; PyTorch semantics, bias-corrected, no
  * weight decay), applied densely to every parameter:

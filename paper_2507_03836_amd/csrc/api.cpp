@@ -447,6 +447,36 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
                     "fhash_fused_train");
 }
 
+int fhash_fused_train_static(const fhash_index* idx, const fhash_mlp_desc* mlp,
+                             const float* pos, const float* target, int64_t n, const void* table,
+                             fhash_dtype table_dt, const float* params, const void* shadow,
+                             float loss_scale, float* d_table, float* d_params, double* loss_sum,
+                             uint32_t flags, const fhash_touch* touch, void* stream) {
+  (void)shadow;
+  int H, NH;
+  int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
+  if (rc) return rc;
+  if (n == 0) return FHASH_OK;
+  if (target == nullptr || d_table == nullptr || d_params == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  const int64_t P = num_params(mlp);
+  const size_t need = fh::fused_ws_bytes(n, P);
+  if (need > fh::static_scratch_bytes())
+    return fail(FHASH_ENOMEM, "decoder-gradient partials need %zu bytes, the static scratch "
+                "holds %zu", need, fh::static_scratch_bytes());
+  void* ws = nullptr;
+  hipError_t e = fh::static_scratch(&ws);
+  if (e != hipSuccess) return hip_status(e, "fhash_fused_train_static scratch");
+  fh::GridDev g;
+  fh::make_grid_dev(idx, &g);
+  g.dedup = dedup_mask(idx, n, flags);
+  if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
+  return hip_status(fh::launch_fused_train(g, H, NH, mlp->compute_dt, pos, target, n, table,
+                                           table_dt, params, loss_scale, d_table, d_params,
+                                           loss_sum, ws, P, S(stream)),
+                    "fhash_fused_train_static");
+}
+
 static int check_step(const fhash_adam_desc* opt, const float* param, const float* grad,
                       const float* m, const float* v, const void* shadow, fhash_dtype shadow_dt,
                       int64_t n) {

@@ -63,6 +63,10 @@ hipError_t launch_fused_train16(const GridDev& g, int H, int NH, fhash_dtype ddt
                                 float loss_scale, float* d_table, float* d_params,
                                 double* loss_sum, void* ws, int64_t P, hipStream_t st);
 
+// static_ws.hip: library-owned scratch for the entry points that allocate nothing
+size_t static_scratch_bytes();
+hipError_t static_scratch(void** ptr);
+
 // optim.hip
 hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
                        void* shadow, fhash_dtype sdt, int64_t n, const int32_t* found_inf,
