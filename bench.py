@@ -450,7 +450,8 @@ def serve_multi_bench(args):
             mlp = fl.mlp_desc(cfg.width, fl.F16 if args.serve_decoder == "f16" else fl.F32)
             models[name] = ResidentModel(index=model.index, mlp=mlp, table=table16,
                                          params=model.mlp_params.clone(), mask_bits=gen["bits"],
-                                         dims=dims, tf=tf, keep=(model._dir,))
+                                         dims=dims, tf=tf, keep=(model._dir,),
+                                         occ=fl.fhash_occupancy_grid(gen["bits"], dims))
             info.append({"model": name, "params": model.n_params, "probe_psnr_db": psnr,
                          "resident_bytes": models[name].nbytes()})
             del gen, pos, tgt
@@ -587,7 +588,8 @@ def serve_bench(args):
     tf = torch.from_numpy(synth.transfer_function()).cuda()
     mlp = fl.mlp_desc(cfg.width, fl.F16 if args.serve_decoder == "f16" else fl.F32)
     rm = ResidentModel(index=model.index, mlp=mlp, table=table16, params=params,
-                       mask_bits=bits, dims=dims, tf=tf, keep=(model._dir,))
+                       mask_bits=bits, dims=dims, tf=tf, keep=(model._dir,),
+                       occ=fl.fhash_occupancy_grid(bits, dims))
     C = 1 << 22
     sizes = [int(x) for x in args.serve_sizes.split(",")]
     rng = np.random.default_rng(5004)
@@ -797,7 +799,8 @@ HEADLINE_DIMS = [432, 432, 432, 60]
 # from rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) passes scaled by a
 # plain streaming copy of known size; valid only while the kernel sources
 # hashed in _fused_src_md5() are unchanged.
-FUSED_TRAFFIC = {"bytes": None, "source_md5": None}
+FUSED_TRAFFIC = {"bytes": 33215274272, "raw_bytes": 19301636096,
+                 "source_md5": "d9465911ed6e7bddcf423a61d718bb79"}
 
 
 def _fused_src_md5():
@@ -1010,7 +1013,7 @@ def _serve_sub(model, gen, dims, args, n_req):
     tf = torch.from_numpy(synth.transfer_function()).cuda()
     rm = ResidentModel(index=model.index, mlp=model.mlp, table=table16,
                        params=model.mlp_params.clone(), mask_bits=gen["bits"], dims=dims, tf=tf,
-                       keep=(model._dir,))
+                       keep=(model._dir,), occ=fl.fhash_occupancy_grid(gen["bits"], dims))
     C = 1 << 22
     rng = np.random.default_rng(5004)
     spec = []
@@ -1054,6 +1057,18 @@ def _serve_sub(model, gen, dims, args, n_req):
             "rates": rates}
 
 
+def copy_calibration():
+    """A plain streaming copy kernel of known size (4 GiB read + 4 GiB
+    written): an elementwise x*1, so that it runs as a kernel rather than a DMA
+    transfer.  Its FETCH_SIZE / WRITE_SIZE readings give the counters' scale."""
+    src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 def headline_bench(args):
     import numpy as np
 
@@ -1091,6 +1106,8 @@ def headline_bench(args):
         small.forward(pos[:4096])
         del small
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        copy_calibration()
     paths, keep = {}, None
     for prec in ("fp32", "mixed"):
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, precision=prec, lazy=True,
@@ -1218,13 +1235,7 @@ def main():
     log(f"[bench] index built in {time.time() - t0:.1f} s: {model.rows} active vertices of "
         f"{dense} ({model.rows / dense:.3f}); params {model.n_params}")
     if args.calibrate_copy:
-        # a plain streaming copy kernel of known size (4 GiB read + 4 GiB written);
-        # an elementwise x*1 so that it runs as a kernel rather than a DMA transfer
-        src = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
     B = args.batch
     pos = torch.empty(B, 4, device="cuda")
     tgt = torch.empty(B, device="cuda")
@@ -1361,6 +1372,15 @@ def main():
                          ("sampler_sort_and_other" if args.sort else "sampler_and_other"):
                          ms - fb_ms - adam_ms - prep_ms - flush_ms / args.steps},
         "optimizer": args.optimizer,
+        # deferred Adam: catch-up and mark time of single timed steps, by step number
+        "lazy_by_step": [{"step": args.warmup + k + 1,
+                          "catch_up_ms": evs[k][1].elapsed_time(evs[k][2]),
+                          "mark_ms": evs[k][0].elapsed_time(evs[k][1]),
+                          "fused_ms": evs[k][2].elapsed_time(evs[k][3])}
+                         for k in sorted({0, 1, 4, 9, 19, 49, 99, 199, 499, 999, 1499, 1999,
+                                          args.steps - 1}) if 0 <= k < args.steps]
+        if lazy else None,
+        "flush_ms": flush_ms,
         "roofline": {"kernel": roof_kernel, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": roof_bytes,

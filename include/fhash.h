@@ -563,6 +563,17 @@ int fhash_render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
                        const uint64_t* mask_bits, const int64_t dims[4], void* ws,
                        size_t ws_bytes, float* rgba, fhash_render_state* state, void* stream);
 
+/* fhash_render_begin with the occupancy grid of the coreset selection
+ * (Sec. 3.1, used by the renderer to skip empty space, Sec. 3.3): occ is the
+ * Morton-brick grid of fhash_occupancy_grid (device) over the same dims,
+ * in place of the mask rows; everything else as fhash_render_begin.  A grid
+ * made from mask_bits gives the state (and so the image) of
+ * fhash_render_begin(mask_bits) bit for bit. */
+int fhash_render_begin_grid(const fhash_view* view, float t, int32_t W, int32_t H,
+                            const uint64_t* occ, const int64_t dims[4], void* ws,
+                            size_t ws_bytes, float* rgba, fhash_render_state* state,
+                            void* stream);
+
 /* pace = clamp(floor(budget / alive), 1, arm_max) (Algorithm 1). */
 int32_t fhash_render_pace(int64_t budget, int64_t alive, int32_t arm_max);
 
@@ -578,6 +589,34 @@ int fhash_render_march(fhash_render_state* state, const fhash_render_opts* opts,
  * `stream` (updates state->n_alive). */
 int fhash_render_composite(fhash_render_state* state, const float* y, const float* tf,
                            const fhash_render_opts* opts, float* rgba, void* stream);
+
+/* Batched steps: n render requests (1 <= n <= FHASH_RENDER_BATCH_MAX) advanced
+ * by one march launch and one composite launch between them, the continuous
+ * batching of requests that share the decode (Sec. 3.3, ARM over a shared
+ * sample budget).  Each request behaves exactly as under the single-request
+ * calls with its own pace: the images are bit for bit those of
+ * fhash_render_march / fhash_render_composite.
+ *
+ * fhash_render_march_batch: states (HOST array of n distinct states, none
+ * pending), paces (HOST int32[n], each in [1, opts->arm_max]); the samples of
+ * all n requests go to pos[out_base, out_base + total) (device float4[cap]),
+ * total = sum of n_samples, with the requests' samples interleaved; the
+ * caller decodes that range (one model per call) into y with the same
+ * indexing, y[j] = decode(pos[j]).  Requires out_base + sum_r pace_r alive_r
+ * <= cap and <= 2^31 - 1 - 64 n.  counts: device int32[1 + n] (scratch, written by
+ * the call).  n_samples: HOST int64[n], per request.  Synchronises `stream`.
+ * fhash_render_composite_batch: composites the values y (the frame of the
+ * march's pos) into the rays of the n states (all pending, from one march
+ * batch or from single marches into the same frame); tf and rgba are HOST
+ * arrays of n device pointers (transfer function float[256][4] and image of
+ * each request).  Updates each state's n_alive.  Synchronises `stream`. */
+#define FHASH_RENDER_BATCH_MAX 32
+int fhash_render_march_batch(fhash_render_state* const* states, const int32_t* paces, int32_t n,
+                             const fhash_render_opts* opts, float* pos, int64_t out_base,
+                             int64_t cap, int32_t* counts, int64_t* n_samples, void* stream);
+int fhash_render_composite_batch(fhash_render_state* const* states, int32_t n, const float* y,
+                                 const float* const* tf, float* const* rgba,
+                                 const fhash_render_opts* opts, int32_t* counts, void* stream);
 
 typedef struct {
   int64_t iterations, samples;

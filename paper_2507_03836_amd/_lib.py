@@ -182,9 +182,12 @@ def _declare(L):
         "fhash_coreset": (C.c_int, [P, P, P, I64, P, P, P, P]),
         "fhash_render_state_bytes": (C.c_int, [I32, I32, P, P]),
         "fhash_render_begin": (C.c_int, [P, F, I32, I32, P, P, P, C.c_size_t, P, P, P]),
+        "fhash_render_begin_grid": (C.c_int, [P, F, I32, I32, P, P, P, C.c_size_t, P, P, P]),
         "fhash_render_pace": (I32, [I64, I64, I32]),
         "fhash_render_march": (C.c_int, [P, P, I32, P, I64, P, P]),
         "fhash_render_composite": (C.c_int, [P, P, P, P, P, P]),
+        "fhash_render_march_batch": (C.c_int, [P, P, I32, P, P, I64, I64, P, P, P]),
+        "fhash_render_composite_batch": (C.c_int, [P, I32, P, P, P, P, P, P]),
         "fhash_render": (C.c_int, [P, P, P, C.c_int, P, P, P, P, F, P, I32, I32, P, P, P, P, P,
                                    P]),
     }
@@ -200,8 +203,10 @@ def exported_symbols() -> list[str]:
             "fhash_mlp_fwd", "fhash_mlp_bwd", "fhash_fused_fwd", "fhash_fused_bwd",
             "fhash_fused_train", "fhash_step", "fhash_check_finite", "fhash_cast",
             "fhash_sample", "fhash_sq_err_sum", "fhash_mse_grad", "fhash_render_state_bytes",
-            "fhash_render_begin", "fhash_render_pace", "fhash_render_march",
-            "fhash_render_composite", "fhash_render", "fhash_sort_samples",
+            "fhash_render_begin", "fhash_render_begin_grid", "fhash_render_pace",
+            "fhash_render_march",
+            "fhash_render_composite", "fhash_render_march_batch",
+            "fhash_render_composite_batch", "fhash_render", "fhash_sort_samples",
             "fhash_lazy_workspace_bytes", "fhash_lazy_init", "fhash_lazy_prepare",
             "fhash_step_lazy", "fhash_lazy_flush", "fhash_lazy_stats", "fhash_feature_mask",
             "fhash_dilate_mask", "fhash_feature_boxes", "fhash_occupancy_words",
@@ -642,6 +647,16 @@ def fhash_render_begin(view: View, t, W, H, mask_bits, dims, ws, rgba) -> Render
     return st
 
 
+def fhash_render_begin_grid(view: View, t, W, H, occ, dims, ws, rgba) -> RenderState:
+    """fhash_render_begin from the coreset's occupancy grid (fhash_occupancy_grid)."""
+    st = RenderState()
+    _check(lib().fhash_render_begin_grid(C.byref(view), C.c_float(t), W, H, _ptr(occ),
+                                         _dims(dims), _ptr(ws), ws.numel() * ws.element_size(),
+                                         _ptr(rgba), C.byref(st), _stream()),
+           "fhash_render_begin_grid")
+    return st
+
+
 def fhash_render_pace(budget, alive, arm_max) -> int:
     return int(lib().fhash_render_pace(int(budget), int(alive), int(arm_max)))
 
@@ -651,6 +666,37 @@ def fhash_render_march(st: RenderState, opts: RenderOpts, pace, pos_out, cap) ->
     _check(lib().fhash_render_march(C.byref(st), C.byref(opts), pace, _ptr(pos_out), cap,
                                     C.byref(ns), _stream()), "fhash_render_march")
     return ns.value
+
+
+RENDER_BATCH_MAX = 32
+
+
+def _state_array(states):
+    return (C.POINTER(RenderState) * len(states))(*[C.pointer(st) for st in states])
+
+
+def fhash_render_march_batch(states, paces, opts: RenderOpts, pos, out_base, cap, counts) -> list:
+    """One march launch over several requests; samples go to pos[out_base:],
+    interleaved.  counts: device int32 tensor of at least 1 + len(states)."""
+    n = len(states)
+    ns = (C.c_int64 * n)()
+    _check(lib().fhash_render_march_batch(_state_array(states), (C.c_int32 * n)(*paces), n,
+                                          C.byref(opts), _ptr(pos), int(out_base), int(cap),
+                                          _ptr(counts), ns, _stream()),
+           "fhash_render_march_batch")
+    return list(ns)
+
+
+def fhash_render_composite_batch(states, y, tfs, opts: RenderOpts, rgbas, counts) -> list:
+    """One composite launch over several requests (y in the march's frame);
+    returns each request's alive-ray count."""
+    n = len(states)
+    tf = (C.c_void_p * n)(*[t.data_ptr() for t in tfs])
+    rg = (C.c_void_p * n)(*[t.data_ptr() for t in rgbas])
+    _check(lib().fhash_render_composite_batch(_state_array(states), n, _ptr(y), tf, rg,
+                                              C.byref(opts), _ptr(counts), _stream()),
+           "fhash_render_composite_batch")
+    return [int(st.n_alive) for st in states]
 
 
 def fhash_render_composite(st: RenderState, y, tf, opts: RenderOpts, rgba):

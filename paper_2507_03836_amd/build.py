@@ -33,11 +33,27 @@ def _compile(src: str) -> str:
     return obj
 
 
+# Measurement probe (not part of the library): the chip's scattered-access
+# ceiling that the fine-level gathers and atomics are held against.
+PROBE_SRC = os.path.join(HERE, "probe", "random_access.hip")
+PROBE = os.path.join(HERE, "probe", "random_access")
+
+
+def _probe() -> str:
+    cmd = [HIPCC, *[f for f in FLAGS if f != "-fPIC"], PROBE_SRC, "-o", PROBE]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the probe:\n{r.stderr}")
+    return PROBE
+
+
 def build(jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        probe = ex.submit(_probe)
         objs = list(ex.map(_compile, SOURCES))
+        probe.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)

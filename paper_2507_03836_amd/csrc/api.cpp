@@ -733,9 +733,10 @@ int fhash_render_state_bytes(int32_t W, int32_t H, const int64_t dims[4], size_t
   return FHASH_OK;
 }
 
-int fhash_render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
-                       const uint64_t* mask_bits, const int64_t dims[4], void* ws,
-                       size_t ws_bytes, float* rgba, fhash_render_state* state, void* stream) {
+static int render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
+                        const uint64_t* mask_bits, bool brick_grid, const int64_t dims[4],
+                        void* ws, size_t ws_bytes, float* rgba, fhash_render_state* state,
+                        void* stream) {
   size_t need;
   int rc = fhash_render_state_bytes(W, H, dims, &need);
   if (rc) return rc;
@@ -753,11 +754,27 @@ int fhash_render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
   state->ws = ws;
   for (int d = 0; d < 4; ++d) state->dims[d] = dims[d];
   int32_t na = 0;
-  hipError_t e = fh::launch_render_begin(view, W, H, mask_bits, dims, t, ws, &na, rgba, S(stream));
+  hipError_t e =
+      fh::launch_render_begin(view, W, H, mask_bits, brick_grid, dims, t, ws, &na, rgba, S(stream));
   if (e != hipSuccess) return hip_status(e, "fhash_render_begin");
   state->n_alive = na;
   state->cur = 0;
   return FHASH_OK;
+}
+
+int fhash_render_begin(const fhash_view* view, float t, int32_t W, int32_t H,
+                       const uint64_t* mask_bits, const int64_t dims[4], void* ws,
+                       size_t ws_bytes, float* rgba, fhash_render_state* state, void* stream) {
+  return render_begin(view, t, W, H, mask_bits, false, dims, ws, ws_bytes, rgba, state, stream);
+}
+
+int fhash_render_begin_grid(const fhash_view* view, float t, int32_t W, int32_t H,
+                            const uint64_t* occ, const int64_t dims[4], void* ws,
+                            size_t ws_bytes, float* rgba, fhash_render_state* state,
+                            void* stream) {
+  if (dims != nullptr && fhash_occupancy_words(dims) < 0)
+    return fail(FHASH_EINVAL, "dims outside the occupancy grid's range");
+  return render_begin(view, t, W, H, occ, true, dims, ws, ws_bytes, rgba, state, stream);
 }
 
 int32_t fhash_render_pace(int64_t budget, int64_t alive, int32_t arm_max) {
@@ -809,6 +826,99 @@ int fhash_render_composite(fhash_render_state* state, const float* y, const floa
   state->n_alive = na;
   state->pending = 0;
   state->iterations += 1;
+  return FHASH_OK;
+}
+
+// n distinct states with distinct workspaces (the batched kernels update
+// each request's rays through its own workspace).
+static int check_batch(fhash_render_state* const* states, int32_t n, bool pending) {
+  if (states == nullptr) return fail(FHASH_EINVAL, "states is NULL");
+  if (n < 1 || n > FHASH_RENDER_BATCH_MAX)
+    return fail(FHASH_EINVAL, "batch of %d requests outside [1, %d]", n, FHASH_RENDER_BATCH_MAX);
+  for (int32_t r = 0; r < n; ++r) {
+    const fhash_render_state* s = states[r];
+    if (s == nullptr || s->ws == nullptr) return fail(FHASH_EINVAL, "state %d is NULL", r);
+    if ((s->pending != 0) != pending)
+      return fail(FHASH_EINVAL, pending ? "state %d: composite without a march"
+                                        : "state %d: previous samples not composited", r);
+    for (int32_t q = 0; q < r; ++q)
+      if (states[q] == s || states[q]->ws == s->ws)
+        return fail(FHASH_EINVAL, "states %d and %d share a state or workspace", q, r);
+  }
+  return FHASH_OK;
+}
+
+int fhash_render_march_batch(fhash_render_state* const* states, const int32_t* paces, int32_t n,
+                             const fhash_render_opts* opts, float* pos, int64_t out_base,
+                             int64_t cap, int32_t* counts, int64_t* n_samples, void* stream) {
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if ((rc = check_batch(states, n, false))) return rc;
+  if (paces == nullptr || counts == nullptr || n_samples == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  if (out_base < 0) return fail(FHASH_EINVAL, "out_base < 0");
+  int64_t need = out_base;
+  for (int32_t r = 0; r < n; ++r) {
+    if (paces[r] < 1 || paces[r] > opts->arm_max)
+      return fail(FHASH_EINVAL, "pace of request %d outside [1, arm_max]", r);
+    need += (int64_t)paces[r] * states[r]->n_alive;
+  }
+  if (need > cap) return fail(FHASH_EINVAL, "sample buffer %lld < out_base + sum pace * alive",
+                              (long long)cap);
+  // (the launch pads each request's rays to whole waves: 63 more per request)
+  if (need + 64 * (int64_t)n > (int64_t)INT32_MAX)
+    return fail(FHASH_EINVAL, "out_base + sum pace * alive exceeds 2^31 - 1 - 64 n");
+  if (need > out_base && (pos == nullptr || !aligned16(pos)))
+    return fail(FHASH_EINVAL, "pos NULL or not 16-byte aligned");
+  fh::RenderBatch b[FHASH_RENDER_BATCH_MAX];
+  for (int32_t r = 0; r < n; ++r) {
+    const fhash_render_state* s = states[r];
+    b[r] = fh::RenderBatch{s->ws, s->W, s->H, s->cur, s->n_alive, paces[r], s->t01, s->dims,
+                           nullptr, nullptr};
+  }
+  int32_t host[1 + FHASH_RENDER_BATCH_MAX];
+  hipError_t e = fh::launch_render_march_batch(b, n, opts->ds, opts->max_steps, pos, out_base,
+                                               counts, host, S(stream));
+  if (e != hipSuccess) return hip_status(e, "fhash_render_march_batch");
+  for (int32_t r = 0; r < n; ++r) {
+    n_samples[r] = host[1 + r];
+    states[r]->pending = 1;
+    states[r]->samples += host[1 + r];
+  }
+  return FHASH_OK;
+}
+
+int fhash_render_composite_batch(fhash_render_state* const* states, int32_t n, const float* y,
+                                 const float* const* tf, float* const* rgba,
+                                 const fhash_render_opts* opts, int32_t* counts, void* stream) {
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if ((rc = check_batch(states, n, true))) return rc;
+  if (tf == nullptr || rgba == nullptr || counts == nullptr)
+    return fail(FHASH_EINVAL, "NULL pointer");
+  int64_t rays = 0;
+  for (int32_t r = 0; r < n; ++r) rays += ((int64_t)states[r]->n_alive + 63) & ~(int64_t)63;
+  if (rays > (int64_t)INT32_MAX)
+    return fail(FHASH_EINVAL, "the batch's alive rays, padded to whole waves, exceed 2^31 - 1");
+  fh::RenderBatch b[FHASH_RENDER_BATCH_MAX];
+  for (int32_t r = 0; r < n; ++r) {
+    const fhash_render_state* s = states[r];
+    if (tf[r] == nullptr || rgba[r] == nullptr)
+      return fail(FHASH_EINVAL, "request %d: NULL transfer function or image", r);
+    b[r] = fh::RenderBatch{s->ws, s->W, s->H, s->cur, s->n_alive, 0, s->t01, s->dims, tf[r],
+                           rgba[r]};
+  }
+  int32_t host[1 + FHASH_RENDER_BATCH_MAX];
+  hipError_t e = fh::launch_render_composite_batch(b, n, y, opts->alpha_stop, counts, host,
+                                                   S(stream));
+  if (e != hipSuccess) return hip_status(e, "fhash_render_composite_batch");
+  for (int32_t r = 0; r < n; ++r) {
+    fhash_render_state* s = states[r];
+    s->cur = 1 - s->cur;
+    s->n_alive = host[1 + r];
+    s->pending = 0;
+    s->iterations += 1;
+  }
   return FHASH_OK;
 }
 

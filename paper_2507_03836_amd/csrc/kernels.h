@@ -104,9 +104,26 @@ hipError_t launch_sort_samples(float* pos, float* target, int64_t n, void* ws, h
 
 // render.hip
 size_t render_ws_bytes(int64_t NR, const int64_t* dims);
+// mask: the voxel mask rows (brick_grid false) or the occupancy grid of
+// fhash_occupancy_grid (brick_grid true).
 hipError_t launch_render_begin(const fhash_view* v, int W, int H, const uint64_t* mask,
-                               const int64_t* dims, float t, void* ws, int32_t* n_alive_host,
-                               float* rgba, hipStream_t st);
+                               bool brick_grid, const int64_t* dims, float t, void* ws,
+                               int32_t* n_alive_host, float* rgba, hipStream_t st);
+// One request of a batched march / composite (host view of its render state).
+struct RenderBatch {
+  void* ws;
+  int32_t W, H, cur, n_alive, pace;
+  float t01;
+  const int64_t* dims;
+  const float* tf;
+  float* rgba;
+};
+hipError_t launch_render_march_batch(const RenderBatch* b, int32_t n, float ds, int32_t max_steps,
+                                     float* pos, int64_t out_base, int32_t* counts_dev,
+                                     int32_t* counts_host, hipStream_t st);
+hipError_t launch_render_composite_batch(const RenderBatch* b, int32_t n, const float* y,
+                                         float alpha_stop, int32_t* counts_dev,
+                                         int32_t* counts_host, hipStream_t st);
 hipError_t launch_render_march(void* ws, int W, int H, const int64_t* dims, float t01, float ds,
                                int32_t max_steps, int32_t pace, int cur, int32_t n_alive,
                                float* pos_out, int32_t* n_samples_host, hipStream_t st);

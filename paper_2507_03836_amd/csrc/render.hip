@@ -107,6 +107,56 @@ __global__ void occupancy_kernel(const uint64_t* __restrict__ mask, int64_t Sx, 
   }
 }
 
+// The same cell bits from the coreset's occupancy grid (one word per 4x4x4
+// brick, bricks [T][Bz][By][Bx], voxel (lx, ly, lz) of a brick at bit
+// lx0 | ly0<<1 | lz0<<2 | lx1<<3 | ly1<<4 | lz1<<5): voxel row (z, y) over
+// x in [64w, 64w + 68) is gathered from 17 bricks, 4 bits each.
+__device__ __forceinline__ uint64_t brick_row_bits(uint64_t b, int ly, int lz) {
+  const int base = (ly & 1) << 1 | (lz & 1) << 2 | (ly >> 1) << 4 | (lz >> 1) << 5;
+  return ((b >> base) & 3ull) | (((b >> (base + 8)) & 3ull) << 2);
+}
+
+__global__ void occupancy_grid_cells_kernel(const uint64_t* __restrict__ grid, int64_t Sx,
+                                            int64_t Sy, int64_t Sz, int t0, int t1,
+                                            uint64_t* __restrict__ occ) {
+  const int64_t Wc = (Sx - 1 + 63) / 64;
+  const int64_t Bx = (Sx + 3) / 4, By = (Sy + 3) / 4, Bz = (Sz + 3) / 4;
+  const int64_t rows = (Sz - 1) * (Sy - 1);
+  const int64_t total = rows * Wc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = e % Wc, row = e / Wc;
+    const int64_t cy = row % (Sy - 1), cz = row / (Sy - 1);
+    uint64_t cur = 0, nxt = 0;
+    // voxel rows y in {cy, cy+1}, z in {cz, cz+1}: one or two brick rows per
+    // axis; each brick word is loaded once for the rows it holds
+    const int64_t zb0 = cz >> 2, zb1 = (cz + 1) >> 2, yb0 = cy >> 2, yb1 = (cy + 1) >> 2;
+    for (int n = t0; n <= t1; ++n)
+      for (int64_t zb = zb0; zb <= zb1; ++zb)
+        for (int64_t yb = yb0; yb <= yb1; ++yb) {
+          const uint64_t* src = grid + ((n * Bz + zb) * By + yb) * Bx;
+          for (int b = 0; b <= 16; ++b) {
+            const int64_t bx = 16 * w + b;
+            if (bx >= Bx) break;
+            const uint64_t word = src[bx];
+            uint64_t r = 0;
+            for (int dz = 0; dz < 2; ++dz)
+              for (int dy = 0; dy < 2; ++dy)
+                if (((cz + dz) >> 2) == zb && ((cy + dy) >> 2) == yb)
+                  r |= brick_row_bits(word, (int)((cy + dy) & 3), (int)((cz + dz) & 3));
+            if (b < 16)
+              cur |= r << (4 * b);
+            else
+              nxt |= r;
+          }
+        }
+    uint64_t bits = cur | (cur >> 1) | (nxt << 63);
+    const int64_t valid = (Sx - 1) - w * 64;
+    if (valid < 64) bits &= (1ull << valid) - 1ull;
+    occ[e] = bits;
+  }
+}
+
 struct MarchArgs {
   const uint64_t* occ;
   int64_t Sx, Sy, Sz;
@@ -145,20 +195,20 @@ __device__ __forceinline__ bool occupied(const MarchArgs& a, float px, float py,
 
 // Walk an alive ray's lattice from its cursor, emitting up to `pace` occupied
 // samples: pass 0 counts, a wave-wide reservation gives each ray a contiguous
-// output range, pass 1 writes the model inputs.
+// output range (offset out_base + the reservation), pass 1 writes the model
+// inputs.  Every lane of the wave calls it (act = false for idle lanes).
+// Returns the ray's sample count (0 when idle).
 template <typename I>
-__global__ void __launch_bounds__(256)
-    march_kernel(MarchArgs a, Ray* __restrict__ rays, const int32_t* __restrict__ alive,
-                 int32_t n_alive, float4* __restrict__ out, int32_t* __restrict__ counter) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool act = i < n_alive;
+__device__ __forceinline__ int32_t march_one(const MarchArgs& a, Ray* __restrict__ rays,
+                                             int32_t rid, bool act, float4* __restrict__ out,
+                                             int32_t* __restrict__ counter, int64_t out_base) {
   Ray ray;
   int32_t k_end = 0, cnt = 0;
   bool exh = false;
   I w_idx = -1;
   uint64_t w_val = 0;
   if (act) {
-    ray = rays[alive[i]];
+    ray = rays[rid];
     int32_t k = ray.k;
     while (cnt < a.pace) {
       if (k >= a.max_steps) {
@@ -189,8 +239,8 @@ __global__ void __launch_bounds__(256)
   int32_t base = 0;
   if (lane == 63 && tot > 0) base = atomicAdd(counter, tot);
   base = __shfl(base, 63, 64);
-  if (!act) return;
-  const int32_t off = base + incl - cnt;
+  if (!act) return 0;
+  const int64_t off = out_base + base + incl - cnt;
   int32_t k = ray.k, w = 0;
   w_idx = -1;
   while (w < cnt) {
@@ -204,10 +254,78 @@ __global__ void __launch_bounds__(256)
     }
     ++k;
   }
-  Ray* rp = rays + alive[i];
+  Ray* rp = rays + rid;
   rp->k = k_end;
-  rp->off = off;
+  rp->off = (int32_t)off;
   rp->cnt = cnt | (exh ? kExhausted : 0);
+  return cnt;
+}
+
+template <typename I>
+__global__ void __launch_bounds__(256)
+    march_kernel(MarchArgs a, Ray* __restrict__ rays, const int32_t* __restrict__ alive,
+                 int32_t n_alive, float4* __restrict__ out, int32_t* __restrict__ counter) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool act = i < n_alive;
+  march_one<I>(a, rays, act ? alive[i] : 0, act, out, counter, 0);
+}
+
+// Several requests in one launch: request r owns the alive rays
+// [first_r, first_r + n_alive_r) of the launch's index space, with first_r a
+// multiple of 64 so that every wave serves one request (its arguments are
+// then wave-uniform, and so are the addresses of its counter atomics).
+constexpr int kBatchMax = FHASH_RENDER_BATCH_MAX;
+
+struct BatchMarchReq {
+  Ray* rays;
+  const int32_t* alive;
+  const uint64_t* occ;
+  int32_t first, n_alive, pace, Wc;
+  int32_t Sx, Sy, Sz, pad;
+  float fx, fy, fz, tn;
+};
+
+struct BatchMarchArgs {
+  BatchMarchReq q[kBatchMax];
+  int32_t n, total, max_steps;
+  float ds;
+  int64_t out_base;
+};
+
+// Request of the wave holding launch index i (wave-uniform, in an SGPR).
+template <typename Q>
+__device__ __forceinline__ int wave_request(const Q* q, int32_t n, int64_t i) {
+  const int64_t w0 = i & ~(int64_t)63;
+  int r = 0;
+  while (r + 1 < n && w0 >= q[r + 1].first) ++r;
+  return __builtin_amdgcn_readfirstlane(r);
+}
+
+// counts[0]: sample counter of the launch; counts[1 + r]: samples of request r.
+template <typename I>
+__global__ void __launch_bounds__(256)
+    march_batch_kernel(BatchMarchArgs A, float4* __restrict__ out, int32_t* __restrict__ counts) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int r = wave_request(A.q, A.n, i);
+  const BatchMarchReq& q = A.q[r];
+  const int64_t j = i - q.first;
+  const bool act = j < q.n_alive;
+  MarchArgs a;
+  a.occ = q.occ;
+  a.Sx = q.Sx;
+  a.Sy = q.Sy;
+  a.Sz = q.Sz;
+  a.Wc = q.Wc;
+  a.fx = q.fx;
+  a.fy = q.fy;
+  a.fz = q.fz;
+  a.tn = q.tn;
+  a.ds = A.ds;
+  a.max_steps = A.max_steps;
+  a.pace = q.pace;
+  int32_t t = march_one<I>(a, q.rays, act ? q.alive[j] : 0, act, out, counts, A.out_base);
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if ((threadIdx.x & 63) == 0 && t > 0) atomicAdd(&counts[1 + r], t);
 }
 
 __device__ __forceinline__ float4 tf_lookup(const float4* __restrict__ tf, float v) {
@@ -221,38 +339,85 @@ __device__ __forceinline__ float4 tf_lookup(const float4* __restrict__ tf, float
                      (1.0f - f) * a.z + f * b.z, (1.0f - f) * a.w + f * b.w);
 }
 
+// Composite the last march's samples of ray rid; a ray still alive afterwards
+// is appended to `next` (one counter atomic per wave).  Every lane of the wave
+// calls it (act = false for idle lanes).
+__device__ __forceinline__ void composite_one(Ray* __restrict__ rays, int32_t rid, bool act,
+                                              const float* __restrict__ y,
+                                              const float4* __restrict__ tf, float alpha_stop,
+                                              float4* __restrict__ rgba,
+                                              int32_t* __restrict__ next,
+                                              int32_t* __restrict__ n_next) {
+  bool keep = false;
+  if (act) {
+    Ray ray = rays[rid];
+    const int32_t cnt = ray.cnt & (kExhausted - 1);
+    bool dead = (ray.cnt & kExhausted) != 0;
+    float cr = ray.cr, cg = ray.cg, cb = ray.cb, A = ray.ca;
+    for (int32_t j = 0; j < cnt; ++j) {
+      const float4 c = tf_lookup(tf, y[ray.off + j]);
+      const float t = (1.0f - A) * c.w;
+      cr += t * c.x;
+      cg += t * c.y;
+      cb += t * c.z;
+      A += t;
+      if (A >= alpha_stop) {
+        dead = true;
+        break;
+      }
+    }
+    Ray* rp = rays + rid;
+    rp->cr = cr, rp->cg = cg, rp->cb = cb, rp->ca = A;
+    if (dead)
+      rgba[ray.pixel] = make_float4(cr, cg, cb, A);
+    keep = !dead;
+  }
+  const uint64_t m = __ballot(keep);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  int32_t base = 0;
+  if (lane == leader) base = atomicAdd(n_next, __popcll(m));
+  base = __shfl(base, leader, 64);
+  if (keep) next[base + __popcll(m & ((1ull << lane) - 1ull))] = rid;
+}
+
 __global__ void __launch_bounds__(256)
     composite_kernel(Ray* __restrict__ rays, const int32_t* __restrict__ alive, int32_t n_alive,
                      const float* __restrict__ y, const float4* __restrict__ tf, float alpha_stop,
                      float4* __restrict__ rgba, int32_t* __restrict__ next,
                      int32_t* __restrict__ n_next) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n_alive) return;
-  const int32_t rid = alive[i];
-  Ray ray = rays[rid];
-  const int32_t cnt = ray.cnt & (kExhausted - 1);
-  bool dead = (ray.cnt & kExhausted) != 0;
-  float cr = ray.cr, cg = ray.cg, cb = ray.cb, A = ray.ca;
-  for (int32_t j = 0; j < cnt; ++j) {
-    const float4 c = tf_lookup(tf, y[ray.off + j]);
-    const float t = (1.0f - A) * c.w;
-    cr += t * c.x;
-    cg += t * c.y;
-    cb += t * c.z;
-    A += t;
-    if (A >= alpha_stop) {
-      dead = true;
-      break;
-    }
-  }
-  Ray* rp = rays + rid;
-  rp->cr = cr, rp->cg = cg, rp->cb = cb, rp->ca = A;
-  if (dead) {
-    rgba[ray.pixel] = make_float4(cr, cg, cb, A);
-  } else {
-    const int32_t s = atomicAdd(n_next, 1);
-    next[s] = rid;
-  }
+  const bool act = i < n_alive;
+  composite_one(rays, act ? alive[i] : 0, act, y, tf, alpha_stop, rgba, next, n_next);
+}
+
+struct BatchCompReq {
+  Ray* rays;
+  const int32_t* alive;
+  int32_t* next;
+  const float4* tf;
+  float4* rgba;
+  int32_t first, n_alive;
+};
+
+struct BatchCompArgs {
+  BatchCompReq q[kBatchMax];
+  int32_t n, total;
+  float alpha_stop;
+};
+
+// counts[1 + r]: rays of request r still alive (the next list's length).
+__global__ void __launch_bounds__(256)
+    composite_batch_kernel(BatchCompArgs A, const float* __restrict__ y,
+                           int32_t* __restrict__ counts) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int r = wave_request(A.q, A.n, i);
+  const BatchCompReq& q = A.q[r];
+  const int64_t j = i - q.first;
+  const bool act = j < q.n_alive;
+  composite_one(q.rays, act ? q.alive[j] : 0, act, y, q.tf, A.alpha_stop, q.rgba, q.next,
+                &counts[1 + r]);
 }
 
 // One thread per alive ray (the kernels have no grid-stride loop): at most
@@ -302,8 +467,8 @@ static RenderWs carve(void* ws, int64_t NR) {
 }
 
 hipError_t launch_render_begin(const fhash_view* v, int W, int H, const uint64_t* mask,
-                               const int64_t* dims, float t, void* ws, int32_t* n_alive_host,
-                               float* rgba, hipStream_t st) {
+                               bool brick_grid, const int64_t* dims, float t, void* ws,
+                               int32_t* n_alive_host, float* rgba, hipStream_t st) {
   const int64_t NR = (int64_t)W * H;
   RenderWs w = carve(ws, NR);
   int t0 = (int)floorf(t), t1 = (int)ceilf(t);
@@ -312,8 +477,12 @@ hipError_t launch_render_begin(const fhash_view* v, int W, int H, const uint64_t
   hipError_t e = hipMemsetAsync(w.counters, 0, 64, st);
   if (e != hipSuccess) return e;
   const int64_t Wc = (dims[0] - 1 + 63) / 64;
-  hipLaunchKernelGGL(occupancy_kernel, dim3(blocks((dims[2] - 1) * (dims[1] - 1) * Wc)), dim3(256),
-                     0, st, mask, dims[0], dims[1], dims[2], dims[3], t0, t1, w.occ);
+  if (brick_grid)
+    hipLaunchKernelGGL(occupancy_grid_cells_kernel, dim3(blocks((dims[2] - 1) * (dims[1] - 1) * Wc)),
+                       dim3(256), 0, st, mask, dims[0], dims[1], dims[2], t0, t1, w.occ);
+  else
+    hipLaunchKernelGGL(occupancy_kernel, dim3(blocks((dims[2] - 1) * (dims[1] - 1) * Wc)),
+                       dim3(256), 0, st, mask, dims[0], dims[1], dims[2], dims[3], t0, t1, w.occ);
   hipLaunchKernelGGL(init_rays_kernel, dim3(blocks(NR)), dim3(256), 0, st, *v, W, H,
                      (float)(dims[0] - 1), (float)(dims[1] - 1), (float)(dims[2] - 1), w.rays,
                      w.alive[0], w.counters, rgba);
@@ -375,6 +544,90 @@ hipError_t launch_render_composite(void* ws, int W, int H, int cur, int32_t n_al
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(n_alive_host, w.counters + nxt, 4, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+hipError_t launch_render_march_batch(const RenderBatch* b, int32_t n, float ds, int32_t max_steps,
+                                     float* pos, int64_t out_base, int32_t* counts_dev,
+                                     int32_t* counts_host, hipStream_t st) {
+  BatchMarchArgs A{};
+  A.n = n;
+  A.ds = ds;
+  A.max_steps = max_steps;
+  A.out_base = out_base;
+  int32_t total = 0;
+  bool wide = false;
+  for (int32_t r = 0; r < n; ++r) {
+    const int64_t* dims = b[r].dims;
+    const int64_t NR = (int64_t)b[r].W * b[r].H;
+    RenderWs w = carve(b[r].ws, NR);
+    BatchMarchReq& q = A.q[r];
+    q.rays = w.rays;
+    q.alive = w.alive[b[r].cur];
+    q.occ = w.occ;
+    q.first = total;
+    q.n_alive = b[r].n_alive;
+    q.pace = b[r].pace;
+    q.Wc = (int32_t)((dims[0] - 1 + 63) / 64);
+    q.Sx = (int32_t)dims[0];
+    q.Sy = (int32_t)dims[1];
+    q.Sz = (int32_t)dims[2];
+    q.fx = (float)(dims[0] - 1);
+    q.fy = (float)(dims[1] - 1);
+    q.fz = (float)(dims[2] - 1);
+    q.tn = b[r].t01;
+    total += (b[r].n_alive + 63) & ~63;
+    if ((dims[2] - 1) * (dims[1] - 1) * (int64_t)q.Wc >= ((int64_t)1 << 31)) wide = true;
+  }
+  A.total = total;
+  hipError_t e = hipMemsetAsync(counts_dev, 0, (size_t)(1 + n) * 4, st);
+  if (e != hipSuccess) return e;
+  if (total > 0) {
+    float4* out = reinterpret_cast<float4*>(pos);
+    if (wide)
+      hipLaunchKernelGGL(march_batch_kernel<int64_t>, dim3(blocks_exact(total)), dim3(256), 0, st,
+                         A, out, counts_dev);
+    else
+      hipLaunchKernelGGL(march_batch_kernel<int32_t>, dim3(blocks_exact(total)), dim3(256), 0, st,
+                         A, out, counts_dev);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(counts_host, counts_dev, (size_t)(1 + n) * 4, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+hipError_t launch_render_composite_batch(const RenderBatch* b, int32_t n, const float* y,
+                                         float alpha_stop, int32_t* counts_dev,
+                                         int32_t* counts_host, hipStream_t st) {
+  BatchCompArgs A{};
+  A.n = n;
+  A.alpha_stop = alpha_stop;
+  int32_t total = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    const int64_t NR = (int64_t)b[r].W * b[r].H;
+    RenderWs w = carve(b[r].ws, NR);
+    BatchCompReq& q = A.q[r];
+    q.rays = w.rays;
+    q.alive = w.alive[b[r].cur];
+    q.next = w.alive[1 - b[r].cur];
+    q.tf = reinterpret_cast<const float4*>(b[r].tf);
+    q.rgba = reinterpret_cast<float4*>(b[r].rgba);
+    q.first = total;
+    q.n_alive = b[r].n_alive;
+    total += (b[r].n_alive + 63) & ~63;
+  }
+  A.total = total;
+  hipError_t e = hipMemsetAsync(counts_dev, 0, (size_t)(1 + n) * 4, st);
+  if (e != hipSuccess) return e;
+  if (total > 0)
+    hipLaunchKernelGGL(composite_batch_kernel, dim3(blocks_exact(total)), dim3(256), 0, st, A, y,
+                       counts_dev);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(counts_host, counts_dev, (size_t)(1 + n) * 4, hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(st);
 }

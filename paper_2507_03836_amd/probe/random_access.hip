@@ -1,0 +1,109 @@
+// Scattered-access ceiling of the chip, the bound that the gather and the
+// scatter-add of the fine levels run against (random rows of tables far larger
+// than L2 and the last-level cache): rates of
+//   - random 128-byte line reads (8 lanes read 16 B each of one line),
+//   - random 16-byte reads (every lane a different line),
+//   - random 16-byte atomic groups (4 lanes add one float each into 16
+//     consecutive bytes, as 2F lanes scatter one x-pair of a row pair),
+// over a 24 GiB buffer, at 64K to 4M threads.  Not part of the library.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+namespace {
+
+// splitmix64 finaliser: the random line of draw (g, k)
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void line_read(const float4* __restrict__ buf, uint64_t nlines, int iters,
+                          float* __restrict__ sink) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t g = t / 8;
+  const int l = (int)(t % 8);
+  float acc = 0.f;
+  for (int k = 0; k < iters; ++k) {
+    const uint64_t line = mix64(g * 131 + k) % nlines;
+    const float4 v = buf[line * 8 + l];
+    acc += v.x + v.y + v.z + v.w;
+  }
+  if (acc == 12345.f) sink[0] = acc;  // keeps the loads; never true on a zeroed buffer
+}
+
+__global__ void word_read(const float4* __restrict__ buf, uint64_t nlines, int iters,
+                          float* __restrict__ sink) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  float acc = 0.f;
+  for (int k = 0; k < iters; ++k) {
+    const uint64_t r = mix64(t * 131 + k);
+    const float4 v = buf[(r % nlines) * 8 + (r >> 60) % 8];
+    acc += v.x + v.y + v.z + v.w;
+  }
+  if (acc == 12345.f) sink[0] = acc;
+}
+
+__global__ void group_atomic(float* __restrict__ buf, uint64_t nlines, int iters) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t g = t / 4;
+  const int l = (int)(t % 4);
+  for (int k = 0; k < iters; ++k) {
+    const uint64_t r = mix64(g * 131 + k);
+    unsafeAtomicAdd(buf + (r % nlines) * 32 + ((r >> 60) % 8) * 4 + l, 1.0f);
+  }
+}
+
+bool ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  std::fprintf(stderr, "%s: %s\n", what, hipGetErrorString(e));
+  return false;
+}
+
+}  // namespace
+
+int main() {
+  const uint64_t bytes = 24ull << 30;
+  const uint64_t nlines = bytes / 128;
+  float* buf = nullptr;
+  float* sink = nullptr;
+  if (!ok(hipMalloc(&buf, bytes), "hipMalloc") || !ok(hipMalloc(&sink, 16), "hipMalloc") ||
+      !ok(hipMemset(buf, 0, bytes), "hipMemset"))
+    return 1;
+  hipEvent_t a, b;
+  if (!ok(hipEventCreate(&a), "event") || !ok(hipEventCreate(&b), "event")) return 1;
+  const int iters = 64;
+  for (int kthreads : {64, 256, 1024, 4096}) {
+    const uint64_t threads = (uint64_t)kthreads * 1024;
+    const unsigned blocks = (unsigned)(threads / 256);
+    float ms[3] = {0, 0, 0};
+    for (int rep = 0; rep < 2; ++rep) {  // the second repetition is reported
+      for (int kind = 0; kind < 3; ++kind) {
+        hipEventRecord(a);
+        if (kind == 0)
+          hipLaunchKernelGGL(line_read, dim3(blocks), dim3(256), 0, 0, (const float4*)buf, nlines,
+                             iters, sink);
+        else if (kind == 1)
+          hipLaunchKernelGGL(word_read, dim3(blocks), dim3(256), 0, 0, (const float4*)buf, nlines,
+                             iters, sink);
+        else
+          hipLaunchKernelGGL(group_atomic, dim3(blocks), dim3(256), 0, 0, buf, nlines, iters);
+        hipEventRecord(b);
+        if (!ok(hipEventSynchronize(b), "kernel")) return 1;
+        hipEventElapsedTime(&ms[kind], a, b);
+      }
+    }
+    const double lines = threads / 8.0 * iters, words = threads * (double)iters,
+                 groups = threads / 4.0 * iters;
+    std::printf("threads %5dK: 128-B line reads %.2f G/s (%.0f GB/s of lines); 16-B reads "
+                "%.2f G/s (%.0f GB/s as 128-B lines); 16-B atomic groups %.2f G/s (%.0f GB/s "
+                "as 128-B read + write)\n",
+                kthreads, lines / ms[0] / 1e6, lines * 128 / ms[0] / 1e6, words / ms[1] / 1e6,
+                words * 128 / ms[1] / 1e6, groups / ms[2] / 1e6, groups * 256 / ms[2] / 1e6);
+    std::fflush(stdout);
+  }
+  return 0;
+}

@@ -65,7 +65,6 @@ class Request:
     # scheduler-private
     alive: int = 0
     done: int = 0
-    y_off: int = 0
     chunk: tuple = (0, 0)
     state: object = None
     ws: object = None
@@ -211,13 +210,15 @@ class Scheduler:
         off = 0
         for m in models:
             start = off
-            for r in renders:
-                if r.model != m:
-                    continue
-                r.y_off = off
-                ns = self.ex.march(r, pace_of[id(r)], off, self.C - off)
-                r.samples += ns
-                off += ns
+            group = [r for r in renders if r.model == m]
+            if group:
+                # one march over the model's renders: their samples share
+                # [start, off) of the buffer, interleaved
+                counts = self.ex.march_batch(group, [pace_of[id(r)] for r in group], off)
+                for r, ns in zip(group, counts):
+                    r.samples += ns
+                    off += ns
+                assert off <= self.C
             for r in points:
                 if r.model != m:
                     continue
@@ -229,9 +230,10 @@ class Scheduler:
                     pt_budget -= k
             if off > start:
                 self.ex.decode(m, start, off)
-        for r in renders:
-            r.alive = self.ex.composite(r)
-            r.iterations += 1
+        if renders:
+            for r, alive in zip(renders, self.ex.composite_batch(renders)):
+                r.alive = alive
+                r.iterations += 1
         completed = []
         for r in points:
             o, k = r.chunk
@@ -292,7 +294,9 @@ def latency_stats(reqs: list[Request]) -> dict:
 @dataclasses.dataclass
 class ResidentModel:
     """A trained model kept on the device: index, decoder table (f32 or f16),
-    MLP parameters, voxel feature mask (for the occupancy test) and TF."""
+    MLP parameters, the occupancy for rendering and TF.  occ: the coreset's
+    occupancy grid (fhash_occupancy_grid), which renders start from; without
+    it, the voxel feature mask rows mask_bits."""
     index: object
     mlp: object
     table: object
@@ -301,10 +305,12 @@ class ResidentModel:
     dims: list
     tf: object
     keep: tuple = ()               # tensors the index views (directory)
+    occ: object = None
 
     def nbytes(self) -> int:
         tot = 0
-        for t in (self.table, self.params, self.mask_bits, self.tf) + tuple(self.keep):
+        occ = self.occ if self.occ is not None else self.mask_bits
+        for t in (self.table, self.params, occ, self.tf) + tuple(self.keep):
             tot += t.numel() * t.element_size()
         return tot
 
@@ -324,6 +330,7 @@ class GpuExecutor:
                                    max_steps=max_steps)
         self.pos = torch.empty(sample_budget, 4, dtype=torch.float32, device="cuda")
         self.y = torch.empty(sample_budget, dtype=torch.float32, device="cuda")
+        self.counts = torch.empty(1 + fl.RENDER_BATCH_MAX, dtype=torch.int32, device="cuda")
 
     def add_model(self, name: str, m: ResidentModel):
         self.models[name] = m
@@ -366,11 +373,25 @@ class GpuExecutor:
         r.ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
         r.result = torch.empty(r.H, r.W, 4, dtype=torch.float32, device="cuda")
         view = r.view if isinstance(r.view, fl.View) else fl.view_struct(r.view)
-        r.state = fl.fhash_render_begin(view, r.t, r.W, r.H, m.mask_bits, m.dims, r.ws, r.result)
+        if m.occ is not None:
+            r.state = fl.fhash_render_begin_grid(view, r.t, r.W, r.H, m.occ, m.dims, r.ws,
+                                                 r.result)
+        else:
+            r.state = fl.fhash_render_begin(view, r.t, r.W, r.H, m.mask_bits, m.dims, r.ws,
+                                            r.result)
         return int(r.state.n_alive)
 
-    def march(self, r: Request, pace: int, off: int, cap: int) -> int:
-        return self.fl.fhash_render_march(r.state, self.opts, pace, self.pos[off:], cap)
+    def march_batch(self, rs: list, paces: list, off: int) -> list:
+        """One march launch per FHASH_RENDER_BATCH_MAX renders; their samples
+        go to pos[off:], interleaved, each ray's at offsets it keeps."""
+        B, out = self.fl.RENDER_BATCH_MAX, []
+        for i in range(0, len(rs), B):
+            ns = self.fl.fhash_render_march_batch([r.state for r in rs[i: i + B]],
+                                                  paces[i: i + B], self.opts, self.pos, off,
+                                                  self.pos.shape[0], self.counts)
+            out += ns
+            off += sum(ns)
+        return out
 
     def load_points(self, r: Request, start: int, k: int, off: int):
         self.pos[off: off + k].copy_(r.pos[start: start + k])
@@ -380,10 +401,16 @@ class GpuExecutor:
         self.fl.fhash_fused_fwd(m.index, m.mlp, self.pos[start:end], end - start, m.table,
                                 m.params, self.y[start:end])
 
-    def composite(self, r: Request) -> int:
-        m = self.models[r.model]
-        self.fl.fhash_render_composite(r.state, self.y[r.y_off:], m.tf, self.opts, r.result)
-        return int(r.state.n_alive)
+    def composite_batch(self, rs: list) -> list:
+        """One composite launch per FHASH_RENDER_BATCH_MAX renders; returns the
+        alive-ray counts."""
+        B, out = self.fl.RENDER_BATCH_MAX, []
+        for i in range(0, len(rs), B):
+            ch = rs[i: i + B]
+            out += self.fl.fhash_render_composite_batch(
+                [r.state for r in ch], self.y, [self.models[r.model].tf for r in ch], self.opts,
+                [r.result for r in ch], self.counts)
+        return out
 
     def store_points(self, r: Request, start: int, k: int, off: int):
         r.result[start: start + k].copy_(self.y[off: off + k])

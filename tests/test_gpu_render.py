@@ -131,3 +131,98 @@ def test_more_rays_than_one_grid_of_65536_blocks(scene):
     a = rgba[..., 3]
     assert bool((a >= 0.99).all()), int((a < 0.99).sum())
     assert st.samples >= W * H
+
+
+def test_batched_steps_equal_single_renders(scene):
+    """fhash_render_march_batch / fhash_render_composite_batch over several
+    requests (uneven sizes, times and paces, samples interleaved in one
+    buffer at a non-zero base) give every request the image, sample count
+    and iteration count of its own fhash_render, bit for bit."""
+    s = scene
+    fl = s["fl"]
+    opts = fl.render_opts()
+    cases = [(40, 32, 4.5, 5.0), (17, 23, 0.0, 1.3), (64, 48, 6.75, 2.6), (8, 8, 2.0, 0.2),
+             (33, 1, 7.0, 3.9), (3, 2, 1.5, 4.4)]
+    reqs = []
+    for W, H, t, az in cases:
+        view = synth.orbit_view(s["dims"], az, 0.25, W, H)
+        whole, stats = _gpu_render(s, view, t, W, H)
+        ws = torch.empty(fl.fhash_render_state_bytes(W, H, s["dims"]), dtype=torch.uint8,
+                         device="cuda")
+        rgba = torch.empty(H, W, 4, device="cuda")
+        st = fl.fhash_render_begin(fl.view_struct(view), t, W, H, s["bits"], s["dims"], ws, rgba)
+        reqs.append(dict(W=W, H=H, whole=whole, stats=stats, ws=ws, rgba=rgba, st=st))
+    base = 7
+    cap = base + sum(r["W"] * r["H"] for r in reqs) * opts.arm_max
+    pos = torch.empty(cap, 4, device="cuda")
+    y = torch.full((cap,), float("nan"), device="cuda")
+    counts = torch.empty(1 + fl.RENDER_BATCH_MAX, dtype=torch.int32, device="cuda")
+    launches = 0
+    while True:
+        act = [r for r in reqs if r["st"].n_alive > 0]
+        if not act:
+            break
+        paces = [fl.fhash_render_pace(r["W"] * r["H"], r["st"].n_alive, opts.arm_max)
+                 for r in act]
+        ns = fl.fhash_render_march_batch([r["st"] for r in act], paces, opts, pos, base, cap,
+                                         counts)
+        total = sum(ns)
+        if total:
+            fl.fhash_fused_fwd(s["idx"], s["mlp"], pos[base: base + total], total, s["tab_d"],
+                               s["prm_d"], y[base: base + total])
+        alive = fl.fhash_render_composite_batch([r["st"] for r in act], y, [s["tf_d"]] * len(act),
+                                                opts, [r["rgba"] for r in act], counts)
+        assert alive == [r["st"].n_alive for r in act]
+        launches += 1
+    assert launches == max(r["stats"].iterations for r in reqs)
+    for r in reqs:
+        np.testing.assert_array_equal(r["rgba"].cpu().numpy(), r["whole"])
+        assert r["st"].samples == r["stats"].samples
+        assert r["st"].iterations == r["stats"].iterations
+
+
+def test_render_from_occupancy_grid_equals_mask_rows(scene):
+    """A render that starts from the coreset's occupancy grid
+    (fhash_render_begin_grid) is the render from the mask rows, bit for bit,
+    at key and in-between times, on a volume whose x extent is not a multiple
+    of the brick or word width."""
+    s = scene
+    fl = s["fl"]
+    opts = fl.render_opts()
+    rng = np.random.default_rng(8)
+    for dims, mask, bits in [(s["dims"], s["mask"], s["bits"])] + [
+            _random_mask(rng, (3, 13, 21, 150)), _random_mask(rng, (2, 6, 5, 67))]:
+        occ = fl.fhash_occupancy_grid(bits, dims)
+        for az, t in ((0.3, 0.0), (2.0, 0.5 * (dims[3] - 1)), (4.1, float(dims[3] - 1) - 0.25)):
+            W, H = 29, 21
+            view = fl.view_struct(synth.orbit_view(dims, az, 0.3, W, H))
+            imgs, stats = [], []
+            for grid in (False, True):
+                ws = torch.empty(fl.fhash_render_state_bytes(W, H, dims), dtype=torch.uint8,
+                                 device="cuda")
+                rgba = torch.empty(H, W, 4, device="cuda")
+                begin = fl.fhash_render_begin_grid if grid else fl.fhash_render_begin
+                st = begin(view, t, W, H, occ if grid else bits, dims, ws, rgba)
+                pos = torch.empty(W * H * 64, 4, device="cuda")
+                y = torch.empty(W * H * 64, device="cuda")
+                while st.n_alive > 0:
+                    pace = fl.fhash_render_pace(W * H, st.n_alive, opts.arm_max)
+                    ns = fl.fhash_render_march(st, opts, pace, pos, W * H * 64)
+                    if ns:
+                        # a decoder stand-in that depends on the sample: the
+                        # position's coordinates (any difference in the samples
+                        # taken shows up in the image)
+                        y[:ns] = pos[:ns, :3].sum(1) / 3.0
+                    fl.fhash_render_composite(st, y, s["tf_d"], opts, rgba)
+                imgs.append(rgba.cpu().numpy())
+                stats.append((st.samples, st.iterations))
+            np.testing.assert_array_equal(imgs[0], imgs[1])
+            assert stats[0] == stats[1]
+
+
+def _random_mask(rng, shape):
+    from paper_2507_03836_amd import synth as S
+    T, Sz, Sy, Sx = shape
+    m = (rng.random(shape) < 0.15).astype(np.uint8)
+    bits = torch.from_numpy(S.pack_mask_rows(m).view(np.int64)).cuda()
+    return [Sx, Sy, Sz, T], m, bits

@@ -1,8 +1,9 @@
 """Continuous-batching server on the device: every result of a mixed stream
 (three resident models: FP32, FP16 tables, FP16 tables with the FP16 decoder;
-renders of uneven sizes and times; point-query batches) equals, bit for bit,
-the same request served alone through the plain entry points (fhash_render,
-fhash_fused_fwd)."""
+two of them rendering from the coreset's occupancy grid; renders of uneven
+sizes and times; point-query batches; batched march and composite launches)
+equals, bit for bit, the same request served alone through the plain entry
+points (fhash_render from the mask rows, fhash_fused_fwd)."""
 import numpy as np
 import pytest
 import torch
@@ -40,10 +41,12 @@ def server_models():
         table = torch.from_numpy(rng.uniform(-1, 1, (rows, 2)).astype(np.float32)).cuda()
         params = synth.mlp_init(width, seed=seed)
         params[-1] = 0.5
+        # m1 and m2 render from the coreset's occupancy grid, m0 from the mask rows
+        occ = fl.fhash_occupancy_grid(bits, dims) if k else None
         models[f"m{k}"] = ResidentModel(index=idx, mlp=fl.mlp_desc(width, mdt),
                                         table=table.to(dt),
                                         params=torch.from_numpy(params).cuda(), mask_bits=bits,
-                                        dims=dims, tf=tf, keep=(dir_t,))
+                                        dims=dims, tf=tf, keep=(dir_t,), occ=occ)
     return fl, models, dims
 
 

@@ -61,3 +61,53 @@ def test_host_calls_reject_bad_arguments():
     fake = C.c_void_p(1 << 20)
     rc = L.fhash_sample(1, 1, 10, None, 8 * 8 * 8 * 2, d, fake, None, bad, fake, fake, None)
     assert rc == fl.EINVAL
+
+
+def test_batched_render_calls_reject_bad_arguments():
+    """Argument checks of the batched render steps run before any device
+    work: batch size, shared states or workspaces, pending flags, paces and
+    the sample capacity."""
+    import ctypes as C
+    import pytest
+    L = fl.lib()
+    opts = fl.render_opts(arm_max=8)
+    sts = []
+    for k in range(3):
+        st = fl.RenderState()
+        st.W, st.H, st.n_alive = 4, 4, 16
+        st.ws = 0x100000 * (k + 1)   # never dereferenced: every call below fails
+        st.dims[:] = [8, 8, 8, 2]
+        sts.append(st)
+    P = C.POINTER(fl.RenderState)
+
+    def march(states, paces, out_base=0, cap=1 << 20):
+        arr = (P * max(len(states), 1))(*[C.pointer(s) for s in states])
+        n = len(states)
+        ns = (C.c_int64 * max(n, 1))()
+        return L.fhash_render_march_batch(arr, (C.c_int32 * max(n, 1))(*paces), n,
+                                          C.byref(opts), C.c_void_p(0x200000), out_base, cap,
+                                          C.c_void_p(0x300000), ns, None)
+
+    def composite(states):
+        n = len(states)
+        arr = (P * max(n, 1))(*[C.pointer(s) for s in states])
+        ptrs = (C.c_void_p * max(n, 1))(*([0x400000] * n))
+        return L.fhash_render_composite_batch(arr, n, C.c_void_p(0x500000), ptrs, ptrs,
+                                              C.byref(opts), C.c_void_p(0x300000), None)
+
+    assert march([], []) == fl.EINVAL
+    assert march([sts[0]] * 33, [1] * 33) == fl.EINVAL             # above the batch maximum
+    assert march([sts[0], sts[1], sts[0]], [1, 1, 1]) == fl.EINVAL  # the same state twice
+    shared = fl.RenderState()
+    C.memmove(C.addressof(shared), C.addressof(sts[1]), C.sizeof(shared))
+    assert march([sts[1], shared], [1, 1]) == fl.EINVAL            # two states, one workspace
+    assert march([sts[0], sts[1]], [1, 0]) == fl.EINVAL            # pace below 1
+    assert march([sts[0], sts[1]], [1, 9]) == fl.EINVAL            # pace above arm_max
+    assert march([sts[0], sts[1]], [2, 2], out_base=5, cap=5 + 63) == fl.EINVAL  # 64 needed
+    assert march([sts[0]], [1], out_base=(1 << 31) - 80, cap=1 << 40) == fl.EINVAL  # 2^31
+    assert march([sts[0]], [1], out_base=-1) == fl.EINVAL
+    assert composite(sts[:2]) == fl.EINVAL                        # nothing marched yet
+    sts[2].pending = 1
+    assert march([sts[0], sts[2]], [1, 1]) == fl.EINVAL            # samples not composited
+    assert composite([sts[2], sts[2]]) == fl.EINVAL
+    assert b"share" in L.fhash_last_error()

@@ -3,10 +3,11 @@
 The executor below models a render as rays of known lengths (lattice samples
 that pass the occupancy test) and a decoder as a fixed function of the sample,
 and moves every sample through one shared buffer exactly like the device
-executor does (march writes at an offset, one decode per model over a range,
-composite reads back at the request's offset).  A bookkeeping mistake (wrong
-offset, a chunk decoded by the wrong model, a request retired early, a budget
-overrun) changes a result or trips an assertion.
+executor does (one march per model group writes the requests' samples
+interleaved, one decode per model over a range, composite reads each ray's run
+back).  A bookkeeping mistake (wrong offset, a chunk decoded by the wrong
+model, a request retired early, a budget overrun) changes a result or trips an
+assertion.
 """
 import numpy as np
 import pytest
@@ -59,20 +60,33 @@ class HostExecutor:
         r.result = r.state["acc"]
         return len(r.state["alive"])
 
-    def march(self, r, pace, off, cap):
-        s = r.state
-        assert pace * len(s["alive"]) <= cap
-        taken, o = [], off
-        for ray in s["alive"]:
-            c = min(pace, s["len"][ray] - s["k"][ray])
-            for j in range(c):
-                self.buf[o] = (r.rid * 100000 + ray, s["k"][ray] + j)
-                o += 1
-            taken.append((ray, c))
-            s["k"][ray] += c
-        s["taken"] = taken
+    def march_batch(self, rs, paces, off):
+        # like the device: one launch for the group, the requests' samples
+        # interleaved ray by ray, each ray's run contiguous at an offset it keeps
+        queues = []
+        for r, pace in zip(rs, paces):
+            s = r.state
+            assert pace >= 1
+            s["taken"] = []
+            queues.append([(r, pace, ray) for ray in s["alive"]])
+        counts = [0] * len(rs)
+        o = off
+        for j in range(max((len(q) for q in queues), default=0)):
+            for i, q in enumerate(queues):
+                if j >= len(q):
+                    continue
+                r, pace, ray = q[j]
+                s = r.state
+                c = min(pace, s["len"][ray] - s["k"][ray])
+                for t in range(c):
+                    self.buf[o + t] = (r.rid * 100000 + ray, s["k"][ray] + t)
+                s["taken"].append((ray, o, c))
+                s["k"][ray] += c
+                o += c
+                counts[i] += c
+        assert o <= self.C
         self.clock += 1e-6 * (o - off)
-        return o - off
+        return counts
 
     def load_points(self, r, start, k, off):
         self.buf[off: off + k, 0] = r.pos[start: start + k]
@@ -85,21 +99,22 @@ class HostExecutor:
         self.buf[start:end] = np.nan
         self.clock += 1e-4
 
-    def composite(self, r):
-        s = r.state
-        o = r.y_off
-        alive = []
-        for ray, c in s["taken"]:
-            for _ in range(c):
-                v = self.y[o]
-                assert np.isfinite(v)
-                s["acc"][ray] += v
-                self.y[o] = np.nan
-                o += 1
-            if s["k"][ray] < s["len"][ray]:
-                alive.append(ray)
-        s["alive"] = alive
-        return len(alive)
+    def composite_batch(self, rs):
+        out = []
+        for r in rs:
+            s = r.state
+            alive = []
+            for ray, o, c in s["taken"]:
+                for j in range(c):
+                    v = self.y[o + j]
+                    assert np.isfinite(v)
+                    s["acc"][ray] += v
+                    self.y[o + j] = np.nan
+                if s["k"][ray] < s["len"][ray]:
+                    alive.append(ray)
+            s["alive"] = alive
+            out.append(len(alive))
+        return out
 
     def store_points(self, r, start, k, off):
         assert np.isfinite(self.y[off: off + k]).all()
@@ -249,13 +264,13 @@ def test_oldest_first_never_starves_and_budget_holds(policy):
     reqs = _mixed_requests(rng, 25)
     ex = HostExecutor(120)
     sch = Scheduler(ex, sample_budget=120, arm_max=16, policy=policy)
-    real = ex.march
+    real = ex.march_batch
 
-    def march(r, pace, off, cap):
-        assert pace >= 1
-        return real(r, pace, off, cap)
+    def march_batch(rs, paces, off):
+        assert all(p >= 1 for p in paces) and len(rs) == len(paces)
+        return real(rs, paces, off)
 
-    ex.march = march
+    ex.march_batch = march_batch
     sch.run(reqs, realtime=True)
     for r in reqs:
         exp = _expected_render(r) if r.kind == "render" else _expected_points(r)
