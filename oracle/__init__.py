@@ -70,6 +70,8 @@ def _declare(L):
     L.or_cell_activity.argtypes = [P, P, P, P]
     L.or_build_level_slots.restype = I64
     L.or_build_level_slots.argtypes = [P, P, P, P]
+    L.or_build_level_slots_bricks.restype = I64
+    L.or_build_level_slots_bricks.argtypes = [P, P, P, P]
     L.or_cell_active_bits.restype = C.c_int
     L.or_cell_active_bits.argtypes = [P, P, P, P]
     L.or_vertex_active_bits.restype = C.c_int
@@ -158,18 +160,26 @@ def cell_activity(res4, mask: np.ndarray) -> np.ndarray:
     return out
 
 
-def level_slots(res4, mask):
-    """Slot map of one level (vertex -> slot within level, -1 inactive), count."""
+LAYOUT_ROWS, LAYOUT_BRICKS = 0, 1
+
+
+def level_slots(res4, mask, layout: int = LAYOUT_ROWS):
+    """Slot map of one level (vertex -> slot within level, -1 inactive), count.
+    layout: rank in the F-Hash equation's order, or in 2^4-vertex bricks."""
     r = _c(res4, np.int64)
     nv = int(np.prod(r))
     out = np.zeros(nv, np.int64)
+    fn = lib().or_build_level_slots_bricks if layout == LAYOUT_BRICKS else \
+        lib().or_build_level_slots
     if mask is None:
         S = np.zeros(4, np.int64)
-        cnt = lib().or_build_level_slots(_p(r), None, _p(S), _p(out))
+        cnt = fn(_p(r), None, _p(S), _p(out))
     else:
         m = _c(mask, np.uint8)
         S = np.array([m.shape[3], m.shape[2], m.shape[1], m.shape[0]], np.int64)
-        cnt = lib().or_build_level_slots(_p(r), _p(m), _p(S), _p(out))
+        cnt = fn(_p(r), _p(m), _p(S), _p(out))
+    if cnt < 0:
+        raise RuntimeError("brick ranking lost a vertex")
     return out, int(cnt)
 
 
@@ -208,15 +218,21 @@ def spatial_hash_slots(res4, bits: int):
 
 class Grid:
     """Oracle-side level structure + (optional) active-vertex slot maps.
-    hash_bits > 0 (no mask): the spatial-hash comparison index."""
+    hash_bits > 0 (no mask): the spatial-hash comparison index.
+    layout: LAYOUT_ROWS (ranks in the F-Hash equation's order) or LAYOUT_BRICKS
+    (ranks in 2 x 2 x 2 x 2 vertex bricks; active index only)."""
 
-    def __init__(self, res, n_features, mask=None, hash_bits: int = 0):
+    def __init__(self, res, n_features, mask=None, hash_bits: int = 0,
+                 layout: int = LAYOUT_ROWS):
         res = np.asarray(res, np.int64).reshape(-1, 4)
         self.res = res
         self.L = res.shape[0]
         self.F = n_features
+        self.layout = layout
         self.maps = []
         self.counts = []
+        if layout == LAYOUT_BRICKS and (mask is None or hash_bits):
+            raise ValueError("the brick order is built for the active-vertex index")
         for l in range(self.L):
             if hash_bits:
                 m, c = spatial_hash_slots(res[l], hash_bits)
@@ -226,7 +242,7 @@ class Grid:
             if mask is None:  # dense box: the slot is the F-Hash equation, no map needed
                 self.counts.append(int(np.prod(res[l])))
                 continue
-            m, c = level_slots(res[l], mask)
+            m, c = level_slots(res[l], mask, layout)
             self.maps.append(m)
             self.counts.append(c)
         self.dense = mask is None and not hash_bits

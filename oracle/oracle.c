@@ -171,6 +171,41 @@ int64_t or_build_level_slots(const int64_t res[4], const uint8_t* mask, const in
   return count;
 }
 
+/* The same active set ranked in another linearisation with preserved locality
+ * (Sec. 3.2.3 allows linearisations other than the F-Hash equation's): the
+ * level is cut into bricks of 2 x 2 x 2 x 2 vertices, brick (bx, by, bz, bt) =
+ * (x/2, y/2, z/2, t/2); bricks are ordered like vertices in the F-Hash
+ * equation (bx fastest, then by, bz, bt) and the vertices inside a brick by
+ *   inner = (x mod 2) + 2 (y mod 2) + 4 (z mod 2) + 8 (t mod 2).
+ * Bricks at an odd upper edge are partial (their missing vertices do not
+ * exist and take no slot).  The slot of an active vertex is its rank among the
+ * active vertices in this order; the map has the same form as above (indexed
+ * by the F-Hash linear vertex id).  mask == NULL makes every vertex active.
+ * Returns the number of active vertices. */
+int64_t or_build_level_slots_bricks(const int64_t res[4], const uint8_t* mask,
+                                    const int64_t S[4], int64_t* slot_map_level) {
+  const int64_t R[4] = {res[0], res[1], res[2], res[3]};
+  const int64_t nv = or_level_vertices(res);
+  /* activity as in the F-Hash order (a map entry >= 0 marks an active vertex) */
+  int64_t count = or_build_level_slots(res, mask, S, slot_map_level);
+  int64_t B[4];
+  for (int d = 0; d < 4; ++d) B[d] = (R[d] + 1) / 2;
+  int64_t next = 0;
+  for (int64_t bt = 0; bt < B[3]; ++bt)
+    for (int64_t bz = 0; bz < B[2]; ++bz)
+      for (int64_t by = 0; by < B[1]; ++by)
+        for (int64_t bx = 0; bx < B[0]; ++bx)
+          for (int inner = 0; inner < 16; ++inner) {
+            const int64_t x = 2 * bx + (inner & 1), y = 2 * by + ((inner >> 1) & 1);
+            const int64_t z = 2 * bz + ((inner >> 2) & 1), t = 2 * bt + ((inner >> 3) & 1);
+            if (x >= R[0] || y >= R[1] || z >= R[2] || t >= R[3]) continue;
+            const int64_t lin = ((t * R[2] + z) * R[1] + y) * R[0] + x;
+            if (slot_map_level[lin] >= 0) slot_map_level[lin] = next++;
+          }
+  (void)nv;
+  return next == count ? count : -1;
+}
+
 /* Activity of one vertex decided from a bit-packed mask, for volumes too large
  * for the whole-level enumeration above.  Same definitions: the vertex is
  * active iff one of the (up to 16) cells having it as a corner contains a

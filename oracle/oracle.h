@@ -50,6 +50,8 @@ void or_cell_activity(const int64_t res[4], const uint8_t* mask, const int64_t S
                       uint8_t* cell_active);
 int64_t or_build_level_slots(const int64_t res[4], const uint8_t* mask, const int64_t S[4],
                              int64_t* slot_map_level);
+int64_t or_build_level_slots_bricks(const int64_t res[4], const uint8_t* mask,
+                                    const int64_t S[4], int64_t* slot_map_level);
 
 int or_cell_active_bits(const int64_t res[4], const uint64_t* bits, const int64_t S[4],
                         const int64_t c[4]);
