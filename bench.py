@@ -127,6 +127,9 @@ def parse():
                          "instead of the vertices of active cells; samples still come from "
                          "the coreset")
     ap.add_argument("--hidden-layers", type=int, default=2)
+    ap.add_argument("--layout", choices=["rows", "bricks"], default="bricks",
+                    help="slot order of the active index: the F-Hash equation's rows, or "
+                         "2x2x2x2 vertex bricks (Sec. 3.2.3 allows other linearisations)")
     ap.add_argument("--sort", action="store_true",
                     help="sort each batch by a 4D Morton key before the fused step")
     ap.add_argument("--field-seed", type=int, default=1002)
@@ -284,7 +287,8 @@ def key_frame_bench(args):
             fl.fhash_sample(seed, 1, P, c, c.numel(), dims, gen["field"], pp, pt, frame_t=ft)
             probes[name] = (pp, pt)
         res = geometric_resolutions(args.levels, 16, 512, 4, rt, dims)
-        cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers)
+        cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers,
+                          layout=LAYOUTS[args.layout])
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3000, lazy=True,
                            max_steps=args.steps + 8)
         torch.cuda.synchronize()
@@ -429,7 +433,8 @@ def serve_multi_bench(args):
             t0 = time.time()
             gen = volume.production_volume(dims, seed=seed)
             res = geometric_resolutions(16, 16, 512, 4, dims[3], dims)
-            cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3)
+            cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3,
+                              layout=LAYOUTS[args.layout])
             model = FHashModel(cfg, gen["bits"], dims, init_seed=seed + 2000, lazy=True,
                                max_steps=args.serve_train_steps + 8)
             B = 1 << 20
@@ -556,7 +561,8 @@ def serve_bench(args):
     gen = volume.production_volume(dims, seed=1003)
     log(f"[serve] volume {dims} in {time.time() - t0:.1f} s; coreset {gen['M']}")
     res = geometric_resolutions(16, 16, 512, 4, dims[3], dims)
-    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3)
+    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3,
+                      layout=LAYOUTS[args.layout])
     model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, lazy=True,
                        max_steps=args.serve_train_steps + 8)
     log(f"[serve] model: {model.rows} active vertices, {model.n_params} params")
@@ -791,6 +797,9 @@ def coreset_bench(args):
                      "traffic": CLASSIFY_TRAFFIC["bytes"] if same else None,
                      "algorithmic_bytes": dom["algorithmic_bytes"], "kernel_ms": dom["ms"]},
         "cpu_baseline": cpu}))
+
+
+LAYOUTS = {"rows": 0, "bricks": 1}
 
 
 # ------------------------------------------------------------------ headline
@@ -1085,7 +1094,8 @@ def headline_bench(args):
     log(f"[headline] volume {dims} in {time.time() - t0:.1f} s; coreset {gen['M']} of "
         f"{gen['N']} voxels")
     res = geometric_resolutions(16, 16, 512, 4, dims[3], dims)
-    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3)
+    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3,
+                      layout=LAYOUTS[args.layout])
     P = 1 << 22
     ppos = torch.empty(P, 4, device="cuda")
     ptgt = torch.empty(P, device="cuda")
@@ -1174,7 +1184,7 @@ def headline_bench(args):
                                "batch 2^20 coreset draws, Adam with deferred large-level "
                                "updates (equal to the dense update bit for bit)",
                    "shape": dims, "levels": 16, "batch": B, "params": mx["params"],
-                   "coreset": gen["M"]},
+                   "coreset": gen["M"], "slot_order": args.layout},
         "paths": {"mixed": mx, "fp32": fp},
         "mixed_over_fp32_samples_per_s": mx["samples_per_s"] / fp["samples_per_s"],
         "equal_psnr": {"target_db": ttp_m["target_db"],
@@ -1223,7 +1233,8 @@ def main():
     log(f"[bench] volume {dims} generated in {time.time() - t0:.1f} s; coreset {gen['M']} "
         f"of {gen['N']} voxels ({gen['M'] / gen['N']:.3f}), threshold {gen['threshold']:.4g}")
     res = geometric_resolutions(args.levels, 16, 512, 4, dims[3], dims)
-    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers)
+    cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers,
+                      layout=LAYOUTS[args.layout])
     t0 = time.time()
     model = FHashModel(cfg, None if args.dense_index else gen["bits"], dims,
                        hash_bits=args.hash_bits, init_seed=3000 + args.field_seed - 1000,
@@ -1365,7 +1376,7 @@ def main():
                                    "level)" if args.hash_bits else "")),
                    "shape": dims, "levels": args.levels, "batch": B,
                    "active_vertices": model.rows, "params": model.n_params,
-                   "coreset": M},
+                   "coreset": M, "slot_order": args.layout},
         "breakdown_ms": {"lazy_mark": mark_ms, "lazy_catch_up": catch_ms,
                          "fused_fwd_bwd": fb_ms, "adam": adam_ms,
                          "final_flush_per_step": flush_ms / args.steps,

@@ -56,10 +56,14 @@ typedef enum { FHASH_F32 = 0, FHASH_F16 = 1, FHASH_BF16 = 2 } fhash_dtype;
  * y * z * t * ceil(x / 64) < 2^31 per level (FHASH_ERANGE otherwise: the
  * kernels index a level's vertex rows and directory words in 32 bits).
  * n_features = F, the embedding size of a vertex (Sec. 4.1): 1, 2, 4 or 8. */
+/* Slot order of an active-vertex index (layout below). */
+enum { FHASH_LAYOUT_ROWS = 0, FHASH_LAYOUT_BRICKS = 1 };
+
 typedef struct {
   int32_t n_levels;
   int32_t n_features;
   int32_t res[FHASH_MAX_LEVELS][4];
+  int32_t layout;  /* FHASH_LAYOUT_ROWS or FHASH_LAYOUT_BRICKS (see the index section) */
 } fhash_grid_desc;
 
 /* Voxel feature mask (the dilated feature region d_k of Sec. 3.1, one bit per
@@ -106,6 +110,19 @@ const char* fhash_last_error(void);
  * (t, z, y): bit b of `bits` is vertex x = 64 w + b, `rank` the number of
  * active vertices before that word in F-Hash order; the entry sits at
  * ((t*Rz + z)*ceil(Rx/64) + w)*Ry + y, so rows y and y+1 are neighbours.
+ *
+ * Brick layout (grid->layout = FHASH_LAYOUT_BRICKS; active index only, Sec.
+ * 3.2.3 allows linearisations other than the F-Hash equation's): the same
+ * active set ranked in bricks of 2 x 2 x 2 x 2 vertices, brick (bx, by, bz, bt)
+ * = (x/2, y/2, z/2, t/2), bricks in the F-Hash equation's order (bx fastest),
+ * vertices inside a brick by inner = x%2 + 2 (y%2) + 4 (z%2) + 8 (t%2); missing
+ * vertices of edge bricks take no slot.  A cell then touches about 5 table
+ * lines instead of 8.  Directory: one entry per 64 bits = 4 bricks of a brick
+ * row (bt, bz, by): bit 16 (bx % 4) + inner of word bx / 4, `rank` the active
+ * vertices before the word in brick order; the entry sits at
+ * ((bt*Bz + bz)*Wb + w)*By + by, Bz = ceil(Rz/2), By = ceil(Ry/2),
+ * Wb = ceil(ceil(Rx/2)/4).  fhash_dense_index and fhash_hash_index return
+ * FHASH_ENOTSUP for this layout.
  *
  * fhash_index_dir_entries: number of 16-byte directory entries the grid needs
  * (0 for a dense index is not implied: the size is for the active form).

@@ -29,9 +29,12 @@ class FHashError(RuntimeError):
         self.code = code
 
 
+LAYOUT_ROWS, LAYOUT_BRICKS = 0, 1
+
+
 class GridDesc(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("n_features", C.c_int32),
-                ("res", (C.c_int32 * 4) * MAX_LEVELS)]
+                ("res", (C.c_int32 * 4) * MAX_LEVELS), ("layout", C.c_int32)]
 
 
 class MaskDesc(C.Structure):
@@ -235,10 +238,11 @@ def _dt(t: torch.Tensor) -> int:
 
 
 # --------------------------------------------------------------------------- descriptors
-def grid_desc(res, n_features: int) -> GridDesc:
+def grid_desc(res, n_features: int, layout: int = LAYOUT_ROWS) -> GridDesc:
     g = GridDesc()
     g.n_levels = len(res)
     g.n_features = n_features
+    g.layout = layout
     for l, r in enumerate(res):
         for d in range(4):
             g.res[l][d] = int(r[d])

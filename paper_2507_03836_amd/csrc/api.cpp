@@ -51,9 +51,13 @@ int check_grid(const fhash_grid_desc* g) {
     // the kernels index a level's vertex rows and directory words in 32 bits
     const double words = (double)g->res[l][1] * g->res[l][2] * g->res[l][3] *
                          (double)((g->res[l][0] + 63) / 64);
-    if (words >= 2147483648.0)
+    const double bwords = (double)((g->res[l][1] + 1) / 2) * ((g->res[l][2] + 1) / 2) *
+                          ((g->res[l][3] + 1) / 2) * (double)(((g->res[l][0] + 1) / 2 + 3) / 4);
+    if (words >= 2147483648.0 || (g->layout == FHASH_LAYOUT_BRICKS && bwords >= 2147483648.0))
       return fail(FHASH_ERANGE, "level %d has 2^31 directory words or more", l);
   }
+  if (g->layout != FHASH_LAYOUT_ROWS && g->layout != FHASH_LAYOUT_BRICKS)
+    return fail(FHASH_EINVAL, "layout %d is neither rows nor bricks", g->layout);
   return FHASH_OK;
 }
 
@@ -160,6 +164,8 @@ int fhash_index_dir_entries(const fhash_grid_desc* grid, int64_t* entries) {
 int fhash_dense_index(const fhash_grid_desc* grid, fhash_index* out, int64_t* slots_per_level) {
   int rc = check_grid(grid);
   if (rc) return rc;
+  if (grid->layout != FHASH_LAYOUT_ROWS)
+    return fail(FHASH_ENOTSUP, "the brick layout is built for the active-vertex index only");
   if (out == nullptr) return fail(FHASH_EINVAL, "out is NULL");
   std::memset(out, 0, sizeof(*out));
   out->grid = *grid;

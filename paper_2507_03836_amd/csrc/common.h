@@ -11,11 +11,13 @@ namespace fh {
 struct LevelDev {
   int32_t rx, ry, rz, rt;  // vertex counts
   float sx, sy, sz, st;    // (float)(R - 1), the FP32 scale of cell location
-  int32_t wv;              // directory words per vertex row: ceil(rx / 64)
+  int32_t wv;              // directory words per vertex row: ceil(rx / 64); bricks:
+                           // words per brick row, ceil(ceil(rx / 2) / 4)
   int32_t hash_bits;       // 0, or b: the level's vertices hash into 2^b rows
   int64_t slot_off;        // first table row of the level
   int64_t dir_off;         // first directory entry of the level
-  int64_t pad1;
+  int32_t brick;           // 1: slots ranked in 2^4-vertex bricks
+  int32_t by;              // brick rows per (bt, bz): ceil(ry / 2)
 };
 static_assert(sizeof(LevelDev) == 64, "LevelDev layout");
 
@@ -50,7 +52,9 @@ inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
       d.sy = (float)(d.ry - 1);
       d.sz = (float)(d.rz - 1);
       d.st = (float)(d.rt - 1);
-      d.wv = (d.rx + 63) / 64;
+      d.brick = gd.layout == FHASH_LAYOUT_BRICKS ? 1 : 0;
+      d.wv = d.brick ? ((d.rx + 1) / 2 + 3) / 4 : (d.rx + 63) / 64;
+      d.by = (d.ry + 1) / 2;
       d.slot_off = idx->slot_offset[l];
       d.dir_off = idx->dir_offset[l];
       const double nv = (double)d.rx * d.ry * d.rz * d.rt;
@@ -58,7 +62,6 @@ inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
     } else {
       d = LevelDev{};
     }
-    d.pad1 = 0;
   }
 }
 
@@ -75,22 +78,55 @@ __device__ __forceinline__ void locate(float p, int R, float s, int& cell, float
   frac = __fsub_rn(u, (float)i);
 }
 
-// Slots of the vertex pair (x, x+1) on vertex row (tz = t*Rz + z, y) of a
-// level.  Dense: the F-Hash equation; active: rank in the directory entry of
-// the word holding x.  Directory entries are stored ((tz*Wv + word)*Ry + y)
-// (rows y and y+1 of a cell are neighbours); the row and word indices are
-// 32-bit: the host rejects levels with 2^31 directory words or more.
 // Row of vertex (x, y, z, t) in a hashed level (see fhash_hash_index).
 __device__ __forceinline__ uint32_t spatial_hash(uint32_t x, uint32_t yzt, uint32_t mask) {
   return (x ^ yzt) & mask;
 }
 
+// Rank-directory lookup: slot of bit b of entry e (valid iff the bit is set).
+__device__ __forceinline__ int64_t entry_slot(const ulonglong2& e, int b, int64_t slot_off,
+                                              bool& valid) {
+  valid = (e.x >> b) & 1ull;
+  const uint64_t below = (b == 0) ? 0ull : (e.x & ((1ull << b) - 1ull));
+  return slot_off + (int64_t)e.y + __popcll(below);
+}
+
+// Directory entries holding vertices x and x+1 of vertex row (t, z, y) of an
+// active level (w1 = w0 when both sit in one entry).  Rows layout: entries
+// ((t*Rz + z)*Wv + word)*Ry + y (rows y and y+1 of a cell are neighbours);
+// bricks: ((bt*Bz + bz)*Wb + word)*By + by.  Bit positions in b0, b1.  Row,
+// word and entry indices are 32-bit: the host rejects levels with 2^31
+// directory entries or more.
+__device__ __forceinline__ void pair_entries(const LevelDev& d, int32_t t, int32_t z, int32_t y,
+                                             int x, int64_t& w0, int64_t& w1, int& b0, int& b1) {
+  if (d.brick) {
+    const int inner = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2) | ((t & 1) << 3);
+    const int bit0 = (x >> 1) * 16 + inner;
+    // x odd: x + 1 is the first x of the next brick, 15 bits further on
+    const int bit1 = (x & 1) ? bit0 + 15 : bit0 + 1;
+    const int32_t btz = (t >> 1) * ((d.rz + 1) >> 1) + (z >> 1);
+    w0 = d.dir_off + (int64_t)((btz * d.wv + (bit0 >> 6)) * d.by + (y >> 1));
+    w1 = ((bit1 >> 6) == (bit0 >> 6)) ? w0 : w0 + d.by;
+    b0 = bit0 & 63;
+    b1 = bit1 & 63;
+  } else {
+    const int32_t tz = t * d.rz + z;
+    w0 = d.dir_off + (int64_t)((tz * d.wv + (x >> 6)) * d.ry + y);
+    w1 = ((x & 63) == 63) ? w0 + d.ry : w0;
+    b0 = x & 63;
+    b1 = (x + 1) & 63;
+  }
+}
+
+// Slots of the vertex pair (x, x+1) on vertex row (t, z, y) of a level.
+// Dense: the F-Hash equation; hashed: the spatial hash; active: ranks in the
+// directory (rows or bricks layout, see pair_entries).
 __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglong2* dir,
-                                               bool active, int32_t tz, int32_t y, int x,
+                                               bool active, int32_t t, int32_t z, int32_t y, int x,
                                                int64_t& s0, int64_t& s1, bool& v0, bool& v1) {
   if (d.hash_bits) {
-    const uint32_t t = (uint32_t)tz / (uint32_t)d.rz, z = (uint32_t)tz - t * (uint32_t)d.rz;
-    const uint32_t yzt = (uint32_t)y * 2654435761u ^ z * 805459861u ^ t * 3674653429u;
+    const uint32_t yzt = (uint32_t)y * 2654435761u ^ (uint32_t)z * 805459861u ^
+                         (uint32_t)t * 3674653429u;
     const uint32_t mask = (d.hash_bits >= 32) ? 0xffffffffu : ((1u << d.hash_bits) - 1u);
     s0 = d.slot_off + spatial_hash((uint32_t)x, yzt, mask);
     s1 = d.slot_off + spatial_hash((uint32_t)x + 1u, yzt, mask);
@@ -98,24 +134,25 @@ __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglon
     return;
   }
   if (!active) {
-    s0 = d.slot_off + ((int64_t)tz * d.ry + y) * d.rx + x;
+    s0 = d.slot_off + ((int64_t)(t * d.rz + z) * d.ry + y) * d.rx + x;
     s1 = s0 + 1;
     v0 = v1 = true;
     return;
   }
-  const int64_t w = d.dir_off + (int64_t)((tz * d.wv + (x >> 6)) * d.ry + y);
-  const int b = x & 63;
-  const ulonglong2 e = dir[w];
-  const uint64_t below = (b == 0) ? 0ull : (e.x & ((1ull << b) - 1ull));
-  v0 = (e.x >> b) & 1ull;
-  s0 = d.slot_off + (int64_t)e.y + __popcll(below);
-  if (b < 63) {
-    v1 = (e.x >> (b + 1)) & 1ull;
-    s1 = s0 + (v0 ? 1 : 0);
+  int64_t w0, w1;
+  int b0, b1;
+  pair_entries(d, t, z, y, x, w0, w1, b0, b1);
+  const ulonglong2 e = dir[w0];
+  s0 = entry_slot(e, b0, d.slot_off, v0);
+  if (w1 == w0) {
+    if (b1 == b0 + 1) {  // neighbouring bits: the next slot
+      v1 = (e.x >> b1) & 1ull;
+      s1 = s0 + (v0 ? 1 : 0);
+    } else {
+      s1 = entry_slot(e, b1, d.slot_off, v1);
+    }
   } else {
-    const ulonglong2 e1 = dir[w + d.ry];  // next word of the same row
-    v1 = e1.x & 1ull;
-    s1 = d.slot_off + (int64_t)e1.y;
+    s1 = entry_slot(dir[w1], b1, d.slot_off, v1);
   }
 }
 #endif

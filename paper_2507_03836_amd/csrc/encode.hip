@@ -64,15 +64,17 @@ __global__ void __launch_bounds__(256)
   const bool active = g.active != 0 && d.hash_bits == 0;
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int32_t tz = (it + dt) * d.rz + (iz + dz);
     int64_t s0, s1;
     bool v0, v1;
-    row_pair_slots(d, g.dir, g.active != 0, tz, iy + dy, ix, s0, s1, v0, v1);
+    row_pair_slots(d, g.dir, g.active != 0, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
     const int64_t o = (t * 8 + r) * 2;
     long long w0 = -1, w1 = -1;
     if (active) {
-      w0 = d.dir_off + (int64_t)((tz * d.wv + (ix >> 6)) * d.ry + iy + dy);
-      if ((ix & 63) == 63) w1 = w0 + d.ry;
+      int64_t e0, e1;
+      int b0, b1;
+      pair_entries(d, it + dt, iz + dz, iy + dy, ix, e0, e1, b0, b1);
+      w0 = e0;
+      if (e1 != e0) w1 = e1;
     }
     out_dir[o] = w0;
     out_dir[o + 1] = w1;

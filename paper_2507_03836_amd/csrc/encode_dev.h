@@ -98,11 +98,10 @@ __device__ __forceinline__ void encode_level(const LevelDev& d, const ulonglong2
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int32_t tz = (it + dt) * d.rz + (iz + dz);
     const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
     int64_t s0, s1;
     bool v0, v1;
-    row_pair_slots(d, dir, active, tz, iy + dy, ix, s0, s1, v0, v1);
+    row_pair_slots(d, dir, active, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
     float e0[F], e1[F];
     RowLoad<F, T>::load(table, v0 ? s0 : 0, e0);
     RowLoad<F, T>::load(table, v1 ? s1 : 0, e1);
@@ -138,11 +137,10 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int32_t tz = (it + dt) * d.rz + (iz + dz);
     const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
     int64_t s0, s1;
     bool v0, v1;
-    row_pair_slots(d, dir, active, tz, iy + dy, ix, s0, s1, v0, v1);
+    row_pair_slots(d, dir, active, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
     const float w0 = wr * (1.0f - fx), w1 = wr * fx;
     if (v0) {
 #pragma unroll
@@ -178,11 +176,10 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int32_t tz = (it + dt) * d.rz + (iz + dz);
     const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
     int64_t s0, s1;
     bool v0, v1;
-    row_pair_slots(d, dir, active, tz, iy + dy, ix, s0, s1, v0, v1);
+    row_pair_slots(d, dir, active, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
     const int64_t s = e ? s1 : s0;
     if (e ? v1 : v0) {
       unsafeAtomicAdd(d_table + s * F + f, wr * wx * gval);
@@ -213,11 +210,10 @@ __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulo
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const int32_t tz = (it + dt) * d.rz + (iz + dz);
     const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
     int64_t s2[2];
     bool v2[2];
-    row_pair_slots(d, dir, active, tz, iy + dy, ix, s2[0], s2[1], v2[0], v2[1]);
+    row_pair_slots(d, dir, active, it + dt, iz + dz, iy + dy, ix, s2[0], s2[1], v2[0], v2[1]);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int64_t s = (valid && v2[e]) ? s2[e] : -1;

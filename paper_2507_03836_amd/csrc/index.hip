@@ -127,6 +127,37 @@ __global__ void dir_interleave_kernel(const ulonglong2* __restrict__ src,
   }
 }
 
+// Brick order (layout FHASH_LAYOUT_BRICKS): word w of brick row (bt, bz, by)
+// holds bricks bx = 4w .. 4w+3, brick q at bits 16q .. 16q+15, vertex inner
+// index (x%2) | (y%2)<<1 | (z%2)<<2 | (t%2)<<3.  Built from the row-major
+// vertex bits (rows (t, z, y) of wv words): the 8 x bits 8w .. 8w+7 of each of
+// the brick row's 8 vertex rows lie in one row word.  Output in brick-linear
+// order (((bt*Bz + bz)*By + by)*Wb + w), ranks still to be written.
+__global__ void brickify_kernel(const ulonglong2* __restrict__ rows, ulonglong2* __restrict__ out,
+                                int64_t rx, int64_t ry, int64_t rz, int64_t rt, int64_t wv,
+                                int64_t wb, int64_t by_n, int64_t bz_n, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = e % wb, row = e / wb;
+    const int64_t by = row % by_n, bz = (row / by_n) % bz_n, bt = row / (by_n * bz_n);
+    uint64_t bits = 0;
+    for (int c = 0; c < 8; ++c) {  // (y%2, z%2, t%2) of the vertex row
+      const int64_t y = 2 * by + (c & 1), z = 2 * bz + ((c >> 1) & 1), t = 2 * bt + (c >> 2);
+      if (y >= ry || z >= rz || t >= rt) continue;
+      const int64_t x0 = 8 * w;  // x bits 8w .. 8w+7 (x >= rx reads the row's zero padding)
+      if (x0 >= rx) continue;
+      const uint64_t xb = (rows[((t * rz + z) * ry + y) * wv + (x0 >> 6)].x >> (x0 & 63)) & 0xFFull;
+      for (int q = 0; q < 4; ++q)
+        for (int ix = 0; ix < 2; ++ix)
+          if ((xb >> (2 * q + ix)) & 1ull) bits |= 1ull << (16 * q + (ix | (c << 1)));
+    }
+    ulonglong2 ent;
+    ent.x = bits;
+    ent.y = 0;
+    out[e] = ent;
+  }
+}
+
 constexpr int kScanThreads = 256;
 constexpr int kScanPerThread = 8;
 constexpr int64_t kScanBlockWords = kScanThreads * kScanPerThread;
@@ -222,6 +253,7 @@ inline int grid_for(int64_t total, int threads) {
 struct LevelSizes {
   int64_t Ct, Cz, Cy, Cx, Wm, Wc, Wv;
   int64_t A, B, Cb, cell, D1, D2, D3, words, nb;
+  int64_t Bx, By, Bz, Bt, Wb, bwords, bnb;  // brick layout
 };
 
 LevelSizes level_sizes(const int32_t* r, const int64_t* dims) {
@@ -243,6 +275,13 @@ LevelSizes level_sizes(const int32_t* r, const int64_t* dims) {
   s.D3 = (int64_t)r[3] * r[2] * r[1] * s.Wc;
   s.words = (int64_t)r[3] * r[2] * r[1] * s.Wv;
   s.nb = (s.words + kScanBlockWords - 1) / kScanBlockWords;
+  s.Bx = ((int64_t)r[0] + 1) / 2;
+  s.By = ((int64_t)r[1] + 1) / 2;
+  s.Bz = ((int64_t)r[2] + 1) / 2;
+  s.Bt = ((int64_t)r[3] + 1) / 2;
+  s.Wb = (s.Bx + 3) / 4;
+  s.bwords = s.Bt * s.Bz * s.By * s.Wb;
+  s.bnb = (s.bwords + kScanBlockWords - 1) / kScanBlockWords;
   return s;
 }
 
@@ -252,6 +291,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int64_t index_dir_words(const fhash_grid_desc* g, int l) {
   const int32_t* r = g->res[l];
+  if (g->layout == FHASH_LAYOUT_BRICKS)
+    return (((int64_t)r[3] + 1) / 2) * (((int64_t)r[2] + 1) / 2) * (((int64_t)r[1] + 1) / 2) *
+           ((((int64_t)r[0] + 1) / 2 + 3) / 4);
   return (int64_t)r[3] * r[2] * r[1] * (((int64_t)r[0] + 63) / 64);
 }
 
@@ -263,21 +305,29 @@ size_t index_workspace_bytes(const fhash_grid_desc* g, const int64_t* dims) {
     b1 = std::max(b1, std::max(std::max(s.B, s.cell), s.D2));
     nb = std::max(nb, s.nb);
   }
-  int64_t words = 1;
-  for (int l = 0; l < g->n_levels; ++l) words = std::max(words, level_sizes(g->res[l], dims).words);
+  int64_t words = 1, bwords = 1;
+  for (int l = 0; l < g->n_levels; ++l) {
+    LevelSizes ls = level_sizes(g->res[l], dims);
+    words = std::max(words, ls.words);
+    bwords = std::max(bwords, ls.bwords);
+    nb = std::max(nb, ls.bnb);
+  }
+  const bool bricks = g->layout == FHASH_LAYOUT_BRICKS;
   return align256(b0 * 8) + align256(b1 * 8) + align256(nb * 8) + align256(8 * FHASH_MAX_LEVELS) +
-         align256(words * 16);
+         align256(words * 16) + (bricks ? align256(bwords * 16) : 0);
 }
 
 hipError_t launch_build_index(const fhash_grid_desc* g, const uint64_t* mask,
                               const int64_t* dims, ulonglong2* dir, const int64_t* dir_off,
                               void* ws, uint64_t* counts_host, hipStream_t st) {
-  int64_t b0 = 1, b1 = 1, nbmax = 1;
+  const bool bricks = g->layout == FHASH_LAYOUT_BRICKS;
+  int64_t b0 = 1, b1 = 1, nbmax = 1, wmax = 1;
   for (int l = 0; l < g->n_levels; ++l) {
     LevelSizes s = level_sizes(g->res[l], dims);
     b0 = std::max(b0, std::max(std::max(s.A, s.Cb), std::max(s.D1, s.D3)));
     b1 = std::max(b1, std::max(std::max(s.B, s.cell), s.D2));
-    nbmax = std::max(nbmax, s.nb);
+    nbmax = std::max(nbmax, std::max(s.nb, s.bnb));
+    wmax = std::max(wmax, s.words);
   }
   char* p = static_cast<char*>(ws);
   uint64_t* buf0 = reinterpret_cast<uint64_t*>(p);
@@ -289,6 +339,8 @@ hipError_t launch_build_index(const fhash_grid_desc* g, const uint64_t* mask,
   uint64_t* counts = reinterpret_cast<uint64_t*>(p);
   p += align256(8 * FHASH_MAX_LEVELS);
   ulonglong2* rowmajor = reinterpret_cast<ulonglong2*>(p);  // one level's directory, F-Hash order
+  p += align256(wmax * 16);
+  ulonglong2* bricked = reinterpret_cast<ulonglong2*>(p);   // brick-linear order (bricks only)
 
   const int T = 256;
   const int64_t Sx = dims[0], Sy = dims[1], Sz = dims[2], St = dims[3];
@@ -314,15 +366,29 @@ hipError_t launch_build_index(const fhash_grid_desc* g, const uint64_t* mask,
     ulonglong2* d = rowmajor;
     hipLaunchKernelGGL(vert_x_kernel, dim3(grid_for(s.words, T)), dim3(T), 0, st, buf0, d,
                        (int64_t)r[3] * r[2] * r[1], s.Wc, s.Wv);
+    // Order of the ranks: F-Hash rows, or bricks (then the words are regrouped first).
+    int64_t words = s.words, nb = s.nb, nrows = (int64_t)r[3] * r[2] * r[1], ry = r[1],
+            wv = s.Wv;
+    if (bricks) {
+      hipLaunchKernelGGL(brickify_kernel, dim3(grid_for(s.bwords, T)), dim3(T), 0, st, rowmajor,
+                         bricked, (int64_t)r[0], (int64_t)r[1], (int64_t)r[2], (int64_t)r[3],
+                         s.Wv, s.Wb, s.By, s.Bz, s.bwords);
+      d = bricked;
+      words = s.bwords;
+      nb = s.bnb;
+      nrows = s.Bt * s.Bz * s.By;
+      ry = s.By;
+      wv = s.Wb;
+    }
     // Ranks: exclusive prefix sum of popcounts.
-    hipLaunchKernelGGL(popc_block_sums_kernel, dim3((unsigned)s.nb), dim3(kScanThreads), 0, st,
-                       d, s.words, partial);
-    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, st, partial, s.nb,
+    hipLaunchKernelGGL(popc_block_sums_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st,
+                       d, words, partial);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(1024), 0, st, partial, nb,
                        counts + l);
-    hipLaunchKernelGGL(write_ranks_kernel, dim3((unsigned)s.nb), dim3(kScanThreads), 0, st, d,
-                       s.words, partial);
-    hipLaunchKernelGGL(dir_interleave_kernel, dim3(grid_for(s.words, T)), dim3(T), 0, st, d,
-                       dir + dir_off[l], (int64_t)r[3] * r[2] * r[1], (int64_t)r[1], s.Wv);
+    hipLaunchKernelGGL(write_ranks_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, d,
+                       words, partial);
+    hipLaunchKernelGGL(dir_interleave_kernel, dim3(grid_for(words, T)), dim3(T), 0, st, d,
+                       dir + dir_off[l], nrows, ry, wv);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

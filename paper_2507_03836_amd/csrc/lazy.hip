@@ -224,10 +224,9 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-        const int32_t tz = (it + dt) * d.rz + (iz + dz);
         int64_t s0, s1;
         bool v0, v1;
-        row_pair_slots(d, g.dir, g.active != 0, tz, iy + dy, ix, s0, s1, v0, v1);
+        row_pair_slots(d, g.dir, g.active != 0, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
         cand[2 * r] = cand[2 * r + 1] = 0;
         prev[2 * r] = prev[2 * r + 1] = 0;
         if (live && (v0 || v1)) {

@@ -46,6 +46,7 @@ class FHashConfig:
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-8
+    layout: int = 0           # slot order of the active index: 0 rows (F-Hash order), 1 bricks
 
     @property
     def n_levels(self) -> int:
@@ -88,7 +89,8 @@ class FHashModel:
         self.precision = precision
         self.decoder = decoder
         self.device = torch.device(device)
-        self.grid = fl.grid_desc(cfg.res, cfg.n_features)
+        self.grid = fl.grid_desc(cfg.res, cfg.n_features,
+                                 fl.LAYOUT_ROWS if mask_bits is None else cfg.layout)
         self.mlp = fl.mlp_desc(cfg.width, {"f32": fl.F32, "f16": fl.F16, "bf16": fl.BF16}[decoder])
         if hash_bits:  # spatial-hash comparison index (mask not used)
             self.index, self.slots_per_level = fl.fhash_hash_index(self.grid, hash_bits)

@@ -87,6 +87,16 @@ def test_level_row_limit_reported_as_erange():
     assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.ERANGE
     g = fl.grid_desc([[64, 2048, 2048, 511]], 2)      # just below
     assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.OK
+    # brick layout: ceil(Ry/2) ceil(Rz/2) ceil(Rt/2) ceil(ceil(Rx/2)/4) entries
+    g = fl.grid_desc([[64, 2048, 2048, 511]], 2, fl.LAYOUT_BRICKS)   # 1024^2 x 256 x 8 = 2^31
+    assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.ERANGE
+    g = fl.grid_desc([[62, 2048, 2048, 511]], 2, fl.LAYOUT_BRICKS)   # x 31 bricks: 8 words
+    assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.ERANGE
+    g = fl.grid_desc([[56, 2048, 2048, 511]], 2, fl.LAYOUT_BRICKS)   # 28 bricks: 7 words
+    assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.OK
+    assert e.value == 1024 * 1024 * 256 * 7
+    g.layout = 2
+    assert L.fhash_index_dir_entries(ctypes.byref(g), ctypes.byref(e)) == fl.EINVAL
 
 
 def test_lazy_descriptor_validated_before_any_launch():
