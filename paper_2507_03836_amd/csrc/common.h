@@ -118,6 +118,27 @@ __device__ __forceinline__ void pair_entries(const LevelDev& d, int32_t t, int32
   }
 }
 
+// Brick layout: the 16 corners of a cell are taken as 8 pairs along one axis
+// a, the first axis (x, y, z, t) whose cell index is even, so that both
+// corners of every pair lie in one brick (neighbouring rows, or rows 2^a apart
+// inside it) and a pair's atomics stay one memory transaction; x when every
+// index is odd (pairs then straddle two bricks).  Rows layout: a = 0, pairs
+// along x (the vertex rows of the F-Hash order).
+__device__ __forceinline__ int pair_axis(const LevelDev& d, int cx, int cy, int cz, int ct) {
+  if (!d.brick) return 0;
+  return !(cx & 1) ? 0 : !(cy & 1) ? 1 : !(cz & 1) ? 2 : !(ct & 1) ? 3 : 0;
+}
+
+// Offsets of corner pair r (0..7) of a cell paired along axis a: the other
+// three axes, in increasing order, take bits 0, 1, 2 of r (the pair's own
+// axis is 0 for its first corner, 1 for its second).
+__device__ __forceinline__ void pair_offsets(int r, int a, int& ox, int& oy, int& oz, int& ot) {
+  ox = a == 0 ? 0 : (r & 1);
+  oy = a == 1 ? 0 : (a == 0 ? (r & 1) : ((r >> 1) & 1));
+  oz = a == 2 ? 0 : (a == 3 ? ((r >> 2) & 1) : ((r >> 1) & 1));
+  ot = a == 3 ? 0 : ((r >> 2) & 1);
+}
+
 // Slots of the vertex pair (x, x+1) on vertex row (t, z, y) of a level.
 // Dense: the F-Hash equation; hashed: the spatial hash; active: ranks in the
 // directory (rows or bricks layout, see pair_entries).
@@ -154,6 +175,48 @@ __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglon
   } else {
     s1 = entry_slot(dir[w1], b1, d.slot_off, v1);
   }
+}
+
+// Corner pair r of the cell (cx, cy, cz, ct) with in-cell fractions (fx, fy,
+// fz, ft), paired along axis a (pair_axis): the two slots and validities and
+// the product wr of the three other axes' weights (the pair's own weights are
+// wr (1 - f_a) and wr f_a, f_a = pair_frac).  Rows layout: the x-pair of row
+// (dy, dz, dt) = bits of r, exactly as the vertex rows are visited.
+__device__ __forceinline__ void corner_pair(const LevelDev& d, const ulonglong2* dir, bool active,
+                                            int cx, int cy, int cz, int ct, float fx, float fy,
+                                            float fz, float ft, int a, int r, int64_t& s0,
+                                            int64_t& s1, bool& v0, bool& v1, float& wr) {
+  if (!d.brick) {
+    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
+    wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
+    row_pair_slots(d, dir, active, ct + dt, cz + dz, cy + dy, cx, s0, s1, v0, v1);
+    return;
+  }
+  int ox, oy, oz, ot;
+  pair_offsets(r, a, ox, oy, oz, ot);
+  const float gx = a == 0 ? 1.0f : (ox ? fx : 1.0f - fx);
+  const float gy = a == 1 ? 1.0f : (oy ? fy : 1.0f - fy);
+  const float gz = a == 2 ? 1.0f : (oz ? fz : 1.0f - fz);
+  const float gt = a == 3 ? 1.0f : (ot ? ft : 1.0f - ft);
+  wr = ((gx * gy) * gz) * gt;
+  const int x = cx + ox, y = cy + oy, z = cz + oz, t = ct + ot;
+  if (a == 0) {  // x pair (neighbouring rows, or the next brick when x is odd)
+    row_pair_slots(d, dir, active, t, z, y, x, s0, s1, v0, v1);
+    return;
+  }
+  // the pair's axis has an even index: both corners in one brick, inner bits
+  // 2^a apart, so in one directory word
+  const int inner = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2) | ((t & 1) << 3);
+  const int bit0 = (x >> 1) * 16 + inner;
+  const int32_t btz = (t >> 1) * ((d.rz + 1) >> 1) + (z >> 1);
+  const ulonglong2 e =
+      dir[d.dir_off + (int64_t)((btz * d.wv + (bit0 >> 6)) * d.by + (y >> 1))];
+  s0 = entry_slot(e, bit0 & 63, d.slot_off, v0);
+  s1 = entry_slot(e, (bit0 & 63) + (1 << a), d.slot_off, v1);
+}
+
+__device__ __forceinline__ float pair_frac(int a, float fx, float fy, float fz, float ft) {
+  return a == 0 ? fx : a == 1 ? fy : a == 2 ? fz : ft;
 }
 #endif
 

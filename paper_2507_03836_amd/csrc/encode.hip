@@ -45,7 +45,9 @@ __global__ void __launch_bounds__(256)
 }
 
 // Instrumentation: per (sample, level) the directory entries and table rows the
-// 8 corner rows (dy, dz, dt) = (r & 1, r >> 1 & 1, r >> 2) of its cell touch.
+// 8 corner pairs of its cell touch (corner_pair: rows layout, pair r = the
+// x-pair of row (dy, dz, dt) = (r & 1, r >> 1 & 1, r >> 2); bricks, pairs along
+// pair_axis).
 __global__ void __launch_bounds__(256)
     corner_rows_kernel(GridDev g, const float4* __restrict__ pos, int64_t n,
                        long long* __restrict__ out_dir, long long* __restrict__ out_slot) {
@@ -62,19 +64,25 @@ __global__ void __launch_bounds__(256)
   locate(p.z, d.rz, d.sz, iz, fz);
   locate(p.w, d.rt, d.st, it, ft);
   const bool active = g.active != 0 && d.hash_bits == 0;
+  const int a = pair_axis(d, ix, iy, iz, it);
   for (int r = 0; r < 8; ++r) {
-    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
+    float wr;
     int64_t s0, s1;
     bool v0, v1;
-    row_pair_slots(d, g.dir, g.active != 0, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
+    corner_pair(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1,
+                wr);
     const int64_t o = (t * 8 + r) * 2;
     long long w0 = -1, w1 = -1;
     if (active) {
+      int ox = 0, oy = r & 1, oz = (r >> 1) & 1, ot = r >> 2;
+      if (d.brick) pair_offsets(r, a, ox, oy, oz, ot);
       int64_t e0, e1;
       int b0, b1;
-      pair_entries(d, it + dt, iz + dz, iy + dy, ix, e0, e1, b0, b1);
+      // the entries of the pair's first corner and of its x neighbour (the
+      // second corner shares the first one's entry unless the pair is along x)
+      pair_entries(d, it + ot, iz + oz, iy + oy, ix + ox, e0, e1, b0, b1);
       w0 = e0;
-      if (e1 != e0) w1 = e1;
+      if (a == 0 && e1 != e0) w1 = e1;
     }
     out_dir[o] = w0;
     out_dir[o + 1] = w1;

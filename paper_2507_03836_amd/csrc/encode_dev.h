@@ -95,18 +95,19 @@ __device__ __forceinline__ void encode_level(const LevelDev& d, const ulonglong2
   float acc[F];
 #pragma unroll
   for (int k = 0; k < F; ++k) acc[k] = 0.0f;
+  const int a = pair_axis(d, ix, iy, iz, it);
+  const float fa = pair_frac(a, fx, fy, fz, ft);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
+    float wr;
     int64_t s0, s1;
     bool v0, v1;
-    row_pair_slots(d, dir, active, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
+    corner_pair(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
     float e0[F], e1[F];
     RowLoad<F, T>::load(table, v0 ? s0 : 0, e0);
     RowLoad<F, T>::load(table, v1 ? s1 : 0, e1);
-    const float w0 = v0 ? wr * (1.0f - fx) : 0.0f;
-    const float w1 = v1 ? wr * fx : 0.0f;
+    const float w0 = v0 ? wr * (1.0f - fa) : 0.0f;
+    const float w1 = v1 ? wr * fa : 0.0f;
 #pragma unroll
     for (int k = 0; k < F; ++k) acc[k] += w0 * e0[k] + w1 * e1[k];
   }
@@ -134,14 +135,15 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
   locate(p.y, d.ry, d.sy, iy, fy);
   locate(p.z, d.rz, d.sz, iz, fz);
   locate(p.w, d.rt, d.st, it, ft);
+  const int a = pair_axis(d, ix, iy, iz, it);
+  const float fa = pair_frac(a, fx, fy, fz, ft);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
+    float wr;
     int64_t s0, s1;
     bool v0, v1;
-    row_pair_slots(d, dir, active, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
-    const float w0 = wr * (1.0f - fx), w1 = wr * fx;
+    corner_pair(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
+    const float w0 = wr * (1.0f - fa), w1 = wr * fa;
     if (v0) {
 #pragma unroll
       for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + s0 * F + k, w0 * g[k]);
@@ -156,9 +158,11 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
 }
 
 // One lane's share of a level's scatter-add.  The lane owns pair element e
-// (vertex x or x+1 of every cell row) and feature f of one sample: 2F
-// consecutive lanes own one sample, so the 2F atomics they issue together hit
-// the 8F contiguous bytes of the row pair's two slots.  Atomics of one
+// (the first or second corner of every corner pair, corner_pair) and feature f
+// of one sample: 2F consecutive lanes own one sample, so the 2F atomics they
+// issue together hit the two slots of one pair (8F contiguous bytes in the
+// rows layout and for x pairs inside a brick; 4F-byte halves a few rows apart
+// inside one brick otherwise).  Atomics of one
 // instruction that fall in the same 64-byte segment are performed as one
 // memory transaction, which is what bounds the scatter on gfx950.
 template <int F>
@@ -172,14 +176,15 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
   locate(p.y, d.ry, d.sy, iy, fy);
   locate(p.z, d.rz, d.sz, iz, fz);
   locate(p.w, d.rt, d.st, it, ft);
-  const float wx = e ? fx : 1.0f - fx;
+  const int a = pair_axis(d, ix, iy, iz, it);
+  const float fa = pair_frac(a, fx, fy, fz, ft);
+  const float wx = e ? fa : 1.0f - fa;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
+    float wr;
     int64_t s0, s1;
     bool v0, v1;
-    row_pair_slots(d, dir, active, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
+    corner_pair(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
     const int64_t s = e ? s1 : s0;
     if (e ? v1 : v0) {
       unsafeAtomicAdd(d_table + s * F + f, wr * wx * gval);
@@ -207,17 +212,19 @@ __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulo
   locate(p.y, d.ry, d.sy, iy, fy);
   locate(p.z, d.rz, d.sz, iz, fz);
   locate(p.w, d.rt, d.st, it, ft);
+  const int a = pair_axis(d, ix, iy, iz, it);
+  const float fa = pair_frac(a, fx, fy, fz, ft);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
-    const float wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
+    float wr;
     int64_t s2[2];
     bool v2[2];
-    row_pair_slots(d, dir, active, it + dt, iz + dz, iy + dy, ix, s2[0], s2[1], v2[0], v2[1]);
+    corner_pair(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s2[0], s2[1], v2[0], v2[1],
+                wr);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int64_t s = (valid && v2[e]) ? s2[e] : -1;
-      const float w = (e ? fx : 1.0f - fx) * wr;
+      const float w = (e ? fa : 1.0f - fa) * wr;
       float v[F];
 #pragma unroll
       for (int k = 0; k < F; ++k) v[k] = (s >= 0) ? w * g[k] : 0.0f;

@@ -221,18 +221,20 @@ __global__ void __launch_bounds__(256)
       locate(p.w, d.rt, d.st, it, ft);
       uint32_t cand[16], prev[16];
       uint32_t won = 0;
+      const int ax = pair_axis(d, ix, iy, iz, it);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
+        float wr;
         int64_t s0, s1;
         bool v0, v1;
-        row_pair_slots(d, g.dir, g.active != 0, it + dt, iz + dz, iy + dy, ix, s0, s1, v0, v1);
+        corner_pair(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, ax, r, s0, s1, v0,
+                    v1, wr);
         cand[2 * r] = cand[2 * r + 1] = 0;
         prev[2 * r] = prev[2 * r + 1] = 0;
         if (live && (v0 || v1)) {
           // F divides 16 and begin is a multiple of 16, so the F floats of a slot
-          // lie in one segment; the two slots of a pair are consecutive rows
-          // (active or dense index) or two hashed rows
+          // lie in one segment; the two slots of a pair are neighbouring rows,
+          // rows of one brick, or two hashed rows
           const int64_t fa = (v0 ? s0 : s1) * F, fb = (v1 ? s1 : s0) * F;
           const bool ina = fa >= begin && fa < end, inb = fb >= begin && fb < end;
           const uint32_t a = ina ? (uint32_t)((fa - begin) / kSeg) : 0u;

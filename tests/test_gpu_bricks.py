@@ -205,9 +205,30 @@ def test_brick_lazy_equals_dense(fl):
         same(getattr(lazy, name)[:n], getattr(dense, name)[:n], name)
 
 
+def _pair_axis(c):
+    for a in range(4):
+        if c[a] % 2 == 0:
+            return a
+    return 0
+
+
+def _pair_offsets(r, a):
+    """Offsets (x, y, z, t) of the first corner of pair r along axis a: the
+    other axes, in increasing order, take bits 0, 1, 2 of r."""
+    o, k = [0, 0, 0, 0], 0
+    for d in range(4):
+        if d != a:
+            o[d] = (r >> k) & 1
+            k += 1
+    return o
+
+
 def test_brick_corner_rows(fl):
-    """fhash_corner_rows on a brick-ordered index: rows equal the oracle's
-    corner slots; directory entries follow the documented brick layout."""
+    """fhash_corner_rows on a brick-ordered index: the 16 rows of every sample
+    and level are the oracle's corner slots (as a set: the corners are taken
+    as 8 pairs along the first axis with an even cell index); the directory
+    entries follow the documented brick layout for the pair's first corner
+    (and its x neighbour's when the pair runs along x)."""
     f, mask = tiny_volume()
     res = _wide_res(16)
     idx, counts, dir_t, _ = _build(fl, res, 2, mask)
@@ -216,16 +237,18 @@ def test_brick_corner_rows(fl):
     pos = np.random.default_rng(5).random((n, 4)).astype(np.float32)
     d_dir, d_slot = fl.fhash_corner_rows(idx, torch.from_numpy(pos).cuda(), n)
     slots, _ = O.corners(g, pos)
-    np.testing.assert_array_equal(d_slot.cpu().numpy().reshape(n, 16, 8, 2),
-                                  slots.reshape(n, 16, 8, 2))
+    got = np.sort(d_slot.cpu().numpy().reshape(n, 16, 16), axis=2)
+    np.testing.assert_array_equal(got, np.sort(slots.reshape(n, 16, 16), axis=2))
     dd = d_dir.cpu().numpy()
     for s in range(0, n, 29):
         for l, R in enumerate(res):
             cell = [O.locate(float(pos[s, d]), R[d])[0] for d in range(4)]
+            a = _pair_axis(cell)
             for r in range(8):
-                y, z, t = cell[1] + (r & 1), cell[2] + ((r >> 1) & 1), cell[3] + (r >> 2)
-                e0, _ = _brick_entry(R, cell[0], y, z, t)
-                e1, _ = _brick_entry(R, cell[0] + 1, y, z, t)
+                o = _pair_offsets(r, a)
+                x, y, z, t = (cell[d] + o[d] for d in range(4))
+                e0, _ = _brick_entry(R, x, y, z, t)
+                e1, _ = _brick_entry(R, x + 1, y, z, t)
                 off = int(idx.dir_offset[l])
                 assert dd[s, l, r, 0] == off + e0
-                assert dd[s, l, r, 1] == (off + e1 if e1 != e0 else -1)
+                assert dd[s, l, r, 1] == (off + e1 if a == 0 and e1 != e0 else -1)
