@@ -127,7 +127,7 @@ def parse():
                          "instead of the vertices of active cells; samples still come from "
                          "the coreset")
     ap.add_argument("--hidden-layers", type=int, default=2)
-    ap.add_argument("--layout", choices=["rows", "bricks"], default="bricks",
+    ap.add_argument("--layout", choices=["rows", "bricks"], default="rows",
                     help="slot order of the active index: the F-Hash equation's rows, or "
                          "2x2x2x2 vertex bricks (Sec. 3.2.3 allows other linearisations)")
     ap.add_argument("--sort", action="store_true",
