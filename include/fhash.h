@@ -122,7 +122,9 @@ const char* fhash_last_error(void);
  * vertices before the word in brick order; the entry sits at
  * ((bt*Bz + bz)*Wb + w)*By + by, Bz = ceil(Rz/2), By = ceil(Ry/2),
  * Wb = ceil(ceil(Rx/2)/4).  fhash_dense_index and fhash_hash_index return
- * FHASH_ENOTSUP for this layout.
+ * FHASH_ENOTSUP for this layout; the fused calls support it for 17-32 decoder
+ * inputs with F = 2 or 4 and 2 or 3 hidden layers of 64 (FHASH_ENOTSUP
+ * otherwise).
  *
  * fhash_index_dir_entries: number of 16-byte directory entries the grid needs
  * (0 for a dense index is not implied: the size is for the active form).

@@ -373,6 +373,12 @@ static int check_fused(const fhash_index* idx, const fhash_mlp_desc* mlp, const 
   if (!fh::fused_supported(idx->grid.n_features, in_w, *H, *NH))
     return fail(FHASH_ENOTSUP, "fused path not built for F=%d in=%d hidden=%dx%d",
                 idx->grid.n_features, in_w, *H, *NH);
+  if (idx->grid.layout == FHASH_LAYOUT_BRICKS) {
+    const int F = idx->grid.n_features, inp = (in_w + 15) / 16 * 16;
+    if (!((F == 2 || F == 4) && inp == 32 && *H == 64 && (*NH == 2 || *NH == 3)))
+      return fail(FHASH_ENOTSUP, "fused kernels on a brick-ordered index are built for 17-32 "
+                  "decoder inputs, F = 2 or 4, 2 or 3 hidden layers of 64 only");
+  }
   if (n < 0) return fail(FHASH_EINVAL, "n < 0");
   if (n > 0 && (pos == nullptr || params == nullptr)) return fail(FHASH_EINVAL, "NULL pointer");
   if (n > 0 && !aligned16(pos)) return fail(FHASH_EINVAL, "pos not 16-byte aligned");

@@ -97,9 +97,12 @@ __device__ __forceinline__ int64_t entry_slot(const ulonglong2& e, int b, int64_
 // bricks: ((bt*Bz + bz)*Wb + word)*By + by.  Bit positions in b0, b1.  Row,
 // word and entry indices are 32-bit: the host rejects levels with 2^31
 // directory entries or more.
+// BRICK: the index's slot order (rows false, bricks true), a compile-time
+// choice so that each order's kernels carry only their own arithmetic.
+template <bool BRICK>
 __device__ __forceinline__ void pair_entries(const LevelDev& d, int32_t t, int32_t z, int32_t y,
                                              int x, int64_t& w0, int64_t& w1, int& b0, int& b1) {
-  if (d.brick) {
+  if constexpr (BRICK) {
     const int inner = (x & 1) | ((y & 1) << 1) | ((z & 1) << 2) | ((t & 1) << 3);
     const int bit0 = (x >> 1) * 16 + inner;
     // x odd: x + 1 is the first x of the next brick, 15 bits further on
@@ -124,8 +127,9 @@ __device__ __forceinline__ void pair_entries(const LevelDev& d, int32_t t, int32
 // inside it) and a pair's atomics stay one memory transaction; x when every
 // index is odd (pairs then straddle two bricks).  Rows layout: a = 0, pairs
 // along x (the vertex rows of the F-Hash order).
-__device__ __forceinline__ int pair_axis(const LevelDev& d, int cx, int cy, int cz, int ct) {
-  if (!d.brick) return 0;
+template <bool BRICK>
+__device__ __forceinline__ int pair_axis(int cx, int cy, int cz, int ct) {
+  if constexpr (!BRICK) return 0;
   return !(cx & 1) ? 0 : !(cy & 1) ? 1 : !(cz & 1) ? 2 : !(ct & 1) ? 3 : 0;
 }
 
@@ -142,6 +146,7 @@ __device__ __forceinline__ void pair_offsets(int r, int a, int& ox, int& oy, int
 // Slots of the vertex pair (x, x+1) on vertex row (t, z, y) of a level.
 // Dense: the F-Hash equation; hashed: the spatial hash; active: ranks in the
 // directory (rows or bricks layout, see pair_entries).
+template <bool BRICK = false>
 __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglong2* dir,
                                                bool active, int32_t t, int32_t z, int32_t y, int x,
                                                int64_t& s0, int64_t& s1, bool& v0, bool& v1) {
@@ -162,7 +167,7 @@ __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglon
   }
   int64_t w0, w1;
   int b0, b1;
-  pair_entries(d, t, z, y, x, w0, w1, b0, b1);
+  pair_entries<BRICK>(d, t, z, y, x, w0, w1, b0, b1);
   const ulonglong2 e = dir[w0];
   s0 = entry_slot(e, b0, d.slot_off, v0);
   if (w1 == w0) {
@@ -182,14 +187,15 @@ __device__ __forceinline__ void row_pair_slots(const LevelDev& d, const ulonglon
 // the product wr of the three other axes' weights (the pair's own weights are
 // wr (1 - f_a) and wr f_a, f_a = pair_frac).  Rows layout: the x-pair of row
 // (dy, dz, dt) = bits of r, exactly as the vertex rows are visited.
+template <bool BRICK>
 __device__ __forceinline__ void corner_pair(const LevelDev& d, const ulonglong2* dir, bool active,
                                             int cx, int cy, int cz, int ct, float fx, float fy,
                                             float fz, float ft, int a, int r, int64_t& s0,
                                             int64_t& s1, bool& v0, bool& v1, float& wr) {
-  if (!d.brick) {
+  if constexpr (!BRICK) {
     const int dy = r & 1, dz = (r >> 1) & 1, dt = (r >> 2) & 1;
     wr = (dy ? fy : 1.0f - fy) * (dz ? fz : 1.0f - fz) * (dt ? ft : 1.0f - ft);
-    row_pair_slots(d, dir, active, ct + dt, cz + dz, cy + dy, cx, s0, s1, v0, v1);
+    row_pair_slots<false>(d, dir, active, ct + dt, cz + dz, cy + dy, cx, s0, s1, v0, v1);
     return;
   }
   int ox, oy, oz, ot;
@@ -201,7 +207,7 @@ __device__ __forceinline__ void corner_pair(const LevelDev& d, const ulonglong2*
   wr = ((gx * gy) * gz) * gt;
   const int x = cx + ox, y = cy + oy, z = cz + oz, t = ct + ot;
   if (a == 0) {  // x pair (neighbouring rows, or the next brick when x is odd)
-    row_pair_slots(d, dir, active, t, z, y, x, s0, s1, v0, v1);
+    row_pair_slots<true>(d, dir, active, t, z, y, x, s0, s1, v0, v1);
     return;
   }
   // the pair's axis has an even index: both corners in one brick, inner bits

@@ -4,8 +4,9 @@
 //
 // One thread per sample, levels in a wave-uniform loop (level constants come from
 // the kernel arguments, i.e. scalar registers).  The 16 corners are visited as 8
-// vertex rows (dy, dz, dt) of an x-pair (x, x+1): one directory entry serves both
-// vertices of a pair unless x sits on bit 63 of a word.
+// pairs (corner_pair): in the rows order the vertex rows (dy, dz, dt) of an x-pair
+// (x, x+1), one directory entry serving both vertices unless x sits on bit 63 of
+// a word; in the brick order pairs along an axis that keeps both in one brick.
 #include "encode_dev.h"
 #include "kernels.h"
 
@@ -23,7 +24,10 @@ __global__ void __launch_bounds__(256)
   float* out = enc + s * (int64_t)g.L * F;
   for (int l = 0; l < g.L; ++l) {
     const LevelDev& d = g.lv[l];
-    encode_level<F, T>(d, g.dir, g.active != 0, p, table, out + l * F);
+    if (d.brick)
+      encode_level<F, T, true>(d, g.dir, g.active != 0, p, table, out + l * F);
+    else
+      encode_level<F, T, false>(d, g.dir, g.active != 0, p, table, out + l * F);
   }
 }
 
@@ -39,9 +43,14 @@ __global__ void __launch_bounds__(256)
   const int r = (int)(t % Q), e = r / F, f = r % F;
   const float4 p = pos[s];
   const float* gin = d_enc + s * (int64_t)g.L * F;
-  for (int l = 0; l < g.L; ++l)
-    scatter_level_lane<F>(g.lv[l], g.dir, g.active != 0, p, e, f, gin[l * F + f], d_table,
-                          g.touch, g.touch_begin);
+  for (int l = 0; l < g.L; ++l) {
+    if (g.lv[l].brick)
+      scatter_level_lane<F, true>(g.lv[l], g.dir, g.active != 0, p, e, f, gin[l * F + f],
+                                  d_table, g.touch, g.touch_begin);
+    else
+      scatter_level_lane<F, false>(g.lv[l], g.dir, g.active != 0, p, e, f, gin[l * F + f],
+                                   d_table, g.touch, g.touch_begin);
+  }
 }
 
 // Instrumentation: per (sample, level) the directory entries and table rows the
@@ -64,13 +73,17 @@ __global__ void __launch_bounds__(256)
   locate(p.z, d.rz, d.sz, iz, fz);
   locate(p.w, d.rt, d.st, it, ft);
   const bool active = g.active != 0 && d.hash_bits == 0;
-  const int a = pair_axis(d, ix, iy, iz, it);
+  const int a = d.brick ? pair_axis<true>(ix, iy, iz, it) : 0;
   for (int r = 0; r < 8; ++r) {
     float wr;
     int64_t s0, s1;
     bool v0, v1;
-    corner_pair(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1,
-                wr);
+    if (d.brick)
+      corner_pair<true>(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1,
+                        v0, v1, wr);
+    else
+      corner_pair<false>(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1,
+                         v0, v1, wr);
     const int64_t o = (t * 8 + r) * 2;
     long long w0 = -1, w1 = -1;
     if (active) {
@@ -80,7 +93,10 @@ __global__ void __launch_bounds__(256)
       int b0, b1;
       // the entries of the pair's first corner and of its x neighbour (the
       // second corner shares the first one's entry unless the pair is along x)
-      pair_entries(d, it + ot, iz + oz, iy + oy, ix + ox, e0, e1, b0, b1);
+      if (d.brick)
+        pair_entries<true>(d, it + ot, iz + oz, iy + oy, ix + ox, e0, e1, b0, b1);
+      else
+        pair_entries<false>(d, it + ot, iz + oz, iy + oy, ix + ox, e0, e1, b0, b1);
       w0 = e0;
       if (a == 0 && e1 != e0) w1 = e1;
     }

@@ -82,7 +82,7 @@ struct RowLoad<8, __half> {
 // Invalid (inactive) corners get weight 0 and read row 0, so every load is
 // unconditional and the 8 directory / 16 table loads overlap in flight.
 // Requires a table with at least one row.
-template <int F, typename T>
+template <int F, typename T, bool BRICK = false>
 __device__ __forceinline__ void encode_level(const LevelDev& d, const ulonglong2* dir, bool active,
                                              const float4 p, const T* __restrict__ table,
                                              float* out) {
@@ -95,14 +95,14 @@ __device__ __forceinline__ void encode_level(const LevelDev& d, const ulonglong2
   float acc[F];
 #pragma unroll
   for (int k = 0; k < F; ++k) acc[k] = 0.0f;
-  const int a = pair_axis(d, ix, iy, iz, it);
+  const int a = pair_axis<BRICK>(ix, iy, iz, it);
   const float fa = pair_frac(a, fx, fy, fz, ft);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     float wr;
     int64_t s0, s1;
     bool v0, v1;
-    corner_pair(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
+    corner_pair<BRICK>(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
     float e0[F], e1[F];
     RowLoad<F, T>::load(table, v0 ? s0 : 0, e0);
     RowLoad<F, T>::load(table, v1 ? s1 : 0, e1);
@@ -124,7 +124,7 @@ __device__ __forceinline__ void mark_touched(uint8_t* touch, int64_t tbeg, int64
 
 // Adjoint of encode_level: d_table[slot_c][k] += w_c g[k] with FP32 hardware
 // atomics (no return value).  Weights are recomputed from the position.
-template <int F>
+template <int F, bool BRICK = false>
 __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong2* dir,
                                               bool active, const float4 p, const float* g,
                                               float* __restrict__ d_table, uint8_t* touch,
@@ -135,14 +135,14 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
   locate(p.y, d.ry, d.sy, iy, fy);
   locate(p.z, d.rz, d.sz, iz, fz);
   locate(p.w, d.rt, d.st, it, ft);
-  const int a = pair_axis(d, ix, iy, iz, it);
+  const int a = pair_axis<BRICK>(ix, iy, iz, it);
   const float fa = pair_frac(a, fx, fy, fz, ft);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     float wr;
     int64_t s0, s1;
     bool v0, v1;
-    corner_pair(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
+    corner_pair<BRICK>(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
     const float w0 = wr * (1.0f - fa), w1 = wr * fa;
     if (v0) {
 #pragma unroll
@@ -165,7 +165,7 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
 // inside one brick otherwise).  Atomics of one
 // instruction that fall in the same 64-byte segment are performed as one
 // memory transaction, which is what bounds the scatter on gfx950.
-template <int F>
+template <int F, bool BRICK = false>
 __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulonglong2* dir,
                                                    bool active, const float4 p, int e, int f,
                                                    float gval, float* __restrict__ d_table,
@@ -176,7 +176,7 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
   locate(p.y, d.ry, d.sy, iy, fy);
   locate(p.z, d.rz, d.sz, iz, fz);
   locate(p.w, d.rt, d.st, it, ft);
-  const int a = pair_axis(d, ix, iy, iz, it);
+  const int a = pair_axis<BRICK>(ix, iy, iz, it);
   const float fa = pair_frac(a, fx, fy, fz, ft);
   const float wx = e ? fa : 1.0f - fa;
 #pragma unroll
@@ -184,7 +184,7 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
     float wr;
     int64_t s0, s1;
     bool v0, v1;
-    corner_pair(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
+    corner_pair<BRICK>(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
     const int64_t s = e ? s1 : s0;
     if (e ? v1 : v0) {
       unsafeAtomicAdd(d_table + s * F + f, wr * wx * gval);
@@ -200,7 +200,7 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
 // run issues the atomics.  All 16 lanes must call it (invalid samples pass
 // valid = false and contribute nothing).  Pays off when samples are sorted by
 // cell and the level is coarse enough that neighbours share vertices.
-template <int F>
+template <int F, bool BRICK = false>
 __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulonglong2* dir,
                                                     bool active, const float4 p, const float* g,
                                                     bool valid, float* __restrict__ d_table,
@@ -212,14 +212,14 @@ __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulo
   locate(p.y, d.ry, d.sy, iy, fy);
   locate(p.z, d.rz, d.sz, iz, fz);
   locate(p.w, d.rt, d.st, it, ft);
-  const int a = pair_axis(d, ix, iy, iz, it);
+  const int a = pair_axis<BRICK>(ix, iy, iz, it);
   const float fa = pair_frac(a, fx, fy, fz, ft);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     float wr;
     int64_t s2[2];
     bool v2[2];
-    corner_pair(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s2[0], s2[1], v2[0], v2[1],
+    corner_pair<BRICK>(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s2[0], s2[1], v2[0], v2[1],
                 wr);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {

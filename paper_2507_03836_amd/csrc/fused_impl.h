@@ -44,7 +44,7 @@ struct FusedArgs {
   int in_w;    // L * F
 };
 
-template <int F, typename T, int INP>
+template <int F, typename T, int INP, bool BRICK>
 __device__ __forceinline__ void gather_block(const GridDev& g, const LevelDev* lv, float4 p,
                                              bool valid, const T* table,
                                              float (&xb)[INP / 16][4]) {
@@ -57,7 +57,7 @@ __device__ __forceinline__ void gather_block(const GridDev& g, const LevelDev* l
       const int l = (16 * a + 4 * grp) / F + j;
       float e[F];
       if (valid && l < g.L) {
-        encode_level<F, T>(lv[l], g.dir, g.active != 0, p, table, e);
+        encode_level<F, T, BRICK>(lv[l], g.dir, g.active != 0, p, table, e);
       } else {
 #pragma unroll
         for (int k = 0; k < F; ++k) e[k] = 0.0f;
@@ -72,7 +72,7 @@ __device__ __forceinline__ void gather_block(const GridDev& g, const LevelDev* l
 // others are redistributed so that 2F consecutive lanes own one (sample,
 // level): pass k of 2F gives lane q the sample-level held by lane
 // k * (64 / 2F) + q / 2F, whose position and gradient arrive by shuffles.
-template <int F, int INP>
+template <int F, int INP, bool BRICK>
 __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* lv, float4 p,
                                               bool valid, const float (&dx)[INP / 16][4],
                                               float* d_table) {
@@ -89,7 +89,7 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
         float gl[F];
 #pragma unroll
         for (int k = 0; k < F; ++k) gl[k] = dx[a][j * F + k];
-        scatter_level_dedup<F>(lv[l], g.dir, g.active != 0, p, gl, valid, d_table, g.touch,
+        scatter_level_dedup<F, BRICK>(lv[l], g.dir, g.active != 0, p, gl, valid, d_table, g.touch,
                                g.touch_begin);
       }
 #pragma unroll
@@ -111,7 +111,7 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
         for (int q = 1; q < F; ++q)
           if (f == q) gval = gsrc[q];
         if (ls < g.L && vs && !((g.dedup >> ls) & 1u))
-          scatter_level_lane<F>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table, g.touch,
+          scatter_level_lane<F, BRICK>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table, g.touch,
                                 g.touch_begin);
       }
     }
@@ -122,7 +122,7 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
 // share its LDS.  D is the decoder arithmetic: float (FP32 MFMA) or a 16-bit
 // type (_Float16 / __bf16 MFMA with FP32 accumulation); the FP32-decoder
 // forward is MODE_FWD, the 16-bit one MODE_FWD16.
-template <int MODE, int F, typename T, int INP, int H, int NH, typename D>
+template <int MODE, int F, typename T, int INP, int H, int NH, typename D, bool BRICK>
 __global__ void __launch_bounds__(64 * waves_per_block(MODE))
     __attribute__((amdgpu_waves_per_eu(is_forward(MODE) ? 1 : 2)))
     fused_kernel(GridDev g, FusedArgs A) {
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(64 * waves_per_block(MODE))
     const bool valid = smp < A.n;
     const float4 p = valid ? A.pos[smp] : make_float4(0.f, 0.f, 0.f, 0.f);
     float xb[S::INB][4];
-    gather_block<F, T, INP>(g, lv, p, valid, table, xb);
+    gather_block<F, T, INP, BRICK>(g, lv, p, valid, table, xb);
     float hs[NH][S::HB][4];
     float yv;
     if constexpr (MODE == MODE_FWD16)
@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(64 * waves_per_block(MODE))
       else
         mlp_block_bwd_t<INP, H, NH, D>(lds, grad, reinterpret_cast<D*>(scratch), xb, hs, dyv,
                                        dxb);
-      scatter_block<F, INP>(g, lv, p, valid, dxb, A.d_table);
+      scatter_block<F, INP, BRICK>(g, lv, p, valid, dxb, A.d_table);
     }
   }
   if constexpr (!FWD) {
@@ -221,12 +221,28 @@ inline int64_t fused_blocks(int64_t n, int mode) {
   return fused_waves(n, mode) / waves_per_block(mode);
 }
 
+// The brick slot order is built for the production decoder shapes only
+// (32 inputs, hidden width 64, 2 or 3 hidden layers, F = 2 or 4); the host
+// rejects other shapes on a brick-ordered index.
+template <int F, int INP, int H, int NH>
+constexpr bool brick_shape() {
+  return (F == 2 || F == 4) && INP == 32 && H == 64 && (NH == 2 || NH == 3);
+}
+
 template <int MODE, int F, typename T, int INP, int H, int NH, typename D>
 hipError_t fused_t(const GridDev& g, FusedArgs A, float* d_params, hipStream_t st) {
   constexpr int kWaves = waves_per_block(MODE);
   const int64_t nb = fused_blocks(A.n, MODE);
-  hipLaunchKernelGGL((fused_kernel<MODE, F, T, INP, H, NH, D>), dim3((unsigned)nb),
-                     dim3(64 * kWaves), 0, st, g, A);
+  if (g.lv[0].brick) {
+    if constexpr (brick_shape<F, INP, H, NH>())
+      hipLaunchKernelGGL((fused_kernel<MODE, F, T, INP, H, NH, D, true>), dim3((unsigned)nb),
+                         dim3(64 * kWaves), 0, st, g, A);
+    else
+      return hipErrorNotSupported;
+  } else {
+    hipLaunchKernelGGL((fused_kernel<MODE, F, T, INP, H, NH, D, false>), dim3((unsigned)nb),
+                       dim3(64 * kWaves), 0, st, g, A);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || is_forward(MODE)) return e;
   return launch_reduce_partials(A.part, nb, A.P, d_params, st);

@@ -221,14 +221,18 @@ __global__ void __launch_bounds__(256)
       locate(p.w, d.rt, d.st, it, ft);
       uint32_t cand[16], prev[16];
       uint32_t won = 0;
-      const int ax = pair_axis(d, ix, iy, iz, it);
+      const int ax = d.brick ? pair_axis<true>(ix, iy, iz, it) : 0;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         float wr;
         int64_t s0, s1;
         bool v0, v1;
-        corner_pair(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, ax, r, s0, s1, v0,
-                    v1, wr);
+        if (d.brick)
+          corner_pair<true>(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, ax, r, s0,
+                            s1, v0, v1, wr);
+        else
+          corner_pair<false>(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, ax, r, s0,
+                             s1, v0, v1, wr);
         cand[2 * r] = cand[2 * r + 1] = 0;
         prev[2 * r] = prev[2 * r + 1] = 0;
         if (live && (v0 || v1)) {

@@ -124,6 +124,14 @@ def test_overflow_skips_step_and_halves_scale(fl):
     for x, y in ((a.params, b.params), (a.m, b.m), (a.v, b.v)):
         assert torch.allclose(x, y, rtol=1e-5, atol=1e-7)
     assert torch.equal(a.params.half(), a.shadow) and torch.equal(b.params.half(), b.shadow)
+    # a finite scale with a non-finite decoder gradient: skipped, scale halved
+    _, d = _model(mask, table0, mlp0, "mixed", loss_scale=2.0 ** 12)
+    pd, md = d.params.clone(), d.m.clone()
+    d.fwd_bwd(pos, tgt)
+    d.d_mlp[3] = float("inf")
+    assert not d.optimizer_step()
+    assert d.skipped == 1 and d.step_count == 0 and d.loss_scale == 2.0 ** 11
+    assert torch.equal(d.params, pd) and torch.equal(d.m, md) and (d.grads == 0).all()
     # scale growth after a clean window
     _, c = _model(mask, table0, mlp0, "mixed", loss_scale=4.0, scale_window=2)
     for _ in range(2):
