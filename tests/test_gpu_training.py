@@ -5,7 +5,9 @@
   finite differences of the loss it computes.
 - Learned-part test: the tiny workload trained by the project's own kernels
   with the decoder trained versus the same tables trained behind a frozen
-  random-init decoder (the method without a learned network).
+  random-init decoder, and versus a no-network linear readout (the sum over
+  levels of each level's first feature plus a bias), same tables, kernels,
+  optimiser and steps.
 """
 import numpy as np
 import pytest
@@ -110,10 +112,57 @@ def _train(fl, f, mask, dims, train_mlp, steps=400, seed=5):
     return psnr_on(model, allpos, alltgt)
 
 
+def _train_linear(fl, f, mask, dims, steps=400, seed=5):
+    """Tables behind a linear readout y = sum_l E_l[., 0] + b: the encoding and
+    its adjoint through fhash_encode_fwd / fhash_encode_bwd, the tables
+    stepped by fhash_step, the bias by the same Adam in FP64 on the host."""
+    from paper_2507_03836_amd.model import FHashConfig, FHashModel
+    cfg = FHashConfig(res=TINY_RES, n_features=2, hidden=32, n_hidden=2)
+    bits = torch.from_numpy(synth.pack_mask_rows(mask).view(np.int64)).cuda()
+    model = FHashModel(cfg, bits, dims, init_seed=seed)
+    F, L = cfg.n_features, cfg.n_levels
+    cs = coreset_ids(mask)
+    csd = torch.from_numpy(cs.view(np.int64)).cuda()
+    fd = torch.from_numpy(f).cuda()
+    n = 4096
+    pos = torch.empty(n, 4, device="cuda")
+    tgt = torch.empty(n, device="cuda")
+    enc = torch.empty(n, L * F, device="cuda")
+    d_enc = torch.zeros(n, L * F, device="cuda")
+    n_tab = model.mlp_off
+    b, mb, vb = 0.5, 0.0, 0.0
+    for k in range(1, steps + 1):
+        fl.fhash_sample(2001, k, n, csd, cs.size, dims, fd, pos, tgt)
+        fl.fhash_encode_fwd(model.index, pos, n, model.table, enc)
+        y = enc[:, 0::F].sum(1) + b
+        dy = 2.0 * (y - tgt) / n
+        d_enc[:, 0::F] = dy[:, None]
+        fl.fhash_encode_bwd(model.index, pos, n, d_enc, model.d_table)
+        fl.fhash_step(model.adam_desc(k), model.params[:n_tab], model.grads[:n_tab],
+                      model.m[:n_tab], model.v[:n_tab])
+        gb = float(dy.double().sum())
+        mb = cfg.beta1 * mb + (1 - cfg.beta1) * gb
+        vb = cfg.beta2 * vb + (1 - cfg.beta2) * gb * gb
+        b -= cfg.lr / (1 - cfg.beta1 ** k) * mb / (np.sqrt(vb / (1 - cfg.beta2 ** k)) + cfg.eps)
+    allpos = torch.from_numpy(O.voxel_positions(cs, dims)).cuda()
+    alltgt = fd.view(-1)[csd].double()
+    se = 0.0
+    for s0 in range(0, allpos.shape[0], 1 << 16):
+        p = allpos[s0: s0 + (1 << 16)]
+        e = torch.empty(p.shape[0], L * F, device="cuda")
+        fl.fhash_encode_fwd(model.index, p, p.shape[0], model.table, e)
+        yy = e[:, 0::F].sum(1).double() + b
+        se += float(((yy - alltgt[s0: s0 + (1 << 16)]) ** 2).sum())
+    return 10.0 * np.log10(allpos.shape[0] / se)
+
+
 def test_trained_decoder_gain(env):
     fl, f, mask, dims = env
     p_full = _train(fl, f, mask, dims, True)
     p_frozen = _train(fl, f, mask, dims, False)
-    print(f"PSNR trained decoder {p_full:.2f} dB, frozen random decoder {p_frozen:.2f} dB")
+    p_linear = _train_linear(fl, f, mask, dims)
+    print(f"PSNR trained decoder {p_full:.2f} dB, frozen random decoder {p_frozen:.2f} dB, "
+          f"linear readout {p_linear:.2f} dB")
     assert p_full > 25.0
     assert p_full > p_frozen + 2.0
+    assert p_full > p_linear
