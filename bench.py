@@ -127,6 +127,9 @@ def parse():
                          "instead of the vertices of active cells; samples still come from "
                          "the coreset")
     ap.add_argument("--hidden-layers", type=int, default=2)
+    ap.add_argument("--moments", choices=["paired", "separate"], default="paired",
+                    help="Adam moments layout: m and v of a 16-parameter segment in one "
+                         "128-byte line (paired), or two arrays")
     ap.add_argument("--layout", choices=["rows", "bricks"], default="rows",
                     help="slot order of the active index: the F-Hash equation's rows, or "
                          "2x2x2x2 vertex bricks (Sec. 3.2.3 allows other linearisations)")
@@ -290,6 +293,7 @@ def key_frame_bench(args):
         cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers,
                           layout=LAYOUTS[args.layout])
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3000, lazy=True,
+                           paired_moments=args.moments == "paired",
                            max_steps=args.steps + 8)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -306,7 +310,7 @@ def key_frame_bench(args):
             r[f"psnr_{name}_db"] = psnr_on(model, pp, pt)
         out["runs"][label] = r
         log(f"[keyframes] {label}: {r}")
-        model.params = model.grads = model.m = model.v = None
+        model.params = model.grads = model.m = model.v = model.mv = None
         del model, probes
         torch.cuda.empty_cache()
     out["value"] = out["runs"]["key_frames"]["psnr_unseen_db"]
@@ -361,6 +365,7 @@ def fold_sweep_bench(args):
                 continue
             cfg = FHashConfig(res=res, n_features=F, hidden=64, n_hidden=2)
             model = FHashModel(cfg, None, dims, init_seed=3000, lazy=True,
+                               paired_moments=args.moments == "paired",
                                max_steps=args.steps + 8)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             fb_ms = []
@@ -392,7 +397,7 @@ def fold_sweep_bench(args):
                          "dense_adam_ms": ev[2].elapsed_time(ev[3]), "psnr_db": psnr})
             cells.append(cell)
             log(f"[fold] fold {fold} F {F}: {cell}")
-            model.params = model.grads = model.m = model.v = model.lazy = None
+            model.params = model.grads = model.m = model.v = model.mv = model.lazy = None
             del model
             torch.cuda.empty_cache()
     out = {"metric": "training ms/step and probe PSNR over embedding size x fold (dense FBB)",
@@ -436,6 +441,7 @@ def serve_multi_bench(args):
             cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3,
                               layout=LAYOUTS[args.layout])
             model = FHashModel(cfg, gen["bits"], dims, init_seed=seed + 2000, lazy=True,
+                               paired_moments=args.moments == "paired",
                                max_steps=args.serve_train_steps + 8)
             B = 1 << 20
             pos = torch.empty(B, 4, device="cuda")
@@ -460,7 +466,7 @@ def serve_multi_bench(args):
             info.append({"model": name, "params": model.n_params, "probe_psnr_db": psnr,
                          "resident_bytes": models[name].nbytes()})
             del gen, pos, tgt
-            model.params = model.grads = model.m = model.v = None
+            model.params = model.grads = model.m = model.v = model.mv = None
             del model
             torch.cuda.empty_cache()
             log(f"[multi] {name}: {info[-1]['params']} params, PSNR {psnr:.1f} dB, resident "
@@ -564,6 +570,7 @@ def serve_bench(args):
     cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3,
                       layout=LAYOUTS[args.layout])
     model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, lazy=True,
+                       paired_moments=args.moments == "paired",
                        max_steps=args.serve_train_steps + 8)
     log(f"[serve] model: {model.rows} active vertices, {model.n_params} params")
     B = 1 << 20
@@ -589,7 +596,7 @@ def serve_bench(args):
     params = model.mlp_params.clone()
     bits = gen["bits"]
     del gen, pos, tgt, ppos, ptgt
-    model.params = model.grads = model.m = model.v = None
+    model.params = model.grads = model.m = model.v = model.mv = None
     torch.cuda.empty_cache()
     tf = torch.from_numpy(synth.transfer_function()).cuda()
     mlp = fl.mlp_desc(cfg.width, fl.F16 if args.serve_decoder == "f16" else fl.F32)
@@ -1107,7 +1114,7 @@ def headline_bench(args):
     for prec in ("fp32", "mixed"):
         small = FHashModel(FHashConfig(res=[[4, 4, 4, 2]] * 16, n_features=2, hidden=64,
                                        n_hidden=3), None, dims, precision=prec, lazy=True,
-                           max_steps=4)
+                           paired_moments=args.moments == "paired", max_steps=4)
         fl.fhash_sample(1, 1, 4096, gen["coreset"], gen["M"], dims, gen["field"], pos, tgt)
         small.prepare(pos[:4096])
         small.fwd_bwd(pos[:4096], tgt[:4096], prepared=True)
@@ -1121,6 +1128,7 @@ def headline_bench(args):
     paths, keep = {}, None
     for prec in ("fp32", "mixed"):
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, precision=prec, lazy=True,
+                           paired_moments=args.moments == "paired",
                            max_steps=args.max_steps + args.warmup + args.steps + 8)
         r, step, t_first = _train_timed(model, gen, dims, B, args.steps, args.warmup, 2003, pos,
                                         tgt)
@@ -1149,11 +1157,11 @@ def headline_bench(args):
                     cpu = cpu_baseline_all_cores(model, gen, dims, B, args.cpu_samples, 2003)
                 except Exception as e:  # reported, never hidden
                     cpu = {"error": repr(e)}
-            model.params = model.grads = model.m = model.v = model.lazy = None
+            model.params = model.grads = model.m = model.v = model.mv = model.lazy = None
             del model
             torch.cuda.empty_cache()
     model = keep
-    model.grads = model.m = model.v = None
+    model.grads = model.m = model.v = model.mv = None
     model.lazy = None
     torch.cuda.empty_cache()
     serve = _serve_sub(model, gen, dims, args, args.serve_requests)
@@ -1240,6 +1248,7 @@ def main():
                        hash_bits=args.hash_bits, init_seed=3000 + args.field_seed - 1000,
                        precision=args.precision, track_touched=args.optimizer == "tracked",
                        lazy=args.optimizer == "lazy",
+                       paired_moments=args.moments == "paired",
                        max_steps=max(args.max_steps, args.warmup + args.steps) + 64)
     torch.cuda.synchronize()
     dense = sum(int(np.prod(r)) for r in res)

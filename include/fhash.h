@@ -314,11 +314,19 @@ int fhash_fused_train_static(const fhash_index* idx, const fhash_mlp_desc* mlp,
  * in flagged segments and taken as zero elsewhere; the flags of that range are
  * cleared.  Results are bit for bit those of the untracked call whenever the
  * gradient is zero in every unflagged segment.
- * All arrays device float[n], 16-byte aligned. */
+ * All arrays device float[n], 16-byte aligned.
+ * Moments layout (opt->moments): FHASH_MOMENTS_SEPARATE, m and v each float[n];
+ * FHASH_MOMENTS_PAIRED, one array in blocks of 32 floats, the m of parameters
+ * 16b .. 16b+15 followed by their v (float[2 * ceil(n / 16) * 16]): pass its
+ * start as m and its start + 16 floats as v (FHASH_EINVAL otherwise).  The
+ * paired layout keeps a segment's two moments in one 128-byte line, which the
+ * deferred update below reads and writes per segment. */
+enum { FHASH_MOMENTS_SEPARATE = 0, FHASH_MOMENTS_PAIRED = 1 };
 typedef struct {
   double lr, beta1, beta2, eps; /* the kernel uses FP32 roundings of b1, 1-b1, b2, 1-b2 */
   int64_t step;                 /* 1-based */
   double grad_scale;
+  int64_t moments;              /* FHASH_MOMENTS_SEPARATE or FHASH_MOMENTS_PAIRED */
 } fhash_adam_desc;
 
 int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
@@ -367,6 +375,8 @@ typedef struct {
   int64_t steps;
   double beta1, beta2, eps;
   int64_t flags; /* library-owned: bit 0, a step with a non-finite grad_scale was recorded */
+  int64_t moments; /* layout of m and v (see fhash_adam_desc), set by the caller; every
+                      fhash_step_lazy must pass the same */
 } fhash_lazy;
 
 size_t fhash_lazy_workspace_bytes(int64_t range_floats, int64_t max_steps);

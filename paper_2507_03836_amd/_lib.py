@@ -52,9 +52,13 @@ class MlpDesc(C.Structure):
                 ("compute_dt", C.c_int32)]
 
 
+MOMENTS_SEPARATE, MOMENTS_PAIRED = 0, 1
+
+
 class AdamDesc(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
-                ("eps", C.c_double), ("step", C.c_int64), ("grad_scale", C.c_double)]
+                ("eps", C.c_double), ("step", C.c_int64), ("grad_scale", C.c_double),
+                ("moments", C.c_int64)]
 
 
 class View(C.Structure):
@@ -100,7 +104,8 @@ def _touch(t):
 class Lazy(C.Structure):
     _fields_ = [("ws", C.c_void_p), ("begin", C.c_int64), ("end", C.c_int64),
                 ("max_steps", C.c_int64), ("steps", C.c_int64), ("beta1", C.c_double),
-                ("beta2", C.c_double), ("eps", C.c_double), ("flags", C.c_int64)]
+                ("beta2", C.c_double), ("eps", C.c_double), ("flags", C.c_int64),
+                ("moments", C.c_int64)]
 
 
 LAZY_FLOATS = 16
@@ -109,7 +114,8 @@ LAZY_FLOATS = 16
 class LazyState:
     """A deferred-Adam descriptor with its device workspace (see fhash_lazy_init)."""
 
-    def __init__(self, begin: int, end: int, max_steps: int, device="cuda"):
+    def __init__(self, begin: int, end: int, max_steps: int, device="cuda",
+                 moments: int = MOMENTS_SEPARATE):
         nb = lib().fhash_lazy_workspace_bytes(int(end) - int(begin), int(max_steps))
         if nb == 0:
             raise ValueError("bad lazy range or max_steps")
@@ -118,6 +124,7 @@ class LazyState:
         self.desc.ws = self.ws.data_ptr()
         self.desc.begin, self.desc.end = int(begin), int(end)
         self.desc.max_steps = int(max_steps)
+        self.desc.moments = int(moments)
         _check(lib().fhash_lazy_init(C.byref(self.desc), _stream()), "fhash_lazy_init")
 
     @property

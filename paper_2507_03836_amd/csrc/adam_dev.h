@@ -32,6 +32,17 @@ inline AdamK make_adam_k(const fhash_adam_desc* o) {
   return k;
 }
 
+// Float offset of the moment of parameter a: a itself, or in the paired
+// layout (blocks of 16 m values followed by the same parameters' 16 v values)
+// 32 (a / 16) + a % 16; the v array starts 16 floats after the m array.
+template <bool PAIRED>
+__host__ __device__ __forceinline__ int64_t moment_off(int64_t a) {
+  if constexpr (PAIRED)
+    return ((a >> 4) << 5) + (a & 15);
+  else
+    return a;
+}
+
 #ifdef __HIPCC__
 // One Adam step (PyTorch semantics, bias-corrected, no weight decay) with
 // every rounding spelled out and contraction off, so that every kernel that

@@ -498,11 +498,15 @@ static int check_step(const fhash_adam_desc* opt, const float* param, const floa
   if (!(opt->lr >= 0.0) || !(opt->beta1 >= 0.0 && opt->beta1 < 1.0) ||
       !(opt->beta2 >= 0.0 && opt->beta2 < 1.0) || !(opt->eps > 0.0))
     return fail(FHASH_EINVAL, "bad Adam hyper-parameters");
+  if (opt->moments != FHASH_MOMENTS_SEPARATE && opt->moments != FHASH_MOMENTS_PAIRED)
+    return fail(FHASH_EINVAL, "moments layout %lld unknown", (long long)opt->moments);
   if (n == 0) return FHASH_OK;
   if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
     return fail(FHASH_EINVAL, "NULL pointer");
   if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
     return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
+  if (opt->moments == FHASH_MOMENTS_PAIRED && v != m + 16)
+    return fail(FHASH_EINVAL, "paired moments: v must start 16 floats after m");
   if (shadow != nullptr) {
     if (shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
       return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
@@ -520,7 +524,8 @@ int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, 
   if (n == 0) return FHASH_OK;
   if ((rc = apply_touch(touch, n, nullptr))) return rc;
   return hip_status(
-      fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, n, found_inf, touch, S(stream)),
+      fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, n, 0, found_inf, touch,
+                      S(stream)),
       "fhash_step");
 }
 
@@ -543,6 +548,8 @@ static int check_lazy(const fhash_lazy* lz) {
     return fail(FHASH_ERANGE, "max_steps outside [0, 2^32 - 1)");
   if (lz->steps < 0 || lz->steps > lz->max_steps)
     return fail(FHASH_EINVAL, "steps %lld outside [0, max_steps]", (long long)lz->steps);
+  if (lz->moments != FHASH_MOMENTS_SEPARATE && lz->moments != FHASH_MOMENTS_PAIRED)
+    return fail(FHASH_EINVAL, "moments layout %lld unknown", (long long)lz->moments);
   return FHASH_OK;
 }
 
@@ -588,6 +595,8 @@ int fhash_lazy_prepare(const fhash_index* idx, const float* pos, int64_t n, fhas
     return fail(FHASH_EINVAL, "NULL pointer");
   if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
     return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
+  if (lz->moments == FHASH_MOMENTS_PAIRED && v != m + 16)
+    return fail(FHASH_EINVAL, "paired moments: v must start 16 floats after m");
   if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
     return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
   if (shadow != nullptr && (reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)
@@ -610,6 +619,8 @@ int fhash_step_lazy(const fhash_adam_desc* opt, float* param, float* grad, float
   if (lz->end > n) return fail(FHASH_EINVAL, "lazy range ends past the parameters");
   if (lz->steps + 1 > lz->max_steps)
     return fail(FHASH_ERANGE, "lazy record full (%lld steps)", (long long)lz->max_steps);
+  if (opt->moments != lz->moments)
+    return fail(FHASH_EINVAL, "the step's moments layout differs from the deferred state's");
   if (lz->beta1 < 0.0) {
     lz->beta1 = opt->beta1;
     lz->beta2 = opt->beta2;
@@ -619,12 +630,12 @@ int fhash_step_lazy(const fhash_adam_desc* opt, float* param, float* grad, float
   }
   hipStream_t st = S(stream);
   // dense part: [0, begin) and [end, n)
-  hipError_t e = fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, lz->begin, found_inf,
-                                 nullptr, st);
+  hipError_t e = fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, lz->begin, 0,
+                                 found_inf, nullptr, st);
   if (e == hipSuccess) {
     void* sh_tail = shadow ? static_cast<void*>(static_cast<uint16_t*>(shadow) + lz->end) : nullptr;
-    e = fh::launch_adam(opt, param + lz->end, grad + lz->end, m + lz->end, v + lz->end, sh_tail,
-                        shadow_dt, n - lz->end, found_inf, nullptr, st);
+    e = fh::launch_adam(opt, param + lz->end, grad + lz->end, m, v, sh_tail, shadow_dt,
+                        n - lz->end, lz->end, found_inf, nullptr, st);
   }
   if (e == hipSuccess)
     e = fh::launch_lazy_step(opt, lz, found_inf, st);
@@ -649,6 +660,8 @@ int fhash_lazy_flush(fhash_lazy* lz, float* param, float* grad, float* m, float*
     return fail(FHASH_EINVAL, "NULL pointer");
   if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
     return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
+  if (lz->moments == FHASH_MOMENTS_PAIRED && v != m + 16)
+    return fail(FHASH_EINVAL, "paired moments: v must start 16 floats after m");
   if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
     return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
   if (shadow != nullptr && (reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)

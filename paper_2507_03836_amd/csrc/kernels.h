@@ -68,9 +68,11 @@ size_t static_scratch_bytes();
 hipError_t static_scratch(void** ptr);
 
 // optim.hip
+// Parameters p[i], g[i] (i < n) are parameters first + i of the whole
+// vector; m, v are the whole vector's moment arrays (o->moments layout).
 hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
-                       void* shadow, fhash_dtype sdt, int64_t n, const int32_t* found_inf,
-                       const fhash_touch* touch, hipStream_t st);
+                       void* shadow, fhash_dtype sdt, int64_t n, int64_t first,
+                       const int32_t* found_inf, const fhash_touch* touch, hipStream_t st);
 hipError_t launch_reduce_partials(const float* part, int64_t nwav, int64_t P, float* d_params,
                                   hipStream_t st);
 hipError_t launch_check_finite(const float* g, int64_t n, int32_t* found, hipStream_t st);

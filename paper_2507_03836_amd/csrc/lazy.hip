@@ -130,6 +130,7 @@ struct Lane {
 // Loads.  stale: done < upto.  A segment never stepped (done == 0, nothing
 // pending) holds m = v = 0 and needs no loads.  begin is a multiple of 16 and
 // end of 4, so a lane's four floats are all inside the range or all outside.
+template <bool PAIRED>
 __device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t pend, bool stale,
                                            int sub, const float* __restrict__ p,
                                            const float* __restrict__ g,
@@ -147,8 +148,8 @@ __device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t
   L.p = L.m = L.v = L.g = z;
   if (L.work) {
     L.p = *reinterpret_cast<const f4v*>(p + L.f);
-    L.m = *reinterpret_cast<const f4v*>(m + L.f);
-    L.v = *reinterpret_cast<const f4v*>(v + L.f);
+    L.m = *reinterpret_cast<const f4v*>(m + moment_off<PAIRED>(L.f));
+    L.v = *reinterpret_cast<const f4v*>(v + moment_off<PAIRED>(L.f));
     if (pend != 0) L.g = *reinterpret_cast<const f4v*>(g + L.f);
   }
   return L;
@@ -177,7 +178,7 @@ __device__ __forceinline__ bool nonzero_state(const f4v m, const f4v v) {
 
 // Replay, stores, gradient reset.  ODD: some recorded step has a non-finite
 // gscale (its zero-gradient form is adam1).
-template <bool ODD>
+template <bool ODD, bool PAIRED>
 __device__ __forceinline__ bool finish_lanes(Lane L, const float4* rec, const AdamK& base,
                                              float* __restrict__ p, float* __restrict__ g,
                                              float* __restrict__ m, float* __restrict__ v,
@@ -186,8 +187,8 @@ __device__ __forceinline__ bool finish_lanes(Lane L, const float4* rec, const Ad
   replay<ODD>(rec, base, active, L.done, L.pend, upto, L.g, L.p, L.m, L.v);
   if (active) {
     *reinterpret_cast<f4v*>(p + L.f) = L.p;
-    *reinterpret_cast<f4v*>(m + L.f) = L.m;
-    *reinterpret_cast<f4v*>(v + L.f) = L.v;
+    *reinterpret_cast<f4v*>(m + moment_off<PAIRED>(L.f)) = L.m;
+    *reinterpret_cast<f4v*>(v + moment_off<PAIRED>(L.f)) = L.v;
     if (shadow != nullptr) store_shadow_group(shadow, sdt, L.f, L.p);
   }
   if (L.work && L.pend != 0 && (L.g[0] != 0.f || L.g[1] != 0.f || L.g[2] != 0.f || L.g[3] != 0.f))
@@ -291,7 +292,7 @@ __device__ __forceinline__ int gap_bin(uint32_t gap) {  // gap >= 1
 // workgroup takes chunks of kChunk entries, sorts them by the number of steps
 // to replay (counting sort in LDS) and runs them 16 at a time, so that the
 // four segments of a wave replay about as many steps.
-template <bool ODD>
+template <bool ODD, bool PAIRED>
 __global__ void __launch_bounds__(256)
     lazy_catchup_kernel(const uint2* __restrict__ list, unsigned long long* ctr,
                         uint2* __restrict__ state, const float4* __restrict__ rec, AdamK base,
@@ -342,12 +343,14 @@ __global__ void __launch_bounds__(256)
     auto fetch = [&](int r0) {
       const int e = r0 + (int)(threadIdx.x / kLanesPerSeg);
       const uint4 en = e < nloc ? srt[e] : make_uint4(0u, upto, 0u, 0u);
-      return load_lanes(en.x, en.y, en.z, e < nloc && en.y < upto, sub, p, g, m, v, begin, end);
+      return load_lanes<PAIRED>(en.x, en.y, en.z, e < nloc && en.y < upto, sub, p, g, m, v,
+                                begin, end);
     };
     Lane cur = fetch(0);
     for (int r0 = 0; r0 < nloc; r0 += 256 / kLanesPerSeg) {
       const Lane nxt = fetch(r0 + 256 / kLanesPerSeg);
-      const bool active = finish_lanes<ODD>(cur, rec, base, p, g, m, v, shadow, sdt, upto);
+      const bool active =
+          finish_lanes<ODD, PAIRED>(cur, rec, base, p, g, m, v, shadow, sdt, upto);
       if (cur.stale && sub == 0) {
         state[cur.seg].x = upto;
         n_stale += 1;
@@ -483,8 +486,11 @@ void launch_catch_up(const fhash_lazy* lz, const LazyWs& w, float* p, float* gr,
                      float* v, void* shadow, fhash_dtype sdt, hipStream_t st) {
   const int64_t nseg = lazy_num_segments(lz->end - lz->begin);
   const bool odd = (lz->flags & 1) != 0;
-  hipLaunchKernelGGL(odd ? lazy_catchup_kernel<true> : lazy_catchup_kernel<false>,
-                     dim3(kListBlocks), dim3(256), 0, st, w.list, w.ctr, w.state, w.rec,
+  auto kern = odd ? (lz->moments == FHASH_MOMENTS_PAIRED ? lazy_catchup_kernel<true, true>
+                                                         : lazy_catchup_kernel<true, false>)
+                  : (lz->moments == FHASH_MOMENTS_PAIRED ? lazy_catchup_kernel<false, true>
+                                                         : lazy_catchup_kernel<false, false>);
+  hipLaunchKernelGGL(kern, dim3(kListBlocks), dim3(256), 0, st, w.list, w.ctr, w.state, w.rec,
                      lazy_base(lz), p, gr, m, v, shadow, (int)sdt, lz->begin, lz->end,
                      (uint32_t)lz->steps, nseg);
   hipLaunchKernelGGL(lazy_empty_list_kernel, dim3(1), dim3(64), 0, st, w.ctr);

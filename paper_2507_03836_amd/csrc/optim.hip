@@ -64,18 +64,21 @@ __device__ __forceinline__ void tracked_load(const f4v* __restrict__ g4, int64_t
   if ((f % FHASH_TOUCH_FLOATS) == 0) touch[seg] = 0;
 }
 
+// Parameter i of p, g is parameter first + i of the whole vector, whose
+// moments sit at m / v + moment_off<PAIRED>(first + i) (first: a multiple of 4).
+template <bool PAIRED>
 __global__ void __launch_bounds__(256)
     adam_kernel(AdamK k, float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                 float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t n,
-                const int32_t* __restrict__ found_inf, uint8_t* __restrict__ touch, int64_t tb,
-                int64_t te) {
+                int64_t first, const int32_t* __restrict__ found_inf,
+                uint8_t* __restrict__ touch, int64_t tb, int64_t te) {
   const bool skip = (found_inf != nullptr) && (*found_inf != 0);
   const int64_t n4 = n >> 2;
   const int64_t S = (int64_t)gridDim.x * blockDim.x;
   f4v* p4 = reinterpret_cast<f4v*>(p);
   f4v* g4 = reinterpret_cast<f4v*>(g);
-  f4v* m4 = reinterpret_cast<f4v*>(m);
-  f4v* v4 = reinterpret_cast<f4v*>(v);
+  auto m4 = [&](int64_t i) { return reinterpret_cast<f4v*>(m + moment_off<PAIRED>(first + 4 * i)); };
+  auto v4 = [&](int64_t i) { return reinterpret_cast<f4v*>(v + moment_off<PAIRED>(first + 4 * i)); };
   const f4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += 2 * S) {
     const int64_t j = i + S;
@@ -84,24 +87,24 @@ __global__ void __launch_bounds__(256)
     tracked_load(g4, i, touch, tb, te, g0);
     if (two) tracked_load(g4, j, touch, tb, te, g1);
     if (!skip) {
-      f4v p0 = __builtin_nontemporal_load(p4 + i), m0 = __builtin_nontemporal_load(m4 + i);
-      f4v v0 = __builtin_nontemporal_load(v4 + i);
+      f4v p0 = __builtin_nontemporal_load(p4 + i), m0 = __builtin_nontemporal_load(m4(i));
+      f4v v0 = __builtin_nontemporal_load(v4(i));
       f4v p1 = zero, m1 = zero, v1 = zero;
       if (two) {
         p1 = __builtin_nontemporal_load(p4 + j);
-        m1 = __builtin_nontemporal_load(m4 + j);
-        v1 = __builtin_nontemporal_load(v4 + j);
+        m1 = __builtin_nontemporal_load(m4(j));
+        v1 = __builtin_nontemporal_load(v4(j));
       }
       adam4(k, g0, p0, m0, v0);
       __builtin_nontemporal_store(p0, p4 + i);
-      __builtin_nontemporal_store(m0, m4 + i);
-      __builtin_nontemporal_store(v0, v4 + i);
+      __builtin_nontemporal_store(m0, m4(i));
+      __builtin_nontemporal_store(v0, v4(i));
       if (shadow != nullptr) store_shadow4(shadow, sdt, i, p0);
       if (two) {
         adam4(k, g1, p1, m1, v1);
         __builtin_nontemporal_store(p1, p4 + j);
-        __builtin_nontemporal_store(m1, m4 + j);
-        __builtin_nontemporal_store(v1, v4 + j);
+        __builtin_nontemporal_store(m1, m4(j));
+        __builtin_nontemporal_store(v1, v4(j));
         if (shadow != nullptr) store_shadow4(shadow, sdt, j, p1);
       }
     }
@@ -115,11 +118,12 @@ __global__ void __launch_bounds__(256)
   if (t < n && t < (n4 << 2) + 4) {
     const float gg = g[t];
     if (!skip) {
-      float pp = p[t], mm = m[t], vv = v[t];
+      const int64_t mo = moment_off<PAIRED>(first + t);
+      float pp = p[t], mm = m[mo], vv = v[mo];
       adam1(k, gg, pp, mm, vv);
       p[t] = pp;
-      m[t] = mm;
-      v[t] = vv;
+      m[mo] = mm;
+      v[mo] = vv;
       if (shadow != nullptr) store_shadow(shadow, sdt, t, pp);
     }
     if (gg != 0.0f) g[t] = 0.0f;
@@ -222,8 +226,8 @@ inline unsigned blocks_for(int64_t n, int64_t per_thread) {
 }  // namespace
 
 hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
-                       void* shadow, fhash_dtype sdt, int64_t n, const int32_t* found_inf,
-                       const fhash_touch* touch, hipStream_t st) {
+                       void* shadow, fhash_dtype sdt, int64_t n, int64_t first,
+                       const int32_t* found_inf, const fhash_touch* touch, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const AdamK k = make_adam_k(o);
   // Two float4 groups per thread per iteration; a deep grid keeps every CU's
@@ -233,8 +237,12 @@ hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, f
   if (b < 1) b = 1;
   uint8_t* tf = touch ? touch->flags : nullptr;
   const int64_t tb = touch ? touch->begin : 0, te = touch ? touch->end : 0;
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)b), dim3(256), 0, st, k, p, g, m, v, shadow,
-                     (int)sdt, n, found_inf, tf, tb, te);
+  if (o->moments == FHASH_MOMENTS_PAIRED)
+    hipLaunchKernelGGL(adam_kernel<true>, dim3((unsigned)b), dim3(256), 0, st, k, p, g, m, v,
+                       shadow, (int)sdt, n, first, found_inf, tf, tb, te);
+  else
+    hipLaunchKernelGGL(adam_kernel<false>, dim3((unsigned)b), dim3(256), 0, st, k, p, g, m, v,
+                       shadow, (int)sdt, n, first, found_inf, tf, tb, te);
   return hipGetLastError();
 }
 

@@ -78,7 +78,8 @@ class FHashModel:
                  table_init: torch.Tensor | None = None, mlp_init: torch.Tensor | None = None,
                  init_seed: int = 3000, precision: str = "fp32", loss_scale: float = 2.0 ** 16,
                  scale_window: int = 2000, track_touched: bool = True, lazy: bool = False,
-                 max_steps: int = 1 << 16, hash_bits: int = 0, decoder: str | None = None):
+                 max_steps: int = 1 << 16, hash_bits: int = 0, decoder: str | None = None,
+                 paired_moments: bool = False):
         if precision not in ("fp32", "mixed"):
             raise ValueError(f"precision must be 'fp32' or 'mixed', not {precision!r}")
         if decoder is None:
@@ -109,8 +110,16 @@ class FHashModel:
         f32 = dict(dtype=torch.float32, device=self.device)
         self.params = torch.zeros(n_alloc, **f32)
         self.grads = torch.zeros(n_alloc, **f32)
-        self.m = torch.zeros(n_alloc, **f32)
-        self.v = torch.zeros(n_alloc, **f32)
+        # Adam moments: separate arrays, or paired (blocks of 16 m then the same
+        # parameters' 16 v: one 128-byte line per segment for the deferred update);
+        # m and v are then the pointers into the pair array the library expects
+        self.paired = bool(paired_moments)
+        if self.paired:
+            self.mv = torch.zeros((n_alloc + 15) // 16 * 32, **f32)
+            self.m, self.v = self.mv, self.mv[16:]
+        else:
+            self.m = torch.zeros(n_alloc, **f32)
+            self.v = torch.zeros(n_alloc, **f32)
         if table_init is not None:
             self.table.copy_(table_init.reshape(-1))
         else:
@@ -145,7 +154,7 @@ class FHashModel:
         if lazy:
             # deferred Adam on [begin, end of the padded table); dense elsewhere
             self.lazy = fl.LazyState(0 if begin is None else begin, self.mlp_off, max_steps,
-                                     device=self.device)
+                                     device=self.device, moments=self._moments_layout())
         elif track_touched and begin is not None:
             self._touch_flags = torch.zeros((self.n_table + seg - 1) // seg,
                                             dtype=torch.uint8, device=self.device)
@@ -181,12 +190,24 @@ class FHashModel:
     def d_mlp(self) -> torch.Tensor:
         return self.grads[self.mlp_off: self.mlp_off + self.n_mlp]
 
+    def _moments_layout(self) -> int:
+        return fl.MOMENTS_PAIRED if self.paired else fl.MOMENTS_SEPARATE
+
+    def moments(self):
+        """(m, v) of the parameters as flat arrays (copies in the paired layout)."""
+        n = self.n_params
+        if not self.paired:
+            return self.m[:n], self.v[:n]
+        mv = self.mv.view(-1, 2, 16)
+        return mv[:, 0].reshape(-1)[:n], mv[:, 1].reshape(-1)[:n]
+
     def adam_desc(self, step: int, grad_scale: float = 1.0) -> fl.AdamDesc:
         c = self.cfg
         o = fl.AdamDesc()
         o.lr, o.beta1, o.beta2, o.eps = c.lr, c.beta1, c.beta2, c.eps
         o.step = step
         o.grad_scale = grad_scale
+        o.moments = self._moments_layout()
         return o
 
     def prepare(self, pos: torch.Tensor, phases: int = fl.LAZY_PREPARE):

@@ -35,7 +35,7 @@ def fl():
     return fl
 
 
-def _pair(precision, begin_level, **kw):
+def _pair(precision, begin_level, dense_kw=None, lazy_kw=None, **kw):
     from paper_2507_03836_amd import _lib as fl
     from paper_2507_03836_amd.model import FHashConfig, FHashModel
     f, mask = tiny_volume()
@@ -51,11 +51,11 @@ def _pair(precision, begin_level, **kw):
     mlp0 = torch.from_numpy(synth.mlp_init(cfg.width, seed=72))
     mk = lambda **a: FHashModel(cfg, bits, dims, table_init=table0, mlp_init=mlp0,
                                 precision=precision, **a, **kw)
-    dense = mk(track_touched=False)
-    lazy = mk(lazy=True)
+    dense = mk(track_touched=False, **(dense_kw or {}))
+    lazy = mk(lazy=True, **(lazy_kw or {}))
     if begin_level:
         begin = int(lazy.index.slot_offset[begin_level]) * 2 // 16 * 16
-        lazy.lazy = fl.LazyState(begin, lazy.mlp_off, 64)
+        lazy.lazy = fl.LazyState(begin, lazy.mlp_off, 64, moments=lazy._moments_layout())
     return cfg, dense, lazy
 
 
@@ -102,8 +102,10 @@ def _run(fl, dense, lazy, steps, batch, flush_at=(), inf_at=()):
     lazy.flush()
     torch.cuda.synchronize()
     n = dense.n_params
-    for name in ("params", "m", "v", "grads"):
+    for name in ("params", "grads"):
         _same(getattr(lazy, name)[:n], getattr(dense, name)[:n], name)
+    for name, a, b in zip(("m", "v"), lazy.moments(), dense.moments()):
+        _same(a, b, name)
     if dense.shadow is not None:
         _same(lazy.shadow[:n], dense.shadow[:n], "shadow")
     assert lazy.lazy.steps == steps
@@ -116,6 +118,18 @@ def test_lazy_equals_dense_fp32(fl, begin_level, batch):
     _run(fl, dense, lazy, steps=14, batch=batch, flush_at=(6,))
     # the parameters did move (a no-op optimiser would also be "equal")
     assert dense.step_count == 14
+
+
+@pytest.mark.parametrize("dense_paired,lazy_paired", [(False, True), (True, True), (True, False)])
+def test_paired_moments_equal_separate(fl, dense_paired, lazy_paired):
+    """The paired moments layout (a segment's m and v in one 128-byte line)
+    changes where m and v live, not a bit of the update: dense and deferred,
+    either layout, against each other."""
+    _, dense, lazy = _pair("fp32", 2, dense_kw={"paired_moments": dense_paired},
+                           lazy_kw={"paired_moments": lazy_paired})
+    assert dense.paired == dense_paired and lazy.paired == lazy_paired
+    _run(fl, dense, lazy, steps=10, batch=200, flush_at=(4,))
+    assert dense.step_count == 10
 
 
 def test_lazy_equals_dense_mixed_with_skipped_step(fl):

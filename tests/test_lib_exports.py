@@ -139,3 +139,31 @@ def test_hash_index_host_only():
     g = fl.grid_desc(res, 2)
     assert L.fhash_hash_index(ctypes.byref(g), 3, ctypes.byref(out), None) == fl.EINVAL
     assert L.fhash_hash_index(ctypes.byref(g), 32, ctypes.byref(out), None) == fl.EINVAL
+
+
+def test_moment_layouts_checked_before_any_launch():
+    """fhash_step and the deferred calls refuse an unknown moments layout, paired
+    moments whose v does not start 16 floats after m, and a step whose layout
+    differs from the deferred state's (host checks, no device)."""
+    L = fl.lib()
+    o = fl.AdamDesc()
+    o.lr, o.beta1, o.beta2, o.eps, o.step, o.grad_scale = 0.01, 0.9, 0.999, 1e-8, 1, 1.0
+    base = 1 << 20   # never dereferenced: every call below fails its checks
+    p, g, m = ctypes.c_void_p(base), ctypes.c_void_p(base + 4096), ctypes.c_void_p(base + 8192)
+    o.moments = 2
+    assert L.fhash_step(ctypes.byref(o), p, g, m, ctypes.c_void_p(base + 8192 + 64), None,
+                        fl.F16, 64, None, None, None) == fl.EINVAL
+    o.moments = fl.MOMENTS_PAIRED
+    assert L.fhash_step(ctypes.byref(o), p, g, m, ctypes.c_void_p(base + 8192 + 128), None,
+                        fl.F16, 64, None, None, None) == fl.EINVAL
+    assert b"16 floats after m" in L.fhash_last_error()
+    lz = fl.Lazy()
+    lz.ws, lz.begin, lz.end, lz.max_steps, lz.steps = base, 0, 64, 8, 0
+    lz.beta1 = lz.beta2 = lz.eps = -1.0
+    lz.moments = fl.MOMENTS_SEPARATE
+    rc = L.fhash_step_lazy(ctypes.byref(o), p, g, m, ctypes.c_void_p(base + 8192 + 64), None,
+                           fl.F16, 64, None, ctypes.byref(lz), None)
+    assert rc == fl.EINVAL and b"layout differs" in L.fhash_last_error()
+    lz.moments = 7
+    assert L.fhash_lazy_flush(ctypes.byref(lz), p, g, m, ctypes.c_void_p(base + 8192 + 64),
+                              None, fl.F16, None) == fl.EINVAL
