@@ -55,10 +55,11 @@ ADAM_RW_BYTES_PER_PARAM = 24
 ADAM_TRAFFIC = {"bytes": 156.90e9, "params": 6390343593,
                 "source_md5": "d602a578d7be1d0da4b2643ea2ed6c36"}
 
-# Catch-up of the deferred Adam (one launch per step), algorithmic bytes per segment of 16
-# floats: every list entry reads its 8-B entry and 4-B state word and writes the state word
-# (16 B); a segment stepped before reads and writes p, m, v (6 x 64 B); a pending gradient
-# is read and reset (2 x 64 B); the FP16 shadow adds 32 B written.
+# Catch-up of the deferred Adam (one launch per step), algorithmic bytes: the claim flags of
+# the whole range are read (1 B per segment of 16 floats); every flagged segment reads and
+# writes its 8-B state word (16 B); a segment stepped before reads and writes p, m, v
+# (6 x 64 B); a pending gradient is read and reset (2 x 64 B); the FP16 shadow adds 32 B
+# written.
 LAZY_ENTRY_BYTES, LAZY_LOADED_BYTES, LAZY_PENDING_BYTES, LAZY_SHADOW_BYTES = 16, 384, 128, 32
 # HBM bytes of one lazy_catchup_kernel launch at the default workload and step count (FP32),
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (copy-calibrated, per launch, averaged
@@ -854,6 +855,17 @@ def _cpu_worker(task):
     return time.perf_counter() - t0
 
 
+def _cpu_worker_init():
+    """Worker start-up: no transparent huge pages in this process.  The oracle
+    works on full-size zero tables and counts on pages being committed only
+    where it writes; with huge pages each scattered write would commit 2 MiB."""
+    import ctypes
+    try:
+        ctypes.CDLL(None, use_errno=True).prctl(41, 1, 0, 0, 0)  # PR_SET_THP_DISABLE
+    except (OSError, AttributeError):
+        pass
+
+
 def cpu_baseline_all_cores(model, gen, dims, batch, n_cpu, seed):
     """The FP64 oracle, as it stands, on every host core the box gives this
     job (one process per core, at most 16): n_cpu coreset draws split over the
@@ -889,7 +901,7 @@ def cpu_baseline_all_cores(model, gen, dims, batch, n_cpu, seed):
         pass
     ctx = mp.get_context("spawn")
     log(f"[cpu] oracle on {workers} processes ({nproc} host CPUs, {cpu_model})")
-    with ctx.Pool(workers) as pool:
+    with ctx.Pool(workers, initializer=_cpu_worker_init) as pool:
         pool.map(_cpu_worker, [("adam", 1024)] * workers)  # start-up outside the timing
         t0 = time.perf_counter()
         pool.map(_cpu_worker, fb)
@@ -1333,7 +1345,8 @@ def main():
     if lazy:
         # dominant kernel: the catch-up of the deferred update (one launch per step)
         d = {k: (st1[k] - st0[k]) / args.steps for k in st1}
-        roof_bytes = (LAZY_ENTRY_BYTES * d["segments"]
+        nseg = (model.lazy.desc.end - model.lazy.desc.begin + 15) // 16
+        roof_bytes = (nseg + LAZY_ENTRY_BYTES * d["segments"]
                       + LAZY_LOADED_BYTES * d["loaded"] + LAZY_PENDING_BYTES * d["pending"]
                       + (LAZY_SHADOW_BYTES * d["loaded"] if mixed else 0))
         roof_kernel, roof_ms = "lazy_catchup_kernel", catch_ms

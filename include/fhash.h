@@ -357,8 +357,8 @@ int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, 
  * enrolled segment still holds that step's (unapplied) gradient.
  *
  * ws: device memory of fhash_lazy_workspace_bytes(end - begin, max_steps)
- * bytes, 16-byte aligned, caller-owned (8 bytes of state and 8 of list per
- * segment, 16 bytes of constants per step).  begin: a multiple of
+ * bytes, 16-byte aligned, caller-owned (8 bytes of state and a 1-byte claim
+ * flag per segment, 16 bytes of constants per step).  begin: a multiple of
  * FHASH_LAZY_FLOATS; end: a multiple of 4; fewer than 2^32 segments.  steps:
  * the number of fhash_step_lazy calls so far (0 after fhash_lazy_init, one
  * more after each; at most max_steps < 2^32 - 1).  beta1, beta2, eps: recorded

@@ -12,14 +12,17 @@
 // zero gradient.  Values read after the catch-up are the dense sweep's values,
 // bit for bit.
 //
-// State word per segment: {done, stamp}.  Prepare for step S+1 stores S+1
-// into stamp (atomic max; the first claimer appends {segment, old stamp} to
-// the step's list), then replays steps done+1..S of the new list entries; the
-// step's gradient is written by the caller's backward; every catch-up empties
-// the list.  The step call only records the constants (and whether found_inf
-// skipped the step) and runs the dense update outside the range; the gradient
-// step of an enrolled segment is applied by its next catch-up or by the flush
-// (which lists every segment behind the last step and catches them up).
+// State word per segment: {done, stamp}, and one claim flag byte.  The mark
+// of prepare for step S+1 sets the flag of every segment the samples touch
+// (a plain byte store: every claimer writes the same value, so no atomics are
+// needed).  The catch-up scans the flags in segment order, clears them, and
+// for each flagged segment not yet enrolled in S+1 replays steps done+1..S
+// (the enrolled step `stamp` with its gradient) and stores {S, S+1}; the
+// step's gradient is written by the caller's backward.  The step call only
+// records the constants (and whether found_inf skipped the step) and runs the
+// dense update outside the range; the gradient step of an enrolled segment is
+// applied by its next catch-up or by the flush (which flags every segment
+// behind the last step and catches them up, keeping their stamps).
 #include "adam_dev.h"
 #include "common.h"
 #include "kernels.h"
@@ -30,8 +33,9 @@ namespace {
 
 constexpr int kSeg = FHASH_LAZY_FLOATS;
 static_assert(kSeg == 16, "segments of 16 floats");
-constexpr int kChunk = 512;  // list entries a workgroup sorts by gap in LDS
+constexpr int kChunk = 512;  // flagged segments a workgroup sorts by gap in LDS
 constexpr int kBins = 32;
+constexpr int kTile = 2048;  // claim flags a workgroup scans per pass (8 per thread)
 
 // Per-step record: {step_size, inv_bc2_sqrt, gscale, kind}; kind 0: a step
 // whose zero-gradient form is adam0 (finite gscale), 1: skipped (found_inf),
@@ -122,7 +126,7 @@ __device__ __forceinline__ void replay(const float4* __restrict__ rec, const Ada
 // loads of the next segments are in flight while these replay.
 struct Lane {
   int64_t f;  // first of the lane's four floats
-  uint32_t seg, done, pend;
+  uint32_t seg, done, pend, stamp;  // stamp: the segment's new stamp (0: state unchanged)
   bool stale, work;
   f4v p, m, v, g;
 };
@@ -131,8 +135,9 @@ struct Lane {
 // pending) holds m = v = 0 and needs no loads.  begin is a multiple of 16 and
 // end of 4, so a lane's four floats are all inside the range or all outside.
 template <bool PAIRED>
-__device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t pend, bool stale,
-                                           int sub, const float* __restrict__ p,
+__device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t pend,
+                                           uint32_t stamp, bool stale, int sub,
+                                           const float* __restrict__ p,
                                            const float* __restrict__ g,
                                            const float* __restrict__ m,
                                            const float* __restrict__ v, int64_t begin,
@@ -141,6 +146,7 @@ __device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t
   L.seg = seg;
   L.done = done;
   L.pend = pend;
+  L.stamp = stamp;
   L.stale = stale;
   L.f = begin + (int64_t)seg * kSeg + 4 * sub;
   L.work = stale && L.f < end && !(pend == 0 && done == 0);
@@ -198,20 +204,14 @@ __device__ __forceinline__ bool finish_lanes(Lane L, const float4* rec, const Ad
 
 // Every segment of [begin, end) that the forward or backward of a sample reads
 // or writes at the levels [l0, l1): the corner row pairs of its cell, exactly
-// as the encoding visits them.  Newly claimed segments are appended to the
-// list as {segment, previous stamp}, one counter atomic per wave and level.
+// as the encoding visits them, gets its claim flag set.
 __global__ void __launch_bounds__(256)
     lazy_mark_kernel(GridDev g, int l0, int l1, const float4* __restrict__ pos, int64_t n,
-                     uint2* __restrict__ state, uint2* __restrict__ list,
-                     unsigned long long* __restrict__ count, int64_t begin, int64_t end,
-                     uint32_t target, unsigned long long cap) {
+                     uint8_t* __restrict__ flags, int64_t begin, int64_t end) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int F = g.F;
-  // the loop bound is wave-uniform: every lane takes part in the appends
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    const bool live = i < n;
-    const float4 p = live ? pos[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float4 p = pos[i];
     for (int l = l0; l < l1; ++l) {
       const LevelDev& d = g.lv[l];
       int ix, iy, iz, it;
@@ -220,8 +220,6 @@ __global__ void __launch_bounds__(256)
       locate(p.y, d.ry, d.sy, iy, fy);
       locate(p.z, d.rz, d.sz, iz, fz);
       locate(p.w, d.rt, d.st, it, ft);
-      uint32_t cand[16], prev[16];
-      uint32_t won = 0;
       const int ax = d.brick ? pair_axis<true>(ix, iy, iz, it) : 0;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -234,46 +232,17 @@ __global__ void __launch_bounds__(256)
         else
           corner_pair<false>(d, g.dir, g.active != 0, ix, iy, iz, it, fx, fy, fz, ft, ax, r, s0,
                              s1, v0, v1, wr);
-        cand[2 * r] = cand[2 * r + 1] = 0;
-        prev[2 * r] = prev[2 * r + 1] = 0;
-        if (live && (v0 || v1)) {
+        if (v0 || v1) {
           // F divides 16 and begin is a multiple of 16, so the F floats of a slot
           // lie in one segment; the two slots of a pair are neighbouring rows,
           // rows of one brick, or two hashed rows
           const int64_t fa = (v0 ? s0 : s1) * F, fb = (v1 ? s1 : s0) * F;
           const bool ina = fa >= begin && fa < end, inb = fb >= begin && fb < end;
-          const uint32_t a = ina ? (uint32_t)((fa - begin) / kSeg) : 0u;
-          const uint32_t b = inb ? (uint32_t)((fb - begin) / kSeg) : 0u;
-          cand[2 * r] = a;
-          cand[2 * r + 1] = b;
-          if (ina) {
-            uint32_t* sa = reinterpret_cast<uint32_t*>(state + a) + 1;
-            const uint32_t oa = atomicMax(sa, target);
-            prev[2 * r] = oa;
-            if (oa < target) won |= 1u << (2 * r);
-          }
-          if (inb && !(ina && b == a)) {
-            uint32_t* sb = reinterpret_cast<uint32_t*>(state + b) + 1;
-            const uint32_t ob = atomicMax(sb, target);
-            prev[2 * r + 1] = ob;
-            if (ob < target) won |= 1u << (2 * r + 1);
-          }
+          const int64_t a = (fa - begin) / kSeg, b = (fb - begin) / kSeg;
+          if (ina) flags[a] = 1;
+          if (inb && !(ina && b == a)) flags[b] = 1;
         }
       }
-      int total;
-      const int off = wave_excl_scan(__popc(won), total);
-      if (total == 0) continue;
-      unsigned long long at = 0;
-      if ((threadIdx.x & 63) == 0) at = atomicAdd(count, (unsigned long long)total);
-      at = __shfl(at, 0, 64) + off;
-#pragma unroll
-      for (int c = 0; c < 16; ++c)
-        if (won & (1u << c)) {
-          // the bound always holds: the list has one entry per segment, and a
-          // segment is listed at most once between two catch-ups
-          if (at < cap) list[at] = make_uint2(cand[c], prev[c]);
-          ++at;
-        }
     }
   }
 }
@@ -286,81 +255,163 @@ __device__ __forceinline__ int gap_bin(uint32_t gap) {  // gap >= 1
   return b < kBins ? b : kBins - 1;
 }
 
-// Catch-up of the list entries [ctr[1], ctr[0]) to step `upto`; ctr[2..5]
-// accumulate the segments caught up, those that loaded data, those with a
-// pending gradient and the segment-steps replayed (workload statistics).  Each
-// workgroup takes chunks of kChunk entries, sorts them by the number of steps
-// to replay (counting sort in LDS) and runs them 16 at a time, so that the
-// four segments of a wave replay about as many steps.
+// Catch-up of the flagged segments to step `upto`; ctr[2..5] accumulate the
+// segments caught up, those that loaded data, those with a pending gradient
+// and the segment-steps replayed (workload statistics).  target: the stamp
+// the caught-up segments take (the step being prepared), or 0 to keep their
+// stamps (the flush); with target != 0 a flagged segment already stamped
+// target was caught up by an earlier prepare of the same step and is left as
+// it is.  Each workgroup scans tiles of kTile flags (clearing them), collects
+// the flagged segments in LDS in segment order, and takes them in chunks of
+// at most kChunk: a counting sort in LDS by the number of steps to replay,
+// then rounds of 64 segments, so that the four segments of a wave replay about
+// as many steps.  The flag array is padded with zeros to whole tiles.
 template <bool ODD, bool PAIRED>
 __global__ void __launch_bounds__(256)
-    lazy_catchup_kernel(const uint2* __restrict__ list, unsigned long long* ctr,
+    lazy_catchup_kernel(uint8_t* __restrict__ flags, int64_t nseg, unsigned long long* ctr,
                         uint2* __restrict__ state, const float4* __restrict__ rec, AdamK base,
                         float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                         float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t begin,
-                        int64_t end, uint32_t upto, int64_t cap) {
+                        int64_t end, uint32_t upto, uint32_t target, int group, int min_flush) {
+  // flagged segments not yet caught up: fewer than kChunk carried over plus
+  // at most one tile's worth
+  __shared__ uint32_t ids[kTile + kChunk];
   __shared__ uint4 srt[kChunk];
   __shared__ int hist[kBins], boff[kBins];
+  __shared__ int wave_total[4];
   __shared__ unsigned long long tally[4];
   if (threadIdx.x < 4) tally[threadIdx.x] = 0ull;
   unsigned long long n_stale = 0, n_work = 0, n_pend = 0, n_steps = 0;
-  const int64_t lo = (int64_t)ctr[1];
-  const int64_t hi = (int64_t)ctr[0] < cap ? (int64_t)ctr[0] : cap;
   const int sub = threadIdx.x & (kLanesPerSeg - 1);
-  for (int64_t c0 = lo + (int64_t)blockIdx.x * kChunk; c0 < hi; c0 += (int64_t)gridDim.x * kChunk) {
-    const int nloc = (int)((hi - c0) < kChunk ? (hi - c0) : kChunk);
-    if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
-    __syncthreads();
-    uint4 ent[kChunk / 256];
-    int bin[kChunk / 256], rank[kChunk / 256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int cnt = 0;  // entries in ids (the same in every thread)
+  // groups of `group` consecutive tiles, grid-strided: a chunk's segments are
+  // mostly neighbours in memory, and the workgroups share dense and sparse
+  // regions of the flags alike
+  const int64_t ntiles = (nseg + kTile - 1) / kTile;
+  for (int64_t it = 0;; ++it) {
+    const int64_t first = (blockIdx.x + it / group * (int64_t)gridDim.x) * group;
+    const int64_t tile = first + it % group;
+    const bool more = first < ntiles;  // workgroup-uniform
+    const int64_t t0 = tile * kTile;
+    if (more && tile < ntiles) {
+      // the flags of segments t0 + 8 threadIdx.x .. + 7
+      uint2* fw = reinterpret_cast<uint2*>(flags + t0) + threadIdx.x;
+      const uint2 w = *fw;
+      uint32_t bits = 0;
+      if ((w.x | w.y) != 0u) {
+        *fw = make_uint2(0u, 0u);
 #pragma unroll
-    for (int k = 0; k < kChunk / 256; ++k) {
-      const int i = threadIdx.x + k * 256;
-      bin[k] = -1;
-      if (i < nloc) {
-        const uint2 e = list[c0 + i];
-        const uint32_t done = state[e.x].x;
-        const uint32_t pend = e.y > done ? e.y : 0u;  // enrolled step not yet applied
-        ent[k] = make_uint4(e.x, done, pend, 0u);
-        bin[k] = (done >= upto || (pend == 0 && done == 0)) ? 0 : gap_bin(upto - done);
-        rank[k] = atomicAdd(&hist[bin[k]], 1);
+        for (int k = 0; k < 4; ++k) {
+          bits |= ((w.x >> (8 * k)) & 0xffu) ? 1u << k : 0u;
+          bits |= ((w.y >> (8 * k)) & 0xffu) ? 1u << (k + 4) : 0u;
+        }
       }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int s = 0;
-      for (int b = 0; b < kBins; ++b) {
-        boff[b] = s;
-        s += hist[b];
-      }
-    }
-    __syncthreads();
+      int wtot;
+      const int off = wave_excl_scan(__popc(bits), wtot);
+      if (lane == 0) wave_total[wid] = wtot;
+      __syncthreads();
+      int at = cnt + off, total = 0;
 #pragma unroll
-    for (int k = 0; k < kChunk / 256; ++k)
-      if (bin[k] >= 0) srt[boff[bin[k]] + rank[k]] = ent[k];
-    __syncthreads();
-    // software-pipelined rounds of 64 segments: load round r+1, replay round r
-    auto fetch = [&](int r0) {
-      const int e = r0 + (int)(threadIdx.x / kLanesPerSeg);
-      const uint4 en = e < nloc ? srt[e] : make_uint4(0u, upto, 0u, 0u);
-      return load_lanes<PAIRED>(en.x, en.y, en.z, e < nloc && en.y < upto, sub, p, g, m, v,
-                                begin, end);
-    };
-    Lane cur = fetch(0);
-    for (int r0 = 0; r0 < nloc; r0 += 256 / kLanesPerSeg) {
-      const Lane nxt = fetch(r0 + 256 / kLanesPerSeg);
-      const bool active =
-          finish_lanes<ODD, PAIRED>(cur, rec, base, p, g, m, v, shadow, sdt, upto);
-      if (cur.stale && sub == 0) {
-        state[cur.seg].x = upto;
-        n_stale += 1;
-        n_work += cur.work;
-        n_pend += cur.work && cur.pend != 0;
-        if (active) n_steps += upto - cur.done;
+      for (int q = 0; q < 4; ++q) {
+        at += q < wid ? wave_total[q] : 0;
+        total += wave_total[q];
       }
-      cur = nxt;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (bits & (1u << k)) ids[at++] = (uint32_t)(t0 + 8 * threadIdx.x + k);
+      cnt += total;
+      __syncthreads();  // ids written; wave_total may be reused
     }
-    __syncthreads();  // srt and hist are reused by the next chunk
+    // full chunks; at the end of a group also a shorter one of at least
+    // min_flush entries (a chunk then stays within one group); at the end
+    // everything
+    const bool group_end = it % group == group - 1;
+    int c0 = 0;
+    while (cnt - c0 >= kChunk || (group_end && cnt - c0 >= min_flush) ||
+           (!more && cnt - c0 > 0)) {
+      const int nloc = cnt - c0 < kChunk ? cnt - c0 : kChunk;
+      if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
+      __syncthreads();
+      uint4 ent[kChunk / 256];
+      int bin[kChunk / 256], rank[kChunk / 256];
+#pragma unroll
+      for (int k = 0; k < kChunk / 256; ++k) {
+        const int i = threadIdx.x + k * 256;
+        bin[k] = -1;
+        if (i < nloc) {
+          const uint32_t seg = ids[c0 + i];
+          const uint2 st = state[seg];
+          const uint32_t done = st.x;
+          if (target == 0u || st.y < target) {
+            // enrolled step not yet applied (stamps never pass upto here)
+            const uint32_t pend = st.y > done && st.y <= upto ? st.y : 0u;
+            ent[k] = make_uint4(seg, done, pend, target != 0u ? target : st.y);
+            bin[k] = (done >= upto || (pend == 0 && done == 0)) ? 0 : gap_bin(upto - done);
+          } else {  // enrolled in this step already: nothing to do
+            ent[k] = make_uint4(seg, upto, 0u, 0u);
+            bin[k] = 0;
+          }
+          rank[k] = atomicAdd(&hist[bin[k]], 1);
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int s = 0;
+        for (int b = 0; b < kBins; ++b) {
+          boff[b] = s;
+          s += hist[b];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kChunk / 256; ++k)
+        if (bin[k] >= 0) srt[boff[bin[k]] + rank[k]] = ent[k];
+      __syncthreads();
+      // software-pipelined rounds of 64 segments: load round r+1, replay round r
+      auto fetch = [&](int r0) {
+        const int e = r0 + (int)(threadIdx.x / kLanesPerSeg);
+        const uint4 en = e < nloc ? srt[e] : make_uint4(0u, upto, 0u, 0u);
+        return load_lanes<PAIRED>(en.x, en.y, en.z, en.w, e < nloc && en.y < upto, sub, p, g, m,
+                                  v, begin, end);
+      };
+      Lane cur = fetch(0);
+      for (int r0 = 0; r0 < nloc; r0 += 256 / kLanesPerSeg) {
+        const Lane nxt = fetch(r0 + 256 / kLanesPerSeg);
+        const bool active =
+            finish_lanes<ODD, PAIRED>(cur, rec, base, p, g, m, v, shadow, sdt, upto);
+        if (sub == 0 && cur.stamp != 0u)
+          state[cur.seg] = make_uint2(cur.stale ? upto : cur.done, cur.stamp);
+        if (cur.stale && sub == 0) {
+          n_stale += 1;
+          n_work += cur.work;
+          n_pend += cur.work && cur.pend != 0;
+          if (active) n_steps += upto - cur.done;
+        }
+        cur = nxt;
+      }
+      c0 += nloc;
+      __syncthreads();  // srt and hist are reused by the next chunk
+    }
+    if (!more) break;
+    if (c0 > 0) {
+      // carry the rest (fewer than kChunk) to the front
+      const int rest = cnt - c0;
+      uint32_t keep[kChunk / 256];
+#pragma unroll
+      for (int k = 0; k < kChunk / 256; ++k) {
+        const int i = threadIdx.x + k * 256;
+        keep[k] = i < rest ? ids[c0 + i] : 0u;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kChunk / 256; ++k) {
+        const int i = threadIdx.x + k * 256;
+        if (i < rest) ids[i] = keep[k];
+      }
+      __syncthreads();
+      cnt = rest;
+    }
   }
   if (n_stale) {
     atomicAdd(&tally[0], n_stale);
@@ -372,51 +423,28 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x < 4 && tally[threadIdx.x] != 0ull) atomicAdd(&ctr[2 + threadIdx.x], tally[threadIdx.x]);
 }
 
-// Flush, first part: append every segment behind step `upto` that was ever
-// enrolled to the list as {segment, stamp} (its stamp <= upto: a segment
-// enrolled in the open step is already at upto).  A workgroup takes 4096 segments (16 per thread, coalesced),
-// ranks its stale ones with a workgroup scan and reserves their list entries
-// with one counter atomic.
-constexpr int kCompactPerThread = 16;
-
+// Flush, first part: flag every segment behind step `upto` that was ever
+// enrolled (a segment enrolled in the open step is already at upto); 8
+// segments per thread, one 8-byte flag store.
 __global__ void __launch_bounds__(256)
-    lazy_compact_kernel(int64_t nseg, const uint2* __restrict__ state, uint2* __restrict__ list,
-                        unsigned long long* __restrict__ count, uint32_t upto) {
-  // runs on an empty list (the flush catches up first): at most nseg entries
-  __shared__ int wave_total[4];
-  __shared__ unsigned long long block_base;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t tile = 256 * kCompactPerThread;
-  for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < nseg; t0 += (int64_t)gridDim.x * tile) {
-    uint32_t mask = 0, stamp[kCompactPerThread];
+    lazy_flag_stale_kernel(int64_t nseg, const uint2* __restrict__ state,
+                           uint8_t* __restrict__ flags, uint32_t upto) {
+  for (int64_t s0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8; s0 < nseg;
+       s0 += (int64_t)gridDim.x * blockDim.x * 8) {
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
-    for (int k = 0; k < kCompactPerThread; ++k) {
-      const int64_t seg = t0 + k * 256 + threadIdx.x;
-      const uint2 st = seg < nseg ? state[seg] : make_uint2(upto, upto);
-      stamp[k] = st.y;
+    for (int k = 0; k < 8; ++k) {
+      const uint2 st = s0 + k < nseg ? state[s0 + k] : make_uint2(upto, upto);
       // never enrolled (done == stamp == 0): m = v = 0 and p is a fixed point of
       // every missed step, so its state already is the dense state at any step
-      if (st.x < upto && (st.x | st.y) != 0u) mask |= 1u << k;
-    }
-    int wtot;
-    const int off = wave_excl_scan(__popc(mask), wtot);
-    if (lane == 0) wave_total[wid] = wtot;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int tot = wave_total[0] + wave_total[1] + wave_total[2] + wave_total[3];
-      block_base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
-    }
-    __syncthreads();
-    unsigned long long at = block_base + off;
-    for (int w = 0; w < wid; ++w) at += wave_total[w];
-#pragma unroll
-    for (int k = 0; k < kCompactPerThread; ++k)
-      if (mask & (1u << k)) {
-        if (at < (unsigned long long)nseg)
-          list[at] = make_uint2((uint32_t)(t0 + k * 256 + threadIdx.x), stamp[k]);
-        ++at;
+      if (st.x < upto && (st.x | st.y) != 0u) {
+        if (k < 4)
+          lo |= 1u << (8 * k);
+        else
+          hi |= 1u << (8 * (k - 4));
       }
-    __syncthreads();  // wave_total and block_base are reused by the next tile
+    }
+    if (lo | hi) *reinterpret_cast<uint2*>(flags + s0) = make_uint2(lo, hi);
   }
 }
 
@@ -426,14 +454,6 @@ __global__ void lazy_record_kernel(float4* rec, int64_t t, float step_size, floa
     const bool skipped = found_inf != nullptr && *found_inf != 0;
     const float kind = skipped ? kSkipped : (isfinite(gscale) ? kStep : kOddScale);
     rec[t] = make_float4(step_size, inv_bc2_sqrt, gscale, kind);
-  }
-}
-
-// Empty the list (after a catch-up every entry has been consumed).
-__global__ void lazy_empty_list_kernel(unsigned long long* ctr) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctr[0] = 0ull;
-    ctr[1] = 0ull;
   }
 }
 
@@ -447,10 +467,12 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct LazyWs {
   uint2* state;
-  uint2* list;
-  unsigned long long* ctr;  // [0] entries, [1] entries caught up
+  uint8_t* flags;           // one per segment, zero-padded to whole tiles
+  unsigned long long* ctr;  // [2..5] workload statistics
   float4* rec;
 };
+
+inline int64_t flag_bytes(int64_t nseg) { return (nseg + kTile - 1) / kTile * kTile; }
 
 LazyWs carve(const fhash_lazy* lz) {
   const int64_t nseg = lazy_num_segments(lz->end - lz->begin);
@@ -458,8 +480,8 @@ LazyWs carve(const fhash_lazy* lz) {
   LazyWs w;
   w.state = reinterpret_cast<uint2*>(b);
   b += align256((size_t)nseg * 8);
-  w.list = reinterpret_cast<uint2*>(b);
-  b += align256((size_t)nseg * 8);
+  w.flags = reinterpret_cast<uint8_t*>(b);
+  b += align256((size_t)flag_bytes(nseg));
   w.ctr = reinterpret_cast<unsigned long long*>(b);
   b += 256;
   w.rec = reinterpret_cast<float4*>(b);
@@ -477,23 +499,34 @@ AdamK lazy_base(const fhash_lazy* lz) {
   return make_adam_k(&o);
 }
 
-// Fixed grid for the list kernels (the list length is only known on the
-// device): grid-strided over chunks.
-constexpr unsigned kListBlocks = 2048;
+// Grid of the catch-up: grid-strided over tiles of flags.
+constexpr int64_t kCatchUpBlocks = 2048;
 
-// Catch up the listed segments to step `steps`, then empty the list.
-void launch_catch_up(const fhash_lazy* lz, const LazyWs& w, float* p, float* gr, float* m,
-                     float* v, void* shadow, fhash_dtype sdt, hipStream_t st) {
+// Catch up the flagged segments to step `steps` (stamping them `target`, or
+// keeping their stamps when 0) and clear the flags.  expected: about how many
+// flags are set (0: unknown, dense); it sizes the groups of tiles so that a
+// group holds about one chunk.
+void launch_catch_up(const fhash_lazy* lz, const LazyWs& w, uint32_t target, int64_t expected,
+                     float* p, float* gr, float* m, float* v, void* shadow, fhash_dtype sdt,
+                     hipStream_t st) {
   const int64_t nseg = lazy_num_segments(lz->end - lz->begin);
+  if (nseg == 0) return;
+  const int64_t ntiles = flag_bytes(nseg) / kTile;
+  int64_t group = 1;
+  if (expected > 0 && expected < nseg) {
+    group = (2 * (int64_t)kChunk * nseg + kTile * expected) / (2 * (int64_t)kTile * expected);
+    group = group < 1 ? 1 : (group > 64 ? 64 : group);
+  }
+  int64_t blocks = (ntiles + group - 1) / group;
+  if (blocks > kCatchUpBlocks) blocks = kCatchUpBlocks;
   const bool odd = (lz->flags & 1) != 0;
   auto kern = odd ? (lz->moments == FHASH_MOMENTS_PAIRED ? lazy_catchup_kernel<true, true>
                                                          : lazy_catchup_kernel<true, false>)
                   : (lz->moments == FHASH_MOMENTS_PAIRED ? lazy_catchup_kernel<false, true>
                                                          : lazy_catchup_kernel<false, false>);
-  hipLaunchKernelGGL(kern, dim3(kListBlocks), dim3(256), 0, st, w.list, w.ctr, w.state, w.rec,
-                     lazy_base(lz), p, gr, m, v, shadow, (int)sdt, lz->begin, lz->end,
-                     (uint32_t)lz->steps, nseg);
-  hipLaunchKernelGGL(lazy_empty_list_kernel, dim3(1), dim3(64), 0, st, w.ctr);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, w.flags, nseg, w.ctr,
+                     w.state, w.rec, lazy_base(lz), p, gr, m, v, shadow, (int)sdt, lz->begin,
+                     lz->end, (uint32_t)lz->steps, target, (int)group, kChunk / 2);
 }
 
 }  // namespace
@@ -502,7 +535,8 @@ int64_t lazy_num_segments(int64_t range_floats) { return (range_floats + kSeg - 
 
 size_t lazy_ws_bytes(int64_t range_floats, int64_t max_steps) {
   const int64_t nseg = lazy_num_segments(range_floats);
-  return 2 * align256((size_t)nseg * 8) + 256 + align256((size_t)(max_steps + 1) * 16);
+  return align256((size_t)nseg * 8) + align256((size_t)flag_bytes(nseg)) + 256 +
+         align256((size_t)(max_steps + 1) * 16);
 }
 
 hipError_t launch_lazy_init(const fhash_lazy* lz, hipStream_t st) {
@@ -522,15 +556,16 @@ hipError_t launch_lazy_prepare(const GridDev& g, int l0, int l1, const float* po
                                void* shadow, fhash_dtype sdt, uint32_t phases, hipStream_t st) {
   const LazyWs w = carve(lz);
   const uint32_t S = (uint32_t)lz->steps;
-  const int64_t nseg = lazy_num_segments(lz->end - lz->begin);
   if ((phases & FHASH_LAZY_MARK) && n > 0 && l0 < l1) {
     int64_t b = (n + 255) / 256;
     if (b > 4096) b = 4096;
     hipLaunchKernelGGL(lazy_mark_kernel, dim3((unsigned)b), dim3(256), 0, st, g, l0, l1,
-                       reinterpret_cast<const float4*>(pos), n, w.state, w.list, w.ctr,
-                       lz->begin, lz->end, S + 1, (unsigned long long)nseg);
+                       reinterpret_cast<const float4*>(pos), n, w.flags, lz->begin, lz->end);
   }
-  if (phases & FHASH_LAZY_CATCH_UP) launch_catch_up(lz, w, p, gr, m, v, shadow, sdt, st);
+  // at most 9 segments per sample and level (8 row pairs, one may straddle)
+  const int64_t expected = n * (int64_t)(l1 > l0 ? l1 - l0 : 0) * 9;
+  if (phases & FHASH_LAZY_CATCH_UP)
+    launch_catch_up(lz, w, S + 1, expected, p, gr, m, v, shadow, sdt, st);
   return hipGetLastError();
 }
 
@@ -558,13 +593,14 @@ hipError_t launch_lazy_flush(const fhash_lazy* lz, float* p, float* gr, float* m
   const LazyWs w = carve(lz);
   const int64_t nseg = lazy_num_segments(lz->end - lz->begin);
   if (nseg == 0 || lz->steps == 0) return hipSuccess;
-  // segments marked without their catch-up first: the list is then empty
-  launch_catch_up(lz, w, p, gr, m, v, shadow, sdt, st);
-  int64_t b = (nseg + 256 * kCompactPerThread - 1) / (256 * kCompactPerThread);
+  // segments marked without their catch-up first (enrolled in the open step);
+  // then every flag is clear
+  launch_catch_up(lz, w, (uint32_t)lz->steps + 1, 0, p, gr, m, v, shadow, sdt, st);
+  int64_t b = (nseg + 256 * 8 - 1) / (256 * 8);
   if (b > 65536) b = 65536;
-  hipLaunchKernelGGL(lazy_compact_kernel, dim3((unsigned)b), dim3(256), 0, st, nseg, w.state,
-                     w.list, w.ctr, (uint32_t)lz->steps);
-  launch_catch_up(lz, w, p, gr, m, v, shadow, sdt, st);
+  hipLaunchKernelGGL(lazy_flag_stale_kernel, dim3((unsigned)b), dim3(256), 0, st, nseg, w.state,
+                     w.flags, (uint32_t)lz->steps);
+  launch_catch_up(lz, w, 0u, 0, p, gr, m, v, shadow, sdt, st);
   return hipGetLastError();
 }
 

@@ -5,7 +5,9 @@
 //   - random 16-byte reads (every lane a different line),
 //   - random 16-byte atomic groups (4 lanes add one float each into 16
 //     consecutive bytes, as 2F lanes scatter one x-pair of a row pair),
-// over a 24 GiB buffer, at 64K to 4M threads.  Not part of the library.
+// over a 24 GiB buffer, at 64K to 4M threads; then atomics against the bytes
+// one instruction puts into a line and the footprint, and a read followed by
+// an atomic into the same line or another.  Not part of the library.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -57,6 +59,37 @@ __global__ void group_atomic(float* __restrict__ buf, uint64_t nlines, int iters
   }
 }
 
+// W lanes add one float each into W consecutive floats of one random line
+// (W divides 32): how the atomic rate depends on the bytes an instruction puts
+// into one line.
+__global__ void wide_atomic(float* __restrict__ buf, uint64_t nlines, int iters, int W) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t g = t / W;
+  const int l = (int)(t % W);
+  for (int k = 0; k < iters; ++k) {
+    const uint64_t r = mix64(g * 131 + k);
+    unsafeAtomicAdd(buf + (r % nlines) * 32 + ((r >> 59) % (32 / W)) * W + l, 1.0f);
+  }
+}
+
+// Gather then scatter, as the fused training step does per row: 4 lanes read
+// 16 bytes of the first half of a random line, then add (the read value + 1)
+// into 16 bytes of the second half of the same line (same = 1) or of another
+// random line (same = 0).
+__global__ void read_then_atomic(float* __restrict__ buf, uint64_t nlines, int iters, int same) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t g = t / 4;
+  const int l = (int)(t % 4);
+  for (int k = 0; k < iters; ++k) {
+    const uint64_t r = mix64(g * 131 + k);
+    const uint64_t a = r % nlines;
+    const uint64_t b = same ? a : mix64(r) % nlines;
+    const int q = (int)((r >> 60) % 4) * 4;
+    const float v = buf[a * 32 + q + l];
+    unsafeAtomicAdd(buf + b * 32 + 16 + q + l, v + 1.0f);
+  }
+}
+
 bool ok(hipError_t e, const char* what) {
   if (e == hipSuccess) return true;
   std::fprintf(stderr, "%s: %s\n", what, hipGetErrorString(e));
@@ -104,6 +137,46 @@ int main() {
                 kthreads, lines / ms[0] / 1e6, lines * 128 / ms[0] / 1e6, words / ms[1] / 1e6,
                 words * 128 / ms[1] / 1e6, groups / ms[2] / 1e6, groups * 256 / ms[2] / 1e6);
     std::fflush(stdout);
+  }
+  // atomic rate against the bytes per line per instruction and the footprint
+  // (4 MiB: one XCD's L2; 128 MiB: inside the last-level cache; 24 GiB), and
+  // against a read of the same line just before; 4M threads
+  {
+    const uint64_t threads = 4096ull * 1024;
+    const unsigned blocks = (unsigned)(threads / 256);
+    for (int W : {1, 4, 16, 32}) {
+      for (uint64_t foot : {(uint64_t)4 << 20, (uint64_t)128 << 20, bytes}) {
+        const uint64_t nl = foot / 128;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          hipEventRecord(a);
+          hipLaunchKernelGGL(wide_atomic, dim3(blocks), dim3(256), 0, 0, buf, nl, iters, W);
+          hipEventRecord(b);
+          if (!ok(hipEventSynchronize(b), "kernel")) return 1;
+          hipEventElapsedTime(&ms, a, b);
+        }
+        const double groups = threads / (double)W * iters;
+        std::printf("atomics: %2d lanes per line, footprint %8.0f MiB: %.2f G lines/s, "
+                    "%.1f G lane-atomics/s\n",
+                    W, foot / 1048576.0, groups / ms / 1e6, threads * (double)iters / ms / 1e6);
+        std::fflush(stdout);
+      }
+    }
+    for (int same : {0, 1}) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        hipEventRecord(a);
+        hipLaunchKernelGGL(read_then_atomic, dim3(blocks), dim3(256), 0, 0, buf, nlines, iters,
+                           same);
+        hipEventRecord(b);
+        if (!ok(hipEventSynchronize(b), "kernel")) return 1;
+        hipEventElapsedTime(&ms, a, b);
+      }
+      const double groups = threads / 4.0 * iters;
+      std::printf("16-B read then 16-B atomic group into %s line: %.2f G pairs/s\n",
+                  same ? "the same" : "another", groups / ms / 1e6);
+      std::fflush(stdout);
+    }
   }
   return 0;
 }

@@ -103,9 +103,10 @@ def test_lazy_descriptor_validated_before_any_launch():
     """The deferred-Adam calls size their workspace and reject malformed
     descriptors on the host (no device needed)."""
     L = fl.lib()
-    # state 8 B + list 8 B per 16-float segment, 256 B counters, 16 B per step (+1)
+    # state 8 B per 16-float segment, one claim flag byte per segment (in whole
+    # tiles of 2048), 256 B counters, 16 B per step (+1); each part 256-aligned
     nb = L.fhash_lazy_workspace_bytes(16 * 1000, 100)
-    assert nb == 8192 + 8192 + 256 + 1792
+    assert nb == 8192 + 2048 + 256 + 1792
     assert L.fhash_lazy_workspace_bytes(-1, 10) == 0
     fake = ctypes.c_void_p(1 << 20)
     o = fl.AdamDesc()
