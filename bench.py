@@ -76,6 +76,14 @@ CLASSIFY_TRAFFIC = {"bytes": 17141931808.0, "shape": [480, 720, 120, 100],
                     "kernel_md5": "069f488afcee6ec399a6892a53ef8c05"}
 
 
+def _layout_kw(args, lazy=True):
+    """Model keywords of the optimiser state layout chosen by --moments (the
+    layout with parameters is built for the deferred update's models)."""
+    return {"paired_moments": args.moments == "paired" or (args.moments == "with-params"
+                                                         and not lazy),
+            "moments_with_params": args.moments == "with-params" and lazy}
+
+
 def _kernel_md5(path, name):
     """md5 of one kernel's source text: from the line holding `name(` back to
     the preceding __global__, through the brace that closes its body."""
@@ -128,9 +136,12 @@ def parse():
                          "instead of the vertices of active cells; samples still come from "
                          "the coreset")
     ap.add_argument("--hidden-layers", type=int, default=2)
-    ap.add_argument("--moments", choices=["paired", "separate"], default="paired",
-                    help="Adam moments layout: m and v of a 16-parameter segment in one "
-                         "128-byte line (paired), or two arrays")
+    ap.add_argument("--moments", choices=["with-params", "paired", "separate"],
+                    default="with-params",
+                    help="optimiser state layout of the deferred-Adam models: a segment's 16 "
+                         "parameters and their m in one 128-byte line and its gradients and v "
+                         "in another (with-params), m and v in one line (paired), or four "
+                         "arrays")
     ap.add_argument("--layout", choices=["rows", "bricks"], default="rows",
                     help="slot order of the active index: the F-Hash equation's rows, or "
                          "2x2x2x2 vertex bricks (Sec. 3.2.3 allows other linearisations)")
@@ -294,7 +305,7 @@ def key_frame_bench(args):
         cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=args.hidden_layers,
                           layout=LAYOUTS[args.layout])
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3000, lazy=True,
-                           paired_moments=args.moments == "paired",
+                           **_layout_kw(args),
                            max_steps=args.steps + 8)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -311,7 +322,7 @@ def key_frame_bench(args):
             r[f"psnr_{name}_db"] = psnr_on(model, pp, pt)
         out["runs"][label] = r
         log(f"[keyframes] {label}: {r}")
-        model.params = model.grads = model.m = model.v = model.mv = None
+        model.params = model.grads = model.m = model.v = model.mv = model.pm = model.gv = None
         del model, probes
         torch.cuda.empty_cache()
     out["value"] = out["runs"]["key_frames"]["psnr_unseen_db"]
@@ -366,7 +377,7 @@ def fold_sweep_bench(args):
                 continue
             cfg = FHashConfig(res=res, n_features=F, hidden=64, n_hidden=2)
             model = FHashModel(cfg, None, dims, init_seed=3000, lazy=True,
-                               paired_moments=args.moments == "paired",
+                               **_layout_kw(args, lazy=False),
                                max_steps=args.steps + 8)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             fb_ms = []
@@ -398,7 +409,8 @@ def fold_sweep_bench(args):
                          "dense_adam_ms": ev[2].elapsed_time(ev[3]), "psnr_db": psnr})
             cells.append(cell)
             log(f"[fold] fold {fold} F {F}: {cell}")
-            model.params = model.grads = model.m = model.v = model.mv = model.lazy = None
+            model.params = model.grads = model.m = model.v = None
+            model.mv = model.pm = model.gv = model.lazy = None
             del model
             torch.cuda.empty_cache()
     out = {"metric": "training ms/step and probe PSNR over embedding size x fold (dense FBB)",
@@ -442,7 +454,7 @@ def serve_multi_bench(args):
             cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3,
                               layout=LAYOUTS[args.layout])
             model = FHashModel(cfg, gen["bits"], dims, init_seed=seed + 2000, lazy=True,
-                               paired_moments=args.moments == "paired",
+                               **_layout_kw(args),
                                max_steps=args.serve_train_steps + 8)
             B = 1 << 20
             pos = torch.empty(B, 4, device="cuda")
@@ -467,7 +479,7 @@ def serve_multi_bench(args):
             info.append({"model": name, "params": model.n_params, "probe_psnr_db": psnr,
                          "resident_bytes": models[name].nbytes()})
             del gen, pos, tgt
-            model.params = model.grads = model.m = model.v = model.mv = None
+            model.params = model.grads = model.m = model.v = model.mv = model.pm = model.gv = None
             del model
             torch.cuda.empty_cache()
             log(f"[multi] {name}: {info[-1]['params']} params, PSNR {psnr:.1f} dB, resident "
@@ -571,7 +583,7 @@ def serve_bench(args):
     cfg = FHashConfig(res=res, n_features=2, hidden=64, n_hidden=3,
                       layout=LAYOUTS[args.layout])
     model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, lazy=True,
-                       paired_moments=args.moments == "paired",
+                       **_layout_kw(args),
                        max_steps=args.serve_train_steps + 8)
     log(f"[serve] model: {model.rows} active vertices, {model.n_params} params")
     B = 1 << 20
@@ -597,7 +609,7 @@ def serve_bench(args):
     params = model.mlp_params.clone()
     bits = gen["bits"]
     del gen, pos, tgt, ppos, ptgt
-    model.params = model.grads = model.m = model.v = model.mv = None
+    model.params = model.grads = model.m = model.v = model.mv = model.pm = model.gv = None
     torch.cuda.empty_cache()
     tf = torch.from_numpy(synth.transfer_function()).cuda()
     mlp = fl.mlp_desc(cfg.width, fl.F16 if args.serve_decoder == "f16" else fl.F32)
@@ -1003,11 +1015,16 @@ def compulsory_lines(model, pos, line=128):
     the fused training kernel must move for this batch (the corners of every
     sample at every level, fhash_corner_rows), in bytes: directory and table
     lines are read once, gradient lines read and written once; plus 20 bytes
-    of sample I/O per sample."""
+    of sample I/O per sample.  In the paired parameter layout a 16-float
+    segment's parameters and gradient fill one 128-byte line: the FP32 path's
+    table lines are its gradient lines (read once, written once)."""
     from paper_2507_03836_amd import _lib as fl
     n = pos.shape[0]
     F = model.cfg.n_features
     tb = 2 if model.shadow is not None else 4
+    paired = getattr(model, "moments_with_params", False)
+    gb = 8 if paired else 4  # bytes of a gradient float's line share
+    shared = paired and model.shadow is None
     dir_lines, tab_lines, grad_lines = [], [], []
     for s in range(0, n, 1 << 16):
         e = min(n, s + (1 << 16))
@@ -1017,13 +1034,16 @@ def compulsory_lines(model, pos, line=128):
         dir_lines.append(torch.unique(d * 16 // line))
         sl = sl.view(-1)
         sl = sl[sl >= 0]
-        tab_lines.append(torch.unique(sl * (F * tb) // line))
-        grad_lines.append(torch.unique(sl * (F * 4) // line))
+        if not shared:
+            tab_lines.append(torch.unique(sl * (F * tb) // line))
+        grad_lines.append(torch.unique(sl * (F * gb) // line))
         del d, sl
     u = lambda xs: int(torch.unique(torch.cat(xs)).numel())
-    nd, nt, ng = u(dir_lines), u(tab_lines), u(grad_lines)
+    nd, ng = u(dir_lines), u(grad_lines)
+    nt = ng if shared else u(tab_lines)
     return {"line_bytes": line, "directory_lines": nd, "table_lines": nt, "gradient_lines": ng,
-            "bytes": line * (nd + nt + 2 * ng) + 20 * n}
+            "table_lines_are_gradient_lines": shared,
+            "bytes": line * (nd + (0 if shared else nt) + 2 * ng) + 20 * n}
 
 
 def _serve_sub(model, gen, dims, args, n_req):
@@ -1036,8 +1056,11 @@ def _serve_sub(model, gen, dims, args, n_req):
     from paper_2507_03836_amd import synth
     from paper_2507_03836_amd.serving import (GpuExecutor, Request, ResidentModel, Scheduler,
                                               latency_stats, poisson_arrivals)
-    table16 = torch.empty(model.n_table, dtype=torch.float16, device="cuda")
-    fl.fhash_cast(model.table, table16)
+    if model.shadow is not None:  # the flushed master rounded to FP16
+        table16 = model.shadow[: model.n_table]
+    else:
+        table16 = torch.empty(model.n_table, dtype=torch.float16, device="cuda")
+        fl.fhash_cast(model.table, table16)
     tf = torch.from_numpy(synth.transfer_function()).cuda()
     rm = ResidentModel(index=model.index, mlp=model.mlp, table=table16,
                        params=model.mlp_params.clone(), mask_bits=gen["bits"], dims=dims, tf=tf,
@@ -1126,7 +1149,7 @@ def headline_bench(args):
     for prec in ("fp32", "mixed"):
         small = FHashModel(FHashConfig(res=[[4, 4, 4, 2]] * 16, n_features=2, hidden=64,
                                        n_hidden=3), None, dims, precision=prec, lazy=True,
-                           paired_moments=args.moments == "paired", max_steps=4)
+                           **_layout_kw(args), max_steps=4)
         fl.fhash_sample(1, 1, 4096, gen["coreset"], gen["M"], dims, gen["field"], pos, tgt)
         small.prepare(pos[:4096])
         small.fwd_bwd(pos[:4096], tgt[:4096], prepared=True)
@@ -1140,7 +1163,7 @@ def headline_bench(args):
     paths, keep = {}, None
     for prec in ("fp32", "mixed"):
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, precision=prec, lazy=True,
-                           paired_moments=args.moments == "paired",
+                           **_layout_kw(args),
                            max_steps=args.max_steps + args.warmup + args.steps + 8)
         r, step, t_first = _train_timed(model, gen, dims, B, args.steps, args.warmup, 2003, pos,
                                         tgt)
@@ -1169,11 +1192,12 @@ def headline_bench(args):
                     cpu = cpu_baseline_all_cores(model, gen, dims, B, args.cpu_samples, 2003)
                 except Exception as e:  # reported, never hidden
                     cpu = {"error": repr(e)}
-            model.params = model.grads = model.m = model.v = model.mv = model.lazy = None
+            model.params = model.grads = model.m = model.v = None
+            model.mv = model.pm = model.gv = model.lazy = None
             del model
             torch.cuda.empty_cache()
     model = keep
-    model.grads = model.m = model.v = model.mv = None
+    model.grads = model.m = model.v = model.mv = model.pm = model.gv = None
     model.lazy = None
     torch.cuda.empty_cache()
     serve = _serve_sub(model, gen, dims, args, args.serve_requests)
@@ -1260,7 +1284,7 @@ def main():
                        hash_bits=args.hash_bits, init_seed=3000 + args.field_seed - 1000,
                        precision=args.precision, track_touched=args.optimizer == "tracked",
                        lazy=args.optimizer == "lazy",
-                       paired_moments=args.moments == "paired",
+                       **_layout_kw(args, args.optimizer == "lazy"),
                        max_steps=max(args.max_steps, args.warmup + args.steps) + 64)
     torch.cuda.synchronize()
     dense = sum(int(np.prod(r)) for r in res)

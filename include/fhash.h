@@ -49,7 +49,11 @@ enum {
   FHASH_ENOTSUP = -5  /* valid but not built (dtype, feature count, width)   */
 };
 
-typedef enum { FHASH_F32 = 0, FHASH_F16 = 1, FHASH_BF16 = 2 } fhash_dtype;
+/* FHASH_F32_PAIRED (a table dtype only): FP32 values stored in runs of 16
+ * floats, each run followed by 16 floats of another array (in the optimiser
+ * layout FHASH_MOMENTS_WITH_PARAMS below, those are the same parameters'
+ * first moments): value i at float i + 16 floor(i / 16). */
+typedef enum { FHASH_F32 = 0, FHASH_F16 = 1, FHASH_BF16 = 2, FHASH_F32_PAIRED = 3 } fhash_dtype;
 
 /* Level structure of the multi-resolution tesseract grid (Sec. 3.2.1-3.2.2).
  * res[l] = vertex counts (x, y, z, t) of level l, each in [2, 2^24], with
@@ -179,8 +183,9 @@ int fhash_key_frame_times(int64_t T, const int32_t* frames, int32_t n_frames, fl
  * fraction = u - cell), look up the 16 corner slots, and blend the corner
  * embeddings with quadrilinear weights prod_d (f_d or 1 - f_d).  Inactive
  * corners contribute zero (no renormalisation).
- * pos: device float4[n]; table: device [rows][F] of table_dt (FHASH_F32 master
- * or FHASH_F16 shadow); enc: device float [n][L*F], level-major.
+ * pos: device float4[n]; table: device [rows][F] of table_dt (FHASH_F32 master,
+ * FHASH_F32_PAIRED master in the paired layout, or FHASH_F16 shadow); enc:
+ * device float [n][L*F], level-major.
  * FP32 accumulation. */
 int fhash_encode_fwd(const fhash_index* idx, const float* pos, int64_t n, const void* table,
                      fhash_dtype table_dt, float* enc, void* stream);
@@ -216,7 +221,8 @@ typedef struct {
 /* Adjoint of the encoding: d_table[slot][k] += w_c * d_enc[s][l*F + k] for every
  * active corner c of every sample and level (FP32 atomics; summation order is
  * not deterministic).  The corner weights are recomputed from pos, not stored.
- * d_enc: device float [n][L*F]; d_table: device float [rows][F], accumulated.
+ * d_enc: device float [n][L*F]; d_table: device float [rows][F], accumulated
+ * (dense; the fused calls below also write a gradient in the paired layout).
  * touch: NULL, or segment flags to set (see fhash_touch). */
 int fhash_encode_bwd(const fhash_index* idx, const float* pos, int64_t n, const float* d_enc,
                      float* d_table, const fhash_touch* touch, void* stream);
@@ -255,7 +261,9 @@ int fhash_mlp_bwd(const fhash_mlp_desc* mlp, const float* params, const void* sh
 /* ------------------------------------------------------------ fused path ----
  * Encoding fused with the decoder.  fhash_fused_fwd: y = MLP(encode(pos)).
  * fhash_fused_bwd: given dy, recompute the encoding and activations and
- * accumulate d_table (atomics) and d_params (deterministic).
+ * accumulate d_table (atomics) and d_params (each workgroup's waves add into
+ * one LDS image in arrival order, the workgroups' images are then summed in a
+ * fixed order: reproducible up to FP32 rounding, not bit for bit).
  * fhash_fused_train: forward, MSE loss against target, backward in one pass:
  *   dL/dy_s = loss_scale * 2 (y_s - target_s) / n,
  * loss_sum (device double, accumulated) += sum_s (y_s - target_s)^2. */
@@ -266,9 +274,14 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
  * fhash_sort_samples; the scatter-add then sums equal slots of neighbouring
  * samples with a wave-level segmented reduction before its atomics on the
  * levels coarse enough for neighbours to share vertices.  Results are the same
- * up to FP32 summation order.  touch: NULL, or segment flags of d_table to set
- * (see fhash_touch). */
+ * up to FP32 summation order.  FHASH_GRAD_PAIRED: d_table is stored in runs
+ * of 16 floats separated by 16-float gaps (gradient value i at
+ * d_table[i + 16 floor(i / 16)]; the gradient array of the optimiser layout
+ * FHASH_MOMENTS_WITH_PARAMS below); the table read is independent of it
+ * (table_dt).  Other bits: FHASH_EINVAL.  touch: NULL, or segment flags of
+ * d_table to set, by logical float index (see fhash_touch). */
 #define FHASH_SAMPLES_SORTED 1u
+#define FHASH_GRAD_PAIRED 2u
 int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
                     const void* table, fhash_dtype table_dt, const float* params,
                     const void* shadow, const float* dy, float* d_table, float* d_params,
@@ -320,13 +333,24 @@ int fhash_fused_train_static(const fhash_index* idx, const fhash_mlp_desc* mlp,
  * 16b .. 16b+15 followed by their v (float[2 * ceil(n / 16) * 16]): pass its
  * start as m and its start + 16 floats as v (FHASH_EINVAL otherwise).  The
  * paired layout keeps a segment's two moments in one 128-byte line, which the
- * deferred update below reads and writes per segment. */
-enum { FHASH_MOMENTS_SEPARATE = 0, FHASH_MOMENTS_PAIRED = 1 };
+ * deferred update below reads and writes per segment.
+ * FHASH_MOMENTS_WITH_PARAMS: two arrays in blocks of 32 floats (each
+ * float[2 * ceil(n / 16) * 16]), one holding parameters 16b .. 16b+15 followed
+ * by their m, the other their gradients followed by their v: pass param and
+ * grad at the arrays' starts, m = param + 16 floats, v = grad + 16 floats
+ * (FHASH_EINVAL otherwise).  A segment's whole optimiser state is then two
+ * lines, the same number as with paired moments while parameters and
+ * gradients stay dense, and the fused calls read such a table as
+ * FHASH_F32_PAIRED and write its gradient with FHASH_GRAD_PAIRED; the lines
+ * the forward gathers parameters from are never the lines the backward's
+ * atomics add into.  shadow stays dense in every layout: shadow[i] is
+ * parameter i. */
+enum { FHASH_MOMENTS_SEPARATE = 0, FHASH_MOMENTS_PAIRED = 1, FHASH_MOMENTS_WITH_PARAMS = 2 };
 typedef struct {
   double lr, beta1, beta2, eps; /* the kernel uses FP32 roundings of b1, 1-b1, b2, 1-b2 */
   int64_t step;                 /* 1-based */
   double grad_scale;
-  int64_t moments;              /* FHASH_MOMENTS_SEPARATE or FHASH_MOMENTS_PAIRED */
+  int64_t moments;              /* FHASH_MOMENTS_SEPARATE, _PAIRED or _WITH_PARAMS */
 } fhash_adam_desc;
 
 int fhash_step(const fhash_adam_desc* opt, float* param, float* grad, float* m, float* v,
@@ -375,8 +399,8 @@ typedef struct {
   int64_t steps;
   double beta1, beta2, eps;
   int64_t flags; /* library-owned: bit 0, a step with a non-finite grad_scale was recorded */
-  int64_t moments; /* layout of m and v (see fhash_adam_desc), set by the caller; every
-                      fhash_step_lazy must pass the same */
+  int64_t moments; /* optimiser state layout (see fhash_adam_desc), set by the caller;
+                      every fhash_step_lazy must pass the same */
 } fhash_lazy;
 
 size_t fhash_lazy_workspace_bytes(int64_t range_floats, int64_t max_steps);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfhash.so")
 
 MAX_LEVELS = 24
 MAX_LAYERS = 8
-F32, F16, BF16 = 0, 1, 2
+F32, F16, BF16, F32_PAIRED = 0, 1, 2, 3
 OK, EINVAL, ENOMEM, EHIP, ERANGE, ENOTSUP = 0, -1, -2, -3, -4, -5
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ERANGE: "ERANGE", ENOTSUP: "ENOTSUP"}
 
@@ -52,7 +52,7 @@ class MlpDesc(C.Structure):
                 ("compute_dt", C.c_int32)]
 
 
-MOMENTS_SEPARATE, MOMENTS_PAIRED = 0, 1
+MOMENTS_SEPARATE, MOMENTS_PAIRED, MOMENTS_WITH_PARAMS = 0, 1, 2
 
 
 class AdamDesc(C.Structure):
@@ -228,11 +228,24 @@ def _check(rc: int, func: str):
         raise FHashError(rc, func, lib().fhash_last_error().decode())
 
 
+class Paired:
+    """A table argument stored in runs of 16 floats separated by 16-float gaps
+    (FHASH_F32_PAIRED): the parameter array of the optimiser layout
+    MOMENTS_WITH_PARAMS, whose gaps hold the first moments."""
+
+    def __init__(self, t: torch.Tensor):
+        if t.dtype != torch.float32:
+            raise TypeError("a paired table is FP32")
+        self.t = t
+
+
 def _ptr(t):
     if t is None:
         return None
     if isinstance(t, torch.Tensor):
         return C.c_void_p(t.data_ptr())
+    if isinstance(t, Paired):
+        return C.c_void_p(t.t.data_ptr())
     return t
 
 
@@ -240,7 +253,9 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _dt(t: torch.Tensor) -> int:
+def _dt(t) -> int:
+    if isinstance(t, Paired):
+        return F32_PAIRED
     return {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}[t.dtype]
 
 
@@ -377,7 +392,7 @@ def fhash_fused_fwd(idx: Index, mlp: MlpDesc, pos, n, table, params, y, shadow=N
            "fhash_fused_fwd")
 
 
-SAMPLES_SORTED = 1
+SAMPLES_SORTED, GRAD_PAIRED = 1, 2
 
 
 def fhash_fused_bwd(idx: Index, mlp: MlpDesc, pos, n, table, params, dy, d_table, d_params,
@@ -409,10 +424,14 @@ def fhash_fused_train(idx: Index, mlp: MlpDesc, pos, target, n, table, params, d
     return ws
 
 
-def fhash_step(opt: AdamDesc, param, grad, m, v, shadow=None, found_inf=None, touch=None):
+def fhash_step(opt: AdamDesc, param, grad, m, v, shadow=None, found_inf=None, touch=None,
+               n=None):
+    """n: the parameter count (param.numel() by default; pass it for the
+    layout MOMENTS_WITH_PARAMS, whose arrays are longer)."""
     sdt = F16 if shadow is None else _dt(shadow)
+    n = param.numel() if n is None else int(n)
     _check(lib().fhash_step(C.byref(opt), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
-                            _ptr(shadow), sdt, param.numel(), _ptr(found_inf), _touch(touch),
+                            _ptr(shadow), sdt, n, _ptr(found_inf), _touch(touch),
                             _stream()), "fhash_step")
 
 
@@ -434,10 +453,11 @@ def fhash_lazy_stats(lazy: LazyState) -> dict:
 
 
 def fhash_step_lazy(opt: AdamDesc, param, grad, m, v, lazy: LazyState, shadow=None,
-                    found_inf=None):
+                    found_inf=None, n=None):
     sdt = F16 if shadow is None else _dt(shadow)
+    n = param.numel() if n is None else int(n)
     _check(lib().fhash_step_lazy(C.byref(opt), _ptr(param), _ptr(grad), _ptr(m), _ptr(v),
-                                 _ptr(shadow), sdt, param.numel(), _ptr(found_inf),
+                                 _ptr(shadow), sdt, n, _ptr(found_inf),
                                  C.byref(lazy.desc), _stream()), "fhash_step_lazy")
 
 

@@ -32,9 +32,10 @@ inline AdamK make_adam_k(const fhash_adam_desc* o) {
   return k;
 }
 
-// Float offset of the moment of parameter a: a itself, or in the paired
-// layout (blocks of 16 m values followed by the same parameters' 16 v values)
-// 32 (a / 16) + a % 16; the v array starts 16 floats after the m array.
+// Float offset of the moment of parameter a: a itself, or, when the moments
+// are stored in runs of 16 separated by 16-float gaps (paired: m runs
+// alternate with v runs, v = m + 16; with parameters: m runs follow the
+// parameters' runs, v runs the gradients'), 32 (a / 16) + a % 16.
 template <bool PAIRED>
 __host__ __device__ __forceinline__ int64_t moment_off(int64_t a) {
   if constexpr (PAIRED)

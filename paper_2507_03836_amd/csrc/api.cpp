@@ -78,8 +78,25 @@ int check_index(const fhash_index* idx) {
 int64_t total_rows(const fhash_index* idx) { return idx->slot_offset[idx->grid.n_levels]; }
 
 int check_table_dt(fhash_dtype dt) {
-  if (dt != FHASH_F32 && dt != FHASH_F16)
-    return fail(FHASH_ENOTSUP, "table dtype %d not supported (F32 or F16)", (int)dt);
+  if (dt != FHASH_F32 && dt != FHASH_F16 && dt != FHASH_F32_PAIRED)
+    return fail(FHASH_ENOTSUP, "table dtype %d not supported (F32, F32_PAIRED or F16)", (int)dt);
+  return FHASH_OK;
+}
+
+// The element type the kernels read for table dtype dt; a paired FP32 table
+// is read through the run mask of g.
+fhash_dtype table_view(fhash_dtype dt, fh::GridDev* g) {
+  if (dt != FHASH_F32_PAIRED) return dt;
+  g->tmask = ~(int64_t)15;
+  return FHASH_F32;
+}
+
+// Flags of the backward calls; FHASH_GRAD_PAIRED sets the gradient's run mask
+// (g may be NULL: check only).
+int apply_bwd_flags(uint32_t flags, fh::GridDev* g) {
+  if ((flags & ~(FHASH_SAMPLES_SORTED | FHASH_GRAD_PAIRED)) != 0)
+    return fail(FHASH_EINVAL, "unknown flags 0x%x", (unsigned)flags);
+  if (g != nullptr) g->gmask = (flags & FHASH_GRAD_PAIRED) ? ~(int64_t)15 : 0;
   return FHASH_OK;
 }
 
@@ -267,7 +284,8 @@ int fhash_encode_fwd(const fhash_index* idx, const float* pos, int64_t n, const 
   if (table == nullptr) return fail(FHASH_EINVAL, "table is NULL");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
-  return hip_status(fh::launch_encode_fwd(g, pos, n, table, table_dt, enc, S(stream)),
+  const fhash_dtype tdt = table_view(table_dt, &g);
+  return hip_status(fh::launch_encode_fwd(g, pos, n, table, tdt, enc, S(stream)),
                     "fhash_encode_fwd");
 }
 
@@ -399,11 +417,12 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
   if (y == nullptr) return fail(FHASH_EINVAL, "y is NULL");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
+  const fhash_dtype tdt = table_view(table_dt, &g);
   const hipError_t e =
       mlp->compute_dt != FHASH_F32
-          ? fh::launch_fused_fwd16(g, H, NH, mlp->compute_dt, pos, n, table, table_dt, params, y,
+          ? fh::launch_fused_fwd16(g, H, NH, mlp->compute_dt, pos, n, table, tdt, params, y,
                                    S(stream))
-          : fh::launch_fused_fwd(g, H, NH, pos, n, table, table_dt, params, y, S(stream));
+          : fh::launch_fused_fwd(g, H, NH, pos, n, table, tdt, params, y, S(stream));
   return hip_status(e, "fhash_fused_fwd");
 }
 
@@ -416,6 +435,7 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
   int H, NH;
   int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
   if (rc) return rc;
+  if ((rc = apply_bwd_flags(flags, nullptr))) return rc;
   const int64_t P = num_params(mlp);
   bool query;
   rc = ws_check(ws, ws_bytes, fh::fused_ws_bytes(n, P), &query);
@@ -425,9 +445,11 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
     return fail(FHASH_EINVAL, "NULL pointer");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
+  if ((rc = apply_bwd_flags(flags, &g))) return rc;
   g.dedup = dedup_mask(idx, n, flags);
   if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
-  return hip_status(fh::launch_fused_bwd(g, H, NH, mlp->compute_dt, pos, n, table, table_dt,
+  const fhash_dtype tdt = table_view(table_dt, &g);
+  return hip_status(fh::launch_fused_bwd(g, H, NH, mlp->compute_dt, pos, n, table, tdt,
                                          params, dy, d_table, d_params, ws, P, S(stream)),
                     "fhash_fused_bwd");
 }
@@ -441,6 +463,7 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
   int H, NH;
   int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
   if (rc) return rc;
+  if ((rc = apply_bwd_flags(flags, nullptr))) return rc;
   const int64_t P = num_params(mlp);
   bool query;
   rc = ws_check(ws, ws_bytes, fh::fused_ws_bytes(n, P), &query);
@@ -450,12 +473,13 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
     return fail(FHASH_EINVAL, "NULL pointer");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
+  if ((rc = apply_bwd_flags(flags, &g))) return rc;
   g.dedup = dedup_mask(idx, n, flags);
   if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
+  const fhash_dtype tdt = table_view(table_dt, &g);
   return hip_status(fh::launch_fused_train(g, H, NH, mlp->compute_dt, pos, target, n, table,
-                                           table_dt, params,
-                                           loss_scale, d_table, d_params, loss_sum, ws, P,
-                                           S(stream)),
+                                           tdt, params, loss_scale, d_table, d_params, loss_sum,
+                                           ws, P, S(stream)),
                     "fhash_fused_train");
 }
 
@@ -468,6 +492,7 @@ int fhash_fused_train_static(const fhash_index* idx, const fhash_mlp_desc* mlp,
   int H, NH;
   int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
   if (rc) return rc;
+  if ((rc = apply_bwd_flags(flags, nullptr))) return rc;
   if (n == 0) return FHASH_OK;
   if (target == nullptr || d_table == nullptr || d_params == nullptr)
     return fail(FHASH_EINVAL, "NULL pointer");
@@ -481,12 +506,25 @@ int fhash_fused_train_static(const fhash_index* idx, const fhash_mlp_desc* mlp,
   if (e != hipSuccess) return hip_status(e, "fhash_fused_train_static scratch");
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
+  if ((rc = apply_bwd_flags(flags, &g))) return rc;
   g.dedup = dedup_mask(idx, n, flags);
   if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
+  const fhash_dtype tdt = table_view(table_dt, &g);
   return hip_status(fh::launch_fused_train(g, H, NH, mlp->compute_dt, pos, target, n, table,
-                                           table_dt, params, loss_scale, d_table, d_params,
+                                           tdt, params, loss_scale, d_table, d_params,
                                            loss_sum, ws, P, S(stream)),
                     "fhash_fused_train_static");
+}
+
+// Where the optimiser layout ties the arrays together (fhash_adam_desc).
+static int check_state_pointers(int64_t layout, const float* param, const float* grad,
+                                const float* m, const float* v) {
+  if (layout == FHASH_MOMENTS_PAIRED && v != m + 16)
+    return fail(FHASH_EINVAL, "paired moments: v must start 16 floats after m");
+  if (layout == FHASH_MOMENTS_WITH_PARAMS && (m != param + 16 || v != grad + 16))
+    return fail(FHASH_EINVAL, "moments with parameters: m must start 16 floats after param "
+                "and v 16 floats after grad");
+  return FHASH_OK;
 }
 
 static int check_step(const fhash_adam_desc* opt, const float* param, const float* grad,
@@ -498,15 +536,15 @@ static int check_step(const fhash_adam_desc* opt, const float* param, const floa
   if (!(opt->lr >= 0.0) || !(opt->beta1 >= 0.0 && opt->beta1 < 1.0) ||
       !(opt->beta2 >= 0.0 && opt->beta2 < 1.0) || !(opt->eps > 0.0))
     return fail(FHASH_EINVAL, "bad Adam hyper-parameters");
-  if (opt->moments != FHASH_MOMENTS_SEPARATE && opt->moments != FHASH_MOMENTS_PAIRED)
+  if (opt->moments != FHASH_MOMENTS_SEPARATE && opt->moments != FHASH_MOMENTS_PAIRED &&
+      opt->moments != FHASH_MOMENTS_WITH_PARAMS)
     return fail(FHASH_EINVAL, "moments layout %lld unknown", (long long)opt->moments);
   if (n == 0) return FHASH_OK;
   if (param == nullptr || grad == nullptr || m == nullptr || v == nullptr)
     return fail(FHASH_EINVAL, "NULL pointer");
   if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
     return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
-  if (opt->moments == FHASH_MOMENTS_PAIRED && v != m + 16)
-    return fail(FHASH_EINVAL, "paired moments: v must start 16 floats after m");
+  if (int rc = check_state_pointers(opt->moments, param, grad, m, v)) return rc;
   if (shadow != nullptr) {
     if (shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
       return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
@@ -548,7 +586,8 @@ static int check_lazy(const fhash_lazy* lz) {
     return fail(FHASH_ERANGE, "max_steps outside [0, 2^32 - 1)");
   if (lz->steps < 0 || lz->steps > lz->max_steps)
     return fail(FHASH_EINVAL, "steps %lld outside [0, max_steps]", (long long)lz->steps);
-  if (lz->moments != FHASH_MOMENTS_SEPARATE && lz->moments != FHASH_MOMENTS_PAIRED)
+  if (lz->moments != FHASH_MOMENTS_SEPARATE && lz->moments != FHASH_MOMENTS_PAIRED &&
+      lz->moments != FHASH_MOMENTS_WITH_PARAMS)
     return fail(FHASH_EINVAL, "moments layout %lld unknown", (long long)lz->moments);
   return FHASH_OK;
 }
@@ -595,8 +634,7 @@ int fhash_lazy_prepare(const fhash_index* idx, const float* pos, int64_t n, fhas
     return fail(FHASH_EINVAL, "NULL pointer");
   if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
     return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
-  if (lz->moments == FHASH_MOMENTS_PAIRED && v != m + 16)
-    return fail(FHASH_EINVAL, "paired moments: v must start 16 floats after m");
+  if ((rc = check_state_pointers(lz->moments, param, grad, m, v))) return rc;
   if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
     return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
   if (shadow != nullptr && (reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)
@@ -632,11 +670,9 @@ int fhash_step_lazy(const fhash_adam_desc* opt, float* param, float* grad, float
   // dense part: [0, begin) and [end, n)
   hipError_t e = fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, lz->begin, 0,
                                  found_inf, nullptr, st);
-  if (e == hipSuccess) {
-    void* sh_tail = shadow ? static_cast<void*>(static_cast<uint16_t*>(shadow) + lz->end) : nullptr;
-    e = fh::launch_adam(opt, param + lz->end, grad + lz->end, m, v, sh_tail, shadow_dt,
-                        n - lz->end, lz->end, found_inf, nullptr, st);
-  }
+  if (e == hipSuccess)
+    e = fh::launch_adam(opt, param, grad, m, v, shadow, shadow_dt, n - lz->end, lz->end,
+                        found_inf, nullptr, st);
   if (e == hipSuccess)
     e = fh::launch_lazy_step(opt, lz, found_inf, st);
   if (e != hipSuccess) return hip_status(e, "fhash_step_lazy");
@@ -660,8 +696,7 @@ int fhash_lazy_flush(fhash_lazy* lz, float* param, float* grad, float* m, float*
     return fail(FHASH_EINVAL, "NULL pointer");
   if (!aligned16(param) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
     return fail(FHASH_EINVAL, "optimiser arrays must be 16-byte aligned");
-  if (lz->moments == FHASH_MOMENTS_PAIRED && v != m + 16)
-    return fail(FHASH_EINVAL, "paired moments: v must start 16 floats after m");
+  if ((rc = check_state_pointers(lz->moments, param, grad, m, v))) return rc;
   if (shadow != nullptr && shadow_dt != FHASH_F16 && shadow_dt != FHASH_BF16)
     return fail(FHASH_EINVAL, "shadow dtype must be F16 or BF16");
   if (shadow != nullptr && (reinterpret_cast<uintptr_t>(shadow) & 7u) != 0)
@@ -974,6 +1009,7 @@ int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* 
   if (rc) return rc;
   fh::GridDev g;
   fh::make_grid_dev(idx, &g);
+  const fhash_dtype tdt = table_view(table_dt, &g);
   while (st.n_alive > 0) {
     const int32_t pace = fhash_render_pace(NR, st.n_alive, opts->arm_max);
     int64_t ns = 0;
@@ -982,9 +1018,9 @@ int fhash_render(const fhash_index* idx, const fhash_mlp_desc* mlp, const void* 
     if (ns > 0) {
       hipError_t e =
           mlp->compute_dt != FHASH_F32
-              ? fh::launch_fused_fwd16(g, H_, NH, mlp->compute_dt, pos, ns, table, table_dt,
+              ? fh::launch_fused_fwd16(g, H_, NH, mlp->compute_dt, pos, ns, table, tdt,
                                        params, y, S(stream))
-              : fh::launch_fused_fwd(g, H_, NH, pos, ns, table, table_dt, params, y, S(stream));
+              : fh::launch_fused_fwd(g, H_, NH, pos, ns, table, tdt, params, y, S(stream));
       if (e != hipSuccess) return hip_status(e, "fhash_render decode");
     }
     rc = fhash_render_composite(&st, y, tf, opts, rgba, stream);

@@ -29,7 +29,16 @@ struct GridDev {
   uint32_t dedup;  // bit l: combine equal slots of neighbouring lanes before level l's atomics
   uint8_t* touch;  // touched-segment flags of the table gradient (NULL: not tracked)
   int64_t touch_begin;  // first tracked float (a multiple of FHASH_TOUCH_FLOATS)
+  // run masks of the table read and of the table gradient (run_off): 0, dense;
+  // ~15, the paired layout (16 values, then 16 floats of the other array)
+  int64_t tmask, gmask;
 };
+
+// Float offset of element i of a vector stored in runs of 16 values separated
+// by 16-float gaps (mask ~15), or densely (mask 0): i + 16 floor(i / 16).
+__host__ __device__ __forceinline__ int64_t run_off(int64_t i, int64_t mask) {
+  return i + (i & mask);
+}
 
 // Fill a GridDev from a public index descriptor (host).
 inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
@@ -41,6 +50,8 @@ inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
   g->dedup = 0;
   g->touch = nullptr;
   g->touch_begin = 0;
+  g->tmask = 0;
+  g->gmask = 0;
   for (int l = 0; l < FHASH_MAX_LEVELS; ++l) {
     LevelDev& d = g->lv[l];
     if (l < gd.n_levels) {

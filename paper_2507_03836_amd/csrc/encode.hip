@@ -25,9 +25,9 @@ __global__ void __launch_bounds__(256)
   for (int l = 0; l < g.L; ++l) {
     const LevelDev& d = g.lv[l];
     if (d.brick)
-      encode_level<F, T, true>(d, g.dir, g.active != 0, p, table, out + l * F);
+      encode_level<F, T, true>(d, g.dir, g.active != 0, p, table, out + l * F, g.tmask);
     else
-      encode_level<F, T, false>(d, g.dir, g.active != 0, p, table, out + l * F);
+      encode_level<F, T, false>(d, g.dir, g.active != 0, p, table, out + l * F, g.tmask);
   }
 }
 
@@ -46,10 +46,10 @@ __global__ void __launch_bounds__(256)
   for (int l = 0; l < g.L; ++l) {
     if (g.lv[l].brick)
       scatter_level_lane<F, true>(g.lv[l], g.dir, g.active != 0, p, e, f, gin[l * F + f],
-                                  d_table, g.touch, g.touch_begin);
+                                  d_table, g.touch, g.touch_begin, g.gmask);
     else
       scatter_level_lane<F, false>(g.lv[l], g.dir, g.active != 0, p, e, f, gin[l * F + f],
-                                   d_table, g.touch, g.touch_begin);
+                                   d_table, g.touch, g.touch_begin, g.gmask);
   }
 }
 

@@ -7,25 +7,26 @@
 
 namespace fh {
 
+// The F values of a table row whose first element is at offset e.
 template <int F, typename T>
 struct RowLoad;
 
 template <>
 struct RowLoad<1, float> {
-  static __device__ __forceinline__ void load(const float* t, int64_t s, float* o) { o[0] = t[s]; }
+  static __device__ __forceinline__ void load(const float* t, int64_t e, float* o) { o[0] = t[e]; }
 };
 template <>
 struct RowLoad<2, float> {
-  static __device__ __forceinline__ void load(const float* t, int64_t s, float* o) {
-    const float2 v = *reinterpret_cast<const float2*>(t + 2 * s);
+  static __device__ __forceinline__ void load(const float* t, int64_t e, float* o) {
+    const float2 v = *reinterpret_cast<const float2*>(t + e);
     o[0] = v.x;
     o[1] = v.y;
   }
 };
 template <>
 struct RowLoad<4, float> {
-  static __device__ __forceinline__ void load(const float* t, int64_t s, float* o) {
-    const float4 v = *reinterpret_cast<const float4*>(t + 4 * s);
+  static __device__ __forceinline__ void load(const float* t, int64_t e, float* o) {
+    const float4 v = *reinterpret_cast<const float4*>(t + e);
     o[0] = v.x;
     o[1] = v.y;
     o[2] = v.z;
@@ -34,23 +35,23 @@ struct RowLoad<4, float> {
 };
 template <>
 struct RowLoad<8, float> {
-  static __device__ __forceinline__ void load(const float* t, int64_t s, float* o) {
-    const float4 a = *reinterpret_cast<const float4*>(t + 8 * s);
-    const float4 b = *reinterpret_cast<const float4*>(t + 8 * s + 4);
+  static __device__ __forceinline__ void load(const float* t, int64_t e, float* o) {
+    const float4 a = *reinterpret_cast<const float4*>(t + e);
+    const float4 b = *reinterpret_cast<const float4*>(t + e + 4);
     o[0] = a.x, o[1] = a.y, o[2] = a.z, o[3] = a.w;
     o[4] = b.x, o[5] = b.y, o[6] = b.z, o[7] = b.w;
   }
 };
 template <>
 struct RowLoad<1, __half> {
-  static __device__ __forceinline__ void load(const __half* t, int64_t s, float* o) {
-    o[0] = __half2float(t[s]);
+  static __device__ __forceinline__ void load(const __half* t, int64_t e, float* o) {
+    o[0] = __half2float(t[e]);
   }
 };
 template <>
 struct RowLoad<2, __half> {
-  static __device__ __forceinline__ void load(const __half* t, int64_t s, float* o) {
-    const __half2 v = *reinterpret_cast<const __half2*>(t + 2 * s);
+  static __device__ __forceinline__ void load(const __half* t, int64_t e, float* o) {
+    const __half2 v = *reinterpret_cast<const __half2*>(t + e);
     const float2 f = __half22float2(v);
     o[0] = f.x;
     o[1] = f.y;
@@ -58,8 +59,8 @@ struct RowLoad<2, __half> {
 };
 template <>
 struct RowLoad<4, __half> {
-  static __device__ __forceinline__ void load(const __half* t, int64_t s, float* o) {
-    const uint2 raw = *reinterpret_cast<const uint2*>(t + 4 * s);
+  static __device__ __forceinline__ void load(const __half* t, int64_t e, float* o) {
+    const uint2 raw = *reinterpret_cast<const uint2*>(t + e);
     const __half2* h = reinterpret_cast<const __half2*>(&raw);
     const float2 a = __half22float2(h[0]), b = __half22float2(h[1]);
     o[0] = a.x, o[1] = a.y, o[2] = b.x, o[3] = b.y;
@@ -67,8 +68,8 @@ struct RowLoad<4, __half> {
 };
 template <>
 struct RowLoad<8, __half> {
-  static __device__ __forceinline__ void load(const __half* t, int64_t s, float* o) {
-    const uint4 raw = *reinterpret_cast<const uint4*>(t + 8 * s);
+  static __device__ __forceinline__ void load(const __half* t, int64_t e, float* o) {
+    const uint4 raw = *reinterpret_cast<const uint4*>(t + e);
     const __half2* h = reinterpret_cast<const __half2*>(&raw);
     for (int i = 0; i < 4; ++i) {
       const float2 a = __half22float2(h[i]);
@@ -81,11 +82,12 @@ struct RowLoad<8, __half> {
 // Forward of one level for one sample: out[k] = sum_c w_c E[slot_c][k].
 // Invalid (inactive) corners get weight 0 and read row 0, so every load is
 // unconditional and the 8 directory / 16 table loads overlap in flight.
-// Requires a table with at least one row.
+// Requires a table with at least one row.  tmask: the table's run mask
+// (run_off; F divides 16, so a row never straddles a run).
 template <int F, typename T, bool BRICK = false>
 __device__ __forceinline__ void encode_level(const LevelDev& d, const ulonglong2* dir, bool active,
                                              const float4 p, const T* __restrict__ table,
-                                             float* out) {
+                                             float* out, int64_t tmask) {
   int ix, iy, iz, it;
   float fx, fy, fz, ft;
   locate(p.x, d.rx, d.sx, ix, fx);
@@ -104,8 +106,8 @@ __device__ __forceinline__ void encode_level(const LevelDev& d, const ulonglong2
     bool v0, v1;
     corner_pair<BRICK>(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
     float e0[F], e1[F];
-    RowLoad<F, T>::load(table, v0 ? s0 : 0, e0);
-    RowLoad<F, T>::load(table, v1 ? s1 : 0, e1);
+    RowLoad<F, T>::load(table, run_off((v0 ? s0 : 0) * F, tmask), e0);
+    RowLoad<F, T>::load(table, run_off((v1 ? s1 : 0) * F, tmask), e1);
     const float w0 = v0 ? wr * (1.0f - fa) : 0.0f;
     const float w1 = v1 ? wr * fa : 0.0f;
 #pragma unroll
@@ -124,11 +126,13 @@ __device__ __forceinline__ void mark_touched(uint8_t* touch, int64_t tbeg, int64
 
 // Adjoint of encode_level: d_table[slot_c][k] += w_c g[k] with FP32 hardware
 // atomics (no return value).  Weights are recomputed from the position.
+// gmask: the gradient's run mask (run_off); touch flags index the logical
+// floats.
 template <int F, bool BRICK = false>
 __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong2* dir,
                                               bool active, const float4 p, const float* g,
                                               float* __restrict__ d_table, uint8_t* touch,
-                                              int64_t tbeg) {
+                                              int64_t tbeg, int64_t gmask) {
   int ix, iy, iz, it;
   float fx, fy, fz, ft;
   locate(p.x, d.rx, d.sx, ix, fx);
@@ -146,12 +150,12 @@ __device__ __forceinline__ void scatter_level(const LevelDev& d, const ulonglong
     const float w0 = wr * (1.0f - fa), w1 = wr * fa;
     if (v0) {
 #pragma unroll
-      for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + s0 * F + k, w0 * g[k]);
+      for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + run_off(s0 * F, gmask) + k, w0 * g[k]);
       mark_touched(touch, tbeg, s0 * F);
     }
     if (v1) {
 #pragma unroll
-      for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + s1 * F + k, w1 * g[k]);
+      for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + run_off(s1 * F, gmask) + k, w1 * g[k]);
       mark_touched(touch, tbeg, s1 * F);
     }
   }
@@ -169,7 +173,7 @@ template <int F, bool BRICK = false>
 __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulonglong2* dir,
                                                    bool active, const float4 p, int e, int f,
                                                    float gval, float* __restrict__ d_table,
-                                                   uint8_t* touch, int64_t tbeg) {
+                                                   uint8_t* touch, int64_t tbeg, int64_t gmask) {
   int ix, iy, iz, it;
   float fx, fy, fz, ft;
   locate(p.x, d.rx, d.sx, ix, fx);
@@ -187,7 +191,7 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
     corner_pair<BRICK>(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
     const int64_t s = e ? s1 : s0;
     if (e ? v1 : v0) {
-      unsafeAtomicAdd(d_table + s * F + f, wr * wx * gval);
+      unsafeAtomicAdd(d_table + run_off(s * F, gmask) + f, wr * wx * gval);
       if (f == 0) mark_touched(touch, tbeg, s * F);  // F divides the segment: one flag per slot
     }
   }
@@ -204,7 +208,7 @@ template <int F, bool BRICK = false>
 __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulonglong2* dir,
                                                     bool active, const float4 p, const float* g,
                                                     bool valid, float* __restrict__ d_table,
-                                                    uint8_t* touch, int64_t tbeg) {
+                                                    uint8_t* touch, int64_t tbeg, int64_t gmask) {
   const int i = threadIdx.x & 15;
   int ix, iy, iz, it;
   float fx, fy, fz, ft;
@@ -248,7 +252,7 @@ __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulo
       const bool tail = (i == 15) || (snext != s);
       if (tail && s >= 0) {
 #pragma unroll
-        for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + s * F + k, v[k]);
+        for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + run_off(s * F, gmask) + k, v[k]);
         mark_touched(touch, tbeg, s * F);
       }
     }

@@ -57,7 +57,7 @@ __device__ __forceinline__ void gather_block(const GridDev& g, const LevelDev* l
       const int l = (16 * a + 4 * grp) / F + j;
       float e[F];
       if (valid && l < g.L) {
-        encode_level<F, T, BRICK>(lv[l], g.dir, g.active != 0, p, table, e);
+        encode_level<F, T, BRICK>(lv[l], g.dir, g.active != 0, p, table, e, g.tmask);
       } else {
 #pragma unroll
         for (int k = 0; k < F; ++k) e[k] = 0.0f;
@@ -90,7 +90,7 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
 #pragma unroll
         for (int k = 0; k < F; ++k) gl[k] = dx[a][j * F + k];
         scatter_level_dedup<F, BRICK>(lv[l], g.dir, g.active != 0, p, gl, valid, d_table, g.touch,
-                               g.touch_begin);
+                                      g.touch_begin, g.gmask);
       }
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
@@ -111,8 +111,8 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
         for (int q = 1; q < F; ++q)
           if (f == q) gval = gsrc[q];
         if (ls < g.L && vs && !((g.dedup >> ls) & 1u))
-          scatter_level_lane<F, BRICK>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table, g.touch,
-                                g.touch_begin);
+          scatter_level_lane<F, BRICK>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table,
+                                       g.touch, g.touch_begin, g.gmask);
       }
     }
 }

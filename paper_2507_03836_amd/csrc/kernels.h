@@ -68,8 +68,8 @@ size_t static_scratch_bytes();
 hipError_t static_scratch(void** ptr);
 
 // optim.hip
-// Parameters p[i], g[i] (i < n) are parameters first + i of the whole
-// vector; m, v are the whole vector's moment arrays (o->moments layout).
+// Adam over the parameters [first, first + n) of a vector: p, g, m, v and
+// shadow point at the vector's start (o->moments layout).
 hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
                        void* shadow, fhash_dtype sdt, int64_t n, int64_t first,
                        const int32_t* found_inf, const fhash_touch* touch, hipStream_t st);

@@ -134,14 +134,15 @@ struct Lane {
 // Loads.  stale: done < upto.  A segment never stepped (done == 0, nothing
 // pending) holds m = v = 0 and needs no loads.  begin is a multiple of 16 and
 // end of 4, so a lane's four floats are all inside the range or all outside.
+// Parameter / gradient float a sits at p / g + run_off(a, pm).
 template <bool PAIRED>
 __device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t pend,
                                            uint32_t stamp, bool stale, int sub,
                                            const float* __restrict__ p,
                                            const float* __restrict__ g,
                                            const float* __restrict__ m,
-                                           const float* __restrict__ v, int64_t begin,
-                                           int64_t end) {
+                                           const float* __restrict__ v, int64_t pm,
+                                           int64_t begin, int64_t end) {
   Lane L;
   L.seg = seg;
   L.done = done;
@@ -153,10 +154,10 @@ __device__ __forceinline__ Lane load_lanes(uint32_t seg, uint32_t done, uint32_t
   const f4v z = {0.f, 0.f, 0.f, 0.f};
   L.p = L.m = L.v = L.g = z;
   if (L.work) {
-    L.p = *reinterpret_cast<const f4v*>(p + L.f);
+    L.p = *reinterpret_cast<const f4v*>(p + run_off(L.f, pm));
     L.m = *reinterpret_cast<const f4v*>(m + moment_off<PAIRED>(L.f));
     L.v = *reinterpret_cast<const f4v*>(v + moment_off<PAIRED>(L.f));
-    if (pend != 0) L.g = *reinterpret_cast<const f4v*>(g + L.f);
+    if (pend != 0) L.g = *reinterpret_cast<const f4v*>(g + run_off(L.f, pm));
   }
   return L;
 }
@@ -188,17 +189,18 @@ template <bool ODD, bool PAIRED>
 __device__ __forceinline__ bool finish_lanes(Lane L, const float4* rec, const AdamK& base,
                                              float* __restrict__ p, float* __restrict__ g,
                                              float* __restrict__ m, float* __restrict__ v,
-                                             void* __restrict__ shadow, int sdt, uint32_t upto) {
+                                             int64_t pm, void* __restrict__ shadow, int sdt,
+                                             uint32_t upto) {
   const bool active = L.work && (L.pend != 0 || nonzero_state(L.m, L.v));
   replay<ODD>(rec, base, active, L.done, L.pend, upto, L.g, L.p, L.m, L.v);
   if (active) {
-    *reinterpret_cast<f4v*>(p + L.f) = L.p;
+    *reinterpret_cast<f4v*>(p + run_off(L.f, pm)) = L.p;
     *reinterpret_cast<f4v*>(m + moment_off<PAIRED>(L.f)) = L.m;
     *reinterpret_cast<f4v*>(v + moment_off<PAIRED>(L.f)) = L.v;
     if (shadow != nullptr) store_shadow_group(shadow, sdt, L.f, L.p);
   }
   if (L.work && L.pend != 0 && (L.g[0] != 0.f || L.g[1] != 0.f || L.g[2] != 0.f || L.g[3] != 0.f))
-    *reinterpret_cast<f4v*>(g + L.f) = (f4v){0.f, 0.f, 0.f, 0.f};
+    *reinterpret_cast<f4v*>(g + run_off(L.f, pm)) = (f4v){0.f, 0.f, 0.f, 0.f};
   return active;
 }
 
@@ -271,8 +273,9 @@ __global__ void __launch_bounds__(256)
     lazy_catchup_kernel(uint8_t* __restrict__ flags, int64_t nseg, unsigned long long* ctr,
                         uint2* __restrict__ state, const float4* __restrict__ rec, AdamK base,
                         float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
-                        float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t begin,
-                        int64_t end, uint32_t upto, uint32_t target, int group, int min_flush) {
+                        float* __restrict__ v, int64_t pm, void* __restrict__ shadow, int sdt,
+                        int64_t begin, int64_t end, uint32_t upto, uint32_t target, int group,
+                        int min_flush) {
   // flagged segments not yet caught up: fewer than kChunk carried over plus
   // at most one tile's worth
   __shared__ uint32_t ids[kTile + kChunk];
@@ -373,13 +376,13 @@ __global__ void __launch_bounds__(256)
         const int e = r0 + (int)(threadIdx.x / kLanesPerSeg);
         const uint4 en = e < nloc ? srt[e] : make_uint4(0u, upto, 0u, 0u);
         return load_lanes<PAIRED>(en.x, en.y, en.z, en.w, e < nloc && en.y < upto, sub, p, g, m,
-                                  v, begin, end);
+                                  v, pm, begin, end);
       };
       Lane cur = fetch(0);
       for (int r0 = 0; r0 < nloc; r0 += 256 / kLanesPerSeg) {
         const Lane nxt = fetch(r0 + 256 / kLanesPerSeg);
         const bool active =
-            finish_lanes<ODD, PAIRED>(cur, rec, base, p, g, m, v, shadow, sdt, upto);
+            finish_lanes<ODD, PAIRED>(cur, rec, base, p, g, m, v, pm, shadow, sdt, upto);
         if (sub == 0 && cur.stamp != 0u)
           state[cur.seg] = make_uint2(cur.stale ? upto : cur.done, cur.stamp);
         if (cur.stale && sub == 0) {
@@ -520,12 +523,12 @@ void launch_catch_up(const fhash_lazy* lz, const LazyWs& w, uint32_t target, int
   int64_t blocks = (ntiles + group - 1) / group;
   if (blocks > kCatchUpBlocks) blocks = kCatchUpBlocks;
   const bool odd = (lz->flags & 1) != 0;
-  auto kern = odd ? (lz->moments == FHASH_MOMENTS_PAIRED ? lazy_catchup_kernel<true, true>
-                                                         : lazy_catchup_kernel<true, false>)
-                  : (lz->moments == FHASH_MOMENTS_PAIRED ? lazy_catchup_kernel<false, true>
-                                                         : lazy_catchup_kernel<false, false>);
+  const bool runs = lz->moments != FHASH_MOMENTS_SEPARATE;  // m, v in runs of 16
+  auto kern = odd ? (runs ? lazy_catchup_kernel<true, true> : lazy_catchup_kernel<true, false>)
+                  : (runs ? lazy_catchup_kernel<false, true> : lazy_catchup_kernel<false, false>);
+  const int64_t pm = lz->moments == FHASH_MOMENTS_WITH_PARAMS ? ~(int64_t)15 : 0;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, w.flags, nseg, w.ctr,
-                     w.state, w.rec, lazy_base(lz), p, gr, m, v, shadow, (int)sdt, lz->begin,
+                     w.state, w.rec, lazy_base(lz), p, gr, m, v, pm, shadow, (int)sdt, lz->begin,
                      lz->end, (uint32_t)lz->steps, target, (int)group, kChunk / 2);
 }
 

@@ -42,41 +42,45 @@ __device__ __forceinline__ void store_shadow4(void* shadow, int sdt, int64_t i, 
 // Streaming sweep: every array is touched once, so loads and stores bypass the
 // caches' retention (non-temporal) and each thread keeps two float4 groups in
 // flight.  The gradient is reset only where it is nonzero.
-// Gradient read of float4 group i under touched-segment tracking: a group that
-// lies inside [tb, te) is read only when its segment is flagged (otherwise the
-// gradient is zero there); a group that opens a segment in the range clears
-// its flag after the read.  The 4 groups of a segment are 4 consecutive lanes
-// of one wave, so all of them have read the flag before the clearing store.
-__device__ __forceinline__ void tracked_load(const f4v* __restrict__ g4, int64_t i,
+// Gradient read of the float4 group at logical index f (a multiple of 4)
+// under touched-segment tracking: a group that lies inside [tb, te) is read
+// only when its segment is flagged (otherwise the gradient is zero there); a
+// group that opens a segment in the range clears its flag after the read.
+// The 4 groups of a segment are 4 consecutive lanes of one wave, so all of
+// them have read the flag before the clearing store.
+__device__ __forceinline__ void tracked_load(const float* __restrict__ g, int64_t f, int64_t pm,
                                              uint8_t* __restrict__ touch, int64_t tb, int64_t te,
                                              f4v& out) {
-  const int64_t f = i << 2;
+  const f4v* g4 = reinterpret_cast<const f4v*>(g + run_off(f, pm));
   if (touch == nullptr || f < tb || f >= te) {
-    out = __builtin_nontemporal_load(g4 + i);
+    out = __builtin_nontemporal_load(g4);
     return;
   }
   const int64_t seg = f / FHASH_TOUCH_FLOATS;
   if (f + 4 <= te && touch[seg] == 0) {
     out = (f4v){0.0f, 0.0f, 0.0f, 0.0f};
   } else {
-    out = __builtin_nontemporal_load(g4 + i);
+    out = __builtin_nontemporal_load(g4);
   }
   if ((f % FHASH_TOUCH_FLOATS) == 0) touch[seg] = 0;
 }
 
-// Parameter i of p, g is parameter first + i of the whole vector, whose
-// moments sit at m / v + moment_off<PAIRED>(first + i) (first: a multiple of 4).
+// The parameters [first, first + n) of the vector (first: a multiple of 4).
+// p, g, m, v and shadow point at the vector's start; parameter a sits at
+// p / g + run_off(a, pm) (pm = ~15: parameters and gradients in runs of 16,
+// interleaved with m and v), at m / v + moment_off<PAIRED>(a) and at
+// shadow[a].
 template <bool PAIRED>
 __global__ void __launch_bounds__(256)
     adam_kernel(AdamK k, float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                 float* __restrict__ v, void* __restrict__ shadow, int sdt, int64_t n,
-                int64_t first, const int32_t* __restrict__ found_inf,
+                int64_t first, int64_t pm, const int32_t* __restrict__ found_inf,
                 uint8_t* __restrict__ touch, int64_t tb, int64_t te) {
   const bool skip = (found_inf != nullptr) && (*found_inf != 0);
   const int64_t n4 = n >> 2;
   const int64_t S = (int64_t)gridDim.x * blockDim.x;
-  f4v* p4 = reinterpret_cast<f4v*>(p);
-  f4v* g4 = reinterpret_cast<f4v*>(g);
+  auto p4 = [&](int64_t i) { return reinterpret_cast<f4v*>(p + run_off(first + 4 * i, pm)); };
+  auto g4 = [&](int64_t i) { return reinterpret_cast<f4v*>(g + run_off(first + 4 * i, pm)); };
   auto m4 = [&](int64_t i) { return reinterpret_cast<f4v*>(m + moment_off<PAIRED>(first + 4 * i)); };
   auto v4 = [&](int64_t i) { return reinterpret_cast<f4v*>(v + moment_off<PAIRED>(first + 4 * i)); };
   const f4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -84,49 +88,50 @@ __global__ void __launch_bounds__(256)
     const int64_t j = i + S;
     const bool two = j < n4;
     f4v g0, g1 = zero;
-    tracked_load(g4, i, touch, tb, te, g0);
-    if (two) tracked_load(g4, j, touch, tb, te, g1);
+    tracked_load(g, first + 4 * i, pm, touch, tb, te, g0);
+    if (two) tracked_load(g, first + 4 * j, pm, touch, tb, te, g1);
     if (!skip) {
-      f4v p0 = __builtin_nontemporal_load(p4 + i), m0 = __builtin_nontemporal_load(m4(i));
+      f4v p0 = __builtin_nontemporal_load(p4(i)), m0 = __builtin_nontemporal_load(m4(i));
       f4v v0 = __builtin_nontemporal_load(v4(i));
       f4v p1 = zero, m1 = zero, v1 = zero;
       if (two) {
-        p1 = __builtin_nontemporal_load(p4 + j);
+        p1 = __builtin_nontemporal_load(p4(j));
         m1 = __builtin_nontemporal_load(m4(j));
         v1 = __builtin_nontemporal_load(v4(j));
       }
       adam4(k, g0, p0, m0, v0);
-      __builtin_nontemporal_store(p0, p4 + i);
+      __builtin_nontemporal_store(p0, p4(i));
       __builtin_nontemporal_store(m0, m4(i));
       __builtin_nontemporal_store(v0, v4(i));
-      if (shadow != nullptr) store_shadow4(shadow, sdt, i, p0);
+      if (shadow != nullptr) store_shadow4(shadow, sdt, first / 4 + i, p0);
       if (two) {
         adam4(k, g1, p1, m1, v1);
-        __builtin_nontemporal_store(p1, p4 + j);
+        __builtin_nontemporal_store(p1, p4(j));
         __builtin_nontemporal_store(m1, m4(j));
         __builtin_nontemporal_store(v1, v4(j));
-        if (shadow != nullptr) store_shadow4(shadow, sdt, j, p1);
+        if (shadow != nullptr) store_shadow4(shadow, sdt, first / 4 + j, p1);
       }
     }
     if (g0[0] != 0.0f || g0[1] != 0.0f || g0[2] != 0.0f || g0[3] != 0.0f)
-      __builtin_nontemporal_store(zero, g4 + i);
+      __builtin_nontemporal_store(zero, g4(i));
     if (two && (g1[0] != 0.0f || g1[1] != 0.0f || g1[2] != 0.0f || g1[3] != 0.0f))
-      __builtin_nontemporal_store(zero, g4 + j);
+      __builtin_nontemporal_store(zero, g4(j));
   }
   // Tail (n not a multiple of 4).
   const int64_t t = (n4 << 2) + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < n && t < (n4 << 2) + 4) {
-    const float gg = g[t];
+    const int64_t a = first + t, po = run_off(a, pm);
+    const float gg = g[po];
     if (!skip) {
-      const int64_t mo = moment_off<PAIRED>(first + t);
-      float pp = p[t], mm = m[mo], vv = v[mo];
+      const int64_t mo = moment_off<PAIRED>(a);
+      float pp = p[po], mm = m[mo], vv = v[mo];
       adam1(k, gg, pp, mm, vv);
-      p[t] = pp;
+      p[po] = pp;
       m[mo] = mm;
       v[mo] = vv;
-      if (shadow != nullptr) store_shadow(shadow, sdt, t, pp);
+      if (shadow != nullptr) store_shadow(shadow, sdt, a, pp);
     }
-    if (gg != 0.0f) g[t] = 0.0f;
+    if (gg != 0.0f) g[po] = 0.0f;
   }
 }
 
@@ -237,12 +242,14 @@ hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, f
   if (b < 1) b = 1;
   uint8_t* tf = touch ? touch->flags : nullptr;
   const int64_t tb = touch ? touch->begin : 0, te = touch ? touch->end : 0;
-  if (o->moments == FHASH_MOMENTS_PAIRED)
+  // moments with parameters: p, g (and m, v) in runs of 16; paired: m, v only
+  const int64_t pm = o->moments == FHASH_MOMENTS_WITH_PARAMS ? ~(int64_t)15 : 0;
+  if (o->moments != FHASH_MOMENTS_SEPARATE)
     hipLaunchKernelGGL(adam_kernel<true>, dim3((unsigned)b), dim3(256), 0, st, k, p, g, m, v,
-                       shadow, (int)sdt, n, first, found_inf, tf, tb, te);
+                       shadow, (int)sdt, n, first, pm, found_inf, tf, tb, te);
   else
     hipLaunchKernelGGL(adam_kernel<false>, dim3((unsigned)b), dim3(256), 0, st, k, p, g, m, v,
-                       shadow, (int)sdt, n, first, found_inf, tf, tb, te);
+                       shadow, (int)sdt, n, first, pm, found_inf, tf, tb, te);
   return hipGetLastError();
 }
 

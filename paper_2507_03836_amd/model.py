@@ -79,7 +79,7 @@ class FHashModel:
                  init_seed: int = 3000, precision: str = "fp32", loss_scale: float = 2.0 ** 16,
                  scale_window: int = 2000, track_touched: bool = True, lazy: bool = False,
                  max_steps: int = 1 << 16, hash_bits: int = 0, decoder: str | None = None,
-                 paired_moments: bool = False):
+                 paired_moments: bool = False, moments_with_params: bool = False):
         if precision not in ("fp32", "mixed"):
             raise ValueError(f"precision must be 'fp32' or 'mixed', not {precision!r}")
         if decoder is None:
@@ -108,24 +108,48 @@ class FHashModel:
         self.n_params = self.mlp_off + self.n_mlp
         n_alloc = (self.n_params + 3) // 4 * 4
         f32 = dict(dtype=torch.float32, device=self.device)
-        self.params = torch.zeros(n_alloc, **f32)
-        self.grads = torch.zeros(n_alloc, **f32)
-        # Adam moments: separate arrays, or paired (blocks of 16 m then the same
-        # parameters' 16 v: one 128-byte line per segment for the deferred update);
-        # m and v are then the pointers into the pair array the library expects
         self.paired = bool(paired_moments)
-        if self.paired:
-            self.mv = torch.zeros((n_alloc + 15) // 16 * 32, **f32)
-            self.m, self.v = self.mv, self.mv[16:]
+        self.moments_with_params = bool(moments_with_params)
+        # the vector Adam sees as one: every parameter, or with the moments
+        # stored beside the parameters the table part only (the decoder then
+        # has arrays of its own and a second, dense update)
+        n_vec = (self.mlp_off + 15) // 16 * 16 if self.moments_with_params else n_alloc
+        self.n_vec = n_vec
+        self.pm = self.gv = self.mv = None
+        if self.moments_with_params:
+            # runs of 16 table parameters, each followed by their 16 m values,
+            # and runs of their 16 gradients, each followed by their 16 v
+            # values: a segment's optimiser state is two 128-byte lines, and
+            # the lines the forward gathers from take none of the atomics
+            self.pm = torch.zeros(2 * n_vec, **f32)
+            self.gv = torch.zeros(2 * n_vec, **f32)
+            self.m, self.v = self.pm[16:], self.gv[16:]
+            self.params = self.grads = None
+            n_mlp4 = (self.n_mlp + 3) // 4 * 4
+            self.mlp_p = torch.zeros(n_mlp4, **f32)
+            self.mlp_g = torch.zeros(n_mlp4, **f32)
+            self.mlp_m = torch.zeros(n_mlp4, **f32)
+            self.mlp_v = torch.zeros(n_mlp4, **f32)
         else:
-            self.m = torch.zeros(n_alloc, **f32)
-            self.v = torch.zeros(n_alloc, **f32)
+            self.params = torch.zeros(n_alloc, **f32)
+            self.grads = torch.zeros(n_alloc, **f32)
+            # Adam moments: separate arrays, or paired (blocks of 16 m then the
+            # same parameters' 16 v: one 128-byte line per segment for the
+            # deferred update); m and v then point into the pair array
+            if self.paired:
+                self.mv = torch.zeros((n_vec + 15) // 16 * 32, **f32)
+                self.m, self.v = self.mv, self.mv[16:]
+            else:
+                self.m = torch.zeros(n_vec, **f32)
+                self.v = torch.zeros(n_vec, **f32)
         if table_init is not None:
-            self.table.copy_(table_init.reshape(-1))
+            table0 = table_init.reshape(-1).to(**f32)
         else:
             g = torch.Generator(device=self.device)
             g.manual_seed(init_seed)
-            self.table.uniform_(-1e-4, 1e-4, generator=g)
+            table0 = torch.empty(self.n_table, **f32).uniform_(-1e-4, 1e-4, generator=g)
+        self._set_table(table0)
+        del table0
         if mlp_init is not None:
             self.mlp_params.copy_(mlp_init.reshape(-1))
         else:
@@ -160,46 +184,111 @@ class FHashModel:
                                             dtype=torch.uint8, device=self.device)
             self.touch = fl.touch_desc(self._touch_flags, begin, self.n_table)
         if precision == "mixed":
-            self.shadow = torch.empty(n_alloc, dtype=torch.float16, device=self.device)
-            fl.fhash_cast(self.params, self.shadow)
+            self.shadow = torch.zeros(n_vec, dtype=torch.float16, device=self.device)
+            if self.moments_with_params:
+                fl.fhash_cast(self.table, self.shadow[: self.n_table])
+            else:
+                fl.fhash_cast(self.params, self.shadow)
             self.found_inf = torch.zeros(1, dtype=torch.int32, device=self.device)
             self.loss_scale = float(loss_scale)
             self.scale_window = int(scale_window)
             self._clean = 0
             self.skipped = 0
 
-    # views into the flat vectors
-    @property
-    def table(self) -> torch.Tensor:
-        return self.params[: self.n_table]
+    # views into the flat vectors (copies of the table part when the moments
+    # are stored beside the parameters)
+    @staticmethod
+    def _runs(a: torch.Tensor, k: int) -> torch.Tensor:
+        """The values of an array of 32-float blocks: first (k = 0) or second
+        (k = 1) 16 of every block, as one flat copy."""
+        return a.view(-1, 2, 16)[:, k].reshape(-1)
 
     @property
-    def read_table(self) -> torch.Tensor:
-        """The table the fused kernels read: the FP16 shadow or the FP32 master."""
-        return self.shadow[: self.n_table] if self.shadow is not None else self.table
+    def table(self) -> torch.Tensor:
+        if self.moments_with_params:
+            return self._runs(self.pm, 0)[: self.n_table]
+        return self.params[: self.n_table]
+
+    def _set_table(self, t: torch.Tensor):
+        if self.moments_with_params:
+            full = torch.zeros(self.n_vec, dtype=torch.float32, device=self.device)
+            full[: self.n_table] = t
+            self.pm.view(-1, 2, 16)[:, 0] = full.view(-1, 16)
+        else:
+            self.params[: self.n_table] = t
+
+    @property
+    def read_table(self):
+        """The table the fused kernels read: the FP16 shadow or the FP32 master
+        (fl.Paired when the moments are stored beside the parameters)."""
+        if self.shadow is not None:
+            return self.shadow[: self.n_table]
+        return fl.Paired(self.pm) if self.moments_with_params else self.table
 
     @property
     def mlp_params(self) -> torch.Tensor:
+        if self.moments_with_params:
+            return self.mlp_p[: self.n_mlp]
         return self.params[self.mlp_off: self.mlp_off + self.n_mlp]
 
     @property
     def d_table(self) -> torch.Tensor:
+        if self.moments_with_params:
+            return self._runs(self.gv, 0)[: self.n_table]
         return self.grads[: self.n_table]
 
     @property
     def d_mlp(self) -> torch.Tensor:
+        if self.moments_with_params:
+            return self.mlp_g[: self.n_mlp]
         return self.grads[self.mlp_off: self.mlp_off + self.n_mlp]
 
+    def _grad_args(self):
+        """(d_table pointer tensor, extra fused flags) of the table gradient."""
+        if self.moments_with_params:
+            return self.gv, fl.GRAD_PAIRED
+        return self.d_table, 0
+
+    def flat_params(self) -> torch.Tensor:
+        """Every parameter as one flat vector [table | pad | decoder] (a copy in
+        the paired parameter layout)."""
+        if not self.moments_with_params:
+            return self.params[: self.n_params]
+        out = torch.zeros(self.n_params, dtype=torch.float32, device=self.device)
+        out[: self.n_table] = self.table
+        out[self.mlp_off:] = self.mlp_params
+        return out
+
+    def flat_grads(self) -> torch.Tensor:
+        if not self.moments_with_params:
+            return self.grads[: self.n_params]
+        out = torch.zeros(self.n_params, dtype=torch.float32, device=self.device)
+        out[: self.n_table] = self.d_table
+        out[self.mlp_off:] = self.d_mlp
+        return out
+
     def _moments_layout(self) -> int:
+        if self.moments_with_params:
+            return fl.MOMENTS_WITH_PARAMS
         return fl.MOMENTS_PAIRED if self.paired else fl.MOMENTS_SEPARATE
 
     def moments(self):
-        """(m, v) of the parameters as flat arrays (copies in the paired layout)."""
+        """(m, v) of the parameters as flat arrays (copies in the layouts with
+        runs)."""
         n = self.n_params
-        if not self.paired:
-            return self.m[:n], self.v[:n]
-        mv = self.mv.view(-1, 2, 16)
-        return mv[:, 0].reshape(-1)[:n], mv[:, 1].reshape(-1)[:n]
+        if self.moments_with_params:
+            m, v = self._runs(self.pm, 1), self._runs(self.gv, 1)
+        elif self.paired:
+            m, v = self._runs(self.mv, 0), self._runs(self.mv, 1)
+        else:
+            m, v = self.m, self.v
+        if not self.moments_with_params:
+            return m[:n], v[:n]
+        mm = torch.zeros(n, dtype=torch.float32, device=self.device)
+        vv = torch.zeros_like(mm)
+        mm[: self.mlp_off], vv[: self.mlp_off] = m[: self.mlp_off], v[: self.mlp_off]
+        mm[self.mlp_off:], vv[self.mlp_off:] = self.mlp_m[: self.n_mlp], self.mlp_v[: self.n_mlp]
+        return mm, vv
 
     def adam_desc(self, step: int, grad_scale: float = 1.0) -> fl.AdamDesc:
         c = self.cfg
@@ -210,19 +299,26 @@ class FHashModel:
         o.moments = self._moments_layout()
         return o
 
+    def _pg(self):
+        """(param, grad) arguments of the table vector for the optimiser calls."""
+        if self.moments_with_params:
+            return self.pm, self.gv
+        return self.params, self.grads
+
     def prepare(self, pos: torch.Tensor, phases: int = fl.LAZY_PREPARE):
         """Under deferred Adam: bring the table rows that pos reads up to date
         (and enrol them in the next step)."""
         if self.lazy is not None:
-            fl.fhash_lazy_prepare(self.index, pos, pos.shape[0], self.lazy, self.params,
-                                  self.grads, self.m, self.v, shadow=self.shadow, phases=phases)
+            p, g = self._pg()
+            fl.fhash_lazy_prepare(self.index, pos, pos.shape[0], self.lazy, p, g, self.m, self.v,
+                                  shadow=self.shadow, phases=phases)
 
     def flush(self):
         """Under deferred Adam: bring every parameter up to date and apply the
         pending gradients (before the whole table is read: rendering, export)."""
         if self.lazy is not None:
-            fl.fhash_lazy_flush(self.lazy, self.params, self.grads, self.m, self.v,
-                                shadow=self.shadow)
+            p, g = self._pg()
+            fl.fhash_lazy_flush(self.lazy, p, g, self.m, self.v, shadow=self.shadow)
 
     def forward(self, pos: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
         n = pos.shape[0]
@@ -241,10 +337,11 @@ class FHashModel:
         s = self.loss_scale if loss_scale is None else loss_scale
         if not prepared:
             self.prepare(pos)
+        d_table, gflag = self._grad_args()
         self._ws = fl.fhash_fused_train(self.index, self.mlp, pos, target, n, self.read_table,
-                                        self.mlp_params, self.d_table, self.d_mlp,
+                                        self.mlp_params, d_table, self.d_mlp,
                                         self.loss_sum, s, ws=self._ws,
-                                        flags=fl.SAMPLES_SORTED if sorted_batch else 0,
+                                        flags=(fl.SAMPLES_SORTED if sorted_batch else 0) | gflag,
                                         touch=self.touch)
 
     def optimizer_step(self, grad_scale: float | None = None, found_inf=None) -> bool:
@@ -260,7 +357,7 @@ class FHashModel:
         self.found_inf.zero_()
         fl.fhash_check_finite(self.d_mlp, self.found_inf)
         opt = self.adam_desc(self.step_count + 1, 1.0 / self.loss_scale)
-        self._step(opt, self.shadow[: self.n_params], self.found_inf)
+        self._step(opt, self.shadow, self.found_inf)
         if int(self.found_inf.item()):
             self.loss_scale *= 0.5
             self._clean = 0
@@ -274,12 +371,19 @@ class FHashModel:
         return True
 
     def _step(self, opt, shadow, found_inf):
-        args = (opt, self.params[: self.n_params], self.grads[: self.n_params],
-                self.m[: self.n_params], self.v[: self.n_params])
+        p, g = self._pg()
+        n = self.n_vec if self.moments_with_params else self.n_params
+        args = (opt, p, g, self.m, self.v)
         if self.lazy is not None:
-            fl.fhash_step_lazy(*args, self.lazy, shadow=shadow, found_inf=found_inf)
+            fl.fhash_step_lazy(*args, self.lazy, shadow=shadow, found_inf=found_inf, n=n)
         else:
-            fl.fhash_step(*args, shadow=shadow, found_inf=found_inf, touch=self.touch)
+            fl.fhash_step(*args, shadow=shadow, found_inf=found_inf, touch=self.touch, n=n)
+        if self.moments_with_params:
+            # the decoder: its own dense arrays, same step constants
+            om = self.adam_desc(opt.step, opt.grad_scale)
+            om.moments = fl.MOMENTS_SEPARATE
+            fl.fhash_step(om, self.mlp_p, self.mlp_g, self.mlp_m, self.mlp_v,
+                          found_inf=found_inf, n=self.n_mlp)
 
     def train_step(self, pos: torch.Tensor, target: torch.Tensor):
         self.fwd_bwd(pos, target)

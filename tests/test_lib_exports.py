@@ -168,3 +168,34 @@ def test_moment_layouts_checked_before_any_launch():
     lz.moments = 7
     assert L.fhash_lazy_flush(ctypes.byref(lz), p, g, m, ctypes.c_void_p(base + 8192 + 64),
                               None, fl.F16, None) == fl.EINVAL
+
+
+def test_moments_with_params_checked_before_any_launch():
+    """With the moments stored beside the parameters, fhash_step and the
+    deferred calls refuse an m that does not start 16 floats after param or a
+    v that does not start 16 floats after grad (host checks, no device)."""
+    L = fl.lib()
+    o = fl.AdamDesc()
+    o.lr, o.beta1, o.beta2, o.eps, o.step, o.grad_scale = 0.01, 0.9, 0.999, 1e-8, 1, 1.0
+    o.moments = fl.MOMENTS_WITH_PARAMS
+    base = 1 << 20   # never dereferenced: every call below fails its checks
+    p, g = ctypes.c_void_p(base), ctypes.c_void_p(base + 8192)
+    ok_m, ok_v = ctypes.c_void_p(base + 64), ctypes.c_void_p(base + 8192 + 64)
+    bad_m, bad_v = ctypes.c_void_p(base + 128), ctypes.c_void_p(base + 8192 + 128)
+    for m, v in ((bad_m, ok_v), (ok_m, bad_v)):
+        assert L.fhash_step(ctypes.byref(o), p, g, m, v, None, fl.F16, 64, None, None,
+                            None) == fl.EINVAL
+        assert b"16 floats after" in L.fhash_last_error()
+    lz = fl.Lazy()
+    lz.ws, lz.begin, lz.end, lz.max_steps, lz.steps = base, 0, 64, 8, 0
+    lz.beta1 = lz.beta2 = lz.eps = -1.0
+    lz.moments = fl.MOMENTS_WITH_PARAMS
+    assert L.fhash_lazy_flush(ctypes.byref(lz), p, g, bad_m, ok_v, None, fl.F16,
+                              None) == fl.EINVAL
+    lz.moments = fl.MOMENTS_PAIRED  # the step's layout differs from the deferred state's
+    rc = L.fhash_step_lazy(ctypes.byref(o), p, g, ok_m, ok_v, None, fl.F16, 64, None,
+                           ctypes.byref(lz), None)
+    assert rc == fl.EINVAL and b"layout differs" in L.fhash_last_error()
+    lz.moments = 3
+    assert L.fhash_lazy_flush(ctypes.byref(lz), p, g, ok_m, ok_v, None, fl.F16,
+                              None) == fl.EINVAL
