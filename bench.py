@@ -61,12 +61,14 @@ ADAM_TRAFFIC = {"bytes": 156.90e9, "params": 6390343593,
 # (6 x 64 B); a pending gradient is read and reset (2 x 64 B); the FP16 shadow adds 32 B
 # written.
 LAZY_ENTRY_BYTES, LAZY_LOADED_BYTES, LAZY_PENDING_BYTES, LAZY_SHADOW_BYTES = 16, 384, 128, 32
-# HBM bytes of one lazy_catchup_kernel launch at the default workload and step count (FP32),
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (copy-calibrated, per launch, averaged
-# over the timed steps); valid only for the sources, parameter count, batch and step count
-# they were taken on.
-CATCHUP_TRAFFIC = {"bytes": 12.98e9, "params": 6390343593, "batch": 1 << 18, "steps": 200,
-                   "source_md5": "05dcf65c0c53af2e83bb86cbf74a280c"}
+# HBM bytes of one lazy_catchup_kernel launch of the training workload (480x720x120x100,
+# FP32, 200 timed steps), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes
+# (copy-calibrated, per launch, averaged over the timed steps); valid only for the
+# sources, optimiser state layout, parameter count, batch and step count they were
+# taken on.
+CATCHUP_TRAFFIC = {"bytes": 9.084e9, "raw_bytes": 6.465e9, "params": 6390343593,
+                   "batch": 1 << 18, "steps": 200, "moments": "with-params",
+                   "source_md5": "145a20f791997ecfa75f13f2c942dc4f"}
 
 # HBM bytes of one feature-extraction launch on the 480x720x120x100 volume from the two
 # counter passes (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the copy-calibrated factors);
@@ -824,12 +826,17 @@ LAYOUTS = {"rows": 0, "bricks": 1}
 
 # ------------------------------------------------------------------ headline
 HEADLINE_DIMS = [432, 432, 432, 60]
+# Memory-side atomic requests per second of the chip on a footprint far beyond
+# the caches (random 16-byte float-atomic groups over 24 GiB, the probe
+# paper_2507_03836_amd/probe/random_access): the bound of the scatter-add.
+ATOMIC_CEILING_GPS = 16.8
 # HBM bytes of one fused training launch (mixed path, 432^3 x 60, batch 2^20)
 # from rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) passes scaled by a
 # plain streaming copy of known size; valid only while the kernel sources
-# hashed in _fused_src_md5() are unchanged.
-FUSED_TRAFFIC = {"bytes": 33189752859, "raw_bytes": 19289133261,
-                 "source_md5": "efa336ecfc1c3c729171b9c24463e31a"}
+# hashed in _fused_src_md5() and the optimiser state layout are those the
+# counters were taken with.
+FUSED_TRAFFIC = {"bytes": 33218403961, "raw_bytes": 19302885069, "moments": "with-params",
+                 "source_md5": "e5a321605487a5434ed4f9f1f3a82091"}
 
 
 def _fused_src_md5():
@@ -1015,35 +1022,41 @@ def compulsory_lines(model, pos, line=128):
     the fused training kernel must move for this batch (the corners of every
     sample at every level, fhash_corner_rows), in bytes: directory and table
     lines are read once, gradient lines read and written once; plus 20 bytes
-    of sample I/O per sample.  In the paired parameter layout a 16-float
-    segment's parameters and gradient fill one 128-byte line: the FP32 path's
-    table lines are its gradient lines (read once, written once)."""
+    of sample I/O per sample.  With the moments stored beside the parameters,
+    a 16-float segment's parameters (FP32 path) and its gradient each take a
+    128-byte line of their own (the other half holds m or v): 8 bytes of line
+    address per value."""
     from paper_2507_03836_amd import _lib as fl
     n = pos.shape[0]
     F = model.cfg.n_features
-    tb = 2 if model.shadow is not None else 4
-    paired = getattr(model, "moments_with_params", False)
-    gb = 8 if paired else 4  # bytes of a gradient float's line share
-    shared = paired and model.shadow is None
+    runs = getattr(model, "moments_with_params", False)
+    tb = 2 if model.shadow is not None else (8 if runs else 4)
+    gb = 8 if runs else 4
     dir_lines, tab_lines, grad_lines = [], [], []
+    requests = 0
     for s in range(0, n, 1 << 16):
         e = min(n, s + (1 << 16))
         d, sl = fl.fhash_corner_rows(model.index, pos[s:e], e - s)
         d = d.view(-1)
         d = d[d >= 0]
         dir_lines.append(torch.unique(d * 16 // line))
+        # the scatter-add's atomic requests: one per corner pair, two when its
+        # rows fall in different 64-byte chunks (16 gradient floats, in either
+        # layout) of the gradient
+        sp = sl.view(-1, 2)
+        v0, v1 = sp[:, 0] >= 0, sp[:, 1] >= 0
+        c0, c1 = sp[:, 0] * F // 16, sp[:, 1] * F // 16
+        requests += int((v0 | v1).sum()) + int((v0 & v1 & (c0 != c1)).sum())
+        del sp, v0, v1, c0, c1
         sl = sl.view(-1)
         sl = sl[sl >= 0]
-        if not shared:
-            tab_lines.append(torch.unique(sl * (F * tb) // line))
+        tab_lines.append(torch.unique(sl * (F * tb) // line))
         grad_lines.append(torch.unique(sl * (F * gb) // line))
         del d, sl
     u = lambda xs: int(torch.unique(torch.cat(xs)).numel())
-    nd, ng = u(dir_lines), u(grad_lines)
-    nt = ng if shared else u(tab_lines)
+    nd, nt, ng = u(dir_lines), u(tab_lines), u(grad_lines)
     return {"line_bytes": line, "directory_lines": nd, "table_lines": nt, "gradient_lines": ng,
-            "table_lines_are_gradient_lines": shared,
-            "bytes": line * (nd + (0 if shared else nt) + 2 * ng) + 20 * n}
+            "bytes": line * (nd + nt + 2 * ng) + 20 * n, "atomic_requests": requests}
 
 
 def _serve_sub(model, gen, dims, args, n_req):
@@ -1205,7 +1218,9 @@ def headline_bench(args):
     fused_ms = mx["breakdown_ms"]["fused_fwd_bwd"]
     alg = 3092 * B  # FP16 gather 1024 + FP32 scatter read-modify-write 2048 + 20 B I/O
     comp = mx["compulsory"]["bytes"]
-    same = FUSED_TRAFFIC["source_md5"] == _fused_src_md5()
+    areq = mx["compulsory"]["atomic_requests"]
+    same = (FUSED_TRAFFIC["source_md5"] == _fused_src_md5() and
+            args.moments == FUSED_TRAFFIC["moments"])
     roof = {"kernel": "fused_kernel<TRAIN, F=2, FP16 table, 32-64-64-64-1, BF16 decoder>",
             "bound": "hbm", "achieved": alg / (fused_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": alg / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -1214,7 +1229,11 @@ def headline_bench(args):
             "compulsory_bytes": comp,
             "compulsory_GB_s": comp / (fused_ms * 1e-3) / 1e9,
             "compulsory_frac": comp / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "compulsory_detail": mx["compulsory"]}
+            "compulsory_detail": mx["compulsory"],
+            # what bounds the kernel: the scatter's memory-side atomic requests
+            "atomic_requests": areq, "atomic_G_per_s": areq / (fused_ms * 1e-3) / 1e9,
+            "atomic_ceiling_G_per_s": ATOMIC_CEILING_GPS,
+            "atomic_frac": areq / (fused_ms * 1e-3) / 1e9 / ATOMIC_CEILING_GPS}
     ttp_m, ttp_f = mx["time_to_psnr"], fp["time_to_psnr"]
     out = {
         "metric": "train samples/s fwd+bwd (FP32 vs FP16/BF16) at equal PSNR; render p50/p99 ms",
@@ -1390,6 +1409,7 @@ def main():
                 for f in ("lazy.hip", "adam_dev.h")]
         md5 = hashlib.md5(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
         same = (md5 == CATCHUP_TRAFFIC["source_md5"] and not mixed and not args.sort and
+                args.moments == CATCHUP_TRAFFIC["moments"] and
                 model.n_params == CATCHUP_TRAFFIC["params"] and
                 args.steps == CATCHUP_TRAFFIC["steps"] and B == CATCHUP_TRAFFIC["batch"])
         traffic = CATCHUP_TRAFFIC["bytes"] if same else None

@@ -6,8 +6,10 @@
 //   - random 16-byte atomic groups (4 lanes add one float each into 16
 //     consecutive bytes, as 2F lanes scatter one x-pair of a row pair),
 // over a 24 GiB buffer, at 64K to 4M threads; then atomics against the bytes
-// one instruction puts into a line and the footprint, and a read followed by
-// an atomic into the same line or another.  Not part of the library.
+// one instruction puts into a line and the footprint, a read followed by an
+// atomic into the same line or another, random byte stores against returning
+// atomics (claim flags), and the deferred Adam update's per-segment traffic in
+// two state layouts.  Not part of the library.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -87,6 +89,58 @@ __global__ void read_then_atomic(float* __restrict__ buf, uint64_t nlines, int i
     const int q = (int)((r >> 60) % 4) * 4;
     const float v = buf[a * 32 + q + l];
     unsafeAtomicAdd(buf + b * 32 + 16 + q + l, v + 1.0f);
+  }
+}
+
+// Random one-byte stores (the deferred update's claim flags).
+__global__ void byte_store(uint8_t* __restrict__ buf, uint64_t n, int iters) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  for (int k = 0; k < iters; ++k) buf[mix64(t * 131 + k) % n] = 1;
+}
+
+// Random returning atomic max on the upper half of 8-byte words (a claim by
+// stamp).
+__global__ void ret_atomic_max(uint32_t* __restrict__ buf, uint64_t nwords, int iters,
+                               uint32_t* __restrict__ sink) {
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint32_t acc = 0;
+  for (int k = 0; k < iters; ++k)
+    acc += atomicMax(buf + 2 * (mix64(t * 131 + k) % nwords) + 1, (uint32_t)k + 1);
+  if (acc == 0xdeadbeefu) sink[0] = acc;
+}
+
+// A deferred Adam update of random 16-float segments, 4 lanes per segment:
+// read p, g, m, v, write p, m, v and a zero g.  LINES == 3: p and g in arrays of
+// their own, m and v paired in one line; LINES == 2: p with m in one line, g
+// with v in another.  nseg segments of 256 bytes of state in buf.
+template <int LINES>
+__global__ void seg_update(float* __restrict__ buf, uint64_t nseg, int iters) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t s0 = t / 4;
+  const int sub = (int)(t % 4);
+  for (int k = 0; k < iters; ++k) {
+    const uint64_t seg = mix64(s0 * 131 + k) % nseg;
+    float *pp, *gp, *mp, *vp;
+    if (LINES == 3) {
+      pp = buf + seg * 16 + 4 * sub;
+      gp = buf + nseg * 16 + seg * 16 + 4 * sub;
+      mp = buf + nseg * 32 + seg * 32 + 4 * sub;
+      vp = mp + 16;
+    } else {
+      pp = buf + seg * 32 + 4 * sub;
+      mp = pp + 16;
+      gp = buf + nseg * 32 + seg * 32 + 4 * sub;
+      vp = gp + 16;
+    }
+    f4 p = *(f4*)pp, g = *(f4*)gp, m = *(f4*)mp, v = *(f4*)vp;
+    m = m * 0.9f + g;
+    v = v * 0.999f + g * g;
+    p = p - m * 0.001f;
+    *(f4*)pp = p;
+    *(f4*)gp = (f4){0.f, 0.f, 0.f, 0.f};
+    *(f4*)mp = m;
+    *(f4*)vp = v;
   }
 }
 
@@ -175,6 +229,57 @@ int main() {
       const double groups = threads / 4.0 * iters;
       std::printf("16-B read then 16-B atomic group into %s line: %.2f G pairs/s\n",
                   same ? "the same" : "another", groups / ms / 1e6);
+      std::fflush(stdout);
+    }
+    // claim flags: byte stores against returning atomics on state words
+    const int it2 = 32;
+    for (uint64_t foot : {(uint64_t)64 << 20, (uint64_t)512 << 20, (uint64_t)4 << 30}) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        hipEventRecord(a);
+        hipLaunchKernelGGL(byte_store, dim3(blocks), dim3(256), 0, 0,
+                           reinterpret_cast<uint8_t*>(buf), foot, it2);
+        hipEventRecord(b);
+        if (!ok(hipEventSynchronize(b), "kernel")) return 1;
+        hipEventElapsedTime(&ms, a, b);
+      }
+      std::printf("random byte stores over %5.0f MiB: %.2f G/s\n", foot / 1048576.0,
+                  threads * (double)it2 / ms / 1e6);
+      std::fflush(stdout);
+    }
+    for (uint64_t foot : {(uint64_t)64 << 20, (uint64_t)4 << 30}) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        hipEventRecord(a);
+        hipLaunchKernelGGL(ret_atomic_max, dim3(blocks), dim3(256), 0, 0,
+                           reinterpret_cast<uint32_t*>(buf), foot / 8, it2,
+                           reinterpret_cast<uint32_t*>(sink));
+        hipEventRecord(b);
+        if (!ok(hipEventSynchronize(b), "kernel")) return 1;
+        hipEventElapsedTime(&ms, a, b);
+      }
+      std::printf("returning atomic max on 8-byte words over %5.0f MiB: %.2f G/s\n",
+                  foot / 1048576.0, threads * (double)it2 / ms / 1e6);
+      std::fflush(stdout);
+    }
+    // the deferred update's segment traffic in two state layouts
+    const uint64_t nseg = bytes / 256;
+    for (int lines : {3, 2}) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        hipEventRecord(a);
+        if (lines == 3)
+          hipLaunchKernelGGL(seg_update<3>, dim3(blocks), dim3(256), 0, 0, buf, nseg, it2);
+        else
+          hipLaunchKernelGGL(seg_update<2>, dim3(blocks), dim3(256), 0, 0, buf, nseg, it2);
+        hipEventRecord(b);
+        if (!ok(hipEventSynchronize(b), "kernel")) return 1;
+        hipEventElapsedTime(&ms, a, b);
+      }
+      std::printf("segment update (p, g, m, v read; p, m, v, g written), %s: %.2f G "
+                  "segments/s\n",
+                  lines == 3 ? "p | g | m+v lines" : "p+m | g+v lines",
+                  threads / 4.0 * it2 / ms / 1e6);
       std::fflush(stdout);
     }
   }
