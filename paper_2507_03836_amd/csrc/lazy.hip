@@ -34,7 +34,7 @@ namespace {
 constexpr int kSeg = FHASH_LAZY_FLOATS;
 static_assert(kSeg == 16, "segments of 16 floats");
 constexpr int kChunk = 512;  // flagged segments a workgroup sorts by gap in LDS
-constexpr int kBins = 32;
+constexpr int kBins = 64;
 constexpr int kTile = 2048;  // claim flags a workgroup scans per pass (8 per thread)
 
 // Per-step record: {step_size, inv_bc2_sqrt, gscale, kind}; kind 0: a step
@@ -251,13 +251,14 @@ __global__ void __launch_bounds__(256)
 
 __device__ __forceinline__ int gap_bin(uint32_t gap) {  // gap >= 1
   if (gap < 16) return (int)gap;
-  const int k = 31 - __clz(gap);          // >= 4
-  const int half = (gap >> (k - 1)) & 1;  // gaps within one bin differ by < 1.5x
-  const int b = 16 + 2 * (k - 4) + half;
+  const int k = 31 - __clz(gap);             // >= 4
+  const int quarter = (gap >> (k - 2)) & 3;  // gaps within one bin differ by < 1.25x
+  const int b = 16 + 4 * (k - 4) + quarter;
   return b < kBins ? b : kBins - 1;
 }
 
-// Catch-up of the flagged segments to step `upto`; ctr[2..5] accumulate the
+// Catch-up of the flagged segments to step `upto`; ctr[0] hands out the groups
+// of tiles (zero at launch); ctr[2..5] accumulate the
 // segments caught up, those that loaded data, those with a pending gradient
 // and the segment-steps replayed (workload statistics).  target: the stamp
 // the caught-up segments take (the step being prepared), or 0 to keep their
@@ -274,8 +275,7 @@ __global__ void __launch_bounds__(256)
                         uint2* __restrict__ state, const float4* __restrict__ rec, AdamK base,
                         float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                         float* __restrict__ v, int64_t pm, void* __restrict__ shadow, int sdt,
-                        int64_t begin, int64_t end, uint32_t upto, uint32_t target, int group,
-                        int min_flush) {
+                        int64_t begin, int64_t end, uint32_t upto, uint32_t target, int group) {
   // flagged segments not yet caught up: fewer than kChunk carried over plus
   // at most one tile's worth
   __shared__ uint32_t ids[kTile + kChunk];
@@ -287,13 +287,21 @@ __global__ void __launch_bounds__(256)
   unsigned long long n_stale = 0, n_work = 0, n_pend = 0, n_steps = 0;
   const int sub = threadIdx.x & (kLanesPerSeg - 1);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __shared__ int64_t next_first;
   int cnt = 0;  // entries in ids (the same in every thread)
-  // groups of `group` consecutive tiles, grid-strided: a chunk's segments are
-  // mostly neighbours in memory, and the workgroups share dense and sparse
-  // regions of the flags alike
+  // groups of `group` consecutive tiles, each claimed by the next workgroup
+  // free (counter ctr[0], zero at launch): a chunk's segments are mostly
+  // neighbours in memory, and the work follows the flags' density
   const int64_t ntiles = (nseg + kTile - 1) / kTile;
+  int64_t first = 0;
   for (int64_t it = 0;; ++it) {
-    const int64_t first = (blockIdx.x + it / group * (int64_t)gridDim.x) * group;
+    if (it % group == 0) {
+      // thread 0 writes next_first again only after the scan's barriers of
+      // this group's first tile, which every thread reaches after reading it
+      if (threadIdx.x == 0) next_first = (int64_t)atomicAdd(&ctr[0], 1ull) * group;
+      __syncthreads();
+      first = next_first;
+    }
     const int64_t tile = first + it % group;
     const bool more = first < ntiles;  // workgroup-uniform
     const int64_t t0 = tile * kTile;
@@ -326,13 +334,10 @@ __global__ void __launch_bounds__(256)
       cnt += total;
       __syncthreads();  // ids written; wave_total may be reused
     }
-    // full chunks; at the end of a group also a shorter one of at least
-    // min_flush entries (a chunk then stays within one group); at the end
-    // everything
-    const bool group_end = it % group == group - 1;
+    // full chunks (the fuller the chunk, the closer the replay lengths its
+    // sort puts into one wave); at the end the rest
     int c0 = 0;
-    while (cnt - c0 >= kChunk || (group_end && cnt - c0 >= min_flush) ||
-           (!more && cnt - c0 > 0)) {
+    while (cnt - c0 >= kChunk || (!more && cnt - c0 > 0)) {
       const int nloc = cnt - c0 < kChunk ? cnt - c0 : kChunk;
       if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
       __syncthreads();
@@ -460,6 +465,12 @@ __global__ void lazy_record_kernel(float4* rec, int64_t t, float step_size, floa
   }
 }
 
+// Zero the catch-up's group counter (a fill kernel, not a memset node, so that
+// the launch sequence can be captured in a graph).
+__global__ void lazy_reset_groups_kernel(unsigned long long* ctr) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[0] = 0ull;
+}
+
 __global__ void __launch_bounds__(256) lazy_zero_kernel(uint4* __restrict__ w, int64_t n16) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -471,7 +482,7 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct LazyWs {
   uint2* state;
   uint8_t* flags;           // one per segment, zero-padded to whole tiles
-  unsigned long long* ctr;  // [2..5] workload statistics
+  unsigned long long* ctr;  // [0] next group of flag tiles, [2..5] workload statistics
   float4* rec;
 };
 
@@ -527,9 +538,10 @@ void launch_catch_up(const fhash_lazy* lz, const LazyWs& w, uint32_t target, int
   auto kern = odd ? (runs ? lazy_catchup_kernel<true, true> : lazy_catchup_kernel<true, false>)
                   : (runs ? lazy_catchup_kernel<false, true> : lazy_catchup_kernel<false, false>);
   const int64_t pm = lz->moments == FHASH_MOMENTS_WITH_PARAMS ? ~(int64_t)15 : 0;
+  hipLaunchKernelGGL(lazy_reset_groups_kernel, dim3(1), dim3(64), 0, st, w.ctr);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, st, w.flags, nseg, w.ctr,
                      w.state, w.rec, lazy_base(lz), p, gr, m, v, pm, shadow, (int)sdt, lz->begin,
-                     lz->end, (uint32_t)lz->steps, target, (int)group, kChunk / 2);
+                     lz->end, (uint32_t)lz->steps, target, (int)group);
 }
 
 }  // namespace
