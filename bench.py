@@ -50,10 +50,10 @@ HBM_PEAK_GBS = 8000.0
 ADAM_RW_BYTES_PER_PARAM = 24
 # HBM bytes of one adam_kernel launch at the default workload (FP32, tracked), from
 # rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) passes scaled by a plain streaming
-# copy of known size; valid only for the parameter count and optimizer source they were
-# taken on.
-ADAM_TRAFFIC = {"bytes": 156.90e9, "params": 6390343593,
-                "source_md5": "d602a578d7be1d0da4b2643ea2ed6c36"}
+# copy of known size; valid only for the parameter count, optimiser state layout and
+# optimizer source they were taken on.
+ADAM_TRAFFIC = {"bytes": 160.80e9, "params": 6390343593, "moments": "with-params",
+                "source_md5": "f6d69b782465363a0baa0efdebaf6158"}
 
 # Catch-up of the deferred Adam (one launch per step), algorithmic bytes: the claim flags of
 # the whole range are read (1 B per segment of 16 floats); every flagged segment reads and
@@ -84,6 +84,11 @@ def _layout_kw(args, lazy=True):
     return {"paired_moments": args.moments == "paired" or (args.moments == "with-params"
                                                          and not lazy),
             "moments_with_params": args.moments == "with-params" and lazy}
+
+
+def _reads_kw(args, precision):
+    """Model keyword of the mixed path's table reads (--mixed-table-reads)."""
+    return {"table_reads": args.mixed_table_reads if precision == "mixed" else "f32"}
 
 
 def _kernel_md5(path, name):
@@ -147,8 +152,21 @@ def parse():
     ap.add_argument("--layout", choices=["rows", "bricks"], default="rows",
                     help="slot order of the active index: the F-Hash equation's rows, or "
                          "2x2x2x2 vertex bricks (Sec. 3.2.3 allows other linearisations)")
-    ap.add_argument("--sort", action="store_true",
-                    help="sort each batch by a 4D Morton key before the fused step")
+    ap.add_argument("--mixed-table-reads", choices=["f16", "f32"], default="f16",
+                    help="what the mixed path's fused kernels gather from the tables: an FP16 "
+                         "copy that the Adam update writes beside the FP32 master (f16), or the "
+                         "FP32 master itself (f32); the decoder runs on BF16 MFMA either way")
+    ap.add_argument("--paths", choices=["fp32,mixed", "mixed,fp32"], default="fp32,mixed",
+                    help="headline: the order in which the two training paths run")
+    ap.add_argument("--no-sort", dest="sort", action="store_false",
+                    help="train on batches in draw order instead of sorting each batch by a "
+                         "4D Morton key before the fused step (sorted, the lanes of one "
+                         "scatter instruction that add into one 64-byte chunk share one "
+                         "atomic request, and the gathers share lines)")
+    ap.add_argument("--sort-reduce", action="store_true",
+                    help="with sorted batches: at the coarse levels, sum a corner across the "
+                         "samples of a scatter instruction before one atomic when they all "
+                         "share its slot (FHASH_SAMPLES_SORTED)")
     ap.add_argument("--field-seed", type=int, default=1002)
     ap.add_argument("--sampler-seed", type=int, default=2002)
     ap.add_argument("--psnr-target", type=float, default=0.0,
@@ -835,8 +853,8 @@ ATOMIC_CEILING_GPS = 16.8
 # plain streaming copy of known size; valid only while the kernel sources
 # hashed in _fused_src_md5() and the optimiser state layout are those the
 # counters were taken with.
-FUSED_TRAFFIC = {"bytes": 33218403961, "raw_bytes": 19302885069, "moments": "with-params",
-                 "source_md5": "e5a321605487a5434ed4f9f1f3a82091"}
+FUSED_TRAFFIC = {"bytes": 19558451324, "raw_bytes": 12416501760, "moments": "with-params",
+                 "sorted": True, "source_md5": "e5a321605487a5434ed4f9f1f3a82091"}
 
 
 def _fused_src_md5():
@@ -939,18 +957,23 @@ def cpu_baseline_all_cores(model, gen, dims, batch, n_cpu, seed):
                        "FP64, one process per core")}
 
 
-def _train_timed(model, gen, dims, B, steps, warmup, sampler_seed, pos, tgt):
+def _train_timed(model, gen, dims, B, steps, warmup, sampler_seed, pos, tgt, sort=True,
+                 sort_reduce=False):
     """warmup + steps training steps; per-phase HIP events on the launch stream
     over the timed steps; the timed region ends with the deferred update
-    flushed.  Returns the breakdown and the step closure."""
+    flushed.  sort: each batch is put in 4D Morton order (fhash_sort_samples)
+    after it is drawn.  Returns the breakdown and the step closure."""
     import numpy as np
 
     from paper_2507_03836_amd import _lib as fl
     stream = torch.cuda.current_stream()
     coreset, M, field = gen["coreset"], gen["M"], gen["field"]
+    sort_ws = [None]
 
     def step(k, ev=None):
         fl.fhash_sample(sampler_seed, k, B, coreset, M, dims, field, pos, tgt)
+        if sort:
+            sort_ws[0] = fl.fhash_sort_samples(pos, tgt, B, sort_ws[0])
         if ev is not None:
             ev[0].record(stream)
         model.prepare(pos, fl.LAZY_MARK)
@@ -959,7 +982,7 @@ def _train_timed(model, gen, dims, B, steps, warmup, sampler_seed, pos, tgt):
         model.prepare(pos, fl.LAZY_CATCH_UP)
         if ev is not None:
             ev[2].record(stream)
-        model.fwd_bwd(pos, tgt, prepared=True)
+        model.fwd_bwd(pos, tgt, prepared=True, sorted_batch=sort and sort_reduce)
         if ev is not None:
             ev[3].record(stream)
         model.optimizer_step()
@@ -990,8 +1013,8 @@ def _train_timed(model, gen, dims, B, steps, warmup, sampler_seed, pos, tgt):
                             "final_flush_per_step": fev[0].elapsed_time(fev[1]) / steps},
            "lazy_per_step": {k: (st1[k] - st0[k]) / steps for k in st1},
            "mean_loss": model.loss_sum.item() / (B * (warmup + steps))}
-    out["breakdown_ms"]["sampler_and_other"] = out["ms_per_step"] - sum(
-        out["breakdown_ms"].values())
+    out["breakdown_ms"]["sampler_sort_and_other" if sort else "sampler_and_other"] = (
+        out["ms_per_step"] - sum(out["breakdown_ms"].values()))
     return out, step, t_first
 
 
@@ -1033,21 +1056,26 @@ def compulsory_lines(model, pos, line=128):
     tb = 2 if model.shadow is not None else (8 if runs else 4)
     gb = 8 if runs else 4
     dir_lines, tab_lines, grad_lines = [], [], []
-    requests = 0
+    requests = {}
     for s in range(0, n, 1 << 16):
         e = min(n, s + (1 << 16))
         d, sl = fl.fhash_corner_rows(model.index, pos[s:e], e - s)
         d = d.view(-1)
         d = d[d >= 0]
         dir_lines.append(torch.unique(d * 16 // line))
-        # the scatter-add's atomic requests: one per corner pair, two when its
-        # rows fall in different 64-byte chunks (16 gradient floats, in either
-        # layout) of the gradient
-        sp = sl.view(-1, 2)
-        v0, v1 = sp[:, 0] >= 0, sp[:, 1] >= 0
-        c0, c1 = sp[:, 0] * F // 16, sp[:, 1] * F // 16
-        requests += int((v0 | v1).sum()) + int((v0 & v1 & (c0 != c1)).sum())
-        del sp, v0, v1, c0, c1
+        # the scatter-add's atomic requests, per level: as issued, and as they would
+        # be if equal slots of a block were summed first (whole blocks on one slot,
+        # or every run of neighbours on one slot)
+        c = sl
+        pad = (-(e - s)) % 16
+        if pad:
+            c = torch.cat([c, torch.full((pad,) + tuple(c.shape[1:]), -1, dtype=c.dtype,
+                                         device=c.device)])
+        c = c.view(-1, 16, c.shape[1], 8, 2).permute(0, 2, 3, 1, 4)  # block, level, pair, i, e
+        for name, v in (("issued", c), ("uniform", _merge_uniform(c)), ("runs", _merge_runs(c))):
+            per_level = _atomic_requests(v, F)
+            requests[name] = per_level if name not in requests else requests[name] + per_level
+        del c
         sl = sl.view(-1)
         sl = sl[sl >= 0]
         tab_lines.append(torch.unique(sl * (F * tb) // line))
@@ -1056,10 +1084,54 @@ def compulsory_lines(model, pos, line=128):
     u = lambda xs: int(torch.unique(torch.cat(xs)).numel())
     nd, nt, ng = u(dir_lines), u(tab_lines), u(grad_lines)
     return {"line_bytes": line, "directory_lines": nd, "table_lines": nt, "gradient_lines": ng,
-            "bytes": line * (nd + nt + 2 * ng) + 20 * n, "atomic_requests": requests}
+            "bytes": line * (nd + nt + 2 * ng) + 20 * n,
+            "atomic_requests": int(requests["issued"].sum()),
+            "atomic_requests_per_level": requests["issued"].tolist(),
+            "atomic_requests_if_summed": {k: requests[k].tolist() for k in ("uniform", "runs")}}
 
 
-def _serve_sub(model, gen, dims, args, n_req):
+def _atomic_requests(c, F):
+    """Memory-side atomic requests of the scatter-add, per level.  c: slots
+    (block, level, pair, sample, pair element), -1 for none.  One scatter
+    instruction covers one corner pair of one level for the 16 samples of a
+    block; lanes that add into distinct floats of one 64-byte chunk share a
+    request, lanes that add into the same float cannot, so a chunk costs as
+    many requests as the most samples on one of its rows."""
+    nb, L = c.shape[0], c.shape[1]
+    v = c.reshape(-1, 32)
+    big = int(v.max()) + 2
+    gid = torch.arange(v.shape[0], device=v.device, dtype=torch.int64)[:, None]
+    key = (gid * big + v)[v >= 0]
+    key, _ = torch.sort(key)
+    key, cnt = torch.unique_consecutive(key, return_counts=True)
+    chunk = (key // big) * big + (key % big) * F // 16
+    chunk, inv = torch.unique_consecutive(chunk, return_inverse=True)
+    most = torch.zeros(chunk.numel(), dtype=cnt.dtype, device=cnt.device)
+    most.scatter_reduce_(0, inv, cnt, "amax")
+    level = (chunk // big) // 8 % L
+    out = torch.zeros(L, dtype=torch.int64, device=c.device)
+    out.scatter_add_(0, level, most)
+    return out.cpu()
+
+
+def _merge_uniform(c):
+    """c with every (block, level, pair) whose 16 samples share one pair of
+    slots reduced to its first sample."""
+    same = ((c == c[:, :, :, :1, :]) | (c < 0)).all(dim=4).all(dim=3, keepdim=True)
+    keep = torch.zeros_like(c, dtype=torch.bool)
+    keep[:, :, :, 0, :] = True
+    return torch.where(same.unsqueeze(4) & ~keep, torch.full_like(c, -1), c)
+
+
+def _merge_runs(c):
+    """c with every run of neighbouring samples on one slot reduced to its
+    last sample (a segmented sum over the block's 16 samples)."""
+    tail = torch.ones_like(c, dtype=torch.bool)
+    tail[:, :, :, :-1, :] = c[:, :, :, :-1, :] != c[:, :, :, 1:, :]
+    return torch.where(tail, c, torch.full_like(c, -1))
+
+
+def _serve_sub(model, table16, mlp_params, gen, dims, args, n_req):
     """Render p50/p99 of the trained mixed model (FP16 tables, its 16-bit
     decoder) at saturation and three Poisson rates: continuous batching
     (backfill) against one request at a time, same arrivals."""
@@ -1069,14 +1141,9 @@ def _serve_sub(model, gen, dims, args, n_req):
     from paper_2507_03836_amd import synth
     from paper_2507_03836_amd.serving import (GpuExecutor, Request, ResidentModel, Scheduler,
                                               latency_stats, poisson_arrivals)
-    if model.shadow is not None:  # the flushed master rounded to FP16
-        table16 = model.shadow[: model.n_table]
-    else:
-        table16 = torch.empty(model.n_table, dtype=torch.float16, device="cuda")
-        fl.fhash_cast(model.table, table16)
     tf = torch.from_numpy(synth.transfer_function()).cuda()
     rm = ResidentModel(index=model.index, mlp=model.mlp, table=table16,
-                       params=model.mlp_params.clone(), mask_bits=gen["bits"], dims=dims, tf=tf,
+                       params=mlp_params, mask_bits=gen["bits"], dims=dims, tf=tf,
                        keep=(model._dir,), occ=fl.fhash_occupancy_grid(gen["bits"], dims))
     C = 1 << 22
     rng = np.random.default_rng(5004)
@@ -1162,8 +1229,10 @@ def headline_bench(args):
     for prec in ("fp32", "mixed"):
         small = FHashModel(FHashConfig(res=[[4, 4, 4, 2]] * 16, n_features=2, hidden=64,
                                        n_hidden=3), None, dims, precision=prec, lazy=True,
-                           **_layout_kw(args), max_steps=4)
+                           **_layout_kw(args), max_steps=4, **_reads_kw(args, prec))
         fl.fhash_sample(1, 1, 4096, gen["coreset"], gen["M"], dims, gen["field"], pos, tgt)
+        if args.sort:
+            fl.fhash_sort_samples(pos, tgt, 4096)
         small.prepare(pos[:4096])
         small.fwd_bwd(pos[:4096], tgt[:4096], prepared=True)
         small.optimizer_step()
@@ -1173,21 +1242,24 @@ def headline_bench(args):
     torch.cuda.synchronize()
     if args.calibrate_copy:
         copy_calibration()
-    paths, keep = {}, None
-    for prec in ("fp32", "mixed"):
+    paths, keep, cpu = {}, None, None
+    for prec in args.paths.split(","):
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, precision=prec, lazy=True,
-                           **_layout_kw(args),
+                           **_layout_kw(args), **_reads_kw(args, prec),
                            max_steps=args.max_steps + args.warmup + args.steps + 8)
         r, step, t_first = _train_timed(model, gen, dims, B, args.steps, args.warmup, 2003, pos,
-                                        tgt)
+                                        tgt, sort=args.sort, sort_reduce=args.sort_reduce)
         log(f"[headline] {prec}: {r['ms_per_step']:.2f} ms/step ({r['samples_per_s'] / 1e6:.1f}"
             f" M samples/s): {r['breakdown_ms']}")
-        # the timed batch's compulsory lines (the batch of the last timed step)
-        fl.fhash_sample(2003, args.warmup + args.steps, B, gen["coreset"], gen["M"], dims,
-                        gen["field"], pos, tgt)
-        r["compulsory"] = compulsory_lines(model, pos)
         r["time_to_psnr"] = _to_psnr(model, step, args.warmup + args.steps, t_first, ppos, ptgt,
                                      args.psnr_target or 40.0, args.eval_every, args.max_steps)
+        # the timed batch's compulsory lines (the batch of the last timed step, in
+        # the order it was trained in; drawn again, after the clock of the PSNR run)
+        fl.fhash_sample(2003, args.warmup + args.steps, B, gen["coreset"], gen["M"], dims,
+                        gen["field"], pos, tgt)
+        if args.sort:
+            fl.fhash_sort_samples(pos, tgt, B)
+        r["compulsory"] = compulsory_lines(model, pos)
         r["params"] = model.n_params
         r["decoder"] = model.decoder
         r["table_reads"] = "f16" if model.shadow is not None else "f32"
@@ -1197,31 +1269,36 @@ def headline_bench(args):
         paths[prec] = r
         model.flush()
         if prec == "mixed":
-            keep = model
-        else:
-            cpu = None
-            if not args.no_cpu_baseline:
-                try:
-                    cpu = cpu_baseline_all_cores(model, gen, dims, B, args.cpu_samples, 2003)
-                except Exception as e:  # reported, never hidden
-                    cpu = {"error": repr(e)}
-            model.params = model.grads = model.m = model.v = None
-            model.mv = model.pm = model.gv = model.lazy = None
-            del model
-            torch.cuda.empty_cache()
-    model = keep
-    model.grads = model.m = model.v = model.mv = model.pm = model.gv = None
-    model.lazy = None
-    torch.cuda.empty_cache()
-    serve = _serve_sub(model, gen, dims, args, args.serve_requests)
+            # what serving keeps of the trained mixed model: its FP16 table (the
+            # flushed master rounded to FP16) and decoder; the rest is freed
+            if model.shadow is not None:
+                table16 = model.shadow[: model.n_table]
+            else:
+                table16 = torch.empty(model.n_table, dtype=torch.float16, device="cuda")
+                fl.fhash_cast(model.table, table16)
+            keep = (model, table16, model.mlp_params.clone())
+        elif not args.no_cpu_baseline:
+            try:
+                cpu = cpu_baseline_all_cores(model, gen, dims, B, args.cpu_samples, 2003)
+            except Exception as e:  # reported, never hidden
+                cpu = {"error": repr(e)}
+        model.params = model.grads = model.m = model.v = None
+        model.mv = model.pm = model.gv = model.lazy = None
+        model.mlp_p = model.mlp_g = model.mlp_m = model.mlp_v = None
+        del model
+        torch.cuda.empty_cache()
+    serve = _serve_sub(*keep, gen, dims, args, args.serve_requests)
     mx, fp = paths["mixed"], paths["fp32"]
     fused_ms = mx["breakdown_ms"]["fused_fwd_bwd"]
-    alg = 3092 * B  # FP16 gather 1024 + FP32 scatter read-modify-write 2048 + 20 B I/O
+    reads16 = mx["table_reads"] == "f16"
+    # FP16 (FP32) gather 1024 (2048) + FP32 scatter read-modify-write 2048 + 20 B I/O
+    alg = (3092 if reads16 else 4116) * B
     comp = mx["compulsory"]["bytes"]
     areq = mx["compulsory"]["atomic_requests"]
-    same = (FUSED_TRAFFIC["source_md5"] == _fused_src_md5() and
-            args.moments == FUSED_TRAFFIC["moments"])
-    roof = {"kernel": "fused_kernel<TRAIN, F=2, FP16 table, 32-64-64-64-1, BF16 decoder>",
+    same = (FUSED_TRAFFIC["source_md5"] == _fused_src_md5() and reads16 and
+            args.moments == FUSED_TRAFFIC["moments"] and args.sort == FUSED_TRAFFIC["sorted"])
+    roof = {"kernel": "fused_kernel<TRAIN, F=2, " + ("FP16" if reads16 else "FP32")
+                      + " table, 32-64-64-64-1, BF16 decoder>",
             "bound": "hbm", "achieved": alg / (fused_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": alg / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "traffic": FUSED_TRAFFIC["bytes"] if same else None,
@@ -1240,7 +1317,8 @@ def headline_bench(args):
         "value": mx["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": mx["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 decoder MFMA, f16 table reads, f32 master/Adam/accumulation",
+        "dtype": "bf16 decoder MFMA, " + mx["table_reads"]
+                 + " table reads, f32 master/Adam/accumulation",
         "data": "synthetic",
         "config": {"workload": "F-Hash differentiated mixed-precision training, 432x432x432x60 "
                                "synthetic volume, 16 levels x 2 features, MLP 32-64-64-64-1, "
@@ -1302,6 +1380,7 @@ def main():
     model = FHashModel(cfg, None if args.dense_index else gen["bits"], dims,
                        hash_bits=args.hash_bits, init_seed=3000 + args.field_seed - 1000,
                        precision=args.precision, track_touched=args.optimizer == "tracked",
+                       **_reads_kw(args, args.precision),
                        lazy=args.optimizer == "lazy",
                        **_layout_kw(args, args.optimizer == "lazy"),
                        max_steps=max(args.max_steps, args.warmup + args.steps) + 64)
@@ -1331,7 +1410,7 @@ def main():
         model.prepare(pos, fl.LAZY_CATCH_UP)
         if ev is not None:
             ev[2].record(stream)
-        model.fwd_bwd(pos, tgt, sorted_batch=args.sort, prepared=True)
+        model.fwd_bwd(pos, tgt, sorted_batch=args.sort and args.sort_reduce, prepared=True)
         if ev is not None:
             ev[3].record(stream)
         model.optimizer_step()
@@ -1366,9 +1445,10 @@ def main():
     loss = model.loss_sum.item() / (B * (args.warmup + args.steps))
     ms = wall * 1e3 / args.steps
     mixed = args.precision == "mixed"
+    shadow = model.shadow is not None
     P = model.n_params
     k_done = args.warmup + args.steps
-    per = ADAM_RW_BYTES_PER_PARAM + (2 if mixed else 0)
+    per = ADAM_RW_BYTES_PER_PARAM + (2 if shadow else 0)
     flagged = None
     if model.touch is None:
         adam_bytes = (per + 4) * P
@@ -1378,7 +1458,7 @@ def main():
         fl.fhash_sample(args.sampler_seed, k_done, B, coreset, M, dims, field, pos, tgt)
         if args.sort:
             sort_ws[0] = fl.fhash_sort_samples(pos, tgt, B, sort_ws[0])
-        model.fwd_bwd(pos, tgt, sorted_batch=args.sort)
+        model.fwd_bwd(pos, tgt, sorted_batch=args.sort and args.sort_reduce)
         flagged = int((model._touch_flags != 0).sum().item())
         model.optimizer_step()
         T = model.touch.end - model.touch.begin
@@ -1391,7 +1471,7 @@ def main():
         nseg = (model.lazy.desc.end - model.lazy.desc.begin + 15) // 16
         roof_bytes = (nseg + LAZY_ENTRY_BYTES * d["segments"]
                       + LAZY_LOADED_BYTES * d["loaded"] + LAZY_PENDING_BYTES * d["pending"]
-                      + (LAZY_SHADOW_BYTES * d["loaded"] if mixed else 0))
+                      + (LAZY_SHADOW_BYTES * d["loaded"] if shadow else 0))
         roof_kernel, roof_ms = "lazy_catchup_kernel", catch_ms
         achieved = roof_bytes / (roof_ms * 1e-3) / 1e9
         extra = {"segments_per_launch": d["segments"], "loaded_per_launch": d["loaded"],
@@ -1401,14 +1481,16 @@ def main():
     import hashlib
     src = os.path.join(ROOT, "paper_2507_03836_amd", "csrc", "optim.hip")
     same_src = hashlib.md5(open(src, "rb").read()).hexdigest() == ADAM_TRAFFIC["source_md5"]
+    # (the order of the samples within a batch changes neither the parameters nor the
+    # segments the update touches)
     traffic = ADAM_TRAFFIC["bytes"] if (same_src and not mixed and model.touch is not None and
-                                        not args.sort and
+                                        args.moments == ADAM_TRAFFIC["moments"] and
                                         model.n_params == ADAM_TRAFFIC["params"]) else None
     if lazy:
         srcs = [os.path.join(ROOT, "paper_2507_03836_amd", "csrc", f)
                 for f in ("lazy.hip", "adam_dev.h")]
         md5 = hashlib.md5(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
-        same = (md5 == CATCHUP_TRAFFIC["source_md5"] and not mixed and not args.sort and
+        same = (md5 == CATCHUP_TRAFFIC["source_md5"] and not mixed and
                 args.moments == CATCHUP_TRAFFIC["moments"] and
                 model.n_params == CATCHUP_TRAFFIC["params"] and
                 args.steps == CATCHUP_TRAFFIC["steps"] and B == CATCHUP_TRAFFIC["batch"])
@@ -1417,7 +1499,8 @@ def main():
         f"fused fwd+bwd {fb_ms:.3f} ms, "
         f"adam {adam_ms:.3f} ms, final flush {flush_ms:.3f} ms; mean loss {loss:.4g}")
     out = {
-        "metric": ("train samples/s fwd+bwd (" + ("FP16 table reads, FP32 master"
+        "metric": ("train samples/s fwd+bwd (" + (("FP16" if shadow else "FP32")
+                                                  + " table reads, BF16 decoder, FP32 master"
                                                   if mixed else "FP32 path")
                    + "), whole training step incl. Adam over every parameter"),
         "value": B / (ms * 1e-3),
@@ -1429,13 +1512,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16 table reads, f32 math" if mixed else "f32",
+        "dtype": (("f16" if shadow else "f32") + " table reads, bf16 decoder MFMA, f32 master"
+                  if mixed else "f32"),
         "data": "synthetic",
         "config": {"workload": (f"F-Hash training, {'x'.join(map(str, dims))} synthetic volume, "
                                 f"{args.levels} levels x 2 features, MLP "
                                 + "-".join(map(str, cfg.width))
                                 + f", batch 2^{int(np.log2(B))} coreset draws"
                                 + (", Morton-sorted batches" if args.sort else "")
+                                + (" with equal slots merged before the atomics" if args.sort and
+                                   args.sort_reduce else "")
                                 + (", dense index (every box vertex)" if args.dense_index
                                    else "")
                                 + (f", spatial-hash index (2^{args.hash_bits} rows per large "

@@ -271,9 +271,11 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
                     const void* table, fhash_dtype table_dt, const float* params,
                     const void* shadow, float* y, void* stream);
 /* flags: FHASH_SAMPLES_SORTED declares that the batch is ordered by
- * fhash_sort_samples; the scatter-add then sums equal slots of neighbouring
- * samples with a wave-level segmented reduction before its atomics on the
- * levels coarse enough for neighbours to share vertices.  Results are the same
+ * fhash_sort_samples; on the levels coarse enough for neighbouring samples to
+ * share vertices, the scatter-add then sums a corner across the samples that
+ * one of its instructions covers (16 at F = 1 and 2, 8 at F = 4) when they all
+ * hit the same slot, and adds the sum with one atomic (atomics of different
+ * lanes into one float cannot share a memory request).  Results are the same
  * up to FP32 summation order.  FHASH_GRAD_PAIRED: d_table is stored in runs
  * of 16 floats separated by 16-float gaps (gradient value i at
  * d_table[i + 16 floor(i / 16)]; the gradient array of the optimiser layout
@@ -538,8 +540,8 @@ int fhash_sample(uint64_t seed, uint64_t step, int64_t n, const uint64_t* corese
 /* Reorder a batch of samples (pos float4[n], target float[n] or NULL, both
  * device, in place) by a 4D Morton key of the positions quantised to 256
  * cells per axis (stable LSD radix sort).  Samples of the same cells become
- * neighbours, which the gathers and the segmented reduction before the
- * scatter-add exploit; the MSE loss and its gradient do not depend on the
+ * neighbours, which the gathers and the merge of equal slots before the
+ * scatter-add's atomics (FHASH_SAMPLES_SORTED) exploit; the MSE loss and its gradient do not depend on the
  * order.  ws: device workspace (query with ws == NULL); n < 2^31. */
 int fhash_sort_samples(float* pos, float* target, int64_t n, void* ws, size_t* ws_bytes,
                        void* stream);

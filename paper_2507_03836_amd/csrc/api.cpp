@@ -360,7 +360,7 @@ int fhash_mlp_bwd(const fhash_mlp_desc* mlp, const float* params, const void* sh
 }
 
 // Levels whose cell count is at most 8 samples' worth: sorted neighbours share
-// their vertices often enough for the segmented reduction to pay.
+// their vertices often enough for the merge of a scatter pass to pay.
 static uint32_t dedup_mask(const fhash_index* idx, int64_t n, uint32_t flags) {
   if (!(flags & FHASH_SAMPLES_SORTED)) return 0u;
   uint32_t m = 0;

@@ -197,19 +197,28 @@ __device__ __forceinline__ void scatter_level_lane(const LevelDev& d, const ulon
   }
 }
 
-// Scatter of one level with a segmented reduction across the 16 lanes of a
-// lane group (the 16 samples of a block, which hold the same level): for every
-// corner, runs of neighbouring lanes with the same slot are summed with an
-// inclusive segmented scan of width-16 shuffles and only the last lane of each
-// run issues the atomics.  All 16 lanes must call it (invalid samples pass
-// valid = false and contribute nothing).  Pays off when samples are sorted by
-// cell and the level is coarse enough that neighbours share vertices.
+// scatter_level_lane for a batch in cell order (fhash_sort_samples): a pass
+// of the scatter holds one level for W / 2F samples (the W lanes that share
+// the level: 64, or 32 at F = 1), and at the coarse levels neighbouring
+// samples often all fall on the same vertex.  Lanes that add into the same
+// float of one chunk cannot share a memory request, so a corner that every
+// sample of the pass hits on one slot is summed across the samples first
+// (xor shuffles) and added by the first sample's lanes alone; any other corner
+// is added lane by lane.  Every lane of the W-lane group calls it (a sample
+// that is not valid passes valid = false and adds nothing).
 template <int F, bool BRICK = false>
-__device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulonglong2* dir,
-                                                    bool active, const float4 p, const float* g,
-                                                    bool valid, float* __restrict__ d_table,
-                                                    uint8_t* touch, int64_t tbeg, int64_t gmask) {
-  const int i = threadIdx.x & 15;
+__device__ __forceinline__ void scatter_level_lane_merge(const LevelDev& d, const ulonglong2* dir,
+                                                         bool active, const float4 p, bool valid,
+                                                         int e, int f, float gval,
+                                                         float* __restrict__ d_table,
+                                                         uint8_t* touch, int64_t tbeg,
+                                                         int64_t gmask) {
+  constexpr int Q = 2 * F;
+  constexpr int W = (16 * Q < 64) ? 16 * Q : 64;
+  const int lane = threadIdx.x & 63;
+  const int base = lane & ~(W - 1);
+  const int lead = base + (lane & (Q - 1));  // the same (e, f) lane of the first sample
+  const uint64_t group = (W == 64) ? ~0ull : (((1ull << W) - 1) << base);
   int ix, iy, iz, it;
   float fx, fy, fz, ft;
   locate(p.x, d.rx, d.sx, ix, fx);
@@ -218,43 +227,27 @@ __device__ __forceinline__ void scatter_level_dedup(const LevelDev& d, const ulo
   locate(p.w, d.rt, d.st, it, ft);
   const int a = pair_axis<BRICK>(ix, iy, iz, it);
   const float fa = pair_frac(a, fx, fy, fz, ft);
+  const float wx = e ? fa : 1.0f - fa;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     float wr;
-    int64_t s2[2];
-    bool v2[2];
-    corner_pair<BRICK>(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s2[0], s2[1], v2[0], v2[1],
-                wr);
+    int64_t s0, s1;
+    bool v0, v1;
+    corner_pair<BRICK>(d, dir, active, ix, iy, iz, it, fx, fy, fz, ft, a, r, s0, s1, v0, v1, wr);
+    const int64_t s = (valid && (e ? v1 : v0)) ? (e ? s1 : s0) : -1;
+    float val = (s >= 0) ? wr * wx * gval : 0.0f;
+    const int64_t s_lead = __shfl(s, lead, 64);
+    const bool same = s_lead >= 0 && (s < 0 || s == s_lead);
+    if ((__ballot(same) & group) == group) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int64_t s = (valid && v2[e]) ? s2[e] : -1;
-      const float w = (e ? fa : 1.0f - fa) * wr;
-      float v[F];
-#pragma unroll
-      for (int k = 0; k < F; ++k) v[k] = (s >= 0) ? w * g[k] : 0.0f;
-      const int64_t sprev = __shfl_up(s, 1, 16);
-      const int64_t snext = __shfl_down(s, 1, 16);
-      bool h = (i == 0) || (sprev != s);
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        const bool ho = __shfl_up(h, o, 16);
-        float vo[F];
-#pragma unroll
-        for (int k = 0; k < F; ++k) vo[k] = __shfl_up(v[k], o, 16);
-        if (i >= o) {
-          if (!h) {
-#pragma unroll
-            for (int k = 0; k < F; ++k) v[k] += vo[k];
-          }
-          h = h || ho;
-        }
+      for (int o = Q; o < W; o <<= 1) val += __shfl_xor(val, o, 64);
+      if (lane == lead) {
+        unsafeAtomicAdd(d_table + run_off(s_lead * F, gmask) + f, val);
+        if (f == 0) mark_touched(touch, tbeg, s_lead * F);
       }
-      const bool tail = (i == 15) || (snext != s);
-      if (tail && s >= 0) {
-#pragma unroll
-        for (int k = 0; k < F; ++k) unsafeAtomicAdd(d_table + run_off(s * F, gmask) + k, v[k]);
-        mark_touched(touch, tbeg, s * F);
-      }
+    } else if (s >= 0) {
+      unsafeAtomicAdd(d_table + run_off(s * F, gmask) + f, val);
+      if (f == 0) mark_touched(touch, tbeg, s * F);
     }
   }
 }

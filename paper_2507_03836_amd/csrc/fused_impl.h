@@ -67,16 +67,17 @@ __device__ __forceinline__ void gather_block(const GridDev& g, const LevelDev* l
     }
 }
 
-// Scatter of a block's encoding gradient.  Levels flagged for the segmented
-// reduction are scattered by their own lane group (scatter_level_dedup); the
-// others are redistributed so that 2F consecutive lanes own one (sample,
-// level): pass k of 2F gives lane q the sample-level held by lane
-// k * (64 / 2F) + q / 2F, whose position and gradient arrive by shuffles.
+// Scatter of a block's encoding gradient, redistributed so that 2F
+// consecutive lanes own one (sample, level): pass k of 2F gives lane q the
+// sample-level held by lane k * (64 / 2F) + q / 2F, whose position and
+// gradient arrive by shuffles.  Levels flagged in g.dedup (sorted batches,
+// coarse levels) sum a corner across the samples of the pass first when they
+// all share its slot (scatter_level_lane_merge).
 template <int F, int INP, bool BRICK>
 __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* lv, float4 p,
                                               bool valid, const float (&dx)[INP / 16][4],
                                               float* d_table) {
-  const int lane = threadIdx.x & 63, grp = lane >> 4;
+  const int lane = threadIdx.x & 63;
   constexpr int LPB = 4 / F;
   constexpr int Q = 2 * F, PER = 64 / Q;
   const int r = lane % Q, e = r / F, f = r % F;
@@ -84,14 +85,6 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
   for (int a = 0; a < INP / 16; ++a)
 #pragma unroll
     for (int j = 0; j < LPB; ++j) {
-      const int l = (16 * a + 4 * grp) / F + j;  // this lane group's level
-      if (l < g.L && ((g.dedup >> l) & 1u)) {
-        float gl[F];
-#pragma unroll
-        for (int k = 0; k < F; ++k) gl[k] = dx[a][j * F + k];
-        scatter_level_dedup<F, BRICK>(lv[l], g.dir, g.active != 0, p, gl, valid, d_table, g.touch,
-                                      g.touch_begin, g.gmask);
-      }
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         const int m = k * PER + lane / Q;  // source lane (= sample-level)
@@ -110,9 +103,14 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
 #pragma unroll
         for (int q = 1; q < F; ++q)
           if (f == q) gval = gsrc[q];
-        if (ls < g.L && vs && !((g.dedup >> ls) & 1u))
-          scatter_level_lane<F, BRICK>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table,
-                                       g.touch, g.touch_begin, g.gmask);
+        if (ls < g.L) {
+          if ((g.dedup >> ls) & 1u)
+            scatter_level_lane_merge<F, BRICK>(lv[ls], g.dir, g.active != 0, ps, vs, e, f, gval,
+                                               d_table, g.touch, g.touch_begin, g.gmask);
+          else if (vs)
+            scatter_level_lane<F, BRICK>(lv[ls], g.dir, g.active != 0, ps, e, f, gval, d_table,
+                                         g.touch, g.touch_begin, g.gmask);
+        }
       }
     }
 }

@@ -5,9 +5,11 @@
 // The order changes neither the MSE loss (a mean) nor its gradient (a sum).
 //
 // Stable LSD radix sort, 4 passes of 8-bit digits over 1024-element tiles:
-// per-tile digit histograms -> one exclusive scan in digit-major order -> a
-// scatter in which each wave ranks equal digits with 8 ballots and waves are
-// ordered through LDS, so every pass is stable.
+// per-tile digit histograms -> an exclusive scan of every digit's row of tile
+// counts (one workgroup per digit) and the digits' totals -> a scatter that
+// adds the digit's base (the totals' exclusive prefix, formed in LDS by every
+// workgroup), in which each wave ranks equal digits with 8 ballots and waves
+// are ordered through LDS, so every pass is stable.
 #include "common.h"
 #include "kernels.h"
 
@@ -54,46 +56,67 @@ __global__ void __launch_bounds__(kTile)
   if (threadIdx.x < 256) hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of m entries in one workgroup.
-__global__ void __launch_bounds__(1024) scan_kernel(uint32_t* __restrict__ a, int64_t m) {
-  __shared__ uint32_t sh[17];
-  const int64_t per = (m + 1023) / 1024;
-  const int64_t b0 = threadIdx.x * per;
-  uint32_t s = 0;
-  for (int64_t i = 0; i < per; ++i)
-    if (b0 + i < m) s += a[b0 + i];
+// Exclusive scan of one digit's row of tile counts, hist[d * nb + 0 .. nb),
+// in place (workgroup d, 1024 threads, 1024 entries per round with a carry);
+// the row's total goes to tot[d].
+__global__ void __launch_bounds__(1024)
+    row_scan_kernel(uint32_t* __restrict__ hist, int64_t nb, uint32_t* __restrict__ tot) {
+  __shared__ uint32_t wsum[16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t x = s;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wid] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
+  uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  uint32_t carry = 0;
+  for (int64_t r0 = 0; r0 < nb; r0 += 1024) {
+    const int64_t i = r0 + threadIdx.x;
+    const uint32_t v = i < nb ? row[i] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
     for (int w = 0; w < 16; ++w) {
-      const uint32_t t = sh[w];
-      sh[w] = run;
-      run += t;
+      before += w < wid ? wsum[w] : 0u;
+      all += wsum[w];
     }
+    if (i < nb) row[i] = carry + before + x - v;
+    carry += all;
+    __syncthreads();  // wsum is rewritten by the next round
   }
-  __syncthreads();
-  uint32_t run = sh[wid] + x - s;
-  for (int64_t i = 0; i < per; ++i)
-    if (b0 + i < m) {
-      const uint32_t t = a[b0 + i];
-      a[b0 + i] = run;
-      run += t;
-    }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
 __global__ void __launch_bounds__(kTile)
     scatter_kernel(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n, int shift,
-                   int64_t nb, const uint32_t* __restrict__ off) {
+                   int64_t nb, const uint32_t* __restrict__ off, const uint32_t* __restrict__ tot) {
   __shared__ uint32_t cnt[kTile / 64][256];
+  __shared__ uint32_t base[256];
   for (int e = threadIdx.x; e < (kTile / 64) * 256; e += kTile) (&cnt[0][0])[e] = 0;
+  if (threadIdx.x < 64) {
+    // digit bases: the exclusive prefix of the 256 digit totals, 4 per lane
+    uint32_t t[4], s4 = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      t[j] = tot[4 * threadIdx.x + j];
+      s4 += t[j];
+    }
+    uint32_t x = s4;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if ((int)threadIdx.x >= o) x += y;
+    }
+    uint32_t run = x - s4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      base[4 * threadIdx.x + j] = run;
+      run += t[j];
+    }
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t i = blockIdx.x * (int64_t)kTile + threadIdx.x;
@@ -120,7 +143,7 @@ __global__ void __launch_bounds__(kTile)
   }
   __syncthreads();
   if (valid) {
-    const uint32_t p = off[d * nb + blockIdx.x] + cnt[w][d] + rank;
+    const uint32_t p = base[d] + off[d * nb + blockIdx.x] + cnt[w][d] + rank;
     kout[p] = k;
     vout[p] = vin[i];
   }
@@ -150,7 +173,7 @@ inline unsigned grid256(int64_t n) {
 
 size_t sort_ws_bytes(int64_t n) {
   const int64_t nb = (n + kTile - 1) / kTile;
-  return 4 * al(n * 4) + al(nb * 256 * 4) + al(n * 16) + al(n * 4);
+  return 4 * al(n * 4) + al(nb * 256 * 4) + al(256 * 4) + al(n * 16) + al(n * 4);
 }
 
 hipError_t launch_sort_samples(float* pos, float* target, int64_t n, void* ws, hipStream_t st) {
@@ -167,6 +190,8 @@ hipError_t launch_sort_samples(float* pos, float* target, int64_t n, void* ws, h
   p += al(n * 4);
   uint32_t* hist = reinterpret_cast<uint32_t*>(p);
   p += al(nb * 256 * 4);
+  uint32_t* tot = reinterpret_cast<uint32_t*>(p);
+  p += al(256 * 4);
   float4* pcopy = reinterpret_cast<float4*>(p);
   p += al(n * 16);
   float* tcopy = reinterpret_cast<float*>(p);
@@ -176,9 +201,9 @@ hipError_t launch_sort_samples(float* pos, float* target, int64_t n, void* ws, h
     const int shift = 8 * pass;
     hipLaunchKernelGGL(hist_kernel, dim3((unsigned)nb), dim3(kTile), 0, st, k0, n, shift, nb,
                        hist);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, hist, nb * 256);
+    hipLaunchKernelGGL(row_scan_kernel, dim3(256), dim3(1024), 0, st, hist, nb, tot);
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)nb), dim3(kTile), 0, st, k0, v0, k1, v1, n,
-                       shift, nb, hist);
+                       shift, nb, hist, tot);
     uint32_t* t = k0;
     k0 = k1;
     k1 = t;

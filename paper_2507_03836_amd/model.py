@@ -12,7 +12,8 @@ the packed MLP parameters, so one dense Adam launch covers every parameter.
 
 Mixed precision (precision="mixed"): the fused kernels read an FP16 copy of
 the tables that the Adam sweep rewrites from the FP32 master values (the
-shadow) and run the decoder on 16-bit MFMA (BF16 by default, `decoder`),
+shadow; table_reads="f32" reads the FP32 master instead and keeps no copy)
+and run the decoder on 16-bit MFMA (BF16 by default, `decoder`),
 accumulating in FP32; gradients, Adam moments and master weights stay FP32.
 The loss is scaled by a dynamic factor (start 2^16, doubled after
 `scale_window` clean steps, halved with the step skipped when a gradient is
@@ -79,13 +80,20 @@ class FHashModel:
                  init_seed: int = 3000, precision: str = "fp32", loss_scale: float = 2.0 ** 16,
                  scale_window: int = 2000, track_touched: bool = True, lazy: bool = False,
                  max_steps: int = 1 << 16, hash_bits: int = 0, decoder: str | None = None,
-                 paired_moments: bool = False, moments_with_params: bool = False):
+                 paired_moments: bool = False, moments_with_params: bool = False,
+                 table_reads: str | None = None):
         if precision not in ("fp32", "mixed"):
             raise ValueError(f"precision must be 'fp32' or 'mixed', not {precision!r}")
         if decoder is None:
             decoder = "bf16" if precision == "mixed" else "f32"
         if decoder not in ("f32", "f16", "bf16"):
             raise ValueError(f"decoder must be 'f32', 'f16' or 'bf16', not {decoder!r}")
+        if table_reads is None:
+            table_reads = "f16" if precision == "mixed" else "f32"
+        if table_reads not in ("f32", "f16") or (table_reads == "f16" and precision != "mixed"):
+            raise ValueError(f"table_reads must be 'f32', or 'f16' under mixed precision, "
+                             f"not {table_reads!r}")
+        self.table_reads = table_reads
         self.cfg = cfg
         self.precision = precision
         self.decoder = decoder
@@ -183,12 +191,13 @@ class FHashModel:
             self._touch_flags = torch.zeros((self.n_table + seg - 1) // seg,
                                             dtype=torch.uint8, device=self.device)
             self.touch = fl.touch_desc(self._touch_flags, begin, self.n_table)
-        if precision == "mixed":
+        if table_reads == "f16":
             self.shadow = torch.zeros(n_vec, dtype=torch.float16, device=self.device)
             if self.moments_with_params:
                 fl.fhash_cast(self.table, self.shadow[: self.n_table])
             else:
                 fl.fhash_cast(self.params, self.shadow)
+        if precision == "mixed":
             self.found_inf = torch.zeros(1, dtype=torch.int32, device=self.device)
             self.loss_scale = float(loss_scale)
             self.scale_window = int(scale_window)
@@ -349,7 +358,7 @@ class FHashModel:
         with the same results); gradients are reset.  The mixed path
         unscales, skips the update on a non-finite gradient and adapts the
         loss scale.  Returns whether the parameters were updated."""
-        if self.shadow is None:
+        if self.precision != "mixed":
             self.step_count += 1
             self._step(self.adam_desc(self.step_count, 1.0 if grad_scale is None else grad_scale),
                        None, found_inf)

@@ -112,8 +112,10 @@ __global__ void ret_atomic_max(uint32_t* __restrict__ buf, uint64_t nwords, int 
 // A deferred Adam update of random 16-float segments, 4 lanes per segment:
 // read p, g, m, v, write p, m, v and a zero g.  LINES == 3: p and g in arrays of
 // their own, m and v paired in one line; LINES == 2: p with m in one line, g
-// with v in another.  nseg segments of 256 bytes of state in buf.
-template <int LINES>
+// with v in another, the [g | v] array DELTA floats after the end of the
+// [p | m] array; LINES == 1: [p | m | g | v], the two lines of a segment
+// adjacent.  nseg segments of 256 bytes of state in buf (+ DELTA floats).
+template <int LINES, int DELTA = 0>
 __global__ void seg_update(float* __restrict__ buf, uint64_t nseg, int iters) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   const uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -127,11 +129,16 @@ __global__ void seg_update(float* __restrict__ buf, uint64_t nseg, int iters) {
       gp = buf + nseg * 16 + seg * 16 + 4 * sub;
       mp = buf + nseg * 32 + seg * 32 + 4 * sub;
       vp = mp + 16;
-    } else {
+    } else if (LINES == 2) {
       pp = buf + seg * 32 + 4 * sub;
       mp = pp + 16;
-      gp = buf + nseg * 32 + seg * 32 + 4 * sub;
+      gp = buf + nseg * 32 + DELTA + seg * 32 + 4 * sub;
       vp = gp + 16;
+    } else {
+      pp = buf + seg * 64 + 4 * sub;
+      mp = pp + 16;
+      gp = pp + 32;
+      vp = pp + 48;
     }
     f4 p = *(f4*)pp, g = *(f4*)gp, m = *(f4*)mp, v = *(f4*)vp;
     m = m * 0.9f + g;
@@ -157,8 +164,9 @@ int main() {
   const uint64_t nlines = bytes / 128;
   float* buf = nullptr;
   float* sink = nullptr;
-  if (!ok(hipMalloc(&buf, bytes), "hipMalloc") || !ok(hipMalloc(&sink, 16), "hipMalloc") ||
-      !ok(hipMemset(buf, 0, bytes), "hipMemset"))
+  const uint64_t slack = 1ull << 20;  // room for the shifted [g | v] array
+  if (!ok(hipMalloc(&buf, bytes + slack), "hipMalloc") || !ok(hipMalloc(&sink, 16), "hipMalloc") ||
+      !ok(hipMemset(buf, 0, bytes + slack), "hipMemset"))
     return 1;
   hipEvent_t a, b;
   if (!ok(hipEventCreate(&a), "event") || !ok(hipEventCreate(&b), "event")) return 1;
@@ -264,22 +272,32 @@ int main() {
     }
     // the deferred update's segment traffic in two state layouts
     const uint64_t nseg = bytes / 256;
-    for (int lines : {3, 2}) {
+    const char* names[5] = {"p | g | m+v lines", "p+m | g+v lines",
+                            "p+m | g+v lines, g+v array 4 KiB further",
+                            "p+m | g+v lines, g+v array 96 KiB further",
+                            "p+m+g+v, the two lines adjacent"};
+    for (int kind = 0; kind < 5; ++kind) {
       float ms = 0.f;
       for (int rep = 0; rep < 2; ++rep) {
         hipEventRecord(a);
-        if (lines == 3)
+        if (kind == 0)
           hipLaunchKernelGGL(seg_update<3>, dim3(blocks), dim3(256), 0, 0, buf, nseg, it2);
-        else
+        else if (kind == 1)
           hipLaunchKernelGGL(seg_update<2>, dim3(blocks), dim3(256), 0, 0, buf, nseg, it2);
+        else if (kind == 2)
+          hipLaunchKernelGGL((seg_update<2, 1024>), dim3(blocks), dim3(256), 0, 0, buf, nseg, it2);
+        else if (kind == 3)
+          hipLaunchKernelGGL((seg_update<2, 24576>), dim3(blocks), dim3(256), 0, 0, buf, nseg,
+                             it2);
+        else
+          hipLaunchKernelGGL(seg_update<1>, dim3(blocks), dim3(256), 0, 0, buf, nseg, it2);
         hipEventRecord(b);
         if (!ok(hipEventSynchronize(b), "kernel")) return 1;
         hipEventElapsedTime(&ms, a, b);
       }
       std::printf("segment update (p, g, m, v read; p, m, v, g written), %s: %.2f G "
                   "segments/s\n",
-                  lines == 3 ? "p | g | m+v lines" : "p+m | g+v lines",
-                  threads / 4.0 * it2 / ms / 1e6);
+                  names[kind], threads / 4.0 * it2 / ms / 1e6);
       std::fflush(stdout);
     }
   }

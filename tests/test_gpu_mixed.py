@@ -226,3 +226,36 @@ def test_fp16_decoder_forward_within_rounding_bound(fl, width):
     rel = float(err.max() / np.abs(y64[:, 0]).max())
     print(f"\nFP16 decoder {width}: max abs err {err.max():.3e} (rel to max|y| {rel:.3e}), "
           f"bound median {np.median(e):.3e}")
+
+
+@pytest.mark.parametrize("lazy", [False, True])
+def test_mixed_fp32_table_reads_match_fp32_path(fl, lazy):
+    """table_reads="f32": the mixed path keeps no FP16 copy and gathers the FP32
+    master; with the FP32 decoder its steps equal the FP32 path's up to the
+    summation order of the atomics (the loss scale is a power of two, so the
+    scaling and unscaling are exact)."""
+    f, mask = tiny_volume()
+    g = O.Grid(np.array(TINY_RES), 2, mask)
+    table0 = synth.table_init(g.total_slots, 2)
+    mlp0 = synth.mlp_init([8, 32, 32, 1], seed=29)
+    kw = dict(lazy=lazy, moments_with_params=lazy, max_steps=8)
+    _, a = _model(mask, table0, mlp0, "mixed", table_reads="f32", **kw)
+    _, b = _model(mask, table0, mlp0, "fp32", **kw)
+    assert a.shadow is None and a.table_reads == "f32"
+    n = 4096
+    pos = torch.empty(n, 4, device="cuda")
+    tgt = torch.empty(n, device="cuda")
+    for k in range(3):
+        fl.fhash_sample(2003, k + 1, n, None, f.size, _dims(mask), torch.from_numpy(f).cuda(),
+                        pos, tgt)
+        for mdl in (a, b):
+            mdl.fwd_bwd(pos, tgt)
+            assert mdl.optimizer_step()
+    for mdl in (a, b):
+        mdl.flush()
+    assert a.skipped == 0 and a.step_count == b.step_count == 3
+    for x, y in ((a.flat_params(), b.flat_params()), (a.table, b.table),
+                 (a.mlp_params, b.mlp_params)):
+        assert torch.allclose(x, y, rtol=1e-5, atol=1e-7)
+    with pytest.raises(ValueError):
+        _model(mask, table0, mlp0, "fp32", table_reads="f16")

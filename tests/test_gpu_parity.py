@@ -489,7 +489,7 @@ def test_one_training_step_tiny(fl, tiny):
     assert abs(model.loss_sum.item() - L * n) <= 1e-4 * L * n
 
 
-# ----------------------------------------------------------------------------- sort + segmented scatter
+# ----------------------------------------------------------------------------- sort + merged scatter
 def _morton_keys(pos):
     q = np.minimum((pos.astype(np.float32) * np.float32(256.0)).astype(np.int64), 255)
     q = np.maximum(q, 0)
@@ -518,14 +518,20 @@ def test_sort_samples_is_a_morton_ordered_permutation(fl):
     assert (np.diff(idx)[same] > 0).all()
 
 
-def test_fused_train_sorted_segmented_scatter(fl, tiny):
+@pytest.mark.parametrize("F,hidden", [(2, [32, 32]), (1, [64, 64]), (4, [64, 64, 64])])
+def test_fused_train_sorted_merged_scatter(fl, tiny, F, hidden):
+    """Sorted batch with FHASH_SAMPLES_SORTED: at the coarse levels a corner
+    that every sample of a scatter pass hits on one slot is summed across the
+    pass before one atomic (64 lanes of one level at F = 2 and 4, 32 at F = 1);
+    the same gradients as the oracle up to FP32 summation order.  The batch
+    ends in a ragged block (n = 16 k + 9)."""
     f, mask = tiny
-    F, width = 2, [8, 32, 32, 1]
+    width = [len(TINY_RES) * F] + hidden + [1]
     idx, counts, dir_t, _ = _build(fl, TINY_RES, F, mask)
     g = O.Grid(np.array(TINY_RES), F, mask)
-    rng = np.random.default_rng(21)
+    rng = np.random.default_rng(21 + F)
     table = rng.uniform(-1, 1, size=(g.total_slots, F)).astype(np.float32)
-    params = _mlp_params(width, 22)
+    params = _mlp_params(width, 22 + F)
     n = 4096 + 9
     pos0, tgt0 = O.sample_batch(5, 3, n, f, coreset_ids(mask))
     pd, td = torch.from_numpy(pos0).cuda(), torch.from_numpy(tgt0).cuda()

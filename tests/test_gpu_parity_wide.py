@@ -6,7 +6,7 @@ the FP64 oracle to enumerate every level, and the finest levels span more than
 64 vertices in x so vertex pairs straddle directory words.
 
 Every fused entry point (forward, backward with a given dy, forward + MSE +
-backward, the segmented-reduction path for sorted batches, FP16 table reads and
+backward, the merged scatter of sorted batches, FP16 table reads and
 the FP16-MFMA inference decoder) is compared element by element with the
 oracle at |gpu - oracle| <= 1e-5 * mag + 1e-12 (mag = the oracle's sum of term
 magnitudes); the FP16 decoder against its layer-by-layer rounding bound.  The
@@ -166,8 +166,8 @@ def test_fused_wide_against_oracle(fl, vol, res, F, hidden, tdt):
 
 
 def test_fused_train_wide_sorted_batch(fl, vol):
-    """Coreset draws sorted by fhash_sort_samples, then the segmented reduction
-    ahead of the atomics, at 32 inputs and three hidden layers."""
+    """Coreset draws sorted by fhash_sort_samples, then the merge of equal
+    slots ahead of the atomics, at 32 inputs and three hidden layers."""
     f, mask = vol
     idx, dir_t, g, table = _setup(fl, vol, WIDE16, 2, "f32")
     width = [32, 64, 64, 64, 1]
