@@ -173,6 +173,10 @@ def parse():
                          "4D Morton key before the fused step (sorted, the lanes of one "
                          "scatter instruction that add into one 64-byte chunk share one "
                          "atomic request, and the gathers share lines)")
+    ap.add_argument("--no-coarse-lds", dest="coarse_lds", action="store_false",
+                    help="add the coarse levels' encoding gradient in the fused kernel instead of "
+                         "summing it in LDS per chunk of the batch before its atomics "
+                         "(FHASH_COARSE_LDS, the default)")
     ap.add_argument("--sort-reduce", action="store_true",
                     help="with sorted batches: at the coarse levels, sum a corner across the "
                          "samples of a scatter instruction before one atomic when they all "
@@ -866,7 +870,7 @@ ATOMIC_CEILING_GPS = 16.8
 # hashed in _fused_src_md5(), the optimiser state layout, the batch order, the
 # table reads and the decoder type are those the counters were taken with.
 FUSED_TRAFFIC = {"bytes": 21336169941, "raw_bytes": 13301701801, "moments": "with-params",
-                 "sorted": True, "table_reads": "f32", "decoder": "f16",
+                 "sorted": True, "table_reads": "f32", "decoder": "f16", "coarse_lds": False,
                  "source_md5": "0a33c209eb5d9354ceeb82ad197734f8"}
 
 
@@ -1055,6 +1059,17 @@ def _to_psnr(model, step, k_done, t_first, ppos, ptgt, target, eval_every, max_s
             "steps": reached[0] if reached else None,
             "seconds": reached[1] if reached else None,
             "final_psnr_db": hist[-1][2], "history": hist}
+
+
+def coarse_levels(res, n):
+    """Levels that FHASH_COARSE_LDS sends through the LDS scatter: from the
+    coarsest on, those with at most one cell per sample of the batch."""
+    lc = 0
+    for r in res:
+        if (r[0] - 1) * (r[1] - 1) * (r[2] - 1) * (r[3] - 1) > n:
+            break
+        lc += 1
+    return lc
 
 
 def compulsory_lines(model, pos, line=128):
@@ -1264,6 +1279,7 @@ def headline_bench(args):
         model = FHashModel(cfg, gen["bits"], dims, init_seed=3003, precision=prec, lazy=True,
                            **_layout_kw(args), **_reads_kw(args, prec),
                            max_steps=args.max_steps + args.warmup + args.steps + 8)
+        model.coarse_lds = args.coarse_lds
         r, step, t_first = _train_timed(model, gen, dims, B, args.steps, args.warmup, 2003, pos,
                                         tgt, sort=args.sort, sort_reduce=args.sort_reduce)
         log(f"[headline] {prec}: {r['ms_per_step']:.2f} ms/step ({r['samples_per_s'] / 1e6:.1f}"
@@ -1315,13 +1331,19 @@ def headline_bench(args):
     # FP16 (FP32) gather 1024 (2048) + FP32 scatter read-modify-write 2048 + 20 B I/O
     alg = (3092 if reads16 else 4116) * B
     comp = mx["compulsory"]["bytes"]
-    areq = mx["compulsory"]["atomic_requests"]
+    # with FHASH_COARSE_LDS the fused kernel issues the requests of the levels
+    # with more than one cell per sample only; the coarse levels' requests are
+    # replaced by one per touched vertex row segment of a chunk's LDS box
+    lc = coarse_levels(cfg.res, B) if args.coarse_lds else 0
+    areq = int(sum(mx["compulsory"]["atomic_requests_per_level"][lc:]))
     same = (FUSED_TRAFFIC["source_md5"] == _fused_src_md5() and
+            args.coarse_lds == FUSED_TRAFFIC["coarse_lds"] and
             mx["table_reads"] == FUSED_TRAFFIC["table_reads"] and
             mx["decoder"] == FUSED_TRAFFIC["decoder"] and
             args.moments == FUSED_TRAFFIC["moments"] and args.sort == FUSED_TRAFFIC["sorted"])
     roof = {"kernel": "fused_kernel<TRAIN, F=2, " + ("FP16" if reads16 else "FP32")
-                      + " table, 32-64-64-64-1, " + mx["decoder"].upper() + " decoder>",
+                      + " table, 32-64-64-64-1, " + mx["decoder"].upper() + " decoder>"
+                      + (f" + coarse_scatter_kernel (levels 0-{lc - 1})" if lc else ""),
             "bound": "hbm", "achieved": alg / (fused_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": alg / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "traffic": FUSED_TRAFFIC["bytes"] if same else None,
@@ -1331,6 +1353,7 @@ def headline_bench(args):
             "compulsory_frac": comp / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "compulsory_detail": mx["compulsory"],
             # what bounds the kernel: the scatter's memory-side atomic requests
+            "coarse_lds_levels": lc,
             "atomic_requests": areq, "atomic_G_per_s": areq / (fused_ms * 1e-3) / 1e9,
             "atomic_ceiling_G_per_s": ATOMIC_CEILING_GPS,
             "atomic_frac": areq / (fused_ms * 1e-3) / 1e9 / ATOMIC_CEILING_GPS}
@@ -1407,6 +1430,7 @@ def main():
                        lazy=args.optimizer == "lazy",
                        **_layout_kw(args, args.optimizer == "lazy"),
                        max_steps=max(args.max_steps, args.warmup + args.steps) + 64)
+    model.coarse_lds = args.coarse_lds
     torch.cuda.synchronize()
     dense = sum(int(np.prod(r)) for r in res)
     log(f"[bench] index built in {time.time() - t0:.1f} s: {model.rows} active vertices of "

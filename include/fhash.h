@@ -280,10 +280,21 @@ int fhash_fused_fwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
  * of 16 floats separated by 16-float gaps (gradient value i at
  * d_table[i + 16 floor(i / 16)]; the gradient array of the optimiser layout
  * FHASH_MOMENTS_WITH_PARAMS below); the table read is independent of it
- * (table_dt).  Other bits: FHASH_EINVAL.  touch: NULL, or segment flags of
- * d_table to set, by logical float index (see fhash_touch). */
+ * (table_dt).  FHASH_COARSE_LDS: the levels with at most one cell per
+ * sample of the batch (0 .. lc - 1, coarsest first; row-ordered indexes only,
+ * ignored on brick-ordered ones) are not added by the fused kernel: their
+ * encoding gradient goes to the workspace, and a second kernel on the same
+ * stream sums it per chunk of 2048 consecutive samples into an LDS image of
+ * the vertex box the chunk touches and adds that box with one atomic per
+ * touched vertex and feature (a chunk whose box exceeds 16000 floats is taken
+ * in 4 parts, and a part that still exceeds it adds its samples directly).
+ * Sorted batches give compact boxes; the results are the same up to FP32
+ * summation order.  The workspace then grows by lc x n x F floats (the size
+ * query includes it).  Other bits: FHASH_EINVAL.  touch: NULL, or segment
+ * flags of d_table to set, by logical float index (see fhash_touch). */
 #define FHASH_SAMPLES_SORTED 1u
 #define FHASH_GRAD_PAIRED 2u
+#define FHASH_COARSE_LDS 4u
 int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos, int64_t n,
                     const void* table, fhash_dtype table_dt, const float* params,
                     const void* shadow, const float* dy, float* d_table, float* d_params,
@@ -307,7 +318,8 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
  * without ordering) race and give wrong d_params.  Otherwise the arguments,
  * results and errors are those of fhash_fused_train; FHASH_ENOMEM if the
  * partials of a launch would exceed the array (never for the decoders the
- * fused path is built for). */
+ * fused path is built for); FHASH_EINVAL for FHASH_COARSE_LDS, whose encoding
+ * gradient needs a workspace. */
 #define FHASH_STATIC_SCRATCH_BYTES 10813440
 int fhash_fused_train_static(const fhash_index* idx, const fhash_mlp_desc* mlp,
                              const float* pos, const float* target, int64_t n, const void* table,

@@ -392,7 +392,7 @@ def fhash_fused_fwd(idx: Index, mlp: MlpDesc, pos, n, table, params, y, shadow=N
            "fhash_fused_fwd")
 
 
-SAMPLES_SORTED, GRAD_PAIRED = 1, 2
+SAMPLES_SORTED, GRAD_PAIRED, COARSE_LDS = 1, 2, 4
 
 
 def fhash_fused_bwd(idx: Index, mlp: MlpDesc, pos, n, table, params, dy, d_table, d_params,

@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libfhash.so")
 SOURCES = ["fused_train.hip", "fused_train16.hip", "fused_bwd.hip", "fused_bwd16.hip", "fused.hip",
            "fused_fwd16.hip", "mlp.hip", "api.cpp",
            "index.hip",
-           "encode.hip", "optim.hip", "lazy.hip", "sampler.hip", "render.hip", "sort.hip", "coreset.hip", "static_ws.hip"]
+           "encode.hip", "optim.hip", "lazy.hip", "sampler.hip", "render.hip", "sort.hip", "coreset.hip", "static_ws.hip",
+           "coarse.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FHASH_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

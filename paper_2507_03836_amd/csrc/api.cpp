@@ -94,7 +94,7 @@ fhash_dtype table_view(fhash_dtype dt, fh::GridDev* g) {
 // Flags of the backward calls; FHASH_GRAD_PAIRED sets the gradient's run mask
 // (g may be NULL: check only).
 int apply_bwd_flags(uint32_t flags, fh::GridDev* g) {
-  if ((flags & ~(FHASH_SAMPLES_SORTED | FHASH_GRAD_PAIRED)) != 0)
+  if ((flags & ~(FHASH_SAMPLES_SORTED | FHASH_GRAD_PAIRED | FHASH_COARSE_LDS)) != 0)
     return fail(FHASH_EINVAL, "unknown flags 0x%x", (unsigned)flags);
   if (g != nullptr) g->gmask = (flags & FHASH_GRAD_PAIRED) ? ~(int64_t)15 : 0;
   return FHASH_OK;
@@ -372,6 +372,35 @@ static uint32_t dedup_mask(const fhash_index* idx, int64_t n, uint32_t flags) {
   return m;
 }
 
+// FHASH_COARSE_LDS: levels 0 .. lc - 1, the coarse levels with at most one
+// cell per sample of the batch, go through the LDS scatter (row order only).
+static int coarse_levels(const fhash_index* idx, int64_t n, uint32_t flags) {
+  if (!(flags & FHASH_COARSE_LDS) || idx->grid.layout != FHASH_LAYOUT_ROWS) return 0;
+  int lc = 0;
+  for (int l = 0; l < idx->grid.n_levels; ++l) {
+    const int32_t* r = idx->grid.res[l];
+    const double cells = (double)(r[0] - 1) * (r[1] - 1) * (r[2] - 1) * (r[3] - 1);
+    if (cells > (double)n) break;
+    lc = l + 1;
+  }
+  return lc;
+}
+
+// Workspace of a fused backward: the decoder-gradient partials, then the
+// coarse levels' encoding gradient (lc levels x n samples x F floats).
+static size_t fused_bwd_ws(int64_t n, int64_t P, int lc, int F) {
+  const size_t part = (fh::fused_ws_bytes(n, P) + 255) & ~(size_t)255;
+  return part + (size_t)lc * (size_t)n * (size_t)F * sizeof(float);
+}
+
+static void set_coarse(fh::GridDev* g, int lc, int64_t n, int64_t P, void* ws) {
+  g->coarse = lc;
+  g->nsamp = n;
+  g->dxc = lc > 0 ? reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                             ((fh::fused_ws_bytes(n, P) + 255) & ~(size_t)255))
+                  : nullptr;
+}
+
 static int check_fused(const fhash_index* idx, const fhash_mlp_desc* mlp, const float* pos,
                        int64_t n, const void* table, fhash_dtype tdt, const float* params,
                        int* H, int* NH, bool backward) {
@@ -437,8 +466,9 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
   if (rc) return rc;
   if ((rc = apply_bwd_flags(flags, nullptr))) return rc;
   const int64_t P = num_params(mlp);
+  const int lc = coarse_levels(idx, n, flags);
   bool query;
-  rc = ws_check(ws, ws_bytes, fh::fused_ws_bytes(n, P), &query);
+  rc = ws_check(ws, ws_bytes, fused_bwd_ws(n, P, lc, idx->grid.n_features), &query);
   if (rc || query) return rc;
   if (n == 0) return FHASH_OK;
   if (dy == nullptr || d_table == nullptr || d_params == nullptr)
@@ -447,6 +477,7 @@ int fhash_fused_bwd(const fhash_index* idx, const fhash_mlp_desc* mlp, const flo
   fh::make_grid_dev(idx, &g);
   if ((rc = apply_bwd_flags(flags, &g))) return rc;
   g.dedup = dedup_mask(idx, n, flags);
+  set_coarse(&g, lc, n, P, ws);
   if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
   const fhash_dtype tdt = table_view(table_dt, &g);
   return hip_status(fh::launch_fused_bwd(g, H, NH, mlp->compute_dt, pos, n, table, tdt,
@@ -465,8 +496,9 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
   if (rc) return rc;
   if ((rc = apply_bwd_flags(flags, nullptr))) return rc;
   const int64_t P = num_params(mlp);
+  const int lc = coarse_levels(idx, n, flags);
   bool query;
-  rc = ws_check(ws, ws_bytes, fh::fused_ws_bytes(n, P), &query);
+  rc = ws_check(ws, ws_bytes, fused_bwd_ws(n, P, lc, idx->grid.n_features), &query);
   if (rc || query) return rc;
   if (n == 0) return FHASH_OK;
   if (target == nullptr || d_table == nullptr || d_params == nullptr)
@@ -475,6 +507,7 @@ int fhash_fused_train(const fhash_index* idx, const fhash_mlp_desc* mlp, const f
   fh::make_grid_dev(idx, &g);
   if ((rc = apply_bwd_flags(flags, &g))) return rc;
   g.dedup = dedup_mask(idx, n, flags);
+  set_coarse(&g, lc, n, P, ws);
   if ((rc = apply_touch(touch, total_rows(idx) * idx->grid.n_features, &g))) return rc;
   const fhash_dtype tdt = table_view(table_dt, &g);
   return hip_status(fh::launch_fused_train(g, H, NH, mlp->compute_dt, pos, target, n, table,
@@ -493,6 +526,8 @@ int fhash_fused_train_static(const fhash_index* idx, const fhash_mlp_desc* mlp,
   int rc = check_fused(idx, mlp, pos, n, table, table_dt, params, &H, &NH, true);
   if (rc) return rc;
   if ((rc = apply_bwd_flags(flags, nullptr))) return rc;
+  if (flags & FHASH_COARSE_LDS)
+    return fail(FHASH_EINVAL, "FHASH_COARSE_LDS needs the workspace of fhash_fused_train");
   if (n == 0) return FHASH_OK;
   if (target == nullptr || d_table == nullptr || d_params == nullptr)
     return fail(FHASH_EINVAL, "NULL pointer");

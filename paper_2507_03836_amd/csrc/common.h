@@ -32,6 +32,11 @@ struct GridDev {
   // run masks of the table read and of the table gradient (run_off): 0, dense;
   // ~15, the paired layout (16 values, then 16 floats of the other array)
   int64_t tmask, gmask;
+  // levels 0 .. coarse - 1: the fused backward leaves their encoding gradient
+  // in dxc ([level][sample][feature], nsamp samples) for the LDS scatter
+  int32_t coarse;
+  float* dxc;
+  int64_t nsamp;
 };
 
 // Float offset of element i of a vector stored in runs of 16 values separated
@@ -52,6 +57,9 @@ inline void make_grid_dev(const fhash_index* idx, GridDev* g) {
   g->touch_begin = 0;
   g->tmask = 0;
   g->gmask = 0;
+  g->coarse = 0;
+  g->dxc = nullptr;
+  g->nsamp = 0;
   for (int l = 0; l < FHASH_MAX_LEVELS; ++l) {
     LevelDev& d = g->lv[l];
     if (l < gd.n_levels) {

@@ -72,15 +72,29 @@ __device__ __forceinline__ void gather_block(const GridDev& g, const LevelDev* l
 // sample-level held by lane k * (64 / 2F) + q / 2F, whose position and
 // gradient arrive by shuffles.  Levels flagged in g.dedup (sorted batches,
 // coarse levels) sum a corner across the samples of the pass first when they
-// all share its slot (scatter_level_lane_merge).
+// all share its slot (scatter_level_lane_merge).  Levels below g.coarse are
+// not added here: their gradient goes to g.dxc for the LDS scatter
+// (coarse.hip).
 template <int F, int INP, bool BRICK>
 __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* lv, float4 p,
-                                              bool valid, const float (&dx)[INP / 16][4],
-                                              float* d_table) {
-  const int lane = threadIdx.x & 63;
+                                              bool valid, int64_t smp,
+                                              const float (&dx)[INP / 16][4], float* d_table) {
+  const int lane = threadIdx.x & 63, grp = lane >> 4;
   constexpr int LPB = 4 / F;
   constexpr int Q = 2 * F, PER = 64 / Q;
   const int r = lane % Q, e = r / F, f = r % F;
+  if (g.coarse > 0 && valid) {
+#pragma unroll
+    for (int a = 0; a < INP / 16; ++a)
+#pragma unroll
+      for (int j = 0; j < LPB; ++j) {
+        const int l = (16 * a + 4 * grp) / F + j;  // this lane group's level
+        if (l < g.coarse)
+#pragma unroll
+          for (int q = 0; q < F; ++q)
+            g.dxc[((int64_t)l * g.nsamp + smp) * F + q] = dx[a][j * F + q];
+      }
+  }
 #pragma unroll
   for (int a = 0; a < INP / 16; ++a)
 #pragma unroll
@@ -103,7 +117,7 @@ __device__ __forceinline__ void scatter_block(const GridDev& g, const LevelDev* 
 #pragma unroll
         for (int q = 1; q < F; ++q)
           if (f == q) gval = gsrc[q];
-        if (ls < g.L) {
+        if (ls < g.L && ls >= g.coarse) {
           if ((g.dedup >> ls) & 1u)
             scatter_level_lane_merge<F, BRICK>(lv[ls], g.dir, g.active != 0, ps, vs, e, f, gval,
                                                d_table, g.touch, g.touch_begin, g.gmask);
@@ -192,7 +206,7 @@ __global__ void __launch_bounds__(64 * waves_per_block(MODE))
       else
         mlp_block_bwd_t<INP, H, NH, D>(lds, grad, reinterpret_cast<D*>(scratch), xb, hs, dyv,
                                        dxb);
-      scatter_block<F, INP, BRICK>(g, lv, p, valid, dxb, A.d_table);
+      scatter_block<F, INP, BRICK>(g, lv, p, valid, smp, dxb, A.d_table);
     }
   }
   if constexpr (!FWD) {
@@ -243,6 +257,10 @@ hipError_t fused_t(const GridDev& g, FusedArgs A, float* d_params, hipStream_t s
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || is_forward(MODE)) return e;
+  if (g.coarse > 0) {
+    e = launch_coarse_scatter(g, reinterpret_cast<const float*>(A.pos), A.n, A.d_table, st);
+    if (e != hipSuccess) return e;
+  }
   return launch_reduce_partials(A.part, nb, A.P, d_params, st);
 }
 

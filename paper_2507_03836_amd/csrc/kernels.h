@@ -73,6 +73,9 @@ hipError_t static_scratch(void** ptr);
 hipError_t launch_adam(const fhash_adam_desc* o, float* p, float* g, float* m, float* v,
                        void* shadow, fhash_dtype sdt, int64_t n, int64_t first,
                        const int32_t* found_inf, const fhash_touch* touch, hipStream_t st);
+// coarse.hip: the LDS scatter of levels 0 .. g.coarse - 1 from g.dxc
+hipError_t launch_coarse_scatter(const GridDev& g, const float* pos, int64_t n, float* d_table,
+                                 hipStream_t st);
 hipError_t launch_reduce_partials(const float* part, int64_t nwav, int64_t P, float* d_params,
                                   hipStream_t st);
 hipError_t launch_check_finite(const float* g, int64_t n, int32_t* found, hipStream_t st);

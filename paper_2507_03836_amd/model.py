@@ -173,6 +173,9 @@ class FHashModel:
         self.step_count = 0
         self.loss_sum = torch.zeros(1, dtype=torch.float64, device=self.device)
         self._ws = None
+        # FHASH_COARSE_LDS: the coarse levels' gradient summed in LDS per chunk
+        # of the batch before its atomics
+        self.coarse_lds = False
         self.shadow = None
         self.loss_scale = 1.0
         self.touch = None
@@ -350,7 +353,8 @@ class FHashModel:
         self._ws = fl.fhash_fused_train(self.index, self.mlp, pos, target, n, self.read_table,
                                         self.mlp_params, d_table, self.d_mlp,
                                         self.loss_sum, s, ws=self._ws,
-                                        flags=(fl.SAMPLES_SORTED if sorted_batch else 0) | gflag,
+                                        flags=(fl.SAMPLES_SORTED if sorted_batch else 0) | gflag
+                                        | (fl.COARSE_LDS if self.coarse_lds else 0),
                                         touch=self.touch)
 
     def optimizer_step(self, grad_scale: float | None = None, found_inf=None) -> bool:

@@ -553,3 +553,62 @@ def test_fused_train_sorted_merged_scatter(fl, tiny, F, hidden):
                          torch.from_numpy(params).cuda(), dt, dp, flags=fl.SAMPLES_SORTED)
     _assert_close(dt.cpu().numpy(), dt_ref, dtm, "sorted fused_train dtable")
     _assert_close(dp.cpu().numpy(), dp_ref, dpm, "sorted fused_train dparams")
+
+
+COARSE_RES = [[4, 4, 4, 2], [8, 8, 8, 3], [24, 24, 24, 2], [32, 32, 32, 8]]
+
+
+@pytest.mark.parametrize("sort", [True, False])
+@pytest.mark.parametrize("F,hidden", [(2, [32, 32]), (1, [64, 64]), (4, [64, 64, 64])])
+def test_fused_coarse_lds_scatter(fl, tiny, F, hidden, sort):
+    """FHASH_COARSE_LDS: the levels with at most one cell per sample (here
+    levels 0-2 of 4) leave the fused kernel through the workspace and are
+    summed per chunk of 2048 samples in LDS before their atomics.  Level 2's
+    vertex box (24^3 x 2 vertices) does not fit the LDS image for a chunk of
+    unsorted draws, nor at F = 4, so those chunks take the direct path; the
+    batch ends in a ragged chunk.  fused_train and fused_bwd against the FP64
+    oracle at the FP32 tolerance."""
+    f, mask = tiny
+    width = [len(COARSE_RES) * F] + hidden + [1]
+    idx, counts, dir_t, _ = _build(fl, COARSE_RES, F, mask)
+    g = O.Grid(np.array(COARSE_RES), F, mask)
+    rng = np.random.default_rng(41 + F)
+    table = rng.uniform(-1, 1, size=(g.total_slots, F)).astype(np.float32)
+    params = _mlp_params(width, 42 + F)
+    n = 8 * 2048 + 9
+    pos0, tgt0 = O.sample_batch(7, 2, n, f, coreset_ids(mask))
+    pd, td = torch.from_numpy(pos0).cuda(), torch.from_numpy(tgt0).cuda()
+    if sort:
+        fl.fhash_sort_samples(pd, td, n)
+    pos, tgt = pd.cpu().numpy(), td.cpu().numpy()
+    enc, emag = O.encode_fwd(g, pos, table.astype(np.float64))
+    y, acts, ymag = O.mlp_fwd(width, params.astype(np.float64), enc, x_mag=emag)
+    L, dy = O.mse(y[:, 0], tgt.astype(np.float64))
+    dym = 2.0 * (ymag[:, 0] + np.abs(tgt)) / n
+    dp_ref, denc, dpm, dencm = O.mlp_bwd(width, params.astype(np.float64), acts,
+                                         dy.reshape(-1, 1), n, dy_mag=dym.reshape(-1, 1),
+                                         x_mag=emag)
+    dt_ref, _ = O.encode_bwd(g, pos, denc)
+    _, dtm = O.encode_bwd(g, pos, dencm)
+    mlp = fl.mlp_desc(width)
+    tab_d, prm = torch.from_numpy(table).cuda(), torch.from_numpy(params).cuda()
+    dt = torch.zeros(g.total_slots, F, device="cuda")
+    dp = torch.zeros(len(params), device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fl.fhash_fused_train(idx, mlp, pd, td, n, tab_d, prm, dt, dp, loss, flags=fl.COARSE_LDS)
+    _assert_close(dt.cpu().numpy(), dt_ref, dtm, "coarse-LDS fused_train dtable")
+    _assert_close(dp.cpu().numpy(), dp_ref, dpm, "coarse-LDS fused_train dparams")
+    lmag = float(((ymag[:, 0] + np.abs(tgt)) * np.abs(y[:, 0] - tgt)).sum()) * 2
+    assert abs(loss.item() - L * n) <= RTOL * lmag + ATOL
+    # the same through fhash_fused_bwd with a given output gradient
+    dyg = rng.normal(size=n).astype(np.float32)
+    dp_ref, denc, dpm, dencm = O.mlp_bwd(width, params.astype(np.float64), acts,
+                                         dyg.astype(np.float64).reshape(-1, 1), n, x_mag=emag)
+    dt_ref, _ = O.encode_bwd(g, pos, denc)
+    _, dtm = O.encode_bwd(g, pos, dencm)
+    dt.zero_()
+    dp.zero_()
+    fl.fhash_fused_bwd(idx, mlp, pd, n, tab_d, prm, torch.from_numpy(dyg).cuda(), dt, dp,
+                       flags=fl.COARSE_LDS)
+    _assert_close(dt.cpu().numpy(), dt_ref, dtm, "coarse-LDS fused_bwd dtable")
+    _assert_close(dp.cpu().numpy(), dp_ref, dpm, "coarse-LDS fused_bwd dparams")

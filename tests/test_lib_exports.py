@@ -199,3 +199,34 @@ def test_moments_with_params_checked_before_any_launch():
     lz.moments = 3
     assert L.fhash_lazy_flush(ctypes.byref(lz), p, g, ok_m, ok_v, None, fl.F16,
                               None) == fl.EINVAL
+
+
+def test_coarse_lds_flag_checked_before_any_launch():
+    """FHASH_COARSE_LDS is a known flag of the workspace calls (its workspace
+    query grows by levels x n x F floats) and is refused by the call without a
+    workspace; an unknown bit is refused."""
+    L = fl.lib()
+    res = [[4, 4, 4, 2], [8, 8, 8, 3], [16, 16, 16, 5]]
+    idx, _ = fl.fhash_hash_index(fl.grid_desc(res, 2), 9)
+    mlp = fl.mlp_desc([6, 32, 32, 1])
+    fake = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: validation or the query ends first
+    n = 4096
+
+    def query(flags):
+        nb = ctypes.c_size_t(0)
+        rc = L.fhash_fused_train(ctypes.byref(idx), ctypes.byref(mlp), fake, fake, n, fake,
+                                 fl.F32, fake, None, ctypes.c_float(1.0), fake, fake, None,
+                                 ctypes.c_uint32(flags), None, None, ctypes.byref(nb), None)
+        return rc, nb.value
+
+    rc0, base = query(0)
+    rc1, grown = query(fl.COARSE_LDS)
+    assert rc0 == fl.OK and rc1 == fl.OK
+    # levels 0 and 1 have at most n cells (27 and 686), level 2 has 13,500
+    assert grown - ((base + 255) // 256 * 256) == 2 * n * 2 * 4
+    rc = L.fhash_fused_train_static(ctypes.byref(idx), ctypes.byref(mlp), fake, fake, n, fake,
+                                    fl.F32, fake, None, ctypes.c_float(1.0), fake, fake, None,
+                                    ctypes.c_uint32(fl.COARSE_LDS), None, None)
+    assert rc == fl.EINVAL and b"COARSE_LDS" in L.fhash_last_error()
+    rc, _ = query(8)
+    assert rc == fl.EINVAL and b"unknown flags" in L.fhash_last_error()
