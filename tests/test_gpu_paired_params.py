@@ -180,5 +180,5 @@ def test_layout_arguments_checked(fl):
     tgt = torch.rand(16).cuda()
     with pytest.raises(fl.FHashError) as e:  # unknown flag bit
         fl.fhash_fused_train(par.index, par.mlp, pos, tgt, 16, fl.Paired(par.pm), par.mlp_params,
-                             par.gv, par.d_mlp, flags=4)
+                             par.gv, par.d_mlp, flags=8)
     assert e.value.code == fl.EINVAL
