@@ -864,21 +864,22 @@ HEADLINE_DIMS = [432, 432, 432, 60]
 # the caches (random 16-byte float-atomic groups over 24 GiB, the probe
 # paper_2507_03836_amd/probe/random_access): the bound of the scatter-add.
 ATOMIC_CEILING_GPS = 16.8
-# HBM bytes of one fused training launch (mixed path, 432^3 x 60, batch 2^20)
+# HBM bytes of one fused training launch and its coarse-level LDS scatter
+# (mixed path, 432^3 x 60, batch 2^20)
 # from rocprofv3 FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) passes scaled by a
 # plain streaming copy of known size; valid only while the kernel sources
 # hashed in _fused_src_md5(), the optimiser state layout, the batch order, the
 # table reads and the decoder type are those the counters were taken with.
-FUSED_TRAFFIC = {"bytes": 21336169941, "raw_bytes": 13301701801, "moments": "with-params",
-                 "sorted": True, "table_reads": "f32", "decoder": "f16", "coarse_lds": False,
-                 "source_md5": "0a33c209eb5d9354ceeb82ad197734f8"}
+FUSED_TRAFFIC = {"bytes": 20078788575, "raw_bytes": 11914593217, "moments": "with-params",
+                 "sorted": True, "table_reads": "f32", "decoder": "f16", "coarse_lds": True,
+                 "source_md5": "4127c1ce49895a88d5ca310ff39de201"}
 
 
 def _fused_src_md5():
     import hashlib
     csrc = os.path.join(ROOT, "paper_2507_03836_amd", "csrc")
     names = ("fused_impl.h", "encode_dev.h", "mlp_dev.h", "mlp_train_dev.h", "common.h",
-             "fused_train.hip", "fused_train16.hip")
+             "fused_train.hip", "fused_train16.hip", "coarse.hip")
     return hashlib.md5(b"".join(open(os.path.join(csrc, n), "rb").read()
                                 for n in names)).hexdigest()
 
