@@ -1335,7 +1335,8 @@ def headline_bench(args):
     # with FHASH_COARSE_LDS the fused kernel issues the requests of the levels
     # with more than one cell per sample only; the coarse levels' requests are
     # replaced by one per touched vertex row segment of a chunk's LDS box
-    lc = coarse_levels(cfg.res, B) if args.coarse_lds else 0
+    # (the library takes the LDS path on row-ordered indexes only)
+    lc = coarse_levels(cfg.res, B) if args.coarse_lds and args.layout == "rows" else 0
     areq = int(sum(mx["compulsory"]["atomic_requests_per_level"][lc:]))
     same = (FUSED_TRAFFIC["source_md5"] == _fused_src_md5() and
             args.coarse_lds == FUSED_TRAFFIC["coarse_lds"] and
