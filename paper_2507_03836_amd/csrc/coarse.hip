@@ -117,24 +117,32 @@ __global__ void __launch_bounds__(kThreads)
     if (V * F <= kCap) {
       for (int i = tid; i < (int)V * F; i += kThreads) acc[i] = 0.0f;
       __syncthreads();
-      // lane group of 16: one sample, one corner per lane (bits x, y, z, t),
-      // so equal cells of neighbouring samples spread over 16 addresses
+      // lane group of 16: one corner per lane (bits x, y, z, t), the group
+      // walking a contiguous run of the range's samples and summing in
+      // registers while its vertex stays the same (neighbours in a sorted batch
+      // often share the cell), so an LDS atomic is issued per change of vertex
       const int cr = tid & 15;
       const int ox = cr & 1, oy = (cr >> 1) & 1, oz = (cr >> 2) & 1, ot = (cr >> 3) & 1;
-      constexpr int kStride = kThreads / 16;
-      for (int i0 = tid >> 4; i0 < bn; i0 += kStride * kUnroll) {
+      constexpr int kGroups = kThreads / 16;
+      const int per = (bn + kGroups - 1) / kGroups;
+      const int ib = (tid >> 4) * per, ie = min(bn, ib + per);
+      int cur = -1;
+      float run[F];
+#pragma unroll
+      for (int k = 0; k < F; ++k) run[k] = 0.0f;
+      for (int i0 = ib; i0 < ie; i0 += kUnroll) {
         float4 pu[kUnroll];
         float gu[kUnroll][F];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const int i = i0 + u * kStride;
-          pu[u] = i < bn ? pos[s0 + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+          const int i = i0 + u;
+          pu[u] = i < ie ? pos[s0 + i] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-          for (int k = 0; k < F; ++k) gu[u][k] = i < bn ? gl[(s0 + i) * F + k] : 0.0f;
+          for (int k = 0; k < F; ++k) gu[u][k] = i < ie ? gl[(s0 + i) * F + k] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          if (i0 + u * kStride >= bn) break;
+          if (i0 + u >= ie) break;
           int cx, cy, cz, ct;
           float fx, fy, fz, ft;
           locate(pu[u].x, d.rx, d.sx, cx, fx);
@@ -145,10 +153,21 @@ __global__ void __launch_bounds__(kThreads)
                           ((oz ? fz : 1.0f - fz) * (ot ? ft : 1.0f - ft));
           const int li = (((ct + ot - blo[3]) * ext[2] + (cz + oz - blo[2])) * ext[1] +
                           (cy + oy - blo[1])) * ext[0] + (cx + ox - blo[0]);
+          if (li != cur) {
+            if (cur >= 0)
 #pragma unroll
-          for (int k = 0; k < F; ++k) atomicAdd(&acc[li * F + k], w * gu[u][k]);
+              for (int k = 0; k < F; ++k) atomicAdd(&acc[cur * F + k], run[k]);
+            cur = li;
+#pragma unroll
+            for (int k = 0; k < F; ++k) run[k] = 0.0f;
+          }
+#pragma unroll
+          for (int k = 0; k < F; ++k) run[k] += w * gu[u][k];
         }
       }
+      if (cur >= 0)
+#pragma unroll
+        for (int k = 0; k < F; ++k) atomicAdd(&acc[cur * F + k], run[k]);
       __syncthreads();
       // the box into the table: x fastest, so neighbouring lanes add into
       // neighbouring slots of a vertex row; kUnroll directory loads in flight
